@@ -1,0 +1,874 @@
+/*
+ * lattice_oracle.c -- plain, slow, FP64 CPU oracle for the lattice field step
+ * described in the CosmoLattice paper (arXiv:2102.01031).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the package smoke check and the
+ * CPU-baseline leg of bench.py may load this library.  It shares no code,
+ * header, table or helper with the HIP library; it is compiled with gcc.
+ *
+ * Conventions (program variables of sec. 4.1-4.2, eq. FieldSpaceTimeNaturalVariables):
+ *   - N^3 periodic lattice, spacing dx, site (x,y,z), index x + N*(y + N*z)
+ *     (sec. 3.1, "Basic lattice definitions").
+ *   - <X> = N^-3 sum_n X(n) is the volume average.
+ *   - alpha-time eta, scale factor a, b = a' (sec. 4.5.2).
+ *   - All volume sums use Neumaier-compensated summation, visited in plain
+ *     z, y, x order, so the oracle's sums are (nearly) correctly rounded.
+ *
+ * Readings of points the paper leaves open (the paper defers the discrete
+ * update formulas to its companion reference):
+ *   R1  velocity-Verlet with self-consistent expansion: kick pi and b by h/2
+ *       at the start point, drift a by h*b, drift phi with the mean scale
+ *       factor (a_n + a_{n+1})/2 raised to alpha-3, kick pi by h/2 at the end
+ *       point, recompute the energies there, kick b by h/2.  E_K is taken at
+ *       integer times.
+ *   R2  4th order velocity-Verlet = Yoshida's triple-jump composition of the
+ *       whole second-order map (Yoshida 1990, Phys. Lett. A 150, 262).
+ *   R3  fixed background: every kick uses a(t) at the kick time and every
+ *       drift uses a(t) at the midpoint time of the drift (closed form of
+ *       eq. ScaleFactorPowerLaw).
+ *   R4  leapfrog energies are measured on momenta synchronised to integer
+ *       time by a half kick that is not written back (sec. 7.2 describes the
+ *       sync before measurements).
+ *   R5  U(1): compact formulation of the U(1) toolkit (sec. 3.2) with the
+ *       plaquette V_i V_{j,+i} V*_{i,+j} V*_j and kicks equal to minus the
+ *       derivative of the lattice Hamiltonian.  The complex field carries the
+ *       1/sqrt(2) normalisation of eq. ChargedScalars.  Only a = 1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Parameters                                                          */
+/* ------------------------------------------------------------------ */
+
+enum { ORC_PHI4 = 0, ORC_PHI4_CHI2 = 1 };
+enum { ORC_NONE = 0, ORC_FIXED = 1, ORC_SELF = 2 };
+enum { ORC_LF = 0, ORC_VV2 = 1, ORC_VV4 = 2 };
+
+typedef struct orc_params {
+    int32_t N;           /* lattice points per dimension                     */
+    int32_t nfields;     /* number of real scalar fields: 1 (phi) or 2 (phi, chi) */
+    int32_t potential;   /* ORC_PHI4: lambda/4 phi^4 ; ORC_PHI4_CHI2: + q/2 phi^2 chi^2 */
+    int32_t expansion;   /* ORC_NONE (a=1), ORC_FIXED (power law), ORC_SELF (Friedmann) */
+    int32_t integrator;  /* ORC_LF, ORC_VV2, ORC_VV4                          */
+    int32_t pad;
+    double dx, dt;       /* lattice spacing and time step (program units)    */
+    double lambda, q;    /* potential couplings                              */
+    double alpha;        /* alpha-time exponent (eq. FLRWmetric)             */
+    double kappa2;       /* (f_star/m_p)^2 in the Friedmann kernel              */
+    double w_eos, H0;    /* fixed background: equation of state, initial H  */
+    double t0, a0;       /* fixed background reference time and scale factor */
+} orc_params;
+
+/* The clock: time, scale factor and its derivative, and the leapfrog phase.
+ * lf_stag = 0: momenta at integer time; +1 / -1: momenta half a step behind
+ * (forward / backward run), so that a sync kick of lf_stag*dt/2 restores them. */
+typedef struct orc_clock {
+    double t, a, b;
+    int32_t lf_stag;
+    int32_t pad;
+} orc_clock;
+
+/* ------------------------------------------------------------------ */
+/* Lattice helpers                                                     */
+/* ------------------------------------------------------------------ */
+
+static size_t at(int N, int x, int y, int z)
+{
+    return (size_t)x + (size_t)N * ((size_t)y + (size_t)N * (size_t)z);
+}
+static int up(int i, int N) { return i + 1 == N ? 0 : i + 1; }
+static int dn(int i, int N) { return i == 0 ? N - 1 : i - 1; }
+
+/* neighbour of (x,y,z) one unit along direction d (0=x,1=y,2=z), sign s=+1/-1 */
+static size_t nbr(int N, int x, int y, int z, int d, int s)
+{
+    int c[3] = {x, y, z};
+    c[d] = s > 0 ? up(c[d], N) : dn(c[d], N);
+    return at(N, c[0], c[1], c[2]);
+}
+
+typedef struct { double s, c; } nsum;   /* Neumaier compensated sum */
+static void nadd(nsum *k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+    else                       k->c += (v - t) + k->s;
+    k->s = t;
+}
+static double nval(const nsum *k) { return k->s + k->c; }
+
+static size_t vol(int N) { return (size_t)N * (size_t)N * (size_t)N; }
+
+/* ------------------------------------------------------------------ */
+/* Lattice operators (sec. 3.1, eqs. forwardbackwardd and               */
+/* ForwardBackwardMomentum)                                            */
+/* ------------------------------------------------------------------ */
+
+/* Laplacian as sum_i of backward(forward(f)):
+ *   (Lap f)(n) = dx^-2 sum_i [ f(n+i) - 2 f(n) + f(n-i) ]                  */
+int orc_laplacian(int N, double dx, const double *f, double *out)
+{
+    if (N < 1) return -1;
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                double s = 0.0;
+                double f0 = f[at(N, x, y, z)];
+                for (int d = 0; d < 3; ++d)
+                    s += f[nbr(N, x, y, z, d, +1)] - 2.0 * f0 + f[nbr(N, x, y, z, d, -1)];
+                out[at(N, x, y, z)] = s / (dx * dx);
+            }
+    return 0;
+}
+
+/* sum_n sum_i (forward derivative of f)^2 = sum_n sum_i ((f(n+i)-f(n))/dx)^2 */
+double orc_grad2_sum(int N, double dx, const double *f)
+{
+    nsum k = {0, 0};
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x)
+                for (int d = 0; d < 3; ++d) {
+                    double g = (f[nbr(N, x, y, z, d, +1)] - f[at(N, x, y, z)]) / dx;
+                    nadd(&k, g * g);
+                }
+    return nval(&k);
+}
+
+/* ------------------------------------------------------------------ */
+/* Potential (sec. 4.2, eq. potentialExampleI in program units)        */
+/*   term 0: lambda/4 phi^4     term 1: q/2 phi^2 chi^2                 */
+/* ------------------------------------------------------------------ */
+
+static double pot_term(const orc_params *p, int m, double phi, double chi)
+{
+    if (m == 0) return 0.25 * p->lambda * phi * phi * phi * phi;
+    if (p->potential == ORC_PHI4_CHI2) return 0.5 * p->q * phi * phi * chi * chi;
+    return 0.0;
+}
+
+static double pot_deriv(const orc_params *p, int s, double phi, double chi)
+{
+    if (s == 0) {
+        double d = p->lambda * phi * phi * phi;
+        if (p->potential == ORC_PHI4_CHI2) d += p->q * phi * chi * chi;
+        return d;
+    }
+    return p->potential == ORC_PHI4_CHI2 ? p->q * phi * phi * chi : 0.0;
+}
+
+static int nterms(const orc_params *p) { return p->potential == ORC_PHI4_CHI2 ? 2 : 1; }
+
+/* kernel of pi_s (sec. 4.5.2): K_s = a^{1+alpha} Lap(phi_s) - a^{3+alpha} dV/dphi_s */
+static void kernel_field(const orc_params *p, double a, double *const *phi, int s,
+                         double *out)
+{
+    int N = p->N;
+    size_t V = vol(N);
+    double *lap = (double *)malloc(V * sizeof(double));
+    orc_laplacian(N, p->dx, phi[s], lap);
+    double c1 = pow(a, 1.0 + p->alpha), c3 = pow(a, 3.0 + p->alpha);
+    for (size_t n = 0; n < V; ++n) {
+        double chi = p->nfields > 1 ? phi[1][n] : 0.0;
+        out[n] = c1 * lap[n] - c3 * pot_deriv(p, s, phi[0][n], chi);
+    }
+    free(lap);
+}
+
+int orc_kernel(const orc_params *p, double a, double *const *phi, int s, double *out)
+{
+    if (s < 0 || s >= p->nfields) return -1;
+    kernel_field(p, a, phi, s, out);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Energies (eq. EK_EG_EV and the E definitions of sec. 4.5.2)         */
+/*   E_K^s = <pi_s^2>/(2 a^6), E_G^s = <sum_i (grad+_i phi_s)^2>/(2 a^2),  */
+/*   E_V^m = <V_m>                                                      */
+/* ------------------------------------------------------------------ */
+
+typedef struct { double EK[2], EG[2], EV[2]; } energies;
+
+static energies energies_of(const orc_params *p, double *const *phi, double *const *pi, double a)
+{
+    energies E;
+    memset(&E, 0, sizeof(E));
+    int N = p->N;
+    size_t V = vol(N);
+    for (int s = 0; s < p->nfields; ++s) {
+        nsum k = {0, 0};
+        for (size_t n = 0; n < V; ++n) nadd(&k, pi[s][n] * pi[s][n]);
+        E.EK[s] = nval(&k) / (double)V / (2.0 * pow(a, 6.0));
+        E.EG[s] = orc_grad2_sum(N, p->dx, phi[s]) / (double)V / (2.0 * a * a);
+    }
+    for (int m = 0; m < nterms(p); ++m) {
+        nsum k = {0, 0};
+        for (size_t n = 0; n < V; ++n)
+            nadd(&k, pot_term(p, m, phi[0][n], p->nfields > 1 ? phi[1][n] : 0.0));
+        E.EV[m] = nval(&k) / (double)V;
+    }
+    return E;
+}
+
+static double EK_tot(const energies *E) { return E->EK[0] + E->EK[1]; }
+static double EG_tot(const energies *E) { return E->EG[0] + E->EG[1]; }
+static double EV_tot(const energies *E) { return E->EV[0] + E->EV[1]; }
+static double rho_tot(const energies *E) { return EK_tot(E) + EG_tot(E) + EV_tot(E); }
+
+/* kernel of b (sec. 4.5.2):
+ *   K_a = a^{2 alpha + 1}/3 kappa^2 [ (alpha-2) E_K + alpha E_G + (alpha+1) E_V ] */
+static double kernel_a(const orc_params *p, double a, const energies *E)
+{
+    double al = p->alpha;
+    return pow(a, 2.0 * al + 1.0) / 3.0 * p->kappa2 *
+           ((al - 2.0) * EK_tot(E) + al * EG_tot(E) + (al + 1.0) * EV_tot(E));
+}
+
+/* Fixed power-law background (eq. ScaleFactorPowerLaw):
+ *   p = 2/(3(1+w) - 2 alpha),  a = a0 (1 + H0 (t - t0)/p)^p,  b = a' = a0 H0 (1 + H0 (t-t0)/p)^(p-1) */
+int orc_fixed_background(const orc_params *p, double t, double *a, double *b)
+{
+    double pw = 2.0 / (3.0 * (1.0 + p->w_eos) - 2.0 * p->alpha);
+    double u = 1.0 + p->H0 * (t - p->t0) / pw;
+    if (u <= 0.0) return -1;
+    *a = p->a0 * pow(u, pw);
+    *b = p->a0 * p->H0 * pow(u, pw - 1.0);
+    return 0;
+}
+
+static double fixed_a(const orc_params *p, double t)
+{
+    double a, b;
+    orc_fixed_background(p, t, &a, &b);
+    return a;
+}
+
+/* Hubble constraint (eq. NewFriedmannEQsI): b^2 = a^{2 alpha + 2} kappa^2 rho / 3.
+ * Returns the positive root for b given the state (expanding universe). */
+int orc_hubble_b0(const orc_params *p, double *const *phi, double *const *pi, double a, double *b0)
+{
+    energies E = energies_of(p, phi, pi, a);
+    double rhs = pow(a, 2.0 * p->alpha + 2.0) * p->kappa2 * rho_tot(&E) / 3.0;
+    if (rhs < 0.0) return -1;
+    *b0 = sqrt(rhs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Integrators (sec. 4.5.2 Hamiltonian system, readings R1-R4)         */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_params *p;
+    double **phi, **pi;
+    double *K[2];          /* scratch for the kernels */
+    double a, b;           /* scale factor and its momentum (SELF) */
+    energies E;            /* energies at the current integer point (SELF) */
+} stepper;
+
+static void kick(stepper *st, double a_kick, double w)
+{
+    const orc_params *p = st->p;
+    size_t V = vol(p->N);
+    for (int s = 0; s < p->nfields; ++s) kernel_field(p, a_kick, st->phi, s, st->K[s]);
+    for (int s = 0; s < p->nfields; ++s)
+        for (size_t n = 0; n < V; ++n) st->pi[s][n] += w * st->K[s][n];
+}
+
+static void drift(stepper *st, double a_mid, double h)
+{
+    const orc_params *p = st->p;
+    size_t V = vol(p->N);
+    double c = h * pow(a_mid, p->alpha - 3.0);
+    for (int s = 0; s < p->nfields; ++s)
+        for (size_t n = 0; n < V; ++n) st->phi[s][n] += c * st->pi[s][n];
+}
+
+/* scale factor seen by a kick at time t */
+static double a_at(stepper *st, double t)
+{
+    switch (st->p->expansion) {
+    case ORC_FIXED: return fixed_a(st->p, t);
+    case ORC_SELF: return st->a;
+    default: return 1.0;
+    }
+}
+
+/* One second-order velocity-Verlet map of size h starting at time t (reading R1/R3). */
+static void vv2(stepper *st, double t, double h)
+{
+    const orc_params *p = st->p;
+    int self = p->expansion == ORC_SELF;
+    double a_n = a_at(st, t);
+    kick(st, a_n, 0.5 * h);                                       /* pi half kick   */
+    if (self) st->b += 0.5 * h * kernel_a(p, a_n, &st->E);        /* b half kick    */
+    double a_n1, a_mid;
+    if (self) {
+        a_n1 = a_n + h * st->b;                                   /* a drift        */
+        a_mid = 0.5 * (a_n + a_n1);
+    } else if (p->expansion == ORC_FIXED) {
+        a_n1 = fixed_a(p, t + h);
+        a_mid = fixed_a(p, t + 0.5 * h);
+    } else {
+        a_n1 = 1.0;
+        a_mid = 1.0;
+    }
+    drift(st, a_mid, h);                                          /* phi drift      */
+    if (self) st->a = a_n1;
+    kick(st, a_n1, 0.5 * h);                                      /* pi half kick   */
+    if (self) {
+        st->E = energies_of(p, st->phi, st->pi, a_n1);            /* energies       */
+        st->b += 0.5 * h * kernel_a(p, a_n1, &st->E);             /* b half kick    */
+    }
+}
+
+/* Yoshida's fourth-order weights (reading R2): w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1 */
+void orc_yoshida4(double *w1, double *w0)
+{
+    double c = cbrt(2.0);
+    *w1 = 1.0 / (2.0 - c);
+    *w0 = -c / (2.0 - c);
+}
+
+/* Evolve |nsteps| steps (backward in time if nsteps < 0).
+ * Return codes: 0 ok, -1 bad arguments, -2 unsupported combination,
+ * -3 leapfrog state is staggered in the other direction (sync first). */
+int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_clock *c, long nsteps)
+{
+    if (p->N < 1 || p->nfields < 1 || p->nfields > 2) return -1;
+    if (p->integrator == ORC_LF && p->expansion == ORC_SELF) return -2;
+    if (nsteps == 0) return 0;
+    int dir = nsteps > 0 ? 1 : -1;
+    long ns = nsteps > 0 ? nsteps : -nsteps;
+    double h = dir * p->dt;
+    size_t V = vol(p->N);
+
+    stepper st;
+    st.p = p;
+    st.phi = (double **)phi;
+    st.pi = (double **)pi;
+    st.K[0] = (double *)malloc(V * sizeof(double));
+    st.K[1] = (double *)malloc(V * sizeof(double));
+    st.a = c->a;
+    st.b = c->b;
+    double t_start = c->t;
+
+    if (p->integrator == ORC_LF) {
+        if (c->lf_stag != 0 && c->lf_stag != dir) { free(st.K[0]); free(st.K[1]); return -3; }
+        for (long k = 0; k < ns; ++k) {
+            double t = t_start + (double)k * h;
+            double w = (c->lf_stag == 0) ? 0.5 * h : h;  /* first kick after a sync is half */
+            kick(&st, a_at(&st, t), w);
+            double a_mid = p->expansion == ORC_FIXED ? fixed_a(p, t + 0.5 * h) : 1.0;
+            drift(&st, a_mid, h);
+            c->lf_stag = dir;
+        }
+    } else {
+        if (p->expansion == ORC_SELF) st.E = energies_of(p, st.phi, st.pi, st.a);
+        double w1, w0;
+        orc_yoshida4(&w1, &w0);
+        for (long k = 0; k < ns; ++k) {
+            double t = t_start + (double)k * h;
+            if (p->integrator == ORC_VV2) {
+                vv2(&st, t, h);
+            } else {
+                vv2(&st, t, w1 * h);
+                vv2(&st, t + w1 * h, w0 * h);
+                vv2(&st, t + w1 * h + w0 * h, w1 * h);
+            }
+        }
+    }
+    c->t = t_start + (double)ns * h;
+    if (p->expansion == ORC_SELF) {
+        c->a = st.a;
+        c->b = st.b;
+    } else if (p->expansion == ORC_FIXED) {
+        orc_fixed_background(p, c->t, &c->a, &c->b);
+    } else {
+        c->a = 1.0;
+        c->b = 0.0;
+    }
+    free(st.K[0]);
+    free(st.K[1]);
+    return 0;
+}
+
+/* Leapfrog sync (sec. 7.2): bring staggered momenta to integer time, in place. */
+int orc_lf_sync(const orc_params *p, double *const *phi, double *const *pi, orc_clock *c)
+{
+    if (c->lf_stag == 0) return 0;
+    stepper st;
+    size_t V = vol(p->N);
+    st.p = p;
+    st.phi = (double **)phi;
+    st.pi = (double **)pi;
+    st.K[0] = (double *)malloc(V * sizeof(double));
+    st.K[1] = (double *)malloc(V * sizeof(double));
+    st.a = c->a;
+    kick(&st, a_at(&st, c->t), 0.5 * c->lf_stag * p->dt);
+    c->lf_stag = 0;
+    free(st.K[0]);
+    free(st.K[1]);
+    return 0;
+}
+
+/* Energies of the state, output layout (11 doubles):
+ *   [0,1] E_K per field, [2,3] E_G per field, [4,5] E_V per term, [6] rho,
+ *   [7] Hubble LHS b^2, [8] Hubble RHS a^{2alpha+2} kappa^2 rho/3,
+ *   [9] (LHS-RHS)/(LHS+RHS), [10] a.
+ * Leapfrog momenta are synchronised on a copy (reading R4). */
+int orc_energy(const orc_params *p, double *const *phi, double *const *pi, const orc_clock *c,
+               double *out)
+{
+    size_t V = vol(p->N);
+    double *pis[2] = {NULL, NULL};
+    for (int s = 0; s < p->nfields; ++s) {
+        pis[s] = (double *)malloc(V * sizeof(double));
+        memcpy(pis[s], pi[s], V * sizeof(double));
+    }
+    if (c->lf_stag != 0) {
+        orc_clock cc = *c;
+        orc_lf_sync(p, phi, pis, &cc);
+    }
+    energies E = energies_of(p, phi, pis, c->a);
+    for (int s = 0; s < p->nfields; ++s) free(pis[s]);
+    double rho = rho_tot(&E);
+    double lhs = c->b * c->b;
+    double rhs = pow(c->a, 2.0 * p->alpha + 2.0) * p->kappa2 * rho / 3.0;
+    out[0] = E.EK[0]; out[1] = E.EK[1];
+    out[2] = E.EG[0]; out[3] = E.EG[1];
+    out[4] = E.EV[0]; out[5] = E.EV[1];
+    out[6] = rho;
+    out[7] = lhs;
+    out[8] = rhs;
+    out[9] = (lhs + rhs) != 0.0 ? (lhs - rhs) / (lhs + rhs) : 0.0;
+    out[10] = c->a;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of the second-order velocity-Verlet map, a = 1, two fields   */
+/* with V = lambda/4 phi^4 + q/2 phi^2 chi^2.                            */
+/*   forward: pi' = pi + h/2 F(phi); phi' = phi + h pi'; pi'' = pi' + h/2 F(phi') */
+/*   F(phi) = Lap phi - grad V(phi);  dF = Lap - H_V(phi)  (symmetric)   */
+/* ------------------------------------------------------------------ */
+
+/* out_s = Lap(l_s) - sum_r H_V(phi)_{sr} l_r  (transpose of dF, which is symmetric) */
+static void jac_F_T(const orc_params *p, double *const *phi, double *const *l, double **out,
+                    double *lap)
+{
+    size_t V = vol(p->N);
+    for (int s = 0; s < 2; ++s) {
+        orc_laplacian(p->N, p->dx, l[s], lap);
+        for (size_t n = 0; n < V; ++n) {
+            double f = phi[0][n], x = phi[1][n];
+            double h00 = 3.0 * p->lambda * f * f + p->q * x * x;   /* d2V/dphi2   */
+            double h01 = 2.0 * p->q * f * x;                         /* d2V/dphidchi */
+            double h11 = p->q * f * f;                               /* d2V/dchi2   */
+            double hl = s == 0 ? h00 * l[0][n] + h01 * l[1][n] : h01 * l[0][n] + h11 * l[1][n];
+            out[s][n] = lap[n] - hl;
+        }
+    }
+}
+
+/* sum_n l(n) . dF/dq(phi(n)),  dF/dq = -(phi chi^2, phi^2 chi) */
+static double dot_dFdq(const orc_params *p, double *const *phi, double *const *l)
+{
+    nsum k = {0, 0};
+    size_t V = vol(p->N);
+    for (size_t n = 0; n < V; ++n) {
+        double f = phi[0][n], x = phi[1][n];
+        nadd(&k, -l[0][n] * f * x * x);
+        nadd(&k, -l[1][n] * f * f * x);
+    }
+    return nval(&k);
+}
+
+static int check_adj(const orc_params *p)
+{
+    if (p->nfields != 2 || p->potential != ORC_PHI4_CHI2 || p->expansion != ORC_NONE) return -2;
+    return 0;
+}
+
+/* One VV2 step of the state (phi, pi) together with its tangent (dphi, dpi)
+ * along an extra coupling direction dq. All arrays are updated in place. */
+int orc_vv2_tangent(const orc_params *p, double *const *phi, double *const *pi,
+                    double *const *dphi, double *const *dpi, double dq)
+{
+    if (check_adj(p)) return -2;
+    size_t V = vol(p->N);
+    double h = p->dt;
+    double *lap = (double *)malloc(V * sizeof(double));
+    double *J[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
+    double *K[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
+    for (int half = 0; half < 2; ++half) {
+        /* kick at the current position: pi += h/2 F(phi); dpi += h/2 (dF dphi + dF/dq dq) */
+        jac_F_T(p, phi, dphi, J, lap);  /* dF symmetric: dF dphi = dF^T dphi */
+        for (int s = 0; s < 2; ++s) kernel_field(p, 1.0, phi, s, K[s]);
+        for (size_t n = 0; n < V; ++n) {
+            double f = phi[0][n], x = phi[1][n];
+            double dFq0 = -f * x * x, dFq1 = -f * f * x;
+            pi[0][n] += 0.5 * h * K[0][n];
+            pi[1][n] += 0.5 * h * K[1][n];
+            dpi[0][n] += 0.5 * h * (J[0][n] + dFq0 * dq);
+            dpi[1][n] += 0.5 * h * (J[1][n] + dFq1 * dq);
+        }
+        if (half == 0) {
+            for (int s = 0; s < 2; ++s)
+                for (size_t n = 0; n < V; ++n) {
+                    phi[s][n] += h * pi[s][n];
+                    dphi[s][n] += h * dpi[s][n];
+                }
+        }
+    }
+    free(lap); free(J[0]); free(J[1]); free(K[0]); free(K[1]);
+    return 0;
+}
+
+/* Pull the adjoint (lphi, lpi) of the state after one VV2 step back to the
+ * state before it.  (phi_n, pi_n) is the state before the step (unchanged).
+ * *dq accumulates the coupling sensitivity of the step. */
+int orc_vv2_adjoint_step(const orc_params *p, double *const *phi_n, double *const *pi_n,
+                         double *const *lphi, double *const *lpi, double *dq)
+{
+    if (check_adj(p)) return -2;
+    size_t V = vol(p->N);
+    double h = p->dt;
+    double *lap = (double *)malloc(V * sizeof(double));
+    double *J[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
+    double *ph1[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
+    double *pi1[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
+    /* positions after the step: phi_{n+1} = phi_n + h (pi_n + h/2 F(phi_n)) */
+    for (int s = 0; s < 2; ++s) {
+        memcpy(ph1[s], phi_n[s], V * sizeof(double));
+        memcpy(pi1[s], pi_n[s], V * sizeof(double));
+    }
+    {
+        stepper st;
+        st.p = p; st.phi = ph1; st.pi = pi1; st.K[0] = J[0]; st.K[1] = J[1];
+        kick(&st, 1.0, 0.5 * h);
+        drift(&st, 1.0, h);
+    }
+    /* second half kick: lphi += h/2 dF(phi_{n+1})^T lpi */
+    *dq += 0.5 * h * dot_dFdq(p, ph1, lpi);
+    jac_F_T(p, ph1, lpi, J, lap);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) lphi[s][n] += 0.5 * h * J[s][n];
+    /* drift: lpi += h lphi */
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];
+    /* first half kick: lphi += h/2 dF(phi_n)^T lpi */
+    *dq += 0.5 * h * dot_dFdq(p, phi_n, lpi);
+    jac_F_T(p, phi_n, lpi, J, lap);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) lphi[s][n] += 0.5 * h * J[s][n];
+    free(lap); free(J[0]); free(J[1]);
+    free(ph1[0]); free(ph1[1]); free(pi1[0]); free(pi1[1]);
+    return 0;
+}
+
+/* Observable: fraction of the energy in chi, O = (E_K^chi + E_G^chi)/rho (a = 1).
+ * Writes O and, if seeds are given, dO/dphi_s(n), dO/dpi_s(n) and the explicit dO/dq. */
+static double observable(const orc_params *p, double *const *phi, double *const *pi,
+                         double **gphi, double **gpi, double *dOdq_explicit)
+{
+    size_t V = vol(p->N);
+    energies E = energies_of(p, phi, pi, 1.0);
+    double rho = rho_tot(&E);
+    double X = E.EK[1] + E.EG[1];
+    double O = X / rho;
+    if (gphi) {
+        double *lap = (double *)malloc(V * sizeof(double));
+        double inv = 1.0 / ((double)V * rho);
+        for (int s = 0; s < 2; ++s) {
+            double wX = s == 1 ? 1.0 : 0.0;   /* d X / d(field s) weight */
+            orc_laplacian(p->N, p->dx, phi[s], lap);
+            for (size_t n = 0; n < V; ++n) {
+                double dV = pot_deriv(p, s, phi[0][n], phi[1][n]);
+                /* dE_G^s/dphi_s(n) = -Lap phi_s / V ; dE_V/dphi_s = dV/dphi_s / V */
+                double dX = wX * (-lap[n]);
+                double drho = -lap[n] + dV;
+                gphi[s][n] = (dX - O * drho) * inv;
+                gpi[s][n] = (wX * pi[s][n] - O * pi[s][n]) * inv;
+            }
+        }
+        free(lap);
+        nsum kq = {0, 0};                                 /* dE_V/dq = <phi^2 chi^2 / 2> */
+        for (size_t n = 0; n < V; ++n) nadd(&kq, 0.5 * phi[0][n] * phi[0][n] * phi[1][n] * phi[1][n]);
+        *dOdq_explicit = -O * (nval(&kq) / (double)V) / rho;
+    }
+    return O;
+}
+
+int orc_observable(const orc_params *p, double *const *phi, double *const *pi, double *O,
+                   double *const *gphi, double *const *gpi, double *dOdq)
+{
+    if (check_adj(p)) return -2;
+    double d = 0.0;
+    *O = observable(p, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
+    if (dOdq) *dOdq = d;
+    return 0;
+}
+
+/* Gradient of O(final state) with respect to the initial phi, pi and q for
+ * nsteps VV2 steps, by reverse sweep with segment recomputation: checkpoints
+ * every ceil(sqrt(nsteps)) steps, each segment re-run forward from its
+ * checkpoint and stored, then pulled back step by step. */
+int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0, long nsteps,
+                    double *O_out, double *const *gphi, double *const *gpi, double *dOdq)
+{
+    if (check_adj(p)) return -2;
+    if (nsteps < 0) return -1;
+    size_t V = vol(p->N), B = V * sizeof(double);
+    long k = 1;
+    while (k * k < nsteps) ++k;
+    long ncp = nsteps / k + 1;
+    double *cp = (double *)malloc((size_t)ncp * 4 * B);   /* phi0, phi1, pi0, pi1 per checkpoint */
+    double *cur[4];
+    for (int i = 0; i < 4; ++i) cur[i] = (double *)malloc(B);
+    memcpy(cur[0], phi0[0], B); memcpy(cur[1], phi0[1], B);
+    memcpy(cur[2], pi0[0], B);  memcpy(cur[3], pi0[1], B);
+    orc_params pv = *p;
+    pv.integrator = ORC_VV2;
+    for (long n = 0; n <= nsteps; ++n) {
+        if (n % k == 0)
+            for (int i = 0; i < 4; ++i) memcpy(cp + ((size_t)(n / k) * 4 + i) * V, cur[i], B);
+        if (n == nsteps) break;
+        orc_clock c = {0, 1, 0, 0, 0};
+        orc_run(&pv, cur, cur + 2, &c, 1);
+    }
+    /* seed at the final state */
+    double *lphi[2] = {gphi[0], gphi[1]}, *lpi[2] = {gpi[0], gpi[1]};
+    double q_acc = 0.0;
+    *O_out = observable(p, cur, cur + 2, lphi, lpi, &q_acc);
+    /* segment states: positions and momenta at steps s0..s1 */
+    double *seg = (double *)malloc((size_t)(k + 1) * 4 * B);
+    for (long s0 = ((nsteps - 1) / k) * k; nsteps > 0 && s0 >= 0; s0 -= k) {
+        long s1 = s0 + k < nsteps ? s0 + k : nsteps;
+        for (int i = 0; i < 4; ++i) memcpy(cur[i], cp + ((size_t)(s0 / k) * 4 + i) * V, B);
+        for (long n = s0; n < s1; ++n) {
+            for (int i = 0; i < 4; ++i) memcpy(seg + ((size_t)(n - s0) * 4 + i) * V, cur[i], B);
+            orc_clock c = {0, 1, 0, 0, 0};
+            orc_run(&pv, cur, cur + 2, &c, 1);
+        }
+        for (long n = s1 - 1; n >= s0; --n) {
+            double *sp[2] = {seg + ((size_t)(n - s0) * 4 + 0) * V, seg + ((size_t)(n - s0) * 4 + 1) * V};
+            double *sm[2] = {seg + ((size_t)(n - s0) * 4 + 2) * V, seg + ((size_t)(n - s0) * 4 + 3) * V};
+            orc_vv2_adjoint_step(p, sp, sm, lphi, lpi, &q_acc);
+        }
+    }
+    *dOdq = q_acc;
+    free(seg);
+    free(cp);
+    for (int i = 0; i < 4; ++i) free(cur[i]);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* U(1) sector: complex scalar + Abelian links, a = 1 (sec. 3.2 U(1)   */
+/* toolkit, sec. 5.2 equations of motion, sec. 5.5.2 kernels; reading R5) */
+/* phi = (phi0 + i phi1)/sqrt(2); psi = phi0 + i phi1 = sqrt(2) phi.     */
+/* links V_i = exp(-i e dx A_i); plaquette angle                        */
+/*   theta_ij(n) = e dx [A_j(n+i) - A_j(n) - A_i(n+j) + A_i(n)]           */
+/* V = lambda/4 (|phi|^2 - v^2)^2, |phi|^2 = (phi0^2 + phi1^2)/2         */
+/* ------------------------------------------------------------------ */
+
+typedef struct orc_u1_params {
+    int32_t N, pad;
+    double dx, dt, lambda, v, e, kappa_g;   /* kappa_g = (f_star/omega_star)^2 */
+} orc_u1_params;
+
+static double theta(const orc_u1_params *p, double *const *A, int x, int y, int z, int i, int j)
+{
+    int N = p->N;
+    return p->e * p->dx *
+           (A[j][nbr(N, x, y, z, i, +1)] - A[j][at(N, x, y, z)] - A[i][nbr(N, x, y, z, j, +1)] +
+            A[i][at(N, x, y, z)]);
+}
+
+/* forces = minus the derivative of the lattice Hamiltonian:
+ *   Fphi_c = {Re,Im}(D^2 psi) - lambda/2 (|phi|^2 - v^2) phi_c
+ *   FA_i   = kappa_g J_i - (e dx^3)^-1 sum_{j != i} [sin theta_ij(n) - sin theta_ij(n-j)]
+ *   J_i    = (e/dx) Im[ conj(psi(n)) V_i(n) psi(n+i) ]                       */
+int orc_u1_forces(const orc_u1_params *p, double *const *phi, double *const *A,
+                  double *const *Fphi, double *const *FA)
+{
+    int N = p->N;
+    double dx = p->dx, e = p->e;
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                size_t n = at(N, x, y, z);
+                double pr = phi[0][n], pim = phi[1][n];
+                double dre = 0.0, dim = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    size_t np = nbr(N, x, y, z, i, +1), nm = nbr(N, x, y, z, i, -1);
+                    double cp = cos(e * dx * A[i][n]), sp = -sin(e * dx * A[i][n]);   /* V_i(n)   */
+                    double cm = cos(e * dx * A[i][nm]), sm = sin(e * dx * A[i][nm]);  /* V_i(n-i)* */
+                    /* V_i(n) psi(n+i) */
+                    double ar = cp * phi[0][np] - sp * phi[1][np];
+                    double ai = cp * phi[1][np] + sp * phi[0][np];
+                    /* conj(V_i(n-i)) psi(n-i) */
+                    double br = cm * phi[0][nm] - sm * phi[1][nm];
+                    double bi = cm * phi[1][nm] + sm * phi[0][nm];
+                    dre += ar - 2.0 * pr + br;
+                    dim += ai - 2.0 * pim + bi;
+                    /* current: Im[conj(psi) V psi(n+i)] = pr*ai - pim*ar */
+                    double J = e / dx * (pr * ai - pim * ar);
+                    double mag = 0.0;
+                    for (int j = 0; j < 3; ++j) {
+                        if (j == i) continue;
+                        int c[3] = {x, y, z};
+                        c[j] = dn(c[j], N);
+                        mag += sin(theta(p, A, x, y, z, i, j)) - sin(theta(p, A, c[0], c[1], c[2], i, j));
+                    }
+                    FA[i][n] = p->kappa_g * J - mag / (e * dx * dx * dx);
+                }
+                double m2 = 0.5 * (pr * pr + pim * pim);
+                double vp = 0.5 * p->lambda * (m2 - p->v * p->v);
+                Fphi[0][n] = dre / (dx * dx) - vp * pr;
+                Fphi[1][n] = dim / (dx * dx) - vp * pim;
+            }
+    return 0;
+}
+
+/* U(1) energies and Gauss constraint. Output layout (12 doubles):
+ *  [0] E_K^phi = <(pi0^2+pi1^2)/2>, [1] E_G^phi = <sum_i |V_i psi(n+i) - psi(n)|^2>/(2 dx^2),
+ *  [2] E_V = <lambda/4 (|phi|^2-v^2)^2>, [3] E_K^A = <sum_i piA_i^2>/(2 kappa_g),
+ *  [4] E_G^A = <sum_{i<j} (1 - cos theta_ij)>/(kappa_g e^2 dx^4), [5] rho,
+ *  [6] max|G|, [7] max|div piA|, [8] max|charge|, [9] <|G|>, [10] <|div piA + charge|>
+ *  with G = div^- piA - e kappa_g (phi0 pi1 - phi1 pi0) (eq. GaussU1-eom, a = 1)
+ *  [11] <|div piA| + |charge|>.
+ * Leapfrog momenta are synchronised on copies when lf_stag != 0. */
+static void u1_energy_plain(const orc_u1_params *p, double *const *phi, double *const *pi,
+                            double *const *A, double *const *piA, double *out)
+{
+    int N = p->N;
+    size_t V = vol(N);
+    double dx = p->dx, e = p->e;
+    nsum sk = {0, 0}, sg = {0, 0}, sv = {0, 0}, ska = {0, 0}, sga = {0, 0};
+    nsum sG = {0, 0}, sLR = {0, 0}, sLRabs = {0, 0};
+    double gmax = 0, dmax = 0, cmax = 0;
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                size_t n = at(N, x, y, z);
+                nadd(&sk, 0.5 * (pi[0][n] * pi[0][n] + pi[1][n] * pi[1][n]));
+                double g = 0.0, ka = 0.0, div = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    size_t np = nbr(N, x, y, z, i, +1), nm = nbr(N, x, y, z, i, -1);
+                    double c = cos(e * dx * A[i][n]), s = -sin(e * dx * A[i][n]);
+                    double ar = c * phi[0][np] - s * phi[1][np];
+                    double ai = c * phi[1][np] + s * phi[0][np];
+                    double dr = ar - phi[0][n], di = ai - phi[1][n];
+                    g += dr * dr + di * di;
+                    ka += piA[i][n] * piA[i][n];
+                    div += (piA[i][n] - piA[i][nm]) / dx;
+                }
+                nadd(&sg, g / (2.0 * dx * dx));
+                double m2 = 0.5 * (phi[0][n] * phi[0][n] + phi[1][n] * phi[1][n]);
+                double u = m2 - p->v * p->v;
+                nadd(&sv, 0.25 * p->lambda * u * u);
+                nadd(&ska, ka / (2.0 * p->kappa_g));
+                double mag = 0.0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = i + 1; j < 3; ++j) mag += 1.0 - cos(theta(p, A, x, y, z, i, j));
+                nadd(&sga, mag / (p->kappa_g * e * e * dx * dx * dx * dx));
+                double charge = e * p->kappa_g * (phi[0][n] * pi[1][n] - phi[1][n] * pi[0][n]);
+                double G = div - charge;
+                if (fabs(G) > gmax) gmax = fabs(G);
+                if (fabs(div) > dmax) dmax = fabs(div);
+                if (fabs(charge) > cmax) cmax = fabs(charge);
+                nadd(&sG, fabs(G));
+                nadd(&sLR, fabs(div + charge));
+                nadd(&sLRabs, fabs(div) + fabs(charge));
+            }
+    out[0] = nval(&sk) / (double)V;
+    out[1] = nval(&sg) / (double)V;
+    out[2] = nval(&sv) / (double)V;
+    out[3] = nval(&ska) / (double)V;
+    out[4] = nval(&sga) / (double)V;
+    out[5] = out[0] + out[1] + out[2] + out[3] + out[4];
+    out[6] = gmax;
+    out[7] = dmax;
+    out[8] = cmax;
+    out[9] = nval(&sG) / (double)V;
+    out[10] = nval(&sLR) / (double)V;
+    out[11] = nval(&sLRabs) / (double)V;
+}
+
+static void u1_kick(const orc_u1_params *p, double *const *phi, double *const *pi,
+                    double *const *A, double *const *piA, double w)
+{
+    size_t V = vol(p->N);
+    double *F[5];
+    for (int i = 0; i < 5; ++i) F[i] = (double *)malloc(V * sizeof(double));
+    orc_u1_forces(p, phi, A, F, F + 2);
+    for (size_t n = 0; n < V; ++n) {
+        pi[0][n] += w * F[0][n];
+        pi[1][n] += w * F[1][n];
+        for (int i = 0; i < 3; ++i) piA[i][n] += w * F[2 + i][n];
+    }
+    for (int i = 0; i < 5; ++i) free(F[i]);
+}
+
+int orc_u1_energy(const orc_u1_params *p, double *const *phi, double *const *pi,
+                  double *const *A, double *const *piA, const orc_clock *c, double *out)
+{
+    size_t V = vol(p->N), B = V * sizeof(double);
+    double *ps[2], *pa[3];
+    for (int i = 0; i < 2; ++i) { ps[i] = (double *)malloc(B); memcpy(ps[i], pi[i], B); }
+    for (int i = 0; i < 3; ++i) { pa[i] = (double *)malloc(B); memcpy(pa[i], piA[i], B); }
+    if (c->lf_stag != 0) u1_kick(p, phi, ps, A, pa, 0.5 * c->lf_stag * p->dt);
+    u1_energy_plain(p, phi, ps, A, pa, out);
+    for (int i = 0; i < 2; ++i) free(ps[i]);
+    for (int i = 0; i < 3; ++i) free(pa[i]);
+    return 0;
+}
+
+/* Gauss residual of the stored (un-synchronised) pairing, same layout [6..11]. */
+int orc_u1_gauss(const orc_u1_params *p, double *const *phi, double *const *pi,
+                 double *const *A, double *const *piA, double *out)
+{
+    u1_energy_plain(p, phi, pi, A, piA, out);
+    return 0;
+}
+
+/* Staggered leapfrog for the U(1) system (a = 1): kick all momenta, then drift
+ * phi and A.  Same staggering convention as orc_run. */
+int orc_u1_run_lf(const orc_u1_params *p, double *const *phi, double *const *pi,
+                  double *const *A, double *const *piA, orc_clock *c, long nsteps)
+{
+    if (nsteps == 0) return 0;
+    int dir = nsteps > 0 ? 1 : -1;
+    long ns = nsteps > 0 ? nsteps : -nsteps;
+    double h = dir * p->dt;
+    if (c->lf_stag != 0 && c->lf_stag != dir) return -3;
+    size_t V = vol(p->N);
+    for (long k = 0; k < ns; ++k) {
+        u1_kick(p, phi, pi, A, piA, c->lf_stag == 0 ? 0.5 * h : h);
+        for (size_t n = 0; n < V; ++n) {
+            phi[0][n] += h * pi[0][n];
+            phi[1][n] += h * pi[1][n];
+            for (int i = 0; i < 3; ++i) A[i][n] += h * piA[i][n];
+        }
+        c->lf_stag = dir;
+    }
+    c->t += (double)ns * h;
+    c->a = 1.0;
+    c->b = 0.0;
+    return 0;
+}
+
+int orc_u1_lf_sync(const orc_u1_params *p, double *const *phi, double *const *pi,
+                   double *const *A, double *const *piA, orc_clock *c)
+{
+    if (c->lf_stag == 0) return 0;
+    u1_kick(p, phi, pi, A, piA, 0.5 * c->lf_stag * p->dt);
+    c->lf_stag = 0;
+    return 0;
+}

@@ -1,0 +1,114 @@
+"""Pins of the oracle's adjoint of the velocity-Verlet step (two fields, a = 1):
+dot-product identity against the tangent-linear step, tangent against central
+differences of the nonlinear step, and the full reverse sweep against central
+differences of the final observable (energy fraction in chi)."""
+import numpy as np
+import pytest
+
+
+def model(orc, N=5, dt=0.01, q=30.0):
+    return orc.ScalarModel(N=N, dx=0.4, dt=dt, nfields=2, potential=orc.PHI4_CHI2, lam=1.0, q=q,
+                           expansion=orc.NONE, integrator=orc.VV2)
+
+
+def state(N, seed=21):
+    rng = np.random.default_rng(seed)
+    V = N ** 3
+    phi = [1.0 + 0.1 * rng.standard_normal(V), 0.05 * rng.standard_normal(V)]
+    pi = [0.1 * rng.standard_normal(V), 0.05 * rng.standard_normal(V)]
+    return phi, pi
+
+
+def test_dot_product_identity(orc):
+    N = 5
+    m = model(orc, N)
+    phi, pi = state(N)
+    rng = np.random.default_rng(1)
+    v = [rng.standard_normal(N ** 3) for _ in range(4)]
+    dq = 0.37
+    w = [rng.standard_normal(N ** 3) for _ in range(4)]
+    # tangent: J v
+    ph, pp = [f.copy() for f in phi], [f.copy() for f in pi]
+    dph, dpp = [v[0].copy(), v[1].copy()], [v[2].copy(), v[3].copy()]
+    orc.vv2_tangent(m, ph, pp, dph, dpp, dq)
+    lhs = sum(np.dot(a, b) for a, b in zip(dph + dpp, w))
+    # adjoint: J^T w
+    lph, lpp = [w[0].copy(), w[1].copy()], [w[2].copy(), w[3].copy()]
+    gq = orc.vv2_adjoint_step(m, phi, pi, lph, lpp)
+    rhs = sum(np.dot(a, b) for a, b in zip(lph + lpp, v)) + dq * gq
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_tangent_matches_central_differences(orc):
+    N = 4
+    m = model(orc, N)
+    phi, pi = state(N, 3)
+    rng = np.random.default_rng(2)
+    v = [rng.standard_normal(N ** 3) for _ in range(4)]
+    dq = 0.5
+    ph, pp = [f.copy() for f in phi], [f.copy() for f in pi]
+    dph, dpp = [v[0].copy(), v[1].copy()], [v[2].copy(), v[3].copy()]
+    orc.vv2_tangent(m, ph, pp, dph, dpp, dq)
+    eps = 1e-6
+
+    def step(sign):
+        mm = model(orc, N, q=m.q + sign * eps * dq)
+        st = orc.ScalarState(mm, [phi[0] + sign * eps * v[0], phi[1] + sign * eps * v[1]],
+                             [pi[0] + sign * eps * v[2], pi[1] + sign * eps * v[3]])
+        st.run(1)
+        return st.phi + st.pi
+
+    fp, fm = step(1), step(-1)
+    for a, b, c in zip(fp, fm, dph + dpp):
+        fd = (a - b) / (2 * eps)
+        assert np.max(np.abs(fd - c)) < 1e-6 * max(1, np.max(np.abs(c)))
+
+
+def test_observable_gradient_seed(orc):
+    N = 4
+    m = model(orc, N)
+    phi, pi = state(N, 5)
+    O, g, gp, dq = orc.observable(m, phi, pi, with_grad=True)
+    assert 0 < O < 1
+    eps = 1e-6
+    for s in range(2):
+        for site in (0, 13, 63):
+            for arr, grad in ((phi, g), (pi, gp)):
+                p_ = [f.copy() for f in arr]; m_ = [f.copy() for f in arr]
+                p_[s][site] += eps; m_[s][site] -= eps
+                if arr is phi:
+                    fd = (orc.observable(m, p_, pi) - orc.observable(m, m_, pi)) / (2 * eps)
+                else:
+                    fd = (orc.observable(m, phi, p_) - orc.observable(m, phi, m_)) / (2 * eps)
+                assert abs(fd - grad[s][site]) < 1e-8 * max(1e-3, abs(fd))
+    fd = (orc.observable(model(orc, N, q=m.q + 1e-5), phi, pi)
+          - orc.observable(model(orc, N, q=m.q - 1e-5), phi, pi)) / 2e-5
+    assert abs(fd - dq) < 1e-7 * max(1e-3, abs(fd))
+
+
+@pytest.mark.parametrize("nsteps", [1, 7, 30])
+def test_reverse_sweep_vs_finite_differences(orc, nsteps):
+    N = 5
+    m = model(orc, N, dt=0.02)
+    phi, pi = state(N, 8)
+    O, g, gp, dq = orc.adjoint_vv2(m, phi, pi, nsteps)
+
+    def O_of(phi_, pi_, q_):
+        st = orc.ScalarState(model(orc, N, dt=0.02, q=q_), phi_, pi_)
+        st.run(nsteps)
+        return orc.observable(model(orc, N, dt=0.02, q=q_), st.phi, st.pi)
+
+    assert abs(O - O_of(phi, pi, m.q)) < 1e-14
+    rng = np.random.default_rng(7)
+    for _ in range(4):
+        v = [rng.standard_normal(N ** 3) for _ in range(4)]
+        vq = rng.standard_normal()
+        nrm = np.sqrt(sum(np.dot(a, a) for a in v) + vq * vq)
+        v = [a / nrm for a in v]
+        vq /= nrm
+        eps = 1e-5
+        fp = O_of([phi[0] + eps * v[0], phi[1] + eps * v[1]], [pi[0] + eps * v[2], pi[1] + eps * v[3]], m.q + eps * vq)
+        fm = O_of([phi[0] - eps * v[0], phi[1] - eps * v[1]], [pi[0] - eps * v[2], pi[1] - eps * v[3]], m.q - eps * vq)
+        fd = (fp - fm) / (2 * eps)
+        ad = np.dot(g[0], v[0]) + np.dot(g[1], v[1]) + np.dot(gp[0], v[2]) + np.dot(gp[1], v[3]) + dq * vq
+        assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-12
