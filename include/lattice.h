@@ -1,0 +1,199 @@
+/*
+ * lattice.h -- C ABI of the MI355X (gfx950) lattice field step.
+ *
+ * The library evolves classical fields on a periodic N^3 lattice in an
+ * expanding (FLRW) background with the symplectic kick/drift integrators of
+ * the CosmoLattice paper (arXiv:2102.01031):
+ *   - real scalar singlets (sec. 4.2 model, sec. 4.5.2 Hamiltonian form),
+ *   - a U(1)-charged complex scalar with Abelian links (sec. 3.2 U(1)
+ *     toolkit, sec. 5.2 equations of motion, sec. 5.5.2 kernels).
+ * All quantities are in the paper's program variables (sec. 4.1, eq.
+ * FieldSpaceTimeNaturalVariables; sec. 5.1, eq. GaugeProgramVar).
+ *
+ * Layout.  Every field component is one contiguous array of N^3 elements
+ * (float64, or float32 in LAT_PREC_F32 mode) in device memory, site
+ * (x, y, z) at index x + N*(y + N*z), x fastest.
+ *
+ * Ownership.  The caller allocates and owns the field arrays and keeps them
+ * alive until lattice_destroy.  lattice_step and lattice_sync overwrite them
+ * in place: when a call returns (in stream order) the arrays hold the new
+ * state.  The library owns only its scratch: one shadow copy of each field
+ * array (stencil passes write out of place), reduction partials, the device
+ * scale-factor record and per-pass coefficient tables; lattice_destroy frees
+ * them.  Fields must not be modified by the caller while work enqueued by the
+ * library is pending.
+ *
+ * Streams.  All device work is enqueued on the stream given to lattice_init
+ * (a hipStream_t passed as void*, NULL = default stream).  lattice_step and
+ * lattice_sync do not synchronise; lattice_energy synchronises the stream.
+ * One context per stream; contexts are not internally locked.
+ *
+ * Errors.  Every call returns a lat_status.  Arguments are validated before
+ * any launch, so a call that fails validation leaves the state untouched.
+ * lattice_last_error(ctx) returns a description of the last failure of that
+ * context (ctx = NULL: the last failure of lattice_init on this thread).
+ * No C++ exception crosses this interface.
+ */
+#ifndef LATTICE_H
+#define LATTICE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lat_status {
+    LAT_OK = 0,
+    LAT_EINVAL = -1,        /* invalid argument (sizes, steps, null or misaligned pointers) */
+    LAT_EUNSUPPORTED = -2,  /* valid but not provided combination (e.g. LF with self-consistent expansion) */
+    LAT_ENODEV = -3,        /* no usable GPU */
+    LAT_EHIP = -4,          /* a HIP runtime call failed; see lattice_last_error */
+    LAT_ESTATE = -5,        /* call not valid in the current state */
+    LAT_ENOMEM = -6         /* device allocation failed */
+} lat_status;
+
+/* evolution algorithm (sec. 4.3 run parameters, "evolver"; sec. 4.5.2) */
+enum lat_integrator {
+    LAT_LF = 0,    /* staggered leapfrog, 2nd order: kick then drift, momenta half a step behind */
+    LAT_VV2 = 1,   /* velocity-Verlet, 2nd order, fields and momenta at the same time */
+    LAT_VV4 = 2    /* 4th order: Yoshida triple-jump composition of three VV2 maps */
+};
+
+/* background (sec. 4.3 "expansion", "fixedBackground"; eqs. NewFriedmannEQsII, ScaleFactorPowerLaw) */
+enum lat_expansion {
+    LAT_EXP_NONE = 0,   /* a = 1 (Minkowski) */
+    LAT_EXP_FIXED = 1,  /* a(t) = a0 (1 + H0 (t - t_ref)/p)^p, p = 2/(3(1+w) - 2 alpha) */
+    LAT_EXP_SELF = 2    /* a'' from the volume-averaged field energies (second Friedmann equation) */
+};
+
+/* model (potential and field content) */
+enum lat_potential {
+    LAT_PHI4 = 0,          /* one real field, V = lambda/4 phi^4 */
+    LAT_PHI4_CHI2 = 1,     /* two real fields, V = lambda/4 phi^4 + q/2 phi^2 chi^2 (sec. 4.2) */
+    LAT_ABELIAN_HIGGS = 2  /* complex phi = (phi0 + i phi1)/sqrt(2) + U(1) links,
+                              V = lambda/4 (|phi|^2 - v^2)^2 */
+};
+
+enum lat_precision {
+    LAT_PREC_F64 = 0,      /* float64 fields and arithmetic */
+    LAT_PREC_F32 = 1       /* float32 field storage and stencil arithmetic; float64 volume
+                              reductions, scale factor, time and coefficients */
+};
+
+typedef struct lat_params {
+    int32_t N;              /* lattice points per dimension, >= 2 */
+    int32_t integrator;     /* enum lat_integrator */
+    int32_t expansion;      /* enum lat_expansion */
+    int32_t potential;      /* enum lat_potential */
+    int32_t precision;      /* enum lat_precision */
+    int32_t lf_staggered;   /* LF only: initial momentum phase, 0 = at integer time,
+                               +1/-1 = half a step behind a forward/backward run (resume) */
+    int32_t reserved0;
+    int32_t reserved1;
+    double dx;              /* lattice spacing, > 0 */
+    double dt;              /* time step, > 0, dt/dx < 1/sqrt(3) (sec. 3.1 stability rule) */
+    double t0;              /* initial time */
+    double alpha;           /* alpha-time exponent (eq. FLRWmetric) */
+    double lambda;          /* quartic coupling */
+    double q;               /* LAT_PHI4_CHI2: q = g^2/lambda */
+    double v;               /* LAT_ABELIAN_HIGGS: vacuum expectation value */
+    double e_charge;        /* LAT_ABELIAN_HIGGS: e = g_A Q_A */
+    double kappa_g;         /* LAT_ABELIAN_HIGGS: (f_star/omega_star)^2 */
+    double kappa2;          /* LAT_EXP_SELF: (f_star/m_p)^2 */
+    double w_eos;           /* LAT_EXP_FIXED: equation of state */
+    double H0;              /* LAT_EXP_FIXED: Hubble rate a'/a at t_ref */
+    double t_ref;           /* LAT_EXP_FIXED: reference time with a(t_ref) = a0 */
+    double a0;              /* LAT_EXP_SELF: initial a; LAT_EXP_FIXED: a(t_ref) */
+    double b0;              /* LAT_EXP_SELF: initial b = a'; NaN = from the Hubble constraint
+                               (eq. NewFriedmannEQsI) on the initial fields */
+} lat_params;
+
+typedef struct lat_fields {
+    void *phi[2];   /* scalar arrays: LAT_PHI4 phi[0]; LAT_PHI4_CHI2 phi[0]=phi, phi[1]=chi;
+                       LAT_ABELIAN_HIGGS the real components phi0, phi1 */
+    void *pi[2];    /* conjugate momenta pi = a^{3-alpha} phi' (sec. 4.5.2), same layout */
+    void *A[3];     /* LAT_ABELIAN_HIGGS: A_i on the link n -> n + i (sec. 3.2) */
+    void *piA[3];   /* LAT_ABELIAN_HIGGS: pi_A,i = a^{1-alpha} F_0i (sec. 5.5.2) */
+} lat_fields;
+
+typedef struct lat_energies {
+    double t, a, b;          /* time, scale factor, b = a' */
+    double EK[2];            /* kinetic energy per scalar field  <pi^2>/(2 a^6)  (eq. EK_EG_EV) */
+    double EG[2];            /* gradient energy per scalar field <sum_i (grad+ phi)^2>/(2 a^2) */
+    double EV[2];            /* potential energy per potential term */
+    double EK_A, EG_A;       /* U(1) electric and magnetic energies */
+    double rho;              /* total energy density */
+    double hubble_lhs;       /* b^2 */
+    double hubble_rhs;       /* a^{2 alpha + 2} kappa2 rho / 3 */
+    double hubble_res;       /* (lhs - rhs)/(lhs + rhs) */
+    double gauss_max;        /* U(1): max_n |G(n)|, G = div- piA - e kappa_g (phi0 pi1 - phi1 pi0) */
+    double gauss_div_max;    /* max_n |div- piA| */
+    double gauss_charge_max; /* max_n |e kappa_g (phi0 pi1 - phi1 pi0)| */
+    double gauss_mean;       /* <|G|> */
+    double gauss_sum_mean;   /* <|div- piA + charge|> */
+    int64_t step;            /* steps taken since lattice_init (signed: backward steps subtract) */
+} lat_energies;
+
+typedef struct lat_ctx lat_ctx;
+
+/* Create a context for the fields f (device pointers, see lat_fields) and
+ * validate p.  Allocates the library scratch, computes b0 from the Hubble
+ * constraint when asked, and leaves the fields untouched.
+ * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (LF with LAT_EXP_SELF; the U(1) model
+ * with another integrator than LF or with expansion), LAT_ENODEV, LAT_ENOMEM,
+ * LAT_EHIP.  On error *ctx is set to NULL. */
+lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
+
+/* Advance |nsteps| time steps (sec. 4.5.2; LF and VV of sec. 4.3), backward
+ * in time (dt -> -dt) when nsteps < 0.  For LF a backward run needs momenta at
+ * integer time or staggered backward (LAT_ESTATE otherwise; call lattice_sync).
+ * Asynchronous on the context stream. */
+lat_status lattice_step(lat_ctx *ctx, int64_t nsteps);
+
+/* LF only: half-kick the momenta to integer time in place (the sync before
+ * measurements of sec. 7.2).  The next step then starts with a half kick.
+ * No-op for VV integrators or already synchronised momenta. */
+lat_status lattice_sync(lat_ctx *ctx);
+
+/* Volume-averaged energies, Hubble and Gauss residuals of the current state
+ * (sec. 4.4 outputs; sec. 5.4 Gauss measure).  LF momenta are synchronised on
+ * the fly without writing them back.  Synchronises the stream; out is host memory. */
+lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
+
+/* Launch statistics of the stencil kernels, per kernel kind:
+ *   0 kick only, 1 kick only + reductions, 2 drift on load + kick,
+ *   3 drift on load + kick + reductions, 4 kick + drift at end (leapfrog),
+ *   5 energy (read only), 6 U(1) leapfrog, 7 U(1) energy.
+ * kernel_ms is accumulated from HIP events recorded on the context stream around
+ * each launch while profiling is on (lattice_profile); it stays 0 otherwise. */
+typedef struct lat_stats {
+    int64_t launches[8];
+    double kernel_ms[8];
+    int32_t blocks;       /* blocks per stencil launch */
+    int32_t threads;      /* threads per block */
+    int32_t tile_x, tile_y, z_chunk;
+    int32_t pad;
+} lat_stats;
+
+/* Turn event timing of every stencil launch on (enable = 1) or off (0). */
+lat_status lattice_profile(lat_ctx *ctx, int enable);
+
+/* Copy the statistics into *out (host memory; synchronises the stream when
+ * profiling); reset = 1 clears them afterwards. */
+lat_status lattice_stats(lat_ctx *ctx, int reset, lat_stats *out);
+
+/* Release the context and its scratch (waits for pending work).  NULL is ignored. */
+void lattice_destroy(lat_ctx *ctx);
+
+/* Text of the last error of ctx (NULL: last lattice_init failure on this thread). */
+const char *lattice_last_error(const lat_ctx *ctx);
+
+/* Library version string. */
+const char *lattice_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LATTICE_H */

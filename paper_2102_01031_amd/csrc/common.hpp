@@ -1,0 +1,96 @@
+// common.hpp -- device-side records shared by the kernels and the runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lat {
+
+// Coefficients of one stencil pass at a kick point p of the schedule.
+//   drift on load   phi += dload * pi            (the drift that ends at p)
+//   kernel          F = ka1 * Lap(phi) - ka3 * dV/dphi       ka1 = a^{1+alpha}, ka3 = a^{3+alpha}
+//   kicks           pi += c1 * F  (momenta now at p: energies sampled here)  pi += c2 * F
+//   drift at end    phi += dend * pi            (leapfrog, local drift)
+// Self-consistent expansion: the last block of pass p fills ka1, ka3, dload of
+// pass p+1 from the energies it reduced (see ScaleRecord).
+struct PassCoef {
+    double ka1, ka3;
+    double dload;
+    double c1, c2;
+    double dend;
+    double h;       // sub-step leaving this kick point (0 at the last point)
+    double cL, cR;  // weights of the two half kicks of b at this point
+    double t;       // time at this kick point
+    double t_next;  // time at the next kick point
+    double pad;
+};
+
+// Scale factor record on the device (self-consistent expansion) and the raw
+// volume sums of the last reducing pass.
+constexpr int kMaxQ = 16;
+struct ScaleRecord {
+    double a, b, t;
+    double pad;
+    double sums[kMaxQ];
+    double maxes[4];
+};
+
+enum LastMode : int { kLastStore = 0, kLastSelf = 1 };
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline void store_agent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double load_agent(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Logical block id from the hardware block id: consecutive hardware blocks are
+// dealt round-robin to the 8 XCDs, so give each XCD a contiguous range of
+// logical tiles (neighbouring tiles then share that XCD's L2).
+__device__ inline int xcd_logical_block(int b, int nb)
+{
+    const int per = nb / 8, rem = nb % 8;
+    const int x = b % 8, j = b / 8;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
+// Block-wide deterministic sum of NQ values per thread into out[] (valid in thread 0).
+template <int NT, int NQ>
+__device__ inline void block_sums(double (&acc)[NQ], double *lds_red, double (&out)[NQ])
+{
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double v = wave_sum(acc[q]);
+        if (lane == 0) lds_red[w * NQ + q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double s = 0.0;
+            for (int i = 0; i < NW; ++i) s += lds_red[i * NQ + q];
+            out[q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace lat

@@ -1,0 +1,827 @@
+// lattice.hip -- C-ABI runtime of the lattice field step (see include/lattice.h).
+//
+// The runtime turns a call lattice_step(n) into a schedule of stencil passes
+// (one pass per kick point) and launches them on the context stream:
+//   leapfrog   pass k: kick (half after a sync, else full) then local drift
+//   VV2 / VV4  kick points p = 0..M of the sub-step sequence (M = n or 3n);
+//              pass p: drift that ends at p (on load), kick h_{p-1}/2, sample
+//              energies, kick h_p/2.  The two half kicks that meet at an inner
+//              point share one force evaluation.
+// For a fixed or absent background every coefficient is known beforehand and
+// uploaded as a table; for self-consistent expansion the pass that samples the
+// energies at point p also advances (a, b) and writes the next pass's drift and
+// kick coefficients on the device, so no host round trip sits between passes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lattice.h"
+#include "common.hpp"
+#include "stage_scalar.hpp"
+
+using namespace lat;
+
+struct lat_ctx;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+// U(1) sector (defined at the end of this file)
+lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir);
+lat_status u1_sync(lat_ctx *c);
+lat_status u1_energy(lat_ctx *c, lat_energies *out);
+size_t u1_partial_capacity(int N);
+
+struct TileCfg {
+    int tx, ty;
+};
+constexpr TileCfg kTiles[] = {{64, 4}, {64, 8}, {32, 8}, {16, 16}, {8, 8}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+enum Variant : int {
+    kKickOnly = 0,     // no drift, kick, momenta in place (VV first point, LF sync)
+    kKickOnlyRed = 1,  // same + reductions (self-consistent first point)
+    kDriftKick = 2,    // drift on load, kick (VV inner and last points)
+    kDriftKickRed = 3, // same + reductions (self-consistent)
+    kKickDrift = 4,    // kick, drift at end (leapfrog)
+    kEnergy = 5        // kick on a copy + reductions, writes nothing
+};
+
+}  // namespace
+
+struct lat_ctx {
+    lat_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool f32 = false;
+    bool u1 = false;
+    int nf = 1;
+    int N = 0;
+    size_t vol = 0;
+    size_t esize = 8;
+    // field arrays: [0] = caller's buffer, [1] = library shadow
+    void *phi[2][2] = {};
+    void *pi[2][2] = {};
+    int cur_phi[2] = {0, 0};
+    int cur_pi[2] = {0, 0};
+    void *A[3][2] = {};
+    void *piA[3] = {};
+    int cur_A[3] = {0, 0, 0};
+    // scratch
+    double *partials = nullptr;
+    size_t partial_cap = 0;
+    unsigned *ticket = nullptr;
+    ScaleRecord *sc = nullptr;
+    ScaleRecord *sc_host = nullptr;
+    PassCoef *coef = nullptr;
+    size_t coef_cap = 0;
+    PassCoef *coef_host = nullptr;
+    size_t coef_host_cap = 0;
+    hipEvent_t upload_ev = nullptr;
+    bool upload_pending = false;
+    // host mirror of the clock
+    double t = 0.0;
+    int lf_stag = 0;
+    int64_t step = 0;
+    // launch geometry
+    int tile = 0;
+    int zc = 0;
+    int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
+    // launch statistics and optional event timing
+    int64_t launches[8] = {};
+    double kernel_ms[8] = {};
+    bool profiling = false;
+    struct Timed {
+        hipEvent_t start, stop;
+        int kind;
+    };
+    std::vector<Timed> timed;      // recorded, not yet harvested
+    std::vector<hipEvent_t> spare; // reusable events
+    std::string err;
+};
+
+namespace {
+
+lat_status fail(lat_ctx *c, lat_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ctx, LAT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// background closed form (eq. ScaleFactorPowerLaw)
+// ---------------------------------------------------------------------------
+void fixed_ab(const lat_params &p, double t, double *a, double *b)
+{
+    const double pw = 2.0 / (3.0 * (1.0 + p.w_eos) - 2.0 * p.alpha);
+    const double u = 1.0 + p.H0 * (t - p.t_ref) / pw;
+    *a = p.a0 * std::pow(u, pw);
+    *b = p.a0 * p.H0 * std::pow(u, pw - 1.0);
+}
+
+double scale_at(const lat_ctx *c, double t)
+{
+    if (c->p.expansion == LAT_EXP_FIXED) {
+        double a, b;
+        fixed_ab(c->p, t, &a, &b);
+        return a;
+    }
+    return 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+int pick_tile(int N)
+{
+    if (N % 64 == 0 && N >= 128) return 1;   // 64 x 8
+    if (N % 64 == 0) return 0;               // 64 x 4
+    if (N % 32 == 0) return 2;               // 32 x 8
+    if (N % 16 == 0) return 3;               // 16 x 16
+    return 4;                                // 8 x 8
+}
+
+void set_geometry(lat_ctx *c, int tile, int zc)
+{
+    const int N = c->N;
+    c->tile = tile;
+    c->tiles_x = (N + kTiles[tile].tx - 1) / kTiles[tile].tx;
+    c->tiles_y = (N + kTiles[tile].ty - 1) / kTiles[tile].ty;
+    if (zc <= 0) {
+        // aim at >= 1024 blocks, at least 4 planes per chunk
+        const long txy = (long)c->tiles_x * c->tiles_y;
+        long z = (long)N * txy / 1024;
+        if (z < 4) z = 4;
+        if (z > N) z = N;
+        zc = (int)z;
+    }
+    if (zc > N) zc = N;
+    c->zc = zc;
+    c->chunks_z = (N + zc - 1) / zc;
+    c->nblocks = c->tiles_x * c->tiles_y * c->chunks_z;
+}
+
+void geometry_from_env(lat_ctx *c)
+{
+    int tile = pick_tile(c->N), zc = 0;
+    if (const char *s = std::getenv("LATTICE_TILE")) {
+        int tx = 0, ty = 0, z = 0;
+        if (std::sscanf(s, "%d,%d,%d", &tx, &ty, &z) >= 2) {
+            for (int i = 0; i < kNumTiles; ++i)
+                if (kTiles[i].tx == tx && kTiles[i].ty == ty) tile = i;
+            zc = z;
+        }
+    }
+    set_geometry(c, tile, zc);
+}
+
+// ---------------------------------------------------------------------------
+// kernel dispatch
+// ---------------------------------------------------------------------------
+template <typename T, int NF, int TX, int TY>
+hipError_t launch_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+{
+    const dim3 grid(nb), block(TX * TY);
+    switch (variant) {
+    case kKickOnly:
+        hipLaunchKernelGGL((scalar_stage<T, NF, TX, TY, false, false, false, false, true>), grid, block, 0, s, a);
+        break;
+    case kKickOnlyRed:
+        hipLaunchKernelGGL((scalar_stage<T, NF, TX, TY, false, false, true, false, true>), grid, block, 0, s, a);
+        break;
+    case kDriftKick:
+        hipLaunchKernelGGL((scalar_stage<T, NF, TX, TY, true, false, false, true, true>), grid, block, 0, s, a);
+        break;
+    case kDriftKickRed:
+        hipLaunchKernelGGL((scalar_stage<T, NF, TX, TY, true, false, true, true, true>), grid, block, 0, s, a);
+        break;
+    case kKickDrift:
+        hipLaunchKernelGGL((scalar_stage<T, NF, TX, TY, false, true, false, true, true>), grid, block, 0, s, a);
+        break;
+    case kEnergy:
+        hipLaunchKernelGGL((scalar_stage<T, NF, TX, TY, false, false, true, false, false>), grid, block, 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int NF>
+hipError_t launch_tile(int tile, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+{
+    switch (tile) {
+    case 0: return launch_variant<T, NF, 64, 4>(variant, a, nb, s);
+    case 1: return launch_variant<T, NF, 64, 8>(variant, a, nb, s);
+    case 2: return launch_variant<T, NF, 32, 8>(variant, a, nb, s);
+    case 3: return launch_variant<T, NF, 16, 16>(variant, a, nb, s);
+    case 4: return launch_variant<T, NF, 8, 8>(variant, a, nb, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Which arrays a variant reads with a halo (must not be written in place) and writes.
+struct VariantIO {
+    bool wphi, wpi, pi_halo;
+};
+VariantIO variant_io(int v)
+{
+    switch (v) {
+    case kKickOnly:
+    case kKickOnlyRed: return {false, true, false};
+    case kDriftKick:
+    case kDriftKickRed: return {true, true, true};
+    case kKickDrift: return {true, true, false};
+    default: return {false, false, false};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// event timing of launches (profiling mode)
+// ---------------------------------------------------------------------------
+lat_status get_event(lat_ctx *c, hipEvent_t *ev)
+{
+    if (!c->spare.empty()) {
+        *ev = c->spare.back();
+        c->spare.pop_back();
+        return LAT_OK;
+    }
+    HIPCHK(c, hipEventCreate(ev));
+    return LAT_OK;
+}
+
+lat_status timing_begin(lat_ctx *c, hipEvent_t *e0, hipEvent_t *e1)
+{
+    lat_status s;
+    if ((s = get_event(c, e0)) != LAT_OK) return s;
+    if ((s = get_event(c, e1)) != LAT_OK) return s;
+    HIPCHK(c, hipEventRecord(*e0, c->stream));
+    return LAT_OK;
+}
+
+lat_status timing_end(lat_ctx *c, hipEvent_t e0, hipEvent_t e1, int kind)
+{
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    c->timed.push_back({e0, e1, kind});
+    return LAT_OK;
+}
+
+lat_status harvest_timing(lat_ctx *c)
+{
+    for (auto &t : c->timed) {
+        HIPCHK(c, hipEventSynchronize(t.stop));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, t.start, t.stop));
+        c->kernel_ms[t.kind] += ms;
+        c->spare.push_back(t.start);
+        c->spare.push_back(t.stop);
+    }
+    c->timed.clear();
+    return LAT_OK;
+}
+
+template <typename T>
+lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode)
+{
+    const VariantIO io = variant_io(variant);
+    ScalarArgs<T> a{};
+    for (int f = 0; f < c->nf; ++f) {
+        const int cp = c->cur_phi[f], cq = c->cur_pi[f];
+        a.phi_in[f] = (const T *)c->phi[f][cp];
+        a.pi_in[f] = (const T *)c->pi[f][cq];
+        a.phi_out[f] = io.wphi ? (T *)c->phi[f][cp ^ 1] : nullptr;
+        a.pi_out[f] = io.wpi ? (io.pi_halo ? (T *)c->pi[f][cq ^ 1] : (T *)c->pi[f][cq]) : nullptr;
+    }
+    a.N = c->N;
+    a.zc = c->zc;
+    a.tiles_x = c->tiles_x;
+    a.tiles_y = c->tiles_y;
+    a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
+    a.lam = c->p.lambda;
+    a.q = c->p.potential == LAT_PHI4_CHI2 ? c->p.q : 0.0;
+    a.coef = c->coef + pass_index;
+    a.coef_next = c->coef + pass_index + 1;
+    a.partials = c->partials;
+    a.ticket = c->ticket;
+    a.sc = c->sc;
+    a.last_mode = last_mode;
+    a.alpha = c->p.alpha;
+    a.kappa2 = c->p.kappa2;
+    a.inv_vol = 1.0 / (double)c->vol;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->profiling) {
+        lat_status st = timing_begin(c, &ev0, &ev1);
+        if (st != LAT_OK) return st;
+    }
+    hipError_t e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, c->stream)
+                              : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, c->stream);
+    if (e != hipSuccess) return fail(c, LAT_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
+    if (c->profiling) {
+        lat_status st = timing_end(c, ev0, ev1, variant);
+        if (st != LAT_OK) return st;
+    }
+    c->launches[variant] += 1;
+    for (int f = 0; f < c->nf; ++f) {
+        if (io.wphi) c->cur_phi[f] ^= 1;
+        if (io.wpi && io.pi_halo) c->cur_pi[f] ^= 1;
+    }
+    return LAT_OK;
+}
+
+lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode)
+{
+    return c->f32 ? run_pass_t<float>(c, variant, pass_index, last_mode)
+                  : run_pass_t<double>(c, variant, pass_index, last_mode);
+}
+
+// ---------------------------------------------------------------------------
+// coefficient tables
+// ---------------------------------------------------------------------------
+lat_status reserve_coef(lat_ctx *c, size_t n)
+{
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_ev));
+        c->upload_pending = false;
+    }
+    if (n > c->coef_cap) {
+        if (c->coef) HIPCHK(c, hipFree(c->coef));
+        c->coef = nullptr;
+        size_t cap = n < 64 ? 64 : n;
+        if (hipMalloc(&c->coef, cap * sizeof(PassCoef)) != hipSuccess)
+            return fail(c, LAT_ENOMEM, "coefficient table allocation failed");
+        c->coef_cap = cap;
+    }
+    if (n > c->coef_host_cap) {
+        if (c->coef_host) HIPCHK(c, hipHostFree(c->coef_host));
+        c->coef_host = nullptr;
+        size_t cap = n < 64 ? 64 : n;
+        if (hipHostMalloc((void **)&c->coef_host, cap * sizeof(PassCoef), hipHostMallocDefault) != hipSuccess)
+            return fail(c, LAT_ENOMEM, "pinned coefficient staging allocation failed");
+        c->coef_host_cap = cap;
+    }
+    std::memset(c->coef_host, 0, n * sizeof(PassCoef));
+    return LAT_OK;
+}
+
+lat_status upload_coef(lat_ctx *c, size_t n)
+{
+    HIPCHK(c, hipMemcpyAsync(c->coef, c->coef_host, n * sizeof(PassCoef), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->upload_ev, c->stream));
+    c->upload_pending = true;
+    return LAT_OK;
+}
+
+// copy shadow buffers back so the caller's arrays hold the state
+lat_status settle(lat_ctx *c)
+{
+    const size_t bytes = c->vol * c->esize;
+    for (int f = 0; f < c->nf; ++f) {
+        if (c->cur_phi[f]) {
+            HIPCHK(c, hipMemcpyAsync(c->phi[f][0], c->phi[f][1], bytes, hipMemcpyDeviceToDevice, c->stream));
+            c->cur_phi[f] = 0;
+        }
+        if (c->cur_pi[f]) {
+            HIPCHK(c, hipMemcpyAsync(c->pi[f][0], c->pi[f][1], bytes, hipMemcpyDeviceToDevice, c->stream));
+            c->cur_pi[f] = 0;
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        if (c->cur_A[i]) {
+            HIPCHK(c, hipMemcpyAsync(c->A[i][0], c->A[i][1], bytes, hipMemcpyDeviceToDevice, c->stream));
+            c->cur_A[i] = 0;
+        }
+    }
+    return LAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scalar schedules
+// ---------------------------------------------------------------------------
+lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    const double al = c->p.alpha;
+    lat_status s = reserve_coef(c, (size_t)ns + 1);
+    if (s != LAT_OK) return s;
+    const double t_start = c->t;
+    int stag = c->lf_stag;
+    for (int64_t k = 0; k < ns; ++k) {
+        PassCoef &P = c->coef_host[k];
+        const double t = t_start + (double)k * h;
+        const double a = scale_at(c, t);
+        P.ka1 = std::pow(a, 1.0 + al);
+        P.ka3 = std::pow(a, 3.0 + al);
+        P.c1 = (stag == 0) ? 0.5 * h : h;
+        P.c2 = 0.0;
+        P.dend = h * std::pow(scale_at(c, t + 0.5 * h), al - 3.0);
+        P.t = t;
+        stag = dir;
+    }
+    if ((s = upload_coef(c, (size_t)ns)) != LAT_OK) return s;
+    for (int64_t k = 0; k < ns; ++k)
+        if ((s = run_pass(c, kKickDrift, (int)k, kLastStore)) != LAT_OK) return s;
+    c->lf_stag = dir;
+    c->t = t_start + (double)ns * h;
+    return LAT_OK;
+}
+
+lat_status step_vv(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    const double al = c->p.alpha;
+    const bool self = c->p.expansion == LAT_EXP_SELF;
+    const int J = c->p.integrator == LAT_VV4 ? 3 : 1;
+    double w[3] = {1.0, 0.0, 0.0};
+    if (J == 3) {
+        const double cr = std::cbrt(2.0);
+        w[0] = 1.0 / (2.0 - cr);
+        w[1] = -cr / (2.0 - cr);
+        w[2] = w[0];
+    }
+    const int64_t M = (int64_t)J * ns;
+    lat_status s = reserve_coef(c, (size_t)M + 2);
+    if (s != LAT_OK) return s;
+    const double t_start = c->t;
+    // sub-step sizes and kick-point times
+    auto hs = [&](int64_t p) { return w[p % J] * h; };
+    auto ts = [&](int64_t p) {
+        if (p >= M) return t_start + (double)ns * h;
+        const double tk = t_start + (double)(p / J) * h;
+        switch (p % J) {
+        case 0: return tk;
+        case 1: return tk + w[0] * h;
+        default: return tk + w[0] * h + w[1] * h;
+        }
+    };
+    for (int64_t p = 0; p <= M; ++p) {
+        PassCoef &P = c->coef_host[p];
+        const double hp = p > 0 ? hs(p - 1) : 0.0;
+        const double hn = p < M ? hs(p) : 0.0;
+        P.c1 = 0.5 * hp;
+        P.c2 = 0.5 * hn;
+        P.cL = P.c1;
+        P.cR = P.c2;
+        P.h = hn;
+        P.t = ts(p);
+        P.t_next = p < M ? ts(p + 1) : ts(M);
+        P.dend = 0.0;
+        if (!self) {
+            const double a = scale_at(c, P.t);
+            P.ka1 = std::pow(a, 1.0 + al);
+            P.ka3 = std::pow(a, 3.0 + al);
+            P.dload = p > 0 ? hp * std::pow(scale_at(c, ts(p - 1) + 0.5 * hp), al - 3.0) : 0.0;
+        }
+    }
+    if ((s = upload_coef(c, (size_t)M + 2)) != LAT_OK) return s;
+    if (self) {
+        hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, c->stream, c->coef, c->sc, al);
+        HIPCHK(c, hipGetLastError());
+    }
+    const int mode = self ? kLastSelf : kLastStore;
+    for (int64_t p = 0; p <= M; ++p) {
+        const int v = p == 0 ? (self ? kKickOnlyRed : kKickOnly) : (self ? kDriftKickRed : kDriftKick);
+        if ((s = run_pass(c, v, (int)p, mode)) != LAT_OK) return s;
+    }
+    c->t = t_start + (double)ns * h;
+    return LAT_OK;
+}
+
+// energy pass + readback of the raw sums and the scale record
+lat_status energy_sums(lat_ctx *c, double kick_c1)
+{
+    lat_status s = reserve_coef(c, 2);
+    if (s != LAT_OK) return s;
+    PassCoef &P = c->coef_host[0];
+    const double a = scale_at(c, c->t);
+    P.ka1 = std::pow(a, 1.0 + c->p.alpha);
+    P.ka3 = std::pow(a, 3.0 + c->p.alpha);
+    P.c1 = kick_c1;
+    P.t = c->t;
+    if ((s = upload_coef(c, 1)) != LAT_OK) return s;
+    if (c->p.expansion == LAT_EXP_SELF && kick_c1 != 0.0) {
+        hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, c->stream, c->coef, c->sc, c->p.alpha);
+        HIPCHK(c, hipGetLastError());
+    }
+    if ((s = run_pass(c, kEnergy, 0, kLastStore)) != LAT_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LAT_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+lat_status validate(const lat_params *p, const lat_fields *f)
+{
+    if (!p || !f) return fail(nullptr, LAT_EINVAL, "null params or fields");
+    if (p->N < 2) return fail(nullptr, LAT_EINVAL, "N must be >= 2");
+    if ((double)p->N * p->N * p->N > 4.0e10) return fail(nullptr, LAT_EINVAL, "N too large");
+    if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(nullptr, LAT_EINVAL, "dx must be > 0");
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(nullptr, LAT_EINVAL, "dt must be > 0");
+    if (p->dt / p->dx >= 1.0 / std::sqrt(3.0))
+        return fail(nullptr, LAT_EINVAL, "dt/dx must be below 1/sqrt(3)");
+    if (p->integrator < LAT_LF || p->integrator > LAT_VV4) return fail(nullptr, LAT_EINVAL, "bad integrator");
+    if (p->expansion < LAT_EXP_NONE || p->expansion > LAT_EXP_SELF) return fail(nullptr, LAT_EINVAL, "bad expansion");
+    if (p->potential < LAT_PHI4 || p->potential > LAT_ABELIAN_HIGGS) return fail(nullptr, LAT_EINVAL, "bad potential");
+    if (p->precision != LAT_PREC_F64 && p->precision != LAT_PREC_F32) return fail(nullptr, LAT_EINVAL, "bad precision");
+    if (p->lf_staggered < -1 || p->lf_staggered > 1) return fail(nullptr, LAT_EINVAL, "lf_staggered must be -1, 0 or 1");
+    if (p->lf_staggered != 0 && p->integrator != LAT_LF)
+        return fail(nullptr, LAT_EINVAL, "lf_staggered needs the LF integrator");
+    if (p->integrator == LAT_LF && p->expansion == LAT_EXP_SELF)
+        return fail(nullptr, LAT_EUNSUPPORTED, "LF with self-consistent expansion is not provided");
+    if (p->expansion == LAT_EXP_FIXED) {
+        const double den = 3.0 * (1.0 + p->w_eos) - 2.0 * p->alpha;
+        if (den == 0.0 || !(p->a0 > 0.0)) return fail(nullptr, LAT_EINVAL, "bad fixed background");
+    }
+    if (p->expansion == LAT_EXP_SELF && !(p->a0 > 0.0)) return fail(nullptr, LAT_EINVAL, "a0 must be > 0");
+    const size_t al = p->precision == LAT_PREC_F32 ? 4 : 8;
+    const int nf = p->potential == LAT_PHI4 ? 1 : 2;
+    for (int i = 0; i < nf; ++i) {
+        if (!f->phi[i] || !f->pi[i]) return fail(nullptr, LAT_EINVAL, "null field pointer");
+        if (!aligned(f->phi[i], al) || !aligned(f->pi[i], al))
+            return fail(nullptr, LAT_EINVAL, "misaligned field pointer");
+    }
+    if (p->potential == LAT_ABELIAN_HIGGS) {
+        if (p->integrator != LAT_LF || p->expansion != LAT_EXP_NONE)
+            return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model is provided with LF and a = 1");
+        if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model runs in float64");
+        if (!(p->e_charge != 0.0) || !(p->kappa_g > 0.0)) return fail(nullptr, LAT_EINVAL, "bad U(1) couplings");
+        for (int i = 0; i < 3; ++i) {
+            if (!f->A[i] || !f->piA[i]) return fail(nullptr, LAT_EINVAL, "null gauge field pointer");
+            if (!aligned(f->A[i], al) || !aligned(f->piA[i], al))
+                return fail(nullptr, LAT_EINVAL, "misaligned gauge field pointer");
+        }
+    }
+    return LAT_OK;
+}
+
+void free_ctx(lat_ctx *c)
+{
+    if (!c) return;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    for (int f = 0; f < 2; ++f) {
+        if (c->phi[f][1]) (void)hipFree(c->phi[f][1]);
+        if (c->pi[f][1]) (void)hipFree(c->pi[f][1]);
+    }
+    for (int i = 0; i < 3; ++i)
+        if (c->A[i][1]) (void)hipFree(c->A[i][1]);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->ticket) (void)hipFree(c->ticket);
+    if (c->sc) (void)hipFree(c->sc);
+    if (c->coef) (void)hipFree(c->coef);
+    if (c->coef_host) (void)hipHostFree(c->coef_host);
+    if (c->sc_host) (void)hipHostFree(c->sc_host);
+    if (c->upload_ev) (void)hipEventDestroy(c->upload_ev);
+    for (auto &t : c->timed) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : c->spare) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *lattice_version(void) { return "paper_2102_01031_amd lattice 0.1 (gfx950)"; }
+
+const char *lattice_last_error(const lat_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f, void *stream)
+{
+    if (!out) return fail(nullptr, LAT_EINVAL, "null ctx pointer");
+    *out = nullptr;
+    lat_status s = validate(p, f);
+    if (s != LAT_OK) return s;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, LAT_ENODEV, "no GPU available");
+
+    lat_ctx *c = new (std::nothrow) lat_ctx();
+    if (!c) return fail(nullptr, LAT_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&c->device);
+    c->f32 = p->precision == LAT_PREC_F32;
+    c->esize = c->f32 ? 4 : 8;
+    c->u1 = p->potential == LAT_ABELIAN_HIGGS;
+    c->nf = p->potential == LAT_PHI4 ? 1 : 2;
+    c->N = p->N;
+    c->vol = (size_t)p->N * p->N * p->N;
+    c->t = p->t0;
+    c->lf_stag = p->lf_staggered;
+    geometry_from_env(c);
+    const size_t bytes = c->vol * c->esize;
+
+    auto bail = [&](lat_status st, const std::string &m) {
+        g_init_error = m;
+        free_ctx(c);
+        return st;
+    };
+    for (int i = 0; i < c->nf; ++i) {
+        c->phi[i][0] = f->phi[i];
+        c->pi[i][0] = f->pi[i];
+        if (hipMalloc(&c->phi[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
+        if (hipMalloc(&c->pi[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
+    }
+    if (c->u1) {
+        for (int i = 0; i < 3; ++i) {
+            c->A[i][0] = f->A[i];
+            c->piA[i] = f->piA[i];
+            if (hipMalloc(&c->A[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
+        }
+        // the complex scalar is read with a halo (covariant Laplacian); momenta in place
+        c->pi[0][1] = nullptr;
+        c->pi[1][1] = nullptr;
+    }
+    c->partial_cap = (size_t)(c->nblocks > 1 ? c->nblocks : 1) * kMaxQ + 64;
+    if (c->u1) c->partial_cap = u1_partial_capacity(c->N) + 64;
+    if (hipMalloc(&c->partials, c->partial_cap * sizeof(double)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&c->ticket, 64) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&c->sc, sizeof(ScaleRecord)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
+    if (hipHostMalloc((void **)&c->sc_host, sizeof(ScaleRecord), hipHostMallocDefault) != hipSuccess)
+        return bail(LAT_ENOMEM, "pinned allocation failed");
+    if (hipEventCreateWithFlags(&c->upload_ev, hipEventDisableTiming) != hipSuccess)
+        return bail(LAT_EHIP, "event creation failed");
+    if (hipMemsetAsync(c->ticket, 0, 64, c->stream) != hipSuccess) return bail(LAT_EHIP, "memset failed");
+
+    // initial scale record
+    std::memset(c->sc_host, 0, sizeof(ScaleRecord));
+    double a = 1.0, b = 0.0;
+    if (p->expansion == LAT_EXP_FIXED) fixed_ab(*p, p->t0, &a, &b);
+    if (p->expansion == LAT_EXP_SELF) {
+        a = p->a0;
+        b = p->b0;
+    }
+    c->sc_host->a = a;
+    c->sc_host->b = std::isnan(b) ? 0.0 : b;
+    c->sc_host->t = p->t0;
+    if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return bail(LAT_EHIP, "upload failed");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
+    if (p->expansion == LAT_EXP_SELF && std::isnan(p->b0)) {
+        // Hubble constraint (eq. NewFriedmannEQsI): b0^2 = a0^{2 alpha + 2} kappa2 rho / 3
+        if (energy_sums(c, 0.0) != LAT_OK) return bail(LAT_EHIP, c->err);
+        const double *S = c->sc_host->sums;
+        const int nf = c->nf;
+        double sk = 0, sg = 0, sv = 0;
+        for (int i = 0; i < nf; ++i) {
+            sk += S[i];
+            sg += S[nf + i];
+            sv += S[2 * nf + i];
+        }
+        const double V = (double)c->vol;
+        const double rho = sk / V / (2.0 * std::pow(a, 6.0)) + sg / (p->dx * p->dx) / V / (2.0 * a * a) + sv / V;
+        const double rhs = std::pow(a, 2.0 * p->alpha + 2.0) * p->kappa2 * rho / 3.0;
+        if (!(rhs >= 0.0)) return bail(LAT_EINVAL, "negative energy: Hubble constraint has no root");
+        c->sc_host->a = a;
+        c->sc_host->b = std::sqrt(rhs);
+        c->sc_host->t = p->t0;
+        if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return bail(LAT_EHIP, "upload failed");
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
+    }
+    *out = c;
+    return LAT_OK;
+}
+
+lat_status lattice_step(lat_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(nullptr, LAT_EINVAL, "null context");
+    if (nsteps == 0) return LAT_OK;
+    const int dir = nsteps > 0 ? 1 : -1;
+    const int64_t ns = nsteps > 0 ? nsteps : -nsteps;
+    if (ns > (1LL << 30)) return fail(c, LAT_EINVAL, "too many steps in one call");
+    lat_status s;
+    if (c->p.integrator == LAT_LF) {
+        if (c->lf_stag != 0 && c->lf_stag != dir)
+            return fail(c, LAT_ESTATE, "leapfrog momenta are staggered in the other direction; sync first");
+        s = c->u1 ? u1_step_lf(c, ns, dir) : step_lf(c, ns, dir);
+    } else {
+        s = step_vv(c, ns, dir);
+    }
+    if (s != LAT_OK) return s;
+    if ((s = settle(c)) != LAT_OK) return s;
+    c->step += nsteps;
+    return LAT_OK;
+}
+
+lat_status lattice_sync(lat_ctx *c)
+{
+    if (!c) return fail(nullptr, LAT_EINVAL, "null context");
+    if (c->p.integrator != LAT_LF || c->lf_stag == 0) return LAT_OK;
+    lat_status s;
+    if (c->u1) {
+        s = u1_sync(c);
+    } else {
+        if ((s = reserve_coef(c, 2)) != LAT_OK) return s;
+        PassCoef &P = c->coef_host[0];
+        const double a = scale_at(c, c->t);
+        P.ka1 = std::pow(a, 1.0 + c->p.alpha);
+        P.ka3 = std::pow(a, 3.0 + c->p.alpha);
+        P.c1 = 0.5 * c->lf_stag * c->p.dt;
+        P.t = c->t;
+        if ((s = upload_coef(c, 1)) != LAT_OK) return s;
+        s = run_pass(c, kKickOnly, 0, kLastStore);
+    }
+    if (s != LAT_OK) return s;
+    if ((s = settle(c)) != LAT_OK) return s;
+    c->lf_stag = 0;
+    return LAT_OK;
+}
+
+lat_status lattice_energy(lat_ctx *c, lat_energies *out)
+{
+    if (!c || !out) return fail(c, LAT_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    if (c->u1) return u1_energy(c, out);
+    const double c1 = (c->p.integrator == LAT_LF && c->lf_stag != 0) ? 0.5 * c->lf_stag * c->p.dt : 0.0;
+    lat_status s = energy_sums(c, c1);
+    if (s != LAT_OK) return s;
+    double a = 1.0, b = 0.0;
+    if (c->p.expansion == LAT_EXP_FIXED) fixed_ab(c->p, c->t, &a, &b);
+    if (c->p.expansion == LAT_EXP_SELF) {
+        a = c->sc_host->a;
+        b = c->sc_host->b;
+    }
+    const double *S = c->sc_host->sums;
+    const int nf = c->nf;
+    const double V = (double)c->vol;
+    double rho = 0.0;
+    for (int i = 0; i < nf; ++i) {
+        out->EK[i] = S[i] / V / (2.0 * std::pow(a, 6.0));
+        out->EG[i] = S[nf + i] / (c->p.dx * c->p.dx) / V / (2.0 * a * a);
+        out->EV[i] = S[2 * nf + i] / V;
+        rho += out->EK[i] + out->EG[i] + out->EV[i];
+    }
+    out->t = c->t;
+    out->a = a;
+    out->b = b;
+    out->rho = rho;
+    out->hubble_lhs = b * b;
+    out->hubble_rhs = std::pow(a, 2.0 * c->p.alpha + 2.0) * c->p.kappa2 * rho / 3.0;
+    const double den = out->hubble_lhs + out->hubble_rhs;
+    out->hubble_res = den != 0.0 ? (out->hubble_lhs - out->hubble_rhs) / den : 0.0;
+    out->step = c->step;
+    return LAT_OK;
+}
+
+lat_status lattice_profile(lat_ctx *c, int enable)
+{
+    if (!c) return fail(nullptr, LAT_EINVAL, "null context");
+    c->profiling = enable != 0;
+    return LAT_OK;
+}
+
+lat_status lattice_stats(lat_ctx *c, int reset, lat_stats *out)
+{
+    if (!c || !out) return fail(c, LAT_EINVAL, "null argument");
+    lat_status s = harvest_timing(c);
+    if (s != LAT_OK) return s;
+    std::memset(out, 0, sizeof(*out));
+    for (int i = 0; i < 8; ++i) {
+        out->launches[i] = c->launches[i];
+        out->kernel_ms[i] = c->kernel_ms[i];
+    }
+    out->blocks = c->nblocks;
+    out->threads = kTiles[c->tile].tx * kTiles[c->tile].ty;
+    out->tile_x = kTiles[c->tile].tx;
+    out->tile_y = kTiles[c->tile].ty;
+    out->z_chunk = c->zc;
+    if (reset) {
+        std::memset(c->launches, 0, sizeof(c->launches));
+        std::memset(c->kernel_ms, 0, sizeof(c->kernel_ms));
+    }
+    return LAT_OK;
+}
+
+void lattice_destroy(lat_ctx *c) { free_ctx(c); }
+
+}  // extern "C"
+
+namespace {
+lat_status u1_step_lf(lat_ctx *c, int64_t, int) { return fail(c, LAT_EUNSUPPORTED, "U(1) not built yet"); }
+lat_status u1_sync(lat_ctx *c) { return fail(c, LAT_EUNSUPPORTED, "U(1) not built yet"); }
+lat_status u1_energy(lat_ctx *c, lat_energies *) { return fail(c, LAT_EUNSUPPORTED, "U(1) not built yet"); }
+size_t u1_partial_capacity(int N) { return (size_t)N * N * 16; }
+}  // namespace

@@ -1,0 +1,189 @@
+"""Thin ctypes binding of the C ABI in include/lattice.h.
+
+Argument marshalling only: torch tensors supply device memory and the stream;
+every step of the lattice update runs in the HIP library.  The library must be
+built (``__graft_entry__.build()``); importing works without it, but creating a
+``Lattice`` raises if ``csrc/liblattice.so`` is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "csrc", "liblattice.so")
+
+LAT_OK, LAT_EINVAL, LAT_EUNSUPPORTED, LAT_ENODEV, LAT_EHIP, LAT_ESTATE, LAT_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "LAT_OK", -1: "LAT_EINVAL", -2: "LAT_EUNSUPPORTED", -3: "LAT_ENODEV", -4: "LAT_EHIP",
+                -5: "LAT_ESTATE", -6: "LAT_ENOMEM"}
+INTEGRATORS = {"lf": 0, "vv2": 1, "vv4": 2}
+EXPANSIONS = {"none": 0, "fixed": 1, "self": 2}
+POTENTIALS = {"phi4": 0, "phi4_chi2": 1, "abelian_higgs": 2}
+PRECISIONS = {"f64": 0, "f32": 1}
+
+
+class LatParams(C.Structure):
+    _fields_ = [("N", C.c_int32), ("integrator", C.c_int32), ("expansion", C.c_int32),
+                ("potential", C.c_int32), ("precision", C.c_int32), ("lf_staggered", C.c_int32),
+                ("reserved0", C.c_int32), ("reserved1", C.c_int32),
+                ("dx", C.c_double), ("dt", C.c_double), ("t0", C.c_double), ("alpha", C.c_double),
+                ("lam", C.c_double), ("q", C.c_double), ("v", C.c_double), ("e_charge", C.c_double),
+                ("kappa_g", C.c_double), ("kappa2", C.c_double), ("w_eos", C.c_double),
+                ("H0", C.c_double), ("t_ref", C.c_double), ("a0", C.c_double), ("b0", C.c_double)]
+
+
+class LatFields(C.Structure):
+    _fields_ = [("phi", C.c_void_p * 2), ("pi", C.c_void_p * 2), ("A", C.c_void_p * 3),
+                ("piA", C.c_void_p * 3)]
+
+
+class LatEnergies(C.Structure):
+    _fields_ = [("t", C.c_double), ("a", C.c_double), ("b", C.c_double), ("EK", C.c_double * 2),
+                ("EG", C.c_double * 2), ("EV", C.c_double * 2), ("EK_A", C.c_double),
+                ("EG_A", C.c_double), ("rho", C.c_double), ("hubble_lhs", C.c_double),
+                ("hubble_rhs", C.c_double), ("hubble_res", C.c_double), ("gauss_max", C.c_double),
+                ("gauss_div_max", C.c_double), ("gauss_charge_max", C.c_double),
+                ("gauss_mean", C.c_double), ("gauss_sum_mean", C.c_double), ("step", C.c_int64)]
+
+
+KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1_lf", "u1_energy"]
+
+
+class LatStats(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("kernel_ms", C.c_double * 8), ("blocks", C.c_int32),
+                ("threads", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
+                ("z_chunk", C.c_int32), ("pad", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.lattice_init.argtypes = [C.POINTER(vp), C.POINTER(LatParams), C.POINTER(LatFields), vp]
+        L.lattice_init.restype = C.c_int
+        L.lattice_step.argtypes = [vp, C.c_int64]
+        L.lattice_step.restype = C.c_int
+        L.lattice_sync.argtypes = [vp]
+        L.lattice_sync.restype = C.c_int
+        L.lattice_energy.argtypes = [vp, C.POINTER(LatEnergies)]
+        L.lattice_energy.restype = C.c_int
+        L.lattice_destroy.argtypes = [vp]
+        L.lattice_destroy.restype = None
+        L.lattice_last_error.argtypes = [vp]
+        L.lattice_last_error.restype = C.c_char_p
+        L.lattice_version.restype = C.c_char_p
+        L.lattice_stats.argtypes = [vp, C.c_int, C.POINTER(LatStats)]
+        L.lattice_stats.restype = C.c_int
+        L.lattice_profile.argtypes = [vp, C.c_int]
+        L.lattice_profile.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def declared_symbols(header: str | None = None) -> list[str]:
+    """Names of the functions declared in include/lattice.h."""
+    header = header or os.path.join(os.path.dirname(HERE), "include", "lattice.h")
+    txt = open(header).read()
+    return sorted(set(re.findall(r"\b(lattice_\w+)\s*\(", txt)))
+
+
+class LatticeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code, ctx=None):
+    if code != LAT_OK:
+        msg = lib().lattice_last_error(ctx).decode()
+        raise LatticeError(code, msg)
+
+
+def make_params(N, dx, dt, integrator="lf", expansion="none", potential="phi4", precision="f64", t0=0.0,
+                alpha=1.0, lam=1.0, q=0.0, v=1.0, e=0.5, kappa_g=1.0, kappa2=0.25, w_eos=1.0 / 3.0, H0=0.0,
+                t_ref=0.0, a0=1.0, b0=math.nan, lf_staggered=0) -> LatParams:
+    return LatParams(N, INTEGRATORS[integrator], EXPANSIONS[expansion], POTENTIALS[potential],
+                     PRECISIONS[precision], lf_staggered, 0, 0, dx, dt, t0, alpha, lam, q, v, e, kappa_g,
+                     kappa2, w_eos, H0, t_ref, a0, b0)
+
+
+class Lattice:
+    """One lattice context bound to torch tensors (state is updated in place).
+
+    phi, pi: lists of contiguous CUDA tensors of N^3 elements (float64, or float32
+    with precision="f32").  For the Abelian-Higgs model also A and piA (3 each).
+    """
+
+    def __init__(self, phi, pi, *, A=None, piA=None, stream=None, **kw):
+        import torch
+        self._torch = torch
+        self.params = make_params(**kw)
+        dtype = torch.float32 if kw.get("precision", "f64") == "f32" else torch.float64
+        N = kw["N"]
+        self._keep = list(phi) + list(pi) + list(A or []) + list(piA or [])
+        for t in self._keep:
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and t.numel() == N ** 3):
+                raise ValueError("fields must be contiguous CUDA tensors of N^3 elements with the run's dtype")
+        f = LatFields()
+        for i, t in enumerate(phi):
+            f.phi[i] = t.data_ptr()
+        for i, t in enumerate(pi):
+            f.pi[i] = t.data_ptr()
+        for i, t in enumerate(A or []):
+            f.A[i] = t.data_ptr()
+        for i, t in enumerate(piA or []):
+            f.piA[i] = t.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._ctx = C.c_void_p()
+        rc = lib().lattice_init(C.byref(self._ctx), C.byref(self.params), C.byref(f),
+                                C.c_void_p(stream.cuda_stream))
+        _check(rc, None)
+
+    def step(self, n: int):
+        _check(lib().lattice_step(self._ctx, int(n)), self._ctx)
+        return self
+
+    def sync(self):
+        _check(lib().lattice_sync(self._ctx), self._ctx)
+        return self
+
+    def energy(self) -> dict:
+        e = LatEnergies()
+        _check(lib().lattice_energy(self._ctx, C.byref(e)), self._ctx)
+        return dict(t=e.t, a=e.a, b=e.b, EK=list(e.EK), EG=list(e.EG), EV=list(e.EV), EK_A=e.EK_A,
+                    EG_A=e.EG_A, rho=e.rho, hubble_lhs=e.hubble_lhs, hubble_rhs=e.hubble_rhs,
+                    hubble_res=e.hubble_res, gauss_max=e.gauss_max, gauss_div_max=e.gauss_div_max,
+                    gauss_charge_max=e.gauss_charge_max, gauss_mean=e.gauss_mean,
+                    gauss_sum_mean=e.gauss_sum_mean, step=e.step)
+
+    def profile(self, enable: bool = True):
+        _check(lib().lattice_profile(self._ctx, 1 if enable else 0), self._ctx)
+        return self
+
+    def stats(self, reset: bool = False) -> dict:
+        s = LatStats()
+        _check(lib().lattice_stats(self._ctx, 1 if reset else 0, C.byref(s)), self._ctx)
+        return dict(launches={k: s.launches[i] for i, k in enumerate(KERNEL_KINDS)},
+                    kernel_ms={k: s.kernel_ms[i] for i, k in enumerate(KERNEL_KINDS)},
+                    blocks=s.blocks, threads=s.threads, tile=(s.tile_x, s.tile_y), z_chunk=s.z_chunk)
+
+    def close(self):
+        if self._ctx:
+            lib().lattice_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every symbol include/lattice.h declares and
+validates its arguments before touching a device (no compute calls here)."""
+import ctypes as C
+import math
+import os
+
+import pytest
+
+from paper_2102_01031_amd import lattice as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_built_and_exports_header_symbols():
+    lib = L.lib()
+    names = L.declared_symbols()
+    assert {"lattice_init", "lattice_step", "lattice_energy", "lattice_destroy", "lattice_sync"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert b"gfx950" in lib.lattice_version()
+
+
+def test_no_oracle_in_product_path():
+    pkg = os.path.join(ROOT, "paper_2102_01031_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "lattice_oracle" not in txt, f
+
+
+def _fields(nf=1, u1=False):
+    f = L.LatFields()
+    for i in range(2):
+        f.phi[i] = 0x10000 + 0x1000 * i
+        f.pi[i] = 0x20000 + 0x1000 * i
+    if u1:
+        for i in range(3):
+            f.A[i] = 0x30000 + 0x1000 * i
+            f.piA[i] = 0x40000 + 0x1000 * i
+    return f
+
+
+def _init(params, fields):
+    ctx = C.c_void_p()
+    rc = L.lib().lattice_init(C.byref(ctx), C.byref(params), C.byref(fields), None)
+    return rc, ctx
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=1, dx=0.5, dt=0.01), L.LAT_EINVAL),
+    (dict(N=8, dx=0.5, dt=0.3), L.LAT_EINVAL),          # dt/dx above 1/sqrt(3)
+    (dict(N=8, dx=-1.0, dt=0.01), L.LAT_EINVAL),
+    (dict(N=8, dx=0.5, dt=0.01, integrator="lf", expansion="self"), L.LAT_EUNSUPPORTED),
+    (dict(N=8, dx=0.5, dt=0.01, potential="abelian_higgs", integrator="vv2"), L.LAT_EUNSUPPORTED),
+    (dict(N=8, dx=0.5, dt=0.01, integrator="vv2", lf_staggered=1), L.LAT_EINVAL),
+])
+def test_validation_errors(kw, code):
+    p = L.make_params(**kw)
+    rc, ctx = _init(p, _fields(2, True))
+    assert rc == code
+    assert not ctx.value
+    assert L.lib().lattice_last_error(None)
+
+
+def test_null_and_misaligned_pointers():
+    p = L.make_params(N=8, dx=0.5, dt=0.01, potential="phi4_chi2")
+    f = _fields(2)
+    f.pi[1] = None
+    assert _init(p, f)[0] == L.LAT_EINVAL
+    f = _fields(2)
+    f.phi[1] = 0x10003
+    assert _init(p, f)[0] == L.LAT_EINVAL
+
+
+def test_no_device_here_reports_enodev():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = L.make_params(N=8, dx=0.5, dt=0.01, integrator="vv4", expansion="self", potential="phi4_chi2", b0=math.nan)
+    rc, ctx = _init(p, _fields(2))
+    assert rc == L.LAT_ENODEV
+    assert b"GPU" in L.lib().lattice_last_error(None)
+
+
+def test_null_context_calls():
+    lib = L.lib()
+    assert lib.lattice_step(None, 1) == L.LAT_EINVAL
+    assert lib.lattice_sync(None) == L.LAT_EINVAL
+    e = L.LatEnergies()
+    assert lib.lattice_energy(None, C.byref(e)) == L.LAT_EINVAL
+    lib.lattice_destroy(None)

@@ -1,0 +1,189 @@
+"""GPU parity of the scalar-sector HIP path against the FP64 oracle on the same
+seeded inputs (float64: 1e-12 relative, max-norm per array and per energy).
+
+Sizes span several tiles and ragged tails (forced tile shapes), the workloads'
+full sizes in the launch configuration the benchmark times, tiny lattices,
+reversibility, determinism and the leapfrog sync semantics."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import (compare_energy, compare_state, gpu_scalar, oracle_model, rel_maxdiff, say,
+                      scalar_kwargs, tile_env, to_dev)
+from paper_2102_01031_amd import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_01031_amd import lattice
+    lattice.lib()
+
+
+def check_run(kw, phi, pi, steps, tol=TOL, tile=None, what=""):
+    say(f"[parity] {what} N={kw['N']} {kw['integrator']} {kw['expansion']} steps={steps} tile={tile}")
+    with tile_env(tile):
+        lat, tp, tq = gpu_scalar(kw, phi, pi, [steps])
+        eg = lat.energy()
+    st = oracle.ScalarState(oracle_model(kw), phi, pi, t=kw.get("t0", 0.0)).run(steps)
+    err = compare_state(tp, tq, st, tol, what)
+    compare_energy(eg, st.energy(), tol, what)
+    lat.close()
+    return err
+
+
+def test_lphi4_32_full_run():
+    """Single field, fixed radiation background, 1000 leapfrog steps (the full run)."""
+    wl = workloads.LPHI4_32
+    phi, pi = wl.initial_fields()
+    check_run(scalar_kwargs(wl), phi, pi, wl.steps, what="lphi4-32")
+
+
+@pytest.mark.parametrize("tile", [None, "64,4,5", "32,8,7", "16,16,3", "8,8,11", "64,8,36"])
+def test_preheat_ragged_tiles(tile):
+    wl = workloads.PREHEAT_128
+    N = 36
+    phi, pi = wl.initial_fields(N=N)
+    check_run(scalar_kwargs(wl, N=N), phi, pi, 6, tile=tile, what="preheat-36")
+
+
+@pytest.mark.parametrize("integ,expn", [("vv2", "self"), ("vv2", "none"), ("vv2", "fixed"), ("vv4", "fixed"),
+                                        ("vv4", "none"), ("lf", "none"), ("lf", "fixed")])
+def test_integrator_expansion_matrix(integ, expn):
+    wl = workloads.PREHEAT_128
+    N = 20
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N, integrator=integ, expansion=expn)
+    check_run(kw, phi, pi, 9, what=f"{integ}-{expn}")
+
+
+def test_preheat_128_full_size():
+    wl = workloads.PREHEAT_128
+    phi, pi = wl.initial_fields()
+    check_run(scalar_kwargs(wl), phi, pi, wl.steps, what="preheat-128")
+
+
+def test_preheat_256_bench_config():
+    """The benchmark workload (256^3, two fields, VV4, self-consistent) in the
+    benchmark's launch configuration, one step against the oracle."""
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields()
+    check_run(scalar_kwargs(wl), phi, pi, 1, what="preheat-256")
+
+
+@pytest.mark.parametrize("N", [2, 3, 5, 7])
+def test_tiny_lattices(N):
+    wl = workloads.PREHEAT_128
+    phi, pi = wl.initial_fields(N=N)
+    for integ, expn in (("vv4", "self"), ("lf", "fixed")):
+        check_run(scalar_kwargs(wl, N=N, integrator=integ, expansion=expn), phi, pi, 5, what=f"tiny-{N}")
+
+
+def test_single_field_vv_self():
+    wl = workloads.LPHI4_32
+    phi, pi = wl.initial_fields(N=24)
+    kw = scalar_kwargs(wl, N=24, integrator="vv4", expansion="self")
+    check_run(kw, phi, pi, 10, what="lphi4-vv4-self")
+
+
+def test_reversibility_on_gpu():
+    import torch
+    wl = workloads.PREHEAT_128
+    N = 32
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    lat, tp, tq = gpu_scalar(kw, phi, pi, [15, -15])
+    e = lat.energy()
+    for s in range(2):
+        assert rel_maxdiff(tp[s].cpu().numpy(), phi[s]) < 1e-12
+        assert rel_maxdiff(tq[s].cpu().numpy(), pi[s]) < 1e-11
+    st0 = oracle.ScalarState(oracle_model(kw), phi, pi)
+    assert abs(e["a"] - 1.0) < 1e-14 and abs(e["b"] - st0.b) < 1e-14 * st0.b and abs(e["t"]) < 1e-15
+    lat.close()
+
+
+def test_determinism_bitwise():
+    wl = workloads.PREHEAT_128
+    N = 48
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    outs = []
+    for _ in range(2):
+        lat, tp, tq = gpu_scalar(kw, phi, pi, [7])
+        e = lat.energy()
+        outs.append(([t.cpu().numpy().copy() for t in tp + tq], e["a"], e["b"], e["rho"]))
+        lat.close()
+    for x, y in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(x, y)
+    assert outs[0][1:] == outs[1][1:]
+
+
+def test_step_chunking_is_invariant():
+    """n steps in one call or in several calls give the same trajectory."""
+    wl = workloads.PREHEAT_128
+    N = 24
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    la, ta, qa = gpu_scalar(kw, phi, pi, [12])
+    lb, tb, qb = gpu_scalar(kw, phi, pi, [5, 4, 3])
+    for x, y in zip(ta + qa, tb + qb):
+        assert rel_maxdiff(x.cpu().numpy(), y.cpu().numpy()) < 1e-14
+    assert abs(la.energy()["a"] - lb.energy()["a"]) < 1e-15
+    la.close()
+    lb.close()
+
+
+def test_lf_sync_semantics():
+    """Energy of a staggered leapfrog state uses synchronised momenta without
+    writing them; lattice_sync writes them (sec. 7.2 sync)."""
+    from paper_2102_01031_amd.lattice import LatticeError, LAT_ESTATE
+    wl = workloads.LPHI4_32
+    N = 24
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    lat, tp, tq = gpu_scalar(kw, phi, pi, [11])
+    before = [t.cpu().numpy().copy() for t in tq]
+    eg = lat.energy()
+    after = [t.cpu().numpy() for t in tq]
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(11)
+    compare_energy(eg, st.energy(), TOL, "lf-stag")
+    with pytest.raises(LatticeError) as ei:
+        lat.step(-1)
+    assert ei.value.code == LAT_ESTATE
+    lat.sync()
+    st.sync()
+    compare_state(tp, tq, st, TOL, "lf-synced")
+    lat.step(-11).sync()
+    st.run(-11).sync()
+    compare_state(tp, tq, st, TOL, "lf-back")
+    assert rel_maxdiff(tp[0].cpu().numpy(), phi[0]) < 1e-13
+    lat.close()
+
+
+def test_fp32_mode_error_is_stated():
+    """float32 fields, float64 reductions and scale factor, against the float64
+    oracle: the measured error is printed and must stay within a float32 budget."""
+    wl = workloads.PREHEAT_128
+    N = 64
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    steps = 20
+    lat, tp, tq = gpu_scalar(kw, phi, pi, [steps], precision="f32")
+    eg = lat.energy()
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(steps)
+    eo = st.energy()
+    ephi = max(rel_maxdiff(tp[s].cpu().numpy(), st.phi[s]) for s in range(2))
+    epi = max(rel_maxdiff(tq[s].cpu().numpy(), st.pi[s]) for s in range(2))
+    erho = abs(eg["rho"] - eo["rho"]) / eo["rho"]
+    ea = abs(eg["a"] - eo["a"]) / eo["a"]
+    say(f"[fp32] N={N} steps={steps}: phi {ephi:.2e} pi {epi:.2e} rho {erho:.2e} a {ea:.2e}")
+    assert ephi < 2e-6 and epi < 2e-4 and erho < 1e-5 and ea < 1e-7
+    lat.close()
