@@ -774,9 +774,14 @@ static void u1_energy_plain(const orc_u1_params *p, double *const *phi, double *
                 double u = m2 - p->v * p->v;
                 nadd(&sv, 0.25 * p->lambda * u * u);
                 nadd(&ska, ka / (2.0 * p->kappa_g));
+                /* 1 - cos(theta) written as 2 sin^2(theta/2): the same quantity without
+                   the cancellation that loses all digits for small plaquette angles */
                 double mag = 0.0;
                 for (int i = 0; i < 3; ++i)
-                    for (int j = i + 1; j < 3; ++j) mag += 1.0 - cos(theta(p, A, x, y, z, i, j));
+                    for (int j = i + 1; j < 3; ++j) {
+                        double sh = sin(0.5 * theta(p, A, x, y, z, i, j));
+                        mag += 2.0 * sh * sh;
+                    }
                 nadd(&sga, mag / (p->kappa_g * e * e * dx * dx * dx * dx));
                 double charge = e * p->kappa_g * (phi[0][n] * pi[1][n] - phi[1][n] * pi[0][n]);
                 double G = div - charge;

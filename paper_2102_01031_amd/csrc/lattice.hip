@@ -24,6 +24,7 @@
 #include "lattice.h"
 #include "common.hpp"
 #include "stage_scalar.hpp"
+#include "stage_rows.hpp"
 
 using namespace lat;
 
@@ -92,6 +93,8 @@ struct lat_ctx {
     int64_t step = 0;
     // launch geometry
     int tile = 0;
+    bool rows = false;   // whole-row kernel (N = 64 * XS)
+    int rows_ty = 8;
     int zc = 0;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
     // launch statistics and optional event timing
@@ -156,36 +159,68 @@ int pick_tile(int N)
     return 4;                                // 8 x 8
 }
 
+bool rows_ok(int N) { return N == 64 || N == 128 || N == 256; }
+
+int auto_chunk(int N, long xy_blocks, long target)
+{
+    long z = (long)N * xy_blocks / target;
+    if (z < 4) z = 4;
+    if (z > N) z = N;
+    return (int)z;
+}
+
 void set_geometry(lat_ctx *c, int tile, int zc)
 {
     const int N = c->N;
+    c->rows = false;
     c->tile = tile;
     c->tiles_x = (N + kTiles[tile].tx - 1) / kTiles[tile].tx;
     c->tiles_y = (N + kTiles[tile].ty - 1) / kTiles[tile].ty;
-    if (zc <= 0) {
-        // aim at >= 1024 blocks, at least 4 planes per chunk
-        const long txy = (long)c->tiles_x * c->tiles_y;
-        long z = (long)N * txy / 1024;
-        if (z < 4) z = 4;
-        if (z > N) z = N;
-        zc = (int)z;
-    }
+    if (zc <= 0) zc = auto_chunk(N, (long)c->tiles_x * c->tiles_y, 512);
     if (zc > N) zc = N;
     c->zc = zc;
     c->chunks_z = (N + zc - 1) / zc;
     c->nblocks = c->tiles_x * c->tiles_y * c->chunks_z;
 }
 
+void set_rows_geometry(lat_ctx *c, int ty, int zc)
+{
+    const int N = c->N;
+    c->rows = true;
+    c->rows_ty = ty;
+    c->tiles_x = 1;
+    c->tiles_y = (N + ty - 1) / ty;
+    if (zc <= 0) zc = auto_chunk(N, c->tiles_y, 256);
+    if (zc > N) zc = N;
+    c->zc = zc;
+    c->chunks_z = (N + zc - 1) / zc;
+    c->nblocks = c->tiles_y * c->chunks_z;
+}
+
 void geometry_from_env(lat_ctx *c)
 {
+    const char *s = std::getenv("LATTICE_TILE");
+    if (s && std::strncmp(s, "rows", 4) == 0 && rows_ok(c->N)) {
+        int ty = 8, z = 0;
+        std::sscanf(s + 4, ",%d,%d", &ty, &z);
+        if (ty != 4) ty = 8;
+        set_rows_geometry(c, ty, z);
+        return;
+    }
     int tile = pick_tile(c->N), zc = 0;
-    if (const char *s = std::getenv("LATTICE_TILE")) {
+    if (s) {
         int tx = 0, ty = 0, z = 0;
         if (std::sscanf(s, "%d,%d,%d", &tx, &ty, &z) >= 2) {
             for (int i = 0; i < kNumTiles; ++i)
                 if (kTiles[i].tx == tx && kTiles[i].ty == ty) tile = i;
             zc = z;
+            set_geometry(c, tile, zc);
+            return;
         }
+    }
+    if (rows_ok(c->N)) {
+        set_rows_geometry(c, 8, 0);
+        return;
     }
     set_geometry(c, tile, zc);
 }
@@ -220,6 +255,51 @@ hipError_t launch_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T, int NF, int XS, int TY>
+hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+{
+    const dim3 grid(nb), block(64 * TY);
+    switch (variant) {
+    case kKickOnly:
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true>), grid, block, 0, s, a);
+        break;
+    case kKickOnlyRed:
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true>), grid, block, 0, s, a);
+        break;
+    case kDriftKick:
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true>), grid, block, 0, s, a);
+        break;
+    case kDriftKickRed:
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true>), grid, block, 0, s, a);
+        break;
+    case kKickDrift:
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true>), grid, block, 0, s, a);
+        break;
+    case kEnergy:
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false>), grid, block, 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int NF>
+hipError_t launch_rows(int N, int ty, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+{
+    const int xs = N / 64;
+    if (ty == 4) {
+        if (xs == 1) return launch_rows_variant<T, NF, 1, 4>(variant, a, nb, s);
+        if (xs == 2) return launch_rows_variant<T, NF, 2, 4>(variant, a, nb, s);
+        if (xs == 4) return launch_rows_variant<T, NF, 4, 4>(variant, a, nb, s);
+    } else {
+        if (xs == 1) return launch_rows_variant<T, NF, 1, 8>(variant, a, nb, s);
+        if (xs == 2) return launch_rows_variant<T, NF, 2, 8>(variant, a, nb, s);
+        if (xs == 4) return launch_rows_variant<T, NF, 4, 8>(variant, a, nb, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int NF>
@@ -328,8 +408,13 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode)
         lat_status st = timing_begin(c, &ev0, &ev1);
         if (st != LAT_OK) return st;
     }
-    hipError_t e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, c->stream)
-                              : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, c->stream);
+    hipError_t e;
+    if (c->rows)
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, variant, a, c->nblocks, c->stream)
+                       : launch_rows<T, 2>(c->N, c->rows_ty, variant, a, c->nblocks, c->stream);
+    else
+        e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, c->stream)
+                       : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, c->stream);
     if (e != hipSuccess) return fail(c, LAT_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
     if (c->profiling) {
         lat_status st = timing_end(c, ev0, ev1, variant);
@@ -804,9 +889,9 @@ lat_status lattice_stats(lat_ctx *c, int reset, lat_stats *out)
         out->kernel_ms[i] = c->kernel_ms[i];
     }
     out->blocks = c->nblocks;
-    out->threads = kTiles[c->tile].tx * kTiles[c->tile].ty;
-    out->tile_x = kTiles[c->tile].tx;
-    out->tile_y = kTiles[c->tile].ty;
+    out->threads = c->rows ? 64 * c->rows_ty : kTiles[c->tile].tx * kTiles[c->tile].ty;
+    out->tile_x = c->rows ? c->N : kTiles[c->tile].tx;
+    out->tile_y = c->rows ? c->rows_ty : kTiles[c->tile].ty;
     out->z_chunk = c->zc;
     if (reset) {
         std::memset(c->launches, 0, sizeof(c->launches));

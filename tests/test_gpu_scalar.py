@@ -54,6 +54,17 @@ def test_preheat_ragged_tiles(tile):
     check_run(scalar_kwargs(wl, N=N), phi, pi, 6, tile=tile, what="preheat-36")
 
 
+@pytest.mark.parametrize("N,tile", [(64, "rows,8,5"), (64, "rows,4,64"), (128, "rows,8,9"), (128, "rows,4,23"),
+                                    (64, None), (128, None)])
+def test_preheat_whole_row_kernel(N, tile):
+    """The whole-row kernel (N = 64, 128, 256) with ragged z chunks."""
+    wl = workloads.PREHEAT_128
+    phi, pi = wl.initial_fields(N=N)
+    check_run(scalar_kwargs(wl, N=N), phi, pi, 3, tile=tile, what=f"rows-{N}")
+    kw = scalar_kwargs(wl, N=N, integrator="lf", expansion="fixed")
+    check_run(kw, phi, pi, 4, tile=tile, what=f"rows-lf-{N}")
+
+
 @pytest.mark.parametrize("integ,expn", [("vv2", "self"), ("vv2", "none"), ("vv2", "fixed"), ("vv4", "fixed"),
                                         ("vv4", "none"), ("lf", "none"), ("lf", "fixed")])
 def test_integrator_expansion_matrix(integ, expn):

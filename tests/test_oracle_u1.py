@@ -158,3 +158,21 @@ def test_u1_reversibility(orc):
     st = orc.U1State(m, *s0).run(30).sync().run(-30).sync()
     for x, y in zip(st.phi + st.pi + st.A + st.piA, s0[0] + s0[1] + s0[2] + s0[3]):
         assert np.max(np.abs(x - y)) < 1e-12
+
+
+def test_magnetic_energy_small_angle_limit(orc):
+    """For small plaquette angles the compact magnetic energy tends to the
+    non-compact sum of 1/2 (grad+_i A_j - grad+_j A_i)^2 (U(1) toolkit expressions),
+    with no loss of digits from cancellation."""
+    N = 5
+    m = model(orc, N, e=0.7, kappa_g=1.0)
+    phi, pi, A, piA = rand_u1(orc, N, Aamp=1e-5)
+    E = orc.U1State(m, phi, pi, A, piA).energy()["EG_A"]
+    a3 = [a.reshape(N, N, N) for a in A]
+    d = lambda f, ax: (np.roll(f, -1, axis=2 - ax) - f) / m.dx     # forward difference along x/y/z
+    F2 = 0.0
+    for i in range(3):
+        for j in range(i + 1, 3):
+            F2 += np.sum((d(a3[j], i) - d(a3[i], j)) ** 2) / 2
+    noncompact = F2 / N ** 3
+    assert abs(E - noncompact) <= 1e-8 * noncompact
