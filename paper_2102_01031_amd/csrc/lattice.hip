@@ -25,6 +25,7 @@
 #include "common.hpp"
 #include "stage_scalar.hpp"
 #include "stage_rows.hpp"
+#include "stage_u1.hpp"
 
 using namespace lat;
 
@@ -727,7 +728,9 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
         c->phi[i][0] = f->phi[i];
         c->pi[i][0] = f->pi[i];
         if (hipMalloc(&c->phi[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
-        if (hipMalloc(&c->pi[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
+        // U(1) momenta are read at their own site only and updated in place
+        if (!c->u1 && hipMalloc(&c->pi[i][1], bytes) != hipSuccess)
+            return bail(LAT_ENOMEM, "shadow allocation failed");
     }
     if (c->u1) {
         for (int i = 0; i < 3; ++i) {
@@ -735,9 +738,6 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
             c->piA[i] = f->piA[i];
             if (hipMalloc(&c->A[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
         }
-        // the complex scalar is read with a halo (covariant Laplacian); momenta in place
-        c->pi[0][1] = nullptr;
-        c->pi[1][1] = nullptr;
     }
     c->partial_cap = (size_t)(c->nblocks > 1 ? c->nblocks : 1) * kMaxQ + 64;
     if (c->u1) c->partial_cap = u1_partial_capacity(c->N) + 64;
@@ -904,9 +904,124 @@ void lattice_destroy(lat_ctx *c) { free_ctx(c); }
 
 }  // extern "C"
 
+// ===========================================================================
+// U(1) sector (a = 1, leapfrog)
+// ===========================================================================
 namespace {
-lat_status u1_step_lf(lat_ctx *c, int64_t, int) { return fail(c, LAT_EUNSUPPORTED, "U(1) not built yet"); }
-lat_status u1_sync(lat_ctx *c) { return fail(c, LAT_EUNSUPPORTED, "U(1) not built yet"); }
-lat_status u1_energy(lat_ctx *c, lat_energies *) { return fail(c, LAT_EUNSUPPORTED, "U(1) not built yet"); }
-size_t u1_partial_capacity(int N) { return (size_t)N * N * 16; }
+
+constexpr int kU1TX = 64, kU1TY = 4;
+
+size_t u1_partial_capacity(int N)
+{
+    const size_t tiles = (size_t)((N + kU1TX - 1) / kU1TX) * ((N + kU1TY - 1) / kU1TY) * (size_t)N;
+    return tiles * (kU1Sums + kU1Maxes);
+}
+
+U1Args u1_args(lat_ctx *c, double ck, double hd, bool write_fields)
+{
+    U1Args a{};
+    for (int i = 0; i < 2; ++i) {
+        a.phi_in[i] = (const double *)c->phi[i][c->cur_phi[i]];
+        a.phi_out[i] = write_fields ? (double *)c->phi[i][c->cur_phi[i] ^ 1] : nullptr;
+        a.pi[i] = (double *)c->pi[i][0];
+    }
+    for (int i = 0; i < 3; ++i) {
+        a.A_in[i] = (const double *)c->A[i][c->cur_A[i]];
+        a.A_out[i] = write_fields ? (double *)c->A[i][c->cur_A[i] ^ 1] : nullptr;
+        a.piA[i] = (double *)c->piA[i];
+    }
+    a.N = c->N;
+    a.tiles_x = (c->N + kU1TX - 1) / kU1TX;
+    a.tiles_y = (c->N + kU1TY - 1) / kU1TY;
+    a.dx = c->p.dx;
+    a.e = c->p.e_charge;
+    a.lam = c->p.lambda;
+    a.v = c->p.v;
+    a.kappa_g = c->p.kappa_g;
+    a.ck = ck;
+    a.hd = hd;
+    a.partials = c->partials;
+    a.ticket = c->ticket;
+    a.sc = c->sc;
+    return a;
+}
+
+lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
+{
+    const int nb = a.tiles_x * a.tiles_y * c->N;
+    const int kind = mode == kU1Energy ? 7 : 6;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->profiling) {
+        lat_status st = timing_begin(c, &ev0, &ev1);
+        if (st != LAT_OK) return st;
+    }
+    switch (mode) {
+    case kU1Step:
+        hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Step>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
+        break;
+    case kU1Kick:
+        hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Kick>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
+        break;
+    default:
+        hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Energy>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
+        break;
+    }
+    HIPCHK(c, hipGetLastError());
+    if (c->profiling) {
+        lat_status st = timing_end(c, ev0, ev1, kind);
+        if (st != LAT_OK) return st;
+    }
+    c->launches[kind] += 1;
+    return LAT_OK;
+}
+
+lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    int stag = c->lf_stag;
+    for (int64_t k = 0; k < ns; ++k) {
+        const double ck = stag == 0 ? 0.5 * h : h;
+        lat_status s = u1_launch(c, kU1Step, u1_args(c, ck, h, true));
+        if (s != LAT_OK) return s;
+        for (int i = 0; i < 2; ++i) c->cur_phi[i] ^= 1;
+        for (int i = 0; i < 3; ++i) c->cur_A[i] ^= 1;
+        stag = dir;
+    }
+    c->lf_stag = dir;
+    c->t += (double)ns * h;
+    return LAT_OK;
+}
+
+lat_status u1_sync(lat_ctx *c)
+{
+    return u1_launch(c, kU1Kick, u1_args(c, 0.5 * c->lf_stag * c->p.dt, 0.0, false));
+}
+
+lat_status u1_energy(lat_ctx *c, lat_energies *out)
+{
+    const double ck = c->lf_stag != 0 ? 0.5 * c->lf_stag * c->p.dt : 0.0;
+    lat_status s = u1_launch(c, kU1Energy, u1_args(c, ck, 0.0, false));
+    if (s != LAT_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double V = (double)c->vol;
+    const double *S = c->sc_host->sums, *M = c->sc_host->maxes;
+    out->t = c->t;
+    out->a = 1.0;
+    out->b = 0.0;
+    out->EK[0] = S[0] / V;
+    out->EG[0] = S[1] / V;
+    out->EV[0] = S[2] / V;
+    out->EK_A = S[3] / V;
+    out->EG_A = S[4] / V;
+    out->rho = out->EK[0] + out->EG[0] + out->EV[0] + out->EK_A + out->EG_A;
+    out->gauss_mean = S[5] / V;
+    out->gauss_sum_mean = S[6] / V;
+    out->gauss_max = M[0];
+    out->gauss_div_max = M[1];
+    out->gauss_charge_max = M[2];
+    out->step = c->step;
+    return LAT_OK;
+}
+
 }  // namespace

@@ -1,0 +1,130 @@
+"""GPU parity of the U(1) (Abelian-Higgs, compact links, leapfrog, a = 1) HIP
+path against the FP64 oracle, the Gauss constraint held to roundoff on the
+GPU, and reversibility."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import rel_maxdiff, say, to_dev
+from paper_2102_01031_amd import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def u1_kwargs(wl, N):
+    return dict(N=N, dx=wl.dx, dt=wl.dt, integrator="lf", expansion="none", potential="abelian_higgs",
+                lam=wl.lam, v=wl.v, e=wl.e, kappa_g=wl.kappa_g)
+
+
+def gpu_u1(kw, fields, steps_list):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    phi, pi, A, piA = [to_dev(f, torch.float64) for f in fields]
+    lat = Lattice(phi, pi, A=A, piA=piA, **kw)
+    for n in steps_list:
+        if n == "sync":
+            lat.sync()
+        else:
+            lat.step(n)
+    torch.cuda.synchronize()
+    return lat, (phi, pi, A, piA)
+
+
+def oracle_u1(kw, fields):
+    m = oracle.U1Model(N=kw["N"], dx=kw["dx"], dt=kw["dt"], lam=kw["lam"], v=kw["v"], e=kw["e"],
+                       kappa_g=kw["kappa_g"])
+    return oracle.U1State(m, *fields)
+
+
+def compare_u1(gt, st, tol, what):
+    names = ("phi", "pi", "A", "piA")
+    for k, (gl, ol) in enumerate(zip(gt, (st.phi, st.pi, st.A, st.piA))):
+        for i, (g, o) in enumerate(zip(gl, ol)):
+            if np.max(np.abs(o)) == 0:
+                assert np.max(np.abs(g.cpu().numpy())) == 0
+                continue
+            e = rel_maxdiff(g.cpu().numpy(), o)
+            assert e <= tol, f"{what} {names[k]}[{i}] rel err {e:.3e}"
+
+
+def compare_u1_energy(eg, eo, tol, what):
+    pairs = (("EK_phi", eg["EK"][0]), ("EG_phi", eg["EG"][0]), ("EV", eg["EV"][0]), ("EK_A", eg["EK_A"]),
+             ("EG_A", eg["EG_A"]), ("rho", eg["rho"]))
+    for k, g in pairs:
+        o = eo[k]
+        assert abs(g - o) <= tol * max(abs(o), 1e-300), f"{what} {k}: {g} vs {o}"
+
+
+@pytest.mark.parametrize("N,steps", [(5, 9), (16, 25), (24, 40), (70, 6)])
+def test_u1_parity_small(N, steps):
+    wl = workloads.ABELIAN_HIGGS_128
+    kw = u1_kwargs(wl, N)
+    fields = wl.initial_fields(N=N)
+    say(f"[u1] N={N} steps={steps}")
+    lat, gt = gpu_u1(kw, fields, [steps])
+    eg = lat.energy()
+    st = oracle_u1(kw, fields).run(steps)
+    compare_u1(gt, st, TOL, f"u1-{N}")
+    compare_u1_energy(eg, st.energy(), TOL, f"u1-{N}")
+    go = st.gauss()
+    assert abs(eg["gauss_div_max"] - go["div_max"]) <= 1e-12 * go["div_max"]
+    assert abs(eg["gauss_charge_max"] - go["charge_max"]) <= 1e-12 * go["charge_max"]
+    scale = max(go["div_max"], go["charge_max"])
+    assert eg["gauss_max"] <= 1e-12 * scale and go["gauss_max"] <= 1e-12 * scale
+    lat.close()
+
+
+def test_u1_parity_full_size():
+    wl = workloads.ABELIAN_HIGGS_128
+    N, steps = wl.N, 3
+    kw = u1_kwargs(wl, N)
+    fields = wl.initial_fields()
+    say(f"[u1] full size N={N} steps={steps}")
+    lat, gt = gpu_u1(kw, fields, [steps])
+    eg = lat.energy()
+    st = oracle_u1(kw, fields).run(steps)
+    compare_u1(gt, st, TOL, "u1-128")
+    compare_u1_energy(eg, st.energy(), TOL, "u1-128")
+    lat.close()
+
+
+def test_u1_gauss_long_run_on_gpu():
+    wl = workloads.ABELIAN_HIGGS_128
+    N = 32
+    kw = u1_kwargs(wl, N)
+    lat, gt = gpu_u1(kw, wl.initial_fields(N=N), [])
+    rho0 = lat.energy()["rho"]
+    worst = 0.0
+    for _ in range(10):
+        lat.step(100)
+        e = lat.energy()
+        scale = max(e["gauss_div_max"], e["gauss_charge_max"])
+        assert scale > 0
+        worst = max(worst, e["gauss_max"] / scale)
+    say(f"[u1] 1000 steps: max |G| / scale = {worst:.2e}, 1 - rho/rho0 = {1 - e['rho'] / rho0:.2e}")
+    assert worst <= 1e-12
+    assert abs(1 - e["rho"] / rho0) < 1e-2
+    lat.close()
+
+
+def test_u1_sync_and_reverse():
+    wl = workloads.ABELIAN_HIGGS_128
+    N = 20
+    kw = u1_kwargs(wl, N)
+    fields = wl.initial_fields(N=N)
+    lat, gt = gpu_u1(kw, fields, [30, "sync"])
+    st = oracle_u1(kw, fields).run(30).sync()
+    compare_u1(gt, st, TOL, "u1-sync")
+    lat.step(-30).sync()
+    for gl, ol in zip(gt, fields):
+        for g, o in zip(gl, ol):
+            assert np.max(np.abs(g.cpu().numpy() - o.reshape(-1))) < 1e-12
+    lat.close()
