@@ -161,10 +161,44 @@ lat_status lattice_sync(lat_ctx *ctx);
  * the fly without writing them back.  Synchronises the stream; out is host memory. */
 lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
 
+/* observable of lattice_grad */
+enum lat_observable {
+    LAT_OBS_CHI_ENERGY_FRACTION = 0   /* O = (E_K^chi + E_G^chi) / rho at the final time */
+};
+
+typedef struct lat_grad_spec {
+    int32_t observable;          /* enum lat_observable */
+    int32_t reserved;
+    int64_t nsteps;              /* T >= 1 velocity-Verlet steps */
+    int64_t checkpoint_stride;   /* steps between stored states; 0 = ceil(sqrt(T)) */
+} lat_grad_spec;
+
+typedef struct lat_grad_out {
+    double value;                /* O after T steps */
+    double dO_dq;                /* total derivative of O with respect to q */
+    void *dO_dphi[2];            /* caller-owned device arrays (N^3 float64) for dO/dphi_s(0); NULL skips */
+    void *dO_dpi[2];             /* caller-owned device arrays for dO/dpi_s(0); NULL skips */
+    double forward_ms;           /* duration of the forward sweep (HIP events) */
+    double reverse_ms;           /* duration of the reverse sweep (HIP events) */
+} lat_grad_out;
+
+/* Gradient of an observable of the state after T steps with respect to the
+ * current fields, momenta and the coupling q, by the hand-written adjoint of
+ * the velocity-Verlet step (sec. 4.5.2 Hamiltonian system at a = 1): a forward
+ * sweep storing the state every checkpoint_stride steps, the adjoint seeded at
+ * T, and a reverse sweep that integrates the state backward together with the
+ * adjoint, re-anchoring the state at every stored checkpoint.  On return the
+ * fields hold their initial values again.  Provided for LAT_PHI4_CHI2 with
+ * LAT_VV2, LAT_EXP_NONE and LAT_PREC_F64 (LAT_EUNSUPPORTED otherwise).  The
+ * library allocates the checkpoints (T/stride + 1 copies of the state) and the
+ * adjoint arrays on first use and keeps them until lattice_destroy.
+ * Synchronises the stream. */
+lat_status lattice_grad(lat_ctx *ctx, const lat_grad_spec *spec, lat_grad_out *out);
+
 /* Launch statistics of the stencil kernels, per kernel kind:
  *   0 kick only, 1 kick only + reductions, 2 drift on load + kick,
  *   3 drift on load + kick + reductions, 4 kick + drift at end (leapfrog),
- *   5 energy (read only), 6 U(1) leapfrog, 7 U(1) energy.
+ *   5 energy (read only), 6 U(1) leapfrog (and U(1) energy), 7 adjoint reverse pass.
  * kernel_ms is accumulated from HIP events recorded on the context stream around
  * each launch while profiling is on (lattice_profile); it stays 0 otherwise. */
 typedef struct lat_stats {

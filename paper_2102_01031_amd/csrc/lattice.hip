@@ -26,6 +26,7 @@
 #include "stage_scalar.hpp"
 #include "stage_rows.hpp"
 #include "stage_u1.hpp"
+#include "stage_adjoint.hpp"
 
 using namespace lat;
 
@@ -108,6 +109,13 @@ struct lat_ctx {
     };
     std::vector<Timed> timed;      // recorded, not yet harvested
     std::vector<hipEvent_t> spare; // reusable events
+    // adjoint scratch: lphi, lpi per field, two buffers each; checkpoints; partials
+    void *lam[2][2][2] = {};       // [kind 0 = lphi, 1 = lpi][field][buffer]
+    int cur_lam[2][2] = {};
+    double *ckpt = nullptr;
+    size_t ckpt_count = 0;
+    double *adj_partials = nullptr;
+    size_t adj_partial_cap = 0;
     std::string err;
 };
 
@@ -220,7 +228,9 @@ void geometry_from_env(lat_ctx *c)
         }
     }
     if (rows_ok(c->N)) {
-        set_rows_geometry(c, 8, 0);
+        // measured on the 256^3 two-field pass: 4-row blocks for float64 (252
+        // registers, one block per CU), 8-row blocks for float32
+        set_rows_geometry(c, c->f32 ? 8 : 4, 0);
         return;
     }
     set_geometry(c, tile, zc);
@@ -677,6 +687,12 @@ void free_ctx(lat_ctx *c)
         (void)hipEventDestroy(t.stop);
     }
     for (auto e : c->spare) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k)
+        for (int f = 0; f < 2; ++f)
+            for (int b = 0; b < 2; ++b)
+                if (c->lam[k][f][b]) (void)hipFree(c->lam[k][f][b]);
+    if (c->ckpt) (void)hipFree(c->ckpt);
+    if (c->adj_partials) (void)hipFree(c->adj_partials);
     delete c;
 }
 
@@ -949,7 +965,7 @@ U1Args u1_args(lat_ctx *c, double ck, double hd, bool write_fields)
 lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
 {
     const int nb = a.tiles_x * a.tiles_y * c->N;
-    const int kind = mode == kU1Energy ? 7 : 6;
+    const int kind = 6;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (c->profiling) {
         lat_status st = timing_begin(c, &ev0, &ev1);
@@ -1025,3 +1041,238 @@ lat_status u1_energy(lat_ctx *c, lat_energies *out)
 }
 
 }  // namespace
+
+// ===========================================================================
+// adjoint of the velocity-Verlet run (two fields, a = 1)
+// ===========================================================================
+namespace {
+
+constexpr int kAdjTX = 64, kAdjTY = 4;
+
+lat_status adj_pass(lat_ctx *c, double dphi, double dlam, double cA, double cB, int nb, int zc, int tiles_x,
+                    int tiles_y)
+{
+    AdjArgs a{};
+    for (int f = 0; f < 2; ++f) {
+        const int cp = c->cur_phi[f], cq = c->cur_pi[f];
+        const int cl = c->cur_lam[0][f], cm = c->cur_lam[1][f];
+        a.phi_in[f] = (const double *)c->phi[f][cp];
+        a.pi_in[f] = (const double *)c->pi[f][cq];
+        a.lphi_in[f] = (const double *)c->lam[0][f][cl];
+        a.lpi_in[f] = (const double *)c->lam[1][f][cm];
+        a.phi_out[f] = (double *)c->phi[f][cp ^ 1];
+        a.pi_out[f] = (double *)c->pi[f][cq ^ 1];
+        a.lphi_out[f] = (double *)c->lam[0][f][cl ^ 1];
+        a.lpi_out[f] = (double *)c->lam[1][f][cm ^ 1];
+    }
+    a.N = c->N;
+    a.zc = zc;
+    a.tiles_x = tiles_x;
+    a.tiles_y = tiles_y;
+    a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
+    a.lam = c->p.lambda;
+    a.q = c->p.q;
+    a.dphi = dphi;
+    a.dlam = dlam;
+    a.cA = cA;
+    a.cB = cB;
+    a.partials = c->adj_partials;
+    a.ticket = c->ticket;
+    a.dq_acc = &c->sc->sums[kMaxQ - 1];
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->profiling) {
+        lat_status st = timing_begin(c, &ev0, &ev1);
+        if (st != LAT_OK) return st;
+    }
+    hipLaunchKernelGGL((adjoint_stage<kAdjTX, kAdjTY>), dim3(nb), dim3(kAdjTX * kAdjTY), 0, c->stream, a);
+    HIPCHK(c, hipGetLastError());
+    if (c->profiling) {
+        lat_status st = timing_end(c, ev0, ev1, 7);
+        if (st != LAT_OK) return st;
+    }
+    c->launches[7] += 1;
+    for (int f = 0; f < 2; ++f) {
+        c->cur_phi[f] ^= 1;
+        c->cur_pi[f] ^= 1;
+        c->cur_lam[0][f] ^= 1;
+        c->cur_lam[1][f] ^= 1;
+    }
+    return LAT_OK;
+}
+
+lat_status checkpoint_io(lat_ctx *c, size_t j, bool store)
+{
+    const size_t bytes = c->vol * sizeof(double);
+    for (int f = 0; f < 2; ++f) {
+        double *slot_phi = c->ckpt + (j * 4 + (size_t)f) * c->vol;
+        double *slot_pi = c->ckpt + (j * 4 + 2 + (size_t)f) * c->vol;
+        void *phi = c->phi[f][c->cur_phi[f]], *pi = c->pi[f][c->cur_pi[f]];
+        if (store) {
+            HIPCHK(c, hipMemcpyAsync(slot_phi, phi, bytes, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(slot_pi, pi, bytes, hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            HIPCHK(c, hipMemcpyAsync(phi, slot_phi, bytes, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(pi, slot_pi, bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    return LAT_OK;
+}
+
+}  // namespace
+
+extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_grad_out *out)
+{
+    if (!c || !spec || !out) return fail(c, LAT_EINVAL, "null argument");
+    if (spec->observable != LAT_OBS_CHI_ENERGY_FRACTION) return fail(c, LAT_EINVAL, "unknown observable");
+    if (c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 || c->p.expansion != LAT_EXP_NONE ||
+        c->f32)
+        return fail(c, LAT_EUNSUPPORTED, "lattice_grad needs two fields, VV2, no expansion and float64");
+    const int64_t T = spec->nsteps;
+    if (T < 1 || T > (1LL << 26)) return fail(c, LAT_EINVAL, "nsteps out of range");
+    int64_t k = spec->checkpoint_stride;
+    if (k <= 0) {
+        k = 1;
+        while (k * k < T) ++k;
+    }
+    if (k > T) k = T;
+    const size_t ncp = (size_t)(T / k) + 1;
+    const size_t bytes = c->vol * sizeof(double);
+    lat_status s;
+
+    // scratch
+    for (int kk = 0; kk < 2; ++kk)
+        for (int f = 0; f < 2; ++f)
+            for (int b = 0; b < 2; ++b)
+                if (!c->lam[kk][f][b] && hipMalloc(&c->lam[kk][f][b], bytes) != hipSuccess)
+                    return fail(c, LAT_ENOMEM, "adjoint array allocation failed");
+    if (ncp > c->ckpt_count) {
+        if (c->ckpt) HIPCHK(c, hipFree(c->ckpt));
+        c->ckpt = nullptr;
+        if (hipMalloc(&c->ckpt, ncp * 4 * bytes) != hipSuccess) {
+            c->ckpt_count = 0;
+            return fail(c, LAT_ENOMEM, "checkpoint allocation failed");
+        }
+        c->ckpt_count = ncp;
+    }
+    const int N = c->N;
+    const int tiles_x = (N + kAdjTX - 1) / kAdjTX, tiles_y = (N + kAdjTY - 1) / kAdjTY;
+    int zc = (int)((long)N * tiles_x * tiles_y / 512);
+    if (zc < 4) zc = 4;
+    if (zc > N) zc = N;
+    const int nb = tiles_x * tiles_y * ((N + zc - 1) / zc);
+    const int seed_blocks = (int)((c->vol + 255) / 256);
+    const size_t need = (size_t)(nb > seed_blocks ? nb : seed_blocks) + 64;
+    if (need > c->adj_partial_cap) {
+        if (c->adj_partials) HIPCHK(c, hipFree(c->adj_partials));
+        c->adj_partials = nullptr;
+        if (hipMalloc(&c->adj_partials, need * sizeof(double)) != hipSuccess) {
+            c->adj_partial_cap = 0;
+            return fail(c, LAT_ENOMEM, "adjoint partials allocation failed");
+        }
+        c->adj_partial_cap = need;
+    }
+    hipEvent_t e0, e1, e2;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventCreate(&e2));
+    auto cleanup = [&]() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+    };
+#define GCHK(expr)                        \
+    do {                                  \
+        lat_status s_ = (expr);           \
+        if (s_ != LAT_OK) {               \
+            cleanup();                    \
+            return s_;                    \
+        }                                 \
+    } while (0)
+
+    const double h = c->p.dt;
+    // ---- forward sweep (leapfrog form of T VV2 steps) with checkpoints
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    GCHK(checkpoint_io(c, 0, true));
+    GCHK(reserve_coef(c, (size_t)T + 3));
+    for (int64_t p = 0; p <= T; ++p) {
+        PassCoef &P = c->coef_host[p];
+        P.ka1 = P.ka3 = 1.0;
+        P.c1 = p > 0 ? 0.5 * h : 0.0;
+        P.c2 = p < T ? 0.5 * h : 0.0;
+        P.dend = p < T ? h : 0.0;
+    }
+    GCHK(upload_coef(c, (size_t)T + 1));
+    for (int64_t p = 0; p < T; ++p) {
+        GCHK(run_pass(c, kKickDrift, (int)p, kLastStore));
+        if ((p + 1) % k == 0 && p + 1 < T) GCHK(checkpoint_io(c, (size_t)((p + 1) / k), true));
+    }
+    GCHK(run_pass(c, kKickOnly, (int)T, kLastStore));   // closing half kick: (phi_T, pi_T)
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+
+    // ---- observable and seed
+    GCHK(energy_sums(c, 0.0));
+    const double V = (double)c->vol;
+    const double *S = c->sc_host->sums;
+    double EK[2], EG[2];
+    for (int f = 0; f < 2; ++f) {
+        EK[f] = S[f] / V / 2.0;
+        EG[f] = S[2 + f] / (c->p.dx * c->p.dx) / V / 2.0;
+    }
+    const double rho = EK[0] + EK[1] + EG[0] + EG[1] + S[4] / V + S[5] / V;
+    const double O = (EK[1] + EG[1]) / rho;
+    {
+        hipLaunchKernelGGL(zero_doubles, dim3(1), dim3(64), 0, c->stream, &c->sc->sums[kMaxQ - 2], 2);
+        HIPCHK(c, hipGetLastError());
+        SeedArgs a{};
+        for (int f = 0; f < 2; ++f) {
+            a.phi[f] = (const double *)c->phi[f][c->cur_phi[f]];
+            a.pi[f] = (const double *)c->pi[f][c->cur_pi[f]];
+            a.lphi[f] = (double *)c->lam[0][f][c->cur_lam[0][f]];
+            a.lpi[f] = (double *)c->lam[1][f][c->cur_lam[1][f]];
+        }
+        a.N = N;
+        a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
+        a.lam = c->p.lambda;
+        a.q = c->p.q;
+        a.O = O;
+        a.inv_vrho = 1.0 / (V * rho);
+        a.partials = c->adj_partials;
+        a.ticket = c->ticket;
+        a.out_sum = &c->sc->sums[kMaxQ - 2];
+        hipLaunchKernelGGL(adjoint_seed, dim3(seed_blocks), dim3(256), 0, c->stream, a);
+        HIPCHK(c, hipGetLastError());
+    }
+
+    // ---- reverse sweep
+    GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, nb, zc, tiles_x, tiles_y));   // closing half kick
+    for (int64_t p = T - 1; p >= 0; --p) {
+        GCHK(adj_pass(c, -h, h, p > 0 ? 0.5 * h : 0.0, 0.5 * h, nb, zc, tiles_x, tiles_y));
+        if (p % k == 0) GCHK(checkpoint_io(c, (size_t)(p / k), false));
+    }
+    HIPCHK(c, hipEventRecord(e2, c->stream));
+
+    // ---- outputs
+    for (int f = 0; f < 2; ++f) {
+        if (out->dO_dphi[f])
+            HIPCHK(c, hipMemcpyAsync(out->dO_dphi[f], c->lam[0][f][c->cur_lam[0][f]], bytes,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        if (out->dO_dpi[f])
+            HIPCHK(c, hipMemcpyAsync(out->dO_dpi[f], c->lam[1][f][c->cur_lam[1][f]], bytes,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    }
+    GCHK(settle(c));
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float fms = 0.f, rms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+    HIPCHK(c, hipEventElapsedTime(&rms, e1, e2));
+    const double dq_adj = c->sc_host->sums[kMaxQ - 1];
+    const double sum_p2c2 = c->sc_host->sums[kMaxQ - 2];
+    out->value = O;
+    out->dO_dq = dq_adj - O * (sum_p2c2 / V) / rho;
+    out->forward_ms = fms;
+    out->reverse_ms = rms;
+    cleanup();
+#undef GCHK
+    return LAT_OK;
+}

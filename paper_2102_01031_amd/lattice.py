@@ -48,7 +48,17 @@ class LatEnergies(C.Structure):
                 ("gauss_mean", C.c_double), ("gauss_sum_mean", C.c_double), ("step", C.c_int64)]
 
 
-KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1_lf", "u1_energy"]
+KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1", "adjoint"]
+
+
+class LatGradSpec(C.Structure):
+    _fields_ = [("observable", C.c_int32), ("reserved", C.c_int32), ("nsteps", C.c_int64),
+                ("checkpoint_stride", C.c_int64)]
+
+
+class LatGradOut(C.Structure):
+    _fields_ = [("value", C.c_double), ("dO_dq", C.c_double), ("dO_dphi", C.c_void_p * 2),
+                ("dO_dpi", C.c_void_p * 2), ("forward_ms", C.c_double), ("reverse_ms", C.c_double)]
 
 
 class LatStats(C.Structure):
@@ -84,6 +94,8 @@ def lib():
         L.lattice_stats.restype = C.c_int
         L.lattice_profile.argtypes = [vp, C.c_int]
         L.lattice_profile.restype = C.c_int
+        L.lattice_grad.argtypes = [vp, C.POINTER(LatGradSpec), C.POINTER(LatGradOut)]
+        L.lattice_grad.restype = C.c_int
         _lib = L
     return _lib
 
@@ -165,6 +177,22 @@ class Lattice:
                     hubble_res=e.hubble_res, gauss_max=e.gauss_max, gauss_div_max=e.gauss_div_max,
                     gauss_charge_max=e.gauss_charge_max, gauss_mean=e.gauss_mean,
                     gauss_sum_mean=e.gauss_sum_mean, step=e.step)
+
+    def grad(self, nsteps: int, stride: int = 0, want_phi: bool = True, want_pi: bool = True) -> dict:
+        """Energy fraction in chi after nsteps and its gradient with respect to the
+        current phi, pi (both fields) and q (hand-written adjoint in the library)."""
+        torch = self._torch
+        N = self.params.N
+        spec = LatGradSpec(0, 0, int(nsteps), int(stride))
+        out = LatGradOut()
+        gphi = [torch.empty(N ** 3, dtype=torch.float64, device="cuda") for _ in range(2)] if want_phi else None
+        gpi = [torch.empty(N ** 3, dtype=torch.float64, device="cuda") for _ in range(2)] if want_pi else None
+        for i in range(2):
+            out.dO_dphi[i] = gphi[i].data_ptr() if gphi else None
+            out.dO_dpi[i] = gpi[i].data_ptr() if gpi else None
+        _check(lib().lattice_grad(self._ctx, C.byref(spec), C.byref(out)), self._ctx)
+        return dict(value=out.value, dO_dq=out.dO_dq, dO_dphi=gphi, dO_dpi=gpi, forward_ms=out.forward_ms,
+                    reverse_ms=out.reverse_ms)
 
     def profile(self, enable: bool = True):
         _check(lib().lattice_profile(self._ctx, 1 if enable else 0), self._ctx)

@@ -1,0 +1,127 @@
+"""GPU checks of the hand-written adjoint (lattice_grad) of the two-field
+velocity-Verlet run at a = 1:
+  - against the oracle's adjoint (segment recomputation, no reverse
+    integration) at small ragged sizes, 1e-10 relative;
+  - at the full differentiable workload (64^3, 2000 steps) against central
+    finite differences of the GPU forward along 8 random unit directions of
+    (initial delta-phi field, q) plus the pure q direction, 1e-6 relative;
+  - through the torch.autograd.Function, and gradcheck at a tiny size;
+  - the fields hold their initial values after the call."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import rel_maxdiff, say, to_dev
+from paper_2102_01031_amd import inputs, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def kw_of(wl, N, q=None):
+    return dict(N=N, dx=wl.dx, dt=wl.dt, integrator="vv2", expansion="none", potential="phi4_chi2",
+                lam=wl.lam, q=wl.q if q is None else q)
+
+
+def gpu_grad(wl, N, phi, pi, T, q=None, stride=0):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_of(wl, N, q))
+    r = lat.grad(T, stride=stride)
+    return lat, tp, tq, r
+
+
+def gpu_observable(wl, N, phi, pi, T, q):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_of(wl, N, q))
+    lat.step(T)
+    e = lat.energy()
+    lat.close()
+    return (e["EK"][1] + e["EG"][1]) / e["rho"]
+
+
+@pytest.mark.parametrize("N,T,stride", [(16, 40, 0), (24, 33, 5), (13, 20, 1), (64, 25, 0)])
+def test_grad_matches_oracle_adjoint(N, T, stride):
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields(N=N)
+    say(f"[adj] oracle parity N={N} T={T} stride={stride}")
+    lat, tp, tq, r = gpu_grad(wl, N, phi, pi, T, stride=stride)
+    m = oracle.ScalarModel(N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2, expansion=oracle.NONE,
+                           integrator=oracle.VV2, lam=wl.lam, q=wl.q)
+    O, g, gp, dq = oracle.adjoint_vv2(m, phi, pi, T)
+    assert abs(r["value"] - O) <= 1e-12 * abs(O)
+    for s in range(2):
+        assert rel_maxdiff(r["dO_dphi"][s].cpu().numpy(), g[s]) <= 1e-10
+        assert rel_maxdiff(r["dO_dpi"][s].cpu().numpy(), gp[s]) <= 1e-10
+    assert abs(r["dO_dq"] - dq) <= 1e-10 * abs(dq)
+    # the fields hold the initial state again
+    for s in range(2):
+        assert np.array_equal(tp[s].cpu().numpy(), phi[s].reshape(-1))
+        assert np.array_equal(tq[s].cpu().numpy(), pi[s].reshape(-1))
+    lat.close()
+
+
+def test_grad_full_workload_vs_finite_differences():
+    wl = workloads.ADJ_64
+    N, T = wl.N, wl.steps
+    phi, pi = wl.initial_fields()
+    lat, tp, tq, r = gpu_grad(wl, N, phi, pi, T)
+    g = r["dO_dphi"][0].cpu().numpy().reshape(N, N, N)
+    dq = r["dO_dq"]
+    O0 = r["value"]
+    say(f"[adj] full workload: O={O0:.6e} dO/dq={dq:.6e} forward {r['forward_ms']:.1f} ms reverse "
+        f"{r['reverse_ms']:.1f} ms")
+    lat.close()
+    assert abs(gpu_observable(wl, N, phi, pi, T, wl.q) - O0) <= 1e-12 * abs(O0)
+    dirs = inputs.random_directions(8, N, seed=7) + [(np.zeros((N, N, N)), 1.0)]
+    worst = 0.0
+    for k, (v, vq) in enumerate(dirs):
+        ad = float(np.sum(g * v) + dq * vq)
+
+        def fd(eps):
+            fp = gpu_observable(wl, N, [phi[0] + eps * v, phi[1]], pi, T, wl.q + eps * vq)
+            fm = gpu_observable(wl, N, [phi[0] - eps * v, phi[1]], pi, T, wl.q - eps * vq)
+            return (fp - fm) / (2 * eps)
+
+        e = 2e-3 if vq == 1.0 else 4e-3
+        d1, d2 = fd(e), fd(e / 2)
+        rich = (4 * d2 - d1) / 3
+        rel = abs(rich - ad) / abs(ad)
+        worst = max(worst, rel)
+        say(f"[adj] dir {k}: adjoint {ad:.10e} fd {rich:.10e} (raw {d2:.10e}) rel {rel:.2e}")
+        assert rel <= 1e-6
+    say(f"[adj] worst relative deviation from finite differences: {worst:.2e}")
+
+
+def test_autograd_function_and_gradcheck():
+    import torch
+    from paper_2102_01031_amd.autograd import chi_energy_fraction
+    wl = workloads.ADJ_64
+    N, T = 12, 15
+    phi, pi = wl.initial_fields(N=N)
+    ts = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (phi[0], phi[1], pi[0], pi[1])]
+    q = torch.tensor(wl.q, dtype=torch.float64, requires_grad=True)
+    O = chi_energy_fraction(*ts, q, N=N, dx=wl.dx, dt=wl.dt, nsteps=T, lam=wl.lam)
+    O.backward()
+    lat, tp, tq, r = gpu_grad(wl, N, phi, pi, T)
+    assert abs(O.item() - r["value"]) < 1e-15 * abs(r["value"]) + 1e-300
+    assert torch.equal(ts[0].grad.reshape(-1), r["dO_dphi"][0])
+    assert torch.equal(ts[3].grad.reshape(-1), r["dO_dpi"][1])
+    assert abs(q.grad.item() - r["dO_dq"]) <= 1e-15 * abs(r["dO_dq"])
+    lat.close()
+    # gradcheck of the Function at a tiny lattice
+    n4 = 4
+    ph4, pi4 = wl.initial_fields(N=n4)
+    xs = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (ph4[0], ph4[1], pi4[0], pi4[1])]
+    q4 = torch.tensor(wl.q, dtype=torch.float64, requires_grad=True)
+    f = lambda a, b, c, d, qq: chi_energy_fraction(a, b, c, d, qq, N=n4, dx=wl.dx, dt=wl.dt, nsteps=6, lam=wl.lam)
+    assert torch.autograd.gradcheck(f, (*xs, q4), eps=1e-6, atol=1e-9, rtol=1e-5)
