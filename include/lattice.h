@@ -145,6 +145,25 @@ typedef struct lat_ctx lat_ctx;
  * LAT_EHIP.  On error *ctx is set to NULL. */
 lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
 
+/* Create one context for a batch of n_real independent lattices that share p
+ * (p->N is ignored) but have their own sizes N_per_real[r] and fields f[r].
+ * Provided for LAT_PHI4 with LAT_LF and LAT_EXP_NONE or LAT_EXP_FIXED, float64 or
+ * float32.  lattice_step on such a context advances every realization with
+ * one batched launch per step; the launches of a call are captured once into a
+ * HIP graph and replayed.  With autotune = 1 the tile shape and z chunk of
+ * each distinct lattice size are chosen by timing candidates on scratch
+ * buffers (the fields are not modified); otherwise a fixed table is used.
+ * lattice_energy_batch reads realization r; lattice_sync and lattice_destroy
+ * act on all of them. */
+lat_status lattice_init_batch(lat_ctx **ctx, const lat_params *p, int32_t n_real, const int32_t *N_per_real,
+                              const lat_fields *f, int32_t autotune, void *stream);
+
+/* Energies of realization r of a batch context (as lattice_energy). */
+lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
+
+/* Tile shape and z chunk the batch uses for lattice size N (host output). */
+lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, int32_t *tile_y, int32_t *z_chunk);
+
 /* Advance |nsteps| time steps (sec. 4.5.2; LF and VV of sec. 4.3), backward
  * in time (dt -> -dt) when nsteps < 0.  For LF a backward run needs momenta at
  * integer time or staggered backward (LAT_ESTATE otherwise; call lattice_sync).

@@ -27,6 +27,9 @@
 #include "stage_rows.hpp"
 #include "stage_u1.hpp"
 #include "stage_adjoint.hpp"
+#include "stage_batch.hpp"
+#include <map>
+#include <utility>
 
 using namespace lat;
 
@@ -41,6 +44,7 @@ lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir);
 lat_status u1_sync(lat_ctx *c);
 lat_status u1_energy(lat_ctx *c, lat_energies *out);
 size_t u1_partial_capacity(int N);
+lat_status batch_step(lat_ctx *c, int64_t nsteps);
 
 struct TileCfg {
     int tx, ty;
@@ -116,6 +120,21 @@ struct lat_ctx {
     size_t ckpt_count = 0;
     double *adj_partials = nullptr;
     size_t adj_partial_cap = 0;
+    // batch of independent lattices
+    bool batch = false;
+    std::vector<lat_ctx *> subs;
+    void *reals_dev = nullptr;          // BatchReal<T>[n]
+    std::vector<char> reals_host;       // host copy (bytes)
+    int *block_real = nullptr;
+    int batch_blocks = 0;
+    std::vector<void *> pi_scratch;
+    std::map<int, std::pair<int, int>> batch_tile;   // N -> (tile x, z chunk)
+    int batch_parity = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t graph_n = 0;
+    int graph_parity = -1;
     std::string err;
 };
 
@@ -693,6 +712,14 @@ void free_ctx(lat_ctx *c)
                 if (c->lam[k][f][b]) (void)hipFree(c->lam[k][f][b]);
     if (c->ckpt) (void)hipFree(c->ckpt);
     if (c->adj_partials) (void)hipFree(c->adj_partials);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->reals_dev) (void)hipFree(c->reals_dev);
+    if (c->block_real) (void)hipFree(c->block_real);
+    for (void *q : c->pi_scratch)
+        if (q) (void)hipFree(q);
+    for (lat_ctx *sub : c->subs) free_ctx(sub);
     delete c;
 }
 
@@ -814,6 +841,7 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
     const int64_t ns = nsteps > 0 ? nsteps : -nsteps;
     if (ns > (1LL << 30)) return fail(c, LAT_EINVAL, "too many steps in one call");
     lat_status s;
+    if (c->batch) return batch_step(c, nsteps);
     if (c->p.integrator == LAT_LF) {
         if (c->lf_stag != 0 && c->lf_stag != dir)
             return fail(c, LAT_ESTATE, "leapfrog momenta are staggered in the other direction; sync first");
@@ -830,6 +858,14 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
 lat_status lattice_sync(lat_ctx *c)
 {
     if (!c) return fail(nullptr, LAT_EINVAL, "null context");
+    if (c->batch) {
+        for (lat_ctx *sub : c->subs) {
+            lat_status st = lattice_sync(sub);
+            if (st != LAT_OK) return fail(c, st, sub->err);
+        }
+        c->lf_stag = 0;
+        return LAT_OK;
+    }
     if (c->p.integrator != LAT_LF || c->lf_stag == 0) return LAT_OK;
     lat_status s;
     if (c->u1) {
@@ -855,6 +891,7 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
 {
     if (!c || !out) return fail(c, LAT_EINVAL, "null argument");
     std::memset(out, 0, sizeof(*out));
+    if (c->batch) return fail(c, LAT_EINVAL, "batch context: use lattice_energy_batch");
     if (c->u1) return u1_energy(c, out);
     const double c1 = (c->p.integrator == LAT_LF && c->lf_stag != 0) ? 0.5 * c->lf_stag * c->p.dt : 0.0;
     lat_status s = energy_sums(c, c1);
@@ -1274,5 +1311,294 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     out->reverse_ms = rms;
     cleanup();
 #undef GCHK
+    return LAT_OK;
+}
+
+// ===========================================================================
+// batches of independent single-field lattices
+// ===========================================================================
+namespace {
+
+constexpr int kBatchTX[] = {64, 32, 16, 8};
+
+template <typename T>
+BatchReal<T> make_real(lat_ctx *sub, void *scratch, int tx, int zc)
+{
+    BatchReal<T> R{};
+    R.phi[0] = (T *)sub->phi[0][0];
+    R.phi[1] = (T *)sub->phi[0][1];
+    R.pi = (T *)sub->pi[0][0];
+    R.pi_scratch = (T *)scratch;
+    R.N = sub->N;
+    R.tx = tx;
+    R.ty = kBatchThreads / tx;
+    R.zc = zc < 1 ? 1 : (zc > R.N ? R.N : zc);
+    R.tiles_x = (R.N + R.tx - 1) / R.tx;
+    R.tiles_y = (R.N + R.ty - 1) / R.ty;
+    return R;
+}
+
+int real_blocks(int N, int tx, int zc)
+{
+    const int ty = kBatchThreads / tx;
+    return ((N + tx - 1) / tx) * ((N + ty - 1) / ty) * ((N + zc - 1) / zc);
+}
+
+// Build the realization table and block table for the realizations in `which`
+// (all when empty) with the tiles in c->batch_tile, and upload them.
+template <typename T>
+lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
+{
+    const int n = (int)c->subs.size();
+    std::vector<BatchReal<T>> reals(n);
+    std::vector<int> blocks;
+    for (int r = 0; r < n; ++r) {
+        const auto tz = c->batch_tile[c->subs[r]->N];
+        reals[r] = make_real<T>(c->subs[r], c->pi_scratch[r], tz.first, tz.second);
+    }
+    std::vector<int> list = which;
+    if (list.empty())
+        for (int r = 0; r < n; ++r) list.push_back(r);
+    for (int r : list) {
+        reals[r].first_block = (int)blocks.size();
+        const int nb = reals[r].tiles_x * reals[r].tiles_y * ((reals[r].N + reals[r].zc - 1) / reals[r].zc);
+        for (int b = 0; b < nb; ++b) blocks.push_back(r);
+    }
+    const size_t rbytes = (size_t)n * sizeof(BatchReal<T>);
+    if (!c->reals_dev && hipMalloc(&c->reals_dev, rbytes) != hipSuccess)
+        return fail(c, LAT_ENOMEM, "batch table allocation failed");
+    if ((int)blocks.size() > c->batch_blocks) {
+        if (c->block_real) HIPCHK(c, hipFree(c->block_real));
+        c->block_real = nullptr;
+        if (hipMalloc(&c->block_real, blocks.size() * sizeof(int)) != hipSuccess)
+            return fail(c, LAT_ENOMEM, "batch block table allocation failed");
+        c->batch_blocks = (int)blocks.size();
+    }
+    HIPCHK(c, hipMemcpy(c->reals_dev, reals.data(), rbytes, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->block_real, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice));
+    c->reals_host.assign((const char *)reals.data(), (const char *)reals.data() + rbytes);
+    c->nblocks = (int)blocks.size();
+    return LAT_OK;
+}
+
+template <typename T>
+BatchArgs<T> batch_args(lat_ctx *c, int pass_index, int parity, int tuning)
+{
+    BatchArgs<T> a{};
+    a.reals = (const BatchReal<T> *)c->reals_dev;
+    a.block_real = c->block_real;
+    a.coef = c->coef + pass_index;
+    a.parity = parity;
+    a.tuning = tuning;
+    a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
+    a.lam = c->p.lambda;
+    return a;
+}
+
+template <typename T>
+lat_status batch_launch(lat_ctx *c, hipStream_t s, int pass_index, int parity, int tuning)
+{
+    hipLaunchKernelGGL(batch_lf_stage<T>, dim3(c->nblocks), dim3(kBatchThreads), 0, s,
+                       batch_args<T>(c, pass_index, parity, tuning));
+    HIPCHK(c, hipGetLastError());
+    return LAT_OK;
+}
+
+// Autotuner: per lattice size, time the candidate tile widths and z chunks on
+// the realizations of that size (writing only to shadow / scratch buffers).
+template <typename T>
+lat_status autotune(lat_ctx *c)
+{
+    std::map<int, std::vector<int>> groups;
+    for (int r = 0; r < (int)c->subs.size(); ++r) groups[c->subs[r]->N].push_back(r);
+    lat_status s = reserve_coef(c, 2);
+    if (s != LAT_OK) return s;
+    c->coef_host[0].ka1 = c->coef_host[0].ka3 = 1.0;
+    c->coef_host[0].c1 = 0.5 * c->p.dt;
+    c->coef_host[0].dend = c->p.dt;
+    if ((s = upload_coef(c, 1)) != LAT_OK) return s;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (auto &g : groups) {
+        const int N = g.first;
+        float best = 1e30f;
+        std::pair<int, int> best_cfg = c->batch_tile[N];
+        for (int tx : kBatchTX) {
+            if (tx > 2 * N && tx != 8) continue;
+            const int zcs[] = {4, 8, 16, 32, N};
+            for (int zc : zcs) {
+                if (zc > N) continue;
+                c->batch_tile[N] = {tx, zc};
+                if ((s = build_tables<T>(c, g.second)) != LAT_OK) return s;
+                if ((s = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return s;   // warm
+                HIPCHK(c, hipEventRecord(e0, c->stream));
+                for (int it = 0; it < 3; ++it)
+                    if ((s = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return s;
+                HIPCHK(c, hipEventRecord(e1, c->stream));
+                HIPCHK(c, hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_cfg = {tx, zc};
+                }
+            }
+        }
+        c->batch_tile[N] = best_cfg;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return LAT_OK;
+}
+
+template <typename T>
+lat_status batch_step_t(lat_ctx *c, int64_t ns)
+{
+    const double h = c->p.dt, al = c->p.alpha;
+    lat_status s = reserve_coef(c, (size_t)ns + 1);
+    if (s != LAT_OK) return s;
+    const double t_start = c->t;
+    int stag = c->lf_stag;
+    for (int64_t k = 0; k < ns; ++k) {
+        PassCoef &P = c->coef_host[k];
+        const double t = t_start + (double)k * h;
+        const double a = scale_at(c, t);
+        P.ka1 = std::pow(a, 1.0 + al);
+        P.ka3 = std::pow(a, 3.0 + al);
+        P.c1 = stag == 0 ? 0.5 * h : h;
+        P.dend = h * std::pow(scale_at(c, t + 0.5 * h), al - 3.0);
+        P.t = t;
+        stag = 1;
+    }
+    if ((s = upload_coef(c, (size_t)ns)) != LAT_OK) return s;
+    // (re)capture the graph of ns batched passes starting at the current parity
+    if (!c->graph_exec || c->graph_n != ns || c->graph_parity != c->batch_parity) {
+        if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+        if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        for (int64_t k = 0; k < ns; ++k) {
+            s = batch_launch<T>(c, c->capture_stream, (int)k, (int)((c->batch_parity + k) & 1), 0);
+            if (s != LAT_OK) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(c->capture_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+        }
+        HIPCHK(c, hipStreamEndCapture(c->capture_stream, &c->graph));
+        HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        c->graph_n = ns;
+        c->graph_parity = c->batch_parity;
+    }
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    c->launches[4] += ns;
+    c->batch_parity = (int)((c->batch_parity + ns) & 1);
+    if (c->batch_parity == 1) {
+        const int n = (int)c->subs.size();
+        hipLaunchKernelGGL(batch_settle<T>, dim3(64, n), dim3(256), 0, c->stream,
+                           (const BatchReal<T> *)c->reals_dev, n, 1);
+        HIPCHK(c, hipGetLastError());
+        c->batch_parity = 0;
+    }
+    c->t = t_start + (double)ns * h;
+    c->lf_stag = 1;
+    for (lat_ctx *sub : c->subs) {
+        sub->t = c->t;
+        sub->lf_stag = 1;
+        sub->step += ns;
+    }
+    return LAT_OK;
+}
+
+lat_status batch_step(lat_ctx *c, int64_t nsteps)
+{
+    if (nsteps < 0) return fail(c, LAT_EUNSUPPORTED, "batch contexts step forward only");
+    lat_status s = c->f32 ? batch_step_t<float>(c, nsteps) : batch_step_t<double>(c, nsteps);
+    if (s == LAT_OK) c->step += nsteps;
+    return s;
+}
+
+}  // namespace
+
+extern "C" lat_status lattice_init_batch(lat_ctx **out, const lat_params *p, int32_t n_real,
+                                         const int32_t *N_per_real, const lat_fields *f, int32_t tune,
+                                         void *stream)
+{
+    if (!out) return fail(nullptr, LAT_EINVAL, "null ctx pointer");
+    *out = nullptr;
+    if (!p || !N_per_real || !f || n_real < 1 || n_real > (1 << 20))
+        return fail(nullptr, LAT_EINVAL, "bad batch arguments");
+    if (p->potential != LAT_PHI4 || p->integrator != LAT_LF ||
+        (p->expansion != LAT_EXP_NONE && p->expansion != LAT_EXP_FIXED))
+        return fail(nullptr, LAT_EUNSUPPORTED, "batches are provided for one field, LF, no or fixed expansion");
+    lat_ctx *c = new (std::nothrow) lat_ctx();
+    if (!c) return fail(nullptr, LAT_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->batch = true;
+    c->stream = (hipStream_t)stream;
+    c->f32 = p->precision == LAT_PREC_F32;
+    c->esize = c->f32 ? 4 : 8;
+    c->nf = 1;
+    c->t = p->t0;
+    c->lf_stag = p->lf_staggered;
+    auto bail = [&](lat_status st, const std::string &m) {
+        free_ctx(c);
+        g_init_error = m;
+        return st;
+    };
+    for (int r = 0; r < n_real; ++r) {
+        lat_params pr = *p;
+        pr.N = N_per_real[r];
+        lat_ctx *sub = nullptr;
+        lat_status st = lattice_init(&sub, &pr, &f[r], stream);
+        if (st != LAT_OK) return bail(st, "realization " + std::to_string(r) + ": " + g_init_error);
+        c->subs.push_back(sub);
+        void *scr = nullptr;
+        if (hipMalloc(&scr, sub->vol * c->esize) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
+        c->pi_scratch.push_back(scr);
+        c->vol += sub->vol;
+        if (!c->batch_tile.count(sub->N)) {
+            const int N = sub->N;
+            const int tx = N % 64 == 0 ? 64 : N % 32 == 0 ? 32 : N % 16 == 0 ? 16 : 8;
+            c->batch_tile[N] = {tx, N >= 48 ? 16 : 8};
+        }
+    }
+    if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(LAT_EHIP, "stream creation failed");
+    if (hipEventCreateWithFlags(&c->upload_ev, hipEventDisableTiming) != hipSuccess)
+        return bail(LAT_EHIP, "event creation failed");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
+    lat_status st;
+    if (tune) {
+        st = c->f32 ? autotune<float>(c) : autotune<double>(c);
+        if (st != LAT_OK) return bail(st, c->err);
+    }
+    st = c->f32 ? build_tables<float>(c, {}) : build_tables<double>(c, {});
+    if (st != LAT_OK) return bail(st, c->err);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
+    *out = c;
+    return LAT_OK;
+}
+
+extern "C" lat_status lattice_energy_batch(lat_ctx *c, int32_t r, lat_energies *out)
+{
+    if (!c || !out) return fail(c, LAT_EINVAL, "null argument");
+    if (!c->batch || r < 0 || r >= (int)c->subs.size()) return fail(c, LAT_EINVAL, "bad realization index");
+    lat_status s = lattice_energy(c->subs[r], out);
+    if (s != LAT_OK) return fail(c, s, c->subs[r]->err);
+    return LAT_OK;
+}
+
+extern "C" lat_status lattice_batch_tile(const lat_ctx *c, int32_t N, int32_t *tx, int32_t *ty, int32_t *zc)
+{
+    if (!c || !c->batch || !tx || !ty || !zc) return LAT_EINVAL;
+    auto it = c->batch_tile.find(N);
+    if (it == c->batch_tile.end()) return LAT_EINVAL;
+    *tx = it->second.first;
+    *ty = kBatchThreads / it->second.first;
+    *zc = it->second.second;
     return LAT_OK;
 }

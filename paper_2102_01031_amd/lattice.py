@@ -96,6 +96,14 @@ def lib():
         L.lattice_profile.restype = C.c_int
         L.lattice_grad.argtypes = [vp, C.POINTER(LatGradSpec), C.POINTER(LatGradOut)]
         L.lattice_grad.restype = C.c_int
+        L.lattice_init_batch.argtypes = [C.POINTER(vp), C.POINTER(LatParams), C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(LatFields), C.c_int32, vp]
+        L.lattice_init_batch.restype = C.c_int
+        L.lattice_energy_batch.argtypes = [vp, C.c_int32, C.POINTER(LatEnergies)]
+        L.lattice_energy_batch.restype = C.c_int
+        L.lattice_batch_tile.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32)]
+        L.lattice_batch_tile.restype = C.c_int
         _lib = L
     return _lib
 
@@ -204,6 +212,71 @@ class Lattice:
         return dict(launches={k: s.launches[i] for i, k in enumerate(KERNEL_KINDS)},
                     kernel_ms={k: s.kernel_ms[i] for i, k in enumerate(KERNEL_KINDS)},
                     blocks=s.blocks, threads=s.threads, tile=(s.tile_x, s.tile_y), z_chunk=s.z_chunk)
+
+    def close(self):
+        if self._ctx:
+            lib().lattice_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _energy_dict(e):
+    return dict(t=e.t, a=e.a, b=e.b, EK=list(e.EK), EG=list(e.EG), EV=list(e.EV), rho=e.rho, step=e.step)
+
+
+class LatticeBatch:
+    """Batch of independent single-field lattices (sizes may differ) stepped by
+    one batched launch per step, replayed from a captured HIP graph.
+
+    phis, pis: lists (one entry per realization) of contiguous CUDA tensors of
+    N_r^3 elements.  Other keyword arguments as for Lattice (N is ignored)."""
+
+    def __init__(self, phis, pis, sizes, *, autotune=True, stream=None, **kw):
+        import torch
+        kw = dict(kw)
+        kw.setdefault("N", int(sizes[0]))
+        self.params = make_params(**kw)
+        dtype = torch.float32 if kw.get("precision", "f64") == "f32" else torch.float64
+        n = len(sizes)
+        self.sizes = [int(v) for v in sizes]
+        self._keep = list(phis) + list(pis)
+        fa = (LatFields * n)()
+        for r in range(n):
+            for t in (phis[r], pis[r]):
+                if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and t.numel() == self.sizes[r] ** 3):
+                    raise ValueError("fields must be contiguous CUDA tensors of N_r^3 elements with the run's dtype")
+            fa[r].phi[0] = phis[r].data_ptr()
+            fa[r].pi[0] = pis[r].data_ptr()
+        Ns = (C.c_int32 * n)(*self.sizes)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._ctx = C.c_void_p()
+        _check(lib().lattice_init_batch(C.byref(self._ctx), C.byref(self.params), n, Ns, fa,
+                                        1 if autotune else 0, C.c_void_p(stream.cuda_stream)), None)
+
+    def step(self, n: int):
+        _check(lib().lattice_step(self._ctx, int(n)), self._ctx)
+        return self
+
+    def sync(self):
+        _check(lib().lattice_sync(self._ctx), self._ctx)
+        return self
+
+    def energy(self, r: int) -> dict:
+        e = LatEnergies()
+        _check(lib().lattice_energy_batch(self._ctx, int(r), C.byref(e)), self._ctx)
+        return _energy_dict(e)
+
+    def tile(self, N: int):
+        tx, ty, zc = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lattice_batch_tile(self._ctx, int(N), C.byref(tx), C.byref(ty), C.byref(zc)), self._ctx)
+        return tx.value, ty.value, zc.value
 
     def close(self):
         if self._ctx:
