@@ -11,7 +11,6 @@ on the host, a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -29,14 +28,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("stage_scalar.hpp", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_2102_01031_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic(kind: str, per_launch_alg: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -45,12 +36,102 @@ def stored_traffic(kind: str, per_launch_alg: float):
         return None
     with open(path) as fh:
         d = json.load(fh)
+    from paper_2102_01031_amd.pmc_summary import kernel_hash
     if d.get("kernel_hash") != kernel_hash():
         return None
     k = d.get("kernels", {}).get(kind)
     if not k:
         return None
     return k["hbm_bytes_per_launch"]
+
+
+def run_extras(args, log):
+    """The other workloads' headline numbers: the adjoint/forward time ratio
+    (two fields, 64^3, 2000 VV2 steps), the batched ensemble rate (256 lattices
+    of 24^3..64^3, float32, 2000 LF steps, one captured graph) and the
+    single-field 32^3 leapfrog run (1000 steps)."""
+    import torch
+
+    from paper_2102_01031_amd import workloads
+    from paper_2102_01031_amd.lattice import Lattice, LatticeBatch
+
+    dev = torch.device("cuda:0")
+    res = {}
+    # adjoint / forward
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields()
+    tp = [torch.tensor(f.reshape(-1), device=dev) for f in phi]
+    tq = [torch.tensor(f.reshape(-1), device=dev) for f in pi]
+    lat = Lattice(tp, tq, N=wl.N, dx=wl.dx, dt=wl.dt, integrator="vv2", expansion="none", potential="phi4_chi2",
+                  lam=wl.lam, q=wl.q)
+    lat.grad(50)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    lat.step(wl.steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - c0
+    lat.step(-wl.steps)
+    torch.cuda.synchronize()
+    lat.stats(reset=True)
+    lat.profile(True)
+    c0 = time.perf_counter()
+    r = lat.grad(wl.steps)
+    gwall = time.perf_counter() - c0
+    st = lat.stats(reset=True)
+    lat.profile(False)
+    fus = 1e3 * st["kernel_ms"]["kick_drift"] / max(st["launches"]["kick_drift"], 1)
+    aus = 1e3 * st["kernel_ms"]["adjoint"] / max(st["launches"]["adjoint"], 1)
+    res["adjoint"] = {"workload": wl.name, "steps": wl.steps, "observable": "(E_K^chi + E_G^chi)/rho",
+                      "value": r["value"], "dO_dq": r["dO_dq"],
+                      "forward_ms": r["forward_ms"], "reverse_ms": r["reverse_ms"],
+                      "ratio_reverse_over_forward": r["reverse_ms"] / r["forward_ms"],
+                      "forward_plain_ms": 1e3 * fwd, "grad_call_ms": 1e3 * gwall,
+                      "kernel_ratio_adjoint_over_forward_pass": aus / fus,
+                      "forward_pass_us": fus, "adjoint_pass_us": aus}
+    lat.close()
+    log(f"[bench] adjoint: reverse/forward {r['reverse_ms'] / r['forward_ms']:.2f}, per pass {aus / fus:.2f}")
+    # batched ensemble
+    bw = workloads.BATCH
+    sizes = bw.sizes()
+    phis, pis = [], []
+    for rr, N in enumerate(sizes):
+        f = bw.initial_fields(rr, N)
+        phis.append(torch.tensor(f[0][0].reshape(-1), device=dev, dtype=torch.float32))
+        pis.append(torch.tensor(f[1][0].reshape(-1), device=dev, dtype=torch.float32))
+    b = bw.base
+    lb = LatticeBatch(phis, pis, sizes, autotune=True, precision="f32", dx=b.dx, dt=b.dt, integrator="lf",
+                      expansion="fixed", potential="phi4", lam=b.lam, alpha=b.alpha, w_eos=b.w_eos, H0=b.H0,
+                      a0=b.a0)
+    lb.step(bw.steps)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    lb.step(bw.steps)
+    torch.cuda.synchronize()
+    bwall = time.perf_counter() - c0
+    sites = sum(N ** 3 for N in sizes)
+    res["batch"] = {"workload": bw.name, "realizations": len(sizes), "sites": sites, "steps": bw.steps,
+                    "value": sites * bw.steps / bwall, "unit": "site-updates/s", "ms": 1e3 * bwall,
+                    "tiles": {str(N): list(lb.tile(N)) for N in sorted(set(sizes))},
+                    "achieved_GBs_alg": sites * 16 * bw.steps / bwall / 1e9}
+    lb.close()
+    log(f"[bench] batch: {res['batch']['value']:.3e} site-updates/s")
+    # single field, 32^3, 1000 LF steps
+    w0 = workloads.LPHI4_32
+    phi, pi = w0.initial_fields()
+    tp = [torch.tensor(phi[0].reshape(-1), device=dev)]
+    tq = [torch.tensor(pi[0].reshape(-1), device=dev)]
+    l0 = Lattice(tp, tq, N=w0.N, dx=w0.dx, dt=w0.dt, integrator="lf", expansion="fixed", potential="phi4",
+                 lam=w0.lam, alpha=w0.alpha, w_eos=w0.w_eos, H0=w0.H0, a0=w0.a0)
+    l0.step(100)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    l0.step(w0.steps)
+    torch.cuda.synchronize()
+    w = time.perf_counter() - c0
+    res["lphi4_32"] = {"workload": w0.name, "steps": w0.steps, "us_per_step": 1e6 * w / w0.steps,
+                       "value": w0.N ** 3 * w0.steps / w, "unit": "site-updates/s"}
+    l0.close()
+    return res
 
 
 def main():
@@ -61,6 +142,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--main-only", action="store_true", help="only the 256^3 workload (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the lattice step "
@@ -117,6 +199,33 @@ def main():
     log(f"[bench] {n_launch} '{kind}' launches, mean {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s; "
         f"a={e['a']:.6f} hubble_res={e['hubble_res']:.2e}")
 
+    # float32-fields mode on the same workload
+    f32 = None
+    if args.precision == "f64" and not args.main_only:
+        tp32 = [t.to(torch.float32) for t in tp]
+        tq32 = [t.to(torch.float32) for t in tq]
+        kw32 = dict(kw, precision="f32")
+        l32 = Lattice(tp32, tq32, stream=stream, **kw32)
+        l32.step(args.warmup)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        l32.step(args.steps)
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - c0
+        l32.stats(reset=True)
+        l32.profile(True)
+        l32.step(args.steps)
+        s32 = l32.stats(reset=True)
+        us32 = 1e3 * s32["kernel_ms"][kind] / max(s32["launches"][kind], 1)
+        f32 = {"value": N ** 3 * stages / w32, "unit": "site-updates/s", "mean_launch_us": us32,
+               "achieved_GBs": N ** 3 * 2 * 4 * 4 / (us32 * 1e-6) / 1e9, "tile": list(s32["tile"]),
+               "z_chunk": s32["z_chunk"]}
+        l32.close()
+        del tp32, tq32
+        log(f"[bench] float32 fields: {f32['value']:.3e} site-updates/s, {us32:.1f} us per pass")
+
+    extras = {} if args.main_only else run_extras(args, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -155,7 +264,9 @@ def main():
                      "mean_launch_us": avg_ms * 1e3},
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBS,
         "cpu_baseline": cpu,
+        "precision_f32": f32,
     }
+    out.update(extras)
     lat.close()
     print(json.dumps(out))
 
