@@ -47,7 +47,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = _build.library_path()
+        path = os.environ.get("ORACLE_LIB") or _build.library_path()
         if not os.path.exists(path):
             _build.build()
         L = C.CDLL(path)

@@ -1,0 +1,55 @@
+"""The pins must catch plausible mistakes in the oracle.  Each case plants one
+mistake in a copy of oracle/lattice_oracle.c (a dropped or wrong term, a sign,
+an index, a coefficient), builds it with gcc into a temporary library and runs
+the named pins against it in a subprocess: at least one of them must fail."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lattice_oracle.c")
+
+MUTANTS = [
+    ("laplacian centre weight", "f[nbr(N, x, y, z, d, +1)] - 2.0 * f0 + f[nbr(N, x, y, z, d, -1)]",
+     "f[nbr(N, x, y, z, d, +1)] - 3.0 * f0 + f[nbr(N, x, y, z, d, -1)]", "test_oracle_scalar.py"),
+    ("potential force sign", "out[n] = c1 * lap[n] - c3 * pot_deriv(p, s, phi[0][n], chi);",
+     "out[n] = c1 * lap[n] + c3 * pot_deriv(p, s, phi[0][n], chi);", "test_oracle_scalar.py"),
+    ("Friedmann kinetic weight", "((al - 2.0) * EK_tot(E)", "((al - 1.0) * EK_tot(E)", "test_oracle_scalar.py"),
+    ("drift scale factor", "drift(st, a_mid, h);                                          /* phi drift      */",
+     "drift(st, a_n1, h);", "test_oracle_scalar.py"),
+    ("Yoshida middle weight sign", "*w0 = -c / (2.0 - c);", "*w0 = c / (2.0 - c);", "test_oracle_scalar.py"),
+    ("leapfrog first half kick", "double w = (c->lf_stag == 0) ? 0.5 * h : h;", "double w = h;",
+     "test_oracle_scalar.py"),
+    ("gradient energy power of a", "/ (double)V / (2.0 * a * a);", "/ (double)V / (2.0 * a);",
+     "test_oracle_scalar.py"),
+    ("U(1) current sign", "double J = e / dx * (pr * ai - pim * ar);", "double J = e / dx * (pr * ai + pim * ar);",
+     "test_oracle_u1.py"),
+    ("U(1) plaquette index", "A[i][nbr(N, x, y, z, j, +1)] +", "A[i][nbr(N, x, y, z, i, +1)] +",
+     "test_oracle_u1.py"),
+    ("U(1) backward link conjugation", "double cm = cos(e * dx * A[i][nm]), sm = sin(e * dx * A[i][nm]);",
+     "double cm = cos(e * dx * A[i][nm]), sm = -sin(e * dx * A[i][nm]);", "test_oracle_u1.py"),
+    ("Hessian cross term", "double h01 = 2.0 * p->q * f * x;", "double h01 = p->q * f * x;",
+     "test_oracle_adjoint.py"),
+    ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
+     "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * h * lphi[s][n];", "test_oracle_adjoint.py"),
+]
+
+
+@pytest.mark.parametrize("name,old,new,tests", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, old, new, tests):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site not found: {name}"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "mut.c")
+        so = os.path.join(d, "libmut.so")
+        open(c, "w").write(src.replace(old, new, 1))
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o", so, c, "-lm"],
+                       check=True, capture_output=True)
+        env = dict(os.environ, ORACLE_LIB=so)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", tests)], cwd=ROOT, env=env, capture_output=True,
+                           text=True, timeout=600)
+        assert r.returncode != 0, f"planted mistake '{name}' was not caught:\n{r.stdout[-2000:]}"
