@@ -47,7 +47,8 @@ def stored_traffic(kind: str, per_launch_alg: float):
 
 def run_extras(args, log):
     """The other workloads' headline numbers: the adjoint/forward time ratio
-    (two fields, 64^3, 2000 VV2 steps), the batched ensemble rate (256 lattices
+    (two fields, 64^3, 2000 VV2 steps), the U(1) stage (128^3 leapfrog), the
+    batched ensemble rate (256 lattices
     of 24^3..64^3, float32, 2000 LF steps, one captured graph) and the
     single-field 32^3 leapfrog run (1000 steps)."""
     import torch
@@ -90,6 +91,33 @@ def run_extras(args, log):
                       "forward_pass_us": fus, "adjoint_pass_us": aus}
     lat.close()
     log(f"[bench] adjoint: reverse/forward {r['reverse_ms'] / r['forward_ms']:.2f}, per pass {aus / fus:.2f}")
+    # U(1) gauge + complex scalar, 128^3, leapfrog: ten N^3 float64 arrays, each
+    # read once and written once per step (160 B per site)
+    uw = workloads.ABELIAN_HIGGS_128
+    uf = uw.initial_fields()
+    ut = [[torch.tensor(a.reshape(-1), device=dev) for a in f] for f in uf]
+    lu = Lattice(ut[0], ut[1], A=ut[2], piA=ut[3], N=uw.N, dx=uw.dx, dt=uw.dt, integrator="lf", expansion="none",
+                 potential="abelian_higgs", lam=uw.lam, v=uw.v, e=uw.e, kappa_g=uw.kappa_g)
+    lu.step(uw.steps)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    lu.step(uw.steps)
+    torch.cuda.synchronize()
+    uwall = time.perf_counter() - c0
+    lu.stats(reset=True)
+    lu.profile(True)
+    lu.step(uw.steps)
+    st = lu.stats(reset=True)
+    lu.profile(False)
+    uus = 1e3 * st["kernel_ms"]["u1"] / max(st["launches"]["u1"], 1)
+    ue = lu.energy()
+    res["u1"] = {"workload": uw.name, "steps": uw.steps, "us_per_step": 1e6 * uwall / uw.steps,
+                 "value": uw.N ** 3 * uw.steps / uwall, "unit": "site-updates/s",
+                 "mean_launch_us": uus, "achieved_GBs_alg": uw.N ** 3 * 160 / (uus * 1e-6) / 1e9,
+                 "gauss_max_over_terms": ue["gauss_max"] / max(ue["gauss_div_max"], ue["gauss_charge_max"], 1e-300)}
+    lu.close()
+    log(f"[bench] U(1): {res['u1']['us_per_step']:.1f} us per step, stage {uus:.1f} us, "
+        f"{res['u1']['achieved_GBs_alg']:.0f} GB/s algorithmic")
     # batched ensemble
     bw = workloads.BATCH
     sizes = bw.sizes()
@@ -122,13 +150,18 @@ def run_extras(args, log):
     tq = [torch.tensor(pi[0].reshape(-1), device=dev)]
     l0 = Lattice(tp, tq, N=w0.N, dx=w0.dx, dt=w0.dt, integrator="lf", expansion="fixed", potential="phi4",
                  lam=w0.lam, alpha=w0.alpha, w_eos=w0.w_eos, H0=w0.H0, a0=w0.a0)
-    l0.step(100)
+    # the first call of a step count captures its graph; later calls replay it
     torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    l0.step(w0.steps)
+    torch.cuda.synchronize()
+    w_first = time.perf_counter() - c0
     c0 = time.perf_counter()
     l0.step(w0.steps)
     torch.cuda.synchronize()
     w = time.perf_counter() - c0
     res["lphi4_32"] = {"workload": w0.name, "steps": w0.steps, "us_per_step": 1e6 * w / w0.steps,
+                       "us_per_step_first_call": 1e6 * w_first / w0.steps,
                        "value": w0.N ** 3 * w0.steps / w, "unit": "site-updates/s"}
     l0.close()
     return res

@@ -89,10 +89,15 @@ struct lat_ctx {
     ScaleRecord *sc_host = nullptr;
     PassCoef *coef = nullptr;
     size_t coef_cap = 0;
-    PassCoef *coef_host = nullptr;
-    size_t coef_host_cap = 0;
-    hipEvent_t upload_ev = nullptr;
-    bool upload_pending = false;
+    // pinned staging for the table: a ring of slots, so the host fills the next
+    // call's table while earlier uploads are still queued behind running passes
+    static constexpr int kRing = 4;
+    PassCoef *coef_host = nullptr;      // the current slot
+    PassCoef *ring_base = nullptr;
+    size_t ring_cap = 0;                // entries per slot
+    int ring_slot = 0;
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_pending[kRing] = {};
     // host mirror of the clock
     double t = 0.0;
     int lf_stag = 0;
@@ -135,6 +140,19 @@ struct lat_ctx {
     hipGraph_t graph = nullptr;
     int64_t graph_n = 0;
     int graph_parity = -1;
+    // single-lattice graphs of the pass launches of lattice_step calls, keyed
+    // by (signed step count, leapfrog phase); least recently used is replaced
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        int64_t n = 0;
+        int stag = 0;
+        int end_phi[2] = {0, 0}, end_pi[2] = {0, 0};
+        int64_t launches[8] = {};
+        uint64_t used = 0;
+    };
+    static constexpr int kStepGraphs = 4;
+    StepGraph sg[kStepGraphs];
+    uint64_t sg_clock = 0;
     std::string err;
 };
 
@@ -406,7 +424,7 @@ lat_status harvest_timing(lat_ctx *c)
 }
 
 template <typename T>
-lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode)
+lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream)
 {
     const VariantIO io = variant_io(variant);
     ScalarArgs<T> a{};
@@ -440,11 +458,11 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode)
     }
     hipError_t e;
     if (c->rows)
-        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, variant, a, c->nblocks, c->stream)
-                       : launch_rows<T, 2>(c->N, c->rows_ty, variant, a, c->nblocks, c->stream);
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, variant, a, c->nblocks, stream)
+                       : launch_rows<T, 2>(c->N, c->rows_ty, variant, a, c->nblocks, stream);
     else
-        e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, c->stream)
-                       : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, c->stream);
+        e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
+                       : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);
     if (e != hipSuccess) return fail(c, LAT_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
     if (c->profiling) {
         lat_status st = timing_end(c, ev0, ev1, variant);
@@ -458,10 +476,88 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode)
     return LAT_OK;
 }
 
+lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream)
+{
+    return c->f32 ? run_pass_t<float>(c, variant, pass_index, last_mode, stream)
+                  : run_pass_t<double>(c, variant, pass_index, last_mode, stream);
+}
+
 lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode)
 {
-    return c->f32 ? run_pass_t<float>(c, variant, pass_index, last_mode)
-                  : run_pass_t<double>(c, variant, pass_index, last_mode);
+    return run_pass(c, variant, pass_index, last_mode, c->stream);
+}
+
+// Enqueue the pass launches of one lattice_step call.  Outside profiling,
+// calls of at least kGraphMinPasses passes are captured once into a HIP graph
+// per (step count, leapfrog phase) and replayed; shorter calls launch directly,
+// where a graph launch costs more than it saves.  The per-call coefficient
+// table is uploaded before, outside the graph, so a replay reads the current
+// coefficients.  Buffer bookkeeping at the start of a call is always the
+// caller's arrays (settled), so a replay ends in the same buffer state as the
+// captured launches.
+constexpr int64_t kGraphMinPasses = 8;
+
+void drop_step_graphs(lat_ctx *c)
+{
+    for (auto &g : c->sg) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = lat_ctx::StepGraph{};
+    }
+}
+
+template <typename F>
+lat_status launch_passes(lat_ctx *c, int64_t key_n, int64_t passes, F &&enqueue)
+{
+    if (c->profiling || passes < kGraphMinPasses || std::getenv("LATTICE_NO_GRAPH")) return enqueue(c->stream);
+    for (int f = 0; f < c->nf; ++f)
+        if (c->cur_phi[f] || c->cur_pi[f]) return enqueue(c->stream);
+    if (!c->capture_stream && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return enqueue(c->stream);
+    lat_ctx::StepGraph *hit = nullptr, *victim = &c->sg[0];
+    for (auto &g : c->sg) {
+        if (g.exec && g.n == key_n && g.stag == c->lf_stag) hit = &g;
+        if (!g.exec || (victim->exec && g.used < victim->used)) victim = &g;
+    }
+    if (!hit) {
+        lat_ctx::StepGraph &g = *victim;
+        if (g.exec) HIPCHK(c, hipGraphExecDestroy(g.exec));
+        g = lat_ctx::StepGraph{};
+        const int stag0 = c->lf_stag;
+        int64_t before[8];
+        std::memcpy(before, c->launches, sizeof(before));
+        HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        lat_status st = enqueue(c->capture_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+        if (st != LAT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, LAT_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return fail(c, LAT_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        for (int i = 0; i < 8; ++i) g.launches[i] = c->launches[i] - before[i];
+        for (int f = 0; f < 2; ++f) {
+            g.end_phi[f] = c->cur_phi[f];
+            g.end_pi[f] = c->cur_pi[f];
+        }
+        g.n = key_n;
+        g.stag = stag0;
+        hit = &g;
+    } else {
+        for (int i = 0; i < 8; ++i) c->launches[i] += hit->launches[i];
+        for (int f = 0; f < 2; ++f) {
+            c->cur_phi[f] = hit->end_phi[f];
+            c->cur_pi[f] = hit->end_pi[f];
+        }
+    }
+    hit->used = ++c->sg_clock;
+    HIPCHK(c, hipGraphLaunch(hit->exec, c->stream));
+    return LAT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -469,11 +565,10 @@ lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode)
 // ---------------------------------------------------------------------------
 lat_status reserve_coef(lat_ctx *c, size_t n)
 {
-    if (c->upload_pending) {
-        HIPCHK(c, hipEventSynchronize(c->upload_ev));
-        c->upload_pending = false;
-    }
     if (n > c->coef_cap) {
+        // captured graphs hold the table's address: drop them with it
+        drop_step_graphs(c);
+        c->graph_n = 0;
         if (c->coef) HIPCHK(c, hipFree(c->coef));
         c->coef = nullptr;
         size_t cap = n < 64 ? 64 : n;
@@ -481,23 +576,36 @@ lat_status reserve_coef(lat_ctx *c, size_t n)
             return fail(c, LAT_ENOMEM, "coefficient table allocation failed");
         c->coef_cap = cap;
     }
-    if (n > c->coef_host_cap) {
-        if (c->coef_host) HIPCHK(c, hipHostFree(c->coef_host));
-        c->coef_host = nullptr;
+    if (n > c->ring_cap) {
+        for (int i = 0; i < lat_ctx::kRing; ++i) {
+            if (c->ring_pending[i]) HIPCHK(c, hipEventSynchronize(c->ring_ev[i]));
+            c->ring_pending[i] = false;
+        }
+        if (c->ring_base) HIPCHK(c, hipHostFree(c->ring_base));
+        c->ring_base = nullptr;
         size_t cap = n < 64 ? 64 : n;
-        if (hipHostMalloc((void **)&c->coef_host, cap * sizeof(PassCoef), hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void **)&c->ring_base, lat_ctx::kRing * cap * sizeof(PassCoef), hipHostMallocDefault) !=
+            hipSuccess)
             return fail(c, LAT_ENOMEM, "pinned coefficient staging allocation failed");
-        c->coef_host_cap = cap;
+        c->ring_cap = cap;
     }
+    c->ring_slot = (c->ring_slot + 1) % lat_ctx::kRing;
+    const int k = c->ring_slot;
+    if (c->ring_pending[k]) {
+        HIPCHK(c, hipEventSynchronize(c->ring_ev[k]));
+        c->ring_pending[k] = false;
+    }
+    c->coef_host = c->ring_base + (size_t)k * c->ring_cap;
     std::memset(c->coef_host, 0, n * sizeof(PassCoef));
     return LAT_OK;
 }
 
 lat_status upload_coef(lat_ctx *c, size_t n)
 {
+    const int k = c->ring_slot;
     HIPCHK(c, hipMemcpyAsync(c->coef, c->coef_host, n * sizeof(PassCoef), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipEventRecord(c->upload_ev, c->stream));
-    c->upload_pending = true;
+    HIPCHK(c, hipEventRecord(c->ring_ev[k], c->stream));
+    c->ring_pending[k] = true;
     return LAT_OK;
 }
 
@@ -548,8 +656,14 @@ lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
         stag = dir;
     }
     if ((s = upload_coef(c, (size_t)ns)) != LAT_OK) return s;
-    for (int64_t k = 0; k < ns; ++k)
-        if ((s = run_pass(c, kKickDrift, (int)k, kLastStore)) != LAT_OK) return s;
+    s = launch_passes(c, dir * ns, ns, [&](hipStream_t st) {
+        for (int64_t k = 0; k < ns; ++k) {
+            lat_status r = run_pass(c, kKickDrift, (int)k, kLastStore, st);
+            if (r != LAT_OK) return r;
+        }
+        return LAT_OK;
+    });
+    if (s != LAT_OK) return s;
     c->lf_stag = dir;
     c->t = t_start + (double)ns * h;
     return LAT_OK;
@@ -603,15 +717,20 @@ lat_status step_vv(lat_ctx *c, int64_t ns, int dir)
         }
     }
     if ((s = upload_coef(c, (size_t)M + 2)) != LAT_OK) return s;
-    if (self) {
-        hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, c->stream, c->coef, c->sc, al);
-        HIPCHK(c, hipGetLastError());
-    }
     const int mode = self ? kLastSelf : kLastStore;
-    for (int64_t p = 0; p <= M; ++p) {
-        const int v = p == 0 ? (self ? kKickOnlyRed : kKickOnly) : (self ? kDriftKickRed : kDriftKick);
-        if ((s = run_pass(c, v, (int)p, mode)) != LAT_OK) return s;
-    }
+    s = launch_passes(c, dir * ns, M + 1, [&](hipStream_t st) {
+        if (self) {
+            hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, st, c->coef, c->sc, al);
+            HIPCHK(c, hipGetLastError());
+        }
+        for (int64_t p = 0; p <= M; ++p) {
+            const int v = p == 0 ? (self ? kKickOnlyRed : kKickOnly) : (self ? kDriftKickRed : kDriftKick);
+            lat_status r = run_pass(c, v, (int)p, mode, st);
+            if (r != LAT_OK) return r;
+        }
+        return LAT_OK;
+    });
+    if (s != LAT_OK) return s;
     c->t = t_start + (double)ns * h;
     return LAT_OK;
 }
@@ -687,7 +806,7 @@ lat_status validate(const lat_params *p, const lat_fields *f)
 void free_ctx(lat_ctx *c)
 {
     if (!c) return;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     for (int f = 0; f < 2; ++f) {
         if (c->phi[f][1]) (void)hipFree(c->phi[f][1]);
         if (c->pi[f][1]) (void)hipFree(c->pi[f][1]);
@@ -698,9 +817,10 @@ void free_ctx(lat_ctx *c)
     if (c->ticket) (void)hipFree(c->ticket);
     if (c->sc) (void)hipFree(c->sc);
     if (c->coef) (void)hipFree(c->coef);
-    if (c->coef_host) (void)hipHostFree(c->coef_host);
+    if (c->ring_base) (void)hipHostFree(c->ring_base);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
-    if (c->upload_ev) (void)hipEventDestroy(c->upload_ev);
+    for (auto e : c->ring_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &t : c->timed) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -713,6 +833,7 @@ void free_ctx(lat_ctx *c)
     if (c->ckpt) (void)hipFree(c->ckpt);
     if (c->adj_partials) (void)hipFree(c->adj_partials);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    drop_step_graphs(c);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->reals_dev) (void)hipFree(c->reals_dev);
@@ -789,8 +910,9 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     if (hipMalloc(&c->sc, sizeof(ScaleRecord)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
     if (hipHostMalloc((void **)&c->sc_host, sizeof(ScaleRecord), hipHostMallocDefault) != hipSuccess)
         return bail(LAT_ENOMEM, "pinned allocation failed");
-    if (hipEventCreateWithFlags(&c->upload_ev, hipEventDisableTiming) != hipSuccess)
-        return bail(LAT_EHIP, "event creation failed");
+    for (auto &e : c->ring_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(LAT_EHIP, "event creation failed");
     if (hipMemsetAsync(c->ticket, 0, 64, c->stream) != hipSuccess) return bail(LAT_EHIP, "memset failed");
 
     // initial scale record
@@ -1472,8 +1594,13 @@ lat_status batch_step_t(lat_ctx *c, int64_t ns)
         stag = 1;
     }
     if ((s = upload_coef(c, (size_t)ns)) != LAT_OK) return s;
+    const bool eager = std::getenv("LATTICE_NO_GRAPH") != nullptr;
+    if (eager) {
+        for (int64_t k = 0; k < ns; ++k)
+            if ((s = batch_launch<T>(c, c->stream, (int)k, (int)((c->batch_parity + k) & 1), 0)) != LAT_OK) return s;
+    }
     // (re)capture the graph of ns batched passes starting at the current parity
-    if (!c->graph_exec || c->graph_n != ns || c->graph_parity != c->batch_parity) {
+    if (!eager && (!c->graph_exec || c->graph_n != ns || c->graph_parity != c->batch_parity)) {
         if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
         if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
         c->graph_exec = nullptr;
@@ -1493,7 +1620,7 @@ lat_status batch_step_t(lat_ctx *c, int64_t ns)
         c->graph_n = ns;
         c->graph_parity = c->batch_parity;
     }
-    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    if (!eager) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
     c->launches[4] += ns;
     c->batch_parity = (int)((c->batch_parity + ns) & 1);
     if (c->batch_parity == 1) {
@@ -1568,8 +1695,9 @@ extern "C" lat_status lattice_init_batch(lat_ctx **out, const lat_params *p, int
     }
     if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(LAT_EHIP, "stream creation failed");
-    if (hipEventCreateWithFlags(&c->upload_ev, hipEventDisableTiming) != hipSuccess)
-        return bail(LAT_EHIP, "event creation failed");
+    for (auto &e : c->ring_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(LAT_EHIP, "event creation failed");
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
     lat_status st;
     if (tune) {

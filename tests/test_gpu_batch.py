@@ -126,3 +126,24 @@ def test_batch_fp32_short_vs_oracle_all_sizes():
         say(f"[batch] fp32 N={N} 100 steps: phi {ephi:.2e} pi {epi:.2e}")
         assert ephi < 2e-6 and epi < 2e-4
     lb.close()
+
+
+def test_batch_graph_replays_match_eager(monkeypatch):
+    import torch
+    wl = workloads.BATCH
+    sizes = [24, 32, 48, 64, 17]
+    la, fa, pa, qa = make_batch(wl, sizes, torch.float32, "f32", autotune=False)
+    monkeypatch.setenv("LATTICE_NO_GRAPH", "1")
+    lb, fb, pb, qb = make_batch(wl, sizes, torch.float32, "f32", autotune=False)
+    for rep in range(4):
+        monkeypatch.delenv("LATTICE_NO_GRAPH", raising=False)
+        la.step(9)
+        torch.cuda.synchronize()
+        monkeypatch.setenv("LATTICE_NO_GRAPH", "1")
+        lb.step(9)
+        torch.cuda.synchronize()
+        for x, y in zip(pa + qa, pb + qb):
+            assert torch.equal(x, y), f"replay {rep} differs"
+        _ = (pa[0] * 2.0).sum().item()
+    la.close()
+    lb.close()
