@@ -63,6 +63,29 @@ __device__ inline double load_agent(const double *p)
 // Logical block id from the hardware block id: consecutive hardware blocks are
 // dealt round-robin to the 8 XCDs, so give each XCD a contiguous range of
 // logical tiles (neighbouring tiles then share that XCD's L2).
+// Element access through a 32-bit byte offset from a uniform base pointer
+// (valid while N^3 * sizeof(T) < 2^32, i.e. N <= 256 in float64).  Forming the
+// offset in 32 bits lets the compiler use the scalar-base + 32-bit-offset
+// global load and store forms, so every array shares one offset register
+// instead of holding a 64-bit address per access.
+template <typename T>
+__device__ __forceinline__ T ld32(const T *base, unsigned i)
+{
+    return *(const T *)((const char *)base + (size_t)(i * (unsigned)sizeof(T)));
+}
+
+template <typename T>
+__device__ __forceinline__ void st32(T *base, unsigned i, T v)
+{
+    *(T *)((char *)base + (size_t)(i * (unsigned)sizeof(T))) = v;
+}
+
+template <typename T>
+__device__ __forceinline__ void st32_nt(T *base, unsigned i, T v)
+{
+    __builtin_nontemporal_store(v, (T *)((char *)base + (size_t)(i * (unsigned)sizeof(T))));
+}
+
 __device__ inline int xcd_logical_block(int b, int nb)
 {
     const int per = nb / 8, rem = nb % 8;

@@ -44,6 +44,7 @@ lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir);
 lat_status u1_sync(lat_ctx *c);
 lat_status u1_energy(lat_ctx *c, lat_energies *out);
 size_t u1_partial_capacity(int N);
+void u1_geometry(lat_ctx *c);
 lat_status batch_step(lat_ctx *c, int64_t nsteps);
 
 struct TileCfg {
@@ -81,6 +82,8 @@ struct lat_ctx {
     void *A[3][2] = {};
     void *piA[3] = {};
     int cur_A[3] = {0, 0, 0};
+    bool u1_rows = false;   // whole-row U(1) leapfrog kernel
+    int u1_ty = 4, u1_zc = 8;
     // scratch
     double *partials = nullptr;
     size_t partial_cap = 0;
@@ -904,7 +907,10 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
         }
     }
     c->partial_cap = (size_t)(c->nblocks > 1 ? c->nblocks : 1) * kMaxQ + 64;
-    if (c->u1) c->partial_cap = u1_partial_capacity(c->N) + 64;
+    if (c->u1) {
+        c->partial_cap = u1_partial_capacity(c->N) + 64;
+        u1_geometry(c);
+    }
     if (hipMalloc(&c->partials, c->partial_cap * sizeof(double)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&c->ticket, 64) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&c->sc, sizeof(ScaleRecord)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
@@ -1108,6 +1114,7 @@ U1Args u1_args(lat_ctx *c, double ck, double hd, bool write_fields)
     a.N = c->N;
     a.tiles_x = (c->N + kU1TX - 1) / kU1TX;
     a.tiles_y = (c->N + kU1TY - 1) / kU1TY;
+    a.zc = c->u1_zc;
     a.dx = c->p.dx;
     a.e = c->p.e_charge;
     a.lam = c->p.lambda;
@@ -1121,6 +1128,45 @@ U1Args u1_args(lat_ctx *c, double ck, double hd, bool write_fields)
     return a;
 }
 
+// whole-row leapfrog pass: N = 64 XS, rows per block TY in {4, 8} (N = 64)
+// or {2, 4} (N = 128), 64 XS TY threads (one site each per plane)
+bool u1_rows_shape_ok(int N, int ty)
+{
+    return (N == 64 && (ty == 4 || ty == 8)) || (N == 128 && (ty == 2 || ty == 4));
+}
+
+hipError_t launch_u1_rows(const lat_ctx *c, const U1Args &a)
+{
+    const int nb = (c->N / c->u1_ty) * ((c->N + c->u1_zc - 1) / c->u1_zc);
+    const dim3 nt(c->N * c->u1_ty);
+    if (c->N == 64 && c->u1_ty == 4) hipLaunchKernelGGL((u1_rows<1, 4>), dim3(nb), nt, 0, c->stream, a);
+    else if (c->N == 64) hipLaunchKernelGGL((u1_rows<1, 8>), dim3(nb), nt, 0, c->stream, a);
+    else if (c->u1_ty == 2) hipLaunchKernelGGL((u1_rows<2, 2>), dim3(nb), nt, 0, c->stream, a);
+    else hipLaunchKernelGGL((u1_rows<2, 4>), dim3(nb), nt, 0, c->stream, a);
+    return hipGetLastError();
+}
+
+// U(1) launch geometry: whole-row kernel for N = 64, 128 unless LATTICE_U1_TILE
+// says "tile"; "TY,zc" overrides the row kernel's rows per block and z chunk.
+void u1_geometry(lat_ctx *c)
+{
+    c->u1_rows = c->N == 64 || c->N == 128;
+    c->u1_ty = c->N == 128 ? 2 : 4;
+    c->u1_zc = c->N == 128 ? 16 : 4;
+    const char *env = std::getenv("LATTICE_U1_TILE");
+    if (!env) return;
+    if (std::strcmp(env, "tile") == 0) {
+        c->u1_rows = false;
+        return;
+    }
+    int ty = 0, zc = 0;
+    if (c->u1_rows && std::sscanf(env, "%d,%d", &ty, &zc) == 2 && u1_rows_shape_ok(c->N, ty) && zc >= 1 &&
+        zc <= c->N) {
+        c->u1_ty = ty;
+        c->u1_zc = zc;
+    }
+}
+
 lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
 {
     const int nb = a.tiles_x * a.tiles_y * c->N;
@@ -1132,6 +1178,10 @@ lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
     }
     switch (mode) {
     case kU1Step:
+        if (c->u1_rows) {
+            HIPCHK(c, launch_u1_rows(c, a));
+            break;
+        }
         hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Step>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
         break;
     case kU1Kick:

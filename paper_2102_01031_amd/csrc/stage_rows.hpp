@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const int y0 = by * TY;
     const int z0 = bz * g.zc;
     const int z1 = min(z0 + g.zc, N);
-    const size_t NN = (size_t)N * (size_t)N;
+    const unsigned NN = (unsigned)N * (unsigned)N;   // N^3 < 2^32
 
     const int yrow = y0 + w;
     const bool valid = yrow < N;
@@ -71,11 +71,11 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     T hAf[HPT][NF], hAp[HPT][NF], hBf[HPT][NF], hBp[HPT][NF];
 
     {
-        const size_t om = (size_t)(z0 == 0 ? N - 1 : z0 - 1) * NN;
-        const size_t o0 = (size_t)z0 * NN;
-        const size_t o1 = (size_t)((z0 + 1) % N) * NN;
-        const size_t o2 = (size_t)(min(z0 + 2, z1) % N) * NN;
-        const size_t oh1 = (size_t)(min(z0 + 1, z1 - 1) % N) * NN;
+        const unsigned om = (unsigned)(z0 == 0 ? N - 1 : z0 - 1) * NN;
+        const unsigned o0 = (unsigned)z0 * NN;
+        const unsigned o1 = (unsigned)((z0 + 1) % N) * NN;
+        const unsigned o2 = (unsigned)(min(z0 + 2, z1) % N) * NN;
+        const unsigned oh1 = (unsigned)(min(z0 + 1, z1 - 1) % N) * NN;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const T *P = g.phi_in[f];
@@ -83,27 +83,27 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
             for (int k = 0; k < XS; ++k) {
                 const int o = yo + lane + 64 * k;
-                const T a = P[om + o];
-                fm[k][f] = DLOAD ? a + dl * Q[om + o] : a;
-                const T b = P[o0 + o];
-                p0[k][f] = Q[o0 + o];
+                const T a = ld32(P, om + o);
+                fm[k][f] = DLOAD ? a + dl * ld32(Q, om + o) : a;
+                const T b = ld32(P, o0 + o);
+                p0[k][f] = ld32(Q, o0 + o);
                 f0[k][f] = DLOAD ? b + dl * p0[k][f] : b;
-                const T c = P[o1 + o];
-                pp[k][f] = Q[o1 + o];
+                const T c = ld32(P, o1 + o);
+                pp[k][f] = ld32(Q, o1 + o);
                 fp[k][f] = DLOAD ? c + dl * pp[k][f] : c;
-                oAf[k][f] = P[o2 + o];
-                oAp[k][f] = Q[o2 + o];
+                oAf[k][f] = ld32(P, o2 + o);
+                oAp[k][f] = ld32(Q, o2 + o);
                 lds[0][f][orow + lane + 64 * k] = f0[k][f];
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 hAf[j][f] = hAp[j][f] = T(0);
                 if (hval[j]) {
-                    T h = P[o0 + hoff[j]];
-                    if (DLOAD) h += dl * Q[o0 + hoff[j]];
+                    T h = ld32(P, o0 + hoff[j]);
+                    if (DLOAD) h += dl * ld32(Q, o0 + hoff[j]);
                     lds[0][f][hslot[j]] = h;
-                    hAf[j][f] = P[oh1 + hoff[j]];
-                    if (DLOAD) hAp[j][f] = Q[oh1 + hoff[j]];
+                    hAf[j][f] = ld32(P, oh1 + hoff[j]);
+                    if (DLOAD) hAp[j][f] = ld32(Q, oh1 + hoff[j]);
                 }
             }
         }
@@ -121,21 +121,21 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
         if (zo >= N) zo -= N;
         int zh = min(z + 2, z1 - 1);
         if (zh >= N) zh -= N;
-        const size_t o3 = (size_t)zo * NN, o2 = (size_t)zh * NN;
+        const unsigned o3 = (unsigned)zo * NN, o2 = (unsigned)zh * NN;
         // (A) loads one plane ahead
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
             for (int k = 0; k < XS; ++k) {
                 const int o = yo + lane + 64 * k;
-                oof[k][f] = g.phi_in[f][o3 + o];
-                oop[k][f] = g.pi_in[f][o3 + o];
+                oof[k][f] = ld32(g.phi_in[f], o3 + o);
+                oop[k][f] = ld32(g.pi_in[f], o3 + o);
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 if (hval[j]) {
-                    hof[j][f] = g.phi_in[f][o2 + hoff[j]];
-                    if (DLOAD) hop[j][f] = g.pi_in[f][o2 + hoff[j]];
+                    hof[j][f] = ld32(g.phi_in[f], o2 + hoff[j]);
+                    if (DLOAD) hop[j][f] = ld32(g.pi_in[f], o2 + hoff[j]);
                 }
             }
         }
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             }
         }
         // (C) the XS sites of this lane at plane z
-        const size_t oz = (size_t)z * NN + yo;
+        const unsigned oz = (unsigned)z * NN + yo;
 #pragma unroll
         for (int k = 0; k < XS; ++k) {
             const int x = lane + 64 * k;
@@ -193,8 +193,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                 const T pn = pm + c2 * F;
                 const T fo = DEND ? f0[k][f] + de * pn : f0[k][f];
                 if (valid) {
-                    if (WPHI) __builtin_nontemporal_store(fo, &g.phi_out[f][oz + x]);
-                    if (WPI) __builtin_nontemporal_store(pn, &g.pi_out[f][oz + x]);
+                    if (WPHI) st32_nt(g.phi_out[f], oz + x, fo);
+                    if (WPI) st32_nt(g.pi_out[f], oz + x, pn);
                 }
             }
             if (RED && valid) {

@@ -29,7 +29,7 @@ struct U1Args {
     const double *A_in[3];
     double *A_out[3];
     double *piA[3];
-    int N, tiles_x, tiles_y;
+    int N, tiles_x, tiles_y, zc;
     double dx, e, lam, v, kappa_g;
     double ck;   // kick weight
     double hd;   // drift weight
@@ -226,6 +226,298 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
                 }
                 __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+        }
+    }
+}
+
+// Leapfrog pass for N = 64 * XS (XS in {1, 2}) that shares the transcendental
+// work between neighbouring sites.  A block owns TY whole x rows and marches z
+// over [z0, z1); each thread owns one site of each plane (row y0 + w / XS,
+// x = 64 (w % XS) + lane for wavefront w).  Per plane every site evaluates its
+// own three plaquette sines sin theta_ij(n) and its three link phases
+// (cos, sin)(e dx A_i(n)) once; the values at n - x and n - y are read from
+// LDS, those at n - z are carried in registers from the previous plane, and
+// the row y0 - 1 below the block is evaluated by the block's threads, one
+// operation each.  Every angle is formed by the same expression, in the same
+// order, as in u1_stage: the same arithmetic without the repeated sines.
+template <int XS, int TY>
+__global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
+{
+    constexpr int NT = 64 * XS * TY;
+    constexpr int NX = 64 * XS;               // == N
+    constexpr int R = TY + 2;                 // LDS rows stand for y0 - 1 .. y0 + TY
+    constexpr int NH = 2 * NX;                // halo cells per plane: LDS rows 0 and TY + 1
+    constexpr int HPT = (NH + NT - 1) / NT;
+    constexpr int NOP = 3 * NX;               // halo-row transcendental operations per plane
+    constexpr int OPT = (NOP + NT - 1) / NT;
+
+    __shared__ double s_p0[R * NX], s_p1[R * NX];                 // psi, rows 0 .. TY+1
+    __shared__ double s_ax[R * NX], s_az[R * NX];                 // A_x, A_z, rows 0 .. TY+1
+    __shared__ double s_ay[(TY + 1) * NX], s_ayn[NX];             // A_y rows 0 .. TY; A_y(row 0, z+1)
+    __shared__ double s_sxy[(TY + 1) * NX], s_syz[(TY + 1) * NX]; // rows 0 .. TY
+    __shared__ double s_cy[(TY + 1) * NX], s_sy[(TY + 1) * NX];   // phase of A_y, rows 0 .. TY
+    __shared__ double s_sxz[TY * NX];                             // own rows (index row - 1)
+    __shared__ double s_cx[TY * NX], s_sx[TY * NX];               // phase of A_x, own rows
+    __shared__ double s_cz[TY * NX], s_sz[TY * NX];               // phase of A_z, own rows
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int r = w / XS + 1;                 // LDS row of this thread's site
+    const int x = (w % XS) * 64 + lane;
+    const int xm = (x - 1) & (NX - 1), xp = (x + 1) & (NX - 1);
+    const int ro = r * NX + x;                // this site in rows 0 .. TY+1 arrays
+    const int wo = (r - 1) * NX + x;          // this site in own-row arrays
+    const int N = NX;
+    const int lid = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int chunks = (N + g.zc - 1) / g.zc;
+    const int bz = lid % chunks;
+    const int by = lid / chunks;
+    const int y0 = by * TY;
+    const int z0 = bz * g.zc;
+    const int z1 = min(z0 + g.zc, N);
+    const unsigned NN = (unsigned)N * (unsigned)N;   // N^3 < 2^32
+    const unsigned so = (unsigned)((y0 + r - 1) * N + x);   // site offset within a plane
+    const int yb = (y0 == 0 ? N - 1 : y0 - 1) * N;
+    const int yt = ((y0 + TY) % N) * N;
+
+    const double edx = g.e * g.dx;
+    const double inv_dx2 = 1.0 / (g.dx * g.dx);
+    const double inv_edx3 = 1.0 / (g.e * g.dx * g.dx * g.dx);
+    const double ck = g.ck, hd = g.hd;
+
+    // halo cells: c < NX is row 0 (y0 - 1), else row TY + 1 (y0 + TY)
+    int hrow[HPT], hx[HPT];
+    unsigned hoff[HPT];
+    bool hval[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int c = tid + j * NT;
+        hval[j] = c < NH;
+        const bool bot = c < NX;
+        hx[j] = bot ? c : c - NX;
+        hrow[j] = bot ? 0 : TY + 1;
+        hoff[j] = hval[j] ? (unsigned)((bot ? yb : yt) + hx[j]) : 0u;
+    }
+
+    double wm[2], w0[2], wp[2];   // psi at z - 1, z, z + 1
+    double a0[3], a1[3];          // A at z, z + 1
+    double czm, szm, sxzm, syzm;  // link phase of A_z and sines theta_xz, theta_yz at n - z
+    double hp0[HPT], hp1[HPT], hax[HPT], hay[HPT], haz[HPT], hayn[HPT];
+
+    // ---- prologue: window, A, halo rows of plane z0, carried values of plane z0 - 1
+    {
+        const unsigned om = (unsigned)(z0 == 0 ? N - 1 : z0 - 1) * NN;
+        const unsigned o0 = (unsigned)z0 * NN;
+        const unsigned o1 = (unsigned)((z0 + 1) % N) * NN;
+        double am[3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            wm[c] = ld32(g.phi_in[c], om + so);
+            w0[c] = ld32(g.phi_in[c], o0 + so);
+            wp[c] = ld32(g.phi_in[c], o1 + so);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            am[i] = ld32(g.A_in[i], om + so);
+            a0[i] = ld32(g.A_in[i], o0 + so);
+            a1[i] = ld32(g.A_in[i], o1 + so);
+        }
+        s_az[ro] = am[2];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            hp0[j] = hp1[j] = hax[j] = hay[j] = haz[j] = hayn[j] = 0.0;
+            if (hval[j]) {
+                hp0[j] = ld32(g.phi_in[0], o0 + hoff[j]);
+                hp1[j] = ld32(g.phi_in[1], o0 + hoff[j]);
+                hax[j] = ld32(g.A_in[0], o0 + hoff[j]);
+                haz[j] = ld32(g.A_in[2], o0 + hoff[j]);
+                if (hrow[j] == 0) {
+                    hay[j] = ld32(g.A_in[1], o0 + hoff[j]);
+                    hayn[j] = ld32(g.A_in[1], o1 + hoff[j]);
+                } else {
+                    s_az[(TY + 1) * NX + hx[j]] = ld32(g.A_in[2], om + hoff[j]);
+                }
+            }
+        }
+        __syncthreads();
+        const double txz = edx * ((s_az[r * NX + xp] - am[2]) - a0[0] + am[0]);
+        const double tyz = edx * ((s_az[(r + 1) * NX + x] - am[2]) - a0[1] + am[1]);
+        sxzm = sin(txz);
+        syzm = sin(tyz);
+        sincos(edx * am[2], &szm, &czm);
+        __syncthreads();
+    }
+
+    for (int z = z0; z < z1; ++z) {
+        const unsigned oz = (unsigned)z * NN;
+        // (A) plane z into LDS
+        s_p0[ro] = w0[0];
+        s_p1[ro] = w0[1];
+        s_ax[ro] = a0[0];
+        s_ay[ro] = a0[1];
+        s_az[ro] = a0[2];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (hval[j]) {
+                const int hs = hrow[j] * NX + hx[j];
+                s_p0[hs] = hp0[j];
+                s_p1[hs] = hp1[j];
+                s_ax[hs] = hax[j];
+                s_az[hs] = haz[j];
+                if (hrow[j] == 0) {
+                    s_ay[hx[j]] = hay[j];
+                    s_ayn[hx[j]] = hayn[j];
+                }
+            }
+        }
+        __syncthreads();
+
+        // (B0) loads for the next plane: psi, A of plane z + 2 and the halo rows
+        // of plane z + 1 (indices clamped to valid planes after the chunk's end)
+        int z2 = min(z + 2, z1);
+        if (z2 >= N) z2 -= N;
+        int zh = min(z + 1, z1 - 1);
+        if (zh >= N) zh -= N;
+        int zhn = zh + 1;
+        if (zhn >= N) zhn -= N;
+        const unsigned o2 = (unsigned)z2 * NN, oh = (unsigned)zh * NN, ohn = (unsigned)zhn * NN;
+        double nps[2], na[3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) nps[c] = ld32(g.phi_in[c], o2 + so);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) na[i] = ld32(g.A_in[i], o2 + so);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (hval[j]) {
+                hp0[j] = ld32(g.phi_in[0], oh + hoff[j]);
+                hp1[j] = ld32(g.phi_in[1], oh + hoff[j]);
+                hax[j] = ld32(g.A_in[0], oh + hoff[j]);
+                haz[j] = ld32(g.A_in[2], oh + hoff[j]);
+                if (hrow[j] == 0) {
+                    hay[j] = ld32(g.A_in[1], oh + hoff[j]);
+                    hayn[j] = ld32(g.A_in[1], ohn + hoff[j]);
+                }
+            }
+        }
+
+        // (B) own plaquette sines and link phases into LDS, one evaluation at a
+        // time (the loops are not unrolled, which keeps the inlined sin and
+        // sincos from being interleaved and bounds the register footprint);
+        // then the halo row's, one operation per thread
+        {
+            const double txy = edx * ((s_ay[r * NX + xp] - a0[1]) - s_ax[(r + 1) * NX + x] + a0[0]);
+            const double txz = edx * ((s_az[r * NX + xp] - a0[2]) - a1[0] + a0[0]);
+            const double tyz = edx * ((s_az[(r + 1) * NX + x] - a0[2]) - a1[1] + a0[1]);
+#pragma unroll 1
+            for (int j = 0; j < 3; ++j) {
+                const double t = j == 0 ? txy : (j == 1 ? txz : tyz);
+                double *dst = j == 0 ? &s_sxy[ro] : (j == 1 ? &s_sxz[wo] : &s_syz[ro]);
+                *dst = sin(t);
+            }
+#pragma unroll 1
+            for (int j = 0; j < 3; ++j) {
+                const double t = edx * (j == 0 ? a0[0] : (j == 1 ? a0[1] : a0[2]));
+                double sv, cv;
+                sincos(t, &sv, &cv);
+                const int sl = j == 1 ? ro : wo;
+                double *ds = j == 0 ? s_sx : (j == 1 ? s_sy : s_sz);
+                double *dc = j == 0 ? s_cx : (j == 1 ? s_cy : s_cz);
+                ds[sl] = sv;
+                dc[sl] = cv;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            const int id = tid + j * NT;
+            if (id < NOP) {
+                const int op = id / NX, hxo = id % NX;
+                const int hxp = (hxo + 1) & (NX - 1);
+                if (op == 0) {
+                    double sv, cv;
+                    sincos(edx * s_ay[hxo], &sv, &cv);
+                    s_sy[hxo] = sv;
+                    s_cy[hxo] = cv;
+                } else if (op == 1) {
+                    s_sxy[hxo] = sin(edx * ((s_ay[hxp] - s_ay[hxo]) - s_ax[NX + hxo] + s_ax[hxo]));
+                } else {
+                    s_syz[hxo] = sin(edx * ((s_az[NX + hxo] - s_az[hxo]) - s_ayn[hxo] + s_ay[hxo]));
+                }
+            }
+        }
+        __syncthreads();
+
+        // (C) forces, kick, drift
+        {
+            const unsigned o = oz + so;
+            double pq[2], pa[3];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) pq[c] = ld32(g.pi[c], o);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) pa[i] = ld32(g.piA[i], o);
+            const double sxy = s_sxy[ro], sxz = s_sxz[wo], syz = s_syz[ro];
+            const double mag[3] = {(sxy - s_sxy[ro - NX]) + (sxz - sxzm),
+                                   (-sxy + s_sxy[r * NX + xm]) + (syz - syzm),
+                                   (-sxz + s_sxz[(r - 1) * NX + xm]) + (-syz + s_syz[ro - NX])};
+            const double pr = w0[0], pim = w0[1];
+            double d2r = 0.0, d2i = 0.0, J[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double qr, qi, rr, ri, sm, cm;
+                if (i == 0) {
+                    qr = s_p0[r * NX + xp]; qi = s_p1[r * NX + xp];
+                    rr = s_p0[r * NX + xm]; ri = s_p1[r * NX + xm];
+                    sm = s_sx[(r - 1) * NX + xm]; cm = s_cx[(r - 1) * NX + xm];
+                } else if (i == 1) {
+                    qr = s_p0[ro + NX]; qi = s_p1[ro + NX];
+                    rr = s_p0[ro - NX]; ri = s_p1[ro - NX];
+                    sm = s_sy[ro - NX]; cm = s_cy[ro - NX];
+                } else {
+                    qr = wp[0]; qi = wp[1];
+                    rr = wm[0]; ri = wm[1];
+                    sm = szm; cm = czm;
+                }
+                const int ow = i == 1 ? ro : wo;
+                const double *Ls = i == 0 ? s_sx : (i == 1 ? s_sy : s_sz);
+                const double *Lc = i == 0 ? s_cx : (i == 1 ? s_cy : s_cz);
+                const double s = -Ls[ow], c = Lc[ow];   // V_i(n) = c + i s
+                const double ar = c * qr - s * qi, ai = c * qi + s * qr;
+                const double br = cm * rr - sm * ri, bi = cm * ri + sm * rr;
+                d2r += ar - 2.0 * pr + br;
+                d2i += ai - 2.0 * pim + bi;
+                J[i] = g.e / g.dx * (pr * ai - pim * ar);
+            }
+            const double m2 = 0.5 * (pr * pr + pim * pim);
+            const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
+            const double F0 = d2r * inv_dx2 - vp * pr;
+            const double F1 = d2i * inv_dx2 - vp * pim;
+            const double q0 = pq[0] + ck * F0, q1 = pq[1] + ck * F1;
+            st32(g.pi[0], o, q0);
+            st32(g.pi[1], o, q1);
+            st32(g.phi_out[0], o, pr + hd * q0);
+            st32(g.phi_out[1], o, pim + hd * q1);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double FA = g.kappa_g * J[i] - mag[i] * inv_edx3;
+                const double qa = pa[i] + ck * FA;
+                st32(g.piA[i], o, qa);
+                st32(g.A_out[i], o, a0[i] + hd * qa);
+            }
+            czm = s_cz[wo];
+            szm = s_sz[wo];
+            sxzm = sxz;
+            syzm = syz;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            wm[c] = w0[c];
+            w0[c] = wp[c];
+            wp[c] = nps[c];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            a0[i] = a1[i];
+            a1[i] = na[i];
         }
     }
 }

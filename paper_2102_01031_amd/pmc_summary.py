@@ -76,6 +76,21 @@ def copy_factor(d, counter):
     return expect_kib / kib, kib
 
 
+def all_kernels(trace_dir, command, out_dir):
+    """Per-kernel stats table of a --kernel-trace --stats run of the whole
+    benchmark (every workload's kernels)."""
+    stats = list(csv.DictReader(open(csv_in(trace_dir, "kernel_stats.csv"))))
+    lines = ["# all kernels of the default benchmark run", "",
+             f"Command: `rocprofv3 --kernel-trace --stats -d <dir> -o all --output-format csv -- {command}`", "",
+             "| kernel | calls | average us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {r['Name'][:100]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    with open(os.path.join(out_dir, "kernels_bench_default.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -85,7 +100,11 @@ def main():
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--command", required=True, help="the bench command that was profiled")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--all-trace", help="--kernel-trace --stats run of the whole default benchmark")
+    ap.add_argument("--all-command", default="python3 bench.py --no-cpu-baseline")
     a = ap.parse_args()
+    if a.all_trace:
+        all_kernels(a.all_trace, a.all_command, a.out)
 
     ff, fk = copy_factor(a.copy_fetch, "FETCH_SIZE")
     wf, wk = copy_factor(a.copy_write, "WRITE_SIZE")
@@ -132,10 +151,10 @@ def main():
              f"Copy calibration: FETCH_SIZE reads {fk:.0f} KiB per 1 GiB copy -> factor {ff:.4f}; "
              f"WRITE_SIZE {wk:.0f} KiB -> factor {wf:.4f}.", "",
              "## kernel stats (rocprofv3 --stats)", "",
-             "| kernel | calls | average ns | total ns | % |", "|---|---|---|---|---|"]
+             "| kernel | calls | average ns | min ns | max ns | total ns | % |", "|---|---|---|---|---|---|---|"]
     for r in stats[:12]:
-        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['TotalDurationNs']} | "
-                     f"{float(r['Percentage']):.2f} |")
+        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | "
+                     f"{r['MaxNs']} | {r['TotalDurationNs']} | {float(r['Percentage']):.2f} |")
     lines += ["", "## per variant (trace mean, counters per dispatch)", "",
               "| variant | launches | mean us (trace) | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes / launch (scaled) |",
               "|---|---|---|---|---|---|"]

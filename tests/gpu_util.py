@@ -22,19 +22,21 @@ def say(msg):
 
 
 @contextmanager
-def tile_env(spec):
-    old = os.environ.get("LATTICE_TILE")
+def tile_env(spec, var="LATTICE_TILE"):
+    """Set a launch-shape override (LATTICE_TILE, LATTICE_U1_TILE) for the
+    lattices created inside the block."""
+    old = os.environ.get(var)
     if spec is None:
-        os.environ.pop("LATTICE_TILE", None)
+        os.environ.pop(var, None)
     else:
-        os.environ["LATTICE_TILE"] = spec
+        os.environ[var] = spec
     try:
         yield
     finally:
         if old is None:
-            os.environ.pop("LATTICE_TILE", None)
+            os.environ.pop(var, None)
         else:
-            os.environ["LATTICE_TILE"] = old
+            os.environ[var] = old
 
 
 def scalar_kwargs(wl, N=None, **over):

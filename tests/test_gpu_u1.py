@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import rel_maxdiff, say, to_dev
+from gpu_util import rel_maxdiff, say, tile_env, to_dev
 from paper_2102_01031_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -79,6 +79,29 @@ def test_u1_parity_small(N, steps):
     assert abs(eg["gauss_charge_max"] - go["charge_max"]) <= 1e-12 * go["charge_max"]
     scale = max(go["div_max"], go["charge_max"])
     assert eg["gauss_max"] <= 1e-12 * scale and go["gauss_max"] <= 1e-12 * scale
+    lat.close()
+
+
+@pytest.mark.parametrize("N,spec,steps", [(64, "4,4", 8), (64, "8,24", 8), (64, "4,64", 5), (64, "8,1", 4),
+                                           (64, "tile", 5), (128, "4,40", 2), (128, "2,8", 2), (128, "2,128", 2)])
+def test_u1_rows_kernel_parity(N, spec, steps):
+    """The whole-row leapfrog kernel (N = 64, 128) over its launch shapes: 2, 4 or
+    8 rows per block, z chunks that divide N, leave a ragged last chunk (24, 40),
+    are one plane (1) or the whole lattice (64); 'tile' forces the per-plane
+    kernel at the same size."""
+    wl = workloads.ABELIAN_HIGGS_128
+    kw = u1_kwargs(wl, N)
+    fields = wl.initial_fields(N=N)
+    say(f"[u1] rows kernel N={N} shape={spec} steps={steps}")
+    with tile_env(spec, "LATTICE_U1_TILE"):
+        lat, gt = gpu_u1(kw, fields, [steps])
+    eg = lat.energy()
+    st = oracle_u1(kw, fields).run(steps)
+    compare_u1(gt, st, TOL, f"u1-rows-{N}-{spec}")
+    compare_u1_energy(eg, st.energy(), TOL, f"u1-rows-{N}-{spec}")
+    go = st.gauss()
+    scale = max(go["div_max"], go["charge_max"])
+    assert eg["gauss_max"] <= 1e-12 * scale
     lat.close()
 
 
