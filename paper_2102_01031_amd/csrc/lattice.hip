@@ -1151,7 +1151,7 @@ hipError_t launch_u1_rows(const lat_ctx *c, const U1Args &a)
 void u1_geometry(lat_ctx *c)
 {
     c->u1_rows = c->N == 64 || c->N == 128;
-    c->u1_ty = c->N == 128 ? 2 : 4;
+    c->u1_ty = 4;
     c->u1_zc = c->N == 128 ? 16 : 4;
     const char *env = std::getenv("LATTICE_U1_TILE");
     if (!env) return;

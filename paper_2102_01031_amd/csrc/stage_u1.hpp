@@ -19,6 +19,7 @@
 //   G = sum_i (piA_i(n) - piA_i(n-i))/dx - e kappa_g (phi0 pi1 - phi1 pi0).
 #pragma once
 #include "common.hpp"
+#include "trig.hpp"
 
 namespace lat {
 
@@ -342,9 +343,9 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
         __syncthreads();
         const double txz = edx * ((s_az[r * NX + xp] - am[2]) - a0[0] + am[0]);
         const double tyz = edx * ((s_az[(r + 1) * NX + x] - am[2]) - a0[1] + am[1]);
-        sxzm = sin(txz);
-        syzm = sin(tyz);
-        sincos(edx * am[2], &szm, &czm);
+        sxzm = lat_sin(txz);
+        syzm = lat_sin(tyz);
+        lat_sincos(edx * am[2], &szm, &czm);
         __syncthreads();
     }
 
@@ -400,25 +401,23 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             }
         }
 
-        // (B) own plaquette sines and link phases into LDS, one evaluation at a
-        // time (the loops are not unrolled, which keeps the inlined sin and
-        // sincos from being interleaved and bounds the register footprint);
-        // then the halo row's, one operation per thread
+        // (B) own plaquette sines and link phases into LDS; then the halo
+        // row's, one operation per thread
         {
             const double txy = edx * ((s_ay[r * NX + xp] - a0[1]) - s_ax[(r + 1) * NX + x] + a0[0]);
             const double txz = edx * ((s_az[r * NX + xp] - a0[2]) - a1[0] + a0[0]);
             const double tyz = edx * ((s_az[(r + 1) * NX + x] - a0[2]) - a1[1] + a0[1]);
-#pragma unroll 1
+#pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double t = j == 0 ? txy : (j == 1 ? txz : tyz);
                 double *dst = j == 0 ? &s_sxy[ro] : (j == 1 ? &s_sxz[wo] : &s_syz[ro]);
-                *dst = sin(t);
+                *dst = lat_sin(t);
             }
-#pragma unroll 1
+#pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double t = edx * (j == 0 ? a0[0] : (j == 1 ? a0[1] : a0[2]));
                 double sv, cv;
-                sincos(t, &sv, &cv);
+                lat_sincos(t, &sv, &cv);
                 const int sl = j == 1 ? ro : wo;
                 double *ds = j == 0 ? s_sx : (j == 1 ? s_sy : s_sz);
                 double *dc = j == 0 ? s_cx : (j == 1 ? s_cy : s_cz);
@@ -434,13 +433,13 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                 const int hxp = (hxo + 1) & (NX - 1);
                 if (op == 0) {
                     double sv, cv;
-                    sincos(edx * s_ay[hxo], &sv, &cv);
+                    lat_sincos(edx * s_ay[hxo], &sv, &cv);
                     s_sy[hxo] = sv;
                     s_cy[hxo] = cv;
                 } else if (op == 1) {
-                    s_sxy[hxo] = sin(edx * ((s_ay[hxp] - s_ay[hxo]) - s_ax[NX + hxo] + s_ax[hxo]));
+                    s_sxy[hxo] = lat_sin(edx * ((s_ay[hxp] - s_ay[hxo]) - s_ax[NX + hxo] + s_ax[hxo]));
                 } else {
-                    s_syz[hxo] = sin(edx * ((s_az[NX + hxo] - s_az[hxo]) - s_ayn[hxo] + s_ay[hxo]));
+                    s_syz[hxo] = lat_sin(edx * ((s_az[NX + hxo] - s_az[hxo]) - s_ayn[hxo] + s_ay[hxo]));
                 }
             }
         }
