@@ -150,9 +150,11 @@ lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f,
  * Provided for LAT_PHI4 with LAT_LF and LAT_EXP_NONE or LAT_EXP_FIXED, float64 or
  * float32.  lattice_step on such a context advances every realization with
  * one batched launch per step; the launches of a call are captured once into a
- * HIP graph and replayed.  With autotune = 1 the tile shape and z chunk of
- * each distinct lattice size are chosen by timing candidates on scratch
- * buffers (the fields are not modified); otherwise a fixed table is used.
+ * HIP graph and replayed.  With autotune = 1 the mode of each distinct
+ * lattice size (a tile shape and z chunk, or one thread per site) is chosen by
+ * timing candidates on scratch buffers, first for that size alone, then with
+ * every realization in the launch (the fields are not modified); otherwise a
+ * fixed table is used (LATTICE_BATCH_TILE="tx,zc" or "site" overrides it).
  * lattice_energy_batch reads realization r; lattice_sync and lattice_destroy
  * act on all of them. */
 lat_status lattice_init_batch(lat_ctx **ctx, const lat_params *p, int32_t n_real, const int32_t *N_per_real,
@@ -161,7 +163,8 @@ lat_status lattice_init_batch(lat_ctx **ctx, const lat_params *p, int32_t n_real
 /* Energies of realization r of a batch context (as lattice_energy). */
 lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
 
-/* Tile shape and z chunk the batch uses for lattice size N (host output). */
+/* Tile shape and z chunk the batch uses for lattice size N (host output);
+ * tile_x = tile_y = z_chunk = 0 means one thread per site, no tiling. */
 lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, int32_t *tile_y, int32_t *z_chunk);
 
 /* Advance |nsteps| time steps (sec. 4.5.2; LF and VV of sec. 4.3), backward

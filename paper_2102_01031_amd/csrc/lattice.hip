@@ -13,12 +13,15 @@
 // kick coefficients on the device, so no host round trip sits between passes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lattice.h"
@@ -28,8 +31,6 @@
 #include "stage_u1.hpp"
 #include "stage_adjoint.hpp"
 #include "stage_batch.hpp"
-#include <map>
-#include <utility>
 
 using namespace lat;
 
@@ -133,7 +134,7 @@ struct lat_ctx {
     std::vector<lat_ctx *> subs;
     void *reals_dev = nullptr;          // BatchReal<T>[n]
     std::vector<char> reals_host;       // host copy (bytes)
-    int *block_real = nullptr;
+    int2 *block_work = nullptr;         // BatchArgs::block_work table
     int batch_blocks = 0;
     std::vector<void *> pi_scratch;
     std::map<int, std::pair<int, int>> batch_tile;   // N -> (tile x, z chunk)
@@ -840,7 +841,7 @@ void free_ctx(lat_ctx *c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->reals_dev) (void)hipFree(c->reals_dev);
-    if (c->block_real) (void)hipFree(c->block_real);
+    if (c->block_work) (void)hipFree(c->block_work);
     for (void *q : c->pi_scratch)
         if (q) (void)hipFree(q);
     for (lat_ctx *sub : c->subs) free_ctx(sub);
@@ -1491,7 +1492,8 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
 // ===========================================================================
 namespace {
 
-constexpr int kBatchTX[] = {64, 32, 16, 8};
+constexpr int kBatchTX[] = {64, 32, 16, 8, 0};   // 0: one thread per site
+constexpr int kBatchSiteMaxN = 512;                // per-site mode: N^3 * 8 < 2^32
 
 template <typename T>
 BatchReal<T> make_real(lat_ctx *sub, void *scratch, int tx, int zc)
@@ -1502,6 +1504,10 @@ BatchReal<T> make_real(lat_ctx *sub, void *scratch, int tx, int zc)
     R.pi = (T *)sub->pi[0][0];
     R.pi_scratch = (T *)scratch;
     R.N = sub->N;
+    if (tx == 0) {   // one thread per site
+        R.tx = R.ty = R.zc = R.tiles_x = R.tiles_y = 0;
+        return R;
+    }
     R.tx = tx;
     R.ty = kBatchThreads / tx;
     R.zc = zc < 1 ? 1 : (zc > R.N ? R.N : zc);
@@ -1512,18 +1518,25 @@ BatchReal<T> make_real(lat_ctx *sub, void *scratch, int tx, int zc)
 
 int real_blocks(int N, int tx, int zc)
 {
+    if (tx == 0) return (int)(((size_t)N * N * N + kBatchThreads - 1) / kBatchThreads);
     const int ty = kBatchThreads / tx;
     return ((N + tx - 1) / tx) * ((N + ty - 1) / ty) * ((N + zc - 1) / zc);
 }
 
 // Build the realization table and block table for the realizations in `which`
-// (all when empty) with the tiles in c->batch_tile, and upload them.
+// (all when empty) with the tiles in c->batch_tile, and upload them.  Blocks
+// are dispatched round-robin over the 8 XCDs (block b on XCD b % 8), so the
+// table is built per XCD and interleaved: whole realizations go to the XCD
+// with the fewest sites so far (largest first), each XCD's list starts with
+// its longest blocks (z-marching tiles by chunk length, then one-site blocks),
+// and shorter lists are padded with empty entries.
+constexpr int kXcds = 8;
+
 template <typename T>
 lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
 {
     const int n = (int)c->subs.size();
     std::vector<BatchReal<T>> reals(n);
-    std::vector<int> blocks;
     for (int r = 0; r < n; ++r) {
         const auto tz = c->batch_tile[c->subs[r]->N];
         reals[r] = make_real<T>(c->subs[r], c->pi_scratch[r], tz.first, tz.second);
@@ -1531,23 +1544,42 @@ lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
     std::vector<int> list = which;
     if (list.empty())
         for (int r = 0; r < n; ++r) list.push_back(r);
+    std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return reals[a].N > reals[b].N; });
+    std::vector<std::vector<int>> per(kXcds);
+    std::vector<double> load(kXcds, 0.0);
     for (int r : list) {
-        reals[r].first_block = (int)blocks.size();
-        const int nb = reals[r].tiles_x * reals[r].tiles_y * ((reals[r].N + reals[r].zc - 1) / reals[r].zc);
-        for (int b = 0; b < nb; ++b) blocks.push_back(r);
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        per[x].push_back(r);
+        load[x] += (double)reals[r].N * reals[r].N * reals[r].N;
     }
+    std::vector<std::vector<int2>> seq(kXcds);
+    size_t longest = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        std::stable_sort(per[x].begin(), per[x].end(), [&](int a, int b) {
+            const int wa = reals[a].tx ? reals[a].zc : 0, wb = reals[b].tx ? reals[b].zc : 0;
+            return wa > wb;
+        });
+        for (int r : per[x]) {
+            const int nb = real_blocks(reals[r].N, reals[r].tx, reals[r].zc);
+            for (int b = 0; b < nb; ++b) seq[x].push_back(make_int2(r, b));
+        }
+        longest = std::max(longest, seq[x].size());
+    }
+    std::vector<int2> blocks(longest * kXcds, make_int2(-1, 0));
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t j = 0; j < seq[x].size(); ++j) blocks[j * kXcds + x] = seq[x][j];
     const size_t rbytes = (size_t)n * sizeof(BatchReal<T>);
     if (!c->reals_dev && hipMalloc(&c->reals_dev, rbytes) != hipSuccess)
         return fail(c, LAT_ENOMEM, "batch table allocation failed");
     if ((int)blocks.size() > c->batch_blocks) {
-        if (c->block_real) HIPCHK(c, hipFree(c->block_real));
-        c->block_real = nullptr;
-        if (hipMalloc(&c->block_real, blocks.size() * sizeof(int)) != hipSuccess)
+        if (c->block_work) HIPCHK(c, hipFree(c->block_work));
+        c->block_work = nullptr;
+        if (hipMalloc(&c->block_work, blocks.size() * sizeof(int2)) != hipSuccess)
             return fail(c, LAT_ENOMEM, "batch block table allocation failed");
         c->batch_blocks = (int)blocks.size();
     }
     HIPCHK(c, hipMemcpy(c->reals_dev, reals.data(), rbytes, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->block_real, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->block_work, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice));
     c->reals_host.assign((const char *)reals.data(), (const char *)reals.data() + rbytes);
     c->nblocks = (int)blocks.size();
     return LAT_OK;
@@ -1558,7 +1590,7 @@ BatchArgs<T> batch_args(lat_ctx *c, int pass_index, int parity, int tuning)
 {
     BatchArgs<T> a{};
     a.reals = (const BatchReal<T> *)c->reals_dev;
-    a.block_real = c->block_real;
+    a.block_work = c->block_work;
     a.coef = c->coef + pass_index;
     a.parity = parity;
     a.tuning = tuning;
@@ -1600,7 +1632,8 @@ lat_status autotune(lat_ctx *c)
             if (tx > 2 * N && tx != 8) continue;
             const int zcs[] = {4, 8, 16, 32, N};
             for (int zc : zcs) {
-                if (zc > N) continue;
+                // one candidate for the per-site mode, which forms 32-bit byte offsets
+                if (zc > N || (tx == 0 && (zc != 4 || N > kBatchSiteMaxN))) continue;
                 c->batch_tile[N] = {tx, zc};
                 if ((s = build_tables<T>(c, g.second)) != LAT_OK) return s;
                 if ((s = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return s;   // warm
@@ -1618,6 +1651,43 @@ lat_status autotune(lat_ctx *c)
             }
         }
         c->batch_tile[N] = best_cfg;
+    }
+    // refine: with every realization in the launch (the sizes share the caches
+    // and the XCDs), revisit each size's shape, largest size first
+    if (groups.size() > 1) {
+        auto time_all = [&](float *ms) -> lat_status {
+            lat_status st = build_tables<T>(c, {});
+            if (st != LAT_OK) return st;
+            if ((st = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return st;   // warm
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            for (int it = 0; it < 3; ++it)
+                if ((st = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return st;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
+            return LAT_OK;
+        };
+        for (auto g = groups.rbegin(); g != groups.rend(); ++g) {
+            const int N = g->first;
+            float best = 0.f;
+            if ((s = time_all(&best)) != LAT_OK) return s;
+            std::pair<int, int> best_cfg = c->batch_tile[N];
+            for (int tx : kBatchTX) {
+                if (tx > 2 * N && tx != 8) continue;
+                const int zcs[] = {4, 8, 16, 32, N};
+                for (int zc : zcs) {
+                    if (zc > N || (tx == 0 && (zc != 4 || N > kBatchSiteMaxN))) continue;
+                    c->batch_tile[N] = {tx, zc};
+                    float ms = 0.f;
+                    if ((s = time_all(&ms)) != LAT_OK) return s;
+                    if (ms < best) {
+                        best = ms;
+                        best_cfg = {tx, zc};
+                    }
+                }
+            }
+            c->batch_tile[N] = best_cfg;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1741,6 +1811,15 @@ extern "C" lat_status lattice_init_batch(lat_ctx **out, const lat_params *p, int
             const int N = sub->N;
             const int tx = N % 64 == 0 ? 64 : N % 32 == 0 ? 32 : N % 16 == 0 ? 16 : 8;
             c->batch_tile[N] = {tx, N >= 48 ? 16 : 8};
+            // LATTICE_BATCH_TILE="tx,zc" (tx in {64, 32, 16, 8}) or "site" sets the
+            // shape of every size when the autotuner is off
+            if (const char *env = std::getenv("LATTICE_BATCH_TILE")) {
+                int etx = 0, ezc = 0;
+                if (std::strcmp(env, "site") == 0 && N <= kBatchSiteMaxN) c->batch_tile[N] = {0, 0};
+                else if (std::sscanf(env, "%d,%d", &etx, &ezc) == 2 && (etx == 64 || etx == 32 || etx == 16 ||
+                                                                        etx == 8) && ezc >= 1)
+                    c->batch_tile[N] = {etx, ezc};
+            }
         }
     }
     if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
@@ -1776,7 +1855,7 @@ extern "C" lat_status lattice_batch_tile(const lat_ctx *c, int32_t N, int32_t *t
     auto it = c->batch_tile.find(N);
     if (it == c->batch_tile.end()) return LAT_EINVAL;
     *tx = it->second.first;
-    *ty = kBatchThreads / it->second.first;
-    *zc = it->second.second;
+    *ty = it->second.first ? kBatchThreads / it->second.first : 0;
+    *zc = it->second.first ? it->second.second : 0;
     return LAT_OK;
 }

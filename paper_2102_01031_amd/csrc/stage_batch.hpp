@@ -3,8 +3,12 @@
 //
 // Physics per site as in stage_scalar.hpp (sec. 4.5.2 at one kick point,
 // V = lambda/4 phi^4).  Each block looks up its realization and tile in a work
-// table; the tile shape (TX x TY = 256 threads, TX in {8, 16, 32, 64}) and the
-// z chunk are per realization, chosen by the autotuner for that lattice size.
+// table.  Per realization, chosen by the autotuner for its lattice size, a
+// block either marches a z chunk of a TX x TY tile (TX x TY = 256 threads,
+// TX in {8, 16, 32, 64}; drifted-phi planes in LDS, z window in registers) or,
+// with TX = 0, updates 256 consecutive sites with one thread each and reads
+// the six neighbours through the caches (no LDS, no barrier: for small
+// lattices, where a z march is a long serial chain over few blocks).
 // The kick and drift coefficients are shared: every realization sits at the
 // same time on the same background.  phi is read with a halo and written to the
 // other buffer of its pair (buffer parity is a launch argument, so a captured
@@ -21,13 +25,13 @@ struct BatchReal {
     T *pi;              // caller buffer
     T *pi_scratch;      // tuning target (state untouched)
     int N, tx, ty, zc;
-    int tiles_x, tiles_y, first_block, pad;
+    int tiles_x, tiles_y, pad0, pad1;
 };
 
 template <typename T>
 struct BatchArgs {
     const BatchReal<T> *reals;
-    const int *block_real;   // realization of each block
+    const int2 *block_work;  // per launched block: (realization, block within it); -1: none
     const PassCoef *coef;
     int parity;              // phi read from buffer parity, written to parity ^ 1
     int tuning;              // 1: write pi to pi_scratch
@@ -41,9 +45,35 @@ template <typename T>
 __global__ void __launch_bounds__(kBatchThreads) batch_lf_stage(const BatchArgs<T> g)
 {
     __shared__ T lds[2][kBatchLds];
-    const int r = g.block_real[blockIdx.x];
-    const BatchReal<T> R = g.reals[r];
-    const int lid = blockIdx.x - R.first_block;
+    // the host lays the table out in dispatch order: block b runs on XCD b % 8,
+    // each realization sits on one XCD (its halos in one L2), the XCDs carry
+    // balanced site counts, and each XCD starts with its longest blocks
+    const int2 wk = g.block_work[blockIdx.x];
+    if (wk.x < 0) return;
+    const BatchReal<T> R = g.reals[wk.x];
+    const int lid = wk.y;
+    if (R.tx == 0) {
+        // one site per thread; the same arithmetic, in the same order, as the tiled path
+        const unsigned N = (unsigned)R.N, NN = N * N, V = NN * N;
+        const unsigned i = (unsigned)lid * kBatchThreads + threadIdx.x;
+        if (i >= V) return;
+        const unsigned z = i / NN, rem = i - z * NN, y = rem / N, x = rem - y * N;
+        const unsigned ixm = x == 0 ? i + N - 1 : i - 1, ixp = x == N - 1 ? i + 1 - N : i + 1;
+        const unsigned iym = y == 0 ? i + NN - N : i - N, iyp = y == N - 1 ? i + N - NN : i + N;
+        const unsigned izm = z == 0 ? i + V - NN : i - NN, izp = z == N - 1 ? i + NN - V : i + NN;
+        const T *P = (g.parity ? R.phi[1] : R.phi[0]);
+        const PassCoef C = *g.coef;
+        const T c1 = (T)C.c1, c2 = (T)C.c2, de = (T)C.dend, ka1 = (T)C.ka1, ka3 = (T)C.ka3;
+        const T idx2 = (T)g.inv_dx2, lam = (T)g.lam;
+        const T f0 = ld32(P, i);
+        const T lap = ((ld32(P, ixp) - T(2) * f0 + ld32(P, ixm)) + (ld32(P, iyp) - T(2) * f0 + ld32(P, iym)) +
+                       (ld32(P, izp) - T(2) * f0 + ld32(P, izm))) * idx2;
+        const T F = ka1 * lap - ka3 * (lam * f0 * f0 * f0);
+        const T pn = (ld32((const T *)R.pi, i) + c1 * F) + c2 * F;
+        st32((g.parity ? R.phi[0] : R.phi[1]), i, f0 + de * pn);
+        st32(g.tuning ? R.pi_scratch : R.pi, i, pn);
+        return;
+    }
     const int TX = R.tx, TY = R.ty, LX = TX + 2;
     const int N = R.N;
     const int bx = lid % R.tiles_x;
@@ -78,8 +108,10 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lf_stage(const BatchArgs<
         hslot = sy * LX + sx;
         hoff = hx + N * hy;
     }
-    const T *P = R.phi[g.parity];
-    T *Pout = R.phi[g.parity ^ 1];
+    // buffers chosen by selects, not by indexing R.phi with a runtime value:
+    // that would make R a per-thread array (moved to LDS or scratch)
+    const T *P = (g.parity ? R.phi[1] : R.phi[0]);
+    T *Pout = (g.parity ? R.phi[0] : R.phi[1]);
     const T *Q = R.pi;
     T *Qout = g.tuning ? R.pi_scratch : R.pi;
     const PassCoef C = *g.coef;
@@ -156,7 +188,7 @@ __global__ void batch_settle(const BatchReal<T> *reals, int n_real, int which)
     const BatchReal<T> R = reals[r];
     const size_t V = (size_t)R.N * R.N * R.N;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += (size_t)gridDim.x * blockDim.x)
-        R.phi[which ^ 1][i] = R.phi[which][i];
+        (which ? R.phi[0] : R.phi[1])[i] = (which ? R.phi[1] : R.phi[0])[i];
 }
 
 }  // namespace lat

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import rel_maxdiff, say, to_dev
+from gpu_util import rel_maxdiff, say, tile_env, to_dev
 from paper_2102_01031_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -58,6 +58,30 @@ def test_batch_fp64_parity_uneven_sizes():
         assert rel_maxdiff(pis[r].cpu().numpy(), st.pi[0]) <= 1e-12, (r, N)
         e, eo = lb.energy(r), st.energy()
         assert abs(e["rho"] - eo["rho"]) <= 1e-12 * eo["rho"] and abs(e["a"] - eo["a"]) <= 1e-14
+    lb.close()
+
+
+@pytest.mark.parametrize("spec", ["site", "16,5"])
+def test_batch_forced_shapes_fp64(spec):
+    """Every realization in one mode: one thread per site ('site': 256 consecutive
+    sites per block, the last block of each lattice partly empty for N = 5, 17,
+    24, 40) or 16-wide tiles with a z chunk of 5 (ragged chunks), against the
+    oracle per realization."""
+    import torch
+    wl = workloads.BATCH
+    sizes = [24, 5, 17, 64, 40, 32, 17]
+    with tile_env(spec, "LATTICE_BATCH_TILE"):
+        lb, fields, phis, pis = make_batch(wl, sizes, torch.float64, "f64", autotune=False)
+    for N in sorted(set(sizes)):
+        t = lb.tile(N)
+        say(f"[batch] forced {spec}: N={N} tile={t}")
+        assert (t == (0, 0, 0)) if spec == "site" else (t[0] == 16 and t[2] == 5)
+    lb.step(11).step(6)
+    torch.cuda.synchronize()
+    for r, N in enumerate(sizes):
+        st = oracle_run(wl, fields[r][0], fields[r][1], N, 17)
+        assert rel_maxdiff(phis[r].cpu().numpy(), st.phi[0]) <= 1e-12, (spec, r, N)
+        assert rel_maxdiff(pis[r].cpu().numpy(), st.pi[0]) <= 1e-12, (spec, r, N)
     lb.close()
 
 
