@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     ap.add_argument("--all-trace", help="--kernel-trace --stats run of the whole default benchmark")
     ap.add_argument("--all-command", default="python3 bench.py --no-cpu-baseline")
+    ap.add_argument("--note", default="", help="provenance line for the summary (which runs, which boxes)")
     a = ap.parse_args()
     if a.all_trace:
         all_kernels(a.all_trace, a.all_command, a.out)
@@ -147,7 +148,8 @@ def main():
              f"- `rocprofv3 --pmc FETCH_SIZE -d <dir> -o fetch --output-format csv -- {a.command}`",
              f"- `rocprofv3 --pmc WRITE_SIZE -d <dir> -o write --output-format csv -- {a.command}`",
              "- the same two counter runs on `python3 paper_2102_01031_amd/pmc_copy.py` (1 GiB device copy)",
-             "", f"Kernel source hash: `{out['kernel_hash']}`", "",
+             "", f"Kernel source hash: `{out['kernel_hash']}`", ""] + ([a.note, ""] if a.note else []) + [
+             
              f"Copy calibration: FETCH_SIZE reads {fk:.0f} KiB per 1 GiB copy -> factor {ff:.4f}; "
              f"WRITE_SIZE {wk:.0f} KiB -> factor {wf:.4f}.", "",
              "## kernel stats (rocprofv3 --stats)", "",
