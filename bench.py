@@ -179,7 +179,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the lattice step "
-              "is single-GPU; see the sharding design in DESIGN.md)", file=sys.stderr)
+              "runs on a single GPU; a multi-GPU run would split the lattice into z slabs with one-plane "
+              "halos, which is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
