@@ -232,6 +232,16 @@ def main():
     e = lat.energy()
     log(f"[bench] {n_launch} '{kind}' launches, mean {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s; "
         f"a={e['a']:.6f} hubble_res={e['hubble_res']:.2e}")
+    # measurement pass (energies and Hubble residual; read-only over phi, pi)
+    lat.stats(reset=True)
+    lat.profile(True)
+    for _ in range(5):
+        lat.energy()
+    se = lat.stats(reset=True)
+    lat.profile(False)
+    e_us = 1e3 * se["kernel_ms"]["energy"] / max(se["launches"]["energy"], 1)
+    energy_pass = {"mean_launch_us": e_us, "alg_bytes_per_launch": N ** 3 * 2 * 2 * esize,
+                   "achieved_GBs_alg": N ** 3 * 2 * 2 * esize / (e_us * 1e-6) / 1e9}
 
     # float32-fields mode on the same workload
     f32 = None
@@ -298,6 +308,7 @@ def main():
                      "mean_launch_us": avg_ms * 1e3},
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBS,
         "cpu_baseline": cpu,
+        "energy_pass": energy_pass,
         "precision_f32": f32,
     }
     out.update(extras)

@@ -156,7 +156,9 @@ lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f,
  * every realization in the launch (the fields are not modified); otherwise a
  * fixed table is used (LATTICE_BATCH_TILE="tx,zc" or "site" overrides it).
  * lattice_energy_batch reads realization r; lattice_sync and lattice_destroy
- * act on all of them. */
+ * act on all of them.  Errors: LAT_EUNSUPPORTED for other physics, LAT_EINVAL
+ * for bad arguments or any realization failing lattice_init's checks; all are
+ * reported before anything is allocated (*ctx stays NULL). */
 lat_status lattice_init_batch(lat_ctx **ctx, const lat_params *p, int32_t n_real, const int32_t *N_per_real,
                               const lat_fields *f, int32_t autotune, void *stream);
 

@@ -1781,6 +1781,16 @@ extern "C" lat_status lattice_init_batch(lat_ctx **out, const lat_params *p, int
     if (p->potential != LAT_PHI4 || p->integrator != LAT_LF ||
         (p->expansion != LAT_EXP_NONE && p->expansion != LAT_EXP_FIXED))
         return fail(nullptr, LAT_EUNSUPPORTED, "batches are provided for one field, LF, no or fixed expansion");
+    // every realization's parameters and pointers are checked before anything is allocated
+    for (int r = 0; r < n_real; ++r) {
+        lat_params pr = *p;
+        pr.N = N_per_real[r];
+        const lat_status vs = validate(&pr, &f[r]);
+        if (vs != LAT_OK) {
+            g_init_error = "realization " + std::to_string(r) + ": " + g_init_error;
+            return vs;
+        }
+    }
     lat_ctx *c = new (std::nothrow) lat_ctx();
     if (!c) return fail(nullptr, LAT_ENOMEM, "host allocation failed");
     c->p = *p;

@@ -91,3 +91,34 @@ def test_null_context_calls():
     e = L.LatEnergies()
     assert lib.lattice_energy(None, C.byref(e)) == L.LAT_EINVAL
     lib.lattice_destroy(None)
+
+
+def _init_batch(params, sizes, nfields=None):
+    n = len(sizes)
+    arr = (C.c_int32 * max(n, 1))(*sizes)
+    fl = (L.LatFields * max(n, 1))()
+    for r in range(n):
+        fl[r].phi[0] = 0x10000 + 0x100000 * r
+        fl[r].pi[0] = 0x20000 + 0x100000 * r
+    ctx = C.c_void_p()
+    rc = L.lib().lattice_init_batch(C.byref(ctx), C.byref(params), n if nfields is None else nfields, arr, fl, 0,
+                                    None)
+    return rc, ctx
+
+
+@pytest.mark.parametrize("kw,sizes,n,code", [
+    (dict(dx=0.5, dt=0.01, integrator="vv2"), [8, 16], None, L.LAT_EUNSUPPORTED),
+    (dict(dx=0.5, dt=0.01, potential="phi4_chi2"), [8, 16], None, L.LAT_EUNSUPPORTED),
+    (dict(dx=0.5, dt=0.01, integrator="vv4", expansion="self"), [8], None, L.LAT_EUNSUPPORTED),
+    (dict(dx=0.5, dt=0.01), [8, 16], 0, L.LAT_EINVAL),
+    (dict(dx=0.5, dt=0.01), [8, 1, 16], None, L.LAT_EINVAL),        # a realization with N = 1
+    (dict(dx=0.5, dt=0.3), [8], None, L.LAT_EINVAL),                 # dt/dx above 1/sqrt(3)
+])
+def test_batch_validation_errors(kw, sizes, n, code):
+    """Batch contexts: unsupported physics is refused before any device call, and
+    a bad realization fails the whole batch with nothing left allocated."""
+    p = L.make_params(N=8, **kw)
+    rc, ctx = _init_batch(p, sizes, n)
+    assert rc == code
+    assert not ctx.value
+    assert L.lib().lattice_last_error(None)
