@@ -1368,6 +1368,8 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     const int tiles_x = (N + kAdjTX - 1) / kAdjTX, tiles_y = (N + kAdjTY - 1) / kAdjTY;
     int zc = (int)((long)N * tiles_x * tiles_y / 512);
     if (zc < 4) zc = 4;
+    if (const char *env = std::getenv("LATTICE_ADJ_ZC")) zc = std::atoi(env);   // z chunk override
+    if (zc < 1) zc = 1;
     if (zc > N) zc = N;
     const int nb = tiles_x * tiles_y * ((N + zc - 1) / zc);
     const int seed_blocks = (int)((c->vol + 255) / 256);
