@@ -40,5 +40,24 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+CEILING_SRC = os.path.join(CSRC, "ceiling.hip")
+CEILING = os.path.join(CSRC, "ceiling")
+
+
+def build_ceiling(verbose: bool = False) -> str:
+    """The streaming-bandwidth probe (an executable; see csrc/ceiling.hip)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    cmd = [hipcc, *flags, "-o", CEILING + ".tmp", CEILING_SRC]
+    if verbose:
+        print(" ".join(cmd))
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    os.replace(CEILING + ".tmp", CEILING)
+    return CEILING
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_ceiling(verbose=True))

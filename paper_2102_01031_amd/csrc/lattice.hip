@@ -110,6 +110,7 @@ struct lat_ctx {
     int tile = 0;
     bool rows = false;   // whole-row kernel (N = 64 * XS)
     int rows_ty = 8;
+    int rows_pf = 1;     // whole-row kernel prefetch depth (planes)
     int zc = 0;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
     // launch statistics and optional event timing
@@ -249,6 +250,11 @@ void set_rows_geometry(lat_ctx *c, int ty, int zc)
 
 void geometry_from_env(lat_ctx *c)
 {
+    // prefetch depth of the whole-row kernel: two planes for float64 at N = 256
+    // (measured 3% faster there; float32 is not faster with it), else one;
+    // LATTICE_ROWS_PF=1|2 overrides
+    c->rows_pf = (!c->f32 && c->N == 256) ? 2 : 1;
+    if (const char *pf = std::getenv("LATTICE_ROWS_PF")) c->rows_pf = std::atoi(pf) == 2 ? 2 : 1;
     const char *s = std::getenv("LATTICE_TILE");
     if (s && std::strncmp(s, "rows", 4) == 0 && rows_ok(c->N)) {
         int ty = 8, z = 0;
@@ -309,28 +315,28 @@ hipError_t launch_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream
     return hipGetLastError();
 }
 
-template <typename T, int NF, int XS, int TY>
+template <typename T, int NF, int XS, int TY, int PF = 1>
 hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
 {
     const dim3 grid(nb), block(64 * TY);
     switch (variant) {
     case kKickOnly:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true, PF>), grid, block, 0, s, a);
         break;
     case kKickOnlyRed:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true, PF>), grid, block, 0, s, a);
         break;
     case kDriftKick:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true, PF>), grid, block, 0, s, a);
         break;
     case kDriftKickRed:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true, PF>), grid, block, 0, s, a);
         break;
     case kKickDrift:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true, PF>), grid, block, 0, s, a);
         break;
     case kEnergy:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false, PF>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -338,10 +344,13 @@ hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipS
     return hipGetLastError();
 }
 
+// pf: prefetch depth in planes (2 is instantiated for N = 256 with 4-row
+// blocks only; 8-row float64 blocks would spill at that depth)
 template <typename T, int NF>
-hipError_t launch_rows(int N, int ty, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+hipError_t launch_rows(int N, int ty, int pf, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
 {
     const int xs = N / 64;
+    if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2>(variant, a, nb, s);
     if (ty == 4) {
         if (xs == 1) return launch_rows_variant<T, NF, 1, 4>(variant, a, nb, s);
         if (xs == 2) return launch_rows_variant<T, NF, 2, 4>(variant, a, nb, s);
@@ -462,8 +471,8 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     }
     hipError_t e;
     if (c->rows)
-        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, variant, a, c->nblocks, stream)
-                       : launch_rows<T, 2>(c->N, c->rows_ty, variant, a, c->nblocks, stream);
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, c->rows_pf, variant, a, c->nblocks, stream)
+                       : launch_rows<T, 2>(c->N, c->rows_ty, c->rows_pf, variant, a, c->nblocks, stream);
     else
         e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
                        : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);

@@ -9,15 +9,20 @@
 // Block order: y tiles of one XCD are contiguous and each XCD walks every z
 // chunk of its y slab, so halo rows between tiles and z-chunk boundaries are
 // shared inside one L2.
+// PF is the prefetch depth in planes: the loads issued while plane z is
+// computed are for own plane z + 2 + PF and halo plane z + 1 + PF, landing in
+// one of PF + 1 register sets that rotate with the (PF + 1)-fold unrolled z
+// loop, so no register copies force an early wait on loads in flight.
 #pragma once
 #include "common.hpp"
 #include "stage_scalar.hpp"
 
 namespace lat {
 
-template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI>
+template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI, int PF = 1>
 __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 {
+    static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
     constexpr int NT = 64 * TY;
     constexpr int NX = 64 * XS;           // == N
     constexpr int NQ = 3 * NF;
@@ -67,8 +72,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const double lamd = g.lam, qd = g.q;
 
     T fm[XS][NF], f0[XS][NF], fp[XS][NF], p0[XS][NF], pp[XS][NF];
-    T oAf[XS][NF], oAp[XS][NF], oBf[XS][NF], oBp[XS][NF];
-    T hAf[HPT][NF], hAp[HPT][NF], hBf[HPT][NF], hBp[HPT][NF];
+    T oAf[XS][NF], oAp[XS][NF], oBf[XS][NF], oBp[XS][NF], oCf[XS][NF], oCp[XS][NF];
+    T hAf[HPT][NF], hAp[HPT][NF], hBf[HPT][NF], hBp[HPT][NF], hCf[HPT][NF], hCp[HPT][NF];
 
     {
         const unsigned om = (unsigned)(z0 == 0 ? N - 1 : z0 - 1) * NN;
@@ -106,6 +111,24 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                     if (DLOAD) hAp[j][f] = ld32(Q, oh1 + hoff[j]);
                 }
             }
+            if constexpr (PF == 2) {
+                const unsigned o3 = (unsigned)(min(z0 + 3, z1) % N) * NN;
+                const unsigned oh2 = (unsigned)(min(z0 + 2, z1 - 1) % N) * NN;
+#pragma unroll
+                for (int k = 0; k < XS; ++k) {
+                    const int o = yo + lane + 64 * k;
+                    oBf[k][f] = ld32(P, o3 + o);
+                    oBp[k][f] = ld32(Q, o3 + o);
+                }
+#pragma unroll
+                for (int j = 0; j < HPT; ++j) {
+                    hBf[j][f] = hBp[j][f] = T(0);
+                    if (hval[j]) {
+                        hBf[j][f] = ld32(P, oh2 + hoff[j]);
+                        if (DLOAD) hBp[j][f] = ld32(Q, oh2 + hoff[j]);
+                    }
+                }
+            }
         }
     }
     __syncthreads();
@@ -117,9 +140,9 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     auto plane = [&](const int z, T (&oif)[XS][NF], T (&oip)[XS][NF], T (&hif)[HPT][NF], T (&hip)[HPT][NF],
                      T (&oof)[XS][NF], T (&oop)[XS][NF], T (&hof)[HPT][NF], T (&hop)[HPT][NF]) {
         const int cur = (z - z0) & 1, nxt = cur ^ 1;
-        int zo = min(z + 3, z1);
+        int zo = min(z + 2 + PF, z1);
         if (zo >= N) zo -= N;
-        int zh = min(z + 2, z1 - 1);
+        int zh = min(z + 1 + PF, z1 - 1);
         if (zh >= N) zh -= N;
         const unsigned o3 = (unsigned)zo * NN, o2 = (unsigned)zh * NN;
         // (A) loads one plane ahead
@@ -221,9 +244,18 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
         }
     };
 
-    for (int z = z0; z < z1; z += 2) {
-        plane(z, oAf, oAp, hAf, hAp, oBf, oBp, hBf, hBp);
-        if (z + 1 < z1) plane(z + 1, oBf, oBp, hBf, hBp, oAf, oAp, hAf, hAp);
+    if constexpr (PF == 1) {
+        for (int z = z0; z < z1; z += 2) {
+            plane(z, oAf, oAp, hAf, hAp, oBf, oBp, hBf, hBp);
+            if (z + 1 < z1) plane(z + 1, oBf, oBp, hBf, hBp, oAf, oAp, hAf, hAp);
+        }
+    } else {
+        // set A holds own plane z + 2 and halo plane z + 1, B the next ones; C is loaded
+        for (int z = z0; z < z1; z += 3) {
+            plane(z, oAf, oAp, hAf, hAp, oCf, oCp, hCf, hCp);
+            if (z + 1 < z1) plane(z + 1, oBf, oBp, hBf, hBp, oAf, oAp, hAf, hAp);
+            if (z + 2 < z1) plane(z + 2, oCf, oCp, hCf, hCp, oBf, oBp, hBf, hBp);
+        }
     }
 
     if constexpr (RED) {

@@ -47,7 +47,7 @@ def variant_key(name: str):
         return None
     args = [a.strip() for a in m.group(2).split(",")]
     prec = "f32" if args[0] == "float" else "f64"
-    v = VARIANTS.get(tuple(args[-5:]))
+    v = VARIANTS.get(tuple(args[4:9]))   # <T, NF, XS or TX, TY, five flags[, prefetch depth]>
     return f"{v}_{prec}" if v else None
 
 
