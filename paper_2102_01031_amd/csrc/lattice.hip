@@ -212,10 +212,13 @@ int pick_tile(int N)
 
 bool rows_ok(int N) { return N == 64 || N == 128 || N == 256; }
 
+// z chunk giving about `target` blocks; down to one plane per block for small
+// lattices, where a longer march is a serial chain over too few blocks
+// (32^3 single field: 4.2 against 5.4 us per step with chunks of 4)
 int auto_chunk(int N, long xy_blocks, long target)
 {
     long z = (long)N * xy_blocks / target;
-    if (z < 4) z = 4;
+    if (z < 1) z = 1;
     if (z > N) z = N;
     return (int)z;
 }

@@ -46,7 +46,7 @@ def test_lphi4_32_full_run():
     check_run(scalar_kwargs(wl), phi, pi, wl.steps, what="lphi4-32")
 
 
-@pytest.mark.parametrize("tile", [None, "64,4,5", "32,8,7", "16,16,3", "8,8,11", "64,8,36"])
+@pytest.mark.parametrize("tile", [None, "64,4,5", "32,8,7", "16,16,3", "8,8,11", "64,8,36", "32,8,1"])
 def test_preheat_ragged_tiles(tile):
     wl = workloads.PREHEAT_128
     N = 36
@@ -55,9 +55,9 @@ def test_preheat_ragged_tiles(tile):
 
 
 @pytest.mark.parametrize("N,tile", [(64, "rows,8,5"), (64, "rows,4,64"), (128, "rows,8,9"), (128, "rows,4,23"),
-                                    (64, None), (128, None)])
+                                    (64, None), (128, None), (64, "rows,4,1")])
 def test_preheat_whole_row_kernel(N, tile):
-    """The whole-row kernel (N = 64, 128, 256) with ragged z chunks."""
+    """The whole-row kernel (N = 64, 128) with ragged and one-plane z chunks."""
     wl = workloads.PREHEAT_128
     phi, pi = wl.initial_fields(N=N)
     check_run(scalar_kwargs(wl, N=N), phi, pi, 3, tile=tile, what=f"rows-{N}")
@@ -87,6 +87,16 @@ def test_preheat_256_bench_config():
     wl = workloads.PREHEAT_256
     phi, pi = wl.initial_fields()
     check_run(scalar_kwargs(wl), phi, pi, 1, what="preheat-256")
+
+
+@pytest.mark.parametrize("tile", ["rows,4,3", "rows,4,1"])
+def test_preheat_256_two_plane_prefetch_ragged(tile):
+    """256^3 float64 runs the whole-row kernel with loads two planes ahead
+    (three rotating register sets, z loop unrolled by three): z chunks that leave
+    a remainder of one after the unrolled groups (3) or hold one plane (1)."""
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields()
+    check_run(scalar_kwargs(wl), phi, pi, 1, tile=tile, what=f"preheat-256-{tile}")
 
 
 @pytest.mark.parametrize("N", [2, 3, 5, 7])
