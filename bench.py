@@ -14,6 +14,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -45,7 +46,32 @@ def stored_traffic(kind: str, per_launch_alg: float):
     return k["hbm_bytes_per_launch"]
 
 
-def run_extras(args, log):
+def measured_ceiling(log):
+    """Streaming ceiling of the stage kernel's access pattern (4 float64 arrays
+    of 256^3 in, 4 out) from the probe csrc/ceiling, run as a child process
+    before this process touches the GPU; None if the probe is not built or
+    fails."""
+    exe = os.path.join(ROOT, "paper_2102_01031_amd", "csrc", "ceiling")
+    if not os.path.exists(exe):
+        return None
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    except (OSError, subprocess.TimeoutExpired):
+        return None
+    if r.returncode != 0:
+        log(f"[bench] ceiling probe failed: {r.stderr.strip()[:200]}")
+        return None
+    out = {}
+    for line in r.stdout.splitlines():
+        try:
+            d = json.loads(line)
+        except ValueError:
+            continue
+        out[d["pattern"]] = d["GBs"]
+    return out or None
+
+
+def run_extras(args, log, only=None):
     """The other workloads' headline numbers: the adjoint/forward time ratio
     (two fields, 64^3, 2000 VV2 steps), the U(1) stage (128^3 leapfrog), the
     batched ensemble rate (256 lattices
@@ -58,115 +84,119 @@ def run_extras(args, log):
 
     dev = torch.device("cuda:0")
     res = {}
-    # adjoint / forward
-    wl = workloads.ADJ_64
-    phi, pi = wl.initial_fields()
-    tp = [torch.tensor(f.reshape(-1), device=dev) for f in phi]
-    tq = [torch.tensor(f.reshape(-1), device=dev) for f in pi]
-    lat = Lattice(tp, tq, N=wl.N, dx=wl.dx, dt=wl.dt, integrator="vv2", expansion="none", potential="phi4_chi2",
-                  lam=wl.lam, q=wl.q)
-    lat.grad(50)
-    torch.cuda.synchronize()
-    c0 = time.perf_counter()
-    lat.step(wl.steps)
-    torch.cuda.synchronize()
-    fwd = time.perf_counter() - c0
-    lat.step(-wl.steps)
-    torch.cuda.synchronize()
-    # sweep times from a call without per-launch instrumentation
-    c0 = time.perf_counter()
-    r = lat.grad(wl.steps)
-    gwall = time.perf_counter() - c0
-    # per-pass kernel times from a second, instrumented call
-    lat.stats(reset=True)
-    lat.profile(True)
-    lat.grad(wl.steps)
-    st = lat.stats(reset=True)
-    lat.profile(False)
-    fus = 1e3 * st["kernel_ms"]["kick_drift"] / max(st["launches"]["kick_drift"], 1)
-    aus = 1e3 * st["kernel_ms"]["adjoint"] / max(st["launches"]["adjoint"], 1)
-    res["adjoint"] = {"workload": wl.name, "steps": wl.steps, "observable": "(E_K^chi + E_G^chi)/rho",
-                      "value": r["value"], "dO_dq": r["dO_dq"],
-                      "forward_ms": r["forward_ms"], "reverse_ms": r["reverse_ms"],
-                      "ratio_reverse_over_forward": r["reverse_ms"] / r["forward_ms"],
-                      "forward_plain_ms": 1e3 * fwd, "grad_call_ms": 1e3 * gwall,
-                      "kernel_ratio_adjoint_over_forward_pass": aus / fus,
-                      "forward_pass_us": fus, "adjoint_pass_us": aus}
-    lat.close()
-    log(f"[bench] adjoint: reverse/forward {r['reverse_ms'] / r['forward_ms']:.2f}, per pass {aus / fus:.2f}")
-    # U(1) gauge + complex scalar, 128^3, leapfrog: ten N^3 float64 arrays, each
-    # read once and written once per step (160 B per site)
-    uw = workloads.ABELIAN_HIGGS_128
-    uf = uw.initial_fields()
-    ut = [[torch.tensor(a.reshape(-1), device=dev) for a in f] for f in uf]
-    lu = Lattice(ut[0], ut[1], A=ut[2], piA=ut[3], N=uw.N, dx=uw.dx, dt=uw.dt, integrator="lf", expansion="none",
-                 potential="abelian_higgs", lam=uw.lam, v=uw.v, e=uw.e, kappa_g=uw.kappa_g)
-    lu.step(uw.steps)
-    torch.cuda.synchronize()
-    c0 = time.perf_counter()
-    lu.step(uw.steps)
-    torch.cuda.synchronize()
-    uwall = time.perf_counter() - c0
-    lu.stats(reset=True)
-    lu.profile(True)
-    lu.step(uw.steps)
-    st = lu.stats(reset=True)
-    lu.profile(False)
-    uus = 1e3 * st["kernel_ms"]["u1"] / max(st["launches"]["u1"], 1)
-    ue = lu.energy()
-    res["u1"] = {"workload": uw.name, "steps": uw.steps, "us_per_step": 1e6 * uwall / uw.steps,
-                 "value": uw.N ** 3 * uw.steps / uwall, "unit": "site-updates/s",
-                 "mean_launch_us": uus, "achieved_GBs_alg": uw.N ** 3 * 160 / (uus * 1e-6) / 1e9,
-                 "gauss_max_over_terms": ue["gauss_max"] / max(ue["gauss_div_max"], ue["gauss_charge_max"], 1e-300)}
-    lu.close()
-    log(f"[bench] U(1): {res['u1']['us_per_step']:.1f} us per step, stage {uus:.1f} us, "
-        f"{res['u1']['achieved_GBs_alg']:.0f} GB/s algorithmic")
-    # batched ensemble
-    bw = workloads.BATCH
-    sizes = bw.sizes()
-    phis, pis = [], []
-    for rr, N in enumerate(sizes):
-        f = bw.initial_fields(rr, N)
-        phis.append(torch.tensor(f[0][0].reshape(-1), device=dev, dtype=torch.float32))
-        pis.append(torch.tensor(f[1][0].reshape(-1), device=dev, dtype=torch.float32))
-    b = bw.base
-    lb = LatticeBatch(phis, pis, sizes, autotune=True, precision="f32", dx=b.dx, dt=b.dt, integrator="lf",
-                      expansion="fixed", potential="phi4", lam=b.lam, alpha=b.alpha, w_eos=b.w_eos, H0=b.H0,
-                      a0=b.a0)
-    lb.step(bw.steps)
-    torch.cuda.synchronize()
-    c0 = time.perf_counter()
-    lb.step(bw.steps)
-    torch.cuda.synchronize()
-    bwall = time.perf_counter() - c0
-    sites = sum(N ** 3 for N in sizes)
-    res["batch"] = {"workload": bw.name, "realizations": len(sizes), "sites": sites, "steps": bw.steps,
-                    "value": sites * bw.steps / bwall, "unit": "site-updates/s", "ms": 1e3 * bwall,
-                    "tiles": {str(N): list(lb.tile(N)) for N in sorted(set(sizes))},
-                    "achieved_GBs_alg": sites * 16 * bw.steps / bwall / 1e9}
-    lb.close()
-    log(f"[bench] batch: {res['batch']['value']:.3e} site-updates/s")
-    # single field, 32^3, 1000 LF steps
-    w0 = workloads.LPHI4_32
-    phi, pi = w0.initial_fields()
-    tp = [torch.tensor(phi[0].reshape(-1), device=dev)]
-    tq = [torch.tensor(pi[0].reshape(-1), device=dev)]
-    l0 = Lattice(tp, tq, N=w0.N, dx=w0.dx, dt=w0.dt, integrator="lf", expansion="fixed", potential="phi4",
-                 lam=w0.lam, alpha=w0.alpha, w_eos=w0.w_eos, H0=w0.H0, a0=w0.a0)
-    # the first call of a step count captures its graph; later calls replay it
-    torch.cuda.synchronize()
-    c0 = time.perf_counter()
-    l0.step(w0.steps)
-    torch.cuda.synchronize()
-    w_first = time.perf_counter() - c0
-    c0 = time.perf_counter()
-    l0.step(w0.steps)
-    torch.cuda.synchronize()
-    w = time.perf_counter() - c0
-    res["lphi4_32"] = {"workload": w0.name, "steps": w0.steps, "us_per_step": 1e6 * w / w0.steps,
-                       "us_per_step_first_call": 1e6 * w_first / w0.steps,
-                       "value": w0.N ** 3 * w0.steps / w, "unit": "site-updates/s"}
-    l0.close()
+    if only in (None, "adjoint"):
+        # adjoint / forward
+        wl = workloads.ADJ_64
+        phi, pi = wl.initial_fields()
+        tp = [torch.tensor(f.reshape(-1), device=dev) for f in phi]
+        tq = [torch.tensor(f.reshape(-1), device=dev) for f in pi]
+        lat = Lattice(tp, tq, N=wl.N, dx=wl.dx, dt=wl.dt, integrator="vv2", expansion="none", potential="phi4_chi2",
+                      lam=wl.lam, q=wl.q)
+        lat.grad(50)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        lat.step(wl.steps)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - c0
+        lat.step(-wl.steps)
+        torch.cuda.synchronize()
+        # sweep times from a call without per-launch instrumentation
+        c0 = time.perf_counter()
+        r = lat.grad(wl.steps)
+        gwall = time.perf_counter() - c0
+        # per-pass kernel times from a second, instrumented call
+        lat.stats(reset=True)
+        lat.profile(True)
+        lat.grad(wl.steps)
+        st = lat.stats(reset=True)
+        lat.profile(False)
+        fus = 1e3 * st["kernel_ms"]["kick_drift"] / max(st["launches"]["kick_drift"], 1)
+        aus = 1e3 * st["kernel_ms"]["adjoint"] / max(st["launches"]["adjoint"], 1)
+        res["adjoint"] = {"workload": wl.name, "steps": wl.steps, "observable": "(E_K^chi + E_G^chi)/rho",
+                          "value": r["value"], "dO_dq": r["dO_dq"],
+                          "forward_ms": r["forward_ms"], "reverse_ms": r["reverse_ms"],
+                          "ratio_reverse_over_forward": r["reverse_ms"] / r["forward_ms"],
+                          "forward_plain_ms": 1e3 * fwd, "grad_call_ms": 1e3 * gwall,
+                          "kernel_ratio_adjoint_over_forward_pass": aus / fus,
+                          "forward_pass_us": fus, "adjoint_pass_us": aus}
+        lat.close()
+        log(f"[bench] adjoint: reverse/forward {r['reverse_ms'] / r['forward_ms']:.2f}, per pass {aus / fus:.2f}")
+    if only in (None, "u1"):
+        # U(1) gauge + complex scalar, 128^3, leapfrog: ten N^3 float64 arrays, each
+        # read once and written once per step (160 B per site)
+        uw = workloads.ABELIAN_HIGGS_128
+        uf = uw.initial_fields()
+        ut = [[torch.tensor(a.reshape(-1), device=dev) for a in f] for f in uf]
+        lu = Lattice(ut[0], ut[1], A=ut[2], piA=ut[3], N=uw.N, dx=uw.dx, dt=uw.dt, integrator="lf", expansion="none",
+                     potential="abelian_higgs", lam=uw.lam, v=uw.v, e=uw.e, kappa_g=uw.kappa_g)
+        lu.step(uw.steps)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        lu.step(uw.steps)
+        torch.cuda.synchronize()
+        uwall = time.perf_counter() - c0
+        lu.stats(reset=True)
+        lu.profile(True)
+        lu.step(uw.steps)
+        st = lu.stats(reset=True)
+        lu.profile(False)
+        uus = 1e3 * st["kernel_ms"]["u1"] / max(st["launches"]["u1"], 1)
+        ue = lu.energy()
+        res["u1"] = {"workload": uw.name, "steps": uw.steps, "us_per_step": 1e6 * uwall / uw.steps,
+                     "value": uw.N ** 3 * uw.steps / uwall, "unit": "site-updates/s",
+                     "mean_launch_us": uus, "achieved_GBs_alg": uw.N ** 3 * 160 / (uus * 1e-6) / 1e9,
+                     "gauss_max_over_terms": ue["gauss_max"] / max(ue["gauss_div_max"], ue["gauss_charge_max"], 1e-300)}
+        lu.close()
+        log(f"[bench] U(1): {res['u1']['us_per_step']:.1f} us per step, stage {uus:.1f} us, "
+            f"{res['u1']['achieved_GBs_alg']:.0f} GB/s algorithmic")
+    if only in (None, "batch"):
+        # batched ensemble
+        bw = workloads.BATCH
+        sizes = bw.sizes()
+        phis, pis = [], []
+        for rr, N in enumerate(sizes):
+            f = bw.initial_fields(rr, N)
+            phis.append(torch.tensor(f[0][0].reshape(-1), device=dev, dtype=torch.float32))
+            pis.append(torch.tensor(f[1][0].reshape(-1), device=dev, dtype=torch.float32))
+        b = bw.base
+        lb = LatticeBatch(phis, pis, sizes, autotune=True, precision="f32", dx=b.dx, dt=b.dt, integrator="lf",
+                          expansion="fixed", potential="phi4", lam=b.lam, alpha=b.alpha, w_eos=b.w_eos, H0=b.H0,
+                          a0=b.a0)
+        lb.step(bw.steps)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        lb.step(bw.steps)
+        torch.cuda.synchronize()
+        bwall = time.perf_counter() - c0
+        sites = sum(N ** 3 for N in sizes)
+        res["batch"] = {"workload": bw.name, "realizations": len(sizes), "sites": sites, "steps": bw.steps,
+                        "value": sites * bw.steps / bwall, "unit": "site-updates/s", "ms": 1e3 * bwall,
+                        "tiles": {str(N): list(lb.tile(N)) for N in sorted(set(sizes))},
+                        "achieved_GBs_alg": sites * 16 * bw.steps / bwall / 1e9}
+        lb.close()
+        log(f"[bench] batch: {res['batch']['value']:.3e} site-updates/s")
+    if only in (None, "lphi4_32"):
+        # single field, 32^3, 1000 LF steps
+        w0 = workloads.LPHI4_32
+        phi, pi = w0.initial_fields()
+        tp = [torch.tensor(phi[0].reshape(-1), device=dev)]
+        tq = [torch.tensor(pi[0].reshape(-1), device=dev)]
+        l0 = Lattice(tp, tq, N=w0.N, dx=w0.dx, dt=w0.dt, integrator="lf", expansion="fixed", potential="phi4",
+                     lam=w0.lam, alpha=w0.alpha, w_eos=w0.w_eos, H0=w0.H0, a0=w0.a0)
+        # the first call of a step count captures its graph; later calls replay it
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        l0.step(w0.steps)
+        torch.cuda.synchronize()
+        w_first = time.perf_counter() - c0
+        c0 = time.perf_counter()
+        l0.step(w0.steps)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - c0
+        res["lphi4_32"] = {"workload": w0.name, "steps": w0.steps, "us_per_step": 1e6 * w / w0.steps,
+                           "us_per_step_first_call": 1e6 * w_first / w0.steps,
+                           "value": w0.N ** 3 * w0.steps / w, "unit": "site-updates/s"}
+        l0.close()
     return res
 
 
@@ -179,12 +209,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--main-only", action="store_true", help="only the 256^3 workload (for profiling)")
+    ap.add_argument("--only", choices=["adjoint", "u1", "batch", "lphi4_32"],
+                    help="only this other workload; prints its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the lattice step "
               "runs on a single GPU; a multi-GPU run would split the lattice into z slabs with one-plane "
               "halos, which is not implemented)", file=sys.stderr)
         sys.exit(2)
+
+    if args.only:
+        print(json.dumps(run_extras(args, log, only=args.only)))
+        return
+    ceilings = None if args.main_only else measured_ceiling(log)
+    if ceilings:
+        log(f"[bench] streaming ceilings (GB/s): {ceilings}")
 
     import numpy as np
     import torch
@@ -308,7 +347,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"scalar_stage {kind}", "alg_bytes_per_launch": alg_bytes,
-                     "mean_launch_us": avg_ms * 1e3},
+                     "mean_launch_us": avg_ms * 1e3,
+                     "measured_ceiling_GBs": (ceilings.get("streams4_256")
+                                              if ceilings and args.precision == "f64" else None),
+                     "frac_of_measured_ceiling": (achieved / ceilings["streams4_256"]
+                                                  if ceilings and "streams4_256" in ceilings and args.precision == "f64"
+                                                  else None)},
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBS,
         "cpu_baseline": cpu,
         "energy_pass": energy_pass,
