@@ -149,8 +149,11 @@ lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f,
  * (p->N is ignored) but have their own sizes N_per_real[r] and fields f[r].
  * Provided for LAT_PHI4 with LAT_LF and LAT_EXP_NONE or LAT_EXP_FIXED, float64 or
  * float32.  lattice_step on such a context advances every realization with
- * one batched launch per step; the launches of a call are captured once into a
- * HIP graph and replayed.  With autotune = 1 the mode of each distinct
+ * batched launches: the realizations are grouped into segments whose arrays
+ * fit the GPU's last-level cache (128 MB of phi and pi per segment), and all
+ * steps of a call run on one segment before the next (the realizations are
+ * independent, so this changes no result); the launches of a call are
+ * captured once into a HIP graph and replayed.  With autotune = 1 the mode of each distinct
  * lattice size (a tile shape and z chunk, or one thread per site) is chosen by
  * timing candidates on scratch buffers, first for that size alone, then with
  * every realization in the launch (the fields are not modified); otherwise a

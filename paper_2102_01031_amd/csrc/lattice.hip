@@ -136,6 +136,8 @@ struct lat_ctx {
     void *reals_dev = nullptr;          // BatchReal<T>[n]
     std::vector<char> reals_host;       // host copy (bytes)
     int2 *block_work = nullptr;         // BatchArgs::block_work table
+    std::vector<int2 *> seg_work;       // per step segment: its block table
+    std::vector<int> seg_blocks;
     int batch_blocks = 0;
     std::vector<void *> pi_scratch;
     std::map<int, std::pair<int, int>> batch_tile;   // N -> (tile x, z chunk)
@@ -854,6 +856,7 @@ void free_ctx(lat_ctx *c)
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->reals_dev) (void)hipFree(c->reals_dev);
     if (c->block_work) (void)hipFree(c->block_work);
+    for (int2 *t : c->seg_work) (void)hipFree(t);
     for (void *q : c->pi_scratch)
         if (q) (void)hipFree(q);
     for (lat_ctx *sub : c->subs) free_ctx(sub);
@@ -1537,17 +1540,11 @@ int real_blocks(int N, int tx, int zc)
     return ((N + tx - 1) / tx) * ((N + ty - 1) / ty) * ((N + zc - 1) / zc);
 }
 
-// Build the realization table and block table for the realizations in `which`
-// (all when empty) with the tiles in c->batch_tile, and upload them.  Blocks
-// are dispatched round-robin over the 8 XCDs (block b on XCD b % 8), so the
-// table is built per XCD and interleaved: whole realizations go to the XCD
-// with the fewest sites so far (largest first), each XCD's list starts with
-// its longest blocks (z-marching tiles by chunk length, then one-site blocks),
-// and shorter lists are padded with empty entries.
 constexpr int kXcds = 8;
 
+// realization descriptors with the tiles in c->batch_tile
 template <typename T>
-lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
+std::vector<BatchReal<T>> batch_reals(lat_ctx *c)
 {
     const int n = (int)c->subs.size();
     std::vector<BatchReal<T>> reals(n);
@@ -1555,9 +1552,18 @@ lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
         const auto tz = c->batch_tile[c->subs[r]->N];
         reals[r] = make_real<T>(c->subs[r], c->pi_scratch[r], tz.first, tz.second);
     }
-    std::vector<int> list = which;
-    if (list.empty())
-        for (int r = 0; r < n; ++r) list.push_back(r);
+    return reals;
+}
+
+// Block table for the realizations in `list`, in dispatch order.  Blocks are
+// dispatched round-robin over the 8 XCDs (block b on XCD b % 8), so the table
+// is built per XCD and interleaved: whole realizations go to the XCD with the
+// fewest sites so far (largest first), each XCD's list starts with its longest
+// blocks (z-marching tiles by chunk length, then one-site blocks), and shorter
+// lists are padded with empty entries.
+template <typename T>
+std::vector<int2> make_block_table(const std::vector<BatchReal<T>> &reals, std::vector<int> list)
+{
     std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return reals[a].N > reals[b].N; });
     std::vector<std::vector<int>> per(kXcds);
     std::vector<double> load(kXcds, 0.0);
@@ -1582,6 +1588,20 @@ lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
     std::vector<int2> blocks(longest * kXcds, make_int2(-1, 0));
     for (int x = 0; x < kXcds; ++x)
         for (size_t j = 0; j < seq[x].size(); ++j) blocks[j * kXcds + x] = seq[x][j];
+    return blocks;
+}
+
+// Upload the realization table and the block table for the realizations in
+// `which` (all when empty); the launch without a segment uses it.
+template <typename T>
+lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
+{
+    const int n = (int)c->subs.size();
+    const std::vector<BatchReal<T>> reals = batch_reals<T>(c);
+    std::vector<int> list = which;
+    if (list.empty())
+        for (int r = 0; r < n; ++r) list.push_back(r);
+    const std::vector<int2> blocks = make_block_table<T>(reals, list);
     const size_t rbytes = (size_t)n * sizeof(BatchReal<T>);
     if (!c->reals_dev && hipMalloc(&c->reals_dev, rbytes) != hipSuccess)
         return fail(c, LAT_ENOMEM, "batch table allocation failed");
@@ -1596,6 +1616,52 @@ lat_status build_tables(lat_ctx *c, const std::vector<int> &which)
     HIPCHK(c, hipMemcpy(c->block_work, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice));
     c->reals_host.assign((const char *)reals.data(), (const char *)reals.data() + rbytes);
     c->nblocks = (int)blocks.size();
+    return LAT_OK;
+}
+
+// Step segments: realizations (largest first) grouped so that each group's
+// working set (phi in both buffers and pi) stays under a byte budget sized for
+// the 256 MB Infinity Cache; lattice_step runs all its steps on one segment
+// before the next, so a segment's arrays stay cache-resident across steps.
+// The realizations are independent, so the order changes no result.
+constexpr double kSegBudgetMB = 128.0;
+
+template <typename T>
+lat_status build_segments(lat_ctx *c)
+{
+    for (int2 *t : c->seg_work) (void)hipFree(t);
+    c->seg_work.clear();
+    c->seg_blocks.clear();
+    double budget = kSegBudgetMB;
+    if (const char *env = std::getenv("LATTICE_BATCH_SEG_MB")) budget = std::atof(env);
+    if (!(budget > 0.0)) return LAT_OK;   // one launch over all realizations per step
+    const int n = (int)c->subs.size();
+    const std::vector<BatchReal<T>> reals = batch_reals<T>(c);
+    std::vector<int> order(n);
+    for (int r = 0; r < n; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reals[a].N > reals[b].N; });
+    std::vector<std::vector<int>> segs(1);
+    double bytes = 0.0;
+    for (int r : order) {
+        const double rb = 3.0 * (double)c->subs[r]->vol * c->esize;
+        if (!segs.back().empty() && bytes + rb > budget * 1048576.0) {
+            segs.emplace_back();
+            bytes = 0.0;
+        }
+        segs.back().push_back(r);
+        bytes += rb;
+    }
+    if (segs.size() < 2) return LAT_OK;
+    for (const auto &sg : segs) {
+        const std::vector<int2> blocks = make_block_table<T>(reals, sg);
+        int2 *d = nullptr;
+        if (hipMalloc(&d, blocks.size() * sizeof(int2)) != hipSuccess)
+            return fail(c, LAT_ENOMEM, "batch segment table allocation failed");
+        c->seg_work.push_back(d);
+        c->seg_blocks.push_back((int)blocks.size());
+        HIPCHK(c, hipMemcpy(d, blocks.data(), blocks.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    c->graph_n = 0;
     return LAT_OK;
 }
 
@@ -1614,10 +1680,15 @@ BatchArgs<T> batch_args(lat_ctx *c, int pass_index, int parity, int tuning)
 }
 
 template <typename T>
-lat_status batch_launch(lat_ctx *c, hipStream_t s, int pass_index, int parity, int tuning)
+lat_status batch_launch(lat_ctx *c, hipStream_t s, int pass_index, int parity, int tuning, int seg = -1)
 {
-    hipLaunchKernelGGL(batch_lf_stage<T>, dim3(c->nblocks), dim3(kBatchThreads), 0, s,
-                       batch_args<T>(c, pass_index, parity, tuning));
+    BatchArgs<T> a = batch_args<T>(c, pass_index, parity, tuning);
+    int nb = c->nblocks;
+    if (seg >= 0) {
+        a.block_work = c->seg_work[seg];
+        nb = c->seg_blocks[seg];
+    }
+    hipLaunchKernelGGL(batch_lf_stage<T>, dim3(nb), dim3(kBatchThreads), 0, s, a);
     HIPCHK(c, hipGetLastError());
     return LAT_OK;
 }
@@ -1666,16 +1737,26 @@ lat_status autotune(lat_ctx *c)
         }
         c->batch_tile[N] = best_cfg;
     }
-    // refine: with every realization in the launch (the sizes share the caches
-    // and the XCDs), revisit each size's shape, largest size first
+    // refine: with every realization stepped as lattice_step runs them (one
+    // launch over all, or segment after segment, sharing the caches and the
+    // XCDs), revisit each size's shape, largest size first
     if (groups.size() > 1) {
         auto time_all = [&](float *ms) -> lat_status {
             lat_status st = build_tables<T>(c, {});
             if (st != LAT_OK) return st;
-            if ((st = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return st;   // warm
+            if ((st = build_segments<T>(c)) != LAT_OK) return st;
+            const int nseg = c->seg_work.empty() ? 1 : (int)c->seg_work.size();
+            auto pass = [&](int reps) -> lat_status {
+                for (int g = 0; g < nseg; ++g)
+                    for (int it = 0; it < reps; ++it) {
+                        lat_status r = batch_launch<T>(c, c->stream, 0, 0, 1, c->seg_work.empty() ? -1 : g);
+                        if (r != LAT_OK) return r;
+                    }
+                return LAT_OK;
+            };
+            if ((st = pass(1)) != LAT_OK) return st;   // warm
             HIPCHK(c, hipEventRecord(e0, c->stream));
-            for (int it = 0; it < 3; ++it)
-                if ((st = batch_launch<T>(c, c->stream, 0, 0, 1)) != LAT_OK) return st;
+            if ((st = pass(3)) != LAT_OK) return st;
             HIPCHK(c, hipEventRecord(e1, c->stream));
             HIPCHK(c, hipEventSynchronize(e1));
             HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
@@ -1729,10 +1810,18 @@ lat_status batch_step_t(lat_ctx *c, int64_t ns)
     }
     if ((s = upload_coef(c, (size_t)ns)) != LAT_OK) return s;
     const bool eager = std::getenv("LATTICE_NO_GRAPH") != nullptr;
-    if (eager) {
-        for (int64_t k = 0; k < ns; ++k)
-            if ((s = batch_launch<T>(c, c->stream, (int)k, (int)((c->batch_parity + k) & 1), 0)) != LAT_OK) return s;
-    }
+    // all steps of one segment, then the next (a single segment: every realization per launch)
+    const int nseg = c->seg_work.empty() ? 1 : (int)c->seg_work.size();
+    auto enqueue = [&](hipStream_t st) -> lat_status {
+        for (int g = 0; g < nseg; ++g)
+            for (int64_t k = 0; k < ns; ++k) {
+                lat_status r = batch_launch<T>(c, st, (int)k, (int)((c->batch_parity + k) & 1), 0,
+                                               c->seg_work.empty() ? -1 : g);
+                if (r != LAT_OK) return r;
+            }
+        return LAT_OK;
+    };
+    if (eager && (s = enqueue(c->stream)) != LAT_OK) return s;
     // (re)capture the graph of ns batched passes starting at the current parity
     if (!eager && (!c->graph_exec || c->graph_n != ns || c->graph_parity != c->batch_parity)) {
         if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
@@ -1740,14 +1829,12 @@ lat_status batch_step_t(lat_ctx *c, int64_t ns)
         c->graph_exec = nullptr;
         c->graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        for (int64_t k = 0; k < ns; ++k) {
-            s = batch_launch<T>(c, c->capture_stream, (int)k, (int)((c->batch_parity + k) & 1), 0);
-            if (s != LAT_OK) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(c->capture_stream, &g);
-                if (g) (void)hipGraphDestroy(g);
-                return s;
-            }
+        s = enqueue(c->capture_stream);
+        if (s != LAT_OK) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(c->capture_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return s;
         }
         HIPCHK(c, hipStreamEndCapture(c->capture_stream, &c->graph));
         HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
@@ -1755,7 +1842,7 @@ lat_status batch_step_t(lat_ctx *c, int64_t ns)
         c->graph_parity = c->batch_parity;
     }
     if (!eager) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
-    c->launches[4] += ns;
+    c->launches[4] += ns * nseg;
     c->batch_parity = (int)((c->batch_parity + ns) & 1);
     if (c->batch_parity == 1) {
         const int n = (int)c->subs.size();
@@ -1858,6 +1945,8 @@ extern "C" lat_status lattice_init_batch(lat_ctx **out, const lat_params *p, int
         if (st != LAT_OK) return bail(st, c->err);
     }
     st = c->f32 ? build_tables<float>(c, {}) : build_tables<double>(c, {});
+    if (st != LAT_OK) return bail(st, c->err);
+    st = c->f32 ? build_segments<float>(c) : build_segments<double>(c);
     if (st != LAT_OK) return bail(st, c->err);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
     *out = c;

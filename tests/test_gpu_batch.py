@@ -1,6 +1,6 @@
 """GPU checks of the batched ensemble path: independent single-field lattices
-of uneven sizes, one batched launch per step replayed from a captured graph,
-autotuned tiles.  FP64 batches match the oracle per realization to 1e-12; the
+of uneven sizes, batched launches replayed from a captured graph (one launch
+over all realizations per step, or segment after segment), autotuned modes.  FP64 batches match the oracle per realization to 1e-12; the
 full float32 ensemble (256 realizations of 24^3..64^3, 2000 steps) is checked
 on sampled realizations against the oracle."""
 import numpy as np
@@ -82,6 +82,32 @@ def test_batch_forced_shapes_fp64(spec):
         st = oracle_run(wl, fields[r][0], fields[r][1], N, 17)
         assert rel_maxdiff(phis[r].cpu().numpy(), st.phi[0]) <= 1e-12, (spec, r, N)
         assert rel_maxdiff(pis[r].cpu().numpy(), st.pi[0]) <= 1e-12, (spec, r, N)
+    lb.close()
+
+
+def test_batch_segments_bitwise_and_oracle():
+    """lattice_step runs the realizations segment by segment (all steps of one
+    segment, then the next).  Tiny segments (a 1 MB budget: most realizations
+    alone) must give bitwise the arrays of one launch over all realizations
+    per step, and both match the oracle."""
+    import torch
+    wl = workloads.BATCH
+    sizes = [24, 64, 17, 48, 32, 5, 64, 40]
+    with tile_env("0", "LATTICE_BATCH_SEG_MB"):
+        la, fa, pa, qa = make_batch(wl, sizes, torch.float64, "f64", autotune=False)
+    with tile_env("1", "LATTICE_BATCH_SEG_MB"):
+        lb, fb, pb, qb = make_batch(wl, sizes, torch.float64, "f64", autotune=False)
+    for n in (9, 4, 9):
+        la.step(n)
+        lb.step(n)
+    torch.cuda.synchronize()
+    for x, y in zip(pa + qa, pb + qb):
+        assert torch.equal(x, y)
+    for r, N in enumerate(sizes):
+        st = oracle_run(wl, fa[r][0], fa[r][1], N, 22)
+        assert rel_maxdiff(pb[r].cpu().numpy(), st.phi[0]) <= 1e-12, (r, N)
+        assert rel_maxdiff(qb[r].cpu().numpy(), st.pi[0]) <= 1e-12, (r, N)
+    la.close()
     lb.close()
 
 
