@@ -231,7 +231,8 @@ def _energy_dict(e):
 
 class LatticeBatch:
     """Batch of independent single-field lattices (sizes may differ) stepped by
-    one batched launch per step, replayed from a captured HIP graph.
+    batched launches (cache-sized segments of realizations, all steps of a call
+    per segment), replayed from a captured HIP graph.
 
     phis, pis: lists (one entry per realization) of contiguous CUDA tensors of
     N_r^3 elements.  Other keyword arguments as for Lattice (N is ignored)."""
