@@ -252,9 +252,11 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
     constexpr int NOP = 3 * NX;               // halo-row transcendental operations per plane
     constexpr int OPT = (NOP + NT - 1) / NT;
 
-    __shared__ double s_p0[R * NX], s_p1[R * NX];                 // psi, rows 0 .. TY+1
-    __shared__ double s_ax[R * NX], s_az[R * NX];                 // A_x, A_z, rows 0 .. TY+1
-    __shared__ double s_ay[(TY + 1) * NX], s_ayn[NX];             // A_y rows 0 .. TY; A_y(row 0, z+1)
+    // psi and A of the current plane, double-buffered by plane parity so that
+    // storing plane z + 1 cannot race with the last reads of plane z
+    __shared__ double s_p0[2][R * NX], s_p1[2][R * NX];           // psi, rows 0 .. TY+1
+    __shared__ double s_ax[2][R * NX], s_az[2][R * NX];           // A_x, A_z, rows 0 .. TY+1
+    __shared__ double s_ay[2][(TY + 1) * NX], s_ayn[2][NX];       // A_y rows 0 .. TY; A_y(row 0, z+1)
     __shared__ double s_sxy[(TY + 1) * NX], s_syz[(TY + 1) * NX]; // rows 0 .. TY
     __shared__ double s_cy[(TY + 1) * NX], s_sy[(TY + 1) * NX];   // phase of A_y, rows 0 .. TY
     __shared__ double s_sxz[TY * NX];                             // own rows (index row - 1)
@@ -323,7 +325,7 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             a0[i] = ld32(g.A_in[i], o0 + so);
             a1[i] = ld32(g.A_in[i], o1 + so);
         }
-        s_az[ro] = am[2];
+        s_az[1][ro] = am[2];
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             hp0[j] = hp1[j] = hax[j] = hay[j] = haz[j] = hayn[j] = 0.0;
@@ -336,13 +338,13 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                     hay[j] = ld32(g.A_in[1], o0 + hoff[j]);
                     hayn[j] = ld32(g.A_in[1], o1 + hoff[j]);
                 } else {
-                    s_az[(TY + 1) * NX + hx[j]] = ld32(g.A_in[2], om + hoff[j]);
+                    s_az[1][(TY + 1) * NX + hx[j]] = ld32(g.A_in[2], om + hoff[j]);
                 }
             }
         }
         __syncthreads();
-        const double txz = edx * ((s_az[r * NX + xp] - am[2]) - a0[0] + am[0]);
-        const double tyz = edx * ((s_az[(r + 1) * NX + x] - am[2]) - a0[1] + am[1]);
+        const double txz = edx * ((s_az[1][r * NX + xp] - am[2]) - a0[0] + am[0]);
+        const double tyz = edx * ((s_az[1][(r + 1) * NX + x] - am[2]) - a0[1] + am[1]);
         sxzm = lat_sin(txz);
         syzm = lat_sin(tyz);
         lat_sincos(edx * am[2], &szm, &czm);
@@ -351,23 +353,24 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
 
     for (int z = z0; z < z1; ++z) {
         const unsigned oz = (unsigned)z * NN;
+        const int b = (z - z0) & 1;
         // (A) plane z into LDS
-        s_p0[ro] = w0[0];
-        s_p1[ro] = w0[1];
-        s_ax[ro] = a0[0];
-        s_ay[ro] = a0[1];
-        s_az[ro] = a0[2];
+        s_p0[b][ro] = w0[0];
+        s_p1[b][ro] = w0[1];
+        s_ax[b][ro] = a0[0];
+        s_ay[b][ro] = a0[1];
+        s_az[b][ro] = a0[2];
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (hval[j]) {
                 const int hs = hrow[j] * NX + hx[j];
-                s_p0[hs] = hp0[j];
-                s_p1[hs] = hp1[j];
-                s_ax[hs] = hax[j];
-                s_az[hs] = haz[j];
+                s_p0[b][hs] = hp0[j];
+                s_p1[b][hs] = hp1[j];
+                s_ax[b][hs] = hax[j];
+                s_az[b][hs] = haz[j];
                 if (hrow[j] == 0) {
-                    s_ay[hx[j]] = hay[j];
-                    s_ayn[hx[j]] = hayn[j];
+                    s_ay[b][hx[j]] = hay[j];
+                    s_ayn[b][hx[j]] = hayn[j];
                 }
             }
         }
@@ -404,9 +407,9 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
         // (B) own plaquette sines and link phases into LDS; then the halo
         // row's, one operation per thread
         {
-            const double txy = edx * ((s_ay[r * NX + xp] - a0[1]) - s_ax[(r + 1) * NX + x] + a0[0]);
-            const double txz = edx * ((s_az[r * NX + xp] - a0[2]) - a1[0] + a0[0]);
-            const double tyz = edx * ((s_az[(r + 1) * NX + x] - a0[2]) - a1[1] + a0[1]);
+            const double txy = edx * ((s_ay[b][r * NX + xp] - a0[1]) - s_ax[b][(r + 1) * NX + x] + a0[0]);
+            const double txz = edx * ((s_az[b][r * NX + xp] - a0[2]) - a1[0] + a0[0]);
+            const double tyz = edx * ((s_az[b][(r + 1) * NX + x] - a0[2]) - a1[1] + a0[1]);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double t = j == 0 ? txy : (j == 1 ? txz : tyz);
@@ -433,13 +436,13 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                 const int hxp = (hxo + 1) & (NX - 1);
                 if (op == 0) {
                     double sv, cv;
-                    lat_sincos(edx * s_ay[hxo], &sv, &cv);
+                    lat_sincos(edx * s_ay[b][hxo], &sv, &cv);
                     s_sy[hxo] = sv;
                     s_cy[hxo] = cv;
                 } else if (op == 1) {
-                    s_sxy[hxo] = lat_sin(edx * ((s_ay[hxp] - s_ay[hxo]) - s_ax[NX + hxo] + s_ax[hxo]));
+                    s_sxy[hxo] = lat_sin(edx * ((s_ay[b][hxp] - s_ay[b][hxo]) - s_ax[b][NX + hxo] + s_ax[b][hxo]));
                 } else {
-                    s_syz[hxo] = lat_sin(edx * ((s_az[NX + hxo] - s_az[hxo]) - s_ayn[hxo] + s_ay[hxo]));
+                    s_syz[hxo] = lat_sin(edx * ((s_az[b][NX + hxo] - s_az[b][hxo]) - s_ayn[b][hxo] + s_ay[b][hxo]));
                 }
             }
         }
@@ -463,12 +466,12 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             for (int i = 0; i < 3; ++i) {
                 double qr, qi, rr, ri, sm, cm;
                 if (i == 0) {
-                    qr = s_p0[r * NX + xp]; qi = s_p1[r * NX + xp];
-                    rr = s_p0[r * NX + xm]; ri = s_p1[r * NX + xm];
+                    qr = s_p0[b][r * NX + xp]; qi = s_p1[b][r * NX + xp];
+                    rr = s_p0[b][r * NX + xm]; ri = s_p1[b][r * NX + xm];
                     sm = s_sx[(r - 1) * NX + xm]; cm = s_cx[(r - 1) * NX + xm];
                 } else if (i == 1) {
-                    qr = s_p0[ro + NX]; qi = s_p1[ro + NX];
-                    rr = s_p0[ro - NX]; ri = s_p1[ro - NX];
+                    qr = s_p0[b][ro + NX]; qi = s_p1[b][ro + NX];
+                    rr = s_p0[b][ro - NX]; ri = s_p1[b][ro - NX];
                     sm = s_sy[ro - NX]; cm = s_cy[ro - NX];
                 } else {
                     qr = wp[0]; qi = wp[1];
@@ -506,7 +509,8 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             sxzm = sxz;
             syzm = syz;
         }
-        __syncthreads();
+        // no barrier here: plane z + 1 goes to the other psi / A buffers, and the
+        // sines and phases read above are rewritten only after the next barrier
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             wm[c] = w0[c];
