@@ -17,7 +17,7 @@ from . import build as _build
 
 PHI4, PHI4_CHI2 = 0, 1
 NONE, FIXED, SELF = 0, 1, 2
-LF, VV2, VV4 = 0, 1, 2
+LF, VV2, VV4, VV6, VV8, VV10 = 0, 1, 2, 3, 4, 5
 
 
 class Params(C.Structure):
@@ -63,6 +63,7 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(Params), pp, pp, C.POINTER(Clock), C.c_long]
         L.orc_lf_sync.argtypes = [C.POINTER(Params), pp, pp, C.POINTER(Clock)]
         L.orc_yoshida4.argtypes = [dp, dp]
+        L.orc_triple_jump.argtypes = [C.c_int, dp, dp]
         L.orc_vv2_tangent.argtypes = [C.POINTER(Params), pp, pp, pp, pp, C.c_double]
         L.orc_vv2_adjoint_step.argtypes = [C.POINTER(Params), pp, pp, pp, pp, dp]
         L.orc_observable.argtypes = [C.POINTER(Params), pp, pp, dp, pp, pp, dp]
@@ -227,6 +228,12 @@ def yoshida4():
     w1, w0 = C.c_double(), C.c_double()
     lib().orc_yoshida4(C.byref(w1), C.byref(w0))
     return w1.value, w0.value
+
+def triple_jump(n):
+    """Weights (x1, x0) raising a symmetric map of order n to order n + 2."""
+    x1, x0 = C.c_double(), C.c_double()
+    lib().orc_triple_jump(int(n), C.byref(x1), C.byref(x0))
+    return x1.value, x0.value
 
 
 # ----------------------------------------------------------------------------

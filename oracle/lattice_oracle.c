@@ -22,7 +22,11 @@
  *       point, recompute the energies there, kick b by h/2.  E_K is taken at
  *       integer times.
  *   R2  4th order velocity-Verlet = Yoshida's triple-jump composition of the
- *       whole second-order map (Yoshida 1990, Phys. Lett. A 150, 262).
+ *       whole second-order map (Yoshida 1990, Phys. Lett. A 150, 262).  The
+ *       6th, 8th and 10th orders repeat the same construction on the map one
+ *       order below: S_{n+2}(h) = S_n(x1 h) S_n(x0 h) S_n(x1 h) with
+ *       x1 = 1/(2 - c), x0 = -c/(2 - c), c = 2^{1/(n+1)} (the recursive triple
+ *       jump of the same paper), 3, 9, 27 and 81 second-order maps per step.
  *   R3  fixed background: every kick uses a(t) at the kick time and every
  *       drift uses a(t) at the midpoint time of the drift (closed form of
  *       eq. ScaleFactorPowerLaw).
@@ -45,14 +49,14 @@
 
 enum { ORC_PHI4 = 0, ORC_PHI4_CHI2 = 1 };
 enum { ORC_NONE = 0, ORC_FIXED = 1, ORC_SELF = 2 };
-enum { ORC_LF = 0, ORC_VV2 = 1, ORC_VV4 = 2 };
+enum { ORC_LF = 0, ORC_VV2 = 1, ORC_VV4 = 2, ORC_VV6 = 3, ORC_VV8 = 4, ORC_VV10 = 5 };
 
 typedef struct orc_params {
     int32_t N;           /* lattice points per dimension                     */
     int32_t nfields;     /* number of real scalar fields: 1 (phi) or 2 (phi, chi) */
     int32_t potential;   /* ORC_PHI4: lambda/4 phi^4 ; ORC_PHI4_CHI2: + q/2 phi^2 chi^2 */
     int32_t expansion;   /* ORC_NONE (a=1), ORC_FIXED (power law), ORC_SELF (Friedmann) */
-    int32_t integrator;  /* ORC_LF, ORC_VV2, ORC_VV4                          */
+    int32_t integrator;  /* ORC_LF, ORC_VV2, ORC_VV4, ORC_VV6, ORC_VV8, ORC_VV10 */
     int32_t pad;
     double dx, dt;       /* lattice spacing and time step (program units)    */
     double lambda, q;    /* potential couplings                              */
@@ -334,12 +338,39 @@ void orc_yoshida4(double *w1, double *w0)
     *w0 = -c / (2.0 - c);
 }
 
+/* Triple-jump weights of order n + 2 from order n (reading R2):
+ * x1 = 1/(2 - c), x0 = -c/(2 - c), c = 2^{1/(n+1)}; n = 2 gives orc_yoshida4. */
+void orc_triple_jump(int n, double *x1, double *x0)
+{
+    double c = pow(2.0, 1.0 / (double)(n + 1));
+    if (n == 2) c = cbrt(2.0);
+    *x1 = 1.0 / (2.0 - c);
+    *x0 = -c / (2.0 - c);
+}
+
+/* One step of the velocity-Verlet map of even order `order` (>= 2) of size h
+ * starting at time t: order 2 is vv2, higher orders the triple jump of the
+ * map two orders below. */
+static void vv_order(stepper *st, int order, double t, double h)
+{
+    if (order == 2) {
+        vv2(st, t, h);
+        return;
+    }
+    double x1, x0;
+    orc_triple_jump(order - 2, &x1, &x0);
+    vv_order(st, order - 2, t, x1 * h);
+    vv_order(st, order - 2, t + x1 * h, x0 * h);
+    vv_order(st, order - 2, t + x1 * h + x0 * h, x1 * h);
+}
+
 /* Evolve |nsteps| steps (backward in time if nsteps < 0).
  * Return codes: 0 ok, -1 bad arguments, -2 unsupported combination,
  * -3 leapfrog state is staggered in the other direction (sync first). */
 int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_clock *c, long nsteps)
 {
     if (p->N < 1 || p->nfields < 1 || p->nfields > 2) return -1;
+    if (p->integrator < ORC_LF || p->integrator > ORC_VV10) return -1;
     if (p->integrator == ORC_LF && p->expansion == ORC_SELF) return -2;
     if (nsteps == 0) return 0;
     int dir = nsteps > 0 ? 1 : -1;
@@ -375,10 +406,12 @@ int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_cloc
             double t = t_start + (double)k * h;
             if (p->integrator == ORC_VV2) {
                 vv2(&st, t, h);
-            } else {
+            } else if (p->integrator == ORC_VV4) {
                 vv2(&st, t, w1 * h);
                 vv2(&st, t + w1 * h, w0 * h);
                 vv2(&st, t + w1 * h + w0 * h, w1 * h);
+            } else {
+                vv_order(&st, 2 * p->integrator, t, h);   /* VV6: 6, VV8: 8, VV10: 10 */
             }
         }
     }

@@ -21,6 +21,10 @@ MUTANTS = [
     ("drift scale factor", "drift(st, a_mid, h);                                          /* phi drift      */",
      "drift(st, a_n1, h);", "test_oracle_scalar.py"),
     ("Yoshida middle weight sign", "*w0 = -c / (2.0 - c);", "*w0 = c / (2.0 - c);", "test_oracle_scalar.py"),
+    ("triple-jump exponent", "double c = pow(2.0, 1.0 / (double)(n + 1));", "double c = pow(2.0, 1.0 / (double)(n + 2));",
+     "test_oracle_scalar.py"),
+    ("triple-jump nesting order", "vv_order(st, order - 2, t + x1 * h, x0 * h);",
+     "vv_order(st, order - 2, t + x1 * h, x1 * h);", "test_oracle_scalar.py"),
     ("leapfrog first half kick", "double w = (c->lf_stag == 0) ? 0.5 * h : h;", "double w = h;",
      "test_oracle_scalar.py"),
     ("gradient energy power of a", "/ (double)V / (2.0 * a * a);", "/ (double)V / (2.0 * a);",

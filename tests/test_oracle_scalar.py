@@ -114,6 +114,59 @@ def test_free_field_vv4_transfer_matrix(orc):
     assert np.max(np.abs(M - exact)) < 10 * th ** 5
 
 
+# --- higher orders: recursive triple jump (VV6, VV8, VV10) ----------------------
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+def test_triple_jump_identities(orc, n):
+    """x1, x0 raise a symmetric order-n map to order n + 2 exactly when
+    2 x1 + x0 = 1 (consistency) and 2 x1^(n+1) + x0^(n+1) = 0 (the order-(n+1)
+    error term cancels); closed form x1 = 1/(2 - 2^(1/(n+1)))."""
+    x1, x0 = orc.triple_jump(n)
+    assert abs(2 * x1 + x0 - 1) < 1e-15
+    assert abs(2 * x1 ** (n + 1) + x0 ** (n + 1)) < 1e-13 * abs(x0) ** (n + 1)
+    assert abs(x1 - 1 / (2 - 2 ** (1 / (n + 1)))) < 1e-15
+    if n == 2:
+        assert (x1, x0) == orc.yoshida4()
+
+
+def composed_matrix(order, s, w2):
+    """Transfer matrix of one step of size s of the order-`order` VV map for a
+    harmonic mode of frequency^2 w2, built from VV2 matrices by the recursion."""
+    if order == 2:
+        return np.array([[1 - s * s * w2 / 2, s], [-s * w2 * (1 - s * s * w2 / 4), 1 - s * s * w2 / 2]])
+    c = 2 ** (1 / (order - 1))
+    x1, x0 = 1 / (2 - c), -c / (2 - c)
+    m1 = composed_matrix(order - 2, x1 * s, w2)
+    return m1 @ composed_matrix(order - 2, x0 * s, w2) @ m1
+
+
+@pytest.mark.parametrize("integ,order", [("VV6", 6), ("VV8", 8), ("VV10", 10)])
+def test_free_field_high_order_transfer_matrix(orc, integ, order):
+    """The oracle's VV6/VV8/VV10 step on a single plane wave equals the product
+    of VV2 transfer matrices given by the recursion, and that product
+    approximates the exact rotation to order h^(order+1) per step."""
+    N, dx, h = 8, 0.5, 0.05
+    n = (2, 1, 1)
+    m = free_model(orc, N, getattr(orc, integ), h, dx)
+    f0 = plane_wave(N, n).reshape(-1)
+    st = orc.ScalarState(m, [f0], [0.3 * f0])
+    w2 = lattice_w2(N, dx, n)
+    M = composed_matrix(order, h, w2)
+    v = np.array([1.0, 0.3])
+    for _ in range(20):
+        st.run(1)
+        v = M @ v
+        assert np.max(np.abs(st.phi[0] - v[0] * f0)) < 1e-13
+        assert np.max(np.abs(st.pi[0] - v[1] * f0)) < 1e-13
+    # local error against exp(h L): halving the step divides it by ~2^(order+1)
+    def err(th):
+        w = 1.0
+        exact = np.array([[math.cos(th), math.sin(th)], [-math.sin(th), math.cos(th)]])
+        return np.max(np.abs(composed_matrix(order, th, w) - exact))
+    th = 0.2          # asymptotic for all three orders, errors still above roundoff
+    r = math.log2(err(th) / err(th / 2))
+    assert abs(r - (order + 1)) < 0.2, r
+
+
 def rand_state(orc, m, seed=11, amp=0.05):
     rng = np.random.default_rng(seed)
     V = m.N ** 3
@@ -188,6 +241,28 @@ def test_convergence_order(orc, integ, exp_, p):
     e3 = np.max(np.abs(res[2] - res[3]))
     for r in (e1 / e2, e2 / e3):
         assert abs(math.log2(r) - p) < 0.15, (e1, e2, e3)
+
+
+@pytest.mark.parametrize("integ,exp_,hs,p", [
+    ("VV6", "SELF", (0.04, 0.02, 0.01, 0.005), 6), ("VV6", "NONE", (0.04, 0.02, 0.01, 0.005), 6),
+    ("VV8", "SELF", (0.04, 0.02, 0.01, 0.005), 8), ("VV10", "SELF", (0.08, 0.04, 0.02, 0.01), 10),
+    ("VV10", "FIXED", (0.08, 0.04, 0.02, 0.01), 10)])
+def test_convergence_order_high(orc, integ, exp_, hs, p):
+    """VV6/VV8/VV10 on the nonlinear two-field system (with the scale factor
+    where expanding): the error under dt halving falls as h^p on the smallest
+    steps (the larger ones are not yet asymptotic for VV8)."""
+    T = 0.8
+    res = []
+    for h in hs:
+        m = two_field_model(orc, 4, getattr(orc, integ), getattr(orc, exp_), dt=h, dx=0.5)
+        m.q = 20.0
+        phi, pi = rand_state(orc, m, amp=0.2)
+        st = orc.ScalarState(m, phi, pi)
+        st.run(int(round(T / h)))
+        res.append(np.concatenate([st.phi[0], st.phi[1], st.pi[0], st.pi[1], [st.a]]))
+    es = [np.max(np.abs(res[i] - res[i + 1])) for i in range(len(res) - 1)]
+    assert es[0] > es[1] > es[2]
+    assert abs(math.log2(es[1] / es[2]) - p) < 0.15, es
 
 
 # --- T9: homogeneous limit = Jacobi cn ------------------------------------------
