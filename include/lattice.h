@@ -57,7 +57,13 @@ typedef enum lat_status {
 enum lat_integrator {
     LAT_LF = 0,    /* staggered leapfrog, 2nd order: kick then drift, momenta half a step behind */
     LAT_VV2 = 1,   /* velocity-Verlet, 2nd order, fields and momenta at the same time */
-    LAT_VV4 = 2    /* 4th order: Yoshida triple-jump composition of three VV2 maps */
+    LAT_VV4 = 2,   /* 4th order: Yoshida triple-jump composition of three VV2 maps */
+    LAT_VV6 = 3,   /* 6th order: triple jump of VV4 maps, 9 VV2 maps (9 kick points) per step */
+    LAT_VV8 = 4,   /* 8th order: triple jump of VV6 maps, 27 VV2 maps per step */
+    LAT_VV10 = 5   /* 10th order: triple jump of VV8 maps, 81 VV2 maps per step.  The VV
+                      family of sec. 4.3 (evolver VV2..VV10); each level S_{n+2}(h) =
+                      S_n(x1 h) S_n(x0 h) S_n(x1 h), x1 = 1/(2 - c), x0 = -c/(2 - c),
+                      c = 2^{1/(n+1)} (Yoshida 1990, Phys. Lett. A 150, 262) */
 };
 
 /* background (sec. 4.3 "expansion", "fixedBackground"; eqs. NewFriedmannEQsII, ScaleFactorPowerLaw) */

@@ -687,34 +687,46 @@ lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
     return LAT_OK;
 }
 
+// Sub-step weights (in units of h) of one velocity-Verlet step of the
+// context's order: VV2 is {1}; each higher order is the triple jump of the
+// order below, S_{n+2}(h) = S_n(x1 h) S_n(x0 h) S_n(x1 h) with x1 = 1/(2 - c),
+// x0 = -c/(2 - c), c = 2^{1/(n+1)} (sec. 4.3 VV family; Yoshida 1990).
+std::vector<double> vv_weights(int integrator)
+{
+    std::vector<double> w{1.0};
+    const int order = integrator == LAT_VV2 ? 2 : 2 * integrator;   // VV4: 4 ... VV10: 10
+    for (int n = 2; n < order; n += 2) {
+        const double cc = n == 2 ? std::cbrt(2.0) : std::pow(2.0, 1.0 / (double)(n + 1));
+        const double x1 = 1.0 / (2.0 - cc), x0 = -cc / (2.0 - cc);
+        std::vector<double> next;
+        next.reserve(3 * w.size());
+        for (double x : {x1, x0, x1})
+            for (double v : w) next.push_back(x * v);
+        w.swap(next);
+    }
+    return w;
+}
+
 lat_status step_vv(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
     const double al = c->p.alpha;
     const bool self = c->p.expansion == LAT_EXP_SELF;
-    const int J = c->p.integrator == LAT_VV4 ? 3 : 1;
-    double w[3] = {1.0, 0.0, 0.0};
-    if (J == 3) {
-        const double cr = std::cbrt(2.0);
-        w[0] = 1.0 / (2.0 - cr);
-        w[1] = -cr / (2.0 - cr);
-        w[2] = w[0];
-    }
+    const std::vector<double> w = vv_weights(c->p.integrator);
+    const int J = (int)w.size();
     const int64_t M = (int64_t)J * ns;
     lat_status s = reserve_coef(c, (size_t)M + 2);
     if (s != LAT_OK) return s;
     const double t_start = c->t;
-    // sub-step sizes and kick-point times
+    // sub-step sizes and kick-point times (within a step, accumulated in order)
     auto hs = [&](int64_t p) { return w[p % J] * h; };
-    auto ts = [&](int64_t p) {
-        if (p >= M) return t_start + (double)ns * h;
-        const double tk = t_start + (double)(p / J) * h;
-        switch (p % J) {
-        case 0: return tk;
-        case 1: return tk + w[0] * h;
-        default: return tk + w[0] * h + w[1] * h;
-        }
-    };
+    std::vector<double> tp((size_t)M + 1);
+    for (int64_t p = 0; p <= M; ++p) {
+        if (p == M) tp[p] = t_start + (double)ns * h;
+        else if (p % J == 0) tp[p] = t_start + (double)(p / J) * h;
+        else tp[p] = tp[p - 1] + hs(p - 1);
+    }
+    auto ts = [&](int64_t p) { return tp[(size_t)(p < M ? p : M)]; };
     for (int64_t p = 0; p <= M; ++p) {
         PassCoef &P = c->coef_host[p];
         const double hp = p > 0 ? hs(p - 1) : 0.0;
@@ -786,7 +798,7 @@ lat_status validate(const lat_params *p, const lat_fields *f)
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(nullptr, LAT_EINVAL, "dt must be > 0");
     if (p->dt / p->dx >= 1.0 / std::sqrt(3.0))
         return fail(nullptr, LAT_EINVAL, "dt/dx must be below 1/sqrt(3)");
-    if (p->integrator < LAT_LF || p->integrator > LAT_VV4) return fail(nullptr, LAT_EINVAL, "bad integrator");
+    if (p->integrator < LAT_LF || p->integrator > LAT_VV10) return fail(nullptr, LAT_EINVAL, "bad integrator");
     if (p->expansion < LAT_EXP_NONE || p->expansion > LAT_EXP_SELF) return fail(nullptr, LAT_EINVAL, "bad expansion");
     if (p->potential < LAT_PHI4 || p->potential > LAT_ABELIAN_HIGGS) return fail(nullptr, LAT_EINVAL, "bad potential");
     if (p->precision != LAT_PREC_F64 && p->precision != LAT_PREC_F32) return fail(nullptr, LAT_EINVAL, "bad precision");

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "csrc", "liblattice.so")
 LAT_OK, LAT_EINVAL, LAT_EUNSUPPORTED, LAT_ENODEV, LAT_EHIP, LAT_ESTATE, LAT_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "LAT_OK", -1: "LAT_EINVAL", -2: "LAT_EUNSUPPORTED", -3: "LAT_ENODEV", -4: "LAT_EHIP",
                 -5: "LAT_ESTATE", -6: "LAT_ENOMEM"}
-INTEGRATORS = {"lf": 0, "vv2": 1, "vv4": 2}
+INTEGRATORS = {"lf": 0, "vv2": 1, "vv4": 2, "vv6": 3, "vv8": 4, "vv10": 5}
 EXPANSIONS = {"none": 0, "fixed": 1, "self": 2}
 POTENTIALS = {"phi4": 0, "phi4_chi2": 1, "abelian_higgs": 2}
 PRECISIONS = {"f64": 0, "f32": 1}

@@ -11,7 +11,8 @@ import numpy as np
 
 import oracle
 
-INTEG = {"lf": oracle.LF, "vv2": oracle.VV2, "vv4": oracle.VV4}
+INTEG = {"lf": oracle.LF, "vv2": oracle.VV2, "vv4": oracle.VV4, "vv6": oracle.VV6, "vv8": oracle.VV8,
+         "vv10": oracle.VV10}
 EXPN = {"none": oracle.NONE, "fixed": oracle.FIXED, "self": oracle.SELF}
 POT = {"phi4": oracle.PHI4, "phi4_chi2": oracle.PHI4_CHI2}
 

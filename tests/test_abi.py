@@ -64,6 +64,16 @@ def test_validation_errors(kw, code):
     assert L.lib().lattice_last_error(None)
 
 
+def test_integrator_codes():
+    """LF, VV2 ... VV10 are codes 0 ... 5; anything else is refused before any device call."""
+    assert L.INTEGRATORS == {"lf": 0, "vv2": 1, "vv4": 2, "vv6": 3, "vv8": 4, "vv10": 5}
+    p = L.make_params(N=8, dx=0.5, dt=0.01)
+    for bad in (6, -1):
+        p.integrator = bad
+        rc, ctx = _init(p, _fields(1))
+        assert rc == L.LAT_EINVAL and not ctx.value
+
+
 def test_null_and_misaligned_pointers():
     p = L.make_params(N=8, dx=0.5, dt=0.01, potential="phi4_chi2")
     f = _fields(2)

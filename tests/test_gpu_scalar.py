@@ -75,6 +75,18 @@ def test_integrator_expansion_matrix(integ, expn):
     check_run(kw, phi, pi, 9, what=f"{integ}-{expn}")
 
 
+@pytest.mark.parametrize("integ,expn,N,steps", [("vv6", "self", 24, 4), ("vv8", "fixed", 20, 2),
+                                                ("vv10", "self", 16, 1), ("vv6", "none", 64, 2),
+                                                ("vv8", "self", 64, 1)])
+def test_higher_order_vv(integ, expn, N, steps):
+    """VV6 / VV8 / VV10 (9, 27, 81 kick points per step, the recursive triple
+    jump) on the tiled and on the whole-row kernel, against the oracle."""
+    wl = workloads.PREHEAT_128
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N, integrator=integ, expansion=expn)
+    check_run(kw, phi, pi, steps, what=f"{integ}-{expn}-{N}")
+
+
 def test_preheat_128_full_size():
     wl = workloads.PREHEAT_128
     phi, pi = wl.initial_fields()
