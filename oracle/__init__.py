@@ -8,6 +8,7 @@ never does.  The numerics live in ``lattice_oracle.c`` (compiled with gcc by
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -64,6 +65,7 @@ def lib():
         L.orc_lf_sync.argtypes = [C.POINTER(Params), pp, pp, C.POINTER(Clock)]
         L.orc_yoshida4.argtypes = [dp, dp]
         L.orc_triple_jump.argtypes = [C.c_int, dp, dp]
+        L.orc_spectrum.argtypes = [C.c_int, C.c_double, dp, C.c_int, dp, dp, C.POINTER(C.c_long)]
         L.orc_vv2_tangent.argtypes = [C.POINTER(Params), pp, pp, pp, pp, C.c_double]
         L.orc_vv2_adjoint_step.argtypes = [C.POINTER(Params), pp, pp, pp, pp, dp]
         L.orc_observable.argtypes = [C.POINTER(Params), pp, pp, dp, pp, pp, dp]
@@ -342,3 +344,26 @@ def _u1_dict(out):
     return dict(EK_phi=out[0], EG_phi=out[1], EV=out[2], EK_A=out[3], EG_A=out[4], rho=out[5],
                 gauss_max=out[6], div_max=out[7], charge_max=out[8], gauss_mean=out[9],
                 gauss_sum_mean=out[10], gauss_abs_mean=out[11])
+
+
+def spectrum_bins(N):
+    """Number of radial bins that hold every mode of an N^3 lattice."""
+    h = N // 2
+    return int(math.isqrt(3 * h * h)) + 1
+
+
+def spectrum(f, dx, nbins=None):
+    """Power spectrum of one field (eq. discretePS): per radial bin b (modes with
+    b <= |n| < b + 1) the sum of |f~|^2 of the unnormalised DFT, the discrete
+    spectrum Delta(b) and the number of modes."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    N = int(round(len(f) ** (1 / 3)))
+    assert N ** 3 == len(f)
+    nb = spectrum_bins(N) if nbins is None else int(nbins)
+    s, d, c = np.zeros(nb), np.zeros(nb), np.zeros(nb, dtype=np.int64)
+    r = lib().orc_spectrum(N, dx, f.ctypes.data_as(C.POINTER(C.c_double)), nb,
+                           s.ctypes.data_as(C.POINTER(C.c_double)), d.ctypes.data_as(C.POINTER(C.c_double)),
+                           c.ctypes.data_as(C.POINTER(C.c_long)))
+    if r < 0:
+        raise RuntimeError("orc_spectrum failed")
+    return s, d, c

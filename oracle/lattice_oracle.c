@@ -910,3 +910,107 @@ int orc_u1_lf_sync(const orc_u1_params *p, double *const *phi, double *const *pi
     c->lf_stag = 0;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Power spectrum (sec. 3.1, eq. discretePS)                           */
+/* ------------------------------------------------------------------ */
+/* Unnormalised forward DFT f~(n~) = sum_n f(n) exp(-2 pi i n~.n / N), one
+ * dimension at a time (plain O(N^4) sums, twiddles indexed by (k j) mod N).
+ * Bin b holds the modes with b <= |n~| < b + 1, n~_i in (-N/2, N/2] (bin 0:
+ * the zero mode only).  Per bin: the sum of |f~|^2 (compensated), the number
+ * of modes and the discrete spectrum of eq. discretePS,
+ *   Delta(b) = k_b^3 / (2 pi^2) (dx/N)^3 sum_b / (4 pi b^2),  k_b = b k_IR,
+ * k_IR = 2 pi / (N dx), and Delta(0) = 0.  With this normalisation
+ * sum_{b >= 1} (k_IR / k_b) Delta(b) = <f^2> - <f>^2 exactly (eq.
+ * discretePSII).  Returns the number of bins filled or -1. */
+static const double ORC_PI = 3.14159265358979323846;
+
+static void dft_axis(int N, double *re, double *im, int axis, const double *cs, const double *sn)
+{
+    double *tr = (double *)malloc((size_t)N * sizeof(double));
+    double *ti = (double *)malloc((size_t)N * sizeof(double));
+    size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)N : (size_t)N * N);
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            size_t base;
+            if (axis == 0) base = (size_t)N * ((size_t)a + (size_t)N * b);
+            else if (axis == 1) base = (size_t)a + (size_t)N * N * b;
+            else base = (size_t)a + (size_t)N * b;
+            for (int k = 0; k < N; ++k) {
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < N; ++j) {
+                    int m = (int)(((long)k * j) % N);
+                    double xr = re[base + stride * j], xi = im[base + stride * j];
+                    /* (xr + i xi)(cos - i sin) */
+                    sr += xr * cs[m] + xi * sn[m];
+                    si += xi * cs[m] - xr * sn[m];
+                }
+                tr[k] = sr;
+                ti[k] = si;
+            }
+            for (int k = 0; k < N; ++k) {
+                re[base + stride * k] = tr[k];
+                im[base + stride * k] = ti[k];
+            }
+        }
+    free(tr);
+    free(ti);
+}
+
+int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, double *delta, long *count)
+{
+    if (N < 1 || !f || nbins < 1) return -1;
+    size_t V = vol(N);
+    double *re = (double *)malloc(V * sizeof(double));
+    double *im = (double *)calloc(V, sizeof(double));
+    double *cs = (double *)malloc((size_t)N * sizeof(double));
+    double *sn = (double *)malloc((size_t)N * sizeof(double));
+    double *comp = (double *)calloc((size_t)nbins, sizeof(double));
+    memcpy(re, f, V * sizeof(double));
+    for (int j = 0; j < N; ++j) {
+        cs[j] = cos(2.0 * ORC_PI * j / N);
+        sn[j] = sin(2.0 * ORC_PI * j / N);
+    }
+    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn);
+    for (int b = 0; b < nbins; ++b) {
+        sum[b] = 0.0;
+        count[b] = 0;
+    }
+    int filled = 0;
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                long nx = x <= N / 2 ? x : x - N, ny = y <= N / 2 ? y : y - N, nz = z <= N / 2 ? z : z - N;
+                long m = nx * nx + ny * ny + nz * nz;
+                long b = (long)sqrt((double)m);
+                while ((b + 1) * (b + 1) <= m) ++b;
+                while (b * b > m) --b;
+                if (b >= nbins) continue;
+                size_t n = (size_t)x + (size_t)N * ((size_t)y + (size_t)N * z);
+                double p = re[n] * re[n] + im[n] * im[n];
+                /* Neumaier */
+                double t = sum[b] + p;
+                if (fabs(sum[b]) >= fabs(p)) comp[b] += (sum[b] - t) + p;
+                else comp[b] += (p - t) + sum[b];
+                sum[b] = t;
+                count[b] += 1;
+                if (b + 1 > filled) filled = (int)b + 1;
+            }
+    double kir = 2.0 * ORC_PI / (N * dx);
+    double v = dx / N;
+    for (int b = 0; b < nbins; ++b) {
+        sum[b] += comp[b];
+        if (b == 0) {
+            delta[b] = 0.0;
+        } else {
+            double kb = b * kir;
+            delta[b] = kb * kb * kb / (2.0 * ORC_PI * ORC_PI) * v * v * v * sum[b] / (4.0 * ORC_PI * (double)b * b);
+        }
+    }
+    free(re);
+    free(im);
+    free(cs);
+    free(sn);
+    free(comp);
+    return filled;
+}

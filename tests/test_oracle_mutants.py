@@ -37,6 +37,10 @@ MUTANTS = [
      "double cm = cos(e * dx * A[i][nm]), sm = -sin(e * dx * A[i][nm]);", "test_oracle_u1.py"),
     ("Hessian cross term", "double h01 = 2.0 * p->q * f * x;", "double h01 = p->q * f * x;",
      "test_oracle_adjoint.py"),
+    ("spectrum shell normalisation", "sum[b] / (4.0 * ORC_PI * (double)b * b)", "sum[b] / (4.0 * ORC_PI * (double)b)",
+     "test_oracle_spectrum.py"),
+    ("DFT twiddle index", "int m = (int)(((long)k * j) % N);", "int m = (int)(((long)k * (j + 1)) % N);",
+     "test_oracle_spectrum.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * h * lphi[s][n];", "test_oracle_adjoint.py"),
 ]
