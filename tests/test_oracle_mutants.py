@@ -39,7 +39,7 @@ MUTANTS = [
      "test_oracle_adjoint.py"),
     ("spectrum shell normalisation", "sum[b] / (4.0 * ORC_PI * (double)b * b)", "sum[b] / (4.0 * ORC_PI * (double)b)",
      "test_oracle_spectrum.py"),
-    ("DFT twiddle index", "int m = (int)(((long)k * j) % N);", "int m = (int)(((long)k * (j + 1)) % N);",
+    ("DFT complex product sign", "sr += xr * cs[m] + xi * sn[m];", "sr += xr * cs[m] - xi * sn[m];",
      "test_oracle_spectrum.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * h * lphi[s][n];", "test_oracle_adjoint.py"),
