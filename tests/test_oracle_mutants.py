@@ -39,7 +39,10 @@ MUTANTS = [
      "test_oracle_adjoint.py"),
     ("spectrum shell normalisation", "sum[b] / (4.0 * ORC_PI * (double)b * b)", "sum[b] / (4.0 * ORC_PI * (double)b)",
      "test_oracle_spectrum.py"),
-    ("DFT complex product sign", "sr += xr * cs[m] + xi * sn[m];", "sr += xr * cs[m] - xi * sn[m];",
+    ("spectrum shells by nearest radius",
+     "long b = (long)sqrt((double)m);\n                while ((b + 1) * (b + 1) <= m) ++b;\n                while (b * b > m) --b;",
+     "long b = (long)(sqrt((double)m) + 0.5);", "test_oracle_spectrum.py"),
+    ("DFT over two axes only", "for (int axis = 0; axis < 3; ++axis) dft_axis", "for (int axis = 0; axis < 2; ++axis) dft_axis",
      "test_oracle_spectrum.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * h * lphi[s][n];", "test_oracle_adjoint.py"),
