@@ -70,6 +70,9 @@ def lib():
         L.orc_vv2_adjoint_step.argtypes = [C.POINTER(Params), pp, pp, pp, pp, dp]
         L.orc_observable.argtypes = [C.POINTER(Params), pp, pp, dp, pp, pp, dp]
         L.orc_adjoint_vv2.argtypes = [C.POINTER(Params), pp, pp, C.c_long, dp, pp, pp, dp]
+        L.orc_observable_kind.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.c_int, pp, pp, dp, pp, pp, dp]
+        L.orc_adjoint_vv2_kind.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.c_int, pp, pp, C.c_long, dp,
+                                           pp, pp, dp]
         L.orc_u1_forces.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp]
         L.orc_u1_energy.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), dp]
         L.orc_u1_gauss.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, dp]
@@ -257,22 +260,29 @@ def vv2_adjoint_step(model: ScalarModel, phi_n, pi_n, lphi, lpi) -> float:
     return dq.value
 
 
-def observable(model: ScalarModel, phi, pi, with_grad=False):
+# Observables of the adjoint: the chi energy fraction (0) and one bin of the
+# power spectrum of eq. discretePS (1), for field `field`, bin `bin` >= 1.
+OBS_CHI_FRACTION = 0
+OBS_SPECTRUM_BIN = 1
+
+
+def observable(model: ScalarModel, phi, pi, with_grad=False, kind=OBS_CHI_FRACTION, field=0, bin=0):
     p = model.cparams()
     O = C.c_double()
     if not with_grad:
         null = C.cast(None, C.POINTER(C.POINTER(C.c_double)))
-        _chk(lib().orc_observable(C.byref(p), _pp(phi), _pp(pi), C.byref(O), null, null, None), "obs")
+        _chk(lib().orc_observable_kind(C.byref(p), kind, field, bin, _pp(phi), _pp(pi), C.byref(O), null, null,
+                                       None), "obs")
         return O.value
     g = [np.zeros_like(phi[0]) for _ in range(2)]
     gp = [np.zeros_like(phi[0]) for _ in range(2)]
     dq = C.c_double()
-    _chk(lib().orc_observable(C.byref(p), _pp(phi), _pp(pi), C.byref(O), _pp(g), _pp(gp),
-                              C.byref(dq)), "obs")
+    _chk(lib().orc_observable_kind(C.byref(p), kind, field, bin, _pp(phi), _pp(pi), C.byref(O), _pp(g), _pp(gp),
+                                   C.byref(dq)), "obs")
     return O.value, g, gp, dq.value
 
 
-def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int):
+def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int, kind=OBS_CHI_FRACTION, field=0, bin=0):
     """O(final), dO/dphi(0) per field, dO/dpi(0) per field, dO/dq."""
     phi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in phi0]
     pi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in pi0]
@@ -280,8 +290,8 @@ def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int):
     gp = [np.zeros_like(phi0[0]) for _ in range(2)]
     O, dq = C.c_double(), C.c_double()
     p = model.cparams()
-    _chk(lib().orc_adjoint_vv2(C.byref(p), _pp(phi0), _pp(pi0), int(nsteps), C.byref(O), _pp(g),
-                               _pp(gp), C.byref(dq)), "adjoint_vv2")
+    _chk(lib().orc_adjoint_vv2_kind(C.byref(p), kind, field, bin, _pp(phi0), _pp(pi0), int(nsteps), C.byref(O),
+                                    _pp(g), _pp(gp), C.byref(dq)), "adjoint_vv2")
     return O.value, g, gp, dq.value
 
 

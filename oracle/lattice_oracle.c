@@ -647,14 +647,24 @@ int orc_observable(const orc_params *p, double *const *phi, double *const *pi, d
     return 0;
 }
 
-/* Gradient of O(final state) with respect to the initial phi, pi and q for
- * nsteps VV2 steps, by reverse sweep with segment recomputation: checkpoints
- * every ceil(sqrt(nsteps)) steps, each segment re-run forward from its
- * checkpoint and stored, then pulled back step by step. */
-int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0, long nsteps,
-                    double *O_out, double *const *gphi, double *const *gpi, double *dOdq)
+/* Observables the reverse sweep can start from: the chi energy fraction above,
+ * or one bin of the power spectrum of one field (defined with the spectrum). */
+enum { ORC_OBS_CHI_FRACTION = 0, ORC_OBS_SPECTRUM_BIN = 1 };
+static double observable_kind(const orc_params *p, int kind, int field, int bin, double *const *phi,
+                              double *const *pi, double **gphi, double **gpi, double *dq);
+
+/* Gradient of O(final state) of observable `kind` with respect to the initial
+ * phi, pi and q for nsteps VV2 steps, by reverse sweep with segment
+ * recomputation: checkpoints every ceil(sqrt(nsteps)) steps, each segment re-run
+ * forward from its checkpoint and stored, then pulled back step by step. */
+
+int orc_adjoint_vv2_kind(const orc_params *p, int kind, int field, int bin, double *const *phi0,
+                         double *const *pi0, long nsteps, double *O_out, double *const *gphi, double *const *gpi,
+                         double *dOdq)
 {
     if (check_adj(p)) return -2;
+    if (kind != ORC_OBS_CHI_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
+    if (kind == ORC_OBS_SPECTRUM_BIN && (field < 0 || field > 1 || bin < 1)) return -1;
     if (nsteps < 0) return -1;
     size_t V = vol(p->N), B = V * sizeof(double);
     long k = 1;
@@ -677,7 +687,7 @@ int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0
     /* seed at the final state */
     double *lphi[2] = {gphi[0], gphi[1]}, *lpi[2] = {gpi[0], gpi[1]};
     double q_acc = 0.0;
-    *O_out = observable(p, cur, cur + 2, lphi, lpi, &q_acc);
+    *O_out = observable_kind(p, kind, field, bin, cur, cur + 2, lphi, lpi, &q_acc);
     /* segment states: positions and momenta at steps s0..s1 */
     double *seg = (double *)malloc((size_t)(k + 1) * 4 * B);
     for (long s0 = ((nsteps - 1) / k) * k; nsteps > 0 && s0 >= 0; s0 -= k) {
@@ -699,6 +709,12 @@ int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0
     free(cp);
     for (int i = 0; i < 4; ++i) free(cur[i]);
     return 0;
+}
+
+int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0, long nsteps,
+                    double *O_out, double *const *gphi, double *const *gpi, double *dOdq)
+{
+    return orc_adjoint_vv2_kind(p, 0, 0, 0, phi0, pi0, nsteps, O_out, gphi, gpi, dOdq);
 }
 
 /* ------------------------------------------------------------------ */
@@ -925,7 +941,8 @@ int orc_u1_lf_sync(const orc_u1_params *p, double *const *phi, double *const *pi
  * discretePSII).  Returns the number of bins filled or -1. */
 static const double ORC_PI = 3.14159265358979323846;
 
-static void dft_axis(int N, double *re, double *im, int axis, const double *cs, const double *sn)
+/* sign -1: forward, sum_j x_j e^{-2 pi i k j/N}; sign +1: unnormalised inverse */
+static void dft_axis(int N, double *re, double *im, int axis, const double *cs, const double *sn, int sign)
 {
     double *tr = (double *)malloc((size_t)N * sizeof(double));
     double *ti = (double *)malloc((size_t)N * sizeof(double));
@@ -941,9 +958,14 @@ static void dft_axis(int N, double *re, double *im, int axis, const double *cs, 
                 for (int j = 0; j < N; ++j) {
                     int m = (int)(((long)k * j) % N);
                     double xr = re[base + stride * j], xi = im[base + stride * j];
-                    /* (xr + i xi)(cos - i sin) */
-                    sr += xr * cs[m] + xi * sn[m];
-                    si += xi * cs[m] - xr * sn[m];
+                    /* (xr + i xi)(cos -+ i sin) */
+                    if (sign < 0) {
+                        sr += xr * cs[m] + xi * sn[m];
+                        si += xi * cs[m] - xr * sn[m];
+                    } else {
+                        sr += xr * cs[m] - xi * sn[m];
+                        si += xi * cs[m] + xr * sn[m];
+                    }
                 }
                 tr[k] = sr;
                 ti[k] = si;
@@ -955,6 +977,26 @@ static void dft_axis(int N, double *re, double *im, int axis, const double *cs, 
         }
     free(tr);
     free(ti);
+}
+
+/* Shell of mode (x, y, z): the integer b with b <= |n~| < b + 1, where each
+ * component n~ is the mode number taken in (-N/2, N/2]. */
+static long shell_of(int N, int x, int y, int z)
+{
+    long nx = x <= N / 2 ? x : x - N, ny = y <= N / 2 ? y : y - N, nz = z <= N / 2 ? z : z - N;
+    long m = nx * nx + ny * ny + nz * nz;
+    long b = (long)sqrt((double)m);
+    while ((b + 1) * (b + 1) <= m) ++b;
+    while (b * b > m) --b;
+    return b;
+}
+
+/* Weight of shell b >= 1 in eq. discretePS: Delta(b) = c_b sum_shell |f~|^2,
+ * c_b = k_b^3/(2 pi^2) (dx/N)^3 / (4 pi b^2), k_b = b k_IR, k_IR = 2 pi/(N dx). */
+static double shell_weight(int N, double dx, long b)
+{
+    double kb = b * (2.0 * ORC_PI / (N * dx)), v = dx / N;
+    return kb * kb * kb / (2.0 * ORC_PI * ORC_PI) * v * v * v / (4.0 * ORC_PI * (double)b * b);
 }
 
 int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, double *delta, long *count)
@@ -971,7 +1013,7 @@ int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, doub
         cs[j] = cos(2.0 * ORC_PI * j / N);
         sn[j] = sin(2.0 * ORC_PI * j / N);
     }
-    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn);
+    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, -1);
     for (int b = 0; b < nbins; ++b) {
         sum[b] = 0.0;
         count[b] = 0;
@@ -980,11 +1022,7 @@ int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, doub
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
             for (int x = 0; x < N; ++x) {
-                long nx = x <= N / 2 ? x : x - N, ny = y <= N / 2 ? y : y - N, nz = z <= N / 2 ? z : z - N;
-                long m = nx * nx + ny * ny + nz * nz;
-                long b = (long)sqrt((double)m);
-                while ((b + 1) * (b + 1) <= m) ++b;
-                while (b * b > m) --b;
+                long b = shell_of(N, x, y, z);
                 if (b >= nbins) continue;
                 size_t n = (size_t)x + (size_t)N * ((size_t)y + (size_t)N * z);
                 double p = re[n] * re[n] + im[n] * im[n];
@@ -996,16 +1034,9 @@ int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, doub
                 count[b] += 1;
                 if (b + 1 > filled) filled = (int)b + 1;
             }
-    double kir = 2.0 * ORC_PI / (N * dx);
-    double v = dx / N;
     for (int b = 0; b < nbins; ++b) {
         sum[b] += comp[b];
-        if (b == 0) {
-            delta[b] = 0.0;
-        } else {
-            double kb = b * kir;
-            delta[b] = kb * kb * kb / (2.0 * ORC_PI * ORC_PI) * v * v * v * sum[b] / (4.0 * ORC_PI * (double)b * b);
-        }
+        delta[b] = b == 0 ? 0.0 : shell_weight(N, dx, b) * sum[b];
     }
     free(re);
     free(im);
@@ -1013,4 +1044,80 @@ int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, doub
     free(sn);
     free(comp);
     return filled;
+}
+
+
+/* Spectrum-bin observable (sec. 3.1, eq. discretePS): O = Delta(b) of field s,
+ * with Delta(b) = c_b sum_{n in shell b} |f~(n)|^2, c_b = k_b^3/(2 pi^2)
+ * (dx/N)^3 / (4 pi b^2).  Its derivative with respect to f(x) is
+ * c_b 2 sum_{n in shell} Re[f~(n) e^{2 pi i n.x/N}], the unnormalised inverse
+ * DFT of the shell-masked transform (real: each shell holds n and -n). */
+static double spectrum_bin_value(int N, double dx, const double *f, int bin, double *g)
+{
+    size_t V = vol(N);
+    double *re = (double *)malloc(V * sizeof(double));
+    double *im = (double *)calloc(V, sizeof(double));
+    double *cs = (double *)malloc((size_t)N * sizeof(double));
+    double *sn = (double *)malloc((size_t)N * sizeof(double));
+    memcpy(re, f, V * sizeof(double));
+    for (int j = 0; j < N; ++j) {
+        cs[j] = cos(2.0 * ORC_PI * j / N);
+        sn[j] = sin(2.0 * ORC_PI * j / N);
+    }
+    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, -1);
+    double sum = 0.0, comp = 0.0;
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                long b = shell_of(N, x, y, z);
+                size_t n = (size_t)x + (size_t)N * ((size_t)y + (size_t)N * z);
+                if (b != bin) {
+                    re[n] = im[n] = 0.0;
+                    continue;
+                }
+                double p = re[n] * re[n] + im[n] * im[n];
+                double t = sum + p;
+                if (fabs(sum) >= fabs(p)) comp += (sum - t) + p;
+                else comp += (p - t) + sum;
+                sum = t;
+            }
+    sum += comp;
+    double cb = bin == 0 ? 0.0 : shell_weight(N, dx, bin);
+    if (g) {
+        for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, +1);
+        for (size_t n = 0; n < V; ++n) g[n] = 2.0 * cb * re[n];
+    }
+    free(re);
+    free(im);
+    free(cs);
+    free(sn);
+    return cb * sum;
+}
+
+/* Observable `kind` of the state and its gradient (seed of the adjoint):
+ * ORC_OBS_CHI_FRACTION as orc_observable; ORC_OBS_SPECTRUM_BIN: Delta(bin) of
+ * phi_field, gradient in gphi[field] only, no explicit q dependence. */
+static double observable_kind(const orc_params *p, int kind, int field, int bin, double *const *phi,
+                              double *const *pi, double **gphi, double **gpi, double *dq)
+{
+    if (kind == ORC_OBS_CHI_FRACTION) return observable(p, phi, pi, gphi, gpi, dq);
+    size_t V = vol(p->N);
+    for (int s = 0; s < 2; ++s) {
+        if (gphi) memset(gphi[s], 0, V * sizeof(double));
+        if (gpi) memset(gpi[s], 0, V * sizeof(double));
+    }
+    if (dq) *dq = 0.0;
+    return spectrum_bin_value(p->N, p->dx, phi[field], bin, gphi ? gphi[field] : NULL);
+}
+
+int orc_observable_kind(const orc_params *p, int kind, int field, int bin, double *const *phi, double *const *pi,
+                        double *O, double *const *gphi, double *const *gpi, double *dOdq)
+{
+    if (check_adj(p)) return -2;
+    if (kind != ORC_OBS_CHI_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
+    if (kind == ORC_OBS_SPECTRUM_BIN && (field < 0 || field > 1 || bin < 1)) return -1;
+    double d = 0.0;
+    *O = observable_kind(p, kind, field, bin, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
+    if (dOdq) *dOdq = d;
+    return 0;
 }

@@ -112,3 +112,88 @@ def test_reverse_sweep_vs_finite_differences(orc, nsteps):
         fd = (fp - fm) / (2 * eps)
         ad = np.dot(g[0], v[0]) + np.dot(g[1], v[1]) + np.dot(gp[0], v[2]) + np.dot(gp[1], v[3]) + dq * vq
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-12
+
+
+# Spectrum-bin observable: O = Delta(b) of one field (eq. discretePS).
+
+def test_spectrum_bin_observable_value_and_seed(orc):
+    N = 6
+    m = model(orc, N)
+    phi, pi = state(N, 11)
+    for field, b in ((0, 1), (1, 2), (0, 3)):
+        O, g, gp, dq = orc.observable(m, phi, pi, with_grad=True, kind=orc.OBS_SPECTRUM_BIN, field=field, bin=b)
+        # the value is the same bin of the oracle's (separately pinned) spectrum
+        ref = orc.spectrum(phi[field], m.dx, 5)[1][b]
+        assert abs(O - ref) <= 1e-13 * abs(ref)
+        # only phi of the chosen field enters; no explicit q dependence
+        assert dq == 0.0
+        assert not np.any(g[1 - field]) and not np.any(gp[0]) and not np.any(gp[1])
+        # Delta(b) is a quadratic form in phi: phi . grad = 2 Delta(b) exactly
+        assert abs(np.dot(phi[field], g[field]) - 2 * O) <= 1e-12 * abs(O)
+        # central differences at sites that are not mirror images of each other
+        eps = 1e-5
+        for site in (0, 7, 50, 101, 197):
+            p_ = [f.copy() for f in phi]; m_ = [f.copy() for f in phi]
+            p_[field][site] += eps; m_[field][site] -= eps
+            kw = dict(kind=orc.OBS_SPECTRUM_BIN, field=field, bin=b)
+            fd = (orc.observable(m, p_, pi, **kw) - orc.observable(m, m_, pi, **kw)) / (2 * eps)
+            assert abs(fd - g[field][site]) <= 1e-7 * np.max(np.abs(g[field]))
+
+
+def test_spectrum_bin_plane_wave_gradient(orc):
+    # f = A cos(2 pi n.x / N) with |n| in shell b: the shell holds +n and -n,
+    # each with |f~|^2 = (A N^3 / 2)^2, so Delta = 2 c_b (A N^3/2)^2 and the
+    # gradient is 2 c_b N^3 f = (4 Delta / (A^2 N^3)) f.
+    N, A = 8, 0.7
+    m = model(orc, N)
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    f = A * np.cos(2 * np.pi * (1 * x + 2 * y + 0 * z) / N).reshape(-1)
+    phi = [f, np.zeros(N ** 3)]
+    pi = [np.zeros(N ** 3), np.zeros(N ** 3)]
+    O, g, gp, dq = orc.observable(m, phi, pi, with_grad=True, kind=orc.OBS_SPECTRUM_BIN, field=0, bin=2)
+    kb = 2 * 2 * np.pi / (N * m.dx)
+    cb = kb ** 3 / (2 * np.pi ** 2) * (m.dx / N) ** 3 / (4 * np.pi * 4)
+    assert abs(O - 2 * cb * (A * N ** 3 / 2) ** 2) <= 1e-12 * O
+    assert np.max(np.abs(g[0] - 2 * cb * N ** 3 * f)) <= 1e-12 * np.max(np.abs(g[0]))
+    # a neighbouring shell sees nothing
+    O1 = orc.observable(m, phi, pi, kind=orc.OBS_SPECTRUM_BIN, field=0, bin=1)
+    assert abs(O1) <= 1e-20
+
+
+@pytest.mark.parametrize("nsteps,field,b", [(1, 0, 1), (7, 1, 2), (30, 0, 2)])
+def test_spectrum_bin_reverse_sweep_vs_finite_differences(orc, nsteps, field, b):
+    N = 5
+    m = model(orc, N, dt=0.02)
+    phi, pi = state(N, 9)
+    kw = dict(kind=orc.OBS_SPECTRUM_BIN, field=field, bin=b)
+    O, g, gp, dq = orc.adjoint_vv2(m, phi, pi, nsteps, **kw)
+
+    def O_of(phi_, pi_, q_):
+        st = orc.ScalarState(model(orc, N, dt=0.02, q=q_), phi_, pi_)
+        st.run(nsteps)
+        return orc.observable(model(orc, N, dt=0.02, q=q_), st.phi, st.pi, **kw)
+
+    assert abs(O - O_of(phi, pi, m.q)) <= 1e-14 * abs(O)
+    rng = np.random.default_rng(17)
+    for _ in range(3):
+        v = [rng.standard_normal(N ** 3) for _ in range(4)]
+        vq = rng.standard_normal()
+        nrm = np.sqrt(sum(np.dot(a, a) for a in v) + vq * vq)
+        v = [a / nrm for a in v]
+        vq /= nrm
+        eps = 1e-5
+        fp = O_of([phi[0] + eps * v[0], phi[1] + eps * v[1]], [pi[0] + eps * v[2], pi[1] + eps * v[3]], m.q + eps * vq)
+        fm = O_of([phi[0] - eps * v[0], phi[1] - eps * v[1]], [pi[0] - eps * v[2], pi[1] - eps * v[3]], m.q - eps * vq)
+        fd = (fp - fm) / (2 * eps)
+        ad = np.dot(g[0], v[0]) + np.dot(g[1], v[1]) + np.dot(gp[0], v[2]) + np.dot(gp[1], v[3]) + dq * vq
+        scale = np.sqrt(sum(np.dot(a, a) for a in g + gp) + dq * dq)
+        assert abs(fd - ad) <= 1e-6 * scale
+
+
+def test_spectrum_bin_rejects_bad_selection(orc):
+    N = 4
+    m = model(orc, N)
+    phi, pi = state(N, 2)
+    for field, b in ((2, 1), (-1, 1), (0, 0)):
+        with pytest.raises(RuntimeError):
+            orc.observable(m, phi, pi, kind=orc.OBS_SPECTRUM_BIN, field=field, bin=b)

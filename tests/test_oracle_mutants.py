@@ -37,11 +37,13 @@ MUTANTS = [
      "double cm = cos(e * dx * A[i][nm]), sm = -sin(e * dx * A[i][nm]);", "test_oracle_u1.py"),
     ("Hessian cross term", "double h01 = 2.0 * p->q * f * x;", "double h01 = p->q * f * x;",
      "test_oracle_adjoint.py"),
-    ("spectrum shell normalisation", "sum[b] / (4.0 * ORC_PI * (double)b * b)", "sum[b] / (4.0 * ORC_PI * (double)b)",
+    ("spectrum shell normalisation", "v * v * v / (4.0 * ORC_PI * (double)b * b)", "v * v * v / (4.0 * ORC_PI * (double)b)",
      "test_oracle_spectrum.py"),
     ("spectrum shells by nearest radius",
-     "long b = (long)sqrt((double)m);\n                while ((b + 1) * (b + 1) <= m) ++b;\n                while (b * b > m) --b;",
+     "long b = (long)sqrt((double)m);\n    while ((b + 1) * (b + 1) <= m) ++b;\n    while (b * b > m) --b;",
      "long b = (long)(sqrt((double)m) + 0.5);", "test_oracle_spectrum.py"),
+    ("inverse DFT with the forward sign", "if (sign < 0) {", "if (sign != 0) {", "test_oracle_adjoint.py"),
+    ("spectrum-bin gradient factor", "g[n] = 2.0 * cb * re[n];", "g[n] = cb * re[n];", "test_oracle_adjoint.py"),
     ("DFT over two axes only", "for (int axis = 0; axis < 3; ++axis) dft_axis", "for (int axis = 0; axis < 2; ++axis) dft_axis",
      "test_oracle_spectrum.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
