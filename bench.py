@@ -284,6 +284,13 @@ def main():
     e_us = 1e3 * se["kernel_ms"]["energy"] / max(se["launches"]["energy"], 1)
     energy_pass = {"mean_launch_us": e_us, "alg_bytes_per_launch": N ** 3 * 2 * 2 * esize,
                    "achieved_GBs_alg": N ** 3 * 2 * 2 * esize / (e_us * 1e-6) / 1e9}
+    # power spectrum of one field (transform and binning on the device, result on the host)
+    lat.spectrum(0, "phi")            # plan and buffers on the first call
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    sp = lat.spectrum(0, "phi")
+    spectrum = {"ms": 1e3 * (time.perf_counter() - c0), "bins": len(sp["sum"]), "field": "phi",
+                "includes": "copy to the transform buffer, float64 real-to-complex FFT, binning, host copy"}
 
     # float32-fields mode on the same workload
     f32 = None
@@ -356,6 +363,7 @@ def main():
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBS,
         "cpu_baseline": cpu,
         "energy_pass": energy_pass,
+        "spectrum": spectrum,
         "precision_f32": f32,
     }
     out.update(extras)

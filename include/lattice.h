@@ -174,6 +174,23 @@ lat_status lattice_init_batch(lat_ctx **ctx, const lat_params *p, int32_t n_real
 /* Energies of realization r of a batch context (as lattice_energy). */
 lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
 
+/* Discrete power spectrum (sec. 3.1, eq. discretePS) of one stored array:
+ * field in [0, number of fields) (U(1): the two components of the complex
+ * scalar), which = 0 for phi, 1 for pi (as stored: a staggered leapfrog state
+ * gives pi at the half step).  Radial bins of unit width: bin b holds the modes
+ * n (n_i in (-N/2, N/2]) with b <= |n| < b + 1; floor(sqrt(3) (N/2)) + 1 bins
+ * hold every mode.  Outputs (host arrays of nbins): sum[b] = sum over the bin
+ * of |f~(n)|^2 of the unnormalised forward DFT, count[b] = number of modes,
+ * delta[b] = k_b^3/(2 pi^2) (dx/N)^3 sum[b]/(4 pi b^2) with k_b = b k_IR,
+ * k_IR = 2 pi/(N dx) (delta[0] = 0), so that sum_{b>=1} (k_IR/k_b) delta[b]
+ * = <f^2> - <f>^2 (eq. discretePSII).  Float64 transform (hipFFT) whatever
+ * the field precision; bin sums are accumulated in an order that may vary at
+ * the last bit.  The transform buffers (about 2 N^3 doubles) are allocated on
+ * the first call.  Synchronizes the context stream.  Errors: LAT_EINVAL for a
+ * batch context, a field or array out of range, or nbins outside [1, 448]. */
+lat_status lattice_spectrum(lat_ctx *ctx, int32_t field, int32_t which, int32_t nbins, double *sum,
+                            double *delta, int64_t *count);
+
 /* Tile shape and z chunk the batch uses for lattice size N (host output);
  * tile_x = tile_y = z_chunk = 0 means one thread per site, no tiling. */
 lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, int32_t *tile_y, int32_t *z_chunk);

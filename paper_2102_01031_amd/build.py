@@ -27,10 +27,13 @@ def library_path() -> str:
     return LIB
 
 
+LIBS = ["-L/opt/rocm/lib", "-lhipfft"]   # power spectra: the library FFT
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *SOURCES]
+    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *SOURCES, *LIBS]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)

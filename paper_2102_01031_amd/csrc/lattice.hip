@@ -12,6 +12,7 @@
 // energies at point p also advances (a, b) and writes the next pass's drift and
 // kick coefficients on the device, so no host round trip sits between passes.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -31,6 +32,7 @@
 #include "stage_u1.hpp"
 #include "stage_adjoint.hpp"
 #include "stage_batch.hpp"
+#include "spectrum.hpp"
 
 using namespace lat;
 
@@ -160,6 +162,11 @@ struct lat_ctx {
     static constexpr int kStepGraphs = 4;
     StepGraph sg[kStepGraphs];
     uint64_t sg_clock = 0;
+    // power spectra (allocated on first use)
+    hipfftHandle fft_plan = nullptr;
+    double *fft_in = nullptr;
+    double2 *fft_out = nullptr;
+    double *spec_part = nullptr;        // per-block sums and counts, then the per-bin totals
     std::string err;
 };
 
@@ -869,6 +876,10 @@ void free_ctx(lat_ctx *c)
     if (c->reals_dev) (void)hipFree(c->reals_dev);
     if (c->block_work) (void)hipFree(c->block_work);
     for (int2 *t : c->seg_work) (void)hipFree(t);
+    if (c->fft_plan) (void)hipfftDestroy(c->fft_plan);
+    if (c->fft_in) (void)hipFree(c->fft_in);
+    if (c->fft_out) (void)hipFree(c->fft_out);
+    if (c->spec_part) (void)hipFree(c->spec_part);
     for (void *q : c->pi_scratch)
         if (q) (void)hipFree(q);
     for (lat_ctx *sub : c->subs) free_ctx(sub);
@@ -1077,6 +1088,64 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
     const double den = out->hubble_lhs + out->hubble_rhs;
     out->hubble_res = den != 0.0 ? (out->hubble_lhs - out->hubble_rhs) / den : 0.0;
     out->step = c->step;
+    return LAT_OK;
+}
+
+// Power spectrum of one stored array (sec. 3.1, eq. discretePS): float64
+// real-to-complex transform of the array (hipFFT), radial binning on the
+// device, normalisation on the host.
+constexpr int kSpecBlocks = 1024;
+
+lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nbins, double *sum, double *delta,
+                            int64_t *count)
+{
+    if (!c || !sum || !delta || !count) return fail(c, LAT_EINVAL, "null argument");
+    if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
+    const int nfld = c->u1 ? 2 : c->nf;
+    if (field < 0 || field >= nfld || (which != 0 && which != 1))
+        return fail(c, LAT_EINVAL, "field or array out of range");
+    if (nbins < 1 || nbins > kSpecMaxBins) return fail(c, LAT_EINVAL, "nbins out of range");
+    const int N = c->N;
+    const size_t V = c->vol, H = (size_t)N * N * (N / 2 + 1);
+    if (!c->fft_plan) {
+        if (hipMalloc(&c->fft_in, V * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->fft_out, H * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&c->spec_part, (size_t)2 * (kSpecBlocks + 1) * kSpecMaxBins * sizeof(double)) != hipSuccess)
+            return fail(c, LAT_ENOMEM, "spectrum buffers");
+        hipfftHandle plan = nullptr;
+        if (hipfftPlan3d(&plan, N, N, N, HIPFFT_D2Z) != HIPFFT_SUCCESS)
+            return fail(c, LAT_EHIP, "hipfftPlan3d failed");
+        c->fft_plan = plan;
+    }
+    if (hipfftSetStream(c->fft_plan, c->stream) != HIPFFT_SUCCESS) return fail(c, LAT_EHIP, "hipfftSetStream failed");
+    const void *src = which == 0 ? c->phi[field][c->cur_phi[field]] : c->pi[field][c->cur_pi[field]];
+    if (c->f32) {
+        hipLaunchKernelGGL(widen_f32, dim3(1024), dim3(256), 0, c->stream, (const float *)src, c->fft_in, V);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->fft_in, src, V * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (hipfftExecD2Z(c->fft_plan, c->fft_in, (hipfftDoubleComplex *)c->fft_out) != HIPFFT_SUCCESS)
+        return fail(c, LAT_EHIP, "hipfftExecD2Z failed");
+    const int nb = (int)std::min<size_t>(kSpecBlocks, (H + kSpecThreads - 1) / kSpecThreads);
+    double *ps = c->spec_part, *pc = ps + (size_t)kSpecBlocks * kSpecMaxBins;
+    double *tot = pc + (size_t)kSpecBlocks * kSpecMaxBins;
+    hipLaunchKernelGGL(spectrum_bin, dim3(nb), dim3(kSpecThreads), 0, c->stream, c->fft_out, N, nbins, ps, pc);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(spectrum_reduce, dim3((nbins + 63) / 64), dim3(64), 0, c->stream, ps, pc, nb, nbins, tot,
+                       tot + kSpecMaxBins);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> host(2 * (size_t)kSpecMaxBins);
+    HIPCHK(c, hipMemcpyAsync(host.data(), tot, host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double pi = 3.14159265358979323846;
+    const double kir = 2.0 * pi / (N * c->p.dx), v = c->p.dx / N;
+    for (int b = 0; b < nbins; ++b) {
+        sum[b] = host[b];
+        count[b] = (int64_t)std::llround(host[kSpecMaxBins + b]);
+        const double kb = b * kir;
+        delta[b] = b == 0 ? 0.0 : kb * kb * kb / (2.0 * pi * pi) * v * v * v * sum[b] / (4.0 * pi * (double)b * b);
+    }
     return LAT_OK;
 }
 

@@ -1,0 +1,72 @@
+// spectrum.hpp -- radial binning of the power of a real field's Fourier
+// transform, for the discrete power spectrum of sec. 3.1 (eq. discretePS).
+//
+// Input: the half spectrum F(kz, ky, kx) of the unnormalised forward DFT of
+// an N^3 real array (x fastest), kx in [0, N/2], as produced by a real-to-
+// complex transform.  Mode n = (nx, ny, nz) with n_i in (-N/2, N/2]; the modes
+// kx in (0, N/2) stand for themselves and their mirror images (-nx, -ny, -nz),
+// which have the same |F| and |n|, so they count twice.  Bin b holds the modes
+// with b <= |n| < b + 1.  Per block: sums of |F|^2 and mode counts per bin in
+// LDS; a second kernel adds the block partials in block order.
+#pragma once
+#include "common.hpp"
+
+namespace lat {
+
+constexpr int kSpecThreads = 256;
+constexpr int kSpecMaxBins = 448;   // >= floor(sqrt(3) 512/2) + 1
+
+__global__ void __launch_bounds__(kSpecThreads) spectrum_bin(const double2 *__restrict__ F, int N, int nbins,
+                                                             double *__restrict__ part_sum,
+                                                             double *__restrict__ part_cnt)
+{
+    __shared__ double s_sum[kSpecMaxBins], s_cnt[kSpecMaxBins];
+    for (int b = threadIdx.x; b < nbins; b += kSpecThreads) s_sum[b] = s_cnt[b] = 0.0;
+    __syncthreads();
+    const int H = N / 2 + 1;
+    const size_t total = (size_t)N * N * H;
+    for (size_t i = (size_t)blockIdx.x * kSpecThreads + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kSpecThreads) {
+        const int kx = (int)(i % H);
+        const size_t r = i / H;
+        const int ky = (int)(r % N), kz = (int)(r / N);
+        const long nx = kx, ny = ky <= N / 2 ? ky : ky - N, nz = kz <= N / 2 ? kz : kz - N;
+        const long m = nx * nx + ny * ny + nz * nz;
+        long b = (long)sqrt((double)m);
+        while ((b + 1) * (b + 1) <= m) ++b;
+        while (b * b > m) --b;
+        if (b >= nbins) continue;
+        const double w = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
+        const double2 f = F[i];
+        atomicAdd(&s_sum[b], w * (f.x * f.x + f.y * f.y));
+        atomicAdd(&s_cnt[b], w);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += kSpecThreads) {
+        part_sum[(size_t)blockIdx.x * nbins + b] = s_sum[b];
+        part_cnt[(size_t)blockIdx.x * nbins + b] = s_cnt[b];
+    }
+}
+
+__global__ void spectrum_reduce(const double *__restrict__ part_sum, const double *__restrict__ part_cnt, int nblocks,
+                                int nbins, double *__restrict__ sum, double *__restrict__ cnt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    double s = 0.0, c = 0.0;
+    for (int k = 0; k < nblocks; ++k) {
+        s += part_sum[(size_t)k * nbins + b];
+        c += part_cnt[(size_t)k * nbins + b];
+    }
+    sum[b] = s;
+    cnt[b] = c;
+}
+
+// widen a float32 field into the float64 transform input
+__global__ void widen_f32(const float *__restrict__ in, double *__restrict__ out, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (double)in[i];
+}
+
+}  // namespace lat

@@ -96,6 +96,9 @@ def lib():
         L.lattice_profile.restype = C.c_int
         L.lattice_grad.argtypes = [vp, C.POINTER(LatGradSpec), C.POINTER(LatGradOut)]
         L.lattice_grad.restype = C.c_int
+        dp = C.POINTER(C.c_double)
+        L.lattice_spectrum.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, dp, dp, C.POINTER(C.c_int64)]
+        L.lattice_spectrum.restype = C.c_int
         L.lattice_init_batch.argtypes = [C.POINTER(vp), C.POINTER(LatParams), C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(LatFields), C.c_int32, vp]
         L.lattice_init_batch.restype = C.c_int
@@ -185,6 +188,24 @@ class Lattice:
                     hubble_res=e.hubble_res, gauss_max=e.gauss_max, gauss_div_max=e.gauss_div_max,
                     gauss_charge_max=e.gauss_charge_max, gauss_mean=e.gauss_mean,
                     gauss_sum_mean=e.gauss_sum_mean, step=e.step)
+
+    def spectrum(self, field: int = 0, array: str = "phi", nbins: int | None = None) -> dict:
+        """Discrete power spectrum (eq. discretePS) of one stored array, computed
+        on the device: per radial bin b (modes with b <= |n| < b + 1) the sum of
+        |f~|^2, the mode count, k_b = b k_IR and Delta(b)."""
+        import math
+
+        import numpy as np
+        N = self.params.N
+        nb = int(math.isqrt(3 * (N // 2) ** 2)) + 1 if nbins is None else int(nbins)
+        s, d = np.zeros(nb), np.zeros(nb)
+        c = np.zeros(nb, dtype=np.int64)
+        dp = C.POINTER(C.c_double)
+        _check(lib().lattice_spectrum(self._ctx, int(field), {"phi": 0, "pi": 1}[array], nb,
+                                      s.ctypes.data_as(dp), d.ctypes.data_as(dp),
+                                      c.ctypes.data_as(C.POINTER(C.c_int64))), self._ctx)
+        kir = 2 * math.pi / (N * self.params.dx)
+        return dict(sum=s, delta=d, count=c, k=kir * np.arange(nb))
 
     def grad(self, nsteps: int, stride: int = 0, want_phi: bool = True, want_pi: bool = True) -> dict:
         """Energy fraction in chi after nsteps and its gradient with respect to the
