@@ -213,14 +213,18 @@ lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
 
 /* observable of lattice_grad */
 enum lat_observable {
-    LAT_OBS_CHI_ENERGY_FRACTION = 0   /* O = (E_K^chi + E_G^chi) / rho at the final time */
+    LAT_OBS_CHI_ENERGY_FRACTION = 0,  /* O = (E_K^chi + E_G^chi) / rho at the final time */
+    LAT_OBS_SPECTRUM_BIN = 1          /* O = Delta(b) of phi_field at the final time: bin b of the power
+                                         spectrum of lattice_spectrum (sec. 3.1, eq. discretePS) */
 };
 
 typedef struct lat_grad_spec {
     int32_t observable;          /* enum lat_observable */
-    int32_t reserved;
+    int32_t field;               /* LAT_OBS_SPECTRUM_BIN: field s in {0, 1}; otherwise 0 */
     int64_t nsteps;              /* T >= 1 velocity-Verlet steps */
     int64_t checkpoint_stride;   /* steps between stored states; 0 = ceil(sqrt(T)) */
+    int32_t bin;                 /* LAT_OBS_SPECTRUM_BIN: shell b, 1 <= b <= floor(sqrt(3) N / 2); otherwise 0 */
+    int32_t reserved;            /* 0 */
 } lat_grad_spec;
 
 typedef struct lat_grad_out {
@@ -242,7 +246,11 @@ typedef struct lat_grad_out {
  * LAT_VV2, LAT_EXP_NONE and LAT_PREC_F64 (LAT_EUNSUPPORTED otherwise).  The
  * library allocates the checkpoints (T/stride + 1 copies of the state) and the
  * adjoint arrays on first use and keeps them until lattice_destroy.
- * Synchronises the stream. */
+ * LAT_OBS_SPECTRUM_BIN seeds the adjoint with dDelta(b)/dphi_s: the
+ * unnormalised inverse transform of phi_s's spectrum kept on shell b, scaled
+ * by 2 c_b (hipFFT float64 transforms; their buffers and plans are kept like
+ * lattice_spectrum's).  A bad observable, field, bin or a nonzero reserved
+ * member gives LAT_EINVAL.  Synchronises the stream. */
 lat_status lattice_grad(lat_ctx *ctx, const lat_grad_spec *spec, lat_grad_out *out);
 
 /* Launch statistics of the stencil kernels, per kernel kind:

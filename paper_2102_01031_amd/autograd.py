@@ -3,9 +3,11 @@
 ``chi_energy_fraction(phi, chi, pi_phi, pi_chi, q, ...)`` evolves the two-field
 lattice (V = lambda/4 phi^4 + q/2 phi^2 chi^2, velocity-Verlet, a = 1) for
 ``nsteps`` and returns O = (E_K^chi + E_G^chi)/rho as a 0-dim float64 tensor.
-Its backward returns dO/d(phi, chi, pi_phi, pi_chi) at the initial time and
-dO/dq, all computed by ``lattice_grad`` (reverse integration with checkpoints)
-during the forward call.  The inputs are copied; they are not modified.
+``spectrum_bin(..., field, bin)`` returns instead Delta(bin) of field ``field``
+at the final time (eq. discretePS).  The backward returns dO/d(phi, chi,
+pi_phi, pi_chi) at the initial time and dO/dq, all computed by
+``lattice_grad`` (reverse integration with checkpoints) during the forward
+call.  The inputs are copied; they are not modified.
 """
 from __future__ import annotations
 
@@ -14,14 +16,14 @@ import torch
 from .lattice import Lattice
 
 
-class _ChiEnergyFraction(torch.autograd.Function):
+class _LatticeObservable(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi, chi, pi_phi, pi_chi, q, N, dx, dt, nsteps, lam, stride):
+    def forward(ctx, phi, chi, pi_phi, pi_chi, q, N, dx, dt, nsteps, lam, stride, observable, field, bin):
         fields = [t.detach().reshape(-1).to(torch.float64).contiguous().clone() for t in (phi, chi, pi_phi, pi_chi)]
         lat = Lattice(fields[:2], fields[2:], N=N, dx=dx, dt=dt, integrator="vv2", expansion="none",
                       potential="phi4_chi2", lam=lam, q=float(q))
         try:
-            r = lat.grad(nsteps, stride=stride)
+            r = lat.grad(nsteps, stride=stride, observable=observable, field=field, bin=bin)
         finally:
             lat.close()
         shape = phi.shape
@@ -33,9 +35,18 @@ class _ChiEnergyFraction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         gphi, gchi, gpp, gpc, gq = ctx.saved_tensors
-        return g * gphi, g * gchi, g * gpp, g * gpc, g * gq, None, None, None, None, None, None
+        return (g * gphi, g * gchi, g * gpp, g * gpc, g * gq) + (None,) * 9
+
+
+def _q(q):
+    return q if torch.is_tensor(q) else torch.tensor(float(q), dtype=torch.float64)
 
 
 def chi_energy_fraction(phi, chi, pi_phi, pi_chi, q, *, N, dx, dt, nsteps, lam=1.0, stride=0):
-    q = q if torch.is_tensor(q) else torch.tensor(float(q), dtype=torch.float64)
-    return _ChiEnergyFraction.apply(phi, chi, pi_phi, pi_chi, q, N, dx, dt, nsteps, lam, stride)
+    return _LatticeObservable.apply(phi, chi, pi_phi, pi_chi, _q(q), N, dx, dt, nsteps, lam, stride,
+                                    "chi_fraction", 0, 0)
+
+
+def spectrum_bin(phi, chi, pi_phi, pi_chi, q, *, N, dx, dt, nsteps, field, bin, lam=1.0, stride=0):
+    return _LatticeObservable.apply(phi, chi, pi_phi, pi_chi, _q(q), N, dx, dt, nsteps, lam, stride,
+                                    "spectrum_bin", int(field), int(bin))

@@ -163,7 +163,8 @@ struct lat_ctx {
     StepGraph sg[kStepGraphs];
     uint64_t sg_clock = 0;
     // power spectra (allocated on first use)
-    hipfftHandle fft_plan = nullptr;
+    hipfftHandle fft_plan = nullptr;      // float64 real-to-complex, N^3
+    hipfftHandle fft_inv = nullptr;       // float64 complex-to-real, N^3 (adjoint seed)
     double *fft_in = nullptr;
     double2 *fft_out = nullptr;
     double *spec_part = nullptr;        // per-block sums and counts, then the per-bin totals
@@ -877,6 +878,7 @@ void free_ctx(lat_ctx *c)
     if (c->block_work) (void)hipFree(c->block_work);
     for (int2 *t : c->seg_work) (void)hipFree(t);
     if (c->fft_plan) (void)hipfftDestroy(c->fft_plan);
+    if (c->fft_inv) (void)hipfftDestroy(c->fft_inv);
     if (c->fft_in) (void)hipFree(c->fft_in);
     if (c->fft_out) (void)hipFree(c->fft_out);
     if (c->spec_part) (void)hipFree(c->spec_part);
@@ -1096,6 +1098,44 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
 // device, normalisation on the host.
 constexpr int kSpecBlocks = 1024;
 
+// Transform buffers and plans on first use (kept until lattice_destroy).
+static lat_status ensure_fft(lat_ctx *c, bool inverse)
+{
+    const int N = c->N;
+    const size_t V = c->vol, H = (size_t)N * N * (N / 2 + 1);
+    if (!c->fft_in && hipMalloc(&c->fft_in, V * sizeof(double)) != hipSuccess) {
+        c->fft_in = nullptr;
+        return fail(c, LAT_ENOMEM, "spectrum buffers");
+    }
+    if (!c->fft_out && hipMalloc(&c->fft_out, H * sizeof(double2)) != hipSuccess) {
+        c->fft_out = nullptr;
+        return fail(c, LAT_ENOMEM, "spectrum buffers");
+    }
+    if (!c->spec_part &&
+        hipMalloc(&c->spec_part, (size_t)2 * (kSpecBlocks + 1) * kSpecMaxBins * sizeof(double)) != hipSuccess) {
+        c->spec_part = nullptr;
+        return fail(c, LAT_ENOMEM, "spectrum buffers");
+    }
+    hipfftHandle *plan = inverse ? &c->fft_inv : &c->fft_plan;
+    if (!*plan) {
+        hipfftHandle h = nullptr;
+        if (hipfftPlan3d(&h, N, N, N, inverse ? HIPFFT_Z2D : HIPFFT_D2Z) != HIPFFT_SUCCESS)
+            return fail(c, LAT_EHIP, "hipfftPlan3d failed");
+        *plan = h;
+    }
+    if (hipfftSetStream(*plan, c->stream) != HIPFFT_SUCCESS) return fail(c, LAT_EHIP, "hipfftSetStream failed");
+    return LAT_OK;
+}
+
+// Weight of shell b >= 1 in eq. discretePS: k_b^3/(2 pi^2) (dx/N)^3 / (4 pi b^2),
+// k_b = b k_IR, k_IR = 2 pi/(N dx).
+static double shell_weight(int N, double dx, long b)
+{
+    const double pi = 3.14159265358979323846;
+    const double kb = b * (2.0 * pi / (N * dx)), v = dx / N;
+    return kb * kb * kb / (2.0 * pi * pi) * v * v * v / (4.0 * pi * (double)b * b);
+}
+
 lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nbins, double *sum, double *delta,
                             int64_t *count)
 {
@@ -1107,17 +1147,8 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
     if (nbins < 1 || nbins > kSpecMaxBins) return fail(c, LAT_EINVAL, "nbins out of range");
     const int N = c->N;
     const size_t V = c->vol, H = (size_t)N * N * (N / 2 + 1);
-    if (!c->fft_plan) {
-        if (hipMalloc(&c->fft_in, V * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->fft_out, H * sizeof(double2)) != hipSuccess ||
-            hipMalloc(&c->spec_part, (size_t)2 * (kSpecBlocks + 1) * kSpecMaxBins * sizeof(double)) != hipSuccess)
-            return fail(c, LAT_ENOMEM, "spectrum buffers");
-        hipfftHandle plan = nullptr;
-        if (hipfftPlan3d(&plan, N, N, N, HIPFFT_D2Z) != HIPFFT_SUCCESS)
-            return fail(c, LAT_EHIP, "hipfftPlan3d failed");
-        c->fft_plan = plan;
-    }
-    if (hipfftSetStream(c->fft_plan, c->stream) != HIPFFT_SUCCESS) return fail(c, LAT_EHIP, "hipfftSetStream failed");
+    lat_status st = ensure_fft(c, false);
+    if (st != LAT_OK) return st;
     const void *src = which == 0 ? c->phi[field][c->cur_phi[field]] : c->pi[field][c->cur_pi[field]];
     if (c->f32) {
         hipLaunchKernelGGL(widen_f32, dim3(1024), dim3(256), 0, c->stream, (const float *)src, c->fft_in, V);
@@ -1138,13 +1169,10 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
     std::vector<double> host(2 * (size_t)kSpecMaxBins);
     HIPCHK(c, hipMemcpyAsync(host.data(), tot, host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const double pi = 3.14159265358979323846;
-    const double kir = 2.0 * pi / (N * c->p.dx), v = c->p.dx / N;
     for (int b = 0; b < nbins; ++b) {
         sum[b] = host[b];
         count[b] = (int64_t)std::llround(host[kSpecMaxBins + b]);
-        const double kb = b * kir;
-        delta[b] = b == 0 ? 0.0 : kb * kb * kb / (2.0 * pi * pi) * v * v * v * sum[b] / (4.0 * pi * (double)b * b);
+        delta[b] = b == 0 ? 0.0 : shell_weight(N, c->p.dx, b) * sum[b];
     }
     return LAT_OK;
 }
@@ -1429,10 +1457,23 @@ lat_status checkpoint_io(lat_ctx *c, size_t j, bool store)
 extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_grad_out *out)
 {
     if (!c || !spec || !out) return fail(c, LAT_EINVAL, "null argument");
-    if (spec->observable != LAT_OBS_CHI_ENERGY_FRACTION) return fail(c, LAT_EINVAL, "unknown observable");
-    if (c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 || c->p.expansion != LAT_EXP_NONE ||
-        c->f32)
+    const bool spec_obs = spec->observable == LAT_OBS_SPECTRUM_BIN;
+    if (spec->observable != LAT_OBS_CHI_ENERGY_FRACTION && !spec_obs)
+        return fail(c, LAT_EINVAL, "unknown observable");
+    if (c->batch || c->u1 || c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 ||
+        c->p.expansion != LAT_EXP_NONE || c->f32)
         return fail(c, LAT_EUNSUPPORTED, "lattice_grad needs two fields, VV2, no expansion and float64");
+    if (spec->reserved != 0) return fail(c, LAT_EINVAL, "reserved field of lat_grad_spec must be 0");
+    if (spec_obs) {
+        const long h2 = (long)(c->N / 2) * (c->N / 2);
+        long bmax = (long)std::sqrt(3.0 * (double)h2);
+        while ((bmax + 1) * (bmax + 1) <= 3 * h2) ++bmax;
+        while (bmax * bmax > 3 * h2) --bmax;
+        if (spec->field < 0 || spec->field > 1 || spec->bin < 1 || spec->bin > bmax)
+            return fail(c, LAT_EINVAL, "spectrum observable: field or bin out of range");
+    } else if (spec->field != 0 || spec->bin != 0) {
+        return fail(c, LAT_EINVAL, "field and bin are 0 for this observable");
+    }
     const int64_t T = spec->nsteps;
     if (T < 1 || T > (1LL << 26)) return fail(c, LAT_EINVAL, "nsteps out of range");
     int64_t k = spec->checkpoint_stride;
@@ -1518,17 +1559,44 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     HIPCHK(c, hipEventRecord(e1, c->stream));
 
     // ---- observable and seed
-    GCHK(energy_sums(c, 0.0));
     const double V = (double)c->vol;
-    const double *S = c->sc_host->sums;
-    double EK[2], EG[2];
-    for (int f = 0; f < 2; ++f) {
-        EK[f] = S[f] / V / 2.0;
-        EG[f] = S[2 + f] / (c->p.dx * c->p.dx) / V / 2.0;
-    }
-    const double rho = EK[0] + EK[1] + EG[0] + EG[1] + S[4] / V + S[5] / V;
-    const double O = (EK[1] + EG[1]) / rho;
-    {
+    double O = 0.0, rho = 0.0, cb = 0.0;
+    if (spec_obs) {
+        // dO/dphi_s = inverse transform of the shell-b half spectrum scaled by
+        // 2 c_b; every other adjoint array starts at zero; O has no explicit q
+        const int s = spec->field;
+        GCHK(ensure_fft(c, false));
+        GCHK(ensure_fft(c, true));
+        cb = shell_weight(N, c->p.dx, spec->bin);
+        hipLaunchKernelGGL(zero_doubles, dim3(1), dim3(64), 0, c->stream, &c->sc->sums[kMaxQ - 2], 2);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->fft_in, c->phi[s][c->cur_phi[s]], bytes, hipMemcpyDeviceToDevice, c->stream));
+        if (hipfftExecD2Z(c->fft_plan, c->fft_in, (hipfftDoubleComplex *)c->fft_out) != HIPFFT_SUCCESS) {
+            cleanup();
+            return fail(c, LAT_EHIP, "hipfftExecD2Z failed");
+        }
+        const size_t H = (size_t)N * N * (N / 2 + 1);
+        hipLaunchKernelGGL(spectrum_shell_seed, dim3((unsigned)((H + kSpecThreads - 1) / kSpecThreads)),
+                           dim3(kSpecThreads), 0, c->stream, c->fft_out, N, (long)spec->bin, 2.0 * cb,
+                           c->adj_partials, c->ticket, &c->sc->sums[kMaxQ - 2]);
+        HIPCHK(c, hipGetLastError());
+        if (hipfftExecZ2D(c->fft_inv, (hipfftDoubleComplex *)c->fft_out, (double *)c->lam[0][s][c->cur_lam[0][s]]) !=
+            HIPFFT_SUCCESS) {
+            cleanup();
+            return fail(c, LAT_EHIP, "hipfftExecZ2D failed");
+        }
+        HIPCHK(c, hipMemsetAsync(c->lam[0][1 - s][c->cur_lam[0][1 - s]], 0, bytes, c->stream));
+        for (int f = 0; f < 2; ++f) HIPCHK(c, hipMemsetAsync(c->lam[1][f][c->cur_lam[1][f]], 0, bytes, c->stream));
+    } else {
+        GCHK(energy_sums(c, 0.0));
+        const double *S = c->sc_host->sums;
+        double EK[2], EG[2];
+        for (int f = 0; f < 2; ++f) {
+            EK[f] = S[f] / V / 2.0;
+            EG[f] = S[2 + f] / (c->p.dx * c->p.dx) / V / 2.0;
+        }
+        rho = EK[0] + EK[1] + EG[0] + EG[1] + S[4] / V + S[5] / V;
+        O = (EK[1] + EG[1]) / rho;
         hipLaunchKernelGGL(zero_doubles, dim3(1), dim3(64), 0, c->stream, &c->sc->sums[kMaxQ - 2], 2);
         HIPCHK(c, hipGetLastError());
         SeedArgs a{};
@@ -1575,9 +1643,15 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
     HIPCHK(c, hipEventElapsedTime(&rms, e1, e2));
     const double dq_adj = c->sc_host->sums[kMaxQ - 1];
-    const double sum_p2c2 = c->sc_host->sums[kMaxQ - 2];
-    out->value = O;
-    out->dO_dq = dq_adj - O * (sum_p2c2 / V) / rho;
+    if (spec_obs) {
+        // sums[kMaxQ - 2] holds the shell's sum of |F|^2
+        out->value = cb * c->sc_host->sums[kMaxQ - 2];
+        out->dO_dq = dq_adj;
+    } else {
+        const double sum_p2c2 = c->sc_host->sums[kMaxQ - 2];
+        out->value = O;
+        out->dO_dq = dq_adj - O * (sum_p2c2 / V) / rho;
+    }
     out->forward_ms = fms;
     out->reverse_ms = rms;
     cleanup();

@@ -62,6 +62,71 @@ __global__ void spectrum_reduce(const double *__restrict__ part_sum, const doubl
     cnt[b] = c;
 }
 
+// Seed of an adjoint from O = Delta(b) of one field (eq. discretePS).  With
+// Delta(b) = c_b sum_{shell b} |F(n)|^2 over the full spectrum,
+// dO/df(x) = 2 c_b sum_{shell b} Re[F(n) e^{+2 pi i n.x/N}]: the unnormalised
+// complex-to-real inverse transform of the half spectrum kept on shell b and
+// scaled by 2 c_b (the shell holds n with -n, so the masked spectrum stays
+// Hermitian).  In place on F; also writes sum_{shell b} |F|^2 (mirror modes
+// counted) to *out_sum, reduced in a fixed order: per thread, per wave, per
+// block, then the last block adds the block partials in block order.
+__global__ void __launch_bounds__(kSpecThreads) spectrum_shell_seed(double2 *__restrict__ F, int N, long bin,
+                                                                    double scale, double *__restrict__ partials,
+                                                                    unsigned *ticket, double *out_sum)
+{
+    __shared__ double lds_red[kSpecThreads / 64];
+    __shared__ int last_flag;
+    const int H = N / 2 + 1;
+    const size_t total = (size_t)N * N * H;
+    const size_t i = (size_t)blockIdx.x * kSpecThreads + threadIdx.x;
+    double acc = 0.0;
+    if (i < total) {
+        const int kx = (int)(i % H);
+        const size_t r = i / H;
+        const int ky = (int)(r % N), kz = (int)(r / N);
+        const long nx = kx, ny = ky <= N / 2 ? ky : ky - N, nz = kz <= N / 2 ? kz : kz - N;
+        const long m = nx * nx + ny * ny + nz * nz;
+        long b = (long)sqrt((double)m);
+        while ((b + 1) * (b + 1) <= m) ++b;
+        while (b * b > m) --b;
+        double2 f = F[i];
+        if (b == bin) {
+            const double w = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
+            acc = w * (f.x * f.x + f.y * f.y);
+            f.x *= scale;
+            f.y *= scale;
+        } else {
+            f.x = f.y = 0.0;
+        }
+        F[i] = f;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double ws = wave_sum(acc);
+    if (lane == 0) lds_red[w] = ws;
+    __syncthreads();
+    if (tid == 0) {
+        double sb = 0.0;
+        for (int k = 0; k < kSpecThreads / 64; ++k) sb += lds_red[k];
+        store_agent(&partials[blockIdx.x], sb);
+        const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (last_flag) {
+        double part = 0.0;
+        for (int k = tid; k < (int)gridDim.x; k += kSpecThreads) part += load_agent(&partials[k]);
+        const double pw = wave_sum(part);
+        if (lane == 0) lds_red[w] = pw;
+        __syncthreads();
+        if (tid == 0) {
+            double sb = 0.0;
+            for (int k = 0; k < kSpecThreads / 64; ++k) sb += lds_red[k];
+            *out_sum = sb;
+            __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // widen a float32 field into the float64 transform input
 __global__ void widen_f32(const float *__restrict__ in, double *__restrict__ out, size_t n)
 {

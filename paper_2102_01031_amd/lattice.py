@@ -51,9 +51,12 @@ class LatEnergies(C.Structure):
 KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1", "adjoint"]
 
 
+OBSERVABLES = {"chi_fraction": 0, "spectrum_bin": 1}
+
+
 class LatGradSpec(C.Structure):
-    _fields_ = [("observable", C.c_int32), ("reserved", C.c_int32), ("nsteps", C.c_int64),
-                ("checkpoint_stride", C.c_int64)]
+    _fields_ = [("observable", C.c_int32), ("field", C.c_int32), ("nsteps", C.c_int64),
+                ("checkpoint_stride", C.c_int64), ("bin", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LatGradOut(C.Structure):
@@ -207,12 +210,16 @@ class Lattice:
         kir = 2 * math.pi / (N * self.params.dx)
         return dict(sum=s, delta=d, count=c, k=kir * np.arange(nb))
 
-    def grad(self, nsteps: int, stride: int = 0, want_phi: bool = True, want_pi: bool = True) -> dict:
-        """Energy fraction in chi after nsteps and its gradient with respect to the
-        current phi, pi (both fields) and q (hand-written adjoint in the library)."""
+    def grad(self, nsteps: int, stride: int = 0, want_phi: bool = True, want_pi: bool = True,
+             observable: str = "chi_fraction", field: int = 0, bin: int = 0) -> dict:
+        """An observable after nsteps and its gradient with respect to the current
+        phi, pi (both fields) and q (hand-written adjoint in the library).
+        observable: "chi_fraction", the energy fraction in chi, or
+        "spectrum_bin", Delta(bin) of field `field` (eq. discretePS)."""
         torch = self._torch
         N = self.params.N
-        spec = LatGradSpec(0, 0, int(nsteps), int(stride))
+        kind = OBSERVABLES[observable]
+        spec = LatGradSpec(kind, int(field), int(nsteps), int(stride), int(bin), 0)
         out = LatGradOut()
         gphi = [torch.empty(N ** 3, dtype=torch.float64, device="cuda") for _ in range(2)] if want_phi else None
         gpi = [torch.empty(N ** 3, dtype=torch.float64, device="cuda") for _ in range(2)] if want_pi else None

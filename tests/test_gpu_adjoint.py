@@ -125,3 +125,109 @@ def test_autograd_function_and_gradcheck():
     q4 = torch.tensor(wl.q, dtype=torch.float64, requires_grad=True)
     f = lambda a, b, c, d, qq: chi_energy_fraction(a, b, c, d, qq, N=n4, dx=wl.dx, dt=wl.dt, nsteps=6, lam=wl.lam)
     assert torch.autograd.gradcheck(f, (*xs, q4), eps=1e-6, atol=1e-9, rtol=1e-5)
+
+
+# Spectrum-bin observable: O = Delta(b) of one field after T steps (eq. discretePS)
+
+def gpu_spectrum_observable(wl, N, phi, pi, T, q, field, b):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_of(wl, N, q))
+    lat.step(T)
+    d = lat.spectrum(field, "phi", nbins=b + 1)["delta"][b]
+    lat.close()
+    return d
+
+
+@pytest.mark.parametrize("N,T,stride,field,b", [(16, 20, 0, 0, 1), (24, 15, 4, 1, 3), (13, 10, 1, 0, 10),
+                                                 (64, 12, 0, 1, 5)])
+def test_spectrum_bin_grad_matches_oracle_adjoint(N, T, stride, field, b):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields(N=N)
+    say(f"[adj] spectrum-bin oracle parity N={N} T={T} stride={stride} field={field} bin={b}")
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_of(wl, N))
+    r = lat.grad(T, stride=stride, observable="spectrum_bin", field=field, bin=b)
+    m = oracle.ScalarModel(N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2, expansion=oracle.NONE,
+                           integrator=oracle.VV2, lam=wl.lam, q=wl.q)
+    O, g, gp, dq = oracle.adjoint_vv2(m, phi, pi, T, kind=oracle.OBS_SPECTRUM_BIN, field=field, bin=b)
+    say(f"[adj]   O={r['value']:.6e} (oracle {O:.6e}) dO/dq={r['dO_dq']:.6e} (oracle {dq:.6e})")
+    assert abs(r["value"] - O) <= 1e-12 * abs(O)
+    for s in range(2):
+        assert rel_maxdiff(r["dO_dphi"][s].cpu().numpy(), g[s]) <= 1e-10
+        assert rel_maxdiff(r["dO_dpi"][s].cpu().numpy(), gp[s]) <= 1e-10
+    assert abs(r["dO_dq"] - dq) <= 1e-10 * abs(dq)
+    for s in range(2):
+        assert np.array_equal(tp[s].cpu().numpy(), phi[s].reshape(-1))
+        assert np.array_equal(tq[s].cpu().numpy(), pi[s].reshape(-1))
+    # the value is the same bin as lattice_spectrum's after T steps
+    assert abs(gpu_spectrum_observable(wl, N, phi, pi, T, wl.q, field, b) - O) <= 1e-12 * abs(O)
+    lat.close()
+
+
+def test_spectrum_bin_grad_full_workload_vs_finite_differences():
+    wl = workloads.ADJ_64
+    N, T, field, b = wl.N, wl.steps, 1, 4
+    phi, pi = wl.initial_fields()
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_of(wl, N))
+    r = lat.grad(T, observable="spectrum_bin", field=field, bin=b)
+    g = r["dO_dphi"][0].cpu().numpy().reshape(N, N, N)
+    dq = r["dO_dq"]
+    O0 = r["value"]
+    say(f"[adj] spectrum bin {b} of field {field}, full workload: O={O0:.6e} dO/dq={dq:.6e} forward "
+        f"{r['forward_ms']:.1f} ms reverse {r['reverse_ms']:.1f} ms")
+    lat.close()
+    assert abs(gpu_spectrum_observable(wl, N, phi, pi, T, wl.q, field, b) - O0) <= 1e-12 * abs(O0)
+    dirs = inputs.random_directions(4, N, seed=11) + [(np.zeros((N, N, N)), 1.0)]
+    for k, (v, vq) in enumerate(dirs):
+        ad = float(np.sum(g * v) + dq * vq)
+
+        def fd(eps):
+            fp = gpu_spectrum_observable(wl, N, [phi[0] + eps * v, phi[1]], pi, T, wl.q + eps * vq, field, b)
+            fm = gpu_spectrum_observable(wl, N, [phi[0] - eps * v, phi[1]], pi, T, wl.q - eps * vq, field, b)
+            return (fp - fm) / (2 * eps)
+
+        e = 2e-3 if vq == 1.0 else 4e-3
+        d1, d2 = fd(e), fd(e / 2)
+        rich = (4 * d2 - d1) / 3
+        rel = abs(rich - ad) / abs(ad)
+        say(f"[adj] spectrum dir {k}: adjoint {ad:.10e} fd {rich:.10e} (raw {d2:.10e}) rel {rel:.2e}")
+        assert rel <= 1e-6
+
+
+def test_spectrum_bin_autograd_and_bad_selection():
+    import torch
+    from paper_2102_01031_amd.autograd import spectrum_bin
+    from paper_2102_01031_amd.lattice import Lattice, LatticeError
+    wl = workloads.ADJ_64
+    N, T = 12, 9
+    phi, pi = wl.initial_fields(N=N)
+    ts = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (phi[0], phi[1], pi[0], pi[1])]
+    q = torch.tensor(wl.q, dtype=torch.float64, requires_grad=True)
+    O = spectrum_bin(*ts, q, N=N, dx=wl.dx, dt=wl.dt, nsteps=T, field=0, bin=2, lam=wl.lam)
+    O.backward()
+    m = oracle.ScalarModel(N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2, expansion=oracle.NONE,
+                           integrator=oracle.VV2, lam=wl.lam, q=wl.q)
+    Oo, g, gp, dq = oracle.adjoint_vv2(m, phi, pi, T, kind=oracle.OBS_SPECTRUM_BIN, field=0, bin=2)
+    assert abs(O.item() - Oo) <= 1e-12 * abs(Oo)
+    assert rel_maxdiff(ts[1].grad.cpu().numpy(), g[1]) <= 1e-10
+    assert rel_maxdiff(ts[2].grad.cpu().numpy(), gp[0]) <= 1e-10
+    assert abs(q.grad.item() - dq) <= 1e-10 * abs(dq)
+    # out-of-range selections are rejected before any work
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_of(wl, N))
+    bmax = int(np.floor(np.sqrt(3 * (N // 2) ** 2)))
+    for field, b in ((2, 1), (-1, 1), (0, 0), (0, bmax + 1)):
+        with pytest.raises(LatticeError):
+            lat.grad(T, observable="spectrum_bin", field=field, bin=b)
+    with pytest.raises(LatticeError):
+        lat.grad(T, observable="chi_fraction", field=1)
+    r = lat.grad(T, observable="spectrum_bin", field=1, bin=bmax)   # the outermost shell is valid
+    assert np.isfinite(r["value"]) and r["value"] >= 0.0
+    lat.close()
