@@ -66,6 +66,8 @@ def lib():
         L.orc_yoshida4.argtypes = [dp, dp]
         L.orc_triple_jump.argtypes = [C.c_int, dp, dp]
         L.orc_spectrum.argtypes = [C.c_int, C.c_double, dp, C.c_int, dp, dp, C.POINTER(C.c_long)]
+        L.orc_occupation.argtypes = [C.POINTER(Params), C.c_double, C.c_double, pp, pp, C.c_int, C.c_double, C.c_int,
+                                     dp, C.POINTER(C.c_long)]
         L.orc_vv2_tangent.argtypes = [C.POINTER(Params), pp, pp, pp, pp, C.c_double]
         L.orc_vv2_adjoint_step.argtypes = [C.POINTER(Params), pp, pp, pp, pp, dp]
         L.orc_observable.argtypes = [C.POINTER(Params), pp, pp, dp, pp, pp, dp]
@@ -377,3 +379,20 @@ def spectrum(f, dx, nbins=None):
     if r < 0:
         raise RuntimeError("orc_spectrum failed")
     return s, d, c
+
+
+def occupation(model: ScalarModel, a, bdot, phi, pi, field, fstar2=1.0, nbins=None):
+    """Lattice occupation number of field `field` per radial bin (eq.
+    OccuppationNum) for fields and momenta at the same time, scale factor a and
+    its derivative bdot; returns (n, count)."""
+    phi = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in phi]
+    pi = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in pi]
+    N = model.N
+    nb = spectrum_bins(N) if nbins is None else int(nbins)
+    n, c = np.zeros(nb), np.zeros(nb, dtype=np.int64)
+    p = model.cparams()
+    r = lib().orc_occupation(C.byref(p), float(a), float(bdot), _pp(phi), _pp(pi), int(field), float(fstar2), nb,
+                             n.ctypes.data_as(C.POINTER(C.c_double)), c.ctypes.data_as(C.POINTER(C.c_long)))
+    if r < 0:
+        raise RuntimeError("orc_occupation failed")
+    return n, c

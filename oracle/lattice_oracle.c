@@ -979,6 +979,20 @@ static void dft_axis(int N, double *re, double *im, int axis, const double *cs, 
     free(ti);
 }
 
+/* Unnormalised forward DFT of a real N^3 array into (re, im), axis by axis;
+ * cs, sn (N entries each) receive cos and sin of 2 pi j/N for later use. */
+static void dft3_real(int N, const double *f, double *re, double *im, double *cs, double *sn)
+{
+    size_t V = vol(N);
+    memcpy(re, f, V * sizeof(double));
+    memset(im, 0, V * sizeof(double));
+    for (int j = 0; j < N; ++j) {
+        cs[j] = cos(2.0 * ORC_PI * j / N);
+        sn[j] = sin(2.0 * ORC_PI * j / N);
+    }
+    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, -1);
+}
+
 /* Shell of mode (x, y, z): the integer b with b <= |n~| < b + 1, where each
  * component n~ is the mode number taken in (-N/2, N/2]. */
 static long shell_of(int N, int x, int y, int z)
@@ -1008,12 +1022,7 @@ int orc_spectrum(int N, double dx, const double *f, int nbins, double *sum, doub
     double *cs = (double *)malloc((size_t)N * sizeof(double));
     double *sn = (double *)malloc((size_t)N * sizeof(double));
     double *comp = (double *)calloc((size_t)nbins, sizeof(double));
-    memcpy(re, f, V * sizeof(double));
-    for (int j = 0; j < N; ++j) {
-        cs[j] = cos(2.0 * ORC_PI * j / N);
-        sn[j] = sin(2.0 * ORC_PI * j / N);
-    }
-    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, -1);
+    dft3_real(N, f, re, im, cs, sn);
     for (int b = 0; b < nbins; ++b) {
         sum[b] = 0.0;
         count[b] = 0;
@@ -1059,12 +1068,7 @@ static double spectrum_bin_value(int N, double dx, const double *f, int bin, dou
     double *im = (double *)calloc(V, sizeof(double));
     double *cs = (double *)malloc((size_t)N * sizeof(double));
     double *sn = (double *)malloc((size_t)N * sizeof(double));
-    memcpy(re, f, V * sizeof(double));
-    for (int j = 0; j < N; ++j) {
-        cs[j] = cos(2.0 * ORC_PI * j / N);
-        sn[j] = sin(2.0 * ORC_PI * j / N);
-    }
-    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, -1);
+    dft3_real(N, f, re, im, cs, sn);
     double sum = 0.0, comp = 0.0;
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
@@ -1120,4 +1124,77 @@ int orc_observable_kind(const orc_params *p, int kind, int field, int bin, doubl
     *O = observable_kind(p, kind, field, bin, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
     if (dOdq) *dOdq = d;
     return 0;
+}
+
+/* Lattice occupation number of scalar field s (eq. OccuppationNum), per radial
+ * bin b >= 1 (shells as the spectrum):
+ *   n_b = (a^2 L^3 / (2 N^6)) F [ omega_b <|f~|^2>_R
+ *                                 + a^{2(1-alpha)}/omega_b <|f~' + (b_/a) f~|^2>_R ],
+ * L = N dx, F = (f_star/omega_star)^2 (argument fstar2), <.>_R the shell sum
+ * divided by 4 pi b^2 as in eq. discretePS, f' = a^{alpha-3} pi (the drift of
+ * sec. 4.5.2), b_ = a', omega_b^2 = k_b^2 + a^2 <d^2V/dphi_s^2> with the volume
+ * average over the lattice and k_b = b k_IR.  n_0 = 0.  Momenta must be at the
+ * same time as the fields.  Returns the number of bins filled or -1. */
+int orc_occupation(const orc_params *p, double a, double bdot, double *const *phi, double *const *pi, int field,
+                   double fstar2, int nbins, double *n, long *count)
+{
+    const int N = p->N;
+    if (N < 1 || nbins < 1 || field < 0 || field >= p->nfields || a <= 0.0) return -1;
+    size_t V = vol(N);
+    /* <d^2 V / dphi_s^2>: lambda/4 phi^4 gives 3 lambda phi^2; q/2 phi^2 chi^2
+     * gives q chi^2 for phi and q phi^2 for chi */
+    double vpp = 0.0;
+    for (size_t i = 0; i < V; ++i) {
+        double u = phi[0][i], w = p->nfields > 1 ? phi[1][i] : 0.0, d = 0.0;
+        if (field == 0) {
+            d = 3.0 * p->lambda * u * u;
+            if (p->potential == ORC_PHI4_CHI2) d += p->q * w * w;
+        } else if (p->potential == ORC_PHI4_CHI2) {
+            d = p->q * u * u;
+        }
+        vpp += d;
+    }
+    vpp /= (double)V;
+    double *fr = (double *)malloc(V * sizeof(double)), *fi = (double *)malloc(V * sizeof(double));
+    double *pr = (double *)malloc(V * sizeof(double)), *pim = (double *)malloc(V * sizeof(double));
+    double *cs = (double *)malloc((size_t)N * sizeof(double)), *sn = (double *)malloc((size_t)N * sizeof(double));
+    double *sf = (double *)calloc((size_t)nbins, sizeof(double)), *sx = (double *)calloc((size_t)nbins, sizeof(double));
+    dft3_real(N, phi[field], fr, fi, cs, sn);
+    dft3_real(N, pi[field], pr, pim, cs, sn);
+    const double cp = pow(a, p->alpha - 3.0), hub = bdot / a;
+    for (int b = 0; b < nbins; ++b) count[b] = 0;
+    int filled = 0;
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                long b = shell_of(N, x, y, z);
+                if (b >= nbins) continue;
+                size_t i = (size_t)x + (size_t)N * ((size_t)y + (size_t)N * z);
+                double xr = cp * pr[i] + hub * fr[i], xi = cp * pim[i] + hub * fi[i];
+                sf[b] += fr[i] * fr[i] + fi[i] * fi[i];
+                sx[b] += xr * xr + xi * xi;
+                count[b] += 1;
+                if (b + 1 > filled) filled = (int)b + 1;
+            }
+    const double L = N * p->dx, N6 = (double)V * (double)V;
+    const double pref = a * a * L * L * L / (2.0 * N6) * fstar2;
+    const double kir = 2.0 * ORC_PI / L;
+    for (int b = 0; b < nbins; ++b) {
+        if (b == 0) {
+            n[b] = 0.0;
+            continue;
+        }
+        double kb = b * kir;
+        double om = sqrt(kb * kb + a * a * vpp);
+        n[b] = pref * (om * sf[b] + pow(a, 2.0 * (1.0 - p->alpha)) * sx[b] / om) / (4.0 * ORC_PI * (double)b * b);
+    }
+    free(fr);
+    free(fi);
+    free(pr);
+    free(pim);
+    free(cs);
+    free(sn);
+    free(sf);
+    free(sx);
+    return filled;
 }

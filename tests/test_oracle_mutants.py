@@ -46,6 +46,14 @@ MUTANTS = [
     ("spectrum-bin gradient factor", "g[n] = 2.0 * cb * re[n];", "g[n] = cb * re[n];", "test_oracle_adjoint.py"),
     ("DFT over two axes only", "for (int axis = 0; axis < 3; ++axis) dft_axis", "for (int axis = 0; axis < 2; ++axis) dft_axis",
      "test_oracle_spectrum.py"),
+    ("occupation Hubble term sign", "xr = cp * pr[i] + hub * fr[i]", "xr = cp * pr[i] - hub * fr[i]",
+     "test_oracle_occupation.py"),
+    ("occupation momentum power of a", "cp = pow(a, p->alpha - 3.0)", "cp = pow(a, p->alpha - 2.0)",
+     "test_oracle_occupation.py"),
+    ("occupation omega placement", "n[b] = pref * (om * sf[b] +", "n[b] = pref * (sf[b] / om +",
+     "test_oracle_occupation.py"),
+    ("occupation cross-coupling mass", "if (p->potential == ORC_PHI4_CHI2) d += p->q * w * w;", "",
+     "test_oracle_occupation.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * h * lphi[s][n];", "test_oracle_adjoint.py"),
 ]
