@@ -191,6 +191,23 @@ lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
 lat_status lattice_spectrum(lat_ctx *ctx, int32_t field, int32_t which, int32_t nbins, double *sum,
                             double *delta, int64_t *count);
 
+/* Lattice occupation number (eq. OccuppationNum, sec. 6.4 measurements)
+ * of real scalar field `field` per radial bin (bins as lattice_spectrum):
+ *   n[b] = (a^2 L^3 / (2 N^6)) fstar2 [ w_b S_phi(b) + a^{2(1-alpha)} S_x(b) / w_b ] / (4 pi b^2)
+ * with L = N dx, S_phi(b) and S_x(b) the bin sums of |f~|^2 for phi_s and for
+ * phi_s' + (a'/a) phi_s (phi' = a^{alpha-3} pi, the drift of sec. 4.5.2),
+ * w_b^2 = k_b^2 + a^2 <d^2V/dphi_s^2> (volume average over the lattice), k_b = b k_IR,
+ * fstar2 = (f_star/omega_star)^2 of the model's units, and a, a' those of the
+ * current time (self-consistent, fixed or a = 1).  The shell average divides by
+ * 4 pi b^2 as in eq. discretePS; count[b] gives the number of modes for a
+ * per-mode mean.  n[0] = 0.  Host arrays of nbins.  Float64 transforms of
+ * phi_s and pi_s (hipFFT); a second half-spectrum buffer is allocated on the
+ * first call.  Synchronizes the context stream.  Errors: LAT_EINVAL for a batch
+ * context, field outside [0, nfields), nbins outside [1, 448] or fstar2 <= 0;
+ * LAT_EUNSUPPORTED for the U(1) model; LAT_ESTATE for leapfrog momenta at the
+ * half step (call lattice_sync first). */
+lat_status lattice_occupation(lat_ctx *ctx, int32_t field, int32_t nbins, double fstar2, double *n, int64_t *count);
+
 /* Tile shape and z chunk the batch uses for lattice size N (host output);
  * tile_x = tile_y = z_chunk = 0 means one thread per site, no tiling. */
 lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, int32_t *tile_y, int32_t *z_chunk);
@@ -202,7 +219,7 @@ lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, in
 lat_status lattice_step(lat_ctx *ctx, int64_t nsteps);
 
 /* LF only: half-kick the momenta to integer time in place (the sync before
- * measurements of sec. 7.2).  The next step then starts with a half kick.
+ * measurements of sec. 6.1).  The next step then starts with a half kick.
  * No-op for VV integrators or already synchronised momenta. */
 lat_status lattice_sync(lat_ctx *ctx);
 

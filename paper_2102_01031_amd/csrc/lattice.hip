@@ -167,6 +167,7 @@ struct lat_ctx {
     hipfftHandle fft_inv = nullptr;       // float64 complex-to-real, N^3 (adjoint seed)
     double *fft_in = nullptr;
     double2 *fft_out = nullptr;
+    double2 *fft_out2 = nullptr;          // second half spectrum (occupation number: momenta)
     double *spec_part = nullptr;        // per-block sums and counts, then the per-bin totals
     std::string err;
 };
@@ -881,6 +882,7 @@ void free_ctx(lat_ctx *c)
     if (c->fft_inv) (void)hipfftDestroy(c->fft_inv);
     if (c->fft_in) (void)hipFree(c->fft_in);
     if (c->fft_out) (void)hipFree(c->fft_out);
+    if (c->fft_out2) (void)hipFree(c->fft_out2);
     if (c->spec_part) (void)hipFree(c->spec_part);
     for (void *q : c->pi_scratch)
         if (q) (void)hipFree(q);
@@ -1112,7 +1114,7 @@ static lat_status ensure_fft(lat_ctx *c, bool inverse)
         return fail(c, LAT_ENOMEM, "spectrum buffers");
     }
     if (!c->spec_part &&
-        hipMalloc(&c->spec_part, (size_t)2 * (kSpecBlocks + 1) * kSpecMaxBins * sizeof(double)) != hipSuccess) {
+        hipMalloc(&c->spec_part, (size_t)4 * (kSpecBlocks + 1) * kSpecMaxBins * sizeof(double)) != hipSuccess) {
         c->spec_part = nullptr;
         return fail(c, LAT_ENOMEM, "spectrum buffers");
     }
@@ -1136,6 +1138,22 @@ static double shell_weight(int N, double dx, long b)
     return kb * kb * kb / (2.0 * pi * pi) * v * v * v / (4.0 * pi * (double)b * b);
 }
 
+// Copy (or widen) one stored array into the transform input and run the
+// forward real-to-complex transform into out.
+static lat_status forward_transform(lat_ctx *c, const void *src, double2 *out)
+{
+    const size_t V = c->vol;
+    if (c->f32) {
+        hipLaunchKernelGGL(widen_f32, dim3(1024), dim3(256), 0, c->stream, (const float *)src, c->fft_in, V);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->fft_in, src, V * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (hipfftExecD2Z(c->fft_plan, c->fft_in, (hipfftDoubleComplex *)out) != HIPFFT_SUCCESS)
+        return fail(c, LAT_EHIP, "hipfftExecD2Z failed");
+    return LAT_OK;
+}
+
 lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nbins, double *sum, double *delta,
                             int64_t *count)
 {
@@ -1150,14 +1168,8 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
     lat_status st = ensure_fft(c, false);
     if (st != LAT_OK) return st;
     const void *src = which == 0 ? c->phi[field][c->cur_phi[field]] : c->pi[field][c->cur_pi[field]];
-    if (c->f32) {
-        hipLaunchKernelGGL(widen_f32, dim3(1024), dim3(256), 0, c->stream, (const float *)src, c->fft_in, V);
-        HIPCHK(c, hipGetLastError());
-    } else {
-        HIPCHK(c, hipMemcpyAsync(c->fft_in, src, V * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    }
-    if (hipfftExecD2Z(c->fft_plan, c->fft_in, (hipfftDoubleComplex *)c->fft_out) != HIPFFT_SUCCESS)
-        return fail(c, LAT_EHIP, "hipfftExecD2Z failed");
+    st = forward_transform(c, src, c->fft_out);
+    if (st != LAT_OK) return st;
     const int nb = (int)std::min<size_t>(kSpecBlocks, (H + kSpecThreads - 1) / kSpecThreads);
     double *ps = c->spec_part, *pc = ps + (size_t)kSpecBlocks * kSpecMaxBins;
     double *tot = pc + (size_t)kSpecBlocks * kSpecMaxBins;
@@ -1173,6 +1185,92 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
         sum[b] = host[b];
         count[b] = (int64_t)std::llround(host[kSpecMaxBins + b]);
         delta[b] = b == 0 ? 0.0 : shell_weight(N, c->p.dx, b) * sum[b];
+    }
+    return LAT_OK;
+}
+
+// Lattice occupation number (eq. OccuppationNum) of one real scalar field:
+// transforms of phi_s and pi_s, shell sums on the device, <phi^2> and <chi^2>
+// for the effective mass by a fixed-order device reduction, normalisation on
+// the host.
+lat_status lattice_occupation(lat_ctx *c, int32_t field, int32_t nbins, double fstar2, double *n, int64_t *count)
+{
+    if (!c || !n || !count) return fail(c, LAT_EINVAL, "null argument");
+    if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
+    if (c->u1) return fail(c, LAT_EUNSUPPORTED, "occupation numbers are defined for real scalar fields");
+    if (field < 0 || field >= c->nf) return fail(c, LAT_EINVAL, "field out of range");
+    if (nbins < 1 || nbins > kSpecMaxBins) return fail(c, LAT_EINVAL, "nbins out of range");
+    if (!(fstar2 > 0.0) || !std::isfinite(fstar2)) return fail(c, LAT_EINVAL, "fstar2 must be positive");
+    if (c->p.integrator == LAT_LF && c->lf_stag != 0)
+        return fail(c, LAT_ESTATE, "momenta are at the half step: call lattice_sync first");
+    const int N = c->N;
+    const size_t V = c->vol, H = (size_t)N * N * (N / 2 + 1);
+    lat_status st = ensure_fft(c, false);
+    if (st != LAT_OK) return st;
+    if (!c->fft_out2 && hipMalloc(&c->fft_out2, H * sizeof(double2)) != hipSuccess) {
+        c->fft_out2 = nullptr;
+        return fail(c, LAT_ENOMEM, "spectrum buffers");
+    }
+    // scale factor and its derivative at the current time
+    double a = 1.0, b = 0.0;
+    if (c->p.expansion == LAT_EXP_FIXED) fixed_ab(c->p, c->t, &a, &b);
+    if (c->p.expansion == LAT_EXP_SELF) {
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        a = c->sc_host->a;
+        b = c->sc_host->b;
+    }
+    st = forward_transform(c, c->phi[field][c->cur_phi[field]], c->fft_out);
+    if (st != LAT_OK) return st;
+    st = forward_transform(c, c->pi[field][c->cur_pi[field]], c->fft_out2);
+    if (st != LAT_OK) return st;
+    const size_t S = (size_t)kSpecBlocks * kSpecMaxBins;
+    double *part = c->spec_part, *tot = part + 3 * S;
+    double *sq_part = tot + 3 * kSpecMaxBins, *sq_tot = sq_part + 2 * kSpecBlocks;
+    const int nb = (int)std::min<size_t>(kSpecBlocks, (H + kSpecThreads - 1) / kSpecThreads);
+    hipLaunchKernelGGL(occupation_bin, dim3(nb), dim3(kSpecThreads), 0, c->stream, c->fft_out, c->fft_out2, N, nbins,
+                       std::pow(a, c->p.alpha - 3.0), b / a, part, S);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(spectrum_reduce_q, dim3((nbins + 63) / 64, 3), dim3(64), 0, c->stream, part, S, nb, nbins, 3,
+                       tot, kSpecMaxBins);
+    HIPCHK(c, hipGetLastError());
+    const int nq = (int)std::min<size_t>(kSpecBlocks, (V + kSpecThreads - 1) / kSpecThreads);
+    const void *f0 = c->phi[0][c->cur_phi[0]], *f1 = c->nf > 1 ? c->phi[1][c->cur_phi[1]] : nullptr;
+    if (c->f32)
+        hipLaunchKernelGGL(sumsq_blocks<float>, dim3(nq), dim3(kSpecThreads), 0, c->stream, (const float *)f0,
+                           (const float *)f1, V, sq_part);
+    else
+        hipLaunchKernelGGL(sumsq_blocks<double>, dim3(nq), dim3(kSpecThreads), 0, c->stream, (const double *)f0,
+                           (const double *)f1, V, sq_part);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(sumsq_reduce, dim3(1), dim3(64), 0, c->stream, sq_part, nq, sq_tot);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> host(3 * (size_t)kSpecMaxBins + 2);
+    HIPCHK(c, hipMemcpyAsync(host.data(), tot, 3 * kSpecMaxBins * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host.data() + 3 * kSpecMaxBins, sq_tot, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // <d^2V/dphi_s^2>: lambda/4 phi^4 -> 3 lambda phi^2; q/2 phi^2 chi^2 -> q chi^2 (phi), q phi^2 (chi)
+    const double p2 = host[3 * kSpecMaxBins] / (double)V, c2 = host[3 * kSpecMaxBins + 1] / (double)V;
+    double vpp = 0.0;
+    if (field == 0) {
+        vpp = 3.0 * c->p.lambda * p2;
+        if (c->p.potential == LAT_PHI4_CHI2) vpp += c->p.q * c2;
+    } else if (c->p.potential == LAT_PHI4_CHI2) {
+        vpp = c->p.q * p2;
+    }
+    const double pi = 3.14159265358979323846;
+    const double L = N * c->p.dx, N6 = (double)V * (double)V;
+    const double pref = a * a * L * L * L / (2.0 * N6) * fstar2, wx = std::pow(a, 2.0 * (1.0 - c->p.alpha));
+    for (int bin = 0; bin < nbins; ++bin) {
+        count[bin] = (int64_t)std::llround(host[2 * kSpecMaxBins + bin]);
+        if (bin == 0) {
+            n[bin] = 0.0;
+            continue;
+        }
+        const double kb = bin * (2.0 * pi / L);
+        const double om = std::sqrt(kb * kb + a * a * vpp);
+        n[bin] = pref * (om * host[bin] + wx * host[kSpecMaxBins + bin] / om) / (4.0 * pi * (double)bin * bin);
     }
     return LAT_OK;
 }

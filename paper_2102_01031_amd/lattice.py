@@ -102,6 +102,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.lattice_spectrum.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, dp, dp, C.POINTER(C.c_int64)]
         L.lattice_spectrum.restype = C.c_int
+        L.lattice_occupation.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, dp, C.POINTER(C.c_int64)]
+        L.lattice_occupation.restype = C.c_int
         L.lattice_init_batch.argtypes = [C.POINTER(vp), C.POINTER(LatParams), C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(LatFields), C.c_int32, vp]
         L.lattice_init_batch.restype = C.c_int
@@ -209,6 +211,22 @@ class Lattice:
                                       c.ctypes.data_as(C.POINTER(C.c_int64))), self._ctx)
         kir = 2 * math.pi / (N * self.params.dx)
         return dict(sum=s, delta=d, count=c, k=kir * np.arange(nb))
+
+    def occupation(self, field: int = 0, nbins: int | None = None, fstar2: float = 1.0) -> dict:
+        """Lattice occupation number (eq. OccuppationNum) of one real field per
+        radial bin, computed on the device from phi, pi, a and a' at the current
+        time; fstar2 = (f_star/omega_star)^2.  Leapfrog momenta must be synced."""
+        import math
+
+        import numpy as np
+        N = self.params.N
+        nb = int(math.isqrt(3 * (N // 2) ** 2)) + 1 if nbins is None else int(nbins)
+        n, c = np.zeros(nb), np.zeros(nb, dtype=np.int64)
+        _check(lib().lattice_occupation(self._ctx, int(field), nb, float(fstar2),
+                                        n.ctypes.data_as(C.POINTER(C.c_double)),
+                                        c.ctypes.data_as(C.POINTER(C.c_int64))), self._ctx)
+        kir = 2 * math.pi / (N * self.params.dx)
+        return dict(n=n, count=c, k=kir * np.arange(nb))
 
     def grad(self, nsteps: int, stride: int = 0, want_phi: bool = True, want_pi: bool = True,
              observable: str = "chi_fraction", field: int = 0, bin: int = 0) -> dict:

@@ -175,7 +175,7 @@ def test_step_chunking_is_invariant():
 
 def test_lf_sync_semantics():
     """Energy of a staggered leapfrog state uses synchronised momenta without
-    writing them; lattice_sync writes them (sec. 7.2 sync)."""
+    writing them; lattice_sync writes them (sec. 6.1 sync)."""
     from paper_2102_01031_amd.lattice import LatticeError, LAT_ESTATE
     wl = workloads.LPHI4_32
     N = 24

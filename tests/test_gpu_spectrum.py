@@ -1,13 +1,16 @@
-"""GPU power spectra (eq. discretePS, lattice_spectrum) against the oracle's
-own-DFT spectrum on the same evolved states, and the sum rule of eq.
-discretePSII on the GPU output."""
+"""GPU power spectra (eq. discretePS, lattice_spectrum) and lattice occupation
+numbers (eq. OccuppationNum, lattice_occupation) against the oracle's
+own-DFT versions.  The oracle's inputs are the seeded initial fields (rounded
+to float32 on the host for float32 lattices) or the oracle's own evolution of
+them; nothing it reads comes from the GPU.  The sum rule of eq. discretePSII
+is checked on the GPU output."""
 import math
 
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import gpu_scalar, say, scalar_kwargs
+from gpu_util import gpu_scalar, oracle_model, say, scalar_kwargs
 from paper_2102_01031_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -20,36 +23,108 @@ def _cuda():
         pytest.skip("no GPU")
 
 
-def check_spectrum(sp, f, dx):
+def host_values(arrs, precision):
+    """The values a lattice of this precision stores, made on the host."""
+    out = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in arrs]
+    if precision == "f32":
+        out = [a.astype(np.float32).astype(np.float64) for a in out]
+    return out
+
+
+def check_spectrum(sp, f, dx, tol):
     """Bins in max-norm relative to the largest bin (transform rounding scales
     with the largest modes, here the zero mode), the mode counts exactly, and
     the sum rule on the GPU output."""
     s, d, c = oracle.spectrum(f, dx, nbins=len(sp["sum"]))
     assert np.array_equal(sp["count"], c)
     rel = np.max(np.abs(sp["sum"] - s)) / s.max()
-    assert rel <= 1e-12, rel
+    assert rel <= tol, rel
     N = round(len(f) ** (1 / 3))
     kir = 2 * math.pi / (N * dx)
     lhs = sum(kir / (b * kir) * sp["delta"][b] for b in range(1, len(sp["delta"])))
     rhs = np.mean(f * f) - np.mean(f) ** 2
-    assert abs(lhs - rhs) <= 1e-10 * rhs, (lhs, rhs)
+    assert abs(lhs - rhs) <= max(1e-10, 10 * tol) * rhs, (lhs, rhs)
     return rel
 
 
 @pytest.mark.parametrize("N,precision", [(16, "f64"), (24, "f64"), (64, "f64"), (27, "f64"), (32, "f32")])
 def test_spectrum_matches_oracle(N, precision):
-    """Both fields, phi and pi, after three VV4 steps; float32 fields are widened
-    to float64 exactly, so the oracle gets the same values."""
+    """Both fields, phi and pi: at the initial state (1e-12), then after three
+    VV4 steps run on each side (float64 only; the evolutions agree to 1e-12,
+    so 1e-10 here)."""
     wl = workloads.PREHEAT_128
     phi, pi = wl.initial_fields(N=N)
     kw = scalar_kwargs(wl, N=N)
-    lat, tp, tq = gpu_scalar(kw, phi, pi, [3], precision=precision)
+    lat, _, _ = gpu_scalar(kw, phi, pi, [], precision=precision)
+    hp, hq = host_values(phi, precision), host_values(pi, precision)
     for field in (0, 1):
-        for arr, t in (("phi", tp), ("pi", tq)):
-            sp = lat.spectrum(field, arr)
-            f = t[field].double().cpu().numpy()       # the stored array, as the GPU holds it
-            rel = check_spectrum(sp, f, kw["dx"])
-            say(f"[spectrum] N={N} {precision} field {field} {arr}: max rel diff {rel:.2e}")
+        for arr, h in (("phi", hp), ("pi", hq)):
+            rel = check_spectrum(lat.spectrum(field, arr), h[field], kw["dx"], 1e-12)
+            say(f"[spectrum] N={N} {precision} initial field {field} {arr}: max rel diff {rel:.2e}")
+    if precision == "f64":
+        lat.step(3)
+        st = oracle.ScalarState(oracle_model(kw), phi, pi).run(3)
+        for field in (0, 1):
+            for arr, h in (("phi", st.phi), ("pi", st.pi)):
+                rel = check_spectrum(lat.spectrum(field, arr), h[field], kw["dx"], 1e-10)
+                say(f"[spectrum] N={N} after 3 VV4 steps field {field} {arr}: max rel diff {rel:.2e}")
     lat.close()
 
 
+def check_occupation(occ, model, a, b, phi, pi, field, fstar2, tol):
+    n, c = oracle.occupation(model, a, b, phi, pi, field, fstar2=fstar2, nbins=len(occ["n"]))
+    assert np.array_equal(occ["count"], c)
+    assert occ["n"][0] == 0.0
+    rel = np.max(np.abs(occ["n"] - n)) / np.max(np.abs(n))
+    assert rel <= tol, rel
+    return rel
+
+
+@pytest.mark.parametrize("N,expansion,precision", [(16, "self", "f64"), (27, "fixed", "f64"),
+                                                   (24, "none", "f64"), (32, "self", "f32")])
+def test_occupation_matches_oracle(N, expansion, precision):
+    """Both fields of the two-field model at the initial state (1e-12 relative
+    to the largest bin), then after three VV4 steps on each side (float64,
+    1e-10).  The oracle takes a and a' from its own clock."""
+    wl = workloads.PREHEAT_128
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N, expansion=expansion, t0=0.4, t_ref=0.0, H0=0.3)
+    if expansion == "fixed":
+        kw.update(w_eos=1 / 3)
+    lat, _, _ = gpu_scalar(kw, phi, pi, [], precision=precision)
+    m = oracle_model(kw)
+    st = oracle.ScalarState(m, host_values(phi, precision), host_values(pi, precision), t=kw["t0"])
+    for field in (0, 1):
+        rel = check_occupation(lat.occupation(field, fstar2=2.5), m, st.a, st.b, st.phi, st.pi, field, 2.5, 1e-12)
+        say(f"[occupation] N={N} {expansion} {precision} initial field {field}: a={st.a:.6f} a'={st.b:.6f} "
+            f"max rel diff {rel:.2e}")
+    if precision == "f64":
+        lat.step(3)
+        st.run(3)
+        for field in (0, 1):
+            rel = check_occupation(lat.occupation(field), m, st.a, st.b, st.phi, st.pi, field, 1.0, 1e-10)
+            say(f"[occupation] N={N} {expansion} after 3 VV4 steps field {field}: max rel diff {rel:.2e}")
+    lat.close()
+
+
+def test_occupation_leapfrog_needs_synced_momenta():
+    """Leapfrog momenta sit at the half step after a step: lattice_occupation
+    refuses them (LAT_ESTATE) until lattice_sync, then matches the oracle's
+    run and sync of the same steps."""
+    from paper_2102_01031_amd.lattice import LatticeError
+    wl = workloads.LPHI4_32
+    N = 16
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    lat, _, _ = gpu_scalar(kw, phi, pi, [7])
+    with pytest.raises(LatticeError):
+        lat.occupation(0)
+    lat.sync()
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(7)
+    st.sync()
+    rel = check_occupation(lat.occupation(0), oracle_model(kw), st.a, st.b, st.phi, st.pi, 0, 1.0, 1e-10)
+    say(f"[occupation] leapfrog N={N} after 7 steps and sync: max rel diff {rel:.2e}")
+    for bad in (dict(field=1), dict(nbins=0), dict(nbins=449), dict(fstar2=0.0)):
+        with pytest.raises(LatticeError):
+            lat.occupation(**bad)
+    lat.close()
