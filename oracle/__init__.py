@@ -68,13 +68,14 @@ def lib():
         L.orc_spectrum.argtypes = [C.c_int, C.c_double, dp, C.c_int, dp, dp, C.POINTER(C.c_long)]
         L.orc_occupation.argtypes = [C.POINTER(Params), C.c_double, C.c_double, pp, pp, C.c_int, C.c_double, C.c_int,
                                      dp, C.POINTER(C.c_long)]
-        L.orc_vv2_tangent.argtypes = [C.POINTER(Params), pp, pp, pp, pp, C.c_double]
-        L.orc_vv2_adjoint_step.argtypes = [C.POINTER(Params), pp, pp, pp, pp, dp]
+        L.orc_vv2_tangent.argtypes = [C.POINTER(Params), C.c_double, pp, pp, pp, pp, C.c_double]
+        L.orc_vv2_adjoint_step.argtypes = [C.POINTER(Params), C.c_double, pp, pp, pp, pp, dp]
         L.orc_observable.argtypes = [C.POINTER(Params), pp, pp, dp, pp, pp, dp]
         L.orc_adjoint_vv2.argtypes = [C.POINTER(Params), pp, pp, C.c_long, dp, pp, pp, dp]
-        L.orc_observable_kind.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.c_int, pp, pp, dp, pp, pp, dp]
-        L.orc_adjoint_vv2_kind.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.c_int, pp, pp, C.c_long, dp,
-                                           pp, pp, dp]
+        L.orc_observable_kind.argtypes = [C.POINTER(Params), C.c_double, C.c_int, C.c_int, C.c_int, pp, pp, dp, pp,
+                                          pp, dp]
+        L.orc_adjoint_vv2_kind.argtypes = [C.POINTER(Params), C.c_double, C.c_int, C.c_int, C.c_int, pp, pp,
+                                           C.c_long, dp, pp, pp, dp]
         L.orc_u1_forces.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp]
         L.orc_u1_energy.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), dp]
         L.orc_u1_gauss.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, dp]
@@ -247,17 +248,18 @@ def triple_jump(n):
 # adjoint (two fields, VV2, a = 1)
 # ----------------------------------------------------------------------------
 
-def vv2_tangent(model: ScalarModel, phi, pi, dphi, dpi, dq=0.0):
-    """Advance (phi, pi) and the tangent (dphi, dpi) by one VV2 step in place."""
+def vv2_tangent(model: ScalarModel, phi, pi, dphi, dpi, dq=0.0, t=0.0):
+    """Advance (phi, pi) and the tangent (dphi, dpi) by one VV2 step from time t in place."""
     p = model.cparams()
-    _chk(lib().orc_vv2_tangent(C.byref(p), _pp(phi), _pp(pi), _pp(dphi), _pp(dpi), dq), "tangent")
+    _chk(lib().orc_vv2_tangent(C.byref(p), float(t), _pp(phi), _pp(pi), _pp(dphi), _pp(dpi), dq), "tangent")
 
 
-def vv2_adjoint_step(model: ScalarModel, phi_n, pi_n, lphi, lpi) -> float:
-    """Pull (lphi, lpi) back through one VV2 step from state (phi_n, pi_n); returns dq."""
+def vv2_adjoint_step(model: ScalarModel, phi_n, pi_n, lphi, lpi, t=0.0) -> float:
+    """Pull (lphi, lpi) back through one VV2 step from state (phi_n, pi_n) at
+    time t; returns dq."""
     p = model.cparams()
     dq = C.c_double(0.0)
-    _chk(lib().orc_vv2_adjoint_step(C.byref(p), _pp(phi_n), _pp(pi_n), _pp(lphi), _pp(lpi),
+    _chk(lib().orc_vv2_adjoint_step(C.byref(p), float(t), _pp(phi_n), _pp(pi_n), _pp(lphi), _pp(lpi),
                                     C.byref(dq)), "adjoint_step")
     return dq.value
 
@@ -268,32 +270,34 @@ OBS_CHI_FRACTION = 0
 OBS_SPECTRUM_BIN = 1
 
 
-def observable(model: ScalarModel, phi, pi, with_grad=False, kind=OBS_CHI_FRACTION, field=0, bin=0):
+def observable(model: ScalarModel, phi, pi, with_grad=False, kind=OBS_CHI_FRACTION, field=0, bin=0, a=1.0):
+    """Observable `kind` of the state at scale factor a (and its gradient)."""
     p = model.cparams()
     O = C.c_double()
     if not with_grad:
         null = C.cast(None, C.POINTER(C.POINTER(C.c_double)))
-        _chk(lib().orc_observable_kind(C.byref(p), kind, field, bin, _pp(phi), _pp(pi), C.byref(O), null, null,
-                                       None), "obs")
+        _chk(lib().orc_observable_kind(C.byref(p), float(a), kind, field, bin, _pp(phi), _pp(pi), C.byref(O), null,
+                                       null, None), "obs")
         return O.value
     g = [np.zeros_like(phi[0]) for _ in range(2)]
     gp = [np.zeros_like(phi[0]) for _ in range(2)]
     dq = C.c_double()
-    _chk(lib().orc_observable_kind(C.byref(p), kind, field, bin, _pp(phi), _pp(pi), C.byref(O), _pp(g), _pp(gp),
-                                   C.byref(dq)), "obs")
+    _chk(lib().orc_observable_kind(C.byref(p), float(a), kind, field, bin, _pp(phi), _pp(pi), C.byref(O), _pp(g),
+                                   _pp(gp), C.byref(dq)), "obs")
     return O.value, g, gp, dq.value
 
 
-def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int, kind=OBS_CHI_FRACTION, field=0, bin=0):
-    """O(final), dO/dphi(0) per field, dO/dpi(0) per field, dO/dq."""
+def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int, kind=OBS_CHI_FRACTION, field=0, bin=0, t=0.0):
+    """O(final), dO/dphi(0) per field, dO/dpi(0) per field, dO/dq, for nsteps
+    VV2 steps from time t (a = 1, or the fixed background a(t))."""
     phi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in phi0]
     pi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in pi0]
     g = [np.zeros_like(phi0[0]) for _ in range(2)]
     gp = [np.zeros_like(phi0[0]) for _ in range(2)]
     O, dq = C.c_double(), C.c_double()
     p = model.cparams()
-    _chk(lib().orc_adjoint_vv2_kind(C.byref(p), kind, field, bin, _pp(phi0), _pp(pi0), int(nsteps), C.byref(O),
-                                    _pp(g), _pp(gp), C.byref(dq)), "adjoint_vv2")
+    _chk(lib().orc_adjoint_vv2_kind(C.byref(p), float(t), kind, field, bin, _pp(phi0), _pp(pi0), int(nsteps),
+                                    C.byref(O), _pp(g), _pp(gp), C.byref(dq)), "adjoint_vv2")
     return O.value, g, gp, dq.value
 
 

@@ -31,7 +31,7 @@
  *       drift uses a(t) at the midpoint time of the drift (closed form of
  *       eq. ScaleFactorPowerLaw).
  *   R4  leapfrog energies are measured on momenta synchronised to integer
- *       time by a half kick that is not written back (sec. 7.2 describes the
+ *       time by a half kick that is not written back (sec. 6.1 describes the
  *       sync before measurements).
  *   R5  U(1): compact formulation of the U(1) toolkit (sec. 3.2) with the
  *       plaquette V_i V_{j,+i} V*_{i,+j} V*_j and kicks equal to minus the
@@ -430,7 +430,7 @@ int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_cloc
     return 0;
 }
 
-/* Leapfrog sync (sec. 7.2): bring staggered momenta to integer time, in place. */
+/* Leapfrog sync (sec. 6.1): bring staggered momenta to integer time, in place. */
 int orc_lf_sync(const orc_params *p, double *const *phi, double *const *pi, orc_clock *c)
 {
     if (c->lf_stag == 0) return 0;
@@ -484,15 +484,22 @@ int orc_energy(const orc_params *p, double *const *phi, double *const *pi, const
 }
 
 /* ------------------------------------------------------------------ */
-/* Adjoint of the second-order velocity-Verlet map, a = 1, two fields   */
-/* with V = lambda/4 phi^4 + q/2 phi^2 chi^2.                            */
-/*   forward: pi' = pi + h/2 F(phi); phi' = phi + h pi'; pi'' = pi' + h/2 F(phi') */
-/*   F(phi) = Lap phi - grad V(phi);  dF = Lap - H_V(phi)  (symmetric)   */
+/* Adjoint of the second-order velocity-Verlet map, two fields with     */
+/* V = lambda/4 phi^4 + q/2 phi^2 chi^2, a = 1 or a fixed background a(t) */
+/* (reading R3: kicks at a(t) of the kick, drifts at a(t + h/2)).        */
+/*   forward: pi' = pi + h/2 K(a_n, phi); phi' = phi + h d pi';          */
+/*            pi'' = pi' + h/2 K(a_n+1, phi')                            */
+/*   K(a, phi) = kL Lap phi - kV grad V(phi), kL = a^{1+alpha},           */
+/*   kV = a^{3+alpha}, d = a(t + h/2)^{alpha-3};                          */
+/*   dK = kL Lap - kV H_V(phi)  (symmetric)                               */
 /* ------------------------------------------------------------------ */
 
-/* out_s = Lap(l_s) - sum_r H_V(phi)_{sr} l_r  (transpose of dF, which is symmetric) */
+/* scale factor of the adjoint's background at time t */
+static double adj_a(const orc_params *p, double t) { return p->expansion == ORC_FIXED ? fixed_a(p, t) : 1.0; }
+
+/* out_s = kL Lap(l_s) - kV sum_r H_V(phi)_{sr} l_r  (transpose of dK, which is symmetric) */
 static void jac_F_T(const orc_params *p, double *const *phi, double *const *l, double **out,
-                    double *lap)
+                    double *lap, double kL, double kV)
 {
     size_t V = vol(p->N);
     for (int s = 0; s < 2; ++s) {
@@ -503,12 +510,13 @@ static void jac_F_T(const orc_params *p, double *const *phi, double *const *l, d
             double h01 = 2.0 * p->q * f * x;                         /* d2V/dphidchi */
             double h11 = p->q * f * f;                               /* d2V/dchi2   */
             double hl = s == 0 ? h00 * l[0][n] + h01 * l[1][n] : h01 * l[0][n] + h11 * l[1][n];
-            out[s][n] = lap[n] - hl;
+            out[s][n] = kL * lap[n] - kV * hl;
         }
     }
 }
 
-/* sum_n l(n) . dF/dq(phi(n)),  dF/dq = -(phi chi^2, phi^2 chi) */
+/* sum_n l(n) . dF/dq(phi(n)) at a = 1,  dF/dq = -(phi chi^2, phi^2 chi); a kick
+ * at scale factor a scales it by kV */
 static double dot_dFdq(const orc_params *p, double *const *phi, double *const *l)
 {
     nsum k = {0, 0};
@@ -523,28 +531,31 @@ static double dot_dFdq(const orc_params *p, double *const *phi, double *const *l
 
 static int check_adj(const orc_params *p)
 {
-    if (p->nfields != 2 || p->potential != ORC_PHI4_CHI2 || p->expansion != ORC_NONE) return -2;
+    if (p->nfields != 2 || p->potential != ORC_PHI4_CHI2 || p->expansion == ORC_SELF) return -2;
     return 0;
 }
 
-/* One VV2 step of the state (phi, pi) together with its tangent (dphi, dpi)
- * along an extra coupling direction dq. All arrays are updated in place. */
-int orc_vv2_tangent(const orc_params *p, double *const *phi, double *const *pi,
+/* One VV2 step from time t of the state (phi, pi) together with its tangent
+ * (dphi, dpi) along an extra coupling direction dq. All arrays are updated in place. */
+int orc_vv2_tangent(const orc_params *p, double t, double *const *phi, double *const *pi,
                     double *const *dphi, double *const *dpi, double dq)
 {
     if (check_adj(p)) return -2;
     size_t V = vol(p->N);
-    double h = p->dt;
+    double h = p->dt, al = p->alpha;
+    double ak[2] = {adj_a(p, t), adj_a(p, t + h)};
+    double dr = h * pow(adj_a(p, t + 0.5 * h), al - 3.0);
     double *lap = (double *)malloc(V * sizeof(double));
     double *J[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
     double *K[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
     for (int half = 0; half < 2; ++half) {
-        /* kick at the current position: pi += h/2 F(phi); dpi += h/2 (dF dphi + dF/dq dq) */
-        jac_F_T(p, phi, dphi, J, lap);  /* dF symmetric: dF dphi = dF^T dphi */
-        for (int s = 0; s < 2; ++s) kernel_field(p, 1.0, phi, s, K[s]);
+        /* kick at the current position: pi += h/2 K(phi); dpi += h/2 (dK dphi + dK/dq dq) */
+        double kL = pow(ak[half], 1.0 + al), kV = pow(ak[half], 3.0 + al);
+        jac_F_T(p, phi, dphi, J, lap, kL, kV);  /* dK symmetric: dK dphi = dK^T dphi */
+        for (int s = 0; s < 2; ++s) kernel_field(p, ak[half], phi, s, K[s]);
         for (size_t n = 0; n < V; ++n) {
             double f = phi[0][n], x = phi[1][n];
-            double dFq0 = -f * x * x, dFq1 = -f * f * x;
+            double dFq0 = -kV * f * x * x, dFq1 = -kV * f * f * x;
             pi[0][n] += 0.5 * h * K[0][n];
             pi[1][n] += 0.5 * h * K[1][n];
             dpi[0][n] += 0.5 * h * (J[0][n] + dFq0 * dq);
@@ -553,8 +564,8 @@ int orc_vv2_tangent(const orc_params *p, double *const *phi, double *const *pi,
         if (half == 0) {
             for (int s = 0; s < 2; ++s)
                 for (size_t n = 0; n < V; ++n) {
-                    phi[s][n] += h * pi[s][n];
-                    dphi[s][n] += h * dpi[s][n];
+                    phi[s][n] += dr * pi[s][n];
+                    dphi[s][n] += dr * dpi[s][n];
                 }
         }
     }
@@ -562,20 +573,23 @@ int orc_vv2_tangent(const orc_params *p, double *const *phi, double *const *pi,
     return 0;
 }
 
-/* Pull the adjoint (lphi, lpi) of the state after one VV2 step back to the
- * state before it.  (phi_n, pi_n) is the state before the step (unchanged).
- * *dq accumulates the coupling sensitivity of the step. */
-int orc_vv2_adjoint_step(const orc_params *p, double *const *phi_n, double *const *pi_n,
+/* Pull the adjoint (lphi, lpi) of the state after one VV2 step from time t
+ * back to the state before it.  (phi_n, pi_n) is the state before the step
+ * (unchanged).  *dq accumulates the coupling sensitivity of the step. */
+int orc_vv2_adjoint_step(const orc_params *p, double t, double *const *phi_n, double *const *pi_n,
                          double *const *lphi, double *const *lpi, double *dq)
 {
     if (check_adj(p)) return -2;
     size_t V = vol(p->N);
-    double h = p->dt;
+    double h = p->dt, al = p->alpha;
+    double a0 = adj_a(p, t), a1 = adj_a(p, t + h), am = adj_a(p, t + 0.5 * h);
+    double kL0 = pow(a0, 1.0 + al), kV0 = pow(a0, 3.0 + al), kL1 = pow(a1, 1.0 + al), kV1 = pow(a1, 3.0 + al);
+    double dr = h * pow(am, al - 3.0);
     double *lap = (double *)malloc(V * sizeof(double));
     double *J[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
     double *ph1[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
     double *pi1[2] = {(double *)malloc(V * sizeof(double)), (double *)malloc(V * sizeof(double))};
-    /* positions after the step: phi_{n+1} = phi_n + h (pi_n + h/2 F(phi_n)) */
+    /* positions after the step: phi_{n+1} = phi_n + h d (pi_n + h/2 K(a_n, phi_n)) */
     for (int s = 0; s < 2; ++s) {
         memcpy(ph1[s], phi_n[s], V * sizeof(double));
         memcpy(pi1[s], pi_n[s], V * sizeof(double));
@@ -583,20 +597,20 @@ int orc_vv2_adjoint_step(const orc_params *p, double *const *phi_n, double *cons
     {
         stepper st;
         st.p = p; st.phi = ph1; st.pi = pi1; st.K[0] = J[0]; st.K[1] = J[1];
-        kick(&st, 1.0, 0.5 * h);
-        drift(&st, 1.0, h);
+        kick(&st, a0, 0.5 * h);
+        drift(&st, am, h);
     }
-    /* second half kick: lphi += h/2 dF(phi_{n+1})^T lpi */
-    *dq += 0.5 * h * dot_dFdq(p, ph1, lpi);
-    jac_F_T(p, ph1, lpi, J, lap);
+    /* second half kick: lphi += h/2 dK(a_{n+1}, phi_{n+1})^T lpi */
+    *dq += 0.5 * h * kV1 * dot_dFdq(p, ph1, lpi);
+    jac_F_T(p, ph1, lpi, J, lap, kL1, kV1);
     for (int s = 0; s < 2; ++s)
         for (size_t n = 0; n < V; ++n) lphi[s][n] += 0.5 * h * J[s][n];
-    /* drift: lpi += h lphi */
+    /* drift: lpi += h d lphi */
     for (int s = 0; s < 2; ++s)
-        for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];
-    /* first half kick: lphi += h/2 dF(phi_n)^T lpi */
-    *dq += 0.5 * h * dot_dFdq(p, phi_n, lpi);
-    jac_F_T(p, phi_n, lpi, J, lap);
+        for (size_t n = 0; n < V; ++n) lpi[s][n] += dr * lphi[s][n];
+    /* first half kick: lphi += h/2 dK(a_n, phi_n)^T lpi */
+    *dq += 0.5 * h * kV0 * dot_dFdq(p, phi_n, lpi);
+    jac_F_T(p, phi_n, lpi, J, lap, kL0, kV0);
     for (int s = 0; s < 2; ++s)
         for (size_t n = 0; n < V; ++n) lphi[s][n] += 0.5 * h * J[s][n];
     free(lap); free(J[0]); free(J[1]);
@@ -604,13 +618,15 @@ int orc_vv2_adjoint_step(const orc_params *p, double *const *phi_n, double *cons
     return 0;
 }
 
-/* Observable: fraction of the energy in chi, O = (E_K^chi + E_G^chi)/rho (a = 1).
- * Writes O and, if seeds are given, dO/dphi_s(n), dO/dpi_s(n) and the explicit dO/dq. */
-static double observable(const orc_params *p, double *const *phi, double *const *pi,
+/* Observable: fraction of the energy in chi, O = (E_K^chi + E_G^chi)/rho at
+ * scale factor a (E_K = <pi^2>/(2 a^6), E_G = <|grad phi|^2>/(2 a^2)).  Writes O
+ * and, if seeds are given, dO/dphi_s(n), dO/dpi_s(n) and the explicit dO/dq. */
+static double observable(const orc_params *p, double a, double *const *phi, double *const *pi,
                          double **gphi, double **gpi, double *dOdq_explicit)
 {
     size_t V = vol(p->N);
-    energies E = energies_of(p, phi, pi, 1.0);
+    energies E = energies_of(p, phi, pi, a);
+    const double ia2 = 1.0 / (a * a), ia6 = ia2 * ia2 * ia2;
     double rho = rho_tot(&E);
     double X = E.EK[1] + E.EG[1];
     double O = X / rho;
@@ -622,11 +638,11 @@ static double observable(const orc_params *p, double *const *phi, double *const 
             orc_laplacian(p->N, p->dx, phi[s], lap);
             for (size_t n = 0; n < V; ++n) {
                 double dV = pot_deriv(p, s, phi[0][n], phi[1][n]);
-                /* dE_G^s/dphi_s(n) = -Lap phi_s / V ; dE_V/dphi_s = dV/dphi_s / V */
-                double dX = wX * (-lap[n]);
-                double drho = -lap[n] + dV;
+                /* dE_G^s/dphi_s(n) = -Lap phi_s / (a^2 V) ; dE_V/dphi_s = dV/dphi_s / V */
+                double dX = wX * (-lap[n]) * ia2;
+                double drho = -lap[n] * ia2 + dV;
                 gphi[s][n] = (dX - O * drho) * inv;
-                gpi[s][n] = (wX * pi[s][n] - O * pi[s][n]) * inv;
+                gpi[s][n] = (wX * pi[s][n] - O * pi[s][n]) * ia6 * inv;
             }
         }
         free(lap);
@@ -642,7 +658,7 @@ int orc_observable(const orc_params *p, double *const *phi, double *const *pi, d
 {
     if (check_adj(p)) return -2;
     double d = 0.0;
-    *O = observable(p, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
+    *O = observable(p, 1.0, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
     if (dOdq) *dOdq = d;
     return 0;
 }
@@ -650,15 +666,15 @@ int orc_observable(const orc_params *p, double *const *phi, double *const *pi, d
 /* Observables the reverse sweep can start from: the chi energy fraction above,
  * or one bin of the power spectrum of one field (defined with the spectrum). */
 enum { ORC_OBS_CHI_FRACTION = 0, ORC_OBS_SPECTRUM_BIN = 1 };
-static double observable_kind(const orc_params *p, int kind, int field, int bin, double *const *phi,
+static double observable_kind(const orc_params *p, double a, int kind, int field, int bin, double *const *phi,
                               double *const *pi, double **gphi, double **gpi, double *dq);
 
 /* Gradient of O(final state) of observable `kind` with respect to the initial
- * phi, pi and q for nsteps VV2 steps, by reverse sweep with segment
- * recomputation: checkpoints every ceil(sqrt(nsteps)) steps, each segment re-run
- * forward from its checkpoint and stored, then pulled back step by step. */
-
-int orc_adjoint_vv2_kind(const orc_params *p, int kind, int field, int bin, double *const *phi0,
+ * phi, pi and q for nsteps VV2 steps from time t_start, by reverse sweep with
+ * segment recomputation: checkpoints every ceil(sqrt(nsteps)) steps, each
+ * segment re-run forward from its checkpoint and stored, then pulled back step
+ * by step. */
+int orc_adjoint_vv2_kind(const orc_params *p, double t_start, int kind, int field, int bin, double *const *phi0,
                          double *const *pi0, long nsteps, double *O_out, double *const *gphi, double *const *gpi,
                          double *dOdq)
 {
@@ -681,13 +697,15 @@ int orc_adjoint_vv2_kind(const orc_params *p, int kind, int field, int bin, doub
         if (n % k == 0)
             for (int i = 0; i < 4; ++i) memcpy(cp + ((size_t)(n / k) * 4 + i) * V, cur[i], B);
         if (n == nsteps) break;
-        orc_clock c = {0, 1, 0, 0, 0};
+        double tn = t_start + (double)n * p->dt;
+        orc_clock c = {tn, adj_a(p, tn), 0, 0, 0};
         orc_run(&pv, cur, cur + 2, &c, 1);
     }
     /* seed at the final state */
     double *lphi[2] = {gphi[0], gphi[1]}, *lpi[2] = {gpi[0], gpi[1]};
     double q_acc = 0.0;
-    *O_out = observable_kind(p, kind, field, bin, cur, cur + 2, lphi, lpi, &q_acc);
+    *O_out = observable_kind(p, adj_a(p, t_start + (double)nsteps * p->dt), kind, field, bin, cur, cur + 2, lphi,
+                             lpi, &q_acc);
     /* segment states: positions and momenta at steps s0..s1 */
     double *seg = (double *)malloc((size_t)(k + 1) * 4 * B);
     for (long s0 = ((nsteps - 1) / k) * k; nsteps > 0 && s0 >= 0; s0 -= k) {
@@ -695,13 +713,14 @@ int orc_adjoint_vv2_kind(const orc_params *p, int kind, int field, int bin, doub
         for (int i = 0; i < 4; ++i) memcpy(cur[i], cp + ((size_t)(s0 / k) * 4 + i) * V, B);
         for (long n = s0; n < s1; ++n) {
             for (int i = 0; i < 4; ++i) memcpy(seg + ((size_t)(n - s0) * 4 + i) * V, cur[i], B);
-            orc_clock c = {0, 1, 0, 0, 0};
+            double tn = t_start + (double)n * p->dt;
+            orc_clock c = {tn, adj_a(p, tn), 0, 0, 0};
             orc_run(&pv, cur, cur + 2, &c, 1);
         }
         for (long n = s1 - 1; n >= s0; --n) {
             double *sp[2] = {seg + ((size_t)(n - s0) * 4 + 0) * V, seg + ((size_t)(n - s0) * 4 + 1) * V};
             double *sm[2] = {seg + ((size_t)(n - s0) * 4 + 2) * V, seg + ((size_t)(n - s0) * 4 + 3) * V};
-            orc_vv2_adjoint_step(p, sp, sm, lphi, lpi, &q_acc);
+            orc_vv2_adjoint_step(p, t_start + (double)n * p->dt, sp, sm, lphi, lpi, &q_acc);
         }
     }
     *dOdq = q_acc;
@@ -714,7 +733,7 @@ int orc_adjoint_vv2_kind(const orc_params *p, int kind, int field, int bin, doub
 int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0, long nsteps,
                     double *O_out, double *const *gphi, double *const *gpi, double *dOdq)
 {
-    return orc_adjoint_vv2_kind(p, 0, 0, 0, phi0, pi0, nsteps, O_out, gphi, gpi, dOdq);
+    return orc_adjoint_vv2_kind(p, 0.0, 0, 0, 0, phi0, pi0, nsteps, O_out, gphi, gpi, dOdq);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1101,10 +1120,10 @@ static double spectrum_bin_value(int N, double dx, const double *f, int bin, dou
 /* Observable `kind` of the state and its gradient (seed of the adjoint):
  * ORC_OBS_CHI_FRACTION as orc_observable; ORC_OBS_SPECTRUM_BIN: Delta(bin) of
  * phi_field, gradient in gphi[field] only, no explicit q dependence. */
-static double observable_kind(const orc_params *p, int kind, int field, int bin, double *const *phi,
+static double observable_kind(const orc_params *p, double a, int kind, int field, int bin, double *const *phi,
                               double *const *pi, double **gphi, double **gpi, double *dq)
 {
-    if (kind == ORC_OBS_CHI_FRACTION) return observable(p, phi, pi, gphi, gpi, dq);
+    if (kind == ORC_OBS_CHI_FRACTION) return observable(p, a, phi, pi, gphi, gpi, dq);
     size_t V = vol(p->N);
     for (int s = 0; s < 2; ++s) {
         if (gphi) memset(gphi[s], 0, V * sizeof(double));
@@ -1114,14 +1133,15 @@ static double observable_kind(const orc_params *p, int kind, int field, int bin,
     return spectrum_bin_value(p->N, p->dx, phi[field], bin, gphi ? gphi[field] : NULL);
 }
 
-int orc_observable_kind(const orc_params *p, int kind, int field, int bin, double *const *phi, double *const *pi,
-                        double *O, double *const *gphi, double *const *gpi, double *dOdq)
+int orc_observable_kind(const orc_params *p, double a, int kind, int field, int bin, double *const *phi,
+                        double *const *pi, double *O, double *const *gphi, double *const *gpi, double *dOdq)
 {
     if (check_adj(p)) return -2;
     if (kind != ORC_OBS_CHI_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
     if (kind == ORC_OBS_SPECTRUM_BIN && (field < 0 || field > 1 || bin < 1)) return -1;
     double d = 0.0;
-    *O = observable_kind(p, kind, field, bin, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
+    if (!(a > 0.0)) return -1;
+    *O = observable_kind(p, a, kind, field, bin, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
     if (dOdq) *dOdq = d;
     return 0;
 }

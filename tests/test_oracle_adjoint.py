@@ -197,3 +197,103 @@ def test_spectrum_bin_rejects_bad_selection(orc):
     for field, b in ((2, 1), (-1, 1), (0, 0)):
         with pytest.raises(RuntimeError):
             orc.observable(m, phi, pi, kind=orc.OBS_SPECTRUM_BIN, field=field, bin=b)
+
+
+# Fixed background a(t) (power law, reading R3): kicks at a of the kick time,
+# drifts at a of the drift midpoint.
+
+def fixed_model(orc, N=5, dt=0.02, q=30.0, alpha=1.0):
+    return orc.ScalarModel(N=N, dx=0.4, dt=dt, nfields=2, potential=orc.PHI4_CHI2, lam=1.0, q=q, alpha=alpha,
+                           expansion=orc.FIXED, w_eos=1 / 3, H0=2.0, t0=0.0, a0=1.0, integrator=orc.VV2)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_fixed_background_dot_product_and_tangent(orc, alpha):
+    N, t = 4, 0.3
+    m = fixed_model(orc, N, alpha=alpha)
+    assert orc.fixed_background(m, t)[0] > 1.3   # the background really moves
+    phi, pi = state(N, 4)
+    rng = np.random.default_rng(5)
+    v = [rng.standard_normal(N ** 3) for _ in range(4)]
+    w = [rng.standard_normal(N ** 3) for _ in range(4)]
+    dq = 0.4
+    ph, pp = [f.copy() for f in phi], [f.copy() for f in pi]
+    dph, dpp = [v[0].copy(), v[1].copy()], [v[2].copy(), v[3].copy()]
+    orc.vv2_tangent(m, ph, pp, dph, dpp, dq, t=t)
+    lhs = sum(np.dot(a, b) for a, b in zip(dph + dpp, w))
+    lph, lpp = [w[0].copy(), w[1].copy()], [w[2].copy(), w[3].copy()]
+    gq = orc.vv2_adjoint_step(m, phi, pi, lph, lpp, t=t)
+    rhs = sum(np.dot(a, b) for a, b in zip(lph + lpp, v)) + dq * gq
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    # tangent against central differences of the nonlinear step from time t
+    eps = 1e-6
+
+    def step(sign):
+        mm = fixed_model(orc, N, q=m.q + sign * eps * dq, alpha=alpha)
+        st = orc.ScalarState(mm, [phi[0] + sign * eps * v[0], phi[1] + sign * eps * v[1]],
+                             [pi[0] + sign * eps * v[2], pi[1] + sign * eps * v[3]], t=t)
+        st.run(1)
+        return st.phi + st.pi
+
+    fp, fm = step(1), step(-1)
+    for a, b, c in zip(fp, fm, dph + dpp):
+        assert np.max(np.abs((a - b) / (2 * eps) - c)) < 1e-6 * max(1, np.max(np.abs(c)))
+    # the nonlinear step of the tangent routine is the integrator's own step
+    st = orc.ScalarState(m, phi, pi, t=t).run(1)
+    for a, b in zip(ph + pp, st.phi + st.pi):
+        assert np.array_equal(a, b)
+
+
+def test_observable_seed_at_scale_factor(orc):
+    N, a = 4, 1.6
+    m = fixed_model(orc, N)
+    phi, pi = state(N, 6)
+    O, g, gp, dq = orc.observable(m, phi, pi, with_grad=True, a=a)
+    # the value is the chi share of the energies the integrator reports where
+    # the background has this scale factor (radiation, H0 = 2: a = 1 + 2t)
+    E = orc.ScalarState(m, phi, pi, t=0.3).energy()
+    assert abs(E["a"] - a) <= 1e-14
+    assert abs(O - (E["EK"][1] + E["EG"][1]) / E["rho"]) <= 1e-14 * O
+    eps = 1e-6
+    for s in range(2):
+        for site in (0, 21, 63):
+            for arr, grad in ((phi, g), (pi, gp)):
+                p_ = [f.copy() for f in arr]; m_ = [f.copy() for f in arr]
+                p_[s][site] += eps; m_[s][site] -= eps
+                if arr is phi:
+                    fd = (orc.observable(m, p_, pi, a=a) - orc.observable(m, m_, pi, a=a)) / (2 * eps)
+                else:
+                    fd = (orc.observable(m, phi, p_, a=a) - orc.observable(m, phi, m_, a=a)) / (2 * eps)
+                assert abs(fd - grad[s][site]) < 1e-8 * max(1e-3, abs(fd))
+    assert O != orc.observable(m, phi, pi, a=1.0)
+
+
+@pytest.mark.parametrize("kind,alpha", [("chi", 1.0), ("chi", 0.5), ("bin", 1.0)])
+def test_fixed_background_reverse_sweep_vs_finite_differences(orc, kind, alpha):
+    N, nsteps, t0 = 5, 20, 0.25
+    m = fixed_model(orc, N, alpha=alpha)
+    phi, pi = state(N, 12)
+    kw = dict(kind=orc.OBS_SPECTRUM_BIN, field=1, bin=2) if kind == "bin" else {}
+    O, g, gp, dq = orc.adjoint_vv2(m, phi, pi, nsteps, t=t0, **kw)
+    aT = orc.fixed_background(m, t0 + nsteps * m.dt)[0]
+
+    def O_of(phi_, pi_, q_):
+        mm = fixed_model(orc, N, q=q_, alpha=alpha)
+        st = orc.ScalarState(mm, phi_, pi_, t=t0).run(nsteps)
+        return orc.observable(mm, st.phi, st.pi, a=aT, **kw)
+
+    assert abs(O - O_of(phi, pi, m.q)) <= 1e-13 * abs(O)
+    rng = np.random.default_rng(19)
+    for _ in range(3):
+        v = [rng.standard_normal(N ** 3) for _ in range(4)]
+        vq = rng.standard_normal()
+        nrm = np.sqrt(sum(np.dot(a, a) for a in v) + vq * vq)
+        v = [a / nrm for a in v]
+        vq /= nrm
+        eps = 1e-5
+        fp = O_of([phi[0] + eps * v[0], phi[1] + eps * v[1]], [pi[0] + eps * v[2], pi[1] + eps * v[3]], m.q + eps * vq)
+        fm = O_of([phi[0] - eps * v[0], phi[1] - eps * v[1]], [pi[0] - eps * v[2], pi[1] - eps * v[3]], m.q - eps * vq)
+        fd = (fp - fm) / (2 * eps)
+        ad = np.dot(g[0], v[0]) + np.dot(g[1], v[1]) + np.dot(gp[0], v[2]) + np.dot(gp[1], v[3]) + dq * vq
+        scale = np.sqrt(sum(np.dot(a, a) for a in g + gp) + dq * dq)
+        assert abs(fd - ad) <= 1e-6 * scale

@@ -54,8 +54,15 @@ MUTANTS = [
      "test_oracle_occupation.py"),
     ("occupation cross-coupling mass", "if (p->potential == ORC_PHI4_CHI2) d += p->q * w * w;", "",
      "test_oracle_occupation.py"),
-    ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += h * lphi[s][n];",
-     "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * h * lphi[s][n];", "test_oracle_adjoint.py"),
+    ("fixed-background adjoint drift at the kick time", "double dr = h * pow(am, al - 3.0);",
+     "double dr = h * pow(a0, al - 3.0);", "test_oracle_adjoint.py"),
+    ("fixed-background second adjoint kick at a_n", "jac_F_T(p, ph1, lpi, J, lap, kL1, kV1);",
+     "jac_F_T(p, ph1, lpi, J, lap, kL0, kV0);", "test_oracle_adjoint.py"),
+    ("coupling sensitivity without the potential factor", "*dq += 0.5 * h * kV1 * dot_dFdq(p, ph1, lpi);",
+     "*dq += 0.5 * h * dot_dFdq(p, ph1, lpi);", "test_oracle_adjoint.py"),
+    ("observable kinetic power of a", "ia6 = ia2 * ia2 * ia2;", "ia6 = ia2 * ia2;", "test_oracle_adjoint.py"),
+    ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += dr * lphi[s][n];",
+     "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * dr * lphi[s][n];", "test_oracle_adjoint.py"),
 ]
 
 
