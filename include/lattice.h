@@ -260,7 +260,10 @@ typedef struct lat_grad_out {
  * T, and a reverse sweep that integrates the state backward together with the
  * adjoint, re-anchoring the state at every stored checkpoint.  On return the
  * fields hold their initial values again.  Provided for LAT_PHI4_CHI2 with
- * LAT_VV2, LAT_EXP_NONE and LAT_PREC_F64 (LAT_EUNSUPPORTED otherwise).  The
+ * LAT_VV2, LAT_PREC_F64 and LAT_EXP_NONE or LAT_EXP_FIXED (LAT_EUNSUPPORTED
+ * otherwise).  On a fixed background the steps run from the context's current
+ * time, kicks use a^{1+alpha} and a^{3+alpha} at the kick time, drifts
+ * a^{alpha-3} at the midpoint, and the energies of O are those at a(T).  The
  * library allocates the checkpoints (T/stride + 1 copies of the state) and the
  * adjoint arrays on first use and keeps them until lattice_destroy.
  * LAT_OBS_SPECTRUM_BIN seeds the adjoint with dDelta(b)/dphi_s: the

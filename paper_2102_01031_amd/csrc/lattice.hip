@@ -1481,8 +1481,8 @@ namespace {
 
 constexpr int kAdjTX = 64, kAdjTY = 4;
 
-lat_status adj_pass(lat_ctx *c, double dphi, double dlam, double cA, double cB, int nb, int zc, int tiles_x,
-                    int tiles_y)
+lat_status adj_pass(lat_ctx *c, double dphi, double dlam, double cA, double cB, double kL, double kV, int nb, int zc,
+                    int tiles_x, int tiles_y)
 {
     AdjArgs a{};
     for (int f = 0; f < 2; ++f) {
@@ -1508,6 +1508,8 @@ lat_status adj_pass(lat_ctx *c, double dphi, double dlam, double cA, double cB, 
     a.dlam = dlam;
     a.cA = cA;
     a.cB = cB;
+    a.kL = kL;
+    a.kV = kV;
     a.partials = c->adj_partials;
     a.ticket = c->ticket;
     a.dq_acc = &c->sc->sums[kMaxQ - 1];
@@ -1559,8 +1561,9 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     if (spec->observable != LAT_OBS_CHI_ENERGY_FRACTION && !spec_obs)
         return fail(c, LAT_EINVAL, "unknown observable");
     if (c->batch || c->u1 || c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 ||
-        c->p.expansion != LAT_EXP_NONE || c->f32)
-        return fail(c, LAT_EUNSUPPORTED, "lattice_grad needs two fields, VV2, no expansion and float64");
+        c->p.expansion == LAT_EXP_SELF || c->f32)
+        return fail(c, LAT_EUNSUPPORTED,
+                    "lattice_grad needs two fields, VV2, no or a fixed expansion, and float64");
     if (spec->reserved != 0) return fail(c, LAT_EINVAL, "reserved field of lat_grad_spec must be 0");
     if (spec_obs) {
         const long h2 = (long)(c->N / 2) * (c->N / 2);
@@ -1636,17 +1639,24 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
         }                                 \
     } while (0)
 
-    const double h = c->p.dt;
+    const double h = c->p.dt, al = c->p.alpha, t_start = c->t;
+    // background factors at kick point p (time t_p = t_start + p h) and of the
+    // drift that leaves it: a = 1, or the fixed a(t) (kicks at t_p, drifts at
+    // the midpoint)
+    auto kick_l = [&](int64_t p) { return std::pow(scale_at(c, t_start + (double)p * h), 1.0 + al); };
+    auto kick_v = [&](int64_t p) { return std::pow(scale_at(c, t_start + (double)p * h), 3.0 + al); };
+    auto drift_d = [&](int64_t p) { return std::pow(scale_at(c, t_start + ((double)p + 0.5) * h), al - 3.0); };
     // ---- forward sweep (leapfrog form of T VV2 steps) with checkpoints
     HIPCHK(c, hipEventRecord(e0, c->stream));
     GCHK(checkpoint_io(c, 0, true));
     GCHK(reserve_coef(c, (size_t)T + 3));
     for (int64_t p = 0; p <= T; ++p) {
         PassCoef &P = c->coef_host[p];
-        P.ka1 = P.ka3 = 1.0;
+        P.ka1 = kick_l(p);
+        P.ka3 = kick_v(p);
         P.c1 = p > 0 ? 0.5 * h : 0.0;
         P.c2 = p < T ? 0.5 * h : 0.0;
-        P.dend = p < T ? h : 0.0;
+        P.dend = p < T ? h * drift_d(p) : 0.0;
     }
     GCHK(upload_coef(c, (size_t)T + 1));
     for (int64_t p = 0; p < T; ++p) {
@@ -1688,10 +1698,12 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     } else {
         GCHK(energy_sums(c, 0.0));
         const double *S = c->sc_host->sums;
+        const double aT = scale_at(c, t_start + (double)T * h);
+        const double ia2 = 1.0 / (aT * aT), ia6 = ia2 * ia2 * ia2;
         double EK[2], EG[2];
         for (int f = 0; f < 2; ++f) {
-            EK[f] = S[f] / V / 2.0;
-            EG[f] = S[2 + f] / (c->p.dx * c->p.dx) / V / 2.0;
+            EK[f] = S[f] / V / 2.0 * ia6;
+            EG[f] = S[2 + f] / (c->p.dx * c->p.dx) / V / 2.0 * ia2;
         }
         rho = EK[0] + EK[1] + EG[0] + EG[1] + S[4] / V + S[5] / V;
         O = (EK[1] + EG[1]) / rho;
@@ -1710,6 +1722,8 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
         a.q = c->p.q;
         a.O = O;
         a.inv_vrho = 1.0 / (V * rho);
+        a.ia2 = ia2;
+        a.ia6 = ia6;
         a.partials = c->adj_partials;
         a.ticket = c->ticket;
         a.out_sum = &c->sc->sums[kMaxQ - 2];
@@ -1718,9 +1732,10 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     }
 
     // ---- reverse sweep
-    GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, nb, zc, tiles_x, tiles_y));   // closing half kick
+    GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, kick_l(T), kick_v(T), nb, zc, tiles_x, tiles_y));   // closing half kick
     for (int64_t p = T - 1; p >= 0; --p) {
-        GCHK(adj_pass(c, -h, h, p > 0 ? 0.5 * h : 0.0, 0.5 * h, nb, zc, tiles_x, tiles_y));
+        const double d = h * drift_d(p);
+        GCHK(adj_pass(c, -d, d, p > 0 ? 0.5 * h : 0.0, 0.5 * h, kick_l(p), kick_v(p), nb, zc, tiles_x, tiles_y));
         if (p % k == 0) GCHK(checkpoint_io(c, (size_t)(p / k), false));
     }
     HIPCHK(c, hipEventRecord(e2, c->stream));

@@ -1,15 +1,18 @@
 // stage_adjoint.hpp -- reverse step and adjoint of the velocity-Verlet map for
-// two real fields with V = lambda/4 phi^4 + q/2 phi^2 chi^2 and a = 1.
+// two real fields with V = lambda/4 phi^4 + q/2 phi^2 chi^2, at a = 1 or on a
+// fixed background a(t).
 //
-// At a = 1 a run of VV2 steps is a leapfrog whose pass p does
-//   pi <- pi + cA F(phi_p) + cB F(phi_p);  phi_{p+1} = phi_p + h pi,
-// with F = Lap phi - grad V (sec. 4.5.2 kernel at a = 1), cA = h/2 (0 at the
-// first point) and cB = h/2.  The reverse pass p, fused, does per site:
-//   reverse drift   phi_p  = phi_{p+1} - h pi          (on load, all stencil points)
-//   adjoint drift   lpi    = lpi + h lphi              (on load, all stencil points)
+// A run of VV2 steps is a leapfrog whose pass p does
+//   pi <- pi + cA F(phi_p) + cB F(phi_p);  phi_{p+1} = phi_p + h d_p pi,
+// with F = kL Lap phi - kV grad V (sec. 4.5.2 kernel; kL = a_p^{1+alpha},
+// kV = a_p^{3+alpha} at the kick time t_p), d_p = a(t_p + h/2)^{alpha-3},
+// cA = h/2 (0 at the first point) and cB = h/2.  The reverse pass p, fused,
+// does per site (dphi = -h d_p, dlam = h d_p):
+//   reverse drift   phi_p  = phi_{p+1} + dphi pi       (on load, all stencil points)
+//   adjoint drift   lpi    = lpi + dlam lphi           (on load, all stencil points)
 //   reverse kick    pi     = (pi - cB F(phi_p)) - cA F(phi_p)
-//   adjoint kick    lphi  += (cB + cA) [Lap lpi - H_V(phi_p) lpi]   (dF is symmetric)
-//   coupling        dO/dq += (cA + cB) sum_n lpi . dF/dq,  dF/dq = -(phi chi^2, phi^2 chi)
+//   adjoint kick    lphi  += (cB + cA) [kL Lap lpi - kV H_V(phi_p) lpi]   (dF is symmetric)
+//   coupling        dO/dq += (cA + cB) sum_n lpi . dF/dq,  dF/dq = -kV (phi chi^2, phi^2 chi)
 // with the Hessian H_V = [[3 lambda phi^2 + q chi^2, 2 q phi chi], [2 q phi chi, q phi^2]].
 // All four arrays of both fields are read with a one-site halo and written to
 // the other buffer of their ping-pong pair.  Layout and tiling follow the
@@ -27,6 +30,7 @@ struct AdjArgs {
     double inv_dx2, lam, q;
     double dphi, dlam;   // drifts on load: phi += dphi * pi, lpi += dlam * lphi
     double cA, cB;       // the two half kicks of the forward pass
+    double kL, kV;       // kernel factors a^{1+alpha}, a^{3+alpha} at this kick point
     double *partials;
     unsigned *ticket;
     double *dq_acc;      // device accumulator of dO/dq
@@ -78,7 +82,7 @@ __global__ void __launch_bounds__(TX *TY) adjoint_stage(const AdjArgs g)
         hoff = hx + N * hy;
     }
     const double dph = g.dphi, dla = g.dlam, cA = g.cA, cB = g.cB;
-    const double lam = g.lam, qc = g.q, idx2 = g.inv_dx2;
+    const double lam = g.lam, qc = g.q, idx2 = g.inv_dx2, kL = g.kL, kV = g.kV;
 
     // array a of a raw 4-tuple: 0 phi, 1 pi, 2 lphi, 3 lpi ; stencil quantities:
     // S0 = phi + dph * pi (fields 0, 1), S1 = lpi + dla * lphi (fields 0, 1)
@@ -160,14 +164,14 @@ __global__ void __launch_bounds__(TX *TY) adjoint_stage(const AdjArgs g)
                           (wp[a] - 2.0 * c0 + wm[a])) * idx2;
             }
             const double u = w0[0], v = w0[1], l0 = w0[2], l1 = w0[3];
-            const double F0 = lap[0] - (lam * u * u * u + qc * u * v * v);
-            const double F1 = lap[1] - qc * u * u * v;
+            const double F0 = kL * lap[0] - kV * (lam * u * u * u + qc * u * v * v);
+            const double F1 = kL * lap[1] - kV * (qc * u * u * v);
             const double h00 = 3.0 * lam * u * u + qc * v * v, h01 = 2.0 * qc * u * v, h11 = qc * u * u;
-            const double G0 = lap[2] - (h00 * l0 + h01 * l1);
-            const double G1 = lap[3] - (h01 * l0 + h11 * l1);
+            const double G0 = kL * lap[2] - kV * (h00 * l0 + h01 * l1);
+            const double G1 = kL * lap[3] - kV * (h01 * l0 + h11 * l1);
             const size_t oz = (size_t)z * NN + own;
             if (valid) {
-                dq += (cA + cB) * (-(l0 * u * v * v) - (l1 * u * u * v));
+                dq += (cA + cB) * kV * (-(l0 * u * v * v) - (l1 * u * u * v));
                 const double np0 = (r0[0][1] - cB * F0) - cA * F0;
                 const double np1 = (r0[1][1] - cB * F1) - cA * F1;
                 const double nl0 = (r0[0][2] + cB * G0) + cA * G0;
@@ -232,16 +236,18 @@ __global__ void __launch_bounds__(TX *TY) adjoint_stage(const AdjArgs g)
     }
 }
 
-// Seed of the adjoint from O = (E_K^chi + E_G^chi)/rho at a = 1 (sec. 4.4
-// energies, eq. EK_EG_EV):  with w = (0, 1) and V = N^3,
-//   dO/dpi_s  = (w_s - O) pi_s / (V rho)
-//   dO/dphi_s = (w_s (-Lap phi_s) - O (-Lap phi_s + dV/dphi_s)) / (V rho)
+// Seed of the adjoint from O = (E_K^chi + E_G^chi)/rho at scale factor a
+// (sec. 4.4 energies, eq. EK_EG_EV: E_K = <pi^2>/(2 a^6), E_G =
+// <|grad phi|^2>/(2 a^2)):  with w = (0, 1) and V = N^3,
+//   dO/dpi_s  = (w_s - O) pi_s / (a^6 V rho)
+//   dO/dphi_s = (w_s (-Lap phi_s)/a^2 - O (-Lap phi_s/a^2 + dV/dphi_s)) / (V rho)
 // and the sum of phi^2 chi^2 / 2 for the explicit coupling derivative.
 struct SeedArgs {
     const double *phi[2], *pi[2];
     double *lphi[2], *lpi[2];
     int N;
     double inv_dx2, lam, q, O, inv_vrho;
+    double ia2, ia6;     // 1/a^2, 1/a^6 at the final time
     double *partials;
     unsigned *ticket;
     double *out_sum;
@@ -269,8 +275,8 @@ __global__ void __launch_bounds__(256) adjoint_seed(const SeedArgs g)
             const double c = P[n];
             const double lap = ((P[xp] - 2.0 * c + P[xm]) + (P[yp] - 2.0 * c + P[ym]) + (P[zp] - 2.0 * c + P[zm])) * g.inv_dx2;
             const double wsel = s == 1 ? 1.0 : 0.0;
-            g.lphi[s][n] = (wsel * (-lap) - g.O * (-lap + dV[s])) * g.inv_vrho;
-            g.lpi[s][n] = (wsel - g.O) * g.pi[s][n] * g.inv_vrho;
+            g.lphi[s][n] = (wsel * (-lap) * g.ia2 - g.O * (-lap * g.ia2 + dV[s])) * g.inv_vrho;
+            g.lpi[s][n] = (wsel - g.O) * g.pi[s][n] * g.ia6 * g.inv_vrho;
         }
         acc = 0.5 * u * u * v * v;
     }

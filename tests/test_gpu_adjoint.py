@@ -231,3 +231,86 @@ def test_spectrum_bin_autograd_and_bad_selection():
     r = lat.grad(T, observable="spectrum_bin", field=1, bin=bmax)   # the outermost shell is valid
     assert np.isfinite(r["value"]) and r["value"] >= 0.0
     lat.close()
+
+
+# Fixed power-law background (radiation, H0 = 2): kicks at a(t_p), drifts at a(t_p + h/2)
+
+def kw_fixed(wl, N, alpha=1.0, t0=0.25, q=None):
+    kw = kw_of(wl, N, q)
+    kw.update(expansion="fixed", w_eos=1 / 3, H0=2.0, t_ref=0.0, a0=1.0, t0=t0, alpha=alpha)
+    return kw
+
+
+def oracle_fixed(wl, N, alpha=1.0):
+    return oracle.ScalarModel(N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2,
+                              expansion=oracle.FIXED, integrator=oracle.VV2, lam=wl.lam, q=wl.q, alpha=alpha,
+                              w_eos=1 / 3, H0=2.0, t0=0.0, a0=1.0)
+
+
+@pytest.mark.parametrize("N,T,stride,alpha,obs", [(16, 40, 0, 1.0, "chi_fraction"), (24, 33, 5, 0.5, "chi_fraction"),
+                                                  (13, 20, 1, 1.0, "spectrum_bin"), (64, 25, 0, 0.5, "spectrum_bin")])
+def test_grad_fixed_background_matches_oracle_adjoint(N, T, stride, alpha, obs):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields(N=N)
+    t0 = 0.25
+    say(f"[adj] fixed background oracle parity N={N} T={T} stride={stride} alpha={alpha} {obs}")
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_fixed(wl, N, alpha, t0))
+    sel = dict(field=1, bin=3) if obs == "spectrum_bin" else {}
+    r = lat.grad(T, stride=stride, observable=obs, **sel)
+    kind = oracle.OBS_SPECTRUM_BIN if obs == "spectrum_bin" else oracle.OBS_CHI_FRACTION
+    O, g, gp, dq = oracle.adjoint_vv2(oracle_fixed(wl, N, alpha), phi, pi, T, kind=kind, t=t0, **sel)
+    say(f"[adj]   O={r['value']:.6e} (oracle {O:.6e}) dO/dq={r['dO_dq']:.6e} (oracle {dq:.6e})")
+    assert abs(r["value"] - O) <= 1e-12 * abs(O)
+    for s in range(2):
+        assert rel_maxdiff(r["dO_dphi"][s].cpu().numpy(), g[s]) <= 1e-10
+        assert rel_maxdiff(r["dO_dpi"][s].cpu().numpy(), gp[s]) <= 1e-10
+    assert abs(r["dO_dq"] - dq) <= 1e-10 * abs(dq)
+    for s in range(2):
+        assert np.array_equal(tp[s].cpu().numpy(), phi[s].reshape(-1))
+        assert np.array_equal(tq[s].cpu().numpy(), pi[s].reshape(-1))
+    lat.close()
+
+
+def test_grad_fixed_background_full_workload_vs_finite_differences():
+    """64^3 x 2000 VV2 steps on the fixed background, chi energy fraction at
+    the final a, against differences of the library's own forward run."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    N, T = wl.N, wl.steps
+    phi, pi = wl.initial_fields()
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_fixed(wl, N))
+    r = lat.grad(T)
+    g = r["dO_dphi"][0].cpu().numpy().reshape(N, N, N)
+    dq, O0 = r["dO_dq"], r["value"]
+    say(f"[adj] fixed background full workload: O={O0:.6e} dO/dq={dq:.6e} forward {r['forward_ms']:.1f} ms "
+        f"reverse {r['reverse_ms']:.1f} ms")
+    lat.close()
+
+    def O_fwd(phi_, q_):
+        tp_, tq_ = to_dev(phi_, torch.float64), to_dev(pi, torch.float64)
+        lt = Lattice(tp_, tq_, **kw_fixed(wl, N, q=q_))
+        lt.step(T)
+        e = lt.energy()
+        lt.close()
+        return (e["EK"][1] + e["EG"][1]) / e["rho"]
+
+    assert abs(O_fwd(phi, wl.q) - O0) <= 1e-12 * abs(O0)
+    dirs = inputs.random_directions(4, N, seed=23) + [(np.zeros((N, N, N)), 1.0)]
+    for k, (v, vq) in enumerate(dirs):
+        ad = float(np.sum(g * v) + dq * vq)
+
+        def fd(eps):
+            return (O_fwd([phi[0] + eps * v, phi[1]], wl.q + eps * vq)
+                    - O_fwd([phi[0] - eps * v, phi[1]], wl.q - eps * vq)) / (2 * eps)
+
+        e = 2e-3 if vq == 1.0 else 4e-3
+        d1, d2 = fd(e), fd(e / 2)
+        rich = (4 * d2 - d1) / 3
+        rel = abs(rich - ad) / abs(ad)
+        say(f"[adj] fixed dir {k}: adjoint {ad:.10e} fd {rich:.10e} rel {rel:.2e}")
+        assert rel <= 1e-6
