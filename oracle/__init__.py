@@ -76,6 +76,8 @@ def lib():
                                           pp, dp]
         L.orc_adjoint_vv2_kind.argtypes = [C.POINTER(Params), C.c_double, C.c_int, C.c_int, C.c_int, pp, pp,
                                            C.c_long, dp, pp, pp, dp]
+        L.orc_adjoint_vv2_self.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.c_int, pp, pp, C.c_double,
+                                           C.c_double, C.c_long, dp, pp, pp, dp, dp, dp]
         L.orc_u1_forces.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp]
         L.orc_u1_energy.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), dp]
         L.orc_u1_gauss.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, dp]
@@ -264,13 +266,14 @@ def vv2_adjoint_step(model: ScalarModel, phi_n, pi_n, lphi, lpi, t=0.0) -> float
     return dq.value
 
 
-# Observables of the adjoint: the chi energy fraction (0) and one bin of the
-# power spectrum of eq. discretePS (1), for field `field`, bin `bin` >= 1.
-OBS_CHI_FRACTION = 0
+# Observables of the adjoint, of field `field`: its energy fraction (0; field
+# 1 is the chi fraction) and one bin `bin` >= 1 of its power spectrum of eq.
+# discretePS (1).
+OBS_ENERGY_FRACTION = 0
 OBS_SPECTRUM_BIN = 1
 
 
-def observable(model: ScalarModel, phi, pi, with_grad=False, kind=OBS_CHI_FRACTION, field=0, bin=0, a=1.0):
+def observable(model: ScalarModel, phi, pi, with_grad=False, kind=OBS_ENERGY_FRACTION, field=1, bin=0, a=1.0):
     """Observable `kind` of the state at scale factor a (and its gradient)."""
     p = model.cparams()
     O = C.c_double()
@@ -287,7 +290,7 @@ def observable(model: ScalarModel, phi, pi, with_grad=False, kind=OBS_CHI_FRACTI
     return O.value, g, gp, dq.value
 
 
-def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int, kind=OBS_CHI_FRACTION, field=0, bin=0, t=0.0):
+def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int, kind=OBS_ENERGY_FRACTION, field=1, bin=0, t=0.0):
     """O(final), dO/dphi(0) per field, dO/dpi(0) per field, dO/dq, for nsteps
     VV2 steps from time t (a = 1, or the fixed background a(t))."""
     phi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in phi0]
@@ -299,6 +302,22 @@ def adjoint_vv2(model: ScalarModel, phi0, pi0, nsteps: int, kind=OBS_CHI_FRACTIO
     _chk(lib().orc_adjoint_vv2_kind(C.byref(p), float(t), kind, field, bin, _pp(phi0), _pp(pi0), int(nsteps),
                                     C.byref(O), _pp(g), _pp(gp), C.byref(dq)), "adjoint_vv2")
     return O.value, g, gp, dq.value
+
+
+def adjoint_vv2_self(model: ScalarModel, phi0, pi0, a0, b0, nsteps: int, kind=OBS_ENERGY_FRACTION, field=1,
+                     bin=0):
+    """Self-consistent expansion: O(final), dO/dphi(0), dO/dpi(0) per field,
+    dO/dq, dO/da0, dO/db0 (b0 taken as an independent input)."""
+    phi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in phi0]
+    pi0 = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in pi0]
+    g = [np.zeros_like(phi0[0]) for _ in range(2)]
+    gp = [np.zeros_like(phi0[0]) for _ in range(2)]
+    O, dq, da, db = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    p = model.cparams()
+    _chk(lib().orc_adjoint_vv2_self(C.byref(p), kind, field, bin, _pp(phi0), _pp(pi0), float(a0), float(b0),
+                                    int(nsteps), C.byref(O), _pp(g), _pp(gp), C.byref(dq), C.byref(da),
+                                    C.byref(db)), "adjoint_vv2_self")
+    return O.value, g, gp, dq.value, da.value, db.value
 
 
 # ----------------------------------------------------------------------------

@@ -618,23 +618,24 @@ int orc_vv2_adjoint_step(const orc_params *p, double t, double *const *phi_n, do
     return 0;
 }
 
-/* Observable: fraction of the energy in chi, O = (E_K^chi + E_G^chi)/rho at
- * scale factor a (E_K = <pi^2>/(2 a^6), E_G = <|grad phi|^2>/(2 a^2)).  Writes O
- * and, if seeds are given, dO/dphi_s(n), dO/dpi_s(n) and the explicit dO/dq. */
-static double observable(const orc_params *p, double a, double *const *phi, double *const *pi,
+/* Observable: fraction of the energy in field f (0 phi, 1 chi),
+ * O = (E_K^f + E_G^f)/rho at scale factor a (E_K = <pi^2>/(2 a^6),
+ * E_G = <|grad phi|^2>/(2 a^2)).  Writes O and, if seeds are given,
+ * dO/dphi_s(n), dO/dpi_s(n) and the explicit dO/dq. */
+static double observable(const orc_params *p, double a, int f, double *const *phi, double *const *pi,
                          double **gphi, double **gpi, double *dOdq_explicit)
 {
     size_t V = vol(p->N);
     energies E = energies_of(p, phi, pi, a);
     const double ia2 = 1.0 / (a * a), ia6 = ia2 * ia2 * ia2;
     double rho = rho_tot(&E);
-    double X = E.EK[1] + E.EG[1];
+    double X = E.EK[f] + E.EG[f];
     double O = X / rho;
     if (gphi) {
         double *lap = (double *)malloc(V * sizeof(double));
         double inv = 1.0 / ((double)V * rho);
         for (int s = 0; s < 2; ++s) {
-            double wX = s == 1 ? 1.0 : 0.0;   /* d X / d(field s) weight */
+            double wX = s == f ? 1.0 : 0.0;   /* d X / d(field s) weight */
             orc_laplacian(p->N, p->dx, phi[s], lap);
             for (size_t n = 0; n < V; ++n) {
                 double dV = pot_deriv(p, s, phi[0][n], phi[1][n]);
@@ -658,14 +659,15 @@ int orc_observable(const orc_params *p, double *const *phi, double *const *pi, d
 {
     if (check_adj(p)) return -2;
     double d = 0.0;
-    *O = observable(p, 1.0, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
+    *O = observable(p, 1.0, 1, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);
     if (dOdq) *dOdq = d;
     return 0;
 }
 
-/* Observables the reverse sweep can start from: the chi energy fraction above,
- * or one bin of the power spectrum of one field (defined with the spectrum). */
-enum { ORC_OBS_CHI_FRACTION = 0, ORC_OBS_SPECTRUM_BIN = 1 };
+/* Observables the reverse sweep can start from: the energy fraction of one
+ * field above, or one bin of the power spectrum of one field (defined with the
+ * spectrum). */
+enum { ORC_OBS_ENERGY_FRACTION = 0, ORC_OBS_SPECTRUM_BIN = 1 };
 static double observable_kind(const orc_params *p, double a, int kind, int field, int bin, double *const *phi,
                               double *const *pi, double **gphi, double **gpi, double *dq);
 
@@ -679,8 +681,8 @@ int orc_adjoint_vv2_kind(const orc_params *p, double t_start, int kind, int fiel
                          double *dOdq)
 {
     if (check_adj(p)) return -2;
-    if (kind != ORC_OBS_CHI_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
-    if (kind == ORC_OBS_SPECTRUM_BIN && (field < 0 || field > 1 || bin < 1)) return -1;
+    if (kind != ORC_OBS_ENERGY_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
+    if (field < 0 || field > 1 || (kind == ORC_OBS_SPECTRUM_BIN && bin < 1)) return -1;
     if (nsteps < 0) return -1;
     size_t V = vol(p->N), B = V * sizeof(double);
     long k = 1;
@@ -733,7 +735,206 @@ int orc_adjoint_vv2_kind(const orc_params *p, double t_start, int kind, int fiel
 int orc_adjoint_vv2(const orc_params *p, double *const *phi0, double *const *pi0, long nsteps,
                     double *O_out, double *const *gphi, double *const *gpi, double *dOdq)
 {
-    return orc_adjoint_vv2_kind(p, 0.0, 0, 0, 0, phi0, pi0, nsteps, O_out, gphi, gpi, dOdq);
+    return orc_adjoint_vv2_kind(p, 0.0, ORC_OBS_ENERGY_FRACTION, 1, 0, phi0, pi0, nsteps, O_out, gphi, gpi, dOdq);
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of the VV2 map with the self-consistent expansion (reading  */
+/* R1), two fields.  One step from (phi_n, pi_n, a_n, b_n):             */
+/*  (1) pi'  = pi_n + h/2 K(a_n, phi_n)                                  */
+/*  (2) b'   = b_n + h/2 K_a(a_n, E(phi_n, pi_n, a_n))                   */
+/*  (3) a1   = a_n + h b'                                                */
+/*  (4) phi1 = phi_n + h abar^{alpha-3} pi',  abar = (a_n + a1)/2        */
+/*  (5) pi1  = pi' + h/2 K(a1, phi1)                                     */
+/*  (6) b1   = b' + h/2 K_a(a1, E(phi1, pi1, a1))                        */
+/* with K_a(a, E) = C(a) Q, C = a^{2 alpha+1} kappa^2/3,                 */
+/* Q = (alpha-2) E_K + alpha E_G + (alpha+1) E_V.  The adjoint pulls    */
+/* (lphi, lpi, la, lb) back through (6) ... (1) in that order.           */
+/* ------------------------------------------------------------------ */
+
+/* Adds w dK_a/dphi_s(n) to gphi and w dK_a/dpi_s(n) to gpi at (a, phi, pi);
+ * returns dK_a/da at fixed fields and sets *dkq = dK_a/dq:
+ *   dE_G/dphi_s = -Lap phi_s/(a^2 V), dE_V/dphi_s = dV/dphi_s / V,
+ *   dE_K/dpi_s = pi_s/(a^6 V), dE_K/da = -6 E_K/a, dE_G/da = -2 E_G/a,
+ *   dE_V/dq = <phi^2 chi^2/2>. */
+static double kernel_a_pullback(const orc_params *p, double a, double *const *phi, double *const *pi, double w,
+                                double **gphi, double **gpi, double *dkq)
+{
+    size_t V = vol(p->N);
+    double al = p->alpha;
+    energies E = energies_of(p, phi, pi, a);
+    double C = pow(a, 2.0 * al + 1.0) / 3.0 * p->kappa2;
+    double Q = (al - 2.0) * EK_tot(&E) + al * EG_tot(&E) + (al + 1.0) * EV_tot(&E);
+    double *lap = (double *)malloc(V * sizeof(double));
+    for (int s = 0; s < 2; ++s) {
+        orc_laplacian(p->N, p->dx, phi[s], lap);
+        for (size_t n = 0; n < V; ++n) {
+            double dV = pot_deriv(p, s, phi[0][n], phi[1][n]);
+            gphi[s][n] += w * C * (al * (-lap[n]) / (a * a * (double)V) + (al + 1.0) * dV / (double)V);
+            gpi[s][n] += w * C * (al - 2.0) * pi[s][n] / (pow(a, 6.0) * (double)V);
+        }
+    }
+    free(lap);
+    nsum kq = {0, 0};
+    for (size_t n = 0; n < V; ++n) nadd(&kq, 0.5 * phi[0][n] * phi[0][n] * phi[1][n] * phi[1][n]);
+    *dkq = C * (al + 1.0) * nval(&kq) / (double)V;
+    return (2.0 * al + 1.0) * C * Q / a + C * ((al - 2.0) * (-6.0) * EK_tot(&E) / a + al * (-2.0) * EG_tot(&E) / a);
+}
+
+/* sum_n l . dK/da at (a, phi):  dK_s/da = (1+alpha) a^alpha Lap phi_s - (3+alpha) a^{2+alpha} dV/dphi_s */
+static double kernel_da_dot(const orc_params *p, double a, double *const *phi, double *const *l)
+{
+    size_t V = vol(p->N);
+    double al = p->alpha;
+    double *lap = (double *)malloc(V * sizeof(double));
+    nsum k = {0, 0};
+    for (int s = 0; s < 2; ++s) {
+        orc_laplacian(p->N, p->dx, phi[s], lap);
+        for (size_t n = 0; n < V; ++n)
+            nadd(&k, l[s][n] * ((1.0 + al) * pow(a, al) * lap[n] -
+                                (3.0 + al) * pow(a, 2.0 + al) * pot_deriv(p, s, phi[0][n], phi[1][n])));
+    }
+    free(lap);
+    return nval(&k);
+}
+
+/* Pull (lphi, lpi, *la, *lb) back through one self-consistent VV2 step from
+ * the state (phi_n, pi_n, a_n, b_n) (unchanged); *dq accumulates. */
+static void self_adjoint_step(const orc_params *p, double *const *phi_n, double *const *pi_n, double a_n,
+                              double b_n, double **lphi, double **lpi, double *la, double *lb, double *dq)
+{
+    size_t V = vol(p->N), B = V * sizeof(double);
+    double h = p->dt, al = p->alpha;
+    double *pp[2], *ph1[2], *pi1[2], *J[2], *K[2];
+    for (int s = 0; s < 2; ++s) {
+        pp[s] = (double *)malloc(B);
+        ph1[s] = (double *)malloc(B);
+        pi1[s] = (double *)malloc(B);
+        J[s] = (double *)malloc(B);
+        K[s] = (double *)malloc(B);
+    }
+    double *lap = (double *)malloc(B);
+    /* forward intermediates */
+    energies En = energies_of(p, phi_n, pi_n, a_n);
+    double bh = b_n + 0.5 * h * kernel_a(p, a_n, &En);
+    double a1 = a_n + h * bh, abar = 0.5 * (a_n + a1);
+    double dr = h * pow(abar, al - 3.0);
+    for (int s = 0; s < 2; ++s) kernel_field(p, a_n, phi_n, s, K[s]);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) {
+            pp[s][n] = pi_n[s][n] + 0.5 * h * K[s][n];
+            ph1[s][n] = phi_n[s][n] + dr * pp[s][n];
+        }
+    for (int s = 0; s < 2; ++s) kernel_field(p, a1, ph1, s, K[s]);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) pi1[s][n] = pp[s][n] + 0.5 * h * K[s][n];
+    double kL0 = pow(a_n, 1.0 + al), kV0 = pow(a_n, 3.0 + al), kL1 = pow(a1, 1.0 + al), kV1 = pow(a1, 3.0 + al);
+    double la1 = *la, la0 = 0.0, dkq;
+    /* (6) b1 = b' + h/2 K_a(a1, E(phi1, pi1, a1)) */
+    double g6 = 0.5 * h * (*lb);
+    la1 += g6 * kernel_a_pullback(p, a1, ph1, pi1, g6, lphi, lpi, &dkq);
+    *dq += g6 * dkq;
+    /* (5) pi1 = pi' + h/2 K(a1, phi1) */
+    la1 += 0.5 * h * kernel_da_dot(p, a1, ph1, lpi);
+    *dq += 0.5 * h * kV1 * dot_dFdq(p, ph1, lpi);
+    jac_F_T(p, ph1, lpi, J, lap, kL1, kV1);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) lphi[s][n] += 0.5 * h * J[s][n];
+    /* (4) phi1 = phi_n + h abar^{alpha-3} pi' */
+    nsum kd = {0, 0};
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) nadd(&kd, lphi[s][n] * pp[s][n]);
+    double labar = h * (al - 3.0) * pow(abar, al - 4.0) * nval(&kd);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) lpi[s][n] += dr * lphi[s][n];
+    la1 += 0.5 * labar;
+    la0 += 0.5 * labar;
+    /* (3) a1 = a_n + h b' */
+    la0 += la1;
+    *lb += h * la1;
+    /* (1) pi' = pi_n + h/2 K(a_n, phi_n), with lpi = the adjoint of pi' */
+    la0 += 0.5 * h * kernel_da_dot(p, a_n, phi_n, lpi);
+    *dq += 0.5 * h * kV0 * dot_dFdq(p, phi_n, lpi);
+    jac_F_T(p, phi_n, lpi, J, lap, kL0, kV0);
+    for (int s = 0; s < 2; ++s)
+        for (size_t n = 0; n < V; ++n) lphi[s][n] += 0.5 * h * J[s][n];
+    /* (2) b' = b_n + h/2 K_a(a_n, E(phi_n, pi_n, a_n)): direct terms of pi_n and phi_n */
+    double g2 = 0.5 * h * (*lb);
+    la0 += g2 * kernel_a_pullback(p, a_n, phi_n, pi_n, g2, lphi, lpi, &dkq);
+    *dq += g2 * dkq;
+    *la = la0;
+    for (int s = 0; s < 2; ++s) {
+        free(pp[s]);
+        free(ph1[s]);
+        free(pi1[s]);
+        free(J[s]);
+        free(K[s]);
+    }
+    free(lap);
+}
+
+/* dO/da at fixed fields for the energy fraction of field f:
+ * O = X/rho, dX/da = -(6 E_K^f + 2 E_G^f)/a, drho/da = -(6 E_K + 2 E_G)/a. */
+static double energy_fraction_da(const orc_params *p, double a, int f, double *const *phi, double *const *pi)
+{
+    energies E = energies_of(p, phi, pi, a);
+    double rho = rho_tot(&E), O = (E.EK[f] + E.EG[f]) / rho;
+    double dX = -(6.0 * E.EK[f] + 2.0 * E.EG[f]) / a, drho = -(6.0 * EK_tot(&E) + 2.0 * EG_tot(&E)) / a;
+    return (dX - O * drho) / rho;
+}
+
+/* Gradient of O(final state) of observable `kind` after nsteps self-consistent
+ * VV2 steps from (phi0, pi0, a0, b0), with respect to phi0, pi0, q, a0 and b0
+ * (b0 an independent input here).  Every step's state is stored; the reverse
+ * sweep pulls the adjoint back step by step. */
+int orc_adjoint_vv2_self(const orc_params *p, int kind, int field, int bin, double *const *phi0, double *const *pi0,
+                         double a0, double b0, long nsteps, double *O_out, double *const *gphi, double *const *gpi,
+                         double *dOdq, double *dOda0, double *dOdb0)
+{
+    if (p->nfields != 2 || p->potential != ORC_PHI4_CHI2 || p->expansion != ORC_SELF) return -2;
+    if (kind != ORC_OBS_ENERGY_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
+    if (field < 0 || field > 1 || (kind == ORC_OBS_SPECTRUM_BIN && bin < 1)) return -1;
+    if (nsteps < 0 || !(a0 > 0.0)) return -1;
+    size_t V = vol(p->N), B = V * sizeof(double);
+    double *st = (double *)malloc((size_t)(nsteps + 1) * 4 * B);
+    double *ab = (double *)malloc((size_t)(nsteps + 1) * 2 * sizeof(double));
+    double *cur[4];
+    for (int i = 0; i < 4; ++i) cur[i] = st + (size_t)i * V;
+    memcpy(cur[0], phi0[0], B); memcpy(cur[1], phi0[1], B);
+    memcpy(cur[2], pi0[0], B);  memcpy(cur[3], pi0[1], B);
+    orc_params pv = *p;
+    pv.integrator = ORC_VV2;
+    orc_clock c = {0.0, a0, b0, 0, 0};
+    ab[0] = a0;
+    ab[1] = b0;
+    for (long n = 0; n < nsteps; ++n) {
+        double *nx[4];
+        for (int i = 0; i < 4; ++i) {
+            nx[i] = st + ((size_t)(n + 1) * 4 + i) * V;
+            memcpy(nx[i], st + ((size_t)n * 4 + i) * V, B);
+        }
+        orc_run(&pv, nx, nx + 2, &c, 1);
+        ab[2 * (n + 1)] = c.a;
+        ab[2 * (n + 1) + 1] = c.b;
+    }
+    double *fin[4];
+    for (int i = 0; i < 4; ++i) fin[i] = st + ((size_t)nsteps * 4 + i) * V;
+    double *lphi[2] = {gphi[0], gphi[1]}, *lpi[2] = {gpi[0], gpi[1]};
+    double q_acc = 0.0, aT = ab[2 * nsteps];
+    *O_out = observable_kind(p, aT, kind, field, bin, fin, fin + 2, lphi, lpi, &q_acc);
+    double la = kind == ORC_OBS_ENERGY_FRACTION ? energy_fraction_da(p, aT, field, fin, fin + 2) : 0.0;
+    double lb = 0.0;
+    for (long n = nsteps - 1; n >= 0; --n) {
+        double *sp[2] = {st + ((size_t)n * 4 + 0) * V, st + ((size_t)n * 4 + 1) * V};
+        double *sm[2] = {st + ((size_t)n * 4 + 2) * V, st + ((size_t)n * 4 + 3) * V};
+        self_adjoint_step(p, sp, sm, ab[2 * n], ab[2 * n + 1], lphi, lpi, &la, &lb, &q_acc);
+    }
+    *dOdq = q_acc;
+    *dOda0 = la;
+    *dOdb0 = lb;
+    free(st);
+    free(ab);
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1118,12 +1319,12 @@ static double spectrum_bin_value(int N, double dx, const double *f, int bin, dou
 }
 
 /* Observable `kind` of the state and its gradient (seed of the adjoint):
- * ORC_OBS_CHI_FRACTION as orc_observable; ORC_OBS_SPECTRUM_BIN: Delta(bin) of
+ * ORC_OBS_ENERGY_FRACTION: energy fraction of phi_field; ORC_OBS_SPECTRUM_BIN: Delta(bin) of
  * phi_field, gradient in gphi[field] only, no explicit q dependence. */
 static double observable_kind(const orc_params *p, double a, int kind, int field, int bin, double *const *phi,
                               double *const *pi, double **gphi, double **gpi, double *dq)
 {
-    if (kind == ORC_OBS_CHI_FRACTION) return observable(p, a, phi, pi, gphi, gpi, dq);
+    if (kind == ORC_OBS_ENERGY_FRACTION) return observable(p, a, field, phi, pi, gphi, gpi, dq);
     size_t V = vol(p->N);
     for (int s = 0; s < 2; ++s) {
         if (gphi) memset(gphi[s], 0, V * sizeof(double));
@@ -1136,9 +1337,9 @@ static double observable_kind(const orc_params *p, double a, int kind, int field
 int orc_observable_kind(const orc_params *p, double a, int kind, int field, int bin, double *const *phi,
                         double *const *pi, double *O, double *const *gphi, double *const *gpi, double *dOdq)
 {
-    if (check_adj(p)) return -2;
-    if (kind != ORC_OBS_CHI_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
-    if (kind == ORC_OBS_SPECTRUM_BIN && (field < 0 || field > 1 || bin < 1)) return -1;
+    if (p->nfields != 2 || p->potential != ORC_PHI4_CHI2) return -2;   /* any expansion: a is an argument */
+    if (kind != ORC_OBS_ENERGY_FRACTION && kind != ORC_OBS_SPECTRUM_BIN) return -1;
+    if (field < 0 || field > 1 || (kind == ORC_OBS_SPECTRUM_BIN && bin < 1)) return -1;
     double d = 0.0;
     if (!(a > 0.0)) return -1;
     *O = observable_kind(p, a, kind, field, bin, phi, pi, (double **)gphi, (double **)gpi, gphi ? &d : NULL);

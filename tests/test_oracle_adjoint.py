@@ -297,3 +297,40 @@ def test_fixed_background_reverse_sweep_vs_finite_differences(orc, kind, alpha):
         ad = np.dot(g[0], v[0]) + np.dot(g[1], v[1]) + np.dot(gp[0], v[2]) + np.dot(gp[1], v[3]) + dq * vq
         scale = np.sqrt(sum(np.dot(a, a) for a in g + gp) + dq * dq)
         assert abs(fd - ad) <= 1e-6 * scale
+
+
+def test_energy_fraction_of_phi(orc):
+    """Field 0's energy fraction: with chi's it adds to 1 - E_V/rho; its seed
+    and reverse sweep against central differences."""
+    N = 5
+    m = model(orc, N, dt=0.02)
+    phi, pi = state(N, 14)
+    Ophi, g, gp, dq = orc.observable(m, phi, pi, with_grad=True, field=0)
+    Ochi = orc.observable(m, phi, pi, field=1)
+    E = orc.ScalarState(m, phi, pi).energy()
+    assert abs(Ophi + Ochi - (1 - sum(E["EV"]) / E["rho"])) <= 1e-14
+    eps = 1e-6
+    for s in range(2):
+        for site in (3, 77):
+            p_ = [f.copy() for f in phi]; m_ = [f.copy() for f in phi]
+            p_[s][site] += eps; m_[s][site] -= eps
+            fd = (orc.observable(m, p_, pi, field=0) - orc.observable(m, m_, pi, field=0)) / (2 * eps)
+            # O is near 1/2 here: the differences carry ~1e-10 of rounding
+            assert abs(fd - g[s][site]) < 1e-7 * max(1e-3, abs(fd))
+    nsteps = 7
+    O, g, gp, dq = orc.adjoint_vv2(m, phi, pi, nsteps, field=0)
+
+    def O_of(phi_, q_):
+        mm = model(orc, N, dt=0.02, q=q_)
+        st = orc.ScalarState(mm, phi_, pi).run(nsteps)
+        return orc.observable(mm, st.phi, st.pi, field=0)
+
+    assert abs(O - O_of(phi, m.q)) <= 1e-14
+    rng = np.random.default_rng(29)
+    v = [rng.standard_normal(N ** 3) for _ in range(2)]
+    vq = 0.3
+    eps = 1e-5
+    fd = (O_of([phi[0] + eps * v[0], phi[1] + eps * v[1]], m.q + eps * vq)
+          - O_of([phi[0] - eps * v[0], phi[1] - eps * v[1]], m.q - eps * vq)) / (2 * eps)
+    ad = np.dot(g[0], v[0]) + np.dot(g[1], v[1]) + dq * vq
+    assert abs(fd - ad) <= 1e-6 * abs(ad)

@@ -61,6 +61,17 @@ MUTANTS = [
     ("coupling sensitivity without the potential factor", "*dq += 0.5 * h * kV1 * dot_dFdq(p, ph1, lpi);",
      "*dq += 0.5 * h * dot_dFdq(p, ph1, lpi);", "test_oracle_adjoint.py"),
     ("observable kinetic power of a", "ia6 = ia2 * ia2 * ia2;", "ia6 = ia2 * ia2;", "test_oracle_adjoint.py"),
+    ("energy fraction of chi whatever the field", "double wX = s == f ? 1.0 : 0.0;", "double wX = s == 1 ? 1.0 : 0.0;",
+     "test_oracle_adjoint.py"),
+    ("self-consistent adjoint without the closing b kick", "double g6 = 0.5 * h * (*lb);", "double g6 = 0.0;",
+     "test_oracle_adjoint_self.py"),
+    ("self-consistent adjoint without the drift's scale-factor term", "    la1 += 0.5 * labar;\n", "",
+     "test_oracle_adjoint_self.py"),
+    ("scale-factor kernel derivative exponent", "return (2.0 * al + 1.0) * C * Q / a", "return (2.0 * al) * C * Q / a",
+     "test_oracle_adjoint_self.py"),
+    ("scale-factor kernel kinetic power of a", "gpi[s][n] += w * C * (al - 2.0) * pi[s][n] / (pow(a, 6.0)",
+     "gpi[s][n] += w * C * (al - 2.0) * pi[s][n] / (pow(a, 4.0)", "test_oracle_adjoint_self.py"),
+    ("a drift adjoint without h", "*lb += h * la1;", "*lb += la1;", "test_oracle_adjoint_self.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += dr * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * dr * lphi[s][n];", "test_oracle_adjoint.py"),
 ]
