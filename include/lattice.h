@@ -230,14 +230,15 @@ lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
 
 /* observable of lattice_grad */
 enum lat_observable {
-    LAT_OBS_CHI_ENERGY_FRACTION = 0,  /* O = (E_K^chi + E_G^chi) / rho at the final time */
-    LAT_OBS_SPECTRUM_BIN = 1          /* O = Delta(b) of phi_field at the final time: bin b of the power
+    LAT_OBS_ENERGY_FRACTION = 0,      /* O = (E_K^s + E_G^s) / rho of field s at the final time
+                                         (s = 1: the energy fraction in chi) */
+    LAT_OBS_SPECTRUM_BIN = 1          /* O = Delta(b) of phi_s at the final time: bin b of the power
                                          spectrum of lattice_spectrum (sec. 3.1, eq. discretePS) */
 };
 
 typedef struct lat_grad_spec {
     int32_t observable;          /* enum lat_observable */
-    int32_t field;               /* LAT_OBS_SPECTRUM_BIN: field s in {0, 1}; otherwise 0 */
+    int32_t field;               /* field s in {0, 1} of the observable */
     int64_t nsteps;              /* T >= 1 velocity-Verlet steps */
     int64_t checkpoint_stride;   /* steps between stored states; 0 = ceil(sqrt(T)) */
     int32_t bin;                 /* LAT_OBS_SPECTRUM_BIN: shell b, 1 <= b <= floor(sqrt(3) N / 2); otherwise 0 */

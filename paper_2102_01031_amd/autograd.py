@@ -3,7 +3,8 @@
 ``chi_energy_fraction(phi, chi, pi_phi, pi_chi, q, ...)`` evolves the two-field
 lattice (V = lambda/4 phi^4 + q/2 phi^2 chi^2, velocity-Verlet, a = 1) for
 ``nsteps`` and returns O = (E_K^chi + E_G^chi)/rho as a 0-dim float64 tensor.
-``spectrum_bin(..., field, bin)`` returns instead Delta(bin) of field ``field``
+``energy_fraction(..., field)`` returns that fraction for either field, and
+``spectrum_bin(..., field, bin)`` returns Delta(bin) of field ``field``
 at the final time (eq. discretePS).  The backward returns dO/d(phi, chi,
 pi_phi, pi_chi) at the initial time and dO/dq, all computed by
 ``lattice_grad`` (reverse integration with checkpoints) during the forward
@@ -45,6 +46,11 @@ def _q(q):
 def chi_energy_fraction(phi, chi, pi_phi, pi_chi, q, *, N, dx, dt, nsteps, lam=1.0, stride=0):
     return _LatticeObservable.apply(phi, chi, pi_phi, pi_chi, _q(q), N, dx, dt, nsteps, lam, stride,
                                     "chi_fraction", 0, 0)
+
+
+def energy_fraction(phi, chi, pi_phi, pi_chi, q, *, N, dx, dt, nsteps, field, lam=1.0, stride=0):
+    return _LatticeObservable.apply(phi, chi, pi_phi, pi_chi, _q(q), N, dx, dt, nsteps, lam, stride,
+                                    "energy_fraction", int(field), 0)
 
 
 def spectrum_bin(phi, chi, pi_phi, pi_chi, q, *, N, dx, dt, nsteps, field, bin, lam=1.0, stride=0):

@@ -1558,22 +1558,22 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
 {
     if (!c || !spec || !out) return fail(c, LAT_EINVAL, "null argument");
     const bool spec_obs = spec->observable == LAT_OBS_SPECTRUM_BIN;
-    if (spec->observable != LAT_OBS_CHI_ENERGY_FRACTION && !spec_obs)
+    if (spec->observable != LAT_OBS_ENERGY_FRACTION && !spec_obs)
         return fail(c, LAT_EINVAL, "unknown observable");
     if (c->batch || c->u1 || c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 ||
         c->p.expansion == LAT_EXP_SELF || c->f32)
         return fail(c, LAT_EUNSUPPORTED,
                     "lattice_grad needs two fields, VV2, no or a fixed expansion, and float64");
     if (spec->reserved != 0) return fail(c, LAT_EINVAL, "reserved field of lat_grad_spec must be 0");
+    if (spec->field < 0 || spec->field > 1) return fail(c, LAT_EINVAL, "observable field out of range");
     if (spec_obs) {
         const long h2 = (long)(c->N / 2) * (c->N / 2);
         long bmax = (long)std::sqrt(3.0 * (double)h2);
         while ((bmax + 1) * (bmax + 1) <= 3 * h2) ++bmax;
         while (bmax * bmax > 3 * h2) --bmax;
-        if (spec->field < 0 || spec->field > 1 || spec->bin < 1 || spec->bin > bmax)
-            return fail(c, LAT_EINVAL, "spectrum observable: field or bin out of range");
-    } else if (spec->field != 0 || spec->bin != 0) {
-        return fail(c, LAT_EINVAL, "field and bin are 0 for this observable");
+        if (spec->bin < 1 || spec->bin > bmax) return fail(c, LAT_EINVAL, "spectrum observable: bin out of range");
+    } else if (spec->bin != 0) {
+        return fail(c, LAT_EINVAL, "bin is 0 for the energy fraction");
     }
     const int64_t T = spec->nsteps;
     if (T < 1 || T > (1LL << 26)) return fail(c, LAT_EINVAL, "nsteps out of range");
@@ -1706,7 +1706,7 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
             EG[f] = S[2 + f] / (c->p.dx * c->p.dx) / V / 2.0 * ia2;
         }
         rho = EK[0] + EK[1] + EG[0] + EG[1] + S[4] / V + S[5] / V;
-        O = (EK[1] + EG[1]) / rho;
+        O = (EK[spec->field] + EG[spec->field]) / rho;
         hipLaunchKernelGGL(zero_doubles, dim3(1), dim3(64), 0, c->stream, &c->sc->sums[kMaxQ - 2], 2);
         HIPCHK(c, hipGetLastError());
         SeedArgs a{};
@@ -1721,6 +1721,7 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
         a.lam = c->p.lambda;
         a.q = c->p.q;
         a.O = O;
+        a.field = spec->field;
         a.inv_vrho = 1.0 / (V * rho);
         a.ia2 = ia2;
         a.ia6 = ia6;

@@ -236,9 +236,9 @@ __global__ void __launch_bounds__(TX *TY) adjoint_stage(const AdjArgs g)
     }
 }
 
-// Seed of the adjoint from O = (E_K^chi + E_G^chi)/rho at scale factor a
-// (sec. 4.4 energies, eq. EK_EG_EV: E_K = <pi^2>/(2 a^6), E_G =
-// <|grad phi|^2>/(2 a^2)):  with w = (0, 1) and V = N^3,
+// Seed of the adjoint from O = (E_K^f + E_G^f)/rho, the energy fraction of
+// field f, at scale factor a (sec. 4.4 energies, eq. EK_EG_EV: E_K =
+// <pi^2>/(2 a^6), E_G = <|grad phi|^2>/(2 a^2)):  with w_s = [s == f] and V = N^3,
 //   dO/dpi_s  = (w_s - O) pi_s / (a^6 V rho)
 //   dO/dphi_s = (w_s (-Lap phi_s)/a^2 - O (-Lap phi_s/a^2 + dV/dphi_s)) / (V rho)
 // and the sum of phi^2 chi^2 / 2 for the explicit coupling derivative.
@@ -246,6 +246,7 @@ struct SeedArgs {
     const double *phi[2], *pi[2];
     double *lphi[2], *lpi[2];
     int N;
+    int field;           // f of the energy fraction
     double inv_dx2, lam, q, O, inv_vrho;
     double ia2, ia6;     // 1/a^2, 1/a^6 at the final time
     double *partials;
@@ -274,7 +275,7 @@ __global__ void __launch_bounds__(256) adjoint_seed(const SeedArgs g)
             const double *P = g.phi[s];
             const double c = P[n];
             const double lap = ((P[xp] - 2.0 * c + P[xm]) + (P[yp] - 2.0 * c + P[ym]) + (P[zp] - 2.0 * c + P[zm])) * g.inv_dx2;
-            const double wsel = s == 1 ? 1.0 : 0.0;
+            const double wsel = s == g.field ? 1.0 : 0.0;
             g.lphi[s][n] = (wsel * (-lap) * g.ia2 - g.O * (-lap * g.ia2 + dV[s])) * g.inv_vrho;
             g.lpi[s][n] = (wsel - g.O) * g.pi[s][n] * g.ia6 * g.inv_vrho;
         }

@@ -51,7 +51,8 @@ class LatEnergies(C.Structure):
 KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1", "adjoint"]
 
 
-OBSERVABLES = {"chi_fraction": 0, "spectrum_bin": 1}
+# observable name -> (enum lat_observable, field forced by the name or None)
+OBSERVABLES = {"chi_fraction": (0, 1), "energy_fraction": (0, None), "spectrum_bin": (1, None)}
 
 
 class LatGradSpec(C.Structure):
@@ -232,11 +233,14 @@ class Lattice:
              observable: str = "chi_fraction", field: int = 0, bin: int = 0) -> dict:
         """An observable after nsteps and its gradient with respect to the current
         phi, pi (both fields) and q (hand-written adjoint in the library).
-        observable: "chi_fraction", the energy fraction in chi, or
-        "spectrum_bin", Delta(bin) of field `field` (eq. discretePS)."""
+        observable: "chi_fraction", the energy fraction in chi; "energy_fraction",
+        that of field `field`; "spectrum_bin", Delta(bin) of field `field`
+        (eq. discretePS)."""
         torch = self._torch
         N = self.params.N
-        kind = OBSERVABLES[observable]
+        kind, forced = OBSERVABLES[observable]
+        if forced is not None:
+            field = forced
         spec = LatGradSpec(kind, int(field), int(nsteps), int(stride), int(bin), 0)
         out = LatGradOut()
         gphi = [torch.empty(N ** 3, dtype=torch.float64, device="cuda") for _ in range(2)] if want_phi else None

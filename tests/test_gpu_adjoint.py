@@ -226,8 +226,9 @@ def test_spectrum_bin_autograd_and_bad_selection():
     for field, b in ((2, 1), (-1, 1), (0, 0), (0, bmax + 1)):
         with pytest.raises(LatticeError):
             lat.grad(T, observable="spectrum_bin", field=field, bin=b)
-    with pytest.raises(LatticeError):
-        lat.grad(T, observable="chi_fraction", field=1)
+    for bad in (dict(field=2), dict(field=0, bin=3)):
+        with pytest.raises(LatticeError):
+            lat.grad(T, observable="energy_fraction", **bad)
     r = lat.grad(T, observable="spectrum_bin", field=1, bin=bmax)   # the outermost shell is valid
     assert np.isfinite(r["value"]) and r["value"] >= 0.0
     lat.close()
@@ -260,7 +261,7 @@ def test_grad_fixed_background_matches_oracle_adjoint(N, T, stride, alpha, obs):
     lat = Lattice(tp, tq, **kw_fixed(wl, N, alpha, t0))
     sel = dict(field=1, bin=3) if obs == "spectrum_bin" else {}
     r = lat.grad(T, stride=stride, observable=obs, **sel)
-    kind = oracle.OBS_SPECTRUM_BIN if obs == "spectrum_bin" else oracle.OBS_CHI_FRACTION
+    kind = oracle.OBS_SPECTRUM_BIN if obs == "spectrum_bin" else oracle.OBS_ENERGY_FRACTION
     O, g, gp, dq = oracle.adjoint_vv2(oracle_fixed(wl, N, alpha), phi, pi, T, kind=kind, t=t0, **sel)
     say(f"[adj]   O={r['value']:.6e} (oracle {O:.6e}) dO/dq={r['dO_dq']:.6e} (oracle {dq:.6e})")
     assert abs(r["value"] - O) <= 1e-12 * abs(O)
@@ -314,3 +315,29 @@ def test_grad_fixed_background_full_workload_vs_finite_differences():
         rel = abs(rich - ad) / abs(ad)
         say(f"[adj] fixed dir {k}: adjoint {ad:.10e} fd {rich:.10e} rel {rel:.2e}")
         assert rel <= 1e-6
+
+
+@pytest.mark.parametrize("N,T,expansion", [(16, 20, "none"), (24, 17, "fixed")])
+def test_energy_fraction_of_phi_matches_oracle(N, T, expansion):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields(N=N)
+    say(f"[adj] energy fraction of phi N={N} T={T} {expansion}")
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    fixed = expansion == "fixed"
+    lat = Lattice(tp, tq, **(kw_fixed(wl, N) if fixed else kw_of(wl, N)))
+    r = lat.grad(T, observable="energy_fraction", field=0)
+    m = oracle_fixed(wl, N) if fixed else oracle.ScalarModel(
+        N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2, expansion=oracle.NONE,
+        integrator=oracle.VV2, lam=wl.lam, q=wl.q)
+    O, g, gp, dq = oracle.adjoint_vv2(m, phi, pi, T, field=0, t=0.25 if fixed else 0.0)
+    say(f"[adj]   O={r['value']:.6e} (oracle {O:.6e}) dO/dq={r['dO_dq']:.6e} (oracle {dq:.6e})")
+    assert abs(r["value"] - O) <= 1e-12 * abs(O)
+    for s in range(2):
+        assert rel_maxdiff(r["dO_dphi"][s].cpu().numpy(), g[s]) <= 1e-10
+        assert rel_maxdiff(r["dO_dpi"][s].cpu().numpy(), gp[s]) <= 1e-10
+    assert abs(r["dO_dq"] - dq) <= 1e-10 * abs(dq)
+    with pytest.raises(Exception):
+        lat.grad(T, observable="energy_fraction", field=0, bin=2)
+    lat.close()
