@@ -291,6 +291,12 @@ def main():
     sp = lat.spectrum(0, "phi")
     spectrum = {"ms": 1e3 * (time.perf_counter() - c0), "bins": len(sp["sum"]), "field": "phi",
                 "includes": "copy to the transform buffer, float64 real-to-complex FFT, binning, host copy"}
+    # occupation number of chi (two transforms, binning, <phi^2> reduction, host copy)
+    lat.occupation(1)                 # second half-spectrum buffer on the first call
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    lat.occupation(1)
+    spectrum["occupation_ms"] = 1e3 * (time.perf_counter() - c0)
 
     # float32-fields mode on the same workload
     f32 = None
