@@ -252,6 +252,8 @@ typedef struct lat_grad_out {
     void *dO_dpi[2];             /* caller-owned device arrays for dO/dpi_s(0); NULL skips */
     double forward_ms;           /* duration of the forward sweep (HIP events) */
     double reverse_ms;           /* duration of the reverse sweep (HIP events) */
+    double dO_da0, dO_db0;       /* self-consistent expansion: dO/da and dO/da' at the start, a' held
+                                    as an independent input (0 otherwise) */
 } lat_grad_out;
 
 /* Gradient of an observable of the state after T steps with respect to the
@@ -261,10 +263,14 @@ typedef struct lat_grad_out {
  * T, and a reverse sweep that integrates the state backward together with the
  * adjoint, re-anchoring the state at every stored checkpoint.  On return the
  * fields hold their initial values again.  Provided for LAT_PHI4_CHI2 with
- * LAT_VV2, LAT_PREC_F64 and LAT_EXP_NONE or LAT_EXP_FIXED (LAT_EUNSUPPORTED
- * otherwise).  On a fixed background the steps run from the context's current
- * time, kicks use a^{1+alpha} and a^{3+alpha} at the kick time, drifts
- * a^{alpha-3} at the midpoint, and the energies of O are those at a(T).  The
+ * LAT_VV2 and LAT_PREC_F64, any expansion (LAT_EUNSUPPORTED otherwise).  On a
+ * fixed background the steps run from the context's current time, kicks use
+ * a^{1+alpha} and a^{3+alpha} at the kick time, drifts a^{alpha-3} at the
+ * midpoint, and the energies of O are those at a(T).  With the self-consistent
+ * expansion the forward sweep is the library's own step; a and a' at the
+ * start are independent inputs (dO_da0, dO_db0; a caller whose a' comes from
+ * the Hubble constraint adds dO_db0 times its derivative), and the scale
+ * factor, a', time and step count are restored on return.  The
  * library allocates the checkpoints (T/stride + 1 copies of the state) and the
  * adjoint arrays on first use and keeps them until lattice_destroy.
  * LAT_OBS_SPECTRUM_BIN seeds the adjoint with dDelta(b)/dphi_s: the

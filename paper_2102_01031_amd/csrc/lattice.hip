@@ -33,6 +33,7 @@
 #include "stage_adjoint.hpp"
 #include "stage_batch.hpp"
 #include "spectrum.hpp"
+#include "stage_adjoint_self.hpp"
 
 using namespace lat;
 
@@ -132,6 +133,10 @@ struct lat_ctx {
     size_t ckpt_count = 0;
     double *adj_partials = nullptr;
     size_t adj_partial_cap = 0;
+    double *self_seg = nullptr;         // self-consistent adjoint: the states of one segment
+    size_t self_seg_cap = 0;            // (in states)
+    double *self_part = nullptr;        // its per-block partials and totals
+    size_t self_part_cap = 0;
     // batch of independent lattices
     bool batch = false;
     std::vector<lat_ctx *> subs;
@@ -871,6 +876,8 @@ void free_ctx(lat_ctx *c)
                 if (c->lam[k][f][b]) (void)hipFree(c->lam[k][f][b]);
     if (c->ckpt) (void)hipFree(c->ckpt);
     if (c->adj_partials) (void)hipFree(c->adj_partials);
+    if (c->self_seg) (void)hipFree(c->self_seg);
+    if (c->self_part) (void)hipFree(c->self_part);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     drop_step_graphs(c);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -1560,10 +1567,9 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     const bool spec_obs = spec->observable == LAT_OBS_SPECTRUM_BIN;
     if (spec->observable != LAT_OBS_ENERGY_FRACTION && !spec_obs)
         return fail(c, LAT_EINVAL, "unknown observable");
-    if (c->batch || c->u1 || c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 ||
-        c->p.expansion == LAT_EXP_SELF || c->f32)
-        return fail(c, LAT_EUNSUPPORTED,
-                    "lattice_grad needs two fields, VV2, no or a fixed expansion, and float64");
+    if (c->batch || c->u1 || c->p.potential != LAT_PHI4_CHI2 || c->p.integrator != LAT_VV2 || c->f32)
+        return fail(c, LAT_EUNSUPPORTED, "lattice_grad needs two fields, VV2 and float64");
+    const bool self = c->p.expansion == LAT_EXP_SELF;
     if (spec->reserved != 0) return fail(c, LAT_EINVAL, "reserved field of lat_grad_spec must be 0");
     if (spec->field < 0 || spec->field > 1) return fail(c, LAT_EINVAL, "observable field out of range");
     if (spec_obs) {
@@ -1621,6 +1627,29 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
         }
         c->adj_partial_cap = need;
     }
+    const int nbk = seed_blocks;   // one site per thread, 256 per block
+    if (self) {
+        const size_t seg_states = (size_t)k + 1;
+        if (seg_states > c->self_seg_cap) {
+            if (c->self_seg) HIPCHK(c, hipFree(c->self_seg));
+            c->self_seg = nullptr;
+            if (hipMalloc(&c->self_seg, seg_states * 4 * bytes) != hipSuccess) {
+                c->self_seg_cap = 0;
+                return fail(c, LAT_ENOMEM, "segment state allocation failed");
+            }
+            c->self_seg_cap = seg_states;
+        }
+        const size_t pneed = (size_t)4 * nbk + 32;
+        if (pneed > c->self_part_cap) {
+            if (c->self_part) HIPCHK(c, hipFree(c->self_part));
+            c->self_part = nullptr;
+            if (hipMalloc(&c->self_part, pneed * sizeof(double)) != hipSuccess) {
+                c->self_part_cap = 0;
+                return fail(c, LAT_ENOMEM, "partials allocation failed");
+            }
+            c->self_part_cap = pneed;
+        }
+    }
     hipEvent_t e0, e1, e2;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -1649,26 +1678,54 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     // ---- forward sweep (leapfrog form of T VV2 steps) with checkpoints
     HIPCHK(c, hipEventRecord(e0, c->stream));
     GCHK(checkpoint_io(c, 0, true));
-    GCHK(reserve_coef(c, (size_t)T + 3));
-    for (int64_t p = 0; p <= T; ++p) {
-        PassCoef &P = c->coef_host[p];
-        P.ka1 = kick_l(p);
-        P.ka3 = kick_v(p);
-        P.c1 = p > 0 ? 0.5 * h : 0.0;
-        P.c2 = p < T ? 0.5 * h : 0.0;
-        P.dend = p < T ? h * drift_d(p) : 0.0;
+    // self-consistent expansion: the library's own VV2 step, one at a time, with
+    // the scale factor and a' of every step and the scale record of every
+    // checkpoint kept on the host
+    std::vector<double> traj_a, traj_b;
+    std::vector<ScaleRecord> recs;
+    const int64_t step_save = c->step;
+    if (self) {
+        traj_a.resize((size_t)T + 1);
+        traj_b.resize((size_t)T + 1);
+        recs.resize(ncp);
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        recs[0] = *c->sc_host;
+        traj_a[0] = c->sc_host->a;
+        traj_b[0] = c->sc_host->b;
+        for (int64_t p = 0; p < T; ++p) {
+            GCHK(step_vv(c, 1, 1));
+            HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            traj_a[(size_t)p + 1] = c->sc_host->a;
+            traj_b[(size_t)p + 1] = c->sc_host->b;
+            if ((p + 1) % k == 0 && p + 1 < T) {
+                GCHK(checkpoint_io(c, (size_t)((p + 1) / k), true));
+                recs[(size_t)((p + 1) / k)] = *c->sc_host;
+            }
+        }
+    } else {
+        GCHK(reserve_coef(c, (size_t)T + 3));
+        for (int64_t p = 0; p <= T; ++p) {
+            PassCoef &P = c->coef_host[p];
+            P.ka1 = kick_l(p);
+            P.ka3 = kick_v(p);
+            P.c1 = p > 0 ? 0.5 * h : 0.0;
+            P.c2 = p < T ? 0.5 * h : 0.0;
+            P.dend = p < T ? h * drift_d(p) : 0.0;
+        }
+        GCHK(upload_coef(c, (size_t)T + 1));
+        for (int64_t p = 0; p < T; ++p) {
+            GCHK(run_pass(c, kKickDrift, (int)p, kLastStore));
+            if ((p + 1) % k == 0 && p + 1 < T) GCHK(checkpoint_io(c, (size_t)((p + 1) / k), true));
+        }
+        GCHK(run_pass(c, kKickOnly, (int)T, kLastStore));   // closing half kick: (phi_T, pi_T)
     }
-    GCHK(upload_coef(c, (size_t)T + 1));
-    for (int64_t p = 0; p < T; ++p) {
-        GCHK(run_pass(c, kKickDrift, (int)p, kLastStore));
-        if ((p + 1) % k == 0 && p + 1 < T) GCHK(checkpoint_io(c, (size_t)((p + 1) / k), true));
-    }
-    GCHK(run_pass(c, kKickOnly, (int)T, kLastStore));   // closing half kick: (phi_T, pi_T)
     HIPCHK(c, hipEventRecord(e1, c->stream));
 
     // ---- observable and seed
     const double V = (double)c->vol;
-    double O = 0.0, rho = 0.0, cb = 0.0;
+    double O = 0.0, rho = 0.0, cb = 0.0, la_T = 0.0;
     if (spec_obs) {
         // dO/dphi_s = inverse transform of the shell-b half spectrum scaled by
         // 2 c_b; every other adjoint array starts at zero; O has no explicit q
@@ -1698,7 +1755,7 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     } else {
         GCHK(energy_sums(c, 0.0));
         const double *S = c->sc_host->sums;
-        const double aT = scale_at(c, t_start + (double)T * h);
+        const double aT = self ? traj_a[(size_t)T] : scale_at(c, t_start + (double)T * h);
         const double ia2 = 1.0 / (aT * aT), ia6 = ia2 * ia2 * ia2;
         double EK[2], EG[2];
         for (int f = 0; f < 2; ++f) {
@@ -1707,6 +1764,11 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
         }
         rho = EK[0] + EK[1] + EG[0] + EG[1] + S[4] / V + S[5] / V;
         O = (EK[spec->field] + EG[spec->field]) / rho;
+        // dO/da(T) at fixed fields: E_K ~ a^-6, E_G ~ a^-2
+        const int fo = spec->field;
+        const double dX = -(6.0 * EK[fo] + 2.0 * EG[fo]) / aT;
+        const double drho = -(6.0 * (EK[0] + EK[1]) + 2.0 * (EG[0] + EG[1])) / aT;
+        la_T = (dX - O * drho) / rho;
         hipLaunchKernelGGL(zero_doubles, dim3(1), dim3(64), 0, c->stream, &c->sc->sums[kMaxQ - 2], 2);
         HIPCHK(c, hipGetLastError());
         SeedArgs a{};
@@ -1733,11 +1795,168 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     }
 
     // ---- reverse sweep
-    GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, kick_l(T), kick_v(T), nb, zc, tiles_x, tiles_y));   // closing half kick
-    for (int64_t p = T - 1; p >= 0; --p) {
-        const double d = h * drift_d(p);
-        GCHK(adj_pass(c, -d, d, p > 0 ? 0.5 * h : 0.0, 0.5 * h, kick_l(p), kick_v(p), nb, zc, tiles_x, tiles_y));
-        if (p % k == 0) GCHK(checkpoint_io(c, (size_t)(p / k), false));
+    double la = la_T, lb = 0.0, dq_self = 0.0, seed_sum = 0.0;
+    if (!self) {
+        GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, kick_l(T), kick_v(T), nb, zc, tiles_x, tiles_y));   // closing half kick
+        for (int64_t p = T - 1; p >= 0; --p) {
+            const double d = h * drift_d(p);
+            GCHK(adj_pass(c, -d, d, p > 0 ? 0.5 * h : 0.0, 0.5 * h, kick_l(p), kick_v(p), nb, zc, tiles_x, tiles_y));
+            if (p % k == 0) GCHK(checkpoint_io(c, (size_t)(p / k), false));
+        }
+    } else {
+        // Self-consistent expansion, step by step in reverse (steps (6) ... (1) of
+        // stage_adjoint_self.hpp): the states of each segment are re-run from its
+        // checkpoint and kept; field pieces run on the device, the adjoints of a
+        // and b on the host from fixed-order device sums.
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        seed_sum = c->sc_host->sums[kMaxQ - 2];
+        const double al = c->p.alpha, kap = c->p.kappa2, idx2 = 1.0 / (c->p.dx * c->p.dx);
+        double *part = c->self_part, *tot = c->self_part + (size_t)4 * nbk;
+        double host[16];
+        auto state = [&](int64_t j, int which, int f) {
+            return c->self_seg + ((size_t)j * 4 + (size_t)(2 * which + f)) * c->vol;
+        };
+        auto args = [&](int64_t j) {
+            SelfAdjArgs g{};
+            for (int f = 0; f < 2; ++f) {
+                g.phi[f] = state(j, 0, f);
+                g.pi[f] = state(j, 1, f);
+                g.lphi[f] = (double *)c->lam[0][f][c->cur_lam[0][f]];
+                g.lpi[f] = (double *)c->lam[1][f][c->cur_lam[1][f]];
+            }
+            g.N = N;
+            g.inv_dx2 = idx2;
+            g.lam = c->p.lambda;
+            g.q = c->p.q;
+            g.part = part;
+            return g;
+        };
+        auto reduce = [&](int nq, int off) -> lat_status {
+            HIPCHK(c, hipGetLastError());
+            hipLaunchKernelGGL(self_adj_reduce, dim3(1), dim3(64), 0, c->stream, (const double *)part, nbk, nq,
+                               tot + off);
+            HIPCHK(c, hipGetLastError());
+            return LAT_OK;
+        };
+        auto fetch = [&](int n) -> lat_status {
+            HIPCHK(c, hipMemcpyAsync(host, tot, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            return LAT_OK;
+        };
+        auto keep = [&](int64_t j) -> lat_status {
+            for (int f = 0; f < 2; ++f) {
+                HIPCHK(c, hipMemcpyAsync(state(j, 0, f), c->phi[f][c->cur_phi[f]], bytes, hipMemcpyDeviceToDevice,
+                                         c->stream));
+                HIPCHK(c, hipMemcpyAsync(state(j, 1, f), c->pi[f][c->cur_pi[f]], bytes, hipMemcpyDeviceToDevice,
+                                         c->stream));
+            }
+            return LAT_OK;
+        };
+        // K_a = C Q from the energy sums S = (sum pi^2, sum |grad+ phi|^2, sum V, sum phi^2 chi^2 / 2)
+        struct KaTerms {
+            double C, dKda, dKdq, ia2, ia6;
+        };
+        auto ka_terms = [&](double a, const double *S4) {
+            KaTerms r;
+            r.ia2 = 1.0 / (a * a);
+            r.ia6 = r.ia2 * r.ia2 * r.ia2;
+            const double EKt = S4[0] / (2.0 * V) * r.ia6, EGt = S4[1] / (2.0 * V) * r.ia2, EVt = S4[2] / V;
+            r.C = std::pow(a, 2.0 * al + 1.0) / 3.0 * kap;
+            const double Q = (al - 2.0) * EKt + al * EGt + (al + 1.0) * EVt;
+            r.dKda = (2.0 * al + 1.0) * r.C * Q / a + r.C * ((al - 2.0) * (-6.0) * EKt / a + al * (-2.0) * EGt / a);
+            r.dKdq = r.C * (al + 1.0) * S4[3] / V;
+            return r;
+        };
+        const dim3 grid((unsigned)nbk), blk(kSelfAdjThreads);
+        for (int64_t s0 = ((T - 1) / k) * k; s0 >= 0; s0 -= k) {
+            const int64_t s1 = std::min<int64_t>(s0 + k, T);
+            GCHK(checkpoint_io(c, (size_t)(s0 / k), false));
+            *c->sc_host = recs[(size_t)(s0 / k)];
+            HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            c->t = t_start + (double)s0 * h;
+            GCHK(keep(0));
+            for (int64_t n = s0; n < s1; ++n) {
+                GCHK(step_vv(c, 1, 1));
+                GCHK(keep(n + 1 - s0));
+            }
+            for (int64_t n = s1 - 1; n >= s0; --n) {
+                const double a0 = traj_a[(size_t)n], a1 = traj_a[(size_t)n + 1], abar = 0.5 * (a0 + a1);
+                const SelfAdjArgs g1 = args(n + 1 - s0), g0 = args(n - s0);
+                hipLaunchKernelGGL(self_adj_energy, grid, blk, 0, c->stream, g1);
+                GCHK(reduce(4, 0));
+                hipLaunchKernelGGL(self_adj_energy, grid, blk, 0, c->stream, g0);
+                GCHK(reduce(4, 4));
+                GCHK(fetch(8));
+                const KaTerms k1 = ka_terms(a1, host), k0 = ka_terms(a0, host + 4);
+                double la1 = la;
+                {   // (6) b kick at n + 1
+                    const double wl = 0.5 * h * lb;
+                    SelfAdjArgs g = g1;
+                    g.c0 = wl * k1.C * al * k1.ia2 / V;
+                    g.c1 = wl * k1.C * (al + 1.0) / V;
+                    g.c2 = wl * k1.C * (al - 2.0) * k1.ia6 / V;
+                    hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g);
+                    HIPCHK(c, hipGetLastError());
+                    la1 += wl * k1.dKda;
+                    dq_self += wl * k1.dKdq;
+                }
+                {   // (5) field kick at n + 1
+                    SelfAdjArgs g = g1;
+                    g.c0 = 0.5 * h * std::pow(a1, 1.0 + al);
+                    g.c1 = 0.5 * h * std::pow(a1, 3.0 + al);
+                    hipLaunchKernelGGL(self_adj_kick, grid, blk, 0, c->stream, g);
+                    GCHK(reduce(3, 8));
+                }
+                {   // (4) drift
+                    SelfDriftArgs d{};
+                    d.g = g0;
+                    d.g.c0 = 0.5 * h;
+                    d.g.c1 = std::pow(a0, 1.0 + al);
+                    d.g.c2 = std::pow(a0, 3.0 + al);
+                    d.dr = h * std::pow(abar, al - 3.0);
+                    hipLaunchKernelGGL(self_adj_drift, grid, blk, 0, c->stream, d);
+                    GCHK(reduce(1, 11));
+                }
+                GCHK(fetch(12));
+                la1 += 0.5 * h * ((1.0 + al) * std::pow(a1, al) * host[8] - (3.0 + al) * std::pow(a1, 2.0 + al) * host[9]);
+                dq_self += 0.5 * h * std::pow(a1, 3.0 + al) * host[10];
+                const double labar = h * (al - 3.0) * std::pow(abar, al - 4.0) * host[11];
+                la1 += 0.5 * labar;
+                double la0 = 0.5 * labar;
+                la0 += la1;   // (3) a1 = a_n + h b'
+                lb += h * la1;
+                {   // (1) field kick at n
+                    SelfAdjArgs g = g0;
+                    g.c0 = 0.5 * h * std::pow(a0, 1.0 + al);
+                    g.c1 = 0.5 * h * std::pow(a0, 3.0 + al);
+                    hipLaunchKernelGGL(self_adj_kick, grid, blk, 0, c->stream, g);
+                    GCHK(reduce(3, 12));
+                }
+                {   // (2) b kick at n
+                    const double wl = 0.5 * h * lb;
+                    SelfAdjArgs g = g0;
+                    g.c0 = wl * k0.C * al * k0.ia2 / V;
+                    g.c1 = wl * k0.C * (al + 1.0) / V;
+                    g.c2 = wl * k0.C * (al - 2.0) * k0.ia6 / V;
+                    hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g);
+                    HIPCHK(c, hipGetLastError());
+                    la0 += wl * k0.dKda;
+                    dq_self += wl * k0.dKdq;
+                }
+                GCHK(fetch(15));
+                la0 += 0.5 * h * ((1.0 + al) * std::pow(a0, al) * host[12] - (3.0 + al) * std::pow(a0, 2.0 + al) * host[13]);
+                dq_self += 0.5 * h * std::pow(a0, 3.0 + al) * host[14];
+                la = la0;
+            }
+        }
+        // the initial state, scale record, time and step count again
+        GCHK(checkpoint_io(c, 0, false));
+        *c->sc_host = recs[0];
+        HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream));
+        c->t = t_start;
+        c->step = step_save;
     }
     HIPCHK(c, hipEventRecord(e2, c->stream));
 
@@ -1756,16 +1975,20 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     float fms = 0.f, rms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
     HIPCHK(c, hipEventElapsedTime(&rms, e1, e2));
-    const double dq_adj = c->sc_host->sums[kMaxQ - 1];
+    // the seed left sums[kMaxQ - 2] (shell power, or sum phi^2 chi^2 / 2); the
+    // reverse sweep accumulated the coupling sensitivity in sums[kMaxQ - 1]
+    // (self-consistent expansion: on the host)
+    const double dq_adj = self ? dq_self : c->sc_host->sums[kMaxQ - 1];
+    const double sum_seed = self ? seed_sum : c->sc_host->sums[kMaxQ - 2];
     if (spec_obs) {
-        // sums[kMaxQ - 2] holds the shell's sum of |F|^2
-        out->value = cb * c->sc_host->sums[kMaxQ - 2];
+        out->value = cb * sum_seed;
         out->dO_dq = dq_adj;
     } else {
-        const double sum_p2c2 = c->sc_host->sums[kMaxQ - 2];
         out->value = O;
-        out->dO_dq = dq_adj - O * (sum_p2c2 / V) / rho;
+        out->dO_dq = dq_adj - O * (sum_seed / V) / rho;
     }
+    out->dO_da0 = self ? la : 0.0;
+    out->dO_db0 = self ? lb : 0.0;
     out->forward_ms = fms;
     out->reverse_ms = rms;
     cleanup();

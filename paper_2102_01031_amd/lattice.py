@@ -62,7 +62,8 @@ class LatGradSpec(C.Structure):
 
 class LatGradOut(C.Structure):
     _fields_ = [("value", C.c_double), ("dO_dq", C.c_double), ("dO_dphi", C.c_void_p * 2),
-                ("dO_dpi", C.c_void_p * 2), ("forward_ms", C.c_double), ("reverse_ms", C.c_double)]
+                ("dO_dpi", C.c_void_p * 2), ("forward_ms", C.c_double), ("reverse_ms", C.c_double),
+                ("dO_da0", C.c_double), ("dO_db0", C.c_double)]
 
 
 class LatStats(C.Structure):
@@ -250,7 +251,7 @@ class Lattice:
             out.dO_dpi[i] = gpi[i].data_ptr() if gpi else None
         _check(lib().lattice_grad(self._ctx, C.byref(spec), C.byref(out)), self._ctx)
         return dict(value=out.value, dO_dq=out.dO_dq, dO_dphi=gphi, dO_dpi=gpi, forward_ms=out.forward_ms,
-                    reverse_ms=out.reverse_ms)
+                    reverse_ms=out.reverse_ms, dO_da0=out.dO_da0, dO_db0=out.dO_db0)
 
     def profile(self, enable: bool = True):
         _check(lib().lattice_profile(self._ctx, 1 if enable else 0), self._ctx)

@@ -341,3 +341,106 @@ def test_energy_fraction_of_phi_matches_oracle(N, T, expansion):
     with pytest.raises(Exception):
         lat.grad(T, observable="energy_fraction", field=0, bin=2)
     lat.close()
+
+
+# Self-consistent expansion: the library's own VV2 step with a and a' evolving;
+# a' at the start is an independent input (passed explicitly, here from the
+# oracle's Hubble constraint).
+
+def kw_self(wl, N, alpha=1.0, kappa2=4.0, b0=None, q=None):
+    kw = kw_of(wl, N, q)
+    kw.update(expansion="self", kappa2=kappa2, a0=1.0, alpha=alpha)
+    if b0 is not None:
+        kw["b0"] = b0
+    return kw
+
+
+def oracle_self(wl, N, alpha=1.0, kappa2=4.0, q=None):
+    return oracle.ScalarModel(N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2,
+                              expansion=oracle.SELF, integrator=oracle.VV2, lam=wl.lam, q=wl.q if q is None else q,
+                              alpha=alpha, kappa2=kappa2)
+
+
+@pytest.mark.parametrize("N,T,stride,alpha,obs,field,b", [(12, 10, 0, 1.0, "energy_fraction", 1, 0),
+                                                           (16, 15, 4, 0.5, "energy_fraction", 0, 0),
+                                                           (13, 8, 1, 1.0, "spectrum_bin", 1, 2)])
+def test_grad_self_consistent_matches_oracle_adjoint(N, T, stride, alpha, obs, field, b):
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields(N=N)
+    m = oracle_self(wl, N, alpha)
+    b0 = oracle.hubble_b0(m, phi, pi, 1.0)
+    say(f"[adj] self-consistent oracle parity N={N} T={T} stride={stride} alpha={alpha} {obs} field={field}")
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_self(wl, N, alpha, b0=b0))
+    e0 = lat.energy()
+    r = lat.grad(T, stride=stride, observable=obs, field=field, bin=b)
+    kind = oracle.OBS_SPECTRUM_BIN if obs == "spectrum_bin" else oracle.OBS_ENERGY_FRACTION
+    O, g, gp, dq, da0, db0 = oracle.adjoint_vv2_self(m, phi, pi, 1.0, b0, T, kind=kind, field=field, bin=b)
+    say(f"[adj]   O={r['value']:.6e} (oracle {O:.6e}) dO/dq={r['dO_dq']:.6e} ({dq:.6e}) "
+        f"dO/da0={r['dO_da0']:.6e} ({da0:.6e}) dO/db0={r['dO_db0']:.6e} ({db0:.6e})")
+    assert abs(r["value"] - O) <= 1e-12 * abs(O)
+    for s in range(2):
+        assert rel_maxdiff(r["dO_dphi"][s].cpu().numpy(), g[s]) <= 1e-10
+        assert rel_maxdiff(r["dO_dpi"][s].cpu().numpy(), gp[s]) <= 1e-10
+    assert abs(r["dO_dq"] - dq) <= 1e-10 * abs(dq)
+    assert abs(r["dO_da0"] - da0) <= 1e-10 * abs(da0)
+    assert abs(r["dO_db0"] - db0) <= 1e-10 * abs(db0)
+    # state, scale factor, time and step count as before the call
+    for s in range(2):
+        assert np.array_equal(tp[s].cpu().numpy(), phi[s].reshape(-1))
+        assert np.array_equal(tq[s].cpu().numpy(), pi[s].reshape(-1))
+    e1 = lat.energy()
+    assert (e1["a"], e1["b"], e1["t"], e1["step"]) == (e0["a"], e0["b"], e0["t"], e0["step"])
+    lat.close()
+
+
+def test_grad_self_consistent_full_workload_vs_finite_differences():
+    """64^3 x 2000 VV2 steps with the self-consistent expansion (kappa^2 of the
+    preheating runs), chi energy fraction at the final a, against differences
+    of the library's own forward run in (delta phi, q, a0, a'0)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    N, T = wl.N, wl.steps
+    phi, pi = wl.initial_fields()
+    kap = 0.25
+    b0 = oracle.hubble_b0(oracle_self(wl, N, kappa2=kap), phi, pi, 1.0)
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **kw_self(wl, N, kappa2=kap, b0=b0))
+    r = lat.grad(T)
+    g = r["dO_dphi"][0].cpu().numpy().reshape(N, N, N)
+    O0 = r["value"]
+    say(f"[adj] self-consistent full workload: O={O0:.6e} dO/dq={r['dO_dq']:.6e} dO/da0={r['dO_da0']:.6e} "
+        f"dO/db0={r['dO_db0']:.6e} forward {r['forward_ms']:.1f} ms reverse {r['reverse_ms']:.1f} ms")
+    lat.close()
+
+    def O_fwd(phi_, q_, a_, b_):
+        tp_, tq_ = to_dev(phi_, torch.float64), to_dev(pi, torch.float64)
+        kw = kw_self(wl, N, kappa2=kap, b0=b_, q=q_)
+        kw["a0"] = a_
+        lt = Lattice(tp_, tq_, **kw)
+        lt.step(T)
+        e = lt.energy()
+        lt.close()
+        return (e["EK"][1] + e["EG"][1]) / e["rho"]
+
+    assert abs(O_fwd(phi, wl.q, 1.0, b0) - O0) <= 1e-12 * abs(O0)
+    rng = np.random.default_rng(37)
+    dirs = inputs.random_directions(3, N, seed=31)
+    for k, (v, _) in enumerate(dirs):
+        w = rng.standard_normal(3)
+        w *= 0.5 / np.linalg.norm(w)
+        ad = float(np.sum(g * v) + r["dO_dq"] * w[0] + r["dO_da0"] * w[1] + r["dO_db0"] * w[2])
+
+        def fd(eps):
+            return (O_fwd([phi[0] + eps * v, phi[1]], wl.q + eps * w[0], 1.0 + eps * w[1], b0 + eps * w[2])
+                    - O_fwd([phi[0] - eps * v, phi[1]], wl.q - eps * w[0], 1.0 - eps * w[1], b0 - eps * w[2])) / (2 * eps)
+
+        # steps smaller than the other workloads': a0 and a'0 move the whole run
+        d1, d2 = fd(1e-3), fd(5e-4)
+        rich = (4 * d2 - d1) / 3
+        rel = abs(rich - ad) / abs(ad)
+        say(f"[adj] self-consistent dir {k}: adjoint {ad:.10e} fd {rich:.10e} rel {rel:.2e}")
+        assert rel <= 1e-6
