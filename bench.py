@@ -121,6 +121,19 @@ def run_extras(args, log, only=None):
                           "forward_pass_us": fus, "adjoint_pass_us": aus}
         lat.close()
         log(f"[bench] adjoint: reverse/forward {r['reverse_ms'] / r['forward_ms']:.2f}, per pass {aus / fus:.2f}")
+        # the same workload with the self-consistent expansion (kappa^2 = 0.25):
+        # step-by-step forward and reverse
+        tp = [torch.tensor(f.reshape(-1), device=dev) for f in phi]
+        tq = [torch.tensor(f.reshape(-1), device=dev) for f in pi]
+        ls = Lattice(tp, tq, N=wl.N, dx=wl.dx, dt=wl.dt, integrator="vv2", expansion="self", potential="phi4_chi2",
+                     lam=wl.lam, q=wl.q, kappa2=0.25)
+        rs = ls.grad(wl.steps)
+        res["adjoint_self"] = {"workload": wl.name + " self-consistent expansion", "steps": wl.steps,
+                               "value": rs["value"], "dO_dq": rs["dO_dq"], "dO_da0": rs["dO_da0"],
+                               "dO_db0": rs["dO_db0"], "forward_ms": rs["forward_ms"], "reverse_ms": rs["reverse_ms"],
+                               "ratio_reverse_over_forward": rs["reverse_ms"] / rs["forward_ms"]}
+        ls.close()
+        log(f"[bench] adjoint, self-consistent: forward {rs['forward_ms']:.1f} ms, reverse {rs['reverse_ms']:.1f} ms")
     if only in (None, "u1"):
         # U(1) gauge + complex scalar, 128^3, leapfrog: ten N^3 float64 arrays, each
         # read once and written once per step (160 B per site)
