@@ -137,6 +137,8 @@ struct lat_ctx {
     size_t self_seg_cap = 0;            // (in states)
     double *self_part = nullptr;        // its per-block partials and totals
     size_t self_part_cap = 0;
+    double *self_traj = nullptr;        // a, a' of every step, scale records of the checkpoints, scalars
+    size_t self_traj_cap = 0;           // (in doubles)
     // batch of independent lattices
     bool batch = false;
     std::vector<lat_ctx *> subs;
@@ -878,6 +880,7 @@ void free_ctx(lat_ctx *c)
     if (c->adj_partials) (void)hipFree(c->adj_partials);
     if (c->self_seg) (void)hipFree(c->self_seg);
     if (c->self_part) (void)hipFree(c->self_part);
+    if (c->self_traj) (void)hipFree(c->self_traj);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     drop_step_graphs(c);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -1639,6 +1642,17 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
             }
             c->self_seg_cap = seg_states;
         }
+        const size_t rec_d = (sizeof(ScaleRecord) + sizeof(double) - 1) / sizeof(double);
+        const size_t tneed = (size_t)2 * ((size_t)T + 1) + ncp * rec_d + 16;
+        if (tneed > c->self_traj_cap) {
+            if (c->self_traj) HIPCHK(c, hipFree(c->self_traj));
+            c->self_traj = nullptr;
+            if (hipMalloc(&c->self_traj, tneed * sizeof(double)) != hipSuccess) {
+                c->self_traj_cap = 0;
+                return fail(c, LAT_ENOMEM, "trajectory allocation failed");
+            }
+            c->self_traj_cap = tneed;
+        }
         const size_t pneed = (size_t)4 * nbk + 32;
         if (pneed > c->self_part_cap) {
             if (c->self_part) HIPCHK(c, hipFree(c->self_part));
@@ -1681,29 +1695,29 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     // self-consistent expansion: the library's own VV2 step, one at a time, with
     // the scale factor and a' of every step and the scale record of every
     // checkpoint kept on the host
-    std::vector<double> traj_a, traj_b;
-    std::vector<ScaleRecord> recs;
+    // device layout of self_traj: (a, a') per step, then the checkpoints' scale records
+    std::vector<double> traj_a;
     const int64_t step_save = c->step;
+    double *traj_dev = c->self_traj;
+    ScaleRecord *rec_dev = self ? (ScaleRecord *)(c->self_traj + 2 * ((size_t)T + 1)) : nullptr;
     if (self) {
-        traj_a.resize((size_t)T + 1);
-        traj_b.resize((size_t)T + 1);
-        recs.resize(ncp);
-        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        recs[0] = *c->sc_host;
-        traj_a[0] = c->sc_host->a;
-        traj_b[0] = c->sc_host->b;
+        HIPCHK(c, hipMemcpyAsync(traj_dev, &c->sc->a, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(rec_dev, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToDevice, c->stream));
         for (int64_t p = 0; p < T; ++p) {
             GCHK(step_vv(c, 1, 1));
-            HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            traj_a[(size_t)p + 1] = c->sc_host->a;
-            traj_b[(size_t)p + 1] = c->sc_host->b;
+            HIPCHK(c, hipMemcpyAsync(traj_dev + 2 * ((size_t)p + 1), &c->sc->a, 2 * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream));
             if ((p + 1) % k == 0 && p + 1 < T) {
                 GCHK(checkpoint_io(c, (size_t)((p + 1) / k), true));
-                recs[(size_t)((p + 1) / k)] = *c->sc_host;
+                HIPCHK(c, hipMemcpyAsync(rec_dev + (p + 1) / k, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToDevice,
+                                         c->stream));
             }
         }
+        std::vector<double> tr(2 * ((size_t)T + 1));
+        HIPCHK(c, hipMemcpyAsync(tr.data(), traj_dev, tr.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        traj_a.resize((size_t)T + 1);
+        for (size_t i = 0; i <= (size_t)T; ++i) traj_a[i] = tr[2 * i];
     } else {
         GCHK(reserve_coef(c, (size_t)T + 3));
         for (int64_t p = 0; p <= T; ++p) {
@@ -1806,14 +1820,20 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     } else {
         // Self-consistent expansion, step by step in reverse (steps (6) ... (1) of
         // stage_adjoint_self.hpp): the states of each segment are re-run from its
-        // checkpoint and kept; field pieces run on the device, the adjoints of a
-        // and b on the host from fixed-order device sums.
+        // checkpoint and kept; field pieces and the adjoints of a and b run on the
+        // device, from fixed-order device sums, with no host round trip per step.
         HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         seed_sum = c->sc_host->sums[kMaxQ - 2];
-        const double al = c->p.alpha, kap = c->p.kappa2, idx2 = 1.0 / (c->p.dx * c->p.dx);
+        const double al = c->p.alpha, idx2 = 1.0 / (c->p.dx * c->p.dx);
         double *part = c->self_part, *tot = c->self_part + (size_t)4 * nbk;
-        double host[16];
+        SelfScalars *scal = (SelfScalars *)(c->self_traj + (c->self_traj_cap - 16));
+        {
+            SelfScalars s0{};
+            s0.la = la_T;
+            HIPCHK(c, hipMemcpyAsync(scal, &s0, sizeof(s0), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
         auto state = [&](int64_t j, int which, int f) {
             return c->self_seg + ((size_t)j * 4 + (size_t)(2 * which + f)) * c->vol;
         };
@@ -1830,18 +1850,14 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
             g.lam = c->p.lambda;
             g.q = c->p.q;
             g.part = part;
+            g.dcoef = scal->bk;
             return g;
         };
         auto reduce = [&](int nq, int off) -> lat_status {
             HIPCHK(c, hipGetLastError());
-            hipLaunchKernelGGL(self_adj_reduce, dim3(1), dim3(64), 0, c->stream, (const double *)part, nbk, nq,
-                               tot + off);
+            hipLaunchKernelGGL(self_adj_reduce, dim3((unsigned)nq), dim3(kSelfAdjThreads), 0, c->stream,
+                               (const double *)part, nbk, nq, tot + off);
             HIPCHK(c, hipGetLastError());
-            return LAT_OK;
-        };
-        auto fetch = [&](int n) -> lat_status {
-            HIPCHK(c, hipMemcpyAsync(host, tot, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
             return LAT_OK;
         };
         auto keep = [&](int64_t j) -> lat_status {
@@ -1853,28 +1869,11 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
             }
             return LAT_OK;
         };
-        // K_a = C Q from the energy sums S = (sum pi^2, sum |grad+ phi|^2, sum V, sum phi^2 chi^2 / 2)
-        struct KaTerms {
-            double C, dKda, dKdq, ia2, ia6;
-        };
-        auto ka_terms = [&](double a, const double *S4) {
-            KaTerms r;
-            r.ia2 = 1.0 / (a * a);
-            r.ia6 = r.ia2 * r.ia2 * r.ia2;
-            const double EKt = S4[0] / (2.0 * V) * r.ia6, EGt = S4[1] / (2.0 * V) * r.ia2, EVt = S4[2] / V;
-            r.C = std::pow(a, 2.0 * al + 1.0) / 3.0 * kap;
-            const double Q = (al - 2.0) * EKt + al * EGt + (al + 1.0) * EVt;
-            r.dKda = (2.0 * al + 1.0) * r.C * Q / a + r.C * ((al - 2.0) * (-6.0) * EKt / a + al * (-2.0) * EGt / a);
-            r.dKdq = r.C * (al + 1.0) * S4[3] / V;
-            return r;
-        };
-        const dim3 grid((unsigned)nbk), blk(kSelfAdjThreads);
+        const dim3 grid((unsigned)nbk), blk(kSelfAdjThreads), one(1), w64(64);
         for (int64_t s0 = ((T - 1) / k) * k; s0 >= 0; s0 -= k) {
             const int64_t s1 = std::min<int64_t>(s0 + k, T);
             GCHK(checkpoint_io(c, (size_t)(s0 / k), false));
-            *c->sc_host = recs[(size_t)(s0 / k)];
-            HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->sc, rec_dev + s0 / k, sizeof(ScaleRecord), hipMemcpyDeviceToDevice, c->stream));
             c->t = t_start + (double)s0 * h;
             GCHK(keep(0));
             for (int64_t n = s0; n < s1; ++n) {
@@ -1882,30 +1881,27 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
                 GCHK(keep(n + 1 - s0));
             }
             for (int64_t n = s1 - 1; n >= s0; --n) {
-                const double a0 = traj_a[(size_t)n], a1 = traj_a[(size_t)n + 1], abar = 0.5 * (a0 + a1);
+                SelfStepConst kc{};
+                kc.a0 = traj_a[(size_t)n];
+                kc.a1 = traj_a[(size_t)n + 1];
+                kc.abar = 0.5 * (kc.a0 + kc.a1);
+                kc.h = h;
+                kc.alpha = al;
+                kc.kappa2 = c->p.kappa2;
+                kc.V = V;
                 const SelfAdjArgs g1 = args(n + 1 - s0), g0 = args(n - s0);
                 hipLaunchKernelGGL(self_adj_energy, grid, blk, 0, c->stream, g1);
                 GCHK(reduce(4, 0));
                 hipLaunchKernelGGL(self_adj_energy, grid, blk, 0, c->stream, g0);
                 GCHK(reduce(4, 4));
-                GCHK(fetch(8));
-                const KaTerms k1 = ka_terms(a1, host), k0 = ka_terms(a0, host + 4);
-                double la1 = la;
-                {   // (6) b kick at n + 1
-                    const double wl = 0.5 * h * lb;
-                    SelfAdjArgs g = g1;
-                    g.c0 = wl * k1.C * al * k1.ia2 / V;
-                    g.c1 = wl * k1.C * (al + 1.0) / V;
-                    g.c2 = wl * k1.C * (al - 2.0) * k1.ia6 / V;
-                    hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g);
-                    HIPCHK(c, hipGetLastError());
-                    la1 += wl * k1.dKda;
-                    dq_self += wl * k1.dKdq;
-                }
+                hipLaunchKernelGGL(self_scal_pre, one, w64, 0, c->stream, (const double *)tot, kc, scal);
+                HIPCHK(c, hipGetLastError());
+                hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g1);            // (6)
+                HIPCHK(c, hipGetLastError());
                 {   // (5) field kick at n + 1
                     SelfAdjArgs g = g1;
-                    g.c0 = 0.5 * h * std::pow(a1, 1.0 + al);
-                    g.c1 = 0.5 * h * std::pow(a1, 3.0 + al);
+                    g.c0 = 0.5 * h * std::pow(kc.a1, 1.0 + al);
+                    g.c1 = 0.5 * h * std::pow(kc.a1, 3.0 + al);
                     hipLaunchKernelGGL(self_adj_kick, grid, blk, 0, c->stream, g);
                     GCHK(reduce(3, 8));
                 }
@@ -1913,48 +1909,38 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
                     SelfDriftArgs d{};
                     d.g = g0;
                     d.g.c0 = 0.5 * h;
-                    d.g.c1 = std::pow(a0, 1.0 + al);
-                    d.g.c2 = std::pow(a0, 3.0 + al);
-                    d.dr = h * std::pow(abar, al - 3.0);
+                    d.g.c1 = std::pow(kc.a0, 1.0 + al);
+                    d.g.c2 = std::pow(kc.a0, 3.0 + al);
+                    d.dr = h * std::pow(kc.abar, al - 3.0);
                     hipLaunchKernelGGL(self_adj_drift, grid, blk, 0, c->stream, d);
                     GCHK(reduce(1, 11));
                 }
-                GCHK(fetch(12));
-                la1 += 0.5 * h * ((1.0 + al) * std::pow(a1, al) * host[8] - (3.0 + al) * std::pow(a1, 2.0 + al) * host[9]);
-                dq_self += 0.5 * h * std::pow(a1, 3.0 + al) * host[10];
-                const double labar = h * (al - 3.0) * std::pow(abar, al - 4.0) * host[11];
-                la1 += 0.5 * labar;
-                double la0 = 0.5 * labar;
-                la0 += la1;   // (3) a1 = a_n + h b'
-                lb += h * la1;
+                hipLaunchKernelGGL(self_scal_mid, one, w64, 0, c->stream, (const double *)tot, kc, scal);   // (3)
+                HIPCHK(c, hipGetLastError());
                 {   // (1) field kick at n
                     SelfAdjArgs g = g0;
-                    g.c0 = 0.5 * h * std::pow(a0, 1.0 + al);
-                    g.c1 = 0.5 * h * std::pow(a0, 3.0 + al);
+                    g.c0 = 0.5 * h * std::pow(kc.a0, 1.0 + al);
+                    g.c1 = 0.5 * h * std::pow(kc.a0, 3.0 + al);
                     hipLaunchKernelGGL(self_adj_kick, grid, blk, 0, c->stream, g);
                     GCHK(reduce(3, 12));
                 }
-                {   // (2) b kick at n
-                    const double wl = 0.5 * h * lb;
-                    SelfAdjArgs g = g0;
-                    g.c0 = wl * k0.C * al * k0.ia2 / V;
-                    g.c1 = wl * k0.C * (al + 1.0) / V;
-                    g.c2 = wl * k0.C * (al - 2.0) * k0.ia6 / V;
-                    hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g);
-                    HIPCHK(c, hipGetLastError());
-                    la0 += wl * k0.dKda;
-                    dq_self += wl * k0.dKdq;
-                }
-                GCHK(fetch(15));
-                la0 += 0.5 * h * ((1.0 + al) * std::pow(a0, al) * host[12] - (3.0 + al) * std::pow(a0, 2.0 + al) * host[13]);
-                dq_self += 0.5 * h * std::pow(a0, 3.0 + al) * host[14];
-                la = la0;
+                hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g0);            // (2)
+                HIPCHK(c, hipGetLastError());
+                hipLaunchKernelGGL(self_scal_post, one, w64, 0, c->stream, (const double *)tot, kc, scal);
+                HIPCHK(c, hipGetLastError());
             }
+        }
+        {
+            SelfScalars sf{};
+            HIPCHK(c, hipMemcpyAsync(&sf, scal, sizeof(sf), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            la = sf.la;
+            lb = sf.lb;
+            dq_self = sf.dq;
         }
         // the initial state, scale record, time and step count again
         GCHK(checkpoint_io(c, 0, false));
-        *c->sc_host = recs[0];
-        HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->sc, rec_dev, sizeof(ScaleRecord), hipMemcpyDeviceToDevice, c->stream));
         c->t = t_start;
         c->step = step_save;
     }

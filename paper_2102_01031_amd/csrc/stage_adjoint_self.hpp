@@ -10,10 +10,10 @@
 //   (6) b1   = b' + h/2 K_a(a1, E(phi1, pi1, a1))
 // with K = a^{1+alpha} Lap phi - a^{3+alpha} grad V and K_a = C(a) Q,
 // C = a^{2 alpha+1} kappa^2/3, Q = (alpha-2) E_K + alpha E_G + (alpha+1) E_V.
-// The host pulls the scalar adjoints of a and b back; these kernels do the
-// field-shaped parts, one site per thread with neighbours through the caches,
-// and write per-block partial sums (NQ per block, fixed order) of the
-// scalar products the host needs.
+// The field-shaped parts run one site per thread with neighbours through the
+// caches and write per-block partial sums (NQ per block, fixed order) of the
+// scalar products that the scalar adjoints of a and b need; three one-thread
+// kernels per step pull those scalars back on the device.
 #pragma once
 #include "common.hpp"
 
@@ -71,6 +71,7 @@ struct SelfAdjArgs {
     double inv_dx2, lam, q;
     double c0, c1, c2;              // piece coefficients (see each kernel)
     double *part;                   // per-block partials
+    const double *dcoef;            // b kick: its three coefficients, on the device
 };
 
 // Energy sums of (phi, pi), both fields together: sum pi^2,
@@ -99,22 +100,23 @@ __global__ void __launch_bounds__(kSelfAdjThreads) self_adj_energy(const SelfAdj
 }
 
 // Pull-back of a b kick b += wb K_a(a, E(phi, pi, a)) into the fields:
-//   lphi_s += c0 (-Lap phi_s) + c1 dV/dphi_s,   lpi_s += c2 pi_s
-// with c0 = wb lb C alpha/(a^2 V), c1 = wb lb C (alpha+1)/V, c2 = wb lb C (alpha-2)/(a^6 V).
+//   lphi_s += d0 (-Lap phi_s) + d1 dV/dphi_s,   lpi_s += d2 pi_s
+// with (d0, d1, d2) = dcoef = wb lb C (alpha/(a^2 V), (alpha+1)/V, (alpha-2)/(a^6 V)).
 __global__ void __launch_bounds__(kSelfAdjThreads) self_adj_bkick(const SelfAdjArgs g)
 {
     const int N = g.N;
     const size_t V = (size_t)N * N * N;
     const size_t n = (size_t)blockIdx.x * kSelfAdjThreads + threadIdx.x;
     if (n >= V) return;
+    const double d0 = g.dcoef[0], d1 = g.dcoef[1], d2 = g.dcoef[2];
     const SelfAdjSite s = self_adj_nbrs(n, N);
     const double u = g.phi[0][n], w = g.phi[1][n];
     const double dV[2] = {g.lam * u * u * u + g.q * u * w * w, g.q * u * u * w};
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
         const double lap = self_adj_lap(g.phi[f], n, s, g.inv_dx2);
-        g.lphi[f][n] += g.c0 * (-lap) + g.c1 * dV[f];
-        g.lpi[f][n] += g.c2 * g.pi[f][n];
+        g.lphi[f][n] += d0 * (-lap) + d1 * dV[f];
+        g.lpi[f][n] += d2 * g.pi[f][n];
     }
 }
 
@@ -178,14 +180,100 @@ __global__ void __launch_bounds__(kSelfAdjThreads) self_adj_drift(const SelfDrif
     self_adj_partials<1>(v, g.part);
 }
 
-// Sum each of nq rows of nb partials in order: out[q] = sum_k part[q nb + k].
-__global__ void self_adj_reduce(const double *__restrict__ part, int nb, int nq, double *__restrict__ out)
+// Scalar adjoints of one reverse step, on the device.  tot holds, in order:
+// energy sums (sum pi^2, sum |grad+ phi|^2, sum V, sum phi^2 chi^2/2) at n + 1
+// [0..3] and at n [4..7]; the field kick sums at n + 1 (sum lpi.Lap phi,
+// sum lpi.dV/dphi, sum lpi.dF/dq) [8..10]; the drift sum lphi.pi' [11]; the
+// field kick sums at n [12..14].
+struct SelfScalars {
+    double la, lb, dq;      // adjoints of a and b, and dO/dq, accumulated
+    double la1, la0;        // adjoints of a_{n+1} and a_n within the step
+    double bk[3];           // coefficients of the next b kick pull-back
+};
+
+struct SelfStepConst {
+    double a0, a1, abar, h, alpha, kappa2, V;
+};
+
+// K_a = C Q at scale factor a from the energy sums S: C, 1/a^2, 1/a^6, dK_a/da, dK_a/dq
+__device__ inline void self_ka(double a, const double *S, const SelfStepConst &k, double &C, double &ia2,
+                               double &ia6, double &dKda, double &dKdq)
 {
-    const int q = threadIdx.x;
+    const double al = k.alpha;
+    ia2 = 1.0 / (a * a);
+    ia6 = ia2 * ia2 * ia2;
+    const double EK = S[0] / (2.0 * k.V) * ia6, EG = S[1] / (2.0 * k.V) * ia2, EV = S[2] / k.V;
+    C = pow(a, 2.0 * al + 1.0) / 3.0 * k.kappa2;
+    const double Q = (al - 2.0) * EK + al * EG + (al + 1.0) * EV;
+    dKda = (2.0 * al + 1.0) * C * Q / a + C * ((al - 2.0) * (-6.0) * EK / a + al * (-2.0) * EG / a);
+    dKdq = C * (al + 1.0) * S[3] / k.V;
+}
+
+__device__ inline void self_bk(SelfScalars *s, double wl, double C, double ia2, double ia6, const SelfStepConst &k)
+{
+    s->bk[0] = wl * C * k.alpha * ia2 / k.V;
+    s->bk[1] = wl * C * (k.alpha + 1.0) / k.V;
+    s->bk[2] = wl * C * (k.alpha - 2.0) * ia6 / k.V;
+}
+
+// (6): the b kick at n + 1 (before its field pull-back)
+__global__ void self_scal_pre(const double *tot, const SelfStepConst k, SelfScalars *s)
+{
+    if (threadIdx.x != 0) return;
+    double C, ia2, ia6, dKda, dKdq;
+    self_ka(k.a1, tot, k, C, ia2, ia6, dKda, dKdq);
+    const double wl = 0.5 * k.h * s->lb;
+    self_bk(s, wl, C, ia2, ia6, k);
+    s->la1 = s->la + wl * dKda;
+    s->dq += wl * dKdq;
+}
+
+// (5), (4), (3) and the scalar part of (2)
+__global__ void self_scal_mid(const double *tot, const SelfStepConst k, SelfScalars *s)
+{
+    if (threadIdx.x != 0) return;
+    const double al = k.alpha, h = k.h;
+    double la1 = s->la1 + 0.5 * h * ((1.0 + al) * pow(k.a1, al) * tot[8] - (3.0 + al) * pow(k.a1, 2.0 + al) * tot[9]);
+    s->dq += 0.5 * h * pow(k.a1, 3.0 + al) * tot[10];
+    const double labar = h * (al - 3.0) * pow(k.abar, al - 4.0) * tot[11];
+    la1 += 0.5 * labar;
+    double la0 = 0.5 * labar + la1;   // (3) a1 = a_n + h b'
+    s->lb += h * la1;
+    double C, ia2, ia6, dKda, dKdq;
+    self_ka(k.a0, tot + 4, k, C, ia2, ia6, dKda, dKdq);
+    const double wl = 0.5 * h * s->lb;
+    self_bk(s, wl, C, ia2, ia6, k);
+    s->la0 = la0 + wl * dKda;
+    s->dq += wl * dKdq;
+}
+
+// (1): the field kick at n
+__global__ void self_scal_post(const double *tot, const SelfStepConst k, SelfScalars *s)
+{
+    if (threadIdx.x != 0) return;
+    const double al = k.alpha, h = k.h;
+    s->la = s->la0 + 0.5 * h * ((1.0 + al) * pow(k.a0, al) * tot[12] - (3.0 + al) * pow(k.a0, 2.0 + al) * tot[13]);
+    s->dq += 0.5 * h * pow(k.a0, 3.0 + al) * tot[14];
+}
+
+// Sum each of the nq rows of nb partials: block q, each thread a fixed strided
+// subset in order, then the fixed wave and block tree; out[q].
+__global__ void __launch_bounds__(kSelfAdjThreads) self_adj_reduce(const double *__restrict__ part, int nb, int nq,
+                                                                   double *__restrict__ out)
+{
+    __shared__ double lds[kSelfAdjThreads / 64];
+    const int q = blockIdx.x;
     if (q >= nq) return;
     double s = 0.0;
-    for (int k = 0; k < nb; ++k) s += part[(size_t)q * nb + k];
-    out[q] = s;
+    for (int k = threadIdx.x; k < nb; k += kSelfAdjThreads) s += part[(size_t)q * nb + k];
+    const double w = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kSelfAdjThreads / 64; ++i) t += lds[i];
+        out[q] = t;
+    }
 }
 
 }  // namespace lat
