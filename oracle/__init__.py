@@ -42,6 +42,11 @@ class U1Params(C.Structure):
                 ("kappa_g", C.c_double)]
 
 
+class SU2Params(C.Structure):
+    _fields_ = [("N", C.c_int32), ("pad", C.c_int32), ("dx", C.c_double), ("dt", C.c_double),
+                ("lam", C.c_double), ("v", C.c_double), ("g", C.c_double)]
+
+
 _lib = None
 
 
@@ -83,6 +88,11 @@ def lib():
         L.orc_u1_gauss.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, dp]
         L.orc_u1_run_lf.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long]
         L.orc_u1_lf_sync.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock)]
+        L.orc_su2_forces.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp]
+        L.orc_su2_energy.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock), dp]
+        L.orc_su2_gauss.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
+        L.orc_su2_run_lf.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long]
+        L.orc_su2_lf_sync.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock)]
         _lib = L
     return _lib
 
@@ -377,6 +387,69 @@ class U1State:
 
 def _u1_dict(out):
     return dict(EK_phi=out[0], EG_phi=out[1], EV=out[2], EK_A=out[3], EG_A=out[4], rho=out[5],
+                gauss_max=out[6], div_max=out[7], charge_max=out[8], gauss_mean=out[9],
+                gauss_sum_mean=out[10], gauss_abs_mean=out[11])
+
+
+# ----------------------------------------------------------------------------
+# SU(2) sector (doublet + SU(2) links, a = 1)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class SU2Model:
+    N: int
+    dx: float
+    dt: float
+    lam: float = 1.0
+    v: float = 1.0
+    g: float = 0.5
+
+    def cparams(self) -> SU2Params:
+        return SU2Params(self.N, 0, self.dx, self.dt, self.lam, self.v, self.g)
+
+
+class SU2State:
+    """phi: 4 real doublet components, pi: 4, U: 12 link arrays (link i, quaternion
+    component k at index 4 i + k), E: 9 electric arrays (link i, colour a at 3 i + a)."""
+
+    def __init__(self, model: SU2Model, phi, pi, U, E, t=0.0, lf_stag=0):
+        self.m = model
+        cp = lambda L: [np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1)).copy() for f in L]
+        self.phi, self.pi, self.U, self.E = cp(phi), cp(pi), cp(U), cp(E)
+        assert len(self.phi) == 4 and len(self.pi) == 4 and len(self.U) == 12 and len(self.E) == 9
+        self._p = model.cparams()
+        self.clock = Clock(t, 1.0, 0.0, lf_stag, 0)
+
+    def _args(self):
+        return _pp(self.phi), _pp(self.pi), _pp(self.U), _pp(self.E)
+
+    def run(self, nsteps: int):
+        _chk(lib().orc_su2_run_lf(C.byref(self._p), *self._args(), C.byref(self.clock), int(nsteps)), "su2 run")
+        return self
+
+    def sync(self):
+        _chk(lib().orc_su2_lf_sync(C.byref(self._p), *self._args(), C.byref(self.clock)), "su2 sync")
+        return self
+
+    def energy(self) -> dict:
+        out = np.zeros(12)
+        _chk(lib().orc_su2_energy(C.byref(self._p), *self._args(), C.byref(self.clock), _dp(out)), "su2 energy")
+        return _su2_dict(out)
+
+    def gauss(self) -> dict:
+        out = np.zeros(12)
+        _chk(lib().orc_su2_gauss(C.byref(self._p), *self._args(), _dp(out)), "su2 gauss")
+        return _su2_dict(out)
+
+    def forces(self):
+        F = [np.zeros_like(self.phi[0]) for _ in range(13)]
+        _chk(lib().orc_su2_forces(C.byref(self._p), _pp(self.phi), _pp(self.U), _pp(F[:4]), _pp(F[4:])),
+             "su2 forces")
+        return F[:4], F[4:]
+
+
+def _su2_dict(out):
+    return dict(EK_phi=out[0], EG_phi=out[1], EV=out[2], EK_B=out[3], EG_B=out[4], rho=out[5],
                 gauss_max=out[6], div_max=out[7], charge_max=out[8], gauss_mean=out[9],
                 gauss_sum_mean=out[10], gauss_abs_mean=out[11])
 

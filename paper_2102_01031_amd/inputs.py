@@ -113,3 +113,40 @@ def random_directions(n: int, N: int, seed: int):
         v /= np.linalg.norm(v)
         out.append((v[:-1].reshape(N, N, N), float(v[-1])))
     return out
+
+
+def random_direction_su2(N: int, amplitude: float, seed: int):
+    """SU(2) doublet of modulus ``amplitude`` with a white-noise direction on the
+    3-sphere per site, in the real components of eq. ChargedScalars:
+    phi_c = sqrt2 |Phi| r_c with r a uniform unit 4-vector (normalised Gaussian).
+    Momenta and electric fields start at zero, links at the identity, so the
+    Gauss constraint holds exactly.  Layout: phi[4], pi[4], U[12] (link i,
+    quaternion component k at 4 i + k, U = u0 I - i u.sigma), E[9] (3 i + a)."""
+    rng = np.random.default_rng(seed)
+    r = rng.standard_normal((4, N, N, N))
+    r /= np.sqrt((r * r).sum(axis=0))
+    phi = [np.sqrt(2.0) * amplitude * r[c] for c in range(4)]
+    z = lambda: np.zeros((N, N, N))
+    U = []
+    for _ in range(3):
+        U += [np.ones((N, N, N)), z(), z(), z()]
+    return phi, [z() for _ in range(4)], U, [z() for _ in range(9)]
+
+
+def random_su2_state(N: int, seed: int, phi_amp: float = 0.3, pi_amp: float = 0.2, link_angle: float = 0.6,
+                     e_amp: float = 0.3):
+    """Generic seeded SU(2) state (no constraint imposed): Gaussian doublet and
+    momenta, links exp(-i (theta/2) n.sigma) with theta uniform in [0, link_angle)
+    and n a uniform unit axis, Gaussian electric fields."""
+    rng = np.random.default_rng(seed)
+    shape = (N, N, N)
+    phi = [phi_amp * rng.standard_normal(shape) for _ in range(4)]
+    pi = [pi_amp * rng.standard_normal(shape) for _ in range(4)]
+    U = []
+    for _ in range(3):
+        th = rng.uniform(0.0, link_angle, size=shape)
+        ax = rng.standard_normal((3,) + shape)
+        ax /= np.sqrt((ax * ax).sum(axis=0))
+        U += [np.cos(0.5 * th)] + [np.sin(0.5 * th) * ax[a] for a in range(3)]
+    E = [e_amp * rng.standard_normal(shape) for _ in range(9)]
+    return phi, pi, U, E

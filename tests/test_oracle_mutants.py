@@ -74,6 +74,25 @@ MUTANTS = [
     ("a drift adjoint without h", "*lb += h * la1;", "*lb += la1;", "test_oracle_adjoint_self.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += dr * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * dr * lphi[s][n];", "test_oracle_adjoint.py"),
+    ("SU(2) magnetic force sign", "- 2.0 / (g * dx * dx * dx) * vs[k];", "+ 2.0 / (g * dx * dx * dx) * vs[k];",
+     "test_oracle_su2.py"),
+    ("SU(2) current without conjugation", "t += conj(psi[r]) * 0.5 * PAULI[k][r][s] * a[s];",
+     "t += psi[r] * 0.5 * PAULI[k][r][s] * a[s];", "test_oracle_su2.py"),
+    ("SU(2) lower staple without a dagger", "mat2 Sm = m2_mul(m2_mul(m2_dag(su2_link(U, j, nimj)),",
+     "mat2 Sm = m2_mul(m2_mul(su2_link(U, j, nimj),", "test_oracle_su2.py"),
+    ("SU(2) lower staple at the wrong site", "shift(N, cp, j, -1, cimj);", "shift(N, c, j, -1, cimj);",
+     "test_oracle_su2.py"),
+    ("SU(2) magnetic energy normalisation", "nadd(&sgb, 2.0 * mag /", "nadd(&sgb, mag /", "test_oracle_su2.py"),
+    ("SU(2) link drift direction", "u[a] = sin(0.5 * th) * Ev[a] / len;", "u[a] = -sin(0.5 * th) * Ev[a] / len;",
+     "test_oracle_su2.py"),
+    ("SU(2) link drift on the right", "mat2 R = m2_mul(su2_exp(h * p->g * p->dx, Ev), su2_link(U, i, n));",
+     "mat2 R = m2_mul(su2_link(U, i, n), su2_exp(h * p->g * p->dx, Ev));", "test_oracle_su2.py"),
+    ("SU(2) Gauss transport the other way", "mat2 Y = m2_mul(m2_mul(m2_dag(Um), X), Um);",
+     "mat2 Y = m2_mul(m2_mul(Um, X), m2_dag(Um));", "test_oracle_su2.py"),
+    ("SU(2) backward link not conjugated", "m2_apply(m2_dag(su2_link(U, i, nm)), qm, b);",
+     "m2_apply(su2_link(U, i, nm), qm, b);", "test_oracle_su2.py"),
+    ("SU(2) plaquette order", "mat2 P = m2_mul(m2_mul(su2_link(U, i, n), su2_link(U, j, at(N, ci[0], ci[1], ci[2]))),",
+     "mat2 P = m2_mul(m2_mul(su2_link(U, j, at(N, ci[0], ci[1], ci[2])), su2_link(U, i, n)),", "test_oracle_su2.py"),
 ]
 
 
