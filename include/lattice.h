@@ -6,7 +6,9 @@
  * the CosmoLattice paper (arXiv:2102.01031):
  *   - real scalar singlets (sec. 4.2 model, sec. 4.5.2 Hamiltonian form),
  *   - a U(1)-charged complex scalar with Abelian links (sec. 3.2 U(1)
- *     toolkit, sec. 5.2 equations of motion, sec. 5.5.2 kernels).
+ *     toolkit, sec. 5.2 equations of motion, sec. 5.5.2 kernels),
+ *   - an SU(2) doublet with SU(2) links (sec. 3.2 SU(N) toolkit; sec. 5,
+ *     eqs. higgsSU2-eom, SU2eom, GaussSU2-eom, energy-contrib).
  * All quantities are in the paper's program variables (sec. 4.1, eq.
  * FieldSpaceTimeNaturalVariables; sec. 5.1, eq. GaugeProgramVar).
  *
@@ -77,8 +79,19 @@ enum lat_expansion {
 enum lat_potential {
     LAT_PHI4 = 0,          /* one real field, V = lambda/4 phi^4 */
     LAT_PHI4_CHI2 = 1,     /* two real fields, V = lambda/4 phi^4 + q/2 phi^2 chi^2 (sec. 4.2) */
-    LAT_ABELIAN_HIGGS = 2  /* complex phi = (phi0 + i phi1)/sqrt(2) + U(1) links,
+    LAT_ABELIAN_HIGGS = 2, /* complex phi = (phi0 + i phi1)/sqrt(2) + U(1) links,
                               V = lambda/4 (|phi|^2 - v^2)^2 */
+    LAT_SU2_HIGGS = 3      /* doublet Phi = (phi0 + i phi1, phi2 + i phi3)/sqrt(2) + SU(2) links
+                              U_i = exp(-i g dx B_i^a T_a), T_a = sigma_a/2, with the electric
+                              field E_i^a conjugate to U_i under left multiplication;
+                              V = lambda/4 (|Phi|^2 - v^2)^2, |Phi|^2 = sum_c phi_c^2/2.
+                              Lattice Hamiltonian per site: sum_c pi_c^2/2
+                              + sum_i |U_i psi(n+i) - psi(n)|^2/(2 dx^2) + V + |E|^2/2
+                              + 2/(g^2 dx^4) sum_{i<j} (2 - Tr P_ij), psi = sqrt(2) Phi and
+                              P_ij = U_i U_j(n+i) U_i(n+j)^dag U_j^dag (the toolkit plaquette);
+                              leapfrog kicks are minus its derivative, the link drift is
+                              U <- exp(-i dt g dx E^a T_a) U.  Provided with LAT_LF, a = 1
+                              and float64; (f_star/omega_star)^2 = 1 (kappa_g is not used). */
 };
 
 enum lat_precision {
@@ -104,7 +117,7 @@ typedef struct lat_params {
     double lambda;          /* quartic coupling */
     double q;               /* LAT_PHI4_CHI2: q = g^2/lambda */
     double v;               /* LAT_ABELIAN_HIGGS: vacuum expectation value */
-    double e_charge;        /* LAT_ABELIAN_HIGGS: e = g_A Q_A */
+    double e_charge;        /* LAT_ABELIAN_HIGGS: e = g_A Q_A; LAT_SU2_HIGGS: g = g_B Q_B */
     double kappa_g;         /* LAT_ABELIAN_HIGGS: (f_star/omega_star)^2 */
     double kappa2;          /* LAT_EXP_SELF: (f_star/m_p)^2 */
     double w_eos;           /* LAT_EXP_FIXED: equation of state */
@@ -121,6 +134,12 @@ typedef struct lat_fields {
     void *pi[2];    /* conjugate momenta pi = a^{3-alpha} phi' (sec. 4.5.2), same layout */
     void *A[3];     /* LAT_ABELIAN_HIGGS: A_i on the link n -> n + i (sec. 3.2) */
     void *piA[3];   /* LAT_ABELIAN_HIGGS: pi_A,i = a^{1-alpha} F_0i (sec. 5.5.2) */
+    void *doublet[4];     /* LAT_SU2_HIGGS: the real components phi0..phi3 of the doublet */
+    void *pi_doublet[4];  /* LAT_SU2_HIGGS: their momenta pi_c = phi_c' (a = 1) */
+    void *U[12];          /* LAT_SU2_HIGGS: link n -> n + i, unit quaternion component k at
+                             U[4 i + k], U = U[4i] I - i (U[4i+1], U[4i+2], U[4i+3]).sigma */
+    void *E[9];           /* LAT_SU2_HIGGS: electric field E_i^a at E[3 i + a] (a = 0, 1, 2
+                             for sigma_1..3), the momentum pi_B of sec. 5 at a = 1 */
 } lat_fields;
 
 typedef struct lat_energies {
@@ -133,12 +152,18 @@ typedef struct lat_energies {
     double hubble_lhs;       /* b^2 */
     double hubble_rhs;       /* a^{2 alpha + 2} kappa2 rho / 3 */
     double hubble_res;       /* (lhs - rhs)/(lhs + rhs) */
-    double gauss_max;        /* U(1): max_n |G(n)|, G = div- piA - e kappa_g (phi0 pi1 - phi1 pi0) */
+    double gauss_max;        /* U(1): max_n |G(n)|, G = div- piA - e kappa_g (phi0 pi1 - phi1 pi0);
+                                SU(2): see gauss_abs_mean */
     double gauss_div_max;    /* max_n |div- piA| */
     double gauss_charge_max; /* max_n |e kappa_g (phi0 pi1 - phi1 pi0)| */
     double gauss_mean;       /* <|G|> */
     double gauss_sum_mean;   /* <|div- piA + charge|> */
     int64_t step;            /* steps taken since lattice_init (signed: backward steps subtract) */
+    double EK_B, EG_B;       /* SU(2) electric <|E|^2>/2 and magnetic <2/(g^2 dx^4) sum_{i<j} (2 - Tr P_ij)> energies */
+    double gauss_abs_mean;   /* <|div E| + |charge|>: the scale the Gauss residual is measured against.
+                                SU(2) (eq. GaussSU2-eom): G^a = dx^-1 sum_i [E_i^a(n) - R(U_i(n-i))^a E_i(n-i)]
+                                - g Im(psi^dag T_a pi_psi), R(U) E.sigma = U^dag (E.sigma) U, with the
+                                Euclidean norm over a in the max and mean fields above */
 } lat_energies;
 
 typedef struct lat_ctx lat_ctx;
@@ -146,8 +171,8 @@ typedef struct lat_ctx lat_ctx;
 /* Create a context for the fields f (device pointers, see lat_fields) and
  * validate p.  Allocates the library scratch, computes b0 from the Hubble
  * constraint when asked, and leaves the fields untouched.
- * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (LF with LAT_EXP_SELF; the U(1) model
- * with another integrator than LF or with expansion), LAT_ENODEV, LAT_ENOMEM,
+ * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (LF with LAT_EXP_SELF; the U(1) and SU(2)
+ * models with another integrator than LF, with expansion or in float32), LAT_ENODEV, LAT_ENOMEM,
  * LAT_EHIP.  On error *ctx is set to NULL. */
 lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
 
@@ -283,7 +308,7 @@ lat_status lattice_grad(lat_ctx *ctx, const lat_grad_spec *spec, lat_grad_out *o
 /* Launch statistics of the stencil kernels, per kernel kind:
  *   0 kick only, 1 kick only + reductions, 2 drift on load + kick,
  *   3 drift on load + kick + reductions, 4 kick + drift at end (leapfrog),
- *   5 energy (read only), 6 U(1) leapfrog (and U(1) energy), 7 adjoint reverse pass.
+ *   5 energy (read only), 6 U(1) or SU(2) leapfrog (and their energy passes), 7 adjoint reverse pass.
  * kernel_ms is accumulated from HIP events recorded on the context stream around
  * each launch while profiling is on (lattice_profile); it stays 0 otherwise. */
 typedef struct lat_stats {

@@ -30,6 +30,7 @@
 #include "stage_scalar.hpp"
 #include "stage_rows.hpp"
 #include "stage_u1.hpp"
+#include "stage_su2.hpp"
 #include "stage_adjoint.hpp"
 #include "stage_batch.hpp"
 #include "spectrum.hpp"
@@ -47,6 +48,10 @@ thread_local std::string g_init_error;
 lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir);
 lat_status u1_sync(lat_ctx *c);
 lat_status u1_energy(lat_ctx *c, lat_energies *out);
+lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir);
+lat_status su2_sync(lat_ctx *c);
+lat_status su2_energy(lat_ctx *c, lat_energies *out);
+size_t su2_partial_capacity(int N);
 size_t u1_partial_capacity(int N);
 void u1_geometry(lat_ctx *c);
 lat_status batch_step(lat_ctx *c, int64_t nsteps);
@@ -74,6 +79,7 @@ struct lat_ctx {
     int device = 0;
     bool f32 = false;
     bool u1 = false;
+    bool su2 = false;
     int nf = 1;
     int N = 0;
     size_t vol = 0;
@@ -86,6 +92,13 @@ struct lat_ctx {
     void *A[3][2] = {};
     void *piA[3] = {};
     int cur_A[3] = {0, 0, 0};
+    // SU(2): doublet components and links ([0] caller's, [1] shadow), momenta in place;
+    // one buffer parity for all of them
+    void *dbl[4][2] = {};
+    void *dpi[4] = {};
+    void *lnk[12][2] = {};
+    void *efl[9] = {};
+    int cur_su2 = 0;
     bool u1_rows = false;   // whole-row U(1) leapfrog kernel
     int u1_ty = 4, u1_zc = 8;
     // scratch
@@ -663,6 +676,13 @@ lat_status settle(lat_ctx *c)
             c->cur_A[i] = 0;
         }
     }
+    if (c->cur_su2) {
+        for (int k = 0; k < 4; ++k)
+            HIPCHK(c, hipMemcpyAsync(c->dbl[k][0], c->dbl[k][1], bytes, hipMemcpyDeviceToDevice, c->stream));
+        for (int k = 0; k < 12; ++k)
+            HIPCHK(c, hipMemcpyAsync(c->lnk[k][0], c->lnk[k][1], bytes, hipMemcpyDeviceToDevice, c->stream));
+        c->cur_su2 = 0;
+    }
     return LAT_OK;
 }
 
@@ -816,7 +836,7 @@ lat_status validate(const lat_params *p, const lat_fields *f)
         return fail(nullptr, LAT_EINVAL, "dt/dx must be below 1/sqrt(3)");
     if (p->integrator < LAT_LF || p->integrator > LAT_VV10) return fail(nullptr, LAT_EINVAL, "bad integrator");
     if (p->expansion < LAT_EXP_NONE || p->expansion > LAT_EXP_SELF) return fail(nullptr, LAT_EINVAL, "bad expansion");
-    if (p->potential < LAT_PHI4 || p->potential > LAT_ABELIAN_HIGGS) return fail(nullptr, LAT_EINVAL, "bad potential");
+    if (p->potential < LAT_PHI4 || p->potential > LAT_SU2_HIGGS) return fail(nullptr, LAT_EINVAL, "bad potential");
     if (p->precision != LAT_PREC_F64 && p->precision != LAT_PREC_F32) return fail(nullptr, LAT_EINVAL, "bad precision");
     if (p->lf_staggered < -1 || p->lf_staggered > 1) return fail(nullptr, LAT_EINVAL, "lf_staggered must be -1, 0 or 1");
     if (p->lf_staggered != 0 && p->integrator != LAT_LF)
@@ -829,7 +849,7 @@ lat_status validate(const lat_params *p, const lat_fields *f)
     }
     if (p->expansion == LAT_EXP_SELF && !(p->a0 > 0.0)) return fail(nullptr, LAT_EINVAL, "a0 must be > 0");
     const size_t al = p->precision == LAT_PREC_F32 ? 4 : 8;
-    const int nf = p->potential == LAT_PHI4 ? 1 : 2;
+    const int nf = p->potential == LAT_PHI4 ? 1 : (p->potential == LAT_SU2_HIGGS ? 0 : 2);
     for (int i = 0; i < nf; ++i) {
         if (!f->phi[i] || !f->pi[i]) return fail(nullptr, LAT_EINVAL, "null field pointer");
         if (!aligned(f->phi[i], al) || !aligned(f->pi[i], al))
@@ -846,6 +866,23 @@ lat_status validate(const lat_params *p, const lat_fields *f)
                 return fail(nullptr, LAT_EINVAL, "misaligned gauge field pointer");
         }
     }
+    if (p->potential == LAT_SU2_HIGGS) {
+        if (p->integrator != LAT_LF || p->expansion != LAT_EXP_NONE)
+            return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model is provided with LF and a = 1");
+        if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model runs in float64");
+        if (!(p->e_charge != 0.0) || !std::isfinite(p->e_charge)) return fail(nullptr, LAT_EINVAL, "bad SU(2) coupling");
+        const void *all[29];
+        for (int k = 0; k < 4; ++k) {
+            all[k] = f->doublet[k];
+            all[4 + k] = f->pi_doublet[k];
+        }
+        for (int k = 0; k < 12; ++k) all[8 + k] = f->U[k];
+        for (int k = 0; k < 9; ++k) all[20 + k] = f->E[k];
+        for (const void *q : all) {
+            if (!q) return fail(nullptr, LAT_EINVAL, "null SU(2) field pointer");
+            if (!aligned(q, al)) return fail(nullptr, LAT_EINVAL, "misaligned SU(2) field pointer");
+        }
+    }
     return LAT_OK;
 }
 
@@ -859,6 +896,10 @@ void free_ctx(lat_ctx *c)
     }
     for (int i = 0; i < 3; ++i)
         if (c->A[i][1]) (void)hipFree(c->A[i][1]);
+    for (int k = 0; k < 4; ++k)
+        if (c->dbl[k][1]) (void)hipFree(c->dbl[k][1]);
+    for (int k = 0; k < 12; ++k)
+        if (c->lnk[k][1]) (void)hipFree(c->lnk[k][1]);
     if (c->partials) (void)hipFree(c->partials);
     if (c->ticket) (void)hipFree(c->ticket);
     if (c->sc) (void)hipFree(c->sc);
@@ -931,7 +972,8 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     c->f32 = p->precision == LAT_PREC_F32;
     c->esize = c->f32 ? 4 : 8;
     c->u1 = p->potential == LAT_ABELIAN_HIGGS;
-    c->nf = p->potential == LAT_PHI4 ? 1 : 2;
+    c->su2 = p->potential == LAT_SU2_HIGGS;
+    c->nf = p->potential == LAT_PHI4 ? 1 : (c->su2 ? 0 : 2);
     c->N = p->N;
     c->vol = (size_t)p->N * p->N * p->N;
     c->t = p->t0;
@@ -959,7 +1001,20 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
             if (hipMalloc(&c->A[i][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
         }
     }
+    if (c->su2) {
+        for (int k = 0; k < 4; ++k) {
+            c->dbl[k][0] = f->doublet[k];
+            c->dpi[k] = f->pi_doublet[k];
+            if (hipMalloc(&c->dbl[k][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
+        }
+        for (int k = 0; k < 12; ++k) {
+            c->lnk[k][0] = f->U[k];
+            if (hipMalloc(&c->lnk[k][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
+        }
+        for (int k = 0; k < 9; ++k) c->efl[k] = f->E[k];
+    }
     c->partial_cap = (size_t)(c->nblocks > 1 ? c->nblocks : 1) * kMaxQ + 64;
+    if (c->su2) c->partial_cap = su2_partial_capacity(c->N) + 64;
     if (c->u1) {
         c->partial_cap = u1_partial_capacity(c->N) + 64;
         u1_geometry(c);
@@ -1026,7 +1081,7 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
     if (c->p.integrator == LAT_LF) {
         if (c->lf_stag != 0 && c->lf_stag != dir)
             return fail(c, LAT_ESTATE, "leapfrog momenta are staggered in the other direction; sync first");
-        s = c->u1 ? u1_step_lf(c, ns, dir) : step_lf(c, ns, dir);
+        s = c->su2 ? su2_step_lf(c, ns, dir) : c->u1 ? u1_step_lf(c, ns, dir) : step_lf(c, ns, dir);
     } else {
         s = step_vv(c, ns, dir);
     }
@@ -1049,7 +1104,9 @@ lat_status lattice_sync(lat_ctx *c)
     }
     if (c->p.integrator != LAT_LF || c->lf_stag == 0) return LAT_OK;
     lat_status s;
-    if (c->u1) {
+    if (c->su2) {
+        s = su2_sync(c);
+    } else if (c->u1) {
         s = u1_sync(c);
     } else {
         if ((s = reserve_coef(c, 2)) != LAT_OK) return s;
@@ -1074,6 +1131,7 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
     std::memset(out, 0, sizeof(*out));
     if (c->batch) return fail(c, LAT_EINVAL, "batch context: use lattice_energy_batch");
     if (c->u1) return u1_energy(c, out);
+    if (c->su2) return su2_energy(c, out);
     const double c1 = (c->p.integrator == LAT_LF && c->lf_stag != 0) ? 0.5 * c->lf_stag * c->p.dt : 0.0;
     lat_status s = energy_sums(c, c1);
     if (s != LAT_OK) return s;
@@ -1169,6 +1227,7 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
 {
     if (!c || !sum || !delta || !count) return fail(c, LAT_EINVAL, "null argument");
     if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
+    if (c->su2) return fail(c, LAT_EUNSUPPORTED, "spectra are provided for the scalar and U(1) models");
     const int nfld = c->u1 ? 2 : c->nf;
     if (field < 0 || field >= nfld || (which != 0 && which != 1))
         return fail(c, LAT_EINVAL, "field or array out of range");
@@ -1207,7 +1266,7 @@ lat_status lattice_occupation(lat_ctx *c, int32_t field, int32_t nbins, double f
 {
     if (!c || !n || !count) return fail(c, LAT_EINVAL, "null argument");
     if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
-    if (c->u1) return fail(c, LAT_EUNSUPPORTED, "occupation numbers are defined for real scalar fields");
+    if (c->u1 || c->su2) return fail(c, LAT_EUNSUPPORTED, "occupation numbers are defined for real scalar fields");
     if (field < 0 || field >= c->nf) return fail(c, LAT_EINVAL, "field out of range");
     if (nbins < 1 || nbins > kSpecMaxBins) return fail(c, LAT_EINVAL, "nbins out of range");
     if (!(fstar2 > 0.0) || !std::isfinite(fstar2)) return fail(c, LAT_EINVAL, "fstar2 must be positive");
@@ -1475,6 +1534,127 @@ lat_status u1_energy(lat_ctx *c, lat_energies *out)
     out->rho = out->EK[0] + out->EG[0] + out->EV[0] + out->EK_A + out->EG_A;
     out->gauss_mean = S[5] / V;
     out->gauss_sum_mean = S[6] / V;
+    out->gauss_abs_mean = S[7] / V;
+    out->gauss_max = M[0];
+    out->gauss_div_max = M[1];
+    out->gauss_charge_max = M[2];
+    out->step = c->step;
+    return LAT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// SU(2) doublet + links (a = 1, leapfrog)
+// ===========================================================================
+namespace {
+
+constexpr int kSU2TX = 64, kSU2TY = 4;
+
+size_t su2_partial_capacity(int N)
+{
+    const size_t tiles = (size_t)((N + kSU2TX - 1) / kSU2TX) * ((N + kSU2TY - 1) / kSU2TY) * (size_t)N;
+    return tiles * (kSU2Sums + kSU2Maxes);
+}
+
+SU2Args su2_args(lat_ctx *c, double ck, double hd, bool write_fields)
+{
+    SU2Args a{};
+    const int cur = c->cur_su2;
+    for (int k = 0; k < 4; ++k) {
+        a.phi_in[k] = (const double *)c->dbl[k][cur];
+        a.phi_out[k] = write_fields ? (double *)c->dbl[k][cur ^ 1] : nullptr;
+        a.pi[k] = (double *)c->dpi[k];
+    }
+    for (int k = 0; k < 12; ++k) {
+        a.U_in[k] = (const double *)c->lnk[k][cur];
+        a.U_out[k] = write_fields ? (double *)c->lnk[k][cur ^ 1] : nullptr;
+    }
+    for (int k = 0; k < 9; ++k) a.E[k] = (double *)c->efl[k];
+    a.N = c->N;
+    a.tiles_x = (c->N + kSU2TX - 1) / kSU2TX;
+    a.tiles_y = (c->N + kSU2TY - 1) / kSU2TY;
+    a.dx = c->p.dx;
+    a.g = c->p.e_charge;
+    a.lam = c->p.lambda;
+    a.v = c->p.v;
+    a.ck = ck;
+    a.hd = hd;
+    a.partials = c->partials;
+    a.ticket = c->ticket;
+    a.sc = c->sc;
+    return a;
+}
+
+lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &a)
+{
+    const size_t nbz = (size_t)a.tiles_x * a.tiles_y * c->N;
+    if (nbz > 0x7fffffffu || (mode == kSU2Energy && nbz * (kSU2Sums + kSU2Maxes) > c->partial_cap))
+        return fail(c, LAT_EINVAL, "SU(2) launch exceeds the partials buffer");
+    const int nb = (int)nbz;
+    const int kind = 6;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->profiling) {
+        lat_status st = timing_begin(c, &ev0, &ev1);
+        if (st != LAT_OK) return st;
+    }
+    const dim3 grid(nb), blk(kSU2TX * kSU2TY);
+    switch (mode) {
+    case kSU2Step: hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Step>), grid, blk, 0, c->stream, a); break;
+    case kSU2Kick: hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Kick>), grid, blk, 0, c->stream, a); break;
+    default: hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Energy>), grid, blk, 0, c->stream, a); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    if (c->profiling) {
+        lat_status st = timing_end(c, ev0, ev1, kind);
+        if (st != LAT_OK) return st;
+    }
+    c->launches[kind] += 1;
+    return LAT_OK;
+}
+
+lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    int stag = c->lf_stag;
+    for (int64_t k = 0; k < ns; ++k) {
+        const double ck = stag == 0 ? 0.5 * h : h;
+        lat_status s = su2_launch(c, kSU2Step, su2_args(c, ck, h, true));
+        if (s != LAT_OK) return s;
+        c->cur_su2 ^= 1;
+        stag = dir;
+    }
+    c->lf_stag = dir;
+    c->t += (double)ns * h;
+    return LAT_OK;
+}
+
+lat_status su2_sync(lat_ctx *c)
+{
+    return su2_launch(c, kSU2Kick, su2_args(c, 0.5 * c->lf_stag * c->p.dt, 0.0, false));
+}
+
+lat_status su2_energy(lat_ctx *c, lat_energies *out)
+{
+    const double ck = c->lf_stag != 0 ? 0.5 * c->lf_stag * c->p.dt : 0.0;
+    lat_status s = su2_launch(c, kSU2Energy, su2_args(c, ck, 0.0, false));
+    if (s != LAT_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double V = (double)c->vol;
+    const double *S = c->sc_host->sums, *M = c->sc_host->maxes;
+    out->t = c->t;
+    out->a = 1.0;
+    out->b = 0.0;
+    out->EK[0] = S[0] / V;
+    out->EG[0] = S[1] / V;
+    out->EV[0] = S[2] / V;
+    out->EK_B = S[3] / V;
+    out->EG_B = S[4] / V;
+    out->rho = out->EK[0] + out->EG[0] + out->EV[0] + out->EK_B + out->EG_B;
+    out->gauss_mean = S[5] / V;
+    out->gauss_sum_mean = S[6] / V;
+    out->gauss_abs_mean = S[7] / V;
     out->gauss_max = M[0];
     out->gauss_div_max = M[1];
     out->gauss_charge_max = M[2];

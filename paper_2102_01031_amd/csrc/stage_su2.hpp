@@ -1,0 +1,357 @@
+// stage_su2.hpp -- SU(2) doublet with SU(2) links at a = 1: the leapfrog pass
+// (kick of the doublet momenta and electric fields, drift of the doublet and
+// the links), the sync half kick, and the energy / Gauss reduction pass.
+//
+// Lattice system (sec. 3.2 SU(N) toolkit; sec. 5, eqs. higgsSU2-eom, SU2eom,
+// GaussSU2-eom, energy-contrib, program variables with f_* = omega_*):
+//   doublet Phi = (psi0, psi1)/sqrt2, psi0 = phi0 + i phi1, psi1 = phi2 + i phi3;
+//   link U_i(n) = exp(-i g dx B_i^a T_a), T_a = sigma_a/2, stored as the unit
+//   quaternion (w, x, y, z) with U = w I - i (x, y, z).sigma;
+//   electric field E_i^a(n), conjugate to U_i(n) under U -> exp(-i eps g dx T_a) U.
+// Hamiltonian per site: sum_c pi_c^2/2 + sum_i |U_i psi(n+i) - psi|^2/(2 dx^2)
+//   + lambda/4 (|Phi|^2 - v^2)^2 + |E|^2/2 + 2/(g^2 dx^4) sum_{i<j} (2 - Tr P_ij),
+//   P_ij(n) = U_i(n) U_j(n+i) U_i(n+j)^dag U_j(n)^dag.
+// Kicks are minus its derivative:
+//   pi_c  += ck [ (D^2 psi)_c - lambda/2 (|Phi|^2 - v^2) phi_c ]
+//   E_i^a += ck [ (g/dx) Im(psi^dag T_a U_i psi(n+i))
+//                 - 2/(g dx^3) vec_a(U_i sum_{j != i} (S+_ij + S-_ij)) ]
+//   S+_ij = U_j(n+i) U_i(n+j)^dag U_j(n)^dag,  S-_ij = U_j(n+i-j)^dag U_i(n-j)^dag U_j(n-j)
+// and the drifts phi += hd pi, U <- exp(-i hd g dx E^a T_a) U.
+// One thread per site; neighbours through the caches.  Momenta are read at
+// their own site only and updated in place; doublet and links are written out
+// of place (the stencil reads the old values).
+#pragma once
+#include "common.hpp"
+
+namespace lat {
+
+struct SU2Args {
+    const double *phi_in[4];
+    double *phi_out[4];
+    double *pi[4];
+    const double *U_in[12];   // link i, component k at 4 i + k
+    double *U_out[12];
+    double *E[9];             // link i, colour a at 3 i + a
+    int N, tiles_x, tiles_y, pad;
+    double dx, g, lam, v;
+    double ck;   // kick weight
+    double hd;   // drift weight
+    double *partials;
+    unsigned *ticket;
+    ScaleRecord *sc;
+};
+
+enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2 };
+constexpr int kSU2Sums = 8, kSU2Maxes = 3;
+
+// unit quaternion q = (w, v) for the matrix w I - i v.sigma
+struct Q4 {
+    double w, x, y, z;
+};
+
+__device__ __forceinline__ Q4 qmul(const Q4 &a, const Q4 &b)
+{
+    // (a0 - i a.s)(b0 - i b.s) = (a0 b0 - a.b) - i (a0 b + b0 a + a x b).s
+    Q4 c;
+    c.w = a.w * b.w - (a.x * b.x + a.y * b.y + a.z * b.z);
+    c.x = a.w * b.x + b.w * a.x + (a.y * b.z - a.z * b.y);
+    c.y = a.w * b.y + b.w * a.y + (a.z * b.x - a.x * b.z);
+    c.z = a.w * b.z + b.w * a.z + (a.x * b.y - a.y * b.x);
+    return c;
+}
+
+__device__ __forceinline__ Q4 qdag(const Q4 &a) { return Q4{a.w, -a.x, -a.y, -a.z}; }
+
+__device__ __forceinline__ Q4 qadd(const Q4 &a, const Q4 &b) { return Q4{a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z}; }
+
+__device__ __forceinline__ Q4 qload(const double *const *U, int i, size_t n)
+{
+    return Q4{U[4 * i][n], U[4 * i + 1][n], U[4 * i + 2][n], U[4 * i + 3][n]};
+}
+
+// (r0 + i s0, r1 + i s1) = U (a + i b, c + i d), U = w I - i v.sigma
+__device__ __forceinline__ void qapply(const Q4 &u, double a, double b, double c, double d, double &r0, double &s0,
+                                       double &r1, double &s1)
+{
+    r0 = u.w * a + u.z * b - u.y * c + u.x * d;
+    s0 = u.w * b - u.z * a - u.y * d - u.x * c;
+    r1 = u.x * b + u.y * a + u.w * c - u.z * d;
+    s1 = -u.x * a + u.y * b + u.w * d + u.z * c;
+}
+
+// Im(psi^dag T_a chi), a = 1..3, psi = (a + i b, c + i d), chi = (p + i q, r + i s)
+__device__ __forceinline__ void isospin(double a, double b, double c, double d, double p, double q, double r, double s,
+                                        double &j1, double &j2, double &j3)
+{
+    j1 = 0.5 * ((a * s - b * r) + (c * q - d * p));
+    j2 = 0.5 * ((c * p + d * q) - (a * r + b * s));
+    j3 = 0.5 * ((a * q - b * p) - (c * s - d * r));
+}
+
+__device__ __forceinline__ size_t su2_at(int N, int x, int y, int z)
+{
+    return (size_t)x + (size_t)N * ((size_t)y + (size_t)N * (size_t)z);
+}
+
+template <int TX, int TY, int MODE>
+__global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
+{
+    constexpr int NT = TX * TY;
+    constexpr int NQ = kSU2Sums + kSU2Maxes;
+    __shared__ double lds_red[(NT / 64) * NQ];
+    __shared__ int last_flag;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int lid = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int bx = lid % g.tiles_x;
+    const int rest = lid / g.tiles_x;
+    const int by = rest % g.tiles_y;
+    const int z = rest / g.tiles_y;
+    const int N = g.N;
+    const int x = bx * TX + tx, y = by * TY + ty;
+    const bool valid = x < N && y < N;
+
+    double acc[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
+
+    if (valid) {
+        const int c[3] = {x, y, z};
+        int cp[3], cm[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cp[i] = c[i] + 1 == N ? 0 : c[i] + 1;
+            cm[i] = c[i] == 0 ? N - 1 : c[i] - 1;
+        }
+        // site index with coordinate i replaced by v (and optionally j by u)
+        auto at1 = [&](int i, int v) {
+            int q[3] = {x, y, z};
+            q[i] = v;
+            return su2_at(N, q[0], q[1], q[2]);
+        };
+        auto at2 = [&](int i, int v, int j, int u) {
+            int q[3] = {x, y, z};
+            q[i] = v;
+            q[j] = u;
+            return su2_at(N, q[0], q[1], q[2]);
+        };
+        const size_t n = su2_at(N, x, y, z);
+        const double *const *P = g.phi_in;
+        const double a0 = P[0][n], b0 = P[1][n], c0 = P[2][n], d0 = P[3][n];
+        const double inv_dx2 = 1.0 / (g.dx * g.dx);
+        const double gdx = g.g / g.dx;
+        const double mcoef = 2.0 / (g.g * g.dx * g.dx * g.dx);
+
+        double l0 = 0.0, l1 = 0.0, l2 = 0.0, l3 = 0.0;   // sum_i U psi(n+i) - 2 psi + U^dag psi(n-i)
+        double grad2 = 0.0;
+        double FE[9];
+        Q4 Ul[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Ul[i] = qload(g.U_in, i, n);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const size_t np = at1(i, cp[i]), nm = at1(i, cm[i]);
+            double r0, s0, r1, s1;
+            qapply(Ul[i], P[0][np], P[1][np], P[2][np], P[3][np], r0, s0, r1, s1);
+            double t0, u0, t1, u1;
+            qapply(qdag(qload(g.U_in, i, nm)), P[0][nm], P[1][nm], P[2][nm], P[3][nm], t0, u0, t1, u1);
+            l0 += r0 - 2.0 * a0 + t0;
+            l1 += s0 - 2.0 * b0 + u0;
+            l2 += r1 - 2.0 * c0 + t1;
+            l3 += s1 - 2.0 * d0 + u1;
+            if (MODE == kSU2Energy) {
+                const double e0 = r0 - a0, e1 = s0 - b0, e2 = r1 - c0, e3 = s1 - d0;
+                grad2 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+            }
+            double j1, j2, j3;
+            isospin(a0, b0, c0, d0, r0, s0, r1, s1, j1, j2, j3);
+            // staple sum of link i
+            Q4 S{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (j == i) continue;
+                const Q4 Ujip = qload(g.U_in, j, np);                     // U_j(n+i)
+                const Q4 Uijp = qload(g.U_in, i, at1(j, cp[j]));          // U_i(n+j)
+                const Q4 Sp = qmul(qmul(Ujip, qdag(Uijp)), qdag(Ul[j]));
+                const Q4 Ujim = qload(g.U_in, j, at2(i, cp[i], j, cm[j])); // U_j(n+i-j)
+                const Q4 Uijm = qload(g.U_in, i, at1(j, cm[j]));           // U_i(n-j)
+                const Q4 Ujjm = qload(g.U_in, j, at1(j, cm[j]));           // U_j(n-j)
+                const Q4 Sm = qmul(qmul(qdag(Ujim), qdag(Uijm)), Ujjm);
+                S = qadd(S, qadd(Sp, Sm));
+            }
+            const Q4 W = qmul(Ul[i], S);
+            FE[3 * i + 0] = gdx * j1 - mcoef * W.x;
+            FE[3 * i + 1] = gdx * j2 - mcoef * W.y;
+            FE[3 * i + 2] = gdx * j3 - mcoef * W.z;
+        }
+        const double m2 = 0.5 * (a0 * a0 + b0 * b0 + c0 * c0 + d0 * d0);
+        const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
+        const double F[4] = {l0 * inv_dx2 - vp * a0, l1 * inv_dx2 - vp * b0, l2 * inv_dx2 - vp * c0,
+                             l3 * inv_dx2 - vp * d0};
+        double pv[4], ev[9];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pv[k] = g.pi[k][n];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ev[k] = g.E[k][n];
+
+        if (MODE == kSU2Energy) {
+            double kin = 0.0, ke = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double s = pv[k] + g.ck * F[k];
+                kin += s * s;
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const double s = ev[k] + g.ck * FE[k];
+                ke += s * s;
+            }
+            acc[0] = 0.5 * kin;
+            acc[1] = grad2 * inv_dx2 * 0.5;
+            const double u = m2 - g.v * g.v;
+            acc[2] = 0.25 * g.lam * u * u;
+            acc[3] = 0.5 * ke;
+            // magnetic: 2 - Tr P = 2 |p|^2 / (1 + p0) per plaquette (unitary P)
+            double mg = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i + 1; j < 3; ++j) {
+                    const Q4 Pij = qmul(qmul(Ul[i], qload(g.U_in, j, at1(i, cp[i]))),
+                                        qmul(qdag(qload(g.U_in, i, at1(j, cp[j]))), qdag(Ul[j])));
+                    mg += 2.0 * (Pij.x * Pij.x + Pij.y * Pij.y + Pij.z * Pij.z) / (1.0 + Pij.w);
+                }
+            acc[4] = 2.0 * mg / (g.g * g.g * g.dx * g.dx * g.dx * g.dx);
+            // Gauss residual of the stored pairing: covariant backward divergence
+            // of E (E_i(n-i) carried to n by U_i(n-i)^dag (E.sigma) U_i(n-i), a
+            // rotation of the vector by the inverse of U's) minus the charge
+            double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const size_t nm = at1(i, cm[i]);
+                const Q4 u = qload(g.U_in, i, nm);
+                const double ex = g.E[3 * i][nm], ey = g.E[3 * i + 1][nm], ez = g.E[3 * i + 2][nm];
+                // t = 2 v x e ; e' = e - w t + v x t  (rotation by the inverse)
+                const double tx2 = 2.0 * (u.y * ez - u.z * ey), ty2 = 2.0 * (u.z * ex - u.x * ez),
+                             tz2 = 2.0 * (u.x * ey - u.y * ex);
+                const double rx = ex - u.w * tx2 + (u.y * tz2 - u.z * ty2);
+                const double ry = ey - u.w * ty2 + (u.z * tx2 - u.x * tz2);
+                const double rz = ez - u.w * tz2 + (u.x * ty2 - u.y * tx2);
+                dv[0] += (ev[3 * i] - rx) / g.dx;
+                dv[1] += (ev[3 * i + 1] - ry) / g.dx;
+                dv[2] += (ev[3 * i + 2] - rz) / g.dx;
+            }
+            double q1, q2, q3;
+            isospin(a0, b0, c0, d0, pv[0], pv[1], pv[2], pv[3], q1, q2, q3);
+            const double ch[3] = {g.g * q1, g.g * q2, g.g * q3};
+            double G2 = 0.0, D2 = 0.0, C2 = 0.0, S2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                G2 += (dv[k] - ch[k]) * (dv[k] - ch[k]);
+                D2 += dv[k] * dv[k];
+                C2 += ch[k] * ch[k];
+                S2 += (dv[k] + ch[k]) * (dv[k] + ch[k]);
+            }
+            const double Gn = sqrt(G2), Dn = sqrt(D2), Cn = sqrt(C2);
+            acc[5] = Gn;
+            acc[6] = sqrt(S2);
+            acc[7] = Dn + Cn;
+            acc[8] = Gn;
+            acc[9] = Dn;
+            acc[10] = Cn;
+        } else {
+            double pn[4], en[9];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                pn[k] = pv[k] + g.ck * F[k];
+                g.pi[k][n] = pn[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                en[k] = ev[k] + g.ck * FE[k];
+                g.E[k][n] = en[k];
+            }
+            if (MODE == kSU2Step) {
+                g.phi_out[0][n] = a0 + g.hd * pn[0];
+                g.phi_out[1][n] = b0 + g.hd * pn[1];
+                g.phi_out[2][n] = c0 + g.hd * pn[2];
+                g.phi_out[3][n] = d0 + g.hd * pn[3];
+                const double hgdx = g.hd * g.g * g.dx;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    // exp(-i hd g dx E.T) = cos(th/2) - i sin(th/2) e.sigma, th = hd g dx |E|
+                    const double ex = en[3 * i], ey = en[3 * i + 1], ez = en[3 * i + 2];
+                    const double len = sqrt(ex * ex + ey * ey + ez * ez);
+                    double sh, chh;
+                    sincos(0.5 * (hgdx * len), &sh, &chh);
+                    Q4 R{chh, 0.0, 0.0, 0.0};
+                    if (len > 0.0) {
+                        R.x = sh * ex / len;
+                        R.y = sh * ey / len;
+                        R.z = sh * ez / len;
+                    }
+                    const Q4 Un = qmul(R, Ul[i]);
+                    g.U_out[4 * i][n] = Un.w;
+                    g.U_out[4 * i + 1][n] = Un.x;
+                    g.U_out[4 * i + 2][n] = Un.y;
+                    g.U_out[4 * i + 3][n] = Un.z;
+                }
+            }
+        }
+    }
+
+    if constexpr (MODE == kSU2Energy) {
+        // block reduction: sums for [0, kSU2Sums), maxes for the rest; the last
+        // block (ticket) combines the block partials in block order
+        const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const double r = k < kSU2Sums ? wave_sum(acc[k]) : wave_max(acc[k]);
+            if (lane == 0) lds_red[w * NQ + k] = r;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int k = 0; k < NQ; ++k) {
+                double r = 0.0;
+                for (int i = 0; i < NT / 64; ++i)
+                    r = k < kSU2Sums ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
+                store_agent(&g.partials[(size_t)lid * NQ + k], r);
+            }
+            const unsigned prev = __hip_atomic_fetch_add(g.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+        }
+        __syncthreads();
+        if (last_flag) {
+            const int nb = gridDim.x;
+            double part[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) part[k] = 0.0;
+            for (int i = tid; i < nb; i += NT) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    const double v = load_agent(&g.partials[(size_t)i * NQ + k]);
+                    part[k] = k < kSU2Sums ? part[k] + v : fmax(part[k], v);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const double r = k < kSU2Sums ? wave_sum(part[k]) : wave_max(part[k]);
+                if (lane == 0) lds_red[w * NQ + k] = r;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int k = 0; k < NQ; ++k) {
+                    double r = 0.0;
+                    for (int i = 0; i < NT / 64; ++i)
+                        r = k < kSU2Sums ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
+                    if (k < kSU2Sums) g.sc->sums[k] = r;
+                    else g.sc->maxes[k - kSU2Sums] = r;
+                }
+                __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+}  // namespace lat

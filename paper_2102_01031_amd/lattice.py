@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "LAT_OK", -1: "LAT_EINVAL", -2: "LAT_EUNSUPPORTED", -3: "LAT_
                 -5: "LAT_ESTATE", -6: "LAT_ENOMEM"}
 INTEGRATORS = {"lf": 0, "vv2": 1, "vv4": 2, "vv6": 3, "vv8": 4, "vv10": 5}
 EXPANSIONS = {"none": 0, "fixed": 1, "self": 2}
-POTENTIALS = {"phi4": 0, "phi4_chi2": 1, "abelian_higgs": 2}
+POTENTIALS = {"phi4": 0, "phi4_chi2": 1, "abelian_higgs": 2, "su2_higgs": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
 
 
@@ -36,7 +36,8 @@ class LatParams(C.Structure):
 
 class LatFields(C.Structure):
     _fields_ = [("phi", C.c_void_p * 2), ("pi", C.c_void_p * 2), ("A", C.c_void_p * 3),
-                ("piA", C.c_void_p * 3)]
+                ("piA", C.c_void_p * 3), ("doublet", C.c_void_p * 4), ("pi_doublet", C.c_void_p * 4),
+                ("U", C.c_void_p * 12), ("E", C.c_void_p * 9)]
 
 
 class LatEnergies(C.Structure):
@@ -45,7 +46,8 @@ class LatEnergies(C.Structure):
                 ("EG_A", C.c_double), ("rho", C.c_double), ("hubble_lhs", C.c_double),
                 ("hubble_rhs", C.c_double), ("hubble_res", C.c_double), ("gauss_max", C.c_double),
                 ("gauss_div_max", C.c_double), ("gauss_charge_max", C.c_double),
-                ("gauss_mean", C.c_double), ("gauss_sum_mean", C.c_double), ("step", C.c_int64)]
+                ("gauss_mean", C.c_double), ("gauss_sum_mean", C.c_double), ("step", C.c_int64),
+                ("EK_B", C.c_double), ("EG_B", C.c_double), ("gauss_abs_mean", C.c_double)]
 
 
 KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1", "adjoint"]
@@ -139,7 +141,10 @@ def _check(code, ctx=None):
 
 def make_params(N, dx, dt, integrator="lf", expansion="none", potential="phi4", precision="f64", t0=0.0,
                 alpha=1.0, lam=1.0, q=0.0, v=1.0, e=0.5, kappa_g=1.0, kappa2=0.25, w_eos=1.0 / 3.0, H0=0.0,
-                t_ref=0.0, a0=1.0, b0=math.nan, lf_staggered=0) -> LatParams:
+                t_ref=0.0, a0=1.0, b0=math.nan, lf_staggered=0, g=None) -> LatParams:
+    """g: the SU(2) coupling g_B Q_B (the same parameter slot as the U(1) charge e)."""
+    if g is not None:
+        e = g
     return LatParams(N, INTEGRATORS[integrator], EXPANSIONS[expansion], POTENTIALS[potential],
                      PRECISIONS[precision], lf_staggered, 0, 0, dx, dt, t0, alpha, lam, q, v, e, kappa_g,
                      kappa2, w_eos, H0, t_ref, a0, b0)
@@ -150,15 +155,20 @@ class Lattice:
 
     phi, pi: lists of contiguous CUDA tensors of N^3 elements (float64, or float32
     with precision="f32").  For the Abelian-Higgs model also A and piA (3 each).
+    For the SU(2) model (potential="su2_higgs", coupling g=...) phi and pi stay
+    empty and doublet, pi_doublet (4 each), U (12: link i, quaternion component
+    k at 4 i + k) and E (9: link i, colour a at 3 i + a) carry the state.
     """
 
-    def __init__(self, phi, pi, *, A=None, piA=None, stream=None, **kw):
+    def __init__(self, phi=(), pi=(), *, A=None, piA=None, doublet=None, pi_doublet=None, U=None, E=None,
+                 stream=None, **kw):
         import torch
         self._torch = torch
         self.params = make_params(**kw)
         dtype = torch.float32 if kw.get("precision", "f64") == "f32" else torch.float64
         N = kw["N"]
-        self._keep = list(phi) + list(pi) + list(A or []) + list(piA or [])
+        self._keep = (list(phi) + list(pi) + list(A or []) + list(piA or []) + list(doublet or [])
+                      + list(pi_doublet or []) + list(U or []) + list(E or []))
         for t in self._keep:
             if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and t.numel() == N ** 3):
                 raise ValueError("fields must be contiguous CUDA tensors of N^3 elements with the run's dtype")
@@ -171,6 +181,10 @@ class Lattice:
             f.A[i] = t.data_ptr()
         for i, t in enumerate(piA or []):
             f.piA[i] = t.data_ptr()
+        for name, ts in (("doublet", doublet), ("pi_doublet", pi_doublet), ("U", U), ("E", E)):
+            arr = getattr(f, name)
+            for i, t in enumerate(ts or []):
+                arr[i] = t.data_ptr()
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -194,7 +208,8 @@ class Lattice:
                     EG_A=e.EG_A, rho=e.rho, hubble_lhs=e.hubble_lhs, hubble_rhs=e.hubble_rhs,
                     hubble_res=e.hubble_res, gauss_max=e.gauss_max, gauss_div_max=e.gauss_div_max,
                     gauss_charge_max=e.gauss_charge_max, gauss_mean=e.gauss_mean,
-                    gauss_sum_mean=e.gauss_sum_mean, step=e.step)
+                    gauss_sum_mean=e.gauss_sum_mean, step=e.step, EK_B=e.EK_B, EG_B=e.EG_B,
+                    gauss_abs_mean=e.gauss_abs_mean)
 
     def spectrum(self, field: int = 0, array: str = "phi", nbins: int | None = None) -> dict:
         """Discrete power spectrum (eq. discretePS) of one stored array, computed

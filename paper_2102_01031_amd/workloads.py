@@ -102,6 +102,29 @@ ABELIAN_HIGGS_128 = U1Workload("abelian-higgs-128^3-LF", N=128, dx=0.4, dt=0.02,
 
 
 @dataclass(frozen=True)
+class SU2Workload:
+    """SU(2) doublet with SU(2) links: the non-Abelian counterpart of the U(1) run
+    (doublet of modulus ``amplitude`` with a white-noise direction per site around
+    the symmetric point, links at the identity, no electric field)."""
+    name: str
+    N: int
+    dx: float
+    dt: float
+    steps: int
+    lam: float = 1.0
+    v: float = 1.0
+    g: float = 0.5
+    amplitude: float = 0.1
+    seed: int = 1004
+
+    def initial_fields(self, N: int | None = None):
+        return inputs.random_direction_su2(self.N if N is None else N, self.amplitude, self.seed)
+
+
+SU2_HIGGS_128 = SU2Workload("su2-higgs-128^3-LF", N=128, dx=0.4, dt=0.02, steps=50)
+
+
+@dataclass(frozen=True)
 class BatchWorkload:
     name: str = "batch-256x{24,32,48,64}^3-LF-fixedRD-fp32"
     n_real: int = 256
