@@ -73,7 +73,7 @@ def measured_ceiling(log):
 
 def run_extras(args, log, only=None):
     """The other workloads' headline numbers: the adjoint/forward time ratio
-    (two fields, 64^3, 2000 VV2 steps), the U(1) stage (128^3 leapfrog), the
+    (two fields, 64^3, 2000 VV2 steps), the U(1) and SU(2) stages (128^3 leapfrog), the
     batched ensemble rate (256 lattices
     of 24^3..64^3, float32, 2000 LF steps, one captured graph) and the
     single-field 32^3 leapfrog run (1000 steps)."""
@@ -153,7 +153,7 @@ def run_extras(args, log, only=None):
         lu.step(uw.steps)
         st = lu.stats(reset=True)
         lu.profile(False)
-        uus = 1e3 * st["kernel_ms"]["u1"] / max(st["launches"]["u1"], 1)
+        uus = 1e3 * st["kernel_ms"]["gauge"] / max(st["launches"]["gauge"], 1)
         ue = lu.energy()
         res["u1"] = {"workload": uw.name, "steps": uw.steps, "us_per_step": 1e6 * uwall / uw.steps,
                      "value": uw.N ** 3 * uw.steps / uwall, "unit": "site-updates/s",
@@ -162,6 +162,36 @@ def run_extras(args, log, only=None):
         lu.close()
         log(f"[bench] U(1): {res['u1']['us_per_step']:.1f} us per step, stage {uus:.1f} us, "
             f"{res['u1']['achieved_GBs_alg']:.0f} GB/s algorithmic")
+    if only in (None, "su2"):
+        # SU(2) doublet + SU(2) links, 128^3, leapfrog: 29 N^3 float64 arrays (doublet 4,
+        # momenta 4, links 12, electric 9), each read once and written once per step
+        # (464 B per site)
+        sw = workloads.SU2_HIGGS_128
+        sf = sw.initial_fields()
+        stt = [[torch.tensor(a.reshape(-1), device=dev) for a in f] for f in sf]
+        ls2 = Lattice(doublet=stt[0], pi_doublet=stt[1], U=stt[2], E=stt[3], N=sw.N, dx=sw.dx, dt=sw.dt,
+                      integrator="lf", expansion="none", potential="su2_higgs", lam=sw.lam, v=sw.v, g=sw.g)
+        ls2.step(sw.steps)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        ls2.step(sw.steps)
+        torch.cuda.synchronize()
+        swall = time.perf_counter() - c0
+        ls2.stats(reset=True)
+        ls2.profile(True)
+        ls2.step(sw.steps)
+        st = ls2.stats(reset=True)
+        ls2.profile(False)
+        sus = 1e3 * st["kernel_ms"]["gauge"] / max(st["launches"]["gauge"], 1)
+        se = ls2.energy()
+        res["su2"] = {"workload": sw.name, "steps": sw.steps, "us_per_step": 1e6 * swall / sw.steps,
+                      "value": sw.N ** 3 * sw.steps / swall, "unit": "site-updates/s",
+                      "mean_launch_us": sus, "achieved_GBs_alg": sw.N ** 3 * 464 / (sus * 1e-6) / 1e9,
+                      "gauss_max_over_terms": se["gauss_max"] / max(se["gauss_div_max"], se["gauss_charge_max"],
+                                                                    1e-300)}
+        ls2.close()
+        log(f"[bench] SU(2): {res['su2']['us_per_step']:.1f} us per step, stage {sus:.1f} us, "
+            f"{res['su2']['achieved_GBs_alg']:.0f} GB/s algorithmic")
     if only in (None, "batch"):
         # batched ensemble
         bw = workloads.BATCH
@@ -222,7 +252,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--main-only", action="store_true", help="only the 256^3 workload (for profiling)")
-    ap.add_argument("--only", choices=["adjoint", "u1", "batch", "lphi4_32"],
+    ap.add_argument("--only", choices=["adjoint", "u1", "su2", "batch", "lphi4_32"],
                     help="only this other workload; prints its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -50,7 +50,8 @@ class LatEnergies(C.Structure):
                 ("EK_B", C.c_double), ("EG_B", C.c_double), ("gauss_abs_mean", C.c_double)]
 
 
-KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "u1", "adjoint"]
+# kind 6 "gauge": the U(1) and SU(2) leapfrog, sync and energy passes
+KERNEL_KINDS = ["kick", "kick_red", "drift_kick", "drift_kick_red", "kick_drift", "energy", "gauge", "adjoint"]
 
 
 # observable name -> (enum lat_observable, field forced by the name or None)
