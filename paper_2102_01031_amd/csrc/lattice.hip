@@ -52,6 +52,7 @@ lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir);
 lat_status su2_sync(lat_ctx *c);
 lat_status su2_energy(lat_ctx *c, lat_energies *out);
 size_t su2_partial_capacity(int N);
+int su2_zc(int N);
 size_t u1_partial_capacity(int N);
 void u1_geometry(lat_ctx *c);
 lat_status batch_step(lat_ctx *c, int64_t nsteps);
@@ -99,6 +100,7 @@ struct lat_ctx {
     void *lnk[12][2] = {};
     void *efl[9] = {};
     int cur_su2 = 0;
+    int su2_zc = 1;
     bool u1_rows = false;   // whole-row U(1) leapfrog kernel
     int u1_ty = 4, u1_zc = 8;
     // scratch
@@ -871,6 +873,8 @@ lat_status validate(const lat_params *p, const lat_fields *f)
             return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model is provided with LF and a = 1");
         if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model runs in float64");
         if (!(p->e_charge != 0.0) || !std::isfinite(p->e_charge)) return fail(nullptr, LAT_EINVAL, "bad SU(2) coupling");
+        if ((double)p->N * p->N * p->N * 8.0 >= 4294967296.0)
+            return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model needs 8 N^3 < 2^32 (32-bit offsets)");
         const void *all[29];
         for (int k = 0; k < 4; ++k) {
             all[k] = f->doublet[k];
@@ -1012,6 +1016,7 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
             if (hipMalloc(&c->lnk[k][1], bytes) != hipSuccess) return bail(LAT_ENOMEM, "shadow allocation failed");
         }
         for (int k = 0; k < 9; ++k) c->efl[k] = f->E[k];
+        c->su2_zc = su2_zc(c->N);
     }
     c->partial_cap = (size_t)(c->nblocks > 1 ? c->nblocks : 1) * kMaxQ + 64;
     if (c->su2) c->partial_cap = su2_partial_capacity(c->N) + 64;
@@ -1553,8 +1558,22 @@ constexpr int kSU2TX = 64, kSU2TY = 4;
 
 size_t su2_partial_capacity(int N)
 {
+    // largest grid: one z plane per block
     const size_t tiles = (size_t)((N + kSU2TX - 1) / kSU2TX) * ((N + kSU2TY - 1) / kSU2TY) * (size_t)N;
     return tiles * (kSU2Sums + kSU2Maxes);
+}
+
+// z planes per block: LATTICE_SU2_ZC if set (1 .. N), else a default that
+// keeps at least 512 blocks
+int su2_zc(int N)
+{
+    const char *env = std::getenv("LATTICE_SU2_ZC");
+    int zc = 0;
+    if (env && std::sscanf(env, "%d", &zc) == 1 && zc >= 1 && zc <= N) return zc;
+    const int tiles = ((N + kSU2TX - 1) / kSU2TX) * ((N + kSU2TY - 1) / kSU2TY);
+    zc = 16;
+    while (zc > 1 && (size_t)tiles * ((N + zc - 1) / zc) < 512) zc /= 2;
+    return zc;
 }
 
 SU2Args su2_args(lat_ctx *c, double ck, double hd, bool write_fields)
@@ -1574,6 +1593,7 @@ SU2Args su2_args(lat_ctx *c, double ck, double hd, bool write_fields)
     a.N = c->N;
     a.tiles_x = (c->N + kSU2TX - 1) / kSU2TX;
     a.tiles_y = (c->N + kSU2TY - 1) / kSU2TY;
+    a.zc = c->su2_zc;
     a.dx = c->p.dx;
     a.g = c->p.e_charge;
     a.lam = c->p.lambda;
@@ -1588,7 +1608,7 @@ SU2Args su2_args(lat_ctx *c, double ck, double hd, bool write_fields)
 
 lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &a)
 {
-    const size_t nbz = (size_t)a.tiles_x * a.tiles_y * c->N;
+    const size_t nbz = (size_t)a.tiles_x * a.tiles_y * (size_t)((c->N + a.zc - 1) / a.zc);
     if (nbz > 0x7fffffffu || (mode == kSU2Energy && nbz * (kSU2Sums + kSU2Maxes) > c->partial_cap))
         return fail(c, LAT_EINVAL, "SU(2) launch exceeds the partials buffer");
     const int nb = (int)nbz;

@@ -17,9 +17,9 @@
 //                 - 2/(g dx^3) vec_a(U_i sum_{j != i} (S+_ij + S-_ij)) ]
 //   S+_ij = U_j(n+i) U_i(n+j)^dag U_j(n)^dag,  S-_ij = U_j(n+i-j)^dag U_i(n-j)^dag U_j(n-j)
 // and the drifts phi += hd pi, U <- exp(-i hd g dx E^a T_a) U.
-// One thread per site; neighbours through the caches.  Momenta are read at
-// their own site only and updated in place; doublet and links are written out
-// of place (the stencil reads the old values).
+// One thread per site of each plane of a z column; neighbours through the
+// caches.  Momenta are read at their own site only and updated in place;
+// doublet and links are written out of place (the stencil reads the old values).
 #pragma once
 #include "common.hpp"
 
@@ -32,7 +32,7 @@ struct SU2Args {
     const double *U_in[12];   // link i, component k at 4 i + k
     double *U_out[12];
     double *E[9];             // link i, colour a at 3 i + a
-    int N, tiles_x, tiles_y, pad;
+    int N, tiles_x, tiles_y, zc;   // zc: z planes per block
     double dx, g, lam, v;
     double ck;   // kick weight
     double hd;   // drift weight
@@ -64,11 +64,6 @@ __device__ __forceinline__ Q4 qdag(const Q4 &a) { return Q4{a.w, -a.x, -a.y, -a.
 
 __device__ __forceinline__ Q4 qadd(const Q4 &a, const Q4 &b) { return Q4{a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z}; }
 
-__device__ __forceinline__ Q4 qload(const double *const *U, int i, size_t n)
-{
-    return Q4{U[4 * i][n], U[4 * i + 1][n], U[4 * i + 2][n], U[4 * i + 3][n]};
-}
-
 // (r0 + i s0, r1 + i s1) = U (a + i b, c + i d), U = w I - i v.sigma
 __device__ __forceinline__ void qapply(const Q4 &u, double a, double b, double c, double d, double &r0, double &s0,
                                        double &r1, double &s1)
@@ -88,11 +83,198 @@ __device__ __forceinline__ void isospin(double a, double b, double c, double d, 
     j3 = 0.5 * ((a * q - b * p) - (c * s - d * r));
 }
 
-__device__ __forceinline__ size_t su2_at(int N, int x, int y, int z)
+// One site's pass.  Site indices are 32-bit element offsets (the caller
+// checks 8 N^3 < 2^32), so every array access is a uniform base plus one
+// 32-bit offset.  c[] = (x, y, z), cp[] / cm[] their periodic successors and
+// predecessors.
+template <int MODE, int NQ>
+__device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], const int (&cp)[3], const int (&cm)[3],
+                                         double (&acc)[NQ])
 {
-    return (size_t)x + (size_t)N * ((size_t)y + (size_t)N * (size_t)z);
+    const unsigned N = (unsigned)g.N;
+    auto off = [&](int x, int y, int z) { return (unsigned)x + N * ((unsigned)y + N * (unsigned)z); };
+    // site index with coordinate i replaced by v (and optionally j by u)
+    auto at1 = [&](int i, int v) {
+        int q[3] = {c[0], c[1], c[2]};
+        q[i] = v;
+        return off(q[0], q[1], q[2]);
+    };
+    auto at2 = [&](int i, int v, int j, int u) {
+        int q[3] = {c[0], c[1], c[2]};
+        q[i] = v;
+        q[j] = u;
+        return off(q[0], q[1], q[2]);
+    };
+    auto L = [&](int i, unsigned m) {
+        return Q4{ld32(g.U_in[4 * i], m), ld32(g.U_in[4 * i + 1], m), ld32(g.U_in[4 * i + 2], m),
+                  ld32(g.U_in[4 * i + 3], m)};
+    };
+    const unsigned n = off(c[0], c[1], c[2]);
+    const double *const *P = g.phi_in;
+    const double a0 = ld32(P[0], n), b0 = ld32(P[1], n), c0 = ld32(P[2], n), d0 = ld32(P[3], n);
+    const double inv_dx2 = 1.0 / (g.dx * g.dx);
+    const double gdx = g.g / g.dx;
+    const double mcoef = 2.0 / (g.g * g.dx * g.dx * g.dx);
+
+    double l0 = 0.0, l1 = 0.0, l2 = 0.0, l3 = 0.0;   // sum_i U psi(n+i) - 2 psi + U^dag psi(n-i)
+    double grad2 = 0.0;
+    double FE[9];
+    Q4 Ul[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Ul[i] = L(i, n);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const unsigned np = at1(i, cp[i]), nm = at1(i, cm[i]);
+        double r0, s0, r1, s1;
+        qapply(Ul[i], ld32(P[0], np), ld32(P[1], np), ld32(P[2], np), ld32(P[3], np), r0, s0, r1, s1);
+        double t0, u0, t1, u1;
+        qapply(qdag(L(i, nm)), ld32(P[0], nm), ld32(P[1], nm), ld32(P[2], nm), ld32(P[3], nm), t0, u0, t1, u1);
+        l0 += r0 - 2.0 * a0 + t0;
+        l1 += s0 - 2.0 * b0 + u0;
+        l2 += r1 - 2.0 * c0 + t1;
+        l3 += s1 - 2.0 * d0 + u1;
+        if (MODE == kSU2Energy) {
+            const double e0 = r0 - a0, e1 = s0 - b0, e2 = r1 - c0, e3 = s1 - d0;
+            grad2 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+        }
+        double j1, j2, j3;
+        isospin(a0, b0, c0, d0, r0, s0, r1, s1, j1, j2, j3);
+        // staple sum of link i
+        Q4 S{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (j == i) continue;
+            const Q4 Sp = qmul(qmul(L(j, np), qdag(L(i, at1(j, cp[j])))), qdag(Ul[j]));   // U_j(n+i) U_i(n+j)^dag U_j^dag
+            const Q4 Sm = qmul(qmul(qdag(L(j, at2(i, cp[i], j, cm[j]))), qdag(L(i, at1(j, cm[j])))),
+                               L(j, at1(j, cm[j])));   // U_j(n+i-j)^dag U_i(n-j)^dag U_j(n-j)
+            S = qadd(S, qadd(Sp, Sm));
+        }
+        const Q4 W = qmul(Ul[i], S);
+        FE[3 * i + 0] = gdx * j1 - mcoef * W.x;
+        FE[3 * i + 1] = gdx * j2 - mcoef * W.y;
+        FE[3 * i + 2] = gdx * j3 - mcoef * W.z;
+    }
+    const double m2 = 0.5 * (a0 * a0 + b0 * b0 + c0 * c0 + d0 * d0);
+    const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
+    const double F[4] = {l0 * inv_dx2 - vp * a0, l1 * inv_dx2 - vp * b0, l2 * inv_dx2 - vp * c0,
+                         l3 * inv_dx2 - vp * d0};
+    double pv[4], ev[9];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[k] = ld32((const double *)g.pi[k], n);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ev[k] = ld32((const double *)g.E[k], n);
+
+    if (MODE == kSU2Energy) {
+        double kin = 0.0, ke = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double s = pv[k] + g.ck * F[k];
+            kin += s * s;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double s = ev[k] + g.ck * FE[k];
+            ke += s * s;
+        }
+        acc[0] += 0.5 * kin;
+        acc[1] += grad2 * inv_dx2 * 0.5;
+        const double u = m2 - g.v * g.v;
+        acc[2] += 0.25 * g.lam * u * u;
+        acc[3] += 0.5 * ke;
+        // magnetic: 2 - Tr P = 2 |p|^2 / (1 + p0) per plaquette (unitary P)
+        double mg = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) {
+                const Q4 Pij = qmul(qmul(Ul[i], L(j, at1(i, cp[i]))), qmul(qdag(L(i, at1(j, cp[j]))), qdag(Ul[j])));
+                mg += 2.0 * (Pij.x * Pij.x + Pij.y * Pij.y + Pij.z * Pij.z) / (1.0 + Pij.w);
+            }
+        acc[4] += 2.0 * mg / (g.g * g.g * g.dx * g.dx * g.dx * g.dx);
+        // Gauss residual of the stored pairing: covariant backward divergence
+        // of E (E_i(n-i) carried to n by U_i(n-i)^dag (E.sigma) U_i(n-i), a
+        // rotation of the vector by the inverse of U's) minus the charge
+        double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const unsigned nm = at1(i, cm[i]);
+            const Q4 u = L(i, nm);
+            const double ex = ld32((const double *)g.E[3 * i], nm), ey = ld32((const double *)g.E[3 * i + 1], nm),
+                         ez = ld32((const double *)g.E[3 * i + 2], nm);
+            // t = 2 v x e ; e' = e - w t + v x t  (rotation by the inverse)
+            const double tx2 = 2.0 * (u.y * ez - u.z * ey), ty2 = 2.0 * (u.z * ex - u.x * ez),
+                         tz2 = 2.0 * (u.x * ey - u.y * ex);
+            const double rx = ex - u.w * tx2 + (u.y * tz2 - u.z * ty2);
+            const double ry = ey - u.w * ty2 + (u.z * tx2 - u.x * tz2);
+            const double rz = ez - u.w * tz2 + (u.x * ty2 - u.y * tx2);
+            dv[0] += (ev[3 * i] - rx) / g.dx;
+            dv[1] += (ev[3 * i + 1] - ry) / g.dx;
+            dv[2] += (ev[3 * i + 2] - rz) / g.dx;
+        }
+        double q1, q2, q3;
+        isospin(a0, b0, c0, d0, pv[0], pv[1], pv[2], pv[3], q1, q2, q3);
+        const double ch[3] = {g.g * q1, g.g * q2, g.g * q3};
+        double G2 = 0.0, D2 = 0.0, C2 = 0.0, S2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G2 += (dv[k] - ch[k]) * (dv[k] - ch[k]);
+            D2 += dv[k] * dv[k];
+            C2 += ch[k] * ch[k];
+            S2 += (dv[k] + ch[k]) * (dv[k] + ch[k]);
+        }
+        const double Gn = sqrt(G2), Dn = sqrt(D2), Cn = sqrt(C2);
+        acc[5] += Gn;
+        acc[6] += sqrt(S2);
+        acc[7] += Dn + Cn;
+        acc[8] = fmax(acc[8], Gn);
+        acc[9] = fmax(acc[9], Dn);
+        acc[10] = fmax(acc[10], Cn);
+    } else {
+        double pn[4], en[9];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pn[k] = pv[k] + g.ck * F[k];
+            st32(g.pi[k], n, pn[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            en[k] = ev[k] + g.ck * FE[k];
+            st32(g.E[k], n, en[k]);
+        }
+        if (MODE == kSU2Step) {
+            st32(g.phi_out[0], n, a0 + g.hd * pn[0]);
+            st32(g.phi_out[1], n, b0 + g.hd * pn[1]);
+            st32(g.phi_out[2], n, c0 + g.hd * pn[2]);
+            st32(g.phi_out[3], n, d0 + g.hd * pn[3]);
+            const double hgdx = g.hd * g.g * g.dx;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                // exp(-i hd g dx E.T) = cos(th/2) - i sin(th/2) e.sigma, th = hd g dx |E|
+                const double ex = en[3 * i], ey = en[3 * i + 1], ez = en[3 * i + 2];
+                const double len = sqrt(ex * ex + ey * ey + ez * ez);
+                double sh, chh;
+                sincos(0.5 * (hgdx * len), &sh, &chh);
+                Q4 R{chh, 0.0, 0.0, 0.0};
+                if (len > 0.0) {
+                    R.x = sh * ex / len;
+                    R.y = sh * ey / len;
+                    R.z = sh * ez / len;
+                }
+                const Q4 Un = qmul(R, Ul[i]);
+                st32(g.U_out[4 * i], n, Un.w);
+                st32(g.U_out[4 * i + 1], n, Un.x);
+                st32(g.U_out[4 * i + 2], n, Un.y);
+                st32(g.U_out[4 * i + 3], n, Un.z);
+            }
+        }
+    }
 }
 
+// Block = TX x TY sites of a z column [z0, z0 + zc); logical blocks run x
+// tile fastest, then y tile, then z chunk, dealt to the XCDs in contiguous
+// ranges, so the blocks of one XCD march neighbouring columns together and
+// a site's values are reused from L2 by the planes z - 1, z, z + 1 that
+// read them.
 template <int TX, int TY, int MODE>
 __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
 {
@@ -107,197 +289,26 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
     const int bx = lid % g.tiles_x;
     const int rest = lid / g.tiles_x;
     const int by = rest % g.tiles_y;
-    const int z = rest / g.tiles_y;
+    const int bz = rest / g.tiles_y;
     const int N = g.N;
     const int x = bx * TX + tx, y = by * TY + ty;
-    const bool valid = x < N && y < N;
+    const int z0 = bz * g.zc, z1 = min(z0 + g.zc, N);
 
     double acc[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
 
-    if (valid) {
-        const int c[3] = {x, y, z};
-        int cp[3], cm[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            cp[i] = c[i] + 1 == N ? 0 : c[i] + 1;
-            cm[i] = c[i] == 0 ? N - 1 : c[i] - 1;
-        }
-        // site index with coordinate i replaced by v (and optionally j by u)
-        auto at1 = [&](int i, int v) {
-            int q[3] = {x, y, z};
-            q[i] = v;
-            return su2_at(N, q[0], q[1], q[2]);
-        };
-        auto at2 = [&](int i, int v, int j, int u) {
-            int q[3] = {x, y, z};
-            q[i] = v;
-            q[j] = u;
-            return su2_at(N, q[0], q[1], q[2]);
-        };
-        const size_t n = su2_at(N, x, y, z);
-        const double *const *P = g.phi_in;
-        const double a0 = P[0][n], b0 = P[1][n], c0 = P[2][n], d0 = P[3][n];
-        const double inv_dx2 = 1.0 / (g.dx * g.dx);
-        const double gdx = g.g / g.dx;
-        const double mcoef = 2.0 / (g.g * g.dx * g.dx * g.dx);
-
-        double l0 = 0.0, l1 = 0.0, l2 = 0.0, l3 = 0.0;   // sum_i U psi(n+i) - 2 psi + U^dag psi(n-i)
-        double grad2 = 0.0;
-        double FE[9];
-        Q4 Ul[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) Ul[i] = qload(g.U_in, i, n);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const size_t np = at1(i, cp[i]), nm = at1(i, cm[i]);
-            double r0, s0, r1, s1;
-            qapply(Ul[i], P[0][np], P[1][np], P[2][np], P[3][np], r0, s0, r1, s1);
-            double t0, u0, t1, u1;
-            qapply(qdag(qload(g.U_in, i, nm)), P[0][nm], P[1][nm], P[2][nm], P[3][nm], t0, u0, t1, u1);
-            l0 += r0 - 2.0 * a0 + t0;
-            l1 += s0 - 2.0 * b0 + u0;
-            l2 += r1 - 2.0 * c0 + t1;
-            l3 += s1 - 2.0 * d0 + u1;
-            if (MODE == kSU2Energy) {
-                const double e0 = r0 - a0, e1 = s0 - b0, e2 = r1 - c0, e3 = s1 - d0;
-                grad2 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
-            }
-            double j1, j2, j3;
-            isospin(a0, b0, c0, d0, r0, s0, r1, s1, j1, j2, j3);
-            // staple sum of link i
-            Q4 S{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (j == i) continue;
-                const Q4 Ujip = qload(g.U_in, j, np);                     // U_j(n+i)
-                const Q4 Uijp = qload(g.U_in, i, at1(j, cp[j]));          // U_i(n+j)
-                const Q4 Sp = qmul(qmul(Ujip, qdag(Uijp)), qdag(Ul[j]));
-                const Q4 Ujim = qload(g.U_in, j, at2(i, cp[i], j, cm[j])); // U_j(n+i-j)
-                const Q4 Uijm = qload(g.U_in, i, at1(j, cm[j]));           // U_i(n-j)
-                const Q4 Ujjm = qload(g.U_in, j, at1(j, cm[j]));           // U_j(n-j)
-                const Q4 Sm = qmul(qmul(qdag(Ujim), qdag(Uijm)), Ujjm);
-                S = qadd(S, qadd(Sp, Sm));
-            }
-            const Q4 W = qmul(Ul[i], S);
-            FE[3 * i + 0] = gdx * j1 - mcoef * W.x;
-            FE[3 * i + 1] = gdx * j2 - mcoef * W.y;
-            FE[3 * i + 2] = gdx * j3 - mcoef * W.z;
-        }
-        const double m2 = 0.5 * (a0 * a0 + b0 * b0 + c0 * c0 + d0 * d0);
-        const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
-        const double F[4] = {l0 * inv_dx2 - vp * a0, l1 * inv_dx2 - vp * b0, l2 * inv_dx2 - vp * c0,
-                             l3 * inv_dx2 - vp * d0};
-        double pv[4], ev[9];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pv[k] = g.pi[k][n];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) ev[k] = g.E[k][n];
-
-        if (MODE == kSU2Energy) {
-            double kin = 0.0, ke = 0.0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double s = pv[k] + g.ck * F[k];
-                kin += s * s;
-            }
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const double s = ev[k] + g.ck * FE[k];
-                ke += s * s;
-            }
-            acc[0] = 0.5 * kin;
-            acc[1] = grad2 * inv_dx2 * 0.5;
-            const double u = m2 - g.v * g.v;
-            acc[2] = 0.25 * g.lam * u * u;
-            acc[3] = 0.5 * ke;
-            // magnetic: 2 - Tr P = 2 |p|^2 / (1 + p0) per plaquette (unitary P)
-            double mg = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = i + 1; j < 3; ++j) {
-                    const Q4 Pij = qmul(qmul(Ul[i], qload(g.U_in, j, at1(i, cp[i]))),
-                                        qmul(qdag(qload(g.U_in, i, at1(j, cp[j]))), qdag(Ul[j])));
-                    mg += 2.0 * (Pij.x * Pij.x + Pij.y * Pij.y + Pij.z * Pij.z) / (1.0 + Pij.w);
-                }
-            acc[4] = 2.0 * mg / (g.g * g.g * g.dx * g.dx * g.dx * g.dx);
-            // Gauss residual of the stored pairing: covariant backward divergence
-            // of E (E_i(n-i) carried to n by U_i(n-i)^dag (E.sigma) U_i(n-i), a
-            // rotation of the vector by the inverse of U's) minus the charge
-            double dv[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const size_t nm = at1(i, cm[i]);
-                const Q4 u = qload(g.U_in, i, nm);
-                const double ex = g.E[3 * i][nm], ey = g.E[3 * i + 1][nm], ez = g.E[3 * i + 2][nm];
-                // t = 2 v x e ; e' = e - w t + v x t  (rotation by the inverse)
-                const double tx2 = 2.0 * (u.y * ez - u.z * ey), ty2 = 2.0 * (u.z * ex - u.x * ez),
-                             tz2 = 2.0 * (u.x * ey - u.y * ex);
-                const double rx = ex - u.w * tx2 + (u.y * tz2 - u.z * ty2);
-                const double ry = ey - u.w * ty2 + (u.z * tx2 - u.x * tz2);
-                const double rz = ez - u.w * tz2 + (u.x * ty2 - u.y * tx2);
-                dv[0] += (ev[3 * i] - rx) / g.dx;
-                dv[1] += (ev[3 * i + 1] - ry) / g.dx;
-                dv[2] += (ev[3 * i + 2] - rz) / g.dx;
-            }
-            double q1, q2, q3;
-            isospin(a0, b0, c0, d0, pv[0], pv[1], pv[2], pv[3], q1, q2, q3);
-            const double ch[3] = {g.g * q1, g.g * q2, g.g * q3};
-            double G2 = 0.0, D2 = 0.0, C2 = 0.0, S2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                G2 += (dv[k] - ch[k]) * (dv[k] - ch[k]);
-                D2 += dv[k] * dv[k];
-                C2 += ch[k] * ch[k];
-                S2 += (dv[k] + ch[k]) * (dv[k] + ch[k]);
-            }
-            const double Gn = sqrt(G2), Dn = sqrt(D2), Cn = sqrt(C2);
-            acc[5] = Gn;
-            acc[6] = sqrt(S2);
-            acc[7] = Dn + Cn;
-            acc[8] = Gn;
-            acc[9] = Dn;
-            acc[10] = Cn;
-        } else {
-            double pn[4], en[9];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                pn[k] = pv[k] + g.ck * F[k];
-                g.pi[k][n] = pn[k];
-            }
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                en[k] = ev[k] + g.ck * FE[k];
-                g.E[k][n] = en[k];
-            }
-            if (MODE == kSU2Step) {
-                g.phi_out[0][n] = a0 + g.hd * pn[0];
-                g.phi_out[1][n] = b0 + g.hd * pn[1];
-                g.phi_out[2][n] = c0 + g.hd * pn[2];
-                g.phi_out[3][n] = d0 + g.hd * pn[3];
-                const double hgdx = g.hd * g.g * g.dx;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    // exp(-i hd g dx E.T) = cos(th/2) - i sin(th/2) e.sigma, th = hd g dx |E|
-                    const double ex = en[3 * i], ey = en[3 * i + 1], ez = en[3 * i + 2];
-                    const double len = sqrt(ex * ex + ey * ey + ez * ez);
-                    double sh, chh;
-                    sincos(0.5 * (hgdx * len), &sh, &chh);
-                    Q4 R{chh, 0.0, 0.0, 0.0};
-                    if (len > 0.0) {
-                        R.x = sh * ex / len;
-                        R.y = sh * ey / len;
-                        R.z = sh * ez / len;
-                    }
-                    const Q4 Un = qmul(R, Ul[i]);
-                    g.U_out[4 * i][n] = Un.w;
-                    g.U_out[4 * i + 1][n] = Un.x;
-                    g.U_out[4 * i + 2][n] = Un.y;
-                    g.U_out[4 * i + 3][n] = Un.z;
-                }
-            }
+    if (x < N && y < N) {
+        int c[3] = {x, y, z0}, cp[3], cm[3];
+        cp[0] = x + 1 == N ? 0 : x + 1;
+        cm[0] = x == 0 ? N - 1 : x - 1;
+        cp[1] = y + 1 == N ? 0 : y + 1;
+        cm[1] = y == 0 ? N - 1 : y - 1;
+        for (int z = z0; z < z1; ++z) {
+            c[2] = z;
+            cp[2] = z + 1 == N ? 0 : z + 1;
+            cm[2] = z == 0 ? N - 1 : z - 1;
+            su2_site<MODE, NQ>(g, c, cp, cm, acc);
         }
     }
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import rel_maxdiff, say, to_dev
+from gpu_util import rel_maxdiff, say, tile_env, to_dev
 from paper_2102_01031_amd import inputs, workloads
 
 pytestmark = pytest.mark.gpu
@@ -88,6 +88,25 @@ def test_su2_parity_generic_state(N, steps, seed):
                    ("gauss_max", "gauss_max"), ("gauss_abs_mean", "gauss_abs_mean")):
         assert abs(eg[kg] - go[ko]) <= 1e-11 * go[ko], (kg, eg[kg], go[ko])
     say(f"[su2]   state rel err {worst:.2e}, rho {eg['rho']:.9e} (oracle {st.energy()['rho']:.9e})")
+    lat.close()
+
+
+@pytest.mark.parametrize("N,zc,steps", [(24, 5, 7), (24, 24, 4), (70, 3, 2), (16, 1, 6)])
+def test_su2_parity_z_columns(N, zc, steps):
+    """Blocks that march z columns of zc planes: a ragged last column (24 / 5,
+    70 / 3), one column over the whole lattice (24) and one plane (1)."""
+    wl = workloads.SU2_HIGGS_128
+    kw = su2_kwargs(wl, N)
+    fields = inputs.random_su2_state(N, 40 + N)
+    say(f"[su2] z columns N={N} zc={zc} steps={steps}")
+    with tile_env(str(zc), "LATTICE_SU2_ZC"):
+        lat, gt = gpu_su2(kw, fields, [steps])
+    eg = lat.energy()
+    st = oracle_su2(kw, fields).run(steps)
+    compare_su2(gt, st, TOL, f"su2-zc-{N}-{zc}")
+    compare_su2_energy(eg, st.energy(), TOL, f"su2-zc-{N}-{zc}")
+    go = st.gauss()
+    assert abs(eg["gauss_max"] - go["gauss_max"]) <= 1e-11 * go["gauss_max"]
     lat.close()
 
 
