@@ -94,6 +94,53 @@ def test_no_device_here_reports_enodev():
     assert b"GPU" in L.lib().lattice_last_error(None)
 
 
+def _su2_fields():
+    f = L.LatFields()
+    for k in range(4):
+        f.doublet[k] = 0x50000 + 0x1000 * k
+        f.pi_doublet[k] = 0x60000 + 0x1000 * k
+    for k in range(12):
+        f.U[k] = 0x70000 + 0x1000 * k
+    for k in range(9):
+        f.E[k] = 0x90000 + 0x1000 * k
+    return f
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(integrator="vv2"), L.LAT_EUNSUPPORTED),
+    (dict(expansion="fixed", H0=0.1), L.LAT_EUNSUPPORTED),
+    (dict(precision="f32"), L.LAT_EUNSUPPORTED),
+    (dict(g=0.0), L.LAT_EINVAL),
+    (dict(N=1700), L.LAT_EUNSUPPORTED),        # 8 N^3 >= 2^32: 32-bit offsets
+])
+def test_su2_validation_errors(kw, code):
+    """SU(2) arguments are checked before any device call."""
+    base = dict(N=8, dx=0.4, dt=0.02, potential="su2_higgs", g=0.5)
+    base.update(kw)
+    rc, ctx = _init(L.make_params(**base), _su2_fields())
+    assert rc == code, (kw, rc, L.lib().lattice_last_error(None))
+    assert not ctx.value
+
+
+@pytest.mark.parametrize("group,k", [("doublet", 2), ("pi_doublet", 0), ("U", 11), ("E", 4)])
+def test_su2_null_and_misaligned_pointers(group, k):
+    p = L.make_params(N=8, dx=0.4, dt=0.02, potential="su2_higgs", g=0.5)
+    f = _su2_fields()
+    getattr(f, group)[k] = None
+    assert _init(p, f)[0] == L.LAT_EINVAL
+    assert b"SU(2)" in L.lib().lattice_last_error(None)
+    f = _su2_fields()
+    getattr(f, group)[k] = 0x80004
+    assert _init(p, f)[0] == L.LAT_EINVAL
+
+
+def test_su2_fields_struct_layout():
+    """The ctypes mirror of lat_fields: the SU(2) members follow the U(1) ones."""
+    assert L.LatFields.doublet.offset == 10 * C.sizeof(C.c_void_p)
+    assert L.LatFields.E.offset == (10 + 4 + 4 + 12) * C.sizeof(C.c_void_p)
+    assert C.sizeof(L.LatFields) == 39 * C.sizeof(C.c_void_p)
+
+
 def test_null_context_calls():
     lib = L.lib()
     assert lib.lattice_step(None, 1) == L.LAT_EINVAL
