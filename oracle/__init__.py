@@ -93,6 +93,9 @@ def lib():
         L.orc_su2_gauss.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
         L.orc_su2_run_lf.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long]
         L.orc_su2_lf_sync.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock)]
+        L.orc_gauss_solve.argtypes = [C.c_int, C.c_double, dp, pp]
+        L.orc_su2_gauss_init.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
+        L.orc_u1_gauss_init.argtypes = [C.POINTER(U1Params), pp, pp, pp, dp]
         _lib = L
     return _lib
 
@@ -379,6 +382,13 @@ class U1State:
         _chk(lib().orc_u1_gauss(C.byref(self._p), *self._args(), _dp(out)), "u1 gauss")
         return _u1_dict(out)
 
+    def gauss_init(self):
+        """pi_A from the lattice Gauss law; returns <rho>."""
+        mean = np.zeros(1)
+        _chk(lib().orc_u1_gauss_init(C.byref(self._p), _pp(self.phi), _pp(self.pi), _pp(self.piA), _dp(mean)),
+             "u1 gauss init")
+        return mean
+
     def forces(self):
         F = [np.zeros_like(self.phi[0]) for _ in range(5)]
         _chk(lib().orc_u1_forces(C.byref(self._p), _pp(self.phi), _pp(self.A), _pp(F[:2]), _pp(F[2:])), "u1 forces")
@@ -441,6 +451,12 @@ class SU2State:
         _chk(lib().orc_su2_gauss(C.byref(self._p), *self._args(), _dp(out)), "su2 gauss")
         return _su2_dict(out)
 
+    def gauss_init(self):
+        """E from the lattice Gauss law (links at the identity); returns <rho^a>."""
+        mean = np.zeros(3)
+        _chk(lib().orc_su2_gauss_init(C.byref(self._p), *self._args(), _dp(mean)), "su2 gauss init")
+        return mean
+
     def forces(self):
         F = [np.zeros_like(self.phi[0]) for _ in range(13)]
         _chk(lib().orc_su2_forces(C.byref(self._p), _pp(self.phi), _pp(self.U), _pp(F[:4]), _pp(F[4:])),
@@ -452,6 +468,15 @@ def _su2_dict(out):
     return dict(EK_phi=out[0], EG_phi=out[1], EV=out[2], EK_B=out[3], EG_B=out[4], rho=out[5],
                 gauss_max=out[6], div_max=out[7], charge_max=out[8], gauss_mean=out[9],
                 gauss_sum_mean=out[10], gauss_abs_mean=out[11])
+
+
+def gauss_solve(rho, dx):
+    """E_i = grad+_i Lap^-1 (rho - <rho>) of a real N^3 array (the oracle's own DFT)."""
+    rho = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).reshape(-1))
+    N = _side(rho)
+    E = [np.zeros_like(rho) for _ in range(3)]
+    _chk(lib().orc_gauss_solve(N, dx, _dp(rho), _pp(E)), "gauss solve")
+    return E
 
 
 def spectrum_bins(N):

@@ -44,6 +44,11 @@
  *       U <- exp(-i h g dx E^a T_a) U; the magnetic term 2/(g^2 dx^4) (2 - Tr P)
  *       per plaquette is the normalisation the toolkit's expansion of Tr P
  *       fixes.  Only a = 1.
+ *   R14 Gauss-consistent initial gauge momenta: with the links at the
+ *       identity (the initial condition of sec. 6.3) the Gauss law is the
+ *       plain lattice divergence div- E = rho; its longitudinal solution uses
+ *       the lattice Laplacian sum_i grad-_i grad+_i (the continuum i k_i / k^2
+ *       of eq. GaugeCurrentFluc would leave a residual of order dx^2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -1807,5 +1812,101 @@ int orc_su2_lf_sync(const orc_su2_params *p, double *const *phi, double *const *
     if (c->lf_stag == 0) return 0;
     su2_kick(p, phi, pi, U, E, 0.5 * c->lf_stag * p->dt);
     c->lf_stag = 0;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gauss-consistent initial gauge momenta (sec. 6.3, eqs. kAi1 and      */
+/* GaugeCurrentFluc; reading R14): with the links at the identity the   */
+/* Gauss law reads div- E = rho, and its longitudinal solution on the   */
+/* lattice is E_i = grad+_i chi with Lap chi = rho - <rho> (the lattice  */
+/* Laplacian sum_i grad-_i grad+_i, so div- E = rho - <rho> exactly).    */
+/* chi comes from the own DFT: chi~(k) = -rho~(k) / L(k),                */
+/* L(k) = (4/dx^2) sum_i sin^2(pi k_i / N), chi~(0) = 0.                  */
+/* ------------------------------------------------------------------ */
+
+int orc_gauss_solve(int N, double dx, const double *rho, double *const *E)
+{
+    size_t V = vol(N);
+    double *re = (double *)malloc(V * sizeof(double)), *im = (double *)malloc(V * sizeof(double));
+    double *cs = (double *)malloc((size_t)N * sizeof(double)), *sn = (double *)malloc((size_t)N * sizeof(double));
+    dft3_real(N, rho, re, im, cs, sn);
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                size_t n = at(N, x, y, z);
+                double sx = sin(ORC_PI * x / N), sy = sin(ORC_PI * y / N), sz = sin(ORC_PI * z / N);
+                double L = 4.0 / (dx * dx) * (sx * sx + sy * sy + sz * sz);
+                if (n == 0) {
+                    re[n] = 0.0;
+                    im[n] = 0.0;
+                } else {
+                    re[n] = -re[n] / L;
+                    im[n] = -im[n] / L;
+                }
+            }
+    for (int axis = 0; axis < 3; ++axis) dft_axis(N, re, im, axis, cs, sn, +1);
+    for (size_t n = 0; n < V; ++n) re[n] /= (double)V;   /* chi, real up to rounding */
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                size_t n = at(N, x, y, z);
+                for (int i = 0; i < 3; ++i) E[i][n] = (re[nbr(N, x, y, z, i, +1)] - re[n]) / dx;
+            }
+    free(re);
+    free(im);
+    free(cs);
+    free(sn);
+    return 0;
+}
+
+/* SU(2): rho^a = g Im(psi^dag T_a pi_psi) of the stored doublet and momenta;
+ * E_i^a from orc_gauss_solve for each a; mean[a] = <rho^a> (what no periodic
+ * field can absorb).  Needs the links at the identity (returns -4 otherwise). */
+int orc_su2_gauss_init(const orc_su2_params *p, double *const *phi, double *const *pi,
+                       double *const *U, double *const *E, double *mean)
+{
+    int N = p->N;
+    size_t V = vol(N);
+    for (int i = 0; i < 3; ++i)
+        for (size_t n = 0; n < V; ++n)
+            if (U[4 * i][n] != 1.0 || U[4 * i + 1][n] != 0.0 || U[4 * i + 2][n] != 0.0 || U[4 * i + 3][n] != 0.0)
+                return -4;
+    double *rho = (double *)malloc(V * sizeof(double));
+    for (int a = 0; a < 3; ++a) {
+        nsum s = {0, 0};
+        for (size_t n = 0; n < V; ++n) {
+            double complex psi[2], pp[2], t = 0.0;
+            su2_psi(phi, n, psi);
+            su2_psi(pi, n, pp);
+            for (int r = 0; r < 2; ++r)
+                for (int q = 0; q < 2; ++q) t += conj(psi[r]) * 0.5 * PAULI[a][r][q] * pp[q];
+            rho[n] = p->g * cimag(t);
+            nadd(&s, rho[n]);
+        }
+        mean[a] = nval(&s) / (double)V;
+        double *Ea[3] = {E[a], E[3 + a], E[6 + a]};
+        orc_gauss_solve(N, p->dx, rho, Ea);
+    }
+    free(rho);
+    return 0;
+}
+
+/* U(1): rho = e kappa_g (phi0 pi1 - phi1 pi0); pi_A from orc_gauss_solve
+ * (the Abelian Gauss law does not involve the links). */
+int orc_u1_gauss_init(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *piA,
+                      double *mean)
+{
+    int N = p->N;
+    size_t V = vol(N);
+    double *rho = (double *)malloc(V * sizeof(double));
+    nsum s = {0, 0};
+    for (size_t n = 0; n < V; ++n) {
+        rho[n] = p->e * p->kappa_g * (phi[0][n] * pi[1][n] - phi[1][n] * pi[0][n]);
+        nadd(&s, rho[n]);
+    }
+    mean[0] = nval(&s) / (double)V;
+    orc_gauss_solve(N, p->dx, rho, piA);
+    free(rho);
     return 0;
 }

@@ -150,3 +150,57 @@ def random_su2_state(N: int, seed: int, phi_amp: float = 0.3, pi_amp: float = 0.
         U += [np.cos(0.5 * th)] + [np.sin(0.5 * th) * ax[a] for a in range(3)]
     E = [e_amp * rng.standard_normal(shape) for _ in range(9)]
     return phi, pi, U, E
+
+
+def _half_space_hermitian(d: np.ndarray) -> np.ndarray:
+    """Hermitian array from the draws of one half of Fourier space: mode k keeps
+    its draw where its flat index is below that of -k, takes conj(d(-k)) where
+    it is above, and its real part where k = -k."""
+    N = d.shape[0]
+    neg = (-np.arange(N)) % N
+    flat = np.arange(N ** 3).reshape(N, N, N)
+    nflat = flat[np.ix_(neg, neg, neg)]
+    dn = d[np.ix_(neg, neg, neg)]
+    return np.where(flat < nflat, d, np.where(flat > nflat, np.conj(dn), d.real + 0j))
+
+
+def charged_fluctuations(N: int, dx: float, ncomp: int, norm: float, amp: float, mass2: float, seed: int):
+    """Charged scalar (ncomp = 2, eq. ChargedScalars' complex field) or doublet
+    (ncomp = 4) with homogeneous components phi_n = norm/sqrt2 (so |Phi| = norm
+    when ncomp = 4) plus fluctuations of eqs. fpr_influct3 and fpr_influct4 at
+    a = 1, no expansion, with the constraints InConstr:1 and InConstr:2 that
+    remove the homogeneous charge:
+        dphi_n(k)  = r_n (e^{i th_n1} + e^{i th_n2}) / sqrt2,
+        dphi'_n(k) = i w_k r_n (e^{i th_n1} - e^{i th_n2}) / sqrt2,
+        th_n2 = th_02 + th_n1 - th_01,
+    E[r_n^2] = (N/dx)^3 amp / w_k, w_k^2 = k^2 + mass2.  Each mode's momenta are
+    then a real multiple of its fields, the same for every component, so the
+    charge density has no homogeneous part; the half-space Hermitian
+    construction keeps that (a pairwise average of k and -k would not).
+    Draw order: th_01, th_02, then r_n for every n, then th_n1 for n >= 1,
+    each over the full N^3 array, from numpy.random.default_rng(seed).
+    Returns (phi, pi): lists of ncomp real (N, N, N) arrays."""
+    rng = np.random.default_rng(seed)
+    shape = (N, N, N)
+    kIR = 2.0 * np.pi / (N * dx)
+    k = kIR * mode_numbers(N)
+    w = np.sqrt(k * k + mass2)
+    th01 = rng.uniform(0.0, 2.0 * np.pi, size=shape)
+    th02 = rng.uniform(0.0, 2.0 * np.pi, size=shape)
+    with np.errstate(divide="ignore"):
+        sigma2 = np.where(w > 0, (N / dx) ** 3 * amp / np.where(w > 0, w, 1.0), 0.0)
+    scale = np.sqrt(sigma2 / 2.0)
+    r = [rng.rayleigh(1.0, size=shape) * scale for _ in range(ncomp)]
+    th1 = [th01] + [rng.uniform(0.0, 2.0 * np.pi, size=shape) for _ in range(1, ncomp)]
+    phi, pi = [], []
+    for n in range(ncomp):
+        th2 = th02 + th1[n] - th01
+        e1, e2 = r[n] * np.exp(1j * th1[n]), r[n] * np.exp(1j * th2)
+        d = (e1 + e2) / np.sqrt(2.0)
+        dp = (1j * w / np.sqrt(2.0)) * (e1 - e2)
+        d[0, 0, 0] = 0.0
+        dp[0, 0, 0] = 0.0
+        d, dp = _half_space_hermitian(d), _half_space_hermitian(dp)
+        phi.append(norm / np.sqrt(2.0) + np.fft.ifftn(d).real)
+        pi.append(np.fft.ifftn(dp).real)
+    return phi, pi

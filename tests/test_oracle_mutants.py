@@ -91,6 +91,13 @@ MUTANTS = [
      "mat2 Y = m2_mul(m2_mul(Um, X), m2_dag(Um));", "test_oracle_su2.py"),
     ("SU(2) backward link not conjugated", "m2_apply(m2_dag(su2_link(U, i, nm)), qm, b);",
      "m2_apply(su2_link(U, i, nm), qm, b);", "test_oracle_su2.py"),
+    ("Gauss solve with the continuum Poisson symbol",
+     "double sx = sin(ORC_PI * x / N), sy = sin(ORC_PI * y / N), sz = sin(ORC_PI * z / N);",
+     "double sx = ORC_PI * x / N, sy = ORC_PI * y / N, sz = ORC_PI * z / N;", "test_oracle_gauss_init.py"),
+    ("Gauss solve field as a backward difference", "E[i][n] = (re[nbr(N, x, y, z, i, +1)] - re[n]) / dx;",
+     "E[i][n] = (re[n] - re[nbr(N, x, y, z, i, -1)]) / dx;", "test_oracle_gauss_init.py"),
+    ("SU(2) initial charge without the 1/2 of T_a", "t += conj(psi[r]) * 0.5 * PAULI[a][r][q] * pp[q];",
+     "t += conj(psi[r]) * PAULI[a][r][q] * pp[q];", "test_oracle_gauss_init.py"),
     ("SU(2) plaquette order", "mat2 P = m2_mul(m2_mul(su2_link(U, i, n), su2_link(U, j, at(N, ci[0], ci[1], ci[2]))),",
      "mat2 P = m2_mul(m2_mul(su2_link(U, j, at(N, ci[0], ci[1], ci[2])), su2_link(U, i, n)),", "test_oracle_su2.py"),
 ]
