@@ -216,6 +216,25 @@ lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
 lat_status lattice_spectrum(lat_ctx *ctx, int32_t field, int32_t which, int32_t nbins, double *sum,
                             double *delta, int64_t *count);
 
+/* Gauss-consistent initial gauge momenta (sec. 6.3, eqs. kAi1 and
+ * GaugeCurrentFluc, on the lattice): overwrite the electric field
+ * (LAT_SU2_HIGGS: E; LAT_ABELIAN_HIGGS: piA) with the longitudinal solution
+ *   E_i = grad+_i Lap^-1 (rho - <rho>),  Lap = sum_i grad-_i grad+_i,
+ * of the lattice Gauss law div- E = rho (eqs. GaussU1-eom and GaussSU2-eom at
+ * a = 1 with unit links), rho the charge density of the stored scalar and
+ * momenta: SU(2) rho^a = g Im(psi^dag T_a pi_psi) per colour, U(1)
+ * rho = e kappa_g (phi0 pi1 - phi1 pi0).  The SU(2) solve needs every link at
+ * the identity, the initial links of sec. 6.3 (LAT_ESTATE otherwise, nothing
+ * written); the Abelian law does not involve the links.  mean_charge (host,
+ * 3 doubles for SU(2), 1 for U(1); NULL skips) receives <rho^a>, the
+ * homogeneous charge that no periodic field can absorb: after the call the
+ * Gauss residual is -<rho^a> at every site (zero for charged fluctuations
+ * whose modes carry no charge, as the paper's constrained phases give).
+ * float64 hipFFT transforms; buffers and plans as lattice_spectrum's.
+ * Synchronizes the stream.  Errors: LAT_EINVAL for other models or a batch
+ * context, LAT_ESTATE, LAT_ENOMEM, LAT_EHIP. */
+lat_status lattice_gauss_init(lat_ctx *ctx, double *mean_charge);
+
 /* Lattice occupation number (eq. OccuppationNum, sec. 6.4 measurements)
  * of real scalar field `field` per radial bin (bins as lattice_spectrum):
  *   n[b] = (a^2 L^3 / (2 N^6)) fstar2 [ w_b S_phi(b) + a^{2(1-alpha)} S_x(b) / w_b ] / (4 pi b^2)

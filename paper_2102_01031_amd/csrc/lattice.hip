@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -31,6 +32,7 @@
 #include "stage_rows.hpp"
 #include "stage_u1.hpp"
 #include "stage_su2.hpp"
+#include "stage_gauss.hpp"
 #include "stage_adjoint.hpp"
 #include "stage_batch.hpp"
 #include "spectrum.hpp"
@@ -1224,6 +1226,73 @@ static lat_status forward_transform(lat_ctx *c, const void *src, double2 *out)
     }
     if (hipfftExecD2Z(c->fft_plan, c->fft_in, (hipfftDoubleComplex *)out) != HIPFFT_SUCCESS)
         return fail(c, LAT_EHIP, "hipfftExecD2Z failed");
+    return LAT_OK;
+}
+
+lat_status lattice_gauss_init(lat_ctx *c, double *mean_charge)
+{
+    if (!c) return fail(nullptr, LAT_EINVAL, "null context");
+    if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
+    if (!c->su2 && !c->u1) return fail(c, LAT_EINVAL, "the Gauss law belongs to the U(1) and SU(2) models");
+    lat_status st = ensure_fft(c, false);
+    if (st != LAT_OK) return st;
+    if ((st = ensure_fft(c, true)) != LAT_OK) return st;
+    const int N = c->N;
+    const size_t V = c->vol;
+    const dim3 grid(1024), blk(256);
+    int *flag = (int *)(c->ticket + 8);   // a word of the ticket block that no reduction uses
+    const int ncol = c->su2 ? 3 : 1;
+    double mean[3] = {0.0, 0.0, 0.0};
+    // device copies of the SU(2) pointer tables
+    struct Tables {
+        const double *dbl[4], *dpi[4], *lnk[12];
+    } tab{};
+    Tables *tab_dev = nullptr;
+    if (c->su2) {
+        for (int k = 0; k < 4; ++k) {
+            tab.dbl[k] = (const double *)c->dbl[k][c->cur_su2];
+            tab.dpi[k] = (const double *)c->dpi[k];
+        }
+        for (int k = 0; k < 12; ++k) tab.lnk[k] = (const double *)c->lnk[k][c->cur_su2];
+        tab_dev = (Tables *)c->spec_part;   // scratch: the spectrum partials are free between calls
+        HIPCHK(c, hipMemcpyAsync(tab_dev, &tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+    }
+    for (int a = 0; a < ncol; ++a) {
+        if (c->su2) {
+            hipLaunchKernelGGL(gauss_charge_su2, grid, blk, 0, c->stream, (const double *const *)((char *)tab_dev + offsetof(Tables, dbl)),
+                               (const double *const *)((char *)tab_dev + offsetof(Tables, dpi)), (const double *const *)((char *)tab_dev + offsetof(Tables, lnk)),
+                               c->p.e_charge, a, V, c->fft_in, flag);
+        } else {
+            hipLaunchKernelGGL(gauss_charge_u1, grid, blk, 0, c->stream, (const double *)c->phi[0][c->cur_phi[0]],
+                               (const double *)c->phi[1][c->cur_phi[1]], (const double *)c->pi[0][0],
+                               (const double *)c->pi[1][0], c->p.e_charge * c->p.kappa_g, V, c->fft_in);
+        }
+        HIPCHK(c, hipGetLastError());
+        if (hipfftExecD2Z(c->fft_plan, c->fft_in, (hipfftDoubleComplex *)c->fft_out) != HIPFFT_SUCCESS)
+            return fail(c, LAT_EHIP, "hipfftExecD2Z failed");
+        double2 zero{};
+        HIPCHK(c, hipMemcpyAsync(&zero, c->fft_out, sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        mean[a] = zero.x / (double)V;
+        if (c->su2 && a == 0) {
+            int bad = 0;
+            HIPCHK(c, hipMemcpy(&bad, flag, sizeof(int), hipMemcpyDeviceToHost));
+            if (bad) return fail(c, LAT_ESTATE, "the SU(2) Gauss solve needs the links at the identity");
+        }
+        hipLaunchKernelGGL(gauss_symbol, grid, blk, 0, c->stream, c->fft_out, N, c->p.dx);
+        HIPCHK(c, hipGetLastError());
+        if (hipfftExecZ2D(c->fft_inv, (hipfftDoubleComplex *)c->fft_out, c->fft_in) != HIPFFT_SUCCESS)
+            return fail(c, LAT_EHIP, "hipfftExecZ2D failed");
+        double *e[3];
+        for (int i = 0; i < 3; ++i) e[i] = c->su2 ? (double *)c->efl[3 * i + a] : (double *)c->piA[i];
+        hipLaunchKernelGGL(gauss_field, grid, blk, 0, c->stream, (const double *)c->fft_in, N,
+                           1.0 / ((double)V * c->p.dx), e[0], e[1], e[2]);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (mean_charge)
+        for (int a = 0; a < ncol; ++a) mean_charge[a] = mean[a];
     return LAT_OK;
 }
 

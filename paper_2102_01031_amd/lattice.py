@@ -109,6 +109,8 @@ def lib():
         L.lattice_spectrum.restype = C.c_int
         L.lattice_occupation.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, dp, C.POINTER(C.c_int64)]
         L.lattice_occupation.restype = C.c_int
+        L.lattice_gauss_init.argtypes = [vp, dp]
+        L.lattice_gauss_init.restype = C.c_int
         L.lattice_init_batch.argtypes = [C.POINTER(vp), C.POINTER(LatParams), C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(LatFields), C.c_int32, vp]
         L.lattice_init_batch.restype = C.c_int
@@ -245,6 +247,15 @@ class Lattice:
                                         c.ctypes.data_as(C.POINTER(C.c_int64))), self._ctx)
         kir = 2 * math.pi / (N * self.params.dx)
         return dict(n=n, count=c, k=kir * np.arange(nb))
+
+    def gauss_init(self):
+        """Set the gauge momenta (SU(2): E, U(1): piA) to the longitudinal solution
+        of the lattice Gauss law for the stored scalar and momenta, on the device;
+        returns the homogeneous charge <rho^a> per colour (one value for U(1))."""
+        import numpy as np
+        mean = np.zeros(3)
+        _check(lib().lattice_gauss_init(self._ctx, mean.ctypes.data_as(C.POINTER(C.c_double))), self._ctx)
+        return mean if self.params.potential == POTENTIALS["su2_higgs"] else mean[:1]
 
     def grad(self, nsteps: int, stride: int = 0, want_phi: bool = True, want_pi: bool = True,
              observable: str = "chi_fraction", field: int = 0, bin: int = 0) -> dict:
