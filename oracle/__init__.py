@@ -94,6 +94,8 @@ def lib():
         L.orc_su2_run_lf.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long]
         L.orc_su2_lf_sync.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock)]
         L.orc_gauss_solve.argtypes = [C.c_int, C.c_double, dp, pp]
+        L.orc_su2_run_vv.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long, C.c_int]
+        L.orc_u1_run_vv.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long, C.c_int]
         L.orc_su2_gauss_init.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
         L.orc_u1_gauss_init.argtypes = [C.POINTER(U1Params), pp, pp, pp, dp]
         _lib = L
@@ -382,6 +384,12 @@ class U1State:
         _chk(lib().orc_u1_gauss(C.byref(self._p), *self._args(), _dp(out)), "u1 gauss")
         return _u1_dict(out)
 
+    def run_vv(self, nsteps: int, order: int = 2):
+        """nsteps of the velocity-Verlet map of the given order (2 ... 10)."""
+        _chk(lib().orc_u1_run_vv(C.byref(self._p), *self._args(), C.byref(self.clock), int(nsteps), int(order)),
+             "u1 run vv")
+        return self
+
     def gauss_init(self):
         """pi_A from the lattice Gauss law; returns <rho>."""
         mean = np.zeros(1)
@@ -450,6 +458,12 @@ class SU2State:
         out = np.zeros(12)
         _chk(lib().orc_su2_gauss(C.byref(self._p), *self._args(), _dp(out)), "su2 gauss")
         return _su2_dict(out)
+
+    def run_vv(self, nsteps: int, order: int = 2):
+        """nsteps of the velocity-Verlet map of the given order (2 ... 10)."""
+        _chk(lib().orc_su2_run_vv(C.byref(self._p), *self._args(), C.byref(self.clock), int(nsteps), int(order)),
+             "su2 run vv")
+        return self
 
     def gauss_init(self):
         """E from the lattice Gauss law (links at the identity); returns <rho^a>."""

@@ -98,6 +98,10 @@ MUTANTS = [
      "E[i][n] = (re[n] - re[nbr(N, x, y, z, i, -1)]) / dx;", "test_oracle_gauss_init.py"),
     ("SU(2) initial charge without the 1/2 of T_a", "t += conj(psi[r]) * 0.5 * PAULI[a][r][q] * pp[q];",
      "t += conj(psi[r]) * PAULI[a][r][q] * pp[q];", "test_oracle_gauss_init.py"),
+    ("gauge VV middle weight sign", "double x1 = 1.0 / (2.0 - c), x0 = -c / (2.0 - c);",
+     "double x1 = 1.0 / (2.0 - c), x0 = c / (2.0 - c);", "test_oracle_gauge_vv.py"),
+    ("gauge VV triple-jump exponent", "double c = pow(2.0, 1.0 / (double)(order - 1));",
+     "double c = pow(2.0, 1.0 / (double)(order));", "test_oracle_gauge_vv.py"),
     ("SU(2) plaquette order", "mat2 P = m2_mul(m2_mul(su2_link(U, i, n), su2_link(U, j, at(N, ci[0], ci[1], ci[2]))),",
      "mat2 P = m2_mul(m2_mul(su2_link(U, j, at(N, ci[0], ci[1], ci[2])), su2_link(U, i, n)),", "test_oracle_su2.py"),
 ]
