@@ -89,9 +89,11 @@ enum lat_potential {
                               + sum_i |U_i psi(n+i) - psi(n)|^2/(2 dx^2) + V + |E|^2/2
                               + 2/(g^2 dx^4) sum_{i<j} (2 - Tr P_ij), psi = sqrt(2) Phi and
                               P_ij = U_i U_j(n+i) U_i(n+j)^dag U_j^dag (the toolkit plaquette);
-                              leapfrog kicks are minus its derivative, the link drift is
-                              U <- exp(-i dt g dx E^a T_a) U.  Provided with LAT_LF, a = 1
-                              and float64; (f_star/omega_star)^2 = 1 (kappa_g is not used). */
+                              kicks are minus its derivative, the link drift is
+                              U <- exp(-i dt g dx E^a T_a) U.  Provided with LF and the VV
+                              family (VV2 = kick(h/2) drift(h) kick(h/2), VV4..VV10 its triple
+                              jumps), a = 1 and float64; (f_star/omega_star)^2 = 1 (kappa_g is
+                              not used).  The U(1) model has the same integrators. */
 };
 
 enum lat_precision {
@@ -172,7 +174,7 @@ typedef struct lat_ctx lat_ctx;
  * validate p.  Allocates the library scratch, computes b0 from the Hubble
  * constraint when asked, and leaves the fields untouched.
  * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (LF with LAT_EXP_SELF; the U(1) and SU(2)
- * models with another integrator than LF, with expansion or in float32), LAT_ENODEV, LAT_ENOMEM,
+ * models with expansion or in float32), LAT_ENODEV, LAT_ENOMEM,
  * LAT_EHIP.  On error *ctx is set to NULL. */
 lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
 

@@ -51,6 +51,7 @@ lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir);
 lat_status u1_sync(lat_ctx *c);
 lat_status u1_energy(lat_ctx *c, lat_energies *out);
 lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir);
+lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir);
 lat_status su2_sync(lat_ctx *c);
 lat_status su2_energy(lat_ctx *c, lat_energies *out);
 size_t su2_partial_capacity(int N);
@@ -860,8 +861,8 @@ lat_status validate(const lat_params *p, const lat_fields *f)
             return fail(nullptr, LAT_EINVAL, "misaligned field pointer");
     }
     if (p->potential == LAT_ABELIAN_HIGGS) {
-        if (p->integrator != LAT_LF || p->expansion != LAT_EXP_NONE)
-            return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model is provided with LF and a = 1");
+        if (p->expansion != LAT_EXP_NONE)
+            return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model is provided at a = 1");
         if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model runs in float64");
         if (!(p->e_charge != 0.0) || !(p->kappa_g > 0.0)) return fail(nullptr, LAT_EINVAL, "bad U(1) couplings");
         for (int i = 0; i < 3; ++i) {
@@ -871,8 +872,8 @@ lat_status validate(const lat_params *p, const lat_fields *f)
         }
     }
     if (p->potential == LAT_SU2_HIGGS) {
-        if (p->integrator != LAT_LF || p->expansion != LAT_EXP_NONE)
-            return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model is provided with LF and a = 1");
+        if (p->expansion != LAT_EXP_NONE)
+            return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model is provided at a = 1");
         if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model runs in float64");
         if (!(p->e_charge != 0.0) || !std::isfinite(p->e_charge)) return fail(nullptr, LAT_EINVAL, "bad SU(2) coupling");
         if ((double)p->N * p->N * p->N * 8.0 >= 4294967296.0)
@@ -1090,7 +1091,7 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
             return fail(c, LAT_ESTATE, "leapfrog momenta are staggered in the other direction; sync first");
         s = c->su2 ? su2_step_lf(c, ns, dir) : c->u1 ? u1_step_lf(c, ns, dir) : step_lf(c, ns, dir);
     } else {
-        s = step_vv(c, ns, dir);
+        s = (c->u1 || c->su2) ? gauge_step_vv(c, ns, dir) : step_vv(c, ns, dir);
     }
     if (s != LAT_OK) return s;
     if ((s = settle(c)) != LAT_OK) return s;
@@ -1748,6 +1749,39 @@ lat_status su2_energy(lat_ctx *c, lat_energies *out)
     out->gauss_div_max = M[1];
     out->gauss_charge_max = M[2];
     out->step = c->step;
+    return LAT_OK;
+}
+
+// Velocity-Verlet family for the U(1) and SU(2) models (a = 1): the sub-steps
+// h_p = w_p h of the triple-jump schedule (vv_weights), one kick-and-drift
+// pass per sub-step whose kick merges the half kicks that meet at its point,
+// (h_{p-1} + h_p)/2, and a closing kick-only pass of h_{M-1}/2; momenta end
+// at integer time.
+lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    const std::vector<double> w = vv_weights(c->p.integrator);
+    const int64_t J = (int64_t)w.size(), M = J * ns;
+    double prev = 0.0;
+    for (int64_t p = 0; p < M; ++p) {
+        const double hp = w[(size_t)(p % J)] * h;
+        const double ck = 0.5 * (prev + hp);
+        lat_status s;
+        if (c->su2) {
+            s = su2_launch(c, kSU2Step, su2_args(c, ck, hp, true));
+            c->cur_su2 ^= 1;
+        } else {
+            s = u1_launch(c, kU1Step, u1_args(c, ck, hp, true));
+            for (int i = 0; i < 2; ++i) c->cur_phi[i] ^= 1;
+            for (int i = 0; i < 3; ++i) c->cur_A[i] ^= 1;
+        }
+        if (s != LAT_OK) return s;
+        prev = hp;
+    }
+    lat_status s = c->su2 ? su2_launch(c, kSU2Kick, su2_args(c, 0.5 * prev, 0.0, false))
+                          : u1_launch(c, kU1Kick, u1_args(c, 0.5 * prev, 0.0, false));
+    if (s != LAT_OK) return s;
+    c->t += (double)ns * h;
     return LAT_OK;
 }
 

@@ -126,6 +126,28 @@ def test_su2_parity_workload_state(N, steps):
     lat.close()
 
 
+@pytest.mark.parametrize("N,integ,order,steps", [(12, "vv2", 2, 6), (12, "vv4", 4, 4), (13, "vv6", 6, 2),
+                                                  (64, "vv4", 4, 1)])
+def test_su2_vv_parity(N, integ, order, steps):
+    """The velocity-Verlet family on the SU(2) system (merged half kicks on the
+    device, plain composition in the oracle)."""
+    wl = workloads.SU2_HIGGS_128
+    kw = su2_kwargs(wl, N)
+    kw["integrator"] = integ
+    fields = inputs.random_su2_state(N, 80 + order)
+    say(f"[su2] {integ} N={N} steps={steps}")
+    lat, gt = gpu_su2(kw, fields, [steps])
+    st = oracle_su2(kw, fields).run_vv(steps, order)
+    worst = compare_su2(gt, st, TOL, f"su2-{integ}-{N}")
+    compare_su2_energy(lat.energy(), st.energy(), TOL, f"su2-{integ}-{N}")
+    say(f"[su2]   state rel err {worst:.2e}")
+    lat.step(-steps)
+    for gl, ol in zip(gt, fields):
+        for g, o in zip(gl, ol):
+            assert np.max(np.abs(g.cpu().numpy() - np.asarray(o).reshape(-1))) < 1e-12
+    lat.close()
+
+
 def test_su2_parity_full_size():
     wl = workloads.SU2_HIGGS_128
     N, steps = wl.N, 2
@@ -191,7 +213,7 @@ def test_su2_rejects_unsupported():
     wl = workloads.SU2_HIGGS_128
     N = 8
     phi, pi, U, E = [to_dev(f, torch.float64) for f in wl.initial_fields(N=N)]
-    for over in (dict(integrator="vv2"), dict(expansion="fixed", H0=0.1)):
+    for over in (dict(integrator="vv4", expansion="self"), dict(expansion="fixed", H0=0.1)):
         kw = su2_kwargs(wl, N)
         kw.update(over)
         with pytest.raises(LatticeError, match="UNSUPPORTED"):

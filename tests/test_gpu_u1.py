@@ -138,6 +138,25 @@ def test_u1_gauss_long_run_on_gpu():
     lat.close()
 
 
+@pytest.mark.parametrize("N,integ,order,steps", [(12, "vv2", 2, 6), (16, "vv4", 4, 4), (13, "vv6", 6, 2),
+                                                  (64, "vv4", 4, 2)])
+def test_u1_vv_parity(N, integ, order, steps):
+    """The velocity-Verlet family on the U(1) system (the row kernel at N = 64)."""
+    wl = workloads.ABELIAN_HIGGS_128
+    kw = u1_kwargs(wl, N)
+    kw["integrator"] = integ
+    rng = np.random.default_rng(90 + order)
+    sh = (N, N, N)
+    fields = ([0.5 * rng.standard_normal(sh) for _ in range(2)], [0.3 * rng.standard_normal(sh) for _ in range(2)],
+              [0.8 * rng.standard_normal(sh) for _ in range(3)], [0.3 * rng.standard_normal(sh) for _ in range(3)])
+    say(f"[u1] {integ} N={N} steps={steps}")
+    lat, gt = gpu_u1(kw, fields, [steps])
+    st = oracle_u1(kw, fields).run_vv(steps, order)
+    compare_u1(gt, st, TOL, f"u1-{integ}-{N}")
+    compare_u1_energy(lat.energy(), st.energy(), TOL, f"u1-{integ}-{N}")
+    lat.close()
+
+
 def test_u1_sync_and_reverse():
     wl = workloads.ABELIAN_HIGGS_128
     N = 20
