@@ -203,7 +203,8 @@ lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
 
 /* Discrete power spectrum (sec. 3.1, eq. discretePS) of one stored array:
  * field in [0, number of fields) (U(1): the two components of the complex
- * scalar), which = 0 for phi, 1 for pi (as stored: a staggered leapfrog state
+ * scalar; SU(2): the four components of the doublet, whose norm spectrum is
+ * half the sum of the four), which = 0 for phi, 1 for pi (as stored: a staggered leapfrog state
  * gives pi at the half step).  Radial bins of unit width: bin b holds the modes
  * n (n_i in (-N/2, N/2]) with b <= |n| < b + 1; floor(sqrt(3) (N/2)) + 1 bins
  * hold every mode.  Outputs (host arrays of nbins): sum[b] = sum over the bin

@@ -1302,8 +1302,7 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
 {
     if (!c || !sum || !delta || !count) return fail(c, LAT_EINVAL, "null argument");
     if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
-    if (c->su2) return fail(c, LAT_EUNSUPPORTED, "spectra are provided for the scalar and U(1) models");
-    const int nfld = c->u1 ? 2 : c->nf;
+    const int nfld = c->su2 ? 4 : (c->u1 ? 2 : c->nf);
     if (field < 0 || field >= nfld || (which != 0 && which != 1))
         return fail(c, LAT_EINVAL, "field or array out of range");
     if (nbins < 1 || nbins > kSpecMaxBins) return fail(c, LAT_EINVAL, "nbins out of range");
@@ -1312,6 +1311,7 @@ lat_status lattice_spectrum(lat_ctx *c, int32_t field, int32_t which, int32_t nb
     lat_status st = ensure_fft(c, false);
     if (st != LAT_OK) return st;
     const void *src = which == 0 ? c->phi[field][c->cur_phi[field]] : c->pi[field][c->cur_pi[field]];
+    if (c->su2) src = which == 0 ? c->dbl[field][c->cur_su2] : c->dpi[field];
     st = forward_transform(c, src, c->fft_out);
     if (st != LAT_OK) return st;
     const int nb = (int)std::min<size_t>(kSpecBlocks, (H + kSpecThreads - 1) / kSpecThreads);

@@ -220,5 +220,32 @@ def test_su2_rejects_unsupported():
             Lattice(doublet=phi, pi_doublet=pi, U=U, E=E, **kw)
     lat = Lattice(doublet=phi, pi_doublet=pi, U=U, E=E, **su2_kwargs(wl, N))
     with pytest.raises(LatticeError, match="UNSUPPORTED"):
-        lat.spectrum(0)
+        lat.occupation(0)
+    with pytest.raises(LatticeError, match="EINVAL"):
+        lat.spectrum(4)
+    lat.close()
+
+
+@pytest.mark.parametrize("N", [16, 27])
+def test_su2_doublet_component_spectra(N):
+    """Power spectra of the doublet's components and momenta (eq. discretePS)
+    after a few steps, against the oracle's own-DFT spectrum of the same
+    arrays (its state after the same steps)."""
+    import math
+    wl = workloads.SU2_HIGGS_128
+    kw = su2_kwargs(wl, N)
+    fields = inputs.random_su2_state(N, 120 + N)
+    lat, gt = gpu_su2(kw, fields, [5, "sync"])
+    st = oracle_su2(kw, fields).run(5).sync()
+    for which, arrs in ((0, st.phi), (1, st.pi)):
+        for c in range(4):
+            sp = lat.spectrum(c, "phi" if which == 0 else "pi")
+            s, d, cnt = oracle.spectrum(arrs[c], wl.dx, nbins=len(sp["sum"]))
+            assert np.array_equal(sp["count"], cnt)
+            rel = np.max(np.abs(sp["sum"] - s)) / s.max()
+            assert rel <= 1e-12, (which, c, rel)
+            kir = 2 * math.pi / (N * wl.dx)
+            lhs = sum(kir / (b * kir) * sp["delta"][b] for b in range(1, len(sp["delta"])))
+            f = arrs[c]
+            assert abs(lhs - (np.mean(f * f) - np.mean(f) ** 2)) <= 1e-10 * np.mean(f * f)
     lat.close()
