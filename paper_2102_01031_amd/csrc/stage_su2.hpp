@@ -32,6 +32,12 @@ struct SU2Args {
     const double *U_in[12];   // link i, component k at 4 i + k
     double *U_out[12];
     double *E[9];             // link i, colour a at 3 i + a
+    // kSU2StepAoS: the doublet and the links as one 32-byte record per site
+    // (phi0..phi3; w, x, y, z), read from *_in4 and written to *_out4
+    const double4 *phi_in4;
+    double4 *phi_out4;
+    const double4 *U_in4[3];
+    double4 *U_out4[3];
     int N, tiles_x, tiles_y, zc;   // zc: z planes per block
     double dx, g, lam, v;
     double ck;   // kick weight
@@ -41,7 +47,17 @@ struct SU2Args {
     ScaleRecord *sc;
 };
 
-enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2 };
+enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2, kSU2StepAoS = 3 };
+
+// one 32-byte record through a 32-bit byte offset (valid while 32 N^3 < 2^32)
+__device__ __forceinline__ double4 ld4(const double4 *base, unsigned i)
+{
+    return *(const double4 *)((const char *)base + (size_t)(i * 32u));
+}
+__device__ __forceinline__ void st4(double4 *base, unsigned i, double4 v)
+{
+    *(double4 *)((char *)base + (size_t)(i * 32u)) = v;
+}
 constexpr int kSU2Sums = 8, kSU2Maxes = 3;
 
 // unit quaternion q = (w, v) for the matrix w I - i v.sigma
@@ -105,13 +121,27 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
         q[j] = u;
         return off(q[0], q[1], q[2]);
     };
+    constexpr bool AOS = MODE == kSU2StepAoS;
     auto L = [&](int i, unsigned m) {
-        return Q4{ld32(g.U_in[4 * i], m), ld32(g.U_in[4 * i + 1], m), ld32(g.U_in[4 * i + 2], m),
-                  ld32(g.U_in[4 * i + 3], m)};
+        if constexpr (AOS) {
+            const double4 v = ld4(g.U_in4[i], m);
+            return Q4{v.x, v.y, v.z, v.w};
+        } else {
+            return Q4{ld32(g.U_in[4 * i], m), ld32(g.U_in[4 * i + 1], m), ld32(g.U_in[4 * i + 2], m),
+                      ld32(g.U_in[4 * i + 3], m)};
+        }
+    };
+    // the doublet at site m as (phi0, phi1, phi2, phi3)
+    auto D = [&](unsigned m) {
+        if constexpr (AOS) {
+            return ld4(g.phi_in4, m);
+        } else {
+            return double4{ld32(g.phi_in[0], m), ld32(g.phi_in[1], m), ld32(g.phi_in[2], m), ld32(g.phi_in[3], m)};
+        }
     };
     const unsigned n = off(c[0], c[1], c[2]);
-    const double *const *P = g.phi_in;
-    const double a0 = ld32(P[0], n), b0 = ld32(P[1], n), c0 = ld32(P[2], n), d0 = ld32(P[3], n);
+    const double4 own = D(n);
+    const double a0 = own.x, b0 = own.y, c0 = own.z, d0 = own.w;
     const double inv_dx2 = 1.0 / (g.dx * g.dx);
     const double gdx = g.g / g.dx;
     const double mcoef = 2.0 / (g.g * g.dx * g.dx * g.dx);
@@ -126,9 +156,10 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
     for (int i = 0; i < 3; ++i) {
         const unsigned np = at1(i, cp[i]), nm = at1(i, cm[i]);
         double r0, s0, r1, s1;
-        qapply(Ul[i], ld32(P[0], np), ld32(P[1], np), ld32(P[2], np), ld32(P[3], np), r0, s0, r1, s1);
+        const double4 dp = D(np), dm = D(nm);
+        qapply(Ul[i], dp.x, dp.y, dp.z, dp.w, r0, s0, r1, s1);
         double t0, u0, t1, u1;
-        qapply(qdag(L(i, nm)), ld32(P[0], nm), ld32(P[1], nm), ld32(P[2], nm), ld32(P[3], nm), t0, u0, t1, u1);
+        qapply(qdag(L(i, nm)), dm.x, dm.y, dm.z, dm.w, t0, u0, t1, u1);
         l0 += r0 - 2.0 * a0 + t0;
         l1 += s0 - 2.0 * b0 + u0;
         l2 += r1 - 2.0 * c0 + t1;
@@ -241,11 +272,16 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
             en[k] = ev[k] + g.ck * FE[k];
             st32(g.E[k], n, en[k]);
         }
-        if (MODE == kSU2Step) {
-            st32(g.phi_out[0], n, a0 + g.hd * pn[0]);
-            st32(g.phi_out[1], n, b0 + g.hd * pn[1]);
-            st32(g.phi_out[2], n, c0 + g.hd * pn[2]);
-            st32(g.phi_out[3], n, d0 + g.hd * pn[3]);
+        if (MODE == kSU2Step || AOS) {
+            const double4 po{a0 + g.hd * pn[0], b0 + g.hd * pn[1], c0 + g.hd * pn[2], d0 + g.hd * pn[3]};
+            if constexpr (AOS) {
+                st4(g.phi_out4, n, po);
+            } else {
+                st32(g.phi_out[0], n, po.x);
+                st32(g.phi_out[1], n, po.y);
+                st32(g.phi_out[2], n, po.z);
+                st32(g.phi_out[3], n, po.w);
+            }
             const double hgdx = g.hd * g.g * g.dx;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -261,10 +297,14 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
                     R.z = sh * ez / len;
                 }
                 const Q4 Un = qmul(R, Ul[i]);
-                st32(g.U_out[4 * i], n, Un.w);
-                st32(g.U_out[4 * i + 1], n, Un.x);
-                st32(g.U_out[4 * i + 2], n, Un.y);
-                st32(g.U_out[4 * i + 3], n, Un.z);
+                if constexpr (AOS) {
+                    st4(g.U_out4[i], n, double4{Un.w, Un.x, Un.y, Un.z});
+                } else {
+                    st32(g.U_out[4 * i], n, Un.w);
+                    st32(g.U_out[4 * i + 1], n, Un.x);
+                    st32(g.U_out[4 * i + 2], n, Un.y);
+                    st32(g.U_out[4 * i + 3], n, Un.z);
+                }
             }
         }
     }
@@ -361,6 +401,43 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
                 }
                 __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+        }
+    }
+}
+
+}  // namespace lat
+
+namespace lat {
+
+// SoA <-> per-site records of the doublet and the links (kSU2StepAoS):
+// a[0..3] the doublet components, a[4 + 4 i + k] component k of link i;
+// r[0] the doublet records, r[1 + i] those of link i.
+struct SU2Soa {
+    double *a[16];
+};
+struct SU2Aos {
+    double4 *r[4];
+};
+
+__global__ void su2_to_aos(const SU2Soa s, const SU2Aos d, size_t V)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < V; n += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            d.r[q][n] = double4{s.a[4 * q][n], s.a[4 * q + 1][n], s.a[4 * q + 2][n], s.a[4 * q + 3][n]};
+    }
+}
+
+__global__ void su2_from_aos(const SU2Aos s, const SU2Soa d, size_t V)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < V; n += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double4 v = s.r[q][n];
+            d.a[4 * q][n] = v.x;
+            d.a[4 * q + 1][n] = v.y;
+            d.a[4 * q + 2][n] = v.z;
+            d.a[4 * q + 3][n] = v.w;
         }
     }
 }

@@ -69,16 +69,19 @@ def compare_su2_energy(eg, eo, tol, what):
             assert abs(g - o) <= tol * abs(o), f"{what} {k}: {g} vs {o}"
 
 
+@pytest.mark.parametrize("layout", ["records", "soa"])
 @pytest.mark.parametrize("N,steps,seed", [(5, 9, 1), (16, 25, 2), (24, 30, 3), (70, 3, 4)])
-def test_su2_parity_generic_state(N, steps, seed):
+def test_su2_parity_generic_state(N, steps, seed, layout):
     """A generic seeded state (random links, electric fields, doublet and
     momenta, no constraint): several 64 x 4 tiles, ragged tails in x (70) and
-    y (5, 70), and odd sizes."""
+    y (5, 70), and odd sizes; the step on per-site records of the doublet and
+    links (default for calls of 4 or more passes) and on the SoA arrays."""
     wl = workloads.SU2_HIGGS_128
     kw = su2_kwargs(wl, N)
     fields = inputs.random_su2_state(N, seed)
-    say(f"[su2] generic state N={N} steps={steps} seed={seed}")
-    lat, gt = gpu_su2(kw, fields, [steps])
+    say(f"[su2] generic state N={N} steps={steps} seed={seed} layout={layout}")
+    with tile_env("0" if layout == "soa" else None, "LATTICE_SU2_AOS"):
+        lat, gt = gpu_su2(kw, fields, [steps])
     eg = lat.energy()
     st = oracle_su2(kw, fields).run(steps)
     worst = compare_su2(gt, st, TOL, f"su2-{N}")
@@ -188,6 +191,24 @@ def test_su2_gauss_and_unitarity_long_run_on_gpu():
     assert unit <= 1e-13
     assert e["EK_B"] > 0 and e["EG_B"] > 0
     assert abs(1 - e["rho"] / rho0) < 1e-2
+    lat.close()
+
+
+def test_su2_layout_transitions():
+    """Calls below and above the per-site-record threshold in turn (SoA for 1
+    and 2 passes, records for 5 and 7), leapfrog and VV4, against the oracle."""
+    wl = workloads.SU2_HIGGS_128
+    N = 18
+    fields = inputs.random_su2_state(N, 140)
+    kw = su2_kwargs(wl, N)
+    lat, gt = gpu_su2(kw, fields, [1, 5, 2, 7, 1])
+    st = oracle_su2(kw, fields).run(16)
+    compare_su2(gt, st, TOL, "su2-layouts-lf")
+    lat.close()
+    kw["integrator"] = "vv4"
+    lat, gt = gpu_su2(kw, fields, [1, 2, 1])          # 3, 6, 3 passes
+    st = oracle_su2(kw, fields).run_vv(4, 4)
+    compare_su2(gt, st, TOL, "su2-layouts-vv4")
     lat.close()
 
 
