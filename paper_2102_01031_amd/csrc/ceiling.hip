@@ -4,6 +4,7 @@
 // compared with besides the HBM peak.  Each line printed is JSON:
 //   copy          one array in, one out, 16 bytes per lane (1 GiB each)
 //   streams4_256  4 float64 arrays in, 4 out, 256^3 each (the two-field stage)
+//   streams4_256_16B  the same with 16 bytes per lane and access
 //   streams10_128 10 float64 arrays in, 10 out, 128^3 each (the U(1) pass;
 //                 the 336 MB working set is largely cache-resident)
 //   read4_256     4 float64 arrays of 256^3 read and summed (the energy pass)
@@ -49,6 +50,18 @@ __global__ void __launch_bounds__(256) streams(const Ptrs<K> p, size_t n)
     }
 }
 
+// the same with 16 bytes per lane and access (two float64 per load and store)
+template <int K>
+__global__ void __launch_bounds__(256) streams16(const Ptrs<K> p, size_t n2)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) {
+        d2 x[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) x[a] = ((const d2 *)p.in[a])[i];
+#pragma unroll
+        for (int a = 0; a < K; ++a) __builtin_nontemporal_store(x[a] + 1.0, &((d2 *)p.out[a])[i]);
+    }
+}
 __global__ void __launch_bounds__(256) read4(const Ptrs<4> p, size_t n, double *partial)
 {
     double s = 0.0;
@@ -120,6 +133,8 @@ int main()
         }
         const float ms = mean_ms([&] { hipLaunchKernelGGL(streams<4>, dim3(65536), dim3(256), 0, 0, p, n); });
         line("streams4_256", 8.0 * 8 * n, ms);
+        const float m16 = mean_ms([&] { hipLaunchKernelGGL(streams16<4>, dim3(32768), dim3(256), 0, 0, p, n / 2); });
+        line("streams4_256_16B", 8.0 * 8 * n, m16);
         void *part;
         CK(alloc(4096 * 8, &part));
         const float mr = mean_ms([&] { hipLaunchKernelGGL(read4, dim3(4096), dim3(256), 0, 0, p, n, (double *)part); });

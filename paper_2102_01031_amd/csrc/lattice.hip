@@ -135,6 +135,8 @@ struct lat_ctx {
     bool rows = false;   // whole-row kernel (N = 64 * XS)
     int rows_ty = 8;
     int rows_pf = 1;     // whole-row kernel prefetch depth (planes)
+    int rows_vw = 1;     // whole-row kernel sites per lane and access (1, or 16-byte vectors)
+    int rows_y_fastest = 0;   // whole-row kernel block order (see stage_rows.hpp)
     int zc = 0;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
     // launch statistics and optional event timing
@@ -292,11 +294,25 @@ void set_rows_geometry(lat_ctx *c, int ty, int zc)
 
 void geometry_from_env(lat_ctx *c)
 {
-    // prefetch depth of the whole-row kernel: two planes for float64 at N = 256
-    // (measured 3% faster there; float32 is not faster with it), else one;
-    // LATTICE_ROWS_PF=1|2 overrides
-    c->rows_pf = (!c->f32 && c->N == 256) ? 2 : 1;
+    // prefetch depth of the whole-row kernel: two planes at N = 256 (float64:
+    // measured 3% faster there; float32 with 4-row blocks and 16-byte accesses:
+    // 1% faster), else one; LATTICE_ROWS_PF=1|2 overrides (two planes are
+    // instantiated for 4-row blocks, and for float32 8-row blocks, at N = 256)
+    c->rows_pf = c->N == 256 ? 2 : 1;
     if (const char *pf = std::getenv("LATTICE_ROWS_PF")) c->rows_pf = std::atoi(pf) == 2 ? 2 : 1;
+    // 16-byte row accesses (four sites per lane) for float32 at N = 256, where
+    // they measured 1.2% faster; float64 keeps one site per lane and access
+    // (16-byte accesses measured 4% slower at 256^3, as did a 16-byte 4-in-4-out
+    // streaming probe against the 8-byte one).  LATTICE_ROWS_VW=1|2|4 overrides
+    // where the row holds a whole number of 16-byte vectors per lane.
+    const int vmax = c->f32 ? 4 : 2;
+    const bool vok = (c->N / 64) % vmax == 0;
+    c->rows_vw = (c->f32 && vok) ? vmax : 1;
+    if (const char *vw = std::getenv("LATTICE_ROWS_VW")) c->rows_vw = (std::atoi(vw) > 1 && vok) ? vmax : 1;
+    // block order at N = 256: y tile fastest (each XCD's blocks form a z slab),
+    // measured about 1% faster than y slabs in both precisions; LATTICE_ROWS_YFAST=0|1
+    c->rows_y_fastest = c->N == 256 ? 1 : 0;
+    if (const char *yo = std::getenv("LATTICE_ROWS_YFAST")) c->rows_y_fastest = std::atoi(yo) != 0;
     const char *s = std::getenv("LATTICE_TILE");
     if (s && std::strncmp(s, "rows", 4) == 0 && rows_ok(c->N)) {
         int ty = 8, z = 0;
@@ -317,9 +333,11 @@ void geometry_from_env(lat_ctx *c)
         }
     }
     if (rows_ok(c->N)) {
-        // measured on the 256^3 two-field pass: 4-row blocks for float64 (252
-        // registers, one block per CU), 8-row blocks for float32
-        set_rows_geometry(c, c->f32 ? 8 : 4, 0);
+        // measured on the 256^3 two-field pass: 4-row blocks with loads two
+        // planes ahead in both precisions (float32 with 16-byte accesses: 1%
+        // faster than 8-row blocks with one plane ahead); 8-row blocks for
+        // float32 at N = 64, 128
+        set_rows_geometry(c, (c->f32 && c->N != 256) ? 8 : 4, 0);
         return;
     }
     set_geometry(c, tile, zc);
@@ -357,28 +375,28 @@ hipError_t launch_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream
     return hipGetLastError();
 }
 
-template <typename T, int NF, int XS, int TY, int PF = 1>
+template <typename T, int NF, int XS, int TY, int PF = 1, int VW = 1>
 hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
 {
     const dim3 grid(nb), block(64 * TY);
     switch (variant) {
     case kKickOnly:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true, PF>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true, PF, VW>), grid, block, 0, s, a);
         break;
     case kKickOnlyRed:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true, PF>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true, PF, VW>), grid, block, 0, s, a);
         break;
     case kDriftKick:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true, PF>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true, PF, VW>), grid, block, 0, s, a);
         break;
     case kDriftKickRed:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true, PF>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true, PF, VW>), grid, block, 0, s, a);
         break;
     case kKickDrift:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true, PF>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true, PF, VW>), grid, block, 0, s, a);
         break;
     case kEnergy:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false, PF>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false, PF, VW>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -387,11 +405,28 @@ hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipS
 }
 
 // pf: prefetch depth in planes (2 is instantiated for N = 256 with 4-row
-// blocks only; 8-row float64 blocks would spill at that depth)
+// blocks only; 8-row float64 blocks would spill at that depth).
+// vw > 1: 16-byte accesses (two float64 or four float32 sites per lane and
+// access), instantiated where the row holds a whole number of them per lane:
+// N = 128, 256 in float64, N = 256 in float32.
 template <typename T, int NF>
-hipError_t launch_rows(int N, int ty, int pf, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
 {
     const int xs = N / 64;
+    constexpr int V = 16 / (int)sizeof(T);
+    if (vw > 1 && xs % V == 0) {
+        if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2, V>(variant, a, nb, s);
+        if constexpr (V == 4) {
+            if (pf == 2 && xs == 4 && ty == 8) return launch_rows_variant<T, NF, 4, 8, 2, V>(variant, a, nb, s);
+        }
+        if (xs == 4) return ty == 4 ? launch_rows_variant<T, NF, 4, 4, 1, V>(variant, a, nb, s)
+                                    : launch_rows_variant<T, NF, 4, 8, 1, V>(variant, a, nb, s);
+        if constexpr (V == 2) {
+            if (xs == 2) return ty == 4 ? launch_rows_variant<T, NF, 2, 4, 1, V>(variant, a, nb, s)
+                                        : launch_rows_variant<T, NF, 2, 8, 1, V>(variant, a, nb, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2>(variant, a, nb, s);
     if (ty == 4) {
         if (xs == 1) return launch_rows_variant<T, NF, 1, 4>(variant, a, nb, s);
@@ -494,6 +529,7 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     a.zc = c->zc;
     a.tiles_x = c->tiles_x;
     a.tiles_y = c->tiles_y;
+    a.y_fastest = c->rows_y_fastest;
     a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
     a.lam = c->p.lambda;
     a.q = c->p.potential == LAT_PHI4_CHI2 ? c->p.q : 0.0;
@@ -513,8 +549,8 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     }
     hipError_t e;
     if (c->rows)
-        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, c->rows_pf, variant, a, c->nblocks, stream)
-                       : launch_rows<T, 2>(c->N, c->rows_ty, c->rows_pf, variant, a, c->nblocks, stream);
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream)
+                       : launch_rows<T, 2>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream);
     else
         e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
                        : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);

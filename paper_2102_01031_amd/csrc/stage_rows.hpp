@@ -1,14 +1,16 @@
 // stage_rows.hpp -- the stencil pass of stage_scalar.hpp for N = 64 * XS with
 // XS in {1, 2, 4}: a block owns whole x rows, so there is no x halo.
 //
-// Block = TY wavefronts; wavefront w owns row y0 + w and its lanes hold the XS
-// sites x = lane + 64 k (k < XS), so every global load or store of a row is one
-// contiguous 512-byte segment per k.  The drifted phi of the current plane for
-// rows y0-1 .. y0+TY sits in LDS (the two halo rows are loaded one cell per
-// thread); z neighbours come from a register window as in the tiled kernel.
-// Block order: y tiles of one XCD are contiguous and each XCD walks every z
-// chunk of its y slab, so halo rows between tiles and z-chunk boundaries are
-// shared inside one L2.
+// Block = TY wavefronts; wavefront w owns row y0 + w and its lanes hold XS
+// sites each, VW consecutive ones per access: x = VW lane + v + 64 VW j
+// (v < VW, j < XS / VW), so every global load or store of a row is one
+// contiguous 64 VW sizeof(T)-byte segment per j (VW = 16 / sizeof(T) gives
+// 16-byte accesses).  The drifted phi of the current plane for rows
+// y0-1 .. y0+TY sits in LDS (the two halo rows are loaded one VW-site vector
+// per thread); z neighbours come from a register window as in the tiled kernel.
+// Block order: the blocks of one XCD form either a y slab through every z
+// chunk or a slab of whole planes (y tile fastest), so halo rows between
+// tiles are shared inside one L2 except at the slab's faces.
 // PF is the prefetch depth in planes: the loads issued while plane z is
 // computed are for own plane z + 2 + PF and halo plane z + 1 + PF, landing in
 // one of PF + 1 register sets that rotate with the (PF + 1)-fold unrolled z
@@ -19,28 +21,76 @@
 
 namespace lat {
 
-template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI, int PF = 1>
+// A lane's VW consecutive sites of a row as one vector (VW = 1: the scalar).
+template <typename T, int V>
+struct RowVec {
+    typedef T type __attribute__((ext_vector_type(V)));
+};
+template <typename T>
+struct RowVec<T, 1> {
+    typedef T type;
+};
+
+template <typename T, typename VT>
+__device__ __forceinline__ T vget(const VT &x, int v)
+{
+    if constexpr (sizeof(VT) == sizeof(T)) return x;
+    else return x[v];
+}
+
+template <typename T, typename VT>
+__device__ __forceinline__ void vset(VT &x, int v, T val)
+{
+    if constexpr (sizeof(VT) == sizeof(T)) x = val;
+    else x[v] = val;
+}
+
+// vector load / non-temporal store at element index i (32-bit byte offset, as ld32)
+template <typename VT, typename T>
+__device__ __forceinline__ VT ldv(const T *base, unsigned i)
+{
+    return *(const VT *)((const char *)base + (size_t)(i * (unsigned)sizeof(T)));
+}
+
+template <typename VT, typename T>
+__device__ __forceinline__ void stv_nt(T *base, unsigned i, VT v)
+{
+    __builtin_nontemporal_store(v, (VT *)((char *)base + (size_t)(i * (unsigned)sizeof(T))));
+}
+
+// VW: sites per lane and access (1, or 16 / sizeof(T) for 16-byte loads and
+// stores); lane l holds x = VW l + v + 64 VW j (v < VW, j < XS / VW), so the x
+// neighbours inside a lane's group come from registers and only the two at
+// the group's ends from the LDS row.
+template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI, int PF = 1,
+          int VW = 1>
 __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 {
     static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
+    static_assert(XS % VW == 0 && VW * sizeof(T) <= 16, "vector width");
+    using VT = typename RowVec<T, VW>::type;
     constexpr int NT = 64 * TY;
     constexpr int NX = 64 * XS;           // == N
+    constexpr int XV = XS / VW;           // vectors per lane and row
     constexpr int NQ = 3 * NF;
-    constexpr int NH = 2 * NX;            // halo cells per plane (rows y0-1 and y0+TY)
-    constexpr int HPT = (NH + NT - 1) / NT;
+    constexpr int NHV = 2 * NX / VW;      // halo vectors per plane (rows y0-1 and y0+TY)
+    constexpr int HPT = (NHV + NT - 1) / NT;
 
-    __shared__ T lds[2][NF][(TY + 2) * NX];
+    __shared__ __attribute__((aligned(16))) T lds[2][NF][(TY + 2) * NX];
     __shared__ double lds_red[(NT / 64) * NQ];
     __shared__ int last_flag;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int N = NX;
-    // logical block: z chunk fastest, then y tile
+    // logical block: z chunk fastest, then y tile (each XCD's range of logical
+    // blocks is a y slab through all z), or y tile fastest (an XCD's range is
+    // a z slab of whole planes, or part of one)
     const int lid = xcd_logical_block(blockIdx.x, gridDim.x);
     const int chunks = (N + g.zc - 1) / g.zc;
-    const int bz = lid % chunks;
-    const int by = lid / chunks;
+    constexpr int tiles = (NX + TY - 1) / TY;
+    const int bz = g.y_fastest ? lid / tiles : lid % chunks;
+    const int by = g.y_fastest ? lid % tiles : lid / chunks;
     const int y0 = by * TY;
     const int z0 = bz * g.zc;
     const int z1 = min(z0 + g.zc, N);
@@ -56,9 +106,9 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
         const int c = tid + j * NT;
-        hval[j] = c < NH;
-        const int r = c < NX ? 0 : 1;
-        const int x = c - r * NX;
+        hval[j] = c < NHV;
+        const int r = c < NX / VW ? 0 : 1;
+        const int x = (c - r * (NX / VW)) * VW;
         int hy = r == 0 ? y0 - 1 : y0 + TY;
         hy = ((hy % N) + N) % N;
         hslot[j] = (r == 0 ? 0 : (TY + 1) * NX) + x;
@@ -70,10 +120,11 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const T ka1 = (T)C.ka1, ka3 = (T)C.ka3, idx2 = (T)g.inv_dx2;
     const T lam = (T)g.lam, qc = (T)g.q;
     const double lamd = g.lam, qd = g.q;
+    const VT vzero = (VT)T(0);
 
     T fm[XS][NF], f0[XS][NF], fp[XS][NF], p0[XS][NF], pp[XS][NF];
-    T oAf[XS][NF], oAp[XS][NF], oBf[XS][NF], oBp[XS][NF], oCf[XS][NF], oCp[XS][NF];
-    T hAf[HPT][NF], hAp[HPT][NF], hBf[HPT][NF], hBp[HPT][NF], hCf[HPT][NF], hCp[HPT][NF];
+    VT oAf[XV][NF], oAp[XV][NF], oBf[XV][NF], oBp[XV][NF], oCf[XV][NF], oCp[XV][NF];
+    VT hAf[HPT][NF], hAp[HPT][NF], hBf[HPT][NF], hBp[HPT][NF], hCf[HPT][NF], hCp[HPT][NF];
 
     {
         const unsigned om = (unsigned)(z0 == 0 ? N - 1 : z0 - 1) * NN;
@@ -86,46 +137,56 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             const T *P = g.phi_in[f];
             const T *Q = g.pi_in[f];
 #pragma unroll
-            for (int k = 0; k < XS; ++k) {
-                const int o = yo + lane + 64 * k;
-                const T a = ld32(P, om + o);
-                fm[k][f] = DLOAD ? a + dl * ld32(Q, om + o) : a;
-                const T b = ld32(P, o0 + o);
-                p0[k][f] = ld32(Q, o0 + o);
-                f0[k][f] = DLOAD ? b + dl * p0[k][f] : b;
-                const T c = ld32(P, o1 + o);
-                pp[k][f] = ld32(Q, o1 + o);
-                fp[k][f] = DLOAD ? c + dl * pp[k][f] : c;
-                oAf[k][f] = ld32(P, o2 + o);
-                oAp[k][f] = ld32(Q, o2 + o);
-                lds[0][f][orow + lane + 64 * k] = f0[k][f];
+            for (int j = 0; j < XV; ++j) {
+                const int x0 = VW * lane + 64 * VW * j;
+                const int o = yo + x0;
+                VT a = ldv<VT>(P, om + o);
+                if (DLOAD) a += dl * ldv<VT>(Q, om + o);
+                VT b = ldv<VT>(P, o0 + o);
+                const VT pb = ldv<VT>(Q, o0 + o);
+                if (DLOAD) b += dl * pb;
+                VT c = ldv<VT>(P, o1 + o);
+                const VT pc = ldv<VT>(Q, o1 + o);
+                if (DLOAD) c += dl * pc;
+                oAf[j][f] = ldv<VT>(P, o2 + o);
+                oAp[j][f] = ldv<VT>(Q, o2 + o);
+                *(VT *)&lds[0][f][orow + x0] = b;
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const int k = j * VW + v;
+                    fm[k][f] = vget<T>(a, v);
+                    f0[k][f] = vget<T>(b, v);
+                    p0[k][f] = vget<T>(pb, v);
+                    fp[k][f] = vget<T>(c, v);
+                    pp[k][f] = vget<T>(pc, v);
+                }
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
-                hAf[j][f] = hAp[j][f] = T(0);
+                hAf[j][f] = hAp[j][f] = vzero;
                 if (hval[j]) {
-                    T h = ld32(P, o0 + hoff[j]);
-                    if (DLOAD) h += dl * ld32(Q, o0 + hoff[j]);
-                    lds[0][f][hslot[j]] = h;
-                    hAf[j][f] = ld32(P, oh1 + hoff[j]);
-                    if (DLOAD) hAp[j][f] = ld32(Q, oh1 + hoff[j]);
+                    VT h = ldv<VT>(P, o0 + hoff[j]);
+                    if (DLOAD) h += dl * ldv<VT>(Q, o0 + hoff[j]);
+                    *(VT *)&lds[0][f][hslot[j]] = h;
+                    hAf[j][f] = ldv<VT>(P, oh1 + hoff[j]);
+                    if (DLOAD) hAp[j][f] = ldv<VT>(Q, oh1 + hoff[j]);
                 }
             }
             if constexpr (PF == 2) {
                 const unsigned o3 = (unsigned)(min(z0 + 3, z1) % N) * NN;
                 const unsigned oh2 = (unsigned)(min(z0 + 2, z1 - 1) % N) * NN;
 #pragma unroll
-                for (int k = 0; k < XS; ++k) {
-                    const int o = yo + lane + 64 * k;
-                    oBf[k][f] = ld32(P, o3 + o);
-                    oBp[k][f] = ld32(Q, o3 + o);
+                for (int j = 0; j < XV; ++j) {
+                    const int o = yo + VW * lane + 64 * VW * j;
+                    oBf[j][f] = ldv<VT>(P, o3 + o);
+                    oBp[j][f] = ldv<VT>(Q, o3 + o);
                 }
 #pragma unroll
                 for (int j = 0; j < HPT; ++j) {
-                    hBf[j][f] = hBp[j][f] = T(0);
+                    hBf[j][f] = hBp[j][f] = vzero;
                     if (hval[j]) {
-                        hBf[j][f] = ld32(P, oh2 + hoff[j]);
-                        if (DLOAD) hBp[j][f] = ld32(Q, oh2 + hoff[j]);
+                        hBf[j][f] = ldv<VT>(P, oh2 + hoff[j]);
+                        if (DLOAD) hBp[j][f] = ldv<VT>(Q, oh2 + hoff[j]);
                     }
                 }
             }
@@ -137,28 +198,28 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
     for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
 
-    auto plane = [&](const int z, T (&oif)[XS][NF], T (&oip)[XS][NF], T (&hif)[HPT][NF], T (&hip)[HPT][NF],
-                     T (&oof)[XS][NF], T (&oop)[XS][NF], T (&hof)[HPT][NF], T (&hop)[HPT][NF]) {
+    auto plane = [&](const int z, VT (&oif)[XV][NF], VT (&oip)[XV][NF], VT (&hif)[HPT][NF], VT (&hip)[HPT][NF],
+                     VT (&oof)[XV][NF], VT (&oop)[XV][NF], VT (&hof)[HPT][NF], VT (&hop)[HPT][NF]) {
         const int cur = (z - z0) & 1, nxt = cur ^ 1;
         int zo = min(z + 2 + PF, z1);
         if (zo >= N) zo -= N;
         int zh = min(z + 1 + PF, z1 - 1);
         if (zh >= N) zh -= N;
         const unsigned o3 = (unsigned)zo * NN, o2 = (unsigned)zh * NN;
-        // (A) loads one plane ahead
+        // (A) loads PF planes ahead
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
-            for (int k = 0; k < XS; ++k) {
-                const int o = yo + lane + 64 * k;
-                oof[k][f] = ld32(g.phi_in[f], o3 + o);
-                oop[k][f] = ld32(g.pi_in[f], o3 + o);
+            for (int j = 0; j < XV; ++j) {
+                const int o = yo + VW * lane + 64 * VW * j;
+                oof[j][f] = ldv<VT>(g.phi_in[f], o3 + o);
+                oop[j][f] = ldv<VT>(g.pi_in[f], o3 + o);
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 if (hval[j]) {
-                    hof[j][f] = ld32(g.phi_in[f], o2 + hoff[j]);
-                    if (DLOAD) hop[j][f] = ld32(g.pi_in[f], o2 + hoff[j]);
+                    hof[j][f] = ldv<VT>(g.phi_in[f], o2 + hoff[j]);
+                    if (DLOAD) hop[j][f] = ldv<VT>(g.pi_in[f], o2 + hoff[j]);
                 }
             }
         }
@@ -167,79 +228,107 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
 #pragma unroll
-                for (int k = 0; k < XS; ++k) lds[nxt][f][orow + lane + 64 * k] = fp[k][f];
+                for (int j = 0; j < XV; ++j) {
+                    VT u;
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) vset<T>(u, v, fp[j * VW + v][f]);
+                    *(VT *)&lds[nxt][f][orow + VW * lane + 64 * VW * j] = u;
+                }
 #pragma unroll
                 for (int j = 0; j < HPT; ++j)
-                    if (hval[j]) lds[nxt][f][hslot[j]] = DLOAD ? hif[j][f] + dl * hip[j][f] : hif[j][f];
+                    if (hval[j]) *(VT *)&lds[nxt][f][hslot[j]] = DLOAD ? hif[j][f] + dl * hip[j][f] : hif[j][f];
             }
         }
         // (C) the XS sites of this lane at plane z
         const unsigned oz = (unsigned)z * NN + yo;
 #pragma unroll
-        for (int k = 0; k < XS; ++k) {
-            const int x = lane + 64 * k;
-            const int xl = x == 0 ? NX - 1 : x - 1;
-            const int xr = x == NX - 1 ? 0 : x + 1;
-            T xp[NF], yp[NF], lap[NF];
+        for (int j = 0; j < XV; ++j) {
+            const int x0 = VW * lane + 64 * VW * j;
+            const int xl = x0 == 0 ? NX - 1 : x0 - 1;
+            const int xr = x0 + VW == NX ? 0 : x0 + VW;
+            VT ymv[NF], ypv[NF], fov[NF], pnv[NF];
+            T xlv[NF], xrv[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const T *L = lds[cur][f];
-                const T c0 = f0[k][f];
-                const T xm = L[orow + xl];
-                xp[f] = L[orow + xr];
-                const T ym = L[orow - NX + x];
-                yp[f] = L[orow + NX + x];
-                lap[f] = ((xp[f] - T(2) * c0 + xm) + (yp[f] - T(2) * c0 + ym) +
-                          (fp[k][f] - T(2) * c0 + fm[k][f])) * idx2;
-            }
-            T dV[NF];
-            if constexpr (NF == 1) {
-                const T u = f0[k][0];
-                dV[0] = lam * u * u * u;
-            } else {
-                const T u = f0[k][0], v = f0[k][1];
-                dV[0] = lam * u * u * u + qc * u * v * v;
-                dV[1] = qc * u * u * v;
+                ymv[f] = *(const VT *)&L[orow - NX + x0];
+                ypv[f] = *(const VT *)&L[orow + NX + x0];
+                xlv[f] = L[orow + xl];
+                xrv[f] = L[orow + xr];
             }
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const T F = ka1 * lap[f] - ka3 * dV[f];
-                const T pm = p0[k][f] + c1 * F;
-                if (RED && valid) {
-                    const double pmd = (double)pm;
-                    acc[f] += pmd * pmd;
-                    const double gx = (double)(xp[f] - f0[k][f]);
-                    const double gy = (double)(yp[f] - f0[k][f]);
-                    const double gz = (double)(fp[k][f] - f0[k][f]);
-                    acc[NF + f] += gx * gx + gy * gy + gz * gz;
+            for (int v = 0; v < VW; ++v) {
+                const int k = j * VW + v;
+                const int km = v == 0 ? k : k - 1, kp = v == VW - 1 ? k : k + 1;
+                T xp[NF], yp[NF], lap[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const T c0 = f0[k][f];
+                    const T xm = v == 0 ? xlv[f] : f0[km][f];
+                    xp[f] = v == VW - 1 ? xrv[f] : f0[kp][f];
+                    const T ym = vget<T>(ymv[f], v);
+                    yp[f] = vget<T>(ypv[f], v);
+                    lap[f] = ((xp[f] - T(2) * c0 + xm) + (yp[f] - T(2) * c0 + ym) +
+                              (fp[k][f] - T(2) * c0 + fm[k][f])) * idx2;
                 }
-                const T pn = pm + c2 * F;
-                const T fo = DEND ? f0[k][f] + de * pn : f0[k][f];
-                if (valid) {
-                    if (WPHI) st32_nt(g.phi_out[f], oz + x, fo);
-                    if (WPI) st32_nt(g.pi_out[f], oz + x, pn);
+                T dV[NF];
+                if constexpr (NF == 1) {
+                    const T u = f0[k][0];
+                    dV[0] = lam * u * u * u;
+                } else {
+                    const T u = f0[k][0], v2 = f0[k][1];
+                    dV[0] = lam * u * u * u + qc * u * v2 * v2;
+                    dV[1] = qc * u * u * v2;
+                }
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const T F = ka1 * lap[f] - ka3 * dV[f];
+                    const T pm = p0[k][f] + c1 * F;
+                    if (RED && valid) {
+                        const double pmd = (double)pm;
+                        acc[f] += pmd * pmd;
+                        const double gx = (double)(xp[f] - f0[k][f]);
+                        const double gy = (double)(yp[f] - f0[k][f]);
+                        const double gz = (double)(fp[k][f] - f0[k][f]);
+                        acc[NF + f] += gx * gx + gy * gy + gz * gz;
+                    }
+                    const T pn = pm + c2 * F;
+                    vset<T>(fov[f], v, DEND ? f0[k][f] + de * pn : f0[k][f]);
+                    vset<T>(pnv[f], v, pn);
+                }
+                if (RED && valid) {
+                    const double u = (double)f0[k][0];
+                    acc[2 * NF] += 0.25 * lamd * u * u * u * u;
+                    if constexpr (NF == 2) {
+                        const double v2 = (double)f0[k][1];
+                        acc[2 * NF + 1] += 0.5 * qd * u * u * v2 * v2;
+                    }
                 }
             }
-            if (RED && valid) {
-                const double u = (double)f0[k][0];
-                acc[2 * NF] += 0.25 * lamd * u * u * u * u;
-                if constexpr (NF == 2) {
-                    const double v = (double)f0[k][1];
-                    acc[2 * NF + 1] += 0.5 * qd * u * u * v * v;
+            if (valid) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    if (WPHI) stv_nt<VT>(g.phi_out[f], oz + x0, fov[f]);
+                    if (WPI) stv_nt<VT>(g.pi_out[f], oz + x0, pnv[f]);
                 }
             }
         }
         __syncthreads();
         // (E) rotate the computed window
 #pragma unroll
-        for (int k = 0; k < XS; ++k) {
+        for (int j = 0; j < XV; ++j) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                fm[k][f] = f0[k][f];
-                f0[k][f] = fp[k][f];
-                p0[k][f] = pp[k][f];
-                fp[k][f] = DLOAD ? oif[k][f] + dl * oip[k][f] : oif[k][f];
-                pp[k][f] = oip[k][f];
+            for (int v = 0; v < VW; ++v) {
+                const int k = j * VW + v;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    fm[k][f] = f0[k][f];
+                    f0[k][f] = fp[k][f];
+                    p0[k][f] = pp[k][f];
+                    const T a = vget<T>(oif[j][f], v);
+                    fp[k][f] = DLOAD ? a + dl * vget<T>(oip[j][f], v) : a;
+                    pp[k][f] = vget<T>(oip[j][f], v);
+                }
             }
         }
     };

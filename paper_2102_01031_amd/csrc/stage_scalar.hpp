@@ -35,6 +35,7 @@ struct ScalarArgs {
     T *phi_out[2];
     T *pi_out[2];
     int N, zc, tiles_x, tiles_y;
+    int y_fastest;          // whole-row kernel block order: 0 z chunk fastest, 1 y tile fastest
     double inv_dx2;
     double lam, q;
     const PassCoef *coef;   // this pass

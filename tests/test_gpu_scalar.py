@@ -111,6 +111,77 @@ def test_preheat_256_two_plane_prefetch_ragged(tile):
     check_run(scalar_kwargs(wl), phi, pi, 1, tile=tile, what=f"preheat-256-{tile}")
 
 
+@pytest.mark.parametrize("N,vw,tile,prec", [(128, "1", None, "f64"), (128, "2", "rows,8,9", "f64"),
+                                             (128, "2", "rows,4,23", "f64"), (256, "1", None, "f64"),
+                                             (256, "2", "rows,4,3", "f64"), (256, "2", "rows,8,7", "f64"),
+                                             (256, "4", None, "f32"), (256, "4", "rows,4,5", "f32"),
+                                             (256, "1", None, "f32")])
+def test_row_access_width(N, vw, tile, prec):
+    """Whole-row kernel with one site per lane and access (LATTICE_ROWS_VW=1)
+    and with 16-byte accesses (two float64 or four float32 sites per lane, the
+    default where the row allows them), ragged z chunks, against the oracle:
+    1e-12 in float64; float32 fields against the float64 oracle at the
+    precision mode's stated bound."""
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    with tile_env(vw, "LATTICE_ROWS_VW"):
+        if prec == "f64":
+            check_run(kw, phi, pi, 1, tile=tile, what=f"rows-vw{vw}-{N}")
+            return
+        say(f"[parity] f32 rows-vw{vw}-{N} tile={tile}")
+        with tile_env(tile):
+            lat, tp, tq = gpu_scalar(kw, phi, pi, [1], precision="f32")
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(1)
+    for s in range(2):
+        assert rel_maxdiff(tp[s].cpu().numpy(), st.phi[s]) < 2e-6
+        assert rel_maxdiff(tq[s].cpu().numpy(), st.pi[s]) < 2e-4
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_row_access_width_bitwise(prec):
+    """Each site's arithmetic is the same expression in either access width, so
+    without self-consistent expansion (whose coefficients depend on the order of
+    the block sums) the fields after leapfrog steps are bitwise equal."""
+    import torch
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields()
+    kw = scalar_kwargs(wl, integrator="lf", expansion="fixed")
+    out = []
+    for vw in ("1", "2" if prec == "f64" else "4"):
+        say(f"[bitwise] 256 {prec} LATTICE_ROWS_VW={vw}")
+        with tile_env(vw, "LATTICE_ROWS_VW"):
+            lat, tp, tq = gpu_scalar(kw, phi, pi, [3], precision=prec)
+        out.append([t.cpu() for t in (*tp, *tq)])
+        lat.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("N,tile", [(256, None), (256, "rows,4,32"), (256, "rows,4,7"), (128, "rows,8,5"),
+                                    (64, "rows,4,3")])
+def test_row_block_order(N, tile):
+    """Whole-row kernel with the y tile as the fastest block index
+    (LATTICE_ROWS_YFAST=1: each XCD's blocks form a slab of whole z planes), on
+    ragged z chunks: VV4 with self-consistent expansion against the oracle, and
+    leapfrog on a fixed background bitwise equal to the default block order."""
+    import torch
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields(N=N)
+    with tile_env("1", "LATTICE_ROWS_YFAST"):
+        check_run(scalar_kwargs(wl, N=N), phi, pi, 1, tile=tile, what=f"rows-yfast-{N}")
+    kw = scalar_kwargs(wl, N=N, integrator="lf", expansion="fixed")
+    out = []
+    for yf in ("0", "1"):
+        with tile_env("1" if yf == "1" else "0", "LATTICE_ROWS_YFAST"), tile_env(tile):
+            lat, tp, tq = gpu_scalar(kw, phi, pi, [3])
+        out.append([t.cpu() for t in (*tp, *tq)])
+        lat.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("N", [2, 3, 5, 7])
 def test_tiny_lattices(N):
     wl = workloads.PREHEAT_128
