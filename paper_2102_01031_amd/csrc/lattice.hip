@@ -294,12 +294,15 @@ void set_rows_geometry(lat_ctx *c, int ty, int zc)
 
 void geometry_from_env(lat_ctx *c)
 {
-    // prefetch depth of the whole-row kernel: two planes at N = 256 (float64:
-    // measured 3% faster there; float32 with 4-row blocks and 16-byte accesses:
-    // 1% faster), else one; LATTICE_ROWS_PF=1|2 overrides (two planes are
-    // instantiated for 4-row blocks, and for float32 8-row blocks, at N = 256)
-    c->rows_pf = c->N == 256 ? 2 : 1;
-    if (const char *pf = std::getenv("LATTICE_ROWS_PF")) c->rows_pf = std::atoi(pf) == 2 ? 2 : 1;
+    // prefetch depth of the whole-row kernel at N = 256: two planes in float64
+    // (3% faster than one; three spill to 118 AGPRs and ran 5% slower), four in
+    // float32 with 4-row blocks and 16-byte accesses (116 against 120 us at two
+    // or three); one elsewhere.  LATTICE_ROWS_PF=1..4 overrides (depths above one
+    // are instantiated at N = 256 only: two planes for 4-row blocks and for
+    // float32 8-row blocks, three for 4-row blocks, four for float32 4-row
+    // blocks with 16-byte accesses; other requests fall back to one plane)
+    c->rows_pf = c->N == 256 ? (c->f32 ? 4 : 2) : 1;
+    if (const char *pf = std::getenv("LATTICE_ROWS_PF")) c->rows_pf = std::min(4, std::max(1, std::atoi(pf)));
     // 16-byte row accesses (four sites per lane) for float32 at N = 256, where
     // they measured 1.2% faster; float64 keeps one site per lane and access
     // (16-byte accesses measured 4% slower at 256^3, as did a 16-byte 4-in-4-out
@@ -418,6 +421,8 @@ hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarA
         if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2, V>(variant, a, nb, s);
         if constexpr (V == 4) {
             if (pf == 2 && xs == 4 && ty == 8) return launch_rows_variant<T, NF, 4, 8, 2, V>(variant, a, nb, s);
+            if (pf == 3 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 3, V>(variant, a, nb, s);
+            if (pf == 4 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 4, V>(variant, a, nb, s);
         }
         if (xs == 4) return ty == 4 ? launch_rows_variant<T, NF, 4, 4, 1, V>(variant, a, nb, s)
                                     : launch_rows_variant<T, NF, 4, 8, 1, V>(variant, a, nb, s);
@@ -428,6 +433,9 @@ hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarA
         return hipErrorInvalidValue;
     }
     if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2>(variant, a, nb, s);
+    if constexpr (sizeof(T) == 8) {
+        if (pf == 3 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 3>(variant, a, nb, s);
+    }
     if (ty == 4) {
         if (xs == 1) return launch_rows_variant<T, NF, 1, 4>(variant, a, nb, s);
         if (xs == 2) return launch_rows_variant<T, NF, 2, 4>(variant, a, nb, s);

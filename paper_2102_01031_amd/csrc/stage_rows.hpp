@@ -66,7 +66,7 @@ template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, b
           int VW = 1>
 __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 {
-    static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
+    static_assert(PF >= 1 && PF <= 4, "prefetch depth 1 .. 4");
     static_assert(XS % VW == 0 && VW * sizeof(T) <= 16, "vector width");
     using VT = typename RowVec<T, VW>::type;
     constexpr int NT = 64 * TY;
@@ -123,8 +123,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const VT vzero = (VT)T(0);
 
     T fm[XS][NF], f0[XS][NF], fp[XS][NF], p0[XS][NF], pp[XS][NF];
-    VT oAf[XV][NF], oAp[XV][NF], oBf[XV][NF], oBp[XV][NF], oCf[XV][NF], oCp[XV][NF];
-    VT hAf[HPT][NF], hAp[HPT][NF], hBf[HPT][NF], hBp[HPT][NF], hCf[HPT][NF], hCp[HPT][NF];
+    // register set s (s < PF + 1) of own-row phi, pi and halo-row phi, pi loads
+    VT of[PF + 1][XV][NF], op[PF + 1][XV][NF], hf[PF + 1][HPT][NF], hp[PF + 1][HPT][NF];
 
     {
         const unsigned om = (unsigned)(z0 == 0 ? N - 1 : z0 - 1) * NN;
@@ -148,8 +148,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                 VT c = ldv<VT>(P, o1 + o);
                 const VT pc = ldv<VT>(Q, o1 + o);
                 if (DLOAD) c += dl * pc;
-                oAf[j][f] = ldv<VT>(P, o2 + o);
-                oAp[j][f] = ldv<VT>(Q, o2 + o);
+                of[0][j][f] = ldv<VT>(P, o2 + o);
+                op[0][j][f] = ldv<VT>(Q, o2 + o);
                 *(VT *)&lds[0][f][orow + x0] = b;
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {
@@ -163,30 +163,32 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
-                hAf[j][f] = hAp[j][f] = vzero;
+                hf[0][j][f] = hp[0][j][f] = vzero;
                 if (hval[j]) {
                     VT h = ldv<VT>(P, o0 + hoff[j]);
                     if (DLOAD) h += dl * ldv<VT>(Q, o0 + hoff[j]);
                     *(VT *)&lds[0][f][hslot[j]] = h;
-                    hAf[j][f] = ldv<VT>(P, oh1 + hoff[j]);
-                    if (DLOAD) hAp[j][f] = ldv<VT>(Q, oh1 + hoff[j]);
+                    hf[0][j][f] = ldv<VT>(P, oh1 + hoff[j]);
+                    if (DLOAD) hp[0][j][f] = ldv<VT>(Q, oh1 + hoff[j]);
                 }
             }
-            if constexpr (PF == 2) {
-                const unsigned o3 = (unsigned)(min(z0 + 3, z1) % N) * NN;
-                const unsigned oh2 = (unsigned)(min(z0 + 2, z1 - 1) % N) * NN;
+            // sets 1 .. PF-1: own plane z0 + 2 + s, halo plane z0 + 1 + s
+#pragma unroll
+            for (int st = 1; st < PF; ++st) {
+                const unsigned os = (unsigned)(min(z0 + 2 + st, z1) % N) * NN;
+                const unsigned ohs = (unsigned)(min(z0 + 1 + st, z1 - 1) % N) * NN;
 #pragma unroll
                 for (int j = 0; j < XV; ++j) {
                     const int o = yo + VW * lane + 64 * VW * j;
-                    oBf[j][f] = ldv<VT>(P, o3 + o);
-                    oBp[j][f] = ldv<VT>(Q, o3 + o);
+                    of[st][j][f] = ldv<VT>(P, os + o);
+                    op[st][j][f] = ldv<VT>(Q, os + o);
                 }
 #pragma unroll
                 for (int j = 0; j < HPT; ++j) {
-                    hBf[j][f] = hBp[j][f] = vzero;
+                    hf[st][j][f] = hp[st][j][f] = vzero;
                     if (hval[j]) {
-                        hBf[j][f] = ldv<VT>(P, oh2 + hoff[j]);
-                        if (DLOAD) hBp[j][f] = ldv<VT>(Q, oh2 + hoff[j]);
+                        hf[st][j][f] = ldv<VT>(P, ohs + hoff[j]);
+                        if (DLOAD) hp[st][j][f] = ldv<VT>(Q, ohs + hoff[j]);
                     }
                 }
             }
@@ -333,17 +335,16 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
         }
     };
 
-    if constexpr (PF == 1) {
-        for (int z = z0; z < z1; z += 2) {
-            plane(z, oAf, oAp, hAf, hAp, oBf, oBp, hBf, hBp);
-            if (z + 1 < z1) plane(z + 1, oBf, oBp, hBf, hBp, oAf, oAp, hAf, hAp);
-        }
-    } else {
-        // set A holds own plane z + 2 and halo plane z + 1, B the next ones; C is loaded
-        for (int z = z0; z < z1; z += 3) {
-            plane(z, oAf, oAp, hAf, hAp, oCf, oCp, hCf, hCp);
-            if (z + 1 < z1) plane(z + 1, oBf, oBp, hBf, hBp, oAf, oAp, hAf, hAp);
-            if (z + 2 < z1) plane(z + 2, oCf, oCp, hCf, hCp, oBf, oBp, hBf, hBp);
+    // at unrolled step u set u holds own plane z + 2 and halo plane z + 1 (read
+    // by the rotation), and set (u + PF) mod (PF + 1) receives the loads PF
+    // planes ahead
+    for (int z = z0; z < z1; z += PF + 1) {
+#pragma unroll
+        for (int u = 0; u <= PF; ++u) {
+            if (z + u < z1) {
+                const int d = (u + PF) % (PF + 1);
+                plane(z + u, of[u], op[u], hf[u], hp[u], of[d], op[d], hf[d], hp[d]);
+            }
         }
     }
 

@@ -101,14 +101,46 @@ def test_preheat_256_bench_config():
     check_run(scalar_kwargs(wl), phi, pi, 1, what="preheat-256")
 
 
-@pytest.mark.parametrize("tile", ["rows,4,3", "rows,4,1"])
-def test_preheat_256_two_plane_prefetch_ragged(tile):
-    """256^3 float64 runs the whole-row kernel with loads two planes ahead
-    (three rotating register sets, z loop unrolled by three): z chunks that leave
-    a remainder of one after the unrolled groups (3) or hold one plane (1)."""
+@pytest.mark.parametrize("tile,pf", [("rows,4,3", "2"), ("rows,4,1", "2"), ("rows,4,5", "3"), ("rows,4,2", "3"),
+                                     ("rows,4,64", "3"), ("rows,4,6", "1")])
+def test_preheat_256_prefetch_depth_ragged(tile, pf):
+    """256^3 float64 on the whole-row kernel with loads PF planes ahead (PF + 1
+    rotating register sets, z loop unrolled by PF + 1): z chunks that leave
+    every remainder after the unrolled groups, or hold one or two planes."""
     wl = workloads.PREHEAT_256
     phi, pi = wl.initial_fields()
-    check_run(scalar_kwargs(wl), phi, pi, 1, tile=tile, what=f"preheat-256-{tile}")
+    with tile_env(pf, "LATTICE_ROWS_PF"):
+        check_run(scalar_kwargs(wl), phi, pi, 1, tile=tile, what=f"preheat-256-{tile}-pf{pf}")
+
+
+@pytest.mark.parametrize("tile,pf", [("rows,4,7", "4"), ("rows,4,64", "4"), ("rows,4,6", "3"), ("rows,4,9", "2"),
+                                     ("rows,8,5", "2")])
+def test_preheat_256_f32_prefetch_depth(tile, pf):
+    """float32 fields with 16-byte accesses at each prefetch depth, ragged z
+    chunks: the stated float32 bound against the float64 oracle, and the fields
+    bitwise equal to one site per lane and access at one plane ahead (leapfrog
+    on a fixed background, where no block sum feeds a coefficient)."""
+    import torch
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields()
+    kw = scalar_kwargs(wl)
+    say(f"[parity] f32 256 tile={tile} pf={pf}")
+    with tile_env(pf, "LATTICE_ROWS_PF"), tile_env(tile):
+        lat, tp, tq = gpu_scalar(kw, phi, pi, [1], precision="f32")
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(1)
+    for s in range(2):
+        assert rel_maxdiff(tp[s].cpu().numpy(), st.phi[s]) < 2e-6
+        assert rel_maxdiff(tq[s].cpu().numpy(), st.pi[s]) < 2e-4
+    lat.close()
+    kl = scalar_kwargs(wl, integrator="lf", expansion="fixed")
+    out = []
+    for env in ((pf, "4", tile), ("1", "1", None)):
+        with tile_env(env[0], "LATTICE_ROWS_PF"), tile_env(env[1], "LATTICE_ROWS_VW"), tile_env(env[2]):
+            lat, tp, tq = gpu_scalar(kl, phi, pi, [2], precision="f32")
+        out.append([t.cpu() for t in (*tp, *tq)])
+        lat.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("N,vw,tile,prec", [(128, "1", None, "f64"), (128, "2", "rows,8,9", "f64"),
