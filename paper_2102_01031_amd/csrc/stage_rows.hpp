@@ -11,10 +11,15 @@
 // Block order: the blocks of one XCD form either a y slab through every z
 // chunk or a slab of whole planes (y tile fastest), so halo rows between
 // tiles are shared inside one L2 except at the slab's faces.
-// PF is the prefetch depth in planes: the loads issued while plane z is
-// computed are for own plane z + 2 + PF and halo plane z + 1 + PF, landing in
-// one of PF + 1 register sets that rotate with the (PF + 1)-fold unrolled z
-// loop, so no register copies force an early wait on loads in flight.
+// PF is the prefetch depth in planes: the loads issued while the plane of
+// march step s is computed are for own plane s + 2 + PF and halo plane
+// s + 1 + PF of the march, landing in one of PF + 1 register sets that rotate
+// with the (PF + 1)-fold unrolled z loop, so no register copies force an early
+// wait on loads in flight.
+// A block marches its z chunk up or down (ScalarArgs::down): passes that
+// alternate direction start on the planes the previous pass wrote last.  With
+// ordinary stores (ScalarArgs::cached_out) instead of non-temporal ones those
+// planes are still held in the memory-side cache when the next pass reads them.
 #pragma once
 #include "common.hpp"
 #include "stage_scalar.hpp"
@@ -94,6 +99,16 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const int y0 = by * TY;
     const int z0 = bz * g.zc;
     const int z1 = min(z0 + g.zc, N);
+    const int len = z1 - z0;
+    // march direction: up (z0, z0 + 1, ...) or down (z1 - 1, z1 - 2, ...);
+    // pl(k) is the k-th plane of the march, k = -1 .. len, wrapped periodically
+    const bool down = g.down != 0;
+    auto pl = [&](const int k) {
+        int z = down ? z1 - 1 - k : z0 + k;
+        if (z < 0) z += N;
+        if (z >= N) z -= N;
+        return z;
+    };
     const unsigned NN = (unsigned)N * (unsigned)N;   // N^3 < 2^32
 
     const int yrow = y0 + w;
@@ -127,11 +142,11 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     VT of[PF + 1][XV][NF], op[PF + 1][XV][NF], hf[PF + 1][HPT][NF], hp[PF + 1][HPT][NF];
 
     {
-        const unsigned om = (unsigned)(z0 == 0 ? N - 1 : z0 - 1) * NN;
-        const unsigned o0 = (unsigned)z0 * NN;
-        const unsigned o1 = (unsigned)((z0 + 1) % N) * NN;
-        const unsigned o2 = (unsigned)(min(z0 + 2, z1) % N) * NN;
-        const unsigned oh1 = (unsigned)(min(z0 + 1, z1 - 1) % N) * NN;
+        const unsigned om = (unsigned)pl(-1) * NN;
+        const unsigned o0 = (unsigned)pl(0) * NN;
+        const unsigned o1 = (unsigned)pl(1) * NN;
+        const unsigned o2 = (unsigned)pl(min(2, len)) * NN;
+        const unsigned oh1 = (unsigned)pl(min(1, len - 1)) * NN;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const T *P = g.phi_in[f];
@@ -172,11 +187,11 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                     if (DLOAD) hp[0][j][f] = ldv<VT>(Q, oh1 + hoff[j]);
                 }
             }
-            // sets 1 .. PF-1: own plane z0 + 2 + s, halo plane z0 + 1 + s
+            // sets 1 .. PF-1: own plane 2 + s of the march, halo plane 1 + s
 #pragma unroll
             for (int st = 1; st < PF; ++st) {
-                const unsigned os = (unsigned)(min(z0 + 2 + st, z1) % N) * NN;
-                const unsigned ohs = (unsigned)(min(z0 + 1 + st, z1 - 1) % N) * NN;
+                const unsigned os = (unsigned)pl(min(2 + st, len)) * NN;
+                const unsigned ohs = (unsigned)pl(min(1 + st, len - 1)) * NN;
 #pragma unroll
                 for (int j = 0; j < XV; ++j) {
                     const int o = yo + VW * lane + 64 * VW * j;
@@ -200,14 +215,13 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
     for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
 
-    auto plane = [&](const int z, VT (&oif)[XV][NF], VT (&oip)[XV][NF], VT (&hif)[HPT][NF], VT (&hip)[HPT][NF],
+    // step sm of the march: plane pl(sm); fm holds the plane behind it in the
+    // march, fp the plane ahead
+    auto plane = [&](const int sm, VT (&oif)[XV][NF], VT (&oip)[XV][NF], VT (&hif)[HPT][NF], VT (&hip)[HPT][NF],
                      VT (&oof)[XV][NF], VT (&oop)[XV][NF], VT (&hof)[HPT][NF], VT (&hop)[HPT][NF]) {
-        const int cur = (z - z0) & 1, nxt = cur ^ 1;
-        int zo = min(z + 2 + PF, z1);
-        if (zo >= N) zo -= N;
-        int zh = min(z + 1 + PF, z1 - 1);
-        if (zh >= N) zh -= N;
-        const unsigned o3 = (unsigned)zo * NN, o2 = (unsigned)zh * NN;
+        const int cur = sm & 1, nxt = cur ^ 1;
+        const unsigned o3 = (unsigned)pl(min(sm + 2 + PF, len)) * NN;
+        const unsigned o2 = (unsigned)pl(min(sm + 1 + PF, len - 1)) * NN;
         // (A) loads PF planes ahead
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -225,8 +239,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                 }
             }
         }
-        // (B) LDS plane z+1
-        if (z + 1 < z1) {
+        // (B) LDS: the plane ahead
+        if (sm + 1 < len) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
 #pragma unroll
@@ -241,8 +255,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                     if (hval[j]) *(VT *)&lds[nxt][f][hslot[j]] = DLOAD ? hif[j][f] + dl * hip[j][f] : hif[j][f];
             }
         }
-        // (C) the XS sites of this lane at plane z
-        const unsigned oz = (unsigned)z * NN + yo;
+        // (C) the XS sites of this lane at plane pl(sm)
+        const unsigned oz = (unsigned)pl(sm) * NN + yo;
 #pragma unroll
         for (int j = 0; j < XV; ++j) {
             const int x0 = VW * lane + 64 * VW * j;
@@ -262,7 +276,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             for (int v = 0; v < VW; ++v) {
                 const int k = j * VW + v;
                 const int km = v == 0 ? k : k - 1, kp = v == VW - 1 ? k : k + 1;
-                T xp[NF], yp[NF], lap[NF];
+                T xp[NF], yp[NF], zpv[NF], lap[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     const T c0 = f0[k][f];
@@ -270,8 +284,12 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                     xp[f] = v == VW - 1 ? xrv[f] : f0[kp][f];
                     const T ym = vget<T>(ymv[f], v);
                     yp[f] = vget<T>(ypv[f], v);
+                    // z + 1 and z - 1 in lattice orientation, so both march
+                    // directions evaluate the same expression
+                    zpv[f] = down ? fm[k][f] : fp[k][f];
+                    const T zm = down ? fp[k][f] : fm[k][f];
                     lap[f] = ((xp[f] - T(2) * c0 + xm) + (yp[f] - T(2) * c0 + ym) +
-                              (fp[k][f] - T(2) * c0 + fm[k][f])) * idx2;
+                              (zpv[f] - T(2) * c0 + zm)) * idx2;
                 }
                 T dV[NF];
                 if constexpr (NF == 1) {
@@ -291,7 +309,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                         acc[f] += pmd * pmd;
                         const double gx = (double)(xp[f] - f0[k][f]);
                         const double gy = (double)(yp[f] - f0[k][f]);
-                        const double gz = (double)(fp[k][f] - f0[k][f]);
+                        const double gz = (double)(zpv[f] - f0[k][f]);
                         acc[NF + f] += gx * gx + gy * gy + gz * gz;
                     }
                     const T pn = pm + c2 * F;
@@ -310,8 +328,13 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             if (valid) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    if (WPHI) stv_nt<VT>(g.phi_out[f], oz + x0, fov[f]);
-                    if (WPI) stv_nt<VT>(g.pi_out[f], oz + x0, pnv[f]);
+                    if (g.cached_out) {
+                        if (WPHI) *(VT *)((char *)g.phi_out[f] + (size_t)((oz + x0) * (unsigned)sizeof(T))) = fov[f];
+                        if (WPI) *(VT *)((char *)g.pi_out[f] + (size_t)((oz + x0) * (unsigned)sizeof(T))) = pnv[f];
+                    } else {
+                        if (WPHI) stv_nt<VT>(g.phi_out[f], oz + x0, fov[f]);
+                        if (WPI) stv_nt<VT>(g.pi_out[f], oz + x0, pnv[f]);
+                    }
                 }
             }
         }
@@ -335,15 +358,15 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
         }
     };
 
-    // at unrolled step u set u holds own plane z + 2 and halo plane z + 1 (read
+    // at unrolled step u set u holds own plane s + 2 and halo plane s + 1 (read
     // by the rotation), and set (u + PF) mod (PF + 1) receives the loads PF
     // planes ahead
-    for (int z = z0; z < z1; z += PF + 1) {
+    for (int sm = 0; sm < len; sm += PF + 1) {
 #pragma unroll
         for (int u = 0; u <= PF; ++u) {
-            if (z + u < z1) {
+            if (sm + u < len) {
                 const int d = (u + PF) % (PF + 1);
-                plane(z + u, of[u], op[u], hf[u], hp[u], of[d], op[d], hf[d], hp[d]);
+                plane(sm + u, of[u], op[u], hf[u], hp[u], of[d], op[d], hf[d], hp[d]);
             }
         }
     }

@@ -36,6 +36,8 @@ struct ScalarArgs {
     T *pi_out[2];
     int N, zc, tiles_x, tiles_y;
     int y_fastest;          // whole-row kernel block order: 0 z chunk fastest, 1 y tile fastest
+    int down;               // whole-row kernel: march each z chunk downward
+    int cached_out;         // whole-row kernel: ordinary stores (else non-temporal)
     double inv_dx2;
     double lam, q;
     const PassCoef *coef;   // this pass

@@ -325,6 +325,52 @@ def test_fp32_mode_error_is_stated():
     lat.close()
 
 
+def test_graph_replays_match_eager_alternating(monkeypatch):
+    """The same with the whole-row kernel alternating its z march direction pass
+    by pass (LATTICE_ROWS_ALT=1; odd passes of a call march down)."""
+    monkeypatch.setenv("LATTICE_ROWS_ALT", "1")
+    test_graph_replays_match_eager("vv4", "self", 64, monkeypatch)
+    test_graph_replays_match_eager("lf", "fixed", 64, monkeypatch)
+
+
+@pytest.mark.parametrize("N,tile,prec", [(256, None, "f64"), (256, "rows,4,7", "f64"), (256, "rows,4,1", "f64"),
+                                         (256, None, "f32"), (256, "rows,4,5", "f32"), (128, "rows,8,9", "f64"),
+                                         (64, "rows,4,3", "f64")])
+def test_row_march_direction(N, tile, prec):
+    """Whole-row kernel with the z march direction alternating pass by pass and
+    ordinary stores (LATTICE_ROWS_ALT=1, the default at N = 256; downward
+    marches start at the top of each z chunk and take z + 1 from the plane
+    behind them), on ragged and
+    one-plane z chunks: two VV4 steps (six passes, both directions) with
+    self-consistent expansion against the oracle, and leapfrog fields bitwise
+    equal to upward marches with non-temporal stores."""
+    import torch
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N)
+    with tile_env("1", "LATTICE_ROWS_ALT"):
+        if prec == "f64":
+            check_run(kw, phi, pi, 2, tile=tile, what=f"rows-alt-{N}")
+        else:
+            say(f"[parity] f32 rows-alt-{N} tile={tile}")
+            with tile_env(tile):
+                lat, tp, tq = gpu_scalar(kw, phi, pi, [2], precision="f32")
+            st = oracle.ScalarState(oracle_model(kw), phi, pi).run(2)
+            for s in range(2):
+                assert rel_maxdiff(tp[s].cpu().numpy(), st.phi[s]) < 2e-6
+                assert rel_maxdiff(tq[s].cpu().numpy(), st.pi[s]) < 2e-4
+            lat.close()
+    kl = scalar_kwargs(wl, N=N, integrator="lf", expansion="fixed")
+    out = []
+    for alt in ("1", "0"):
+        with tile_env(alt, "LATTICE_ROWS_ALT"), tile_env(tile):
+            lat, tp, tq = gpu_scalar(kl, phi, pi, [3], precision=prec)
+        out.append([t.cpu() for t in (*tp, *tq)])
+        lat.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("integ,expn,N", [("vv4", "self", 48), ("lf", "fixed", 32), ("vv2", "none", 64)])
 def test_graph_replays_match_eager(integ, expn, N, monkeypatch):
     """Calls of eight or more passes are captured once into a HIP graph per step
