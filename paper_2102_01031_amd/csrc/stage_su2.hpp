@@ -39,6 +39,7 @@ struct SU2Args {
     const double4 *U_in4[3];
     double4 *U_out4[3];
     int N, tiles_x, tiles_y, zc;   // zc: z planes per block
+    int down;                      // march the z column downward (sites are independent)
     double dx, g, lam, v;
     double ck;   // kick weight
     double hd;   // drift weight
@@ -344,7 +345,8 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
         cm[0] = x == 0 ? N - 1 : x - 1;
         cp[1] = y + 1 == N ? 0 : y + 1;
         cm[1] = y == 0 ? N - 1 : y - 1;
-        for (int z = z0; z < z1; ++z) {
+        for (int s = 0; s < z1 - z0; ++s) {
+            const int z = g.down ? z1 - 1 - s : z0 + s;
             c[2] = z;
             cp[2] = z + 1 == N ? 0 : z + 1;
             cm[2] = z == 0 ? N - 1 : z - 1;

@@ -113,6 +113,31 @@ def test_su2_parity_z_columns(N, zc, steps):
     lat.close()
 
 
+@pytest.mark.parametrize("layout", ["records", "soa"])
+@pytest.mark.parametrize("N,zc,steps", [(24, 5, 7), (70, 3, 4), (32, 16, 5)])
+def test_su2_alternating_march(N, zc, steps, layout):
+    """Leapfrog passes that alternate the z march direction of every column
+    (LATTICE_SU2_ALT=1): against the oracle, and every field bitwise equal to
+    upward marches only (each site's update is independent of the order)."""
+    import torch
+    wl = workloads.SU2_HIGGS_128
+    kw = su2_kwargs(wl, N)
+    fields = inputs.random_su2_state(N, 70 + N)
+    say(f"[su2] alternating march N={N} zc={zc} steps={steps} layout={layout}")
+    out = []
+    for alt in ("1", "0"):
+        with tile_env(alt, "LATTICE_SU2_ALT"), tile_env(str(zc), "LATTICE_SU2_ZC"), \
+                tile_env("0" if layout == "soa" else None, "LATTICE_SU2_AOS"):
+            lat, gt = gpu_su2(kw, fields, [steps])
+        out.append([t.cpu() for group in gt for t in (group if isinstance(group, (list, tuple)) else [group])])
+        if alt == "1":
+            st = oracle_su2(kw, fields).run(steps)
+            compare_su2(gt, st, TOL, f"su2-alt-{N}")
+        lat.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("N,steps", [(12, 40), (32, 10)])
 def test_su2_parity_workload_state(N, steps):
     """The bench workload's initial state (white-noise doublet direction, unit
