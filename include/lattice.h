@@ -219,7 +219,7 @@ lat_status lattice_energy_batch(lat_ctx *ctx, int32_t r, lat_energies *out);
 lat_status lattice_spectrum(lat_ctx *ctx, int32_t field, int32_t which, int32_t nbins, double *sum,
                             double *delta, int64_t *count);
 
-/* Gauss-consistent initial gauge momenta (sec. 6.3, eqs. kAi1 and
+/* Gauss-consistent initial gauge momenta (sec. 5.5.1, eqs. kAi1 and
  * GaugeCurrentFluc, on the lattice): overwrite the electric field
  * (LAT_SU2_HIGGS: E; LAT_ABELIAN_HIGGS: piA) with the longitudinal solution
  *   E_i = grad+_i Lap^-1 (rho - <rho>),  Lap = sum_i grad-_i grad+_i,
@@ -227,7 +227,7 @@ lat_status lattice_spectrum(lat_ctx *ctx, int32_t field, int32_t which, int32_t 
  * a = 1 with unit links), rho the charge density of the stored scalar and
  * momenta: SU(2) rho^a = g Im(psi^dag T_a pi_psi) per colour, U(1)
  * rho = e kappa_g (phi0 pi1 - phi1 pi0).  The SU(2) solve needs every link at
- * the identity, the initial links of sec. 6.3 (LAT_ESTATE otherwise, nothing
+ * the identity, the initial links of sec. 5.5.1 (LAT_ESTATE otherwise, nothing
  * written); the Abelian law does not involve the links.  mean_charge (host,
  * 3 doubles for SU(2), 1 for U(1); NULL skips) receives <rho^a>, the
  * homogeneous charge that no periodic field can absorb: after the call the

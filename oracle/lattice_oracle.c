@@ -45,7 +45,7 @@
  *       per plaquette is the normalisation the toolkit's expansion of Tr P
  *       fixes.  Only a = 1.
  *   R14 Gauss-consistent initial gauge momenta: with the links at the
- *       identity (the initial condition of sec. 6.3) the Gauss law is the
+ *       identity (the initial condition of sec. 5.5.1) the Gauss law is the
  *       plain lattice divergence div- E = rho; its longitudinal solution uses
  *       the lattice Laplacian sum_i grad-_i grad+_i (the continuum i k_i / k^2
  *       of eq. GaugeCurrentFluc would leave a residual of order dx^2).
@@ -1820,7 +1820,7 @@ int orc_su2_lf_sync(const orc_su2_params *p, double *const *phi, double *const *
 }
 
 /* ------------------------------------------------------------------ */
-/* Gauss-consistent initial gauge momenta (sec. 6.3, eqs. kAi1 and      */
+/* Gauss-consistent initial gauge momenta (sec. 5.5.1, eqs. kAi1 and      */
 /* GaugeCurrentFluc; reading R14): with the links at the identity the   */
 /* Gauss law reads div- E = rho, and its longitudinal solution on the   */
 /* lattice is E_i = grad+_i chi with Lap chi = rho - <rho> (the lattice  */

@@ -1,4 +1,4 @@
-// stage_gauss.hpp -- Gauss-consistent initial gauge momenta (sec. 6.3, eqs.
+// stage_gauss.hpp -- Gauss-consistent initial gauge momenta (sec. 5.5.1, eqs.
 // kAi1 and GaugeCurrentFluc on the lattice).  With the links at the identity
 // the Gauss law is the plain lattice divergence div- E = rho; its
 // longitudinal solution is E_i = grad+_i chi with Lap chi = rho - <rho>,

@@ -1,5 +1,5 @@
 """GPU parity of lattice_gauss_init (Gauss-consistent initial gauge momenta,
-sec. 6.3) against the oracle's solve on the same seeded charged fluctuations,
+sec. 5.5.1) against the oracle's solve on the same seeded charged fluctuations,
 the Gauss residual after the init and along the evolution, and its errors."""
 import numpy as np
 import pytest

@@ -80,15 +80,20 @@ def check_occupation(occ, model, a, b, phi, pi, field, fstar2, tol):
     return rel
 
 
-@pytest.mark.parametrize("N,expansion,precision", [(16, "self", "f64"), (27, "fixed", "f64"),
-                                                   (24, "none", "f64"), (32, "self", "f32")])
-def test_occupation_matches_oracle(N, expansion, precision):
+@pytest.mark.parametrize("N,expansion,precision,alpha,a0", [(16, "self", "f64", 1.0, 1.0), (27, "fixed", "f64", 1.0, 1.0),
+                                                              (24, "none", "f64", 1.0, 1.0),
+                                                              (32, "self", "f32", 1.0, 1.0),
+                                                              (16, "self", "f64", 0.5, 1.6),
+                                                              (27, "fixed", "f64", 0.5, 1.3)])
+def test_occupation_matches_oracle(N, expansion, precision, alpha, a0):
     """Both fields of the two-field model at the initial state (1e-12 relative
     to the largest bin), then after three VV4 steps on each side (float64,
-    1e-10).  The oracle takes a and a' from its own clock."""
+    1e-10).  The oracle takes a and a' from its own clock.  The alpha = 0.5
+    cases start from a != 1, where the momentum term's weight a^{2(1 - alpha)}
+    differs from 1."""
     wl = workloads.PREHEAT_128
     phi, pi = wl.initial_fields(N=N)
-    kw = scalar_kwargs(wl, N=N, expansion=expansion, t0=0.4, t_ref=0.0, H0=0.3)
+    kw = scalar_kwargs(wl, N=N, expansion=expansion, t0=0.4, t_ref=0.0, H0=0.3, alpha=alpha, a0=a0)
     if expansion == "fixed":
         kw.update(w_eos=1 / 3)
     lat, _, _ = gpu_scalar(kw, phi, pi, [], precision=precision)
@@ -96,7 +101,7 @@ def test_occupation_matches_oracle(N, expansion, precision):
     st = oracle.ScalarState(m, host_values(phi, precision), host_values(pi, precision), t=kw["t0"])
     for field in (0, 1):
         rel = check_occupation(lat.occupation(field, fstar2=2.5), m, st.a, st.b, st.phi, st.pi, field, 2.5, 1e-12)
-        say(f"[occupation] N={N} {expansion} {precision} initial field {field}: a={st.a:.6f} a'={st.b:.6f} "
+        say(f"[occupation] N={N} {expansion} {precision} alpha={alpha} initial field {field}: a={st.a:.6f} a'={st.b:.6f} "
             f"max rel diff {rel:.2e}")
     if precision == "f64":
         lat.step(3)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Gauss-consistent initial gauge momenta (sec. 6.3, eqs.
+"""Pins of the oracle's Gauss-consistent initial gauge momenta (sec. 5.5.1, eqs.
 kAi1 and GaugeCurrentFluc on the lattice) and of the charged-fluctuation
 generator (eqs. fpr_influct3, fpr_influct4 with InConstr:1, InConstr:2):
 

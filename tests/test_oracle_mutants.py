@@ -52,6 +52,13 @@ MUTANTS = [
      "test_oracle_occupation.py"),
     ("occupation omega placement", "n[b] = pref * (om * sf[b] +", "n[b] = pref * (sf[b] / om +",
      "test_oracle_occupation.py"),
+    ("occupation momentum weight with the inverse power of a",
+     "pow(a, 2.0 * (1.0 - p->alpha)) * sx[b]", "pow(a, 2.0 * (p->alpha - 1.0)) * sx[b]",
+     "test_oracle_occupation.py"),
+    ("occupation momentum weight with half the power of a",
+     "pow(a, 2.0 * (1.0 - p->alpha)) * sx[b]", "pow(a, 1.0 - p->alpha) * sx[b]", "test_oracle_occupation.py"),
+    ("occupation momentum weight dropped", "pow(a, 2.0 * (1.0 - p->alpha)) * sx[b]", "sx[b]",
+     "test_oracle_occupation.py"),
     ("occupation cross-coupling mass", "if (p->potential == ORC_PHI4_CHI2) d += p->q * w * w;", "",
      "test_oracle_occupation.py"),
     ("fixed-background adjoint drift at the kick time", "double dr = h * pow(am, al - 3.0);",

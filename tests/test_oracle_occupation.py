@@ -6,7 +6,13 @@ The shell normalisation of eq. discretePS divides by 4 pi b^2, so
 4 pi b^2 n_b = E / omega, for a travelling wave (E = L^3 A^2 omega^2 / 2) and
 a standing wave (E = L^3 A^2 omega^2 / 4), with omega^2 = k^2 + a^2 <V''>
 from the homogeneous background.  In an expanding background, momenta that
-make phi' + (a'/a) phi vanish leave only the field term."""
+make phi' + (a'/a) phi vanish leave only the field term.
+
+The alpha-time exponent is a choice of clock, not of physics: one physical
+state (phi, its cosmic-time rate phi_t, a and H = a_t/a) written in alpha-time
+has pi = a^{3-alpha} phi' = a^3 phi_t (phi' = a^alpha phi_t) and
+a' = a^{alpha+1} H, and its occupation number must come out the same for every
+alpha.  That fixes how the momentum term is weighted by a at alpha != 1."""
 import numpy as np
 import pytest
 
@@ -115,6 +121,33 @@ def test_expanding_background_comoving_momentum(orc, alpha):
         n0, _ = orc.occupation(m, a, bdot, phi, [np.zeros(N ** 3)], 0)
         want = a * a * L ** 3 * A * A / 4 * (k + (bdot / a) ** 2 / k)
         assert abs(quanta(n0, B) - want) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.0, 1.5])
+def test_same_state_any_alpha(orc, alpha):
+    # a random field with a random rate, a != 1 and H != 0, so phi_t + H phi
+    # is far from zero in every shell; the state is fixed in cosmic time
+    rng = np.random.default_rng(11)
+    a, H = 1.7, 0.45
+    V = N ** 3
+    phi = [0.3 + 0.05 * rng.standard_normal(V), 0.02 * rng.standard_normal(V)]
+    phi_t = [0.07 * rng.standard_normal(V), 0.03 * rng.standard_normal(V)]
+    pi = [a ** 3 * phi_t[0], a ** 3 * phi_t[1]]
+    for field in (0, 1):
+        ref, cref = orc.occupation(model(orc, N, DX, lam=1.3, q=20.0, nfields=2, alpha=1.0),
+                                   a, a ** 2 * H, phi, pi, field)
+        got, cgot = orc.occupation(model(orc, N, DX, lam=1.3, q=20.0, nfields=2, alpha=alpha),
+                                   a, a ** (alpha + 1) * H, phi, pi, field)
+        assert np.array_equal(cref, cgot)
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale
+        # the momentum term is a sizeable part of n in every filled shell, so a
+        # wrong power of a in its weight cannot hide below the tolerance
+        zero_rate = [np.zeros(V), np.zeros(V)]
+        fld, _ = orc.occupation(model(orc, N, DX, lam=1.3, q=20.0, nfields=2, alpha=alpha),
+                                a, 0.0, phi, zero_rate, field)
+        filled = cref[1:] > 0
+        assert np.all(np.abs(got[1:] - fld[1:])[filled] > 1e-3 * np.abs(got[1:])[filled])
 
 
 def test_rejects_bad_arguments(orc):
