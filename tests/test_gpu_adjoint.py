@@ -444,3 +444,74 @@ def test_grad_self_consistent_full_workload_vs_finite_differences():
         rel = abs(rich - ad) / abs(ad)
         say(f"[adj] self-consistent dir {k}: adjoint {ad:.10e} fd {rich:.10e} rel {rel:.2e}")
         assert rel <= 1e-6
+
+
+@pytest.mark.parametrize("expansion,alpha", [("fixed", 0.5), ("self", 1.0)])
+def test_autograd_with_expansion_and_forward_only_path(expansion, alpha):
+    """The autograd wrapper with a fixed or self-consistent background gives
+    the gradients lattice_grad gives for the same context (bitwise), dO/da0
+    and dO/da'0 for the self-consistent one, and passes gradcheck at a tiny
+    lattice.  Without a wanted gradient (no_grad, or no input requiring one)
+    it runs the forward steps only, with the same value."""
+    import torch
+    from paper_2102_01031_amd.autograd import chi_energy_fraction, energy_fraction
+    from paper_2102_01031_amd.lattice import Lattice
+    wl = workloads.ADJ_64
+    N, T = 12, 11
+    phi, pi = wl.initial_fields(N=N)
+    if expansion == "fixed":
+        bgk = dict(expansion="fixed", alpha=alpha, a0=1.0, w_eos=1 / 3, H0=2.0, t0=0.25, t_ref=0.0)
+        ctx_kw = kw_fixed(wl, N, alpha=alpha)
+    else:
+        kap = 4.0
+        b0 = oracle.hubble_b0(oracle_self(wl, N, alpha, kappa2=kap), phi, pi, 1.0)
+        bgk = dict(expansion="self", alpha=alpha, kappa2=kap)
+        ctx_kw = kw_self(wl, N, alpha, kappa2=kap, b0=b0)
+    say(f"[adj] autograd {expansion} alpha={alpha} N={N} T={T}")
+    ts = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (phi[0], phi[1], pi[0], pi[1])]
+    q = torch.tensor(wl.q, dtype=torch.float64, requires_grad=True)
+    extra = {}
+    if expansion == "self":
+        a0t = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        b0t = torch.tensor(b0, dtype=torch.float64, requires_grad=True)
+        extra = dict(a0=a0t, b0=b0t)
+    O = energy_fraction(*ts, q, N=N, dx=wl.dx, dt=wl.dt, nsteps=T, field=0, lam=wl.lam, **bgk, **extra)
+    O.backward()
+    tp, tq = to_dev(phi, torch.float64), to_dev(pi, torch.float64)
+    lat = Lattice(tp, tq, **ctx_kw)
+    r = lat.grad(T, observable="energy_fraction", field=0)
+    lat.close()
+    assert O.item() == r["value"]
+    assert torch.equal(ts[0].grad.reshape(-1), r["dO_dphi"][0])
+    assert torch.equal(ts[1].grad.reshape(-1), r["dO_dphi"][1])
+    assert torch.equal(ts[2].grad.reshape(-1), r["dO_dpi"][0])
+    assert torch.equal(ts[3].grad.reshape(-1), r["dO_dpi"][1])
+    assert q.grad.item() == r["dO_dq"]
+    if expansion == "self":
+        assert a0t.grad.item() == r["dO_da0"] and b0t.grad.item() == r["dO_db0"]
+    # forward only: under no_grad and with plain inputs
+    with torch.no_grad():
+        O1 = energy_fraction(*ts, q, N=N, dx=wl.dx, dt=wl.dt, nsteps=T, field=0, lam=wl.lam, **bgk, **extra)
+    plain = [t.detach() for t in ts]
+    O2 = energy_fraction(*plain, wl.q, N=N, dx=wl.dx, dt=wl.dt, nsteps=T, field=0, lam=wl.lam, **bgk,
+                         **({k: float(v) for k, v in extra.items()}))
+    assert not O1.requires_grad and not O2.requires_grad
+    for v in (O1.item(), O2.item()):
+        assert abs(v - r["value"]) <= 1e-13 * abs(r["value"]), (v, r["value"])
+    # gradcheck at a tiny lattice, through every differentiable input
+    n4 = 4
+    ph4, pi4 = wl.initial_fields(N=n4)
+    xs = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (ph4[0], ph4[1], pi4[0], pi4[1])]
+    q4 = torch.tensor(wl.q, dtype=torch.float64, requires_grad=True)
+    if expansion == "self":
+        b04 = oracle.hubble_b0(oracle_self(wl, n4, alpha, kappa2=kap), ph4, pi4, 1.0)
+        sc = [torch.tensor(1.0, dtype=torch.float64, requires_grad=True),
+              torch.tensor(b04, dtype=torch.float64, requires_grad=True)]
+        f = lambda a, b, c, d, qq, aa, bb: chi_energy_fraction(a, b, c, d, qq, N=n4, dx=wl.dx, dt=wl.dt, nsteps=6,
+                                                               lam=wl.lam, a0=aa, b0=bb, **bgk)
+        assert torch.autograd.gradcheck(f, (*xs, q4, *sc), eps=1e-6, atol=1e-9, rtol=1e-5)
+    else:
+        f = lambda a, b, c, d, qq: chi_energy_fraction(a, b, c, d, qq, N=n4, dx=wl.dx, dt=wl.dt, nsteps=6,
+                                                       lam=wl.lam, **bgk)
+        assert torch.autograd.gradcheck(f, (*xs, q4), eps=1e-6, atol=1e-9, rtol=1e-5)
+
