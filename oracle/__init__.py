@@ -184,11 +184,11 @@ class ScalarState:
 
     def energy(self) -> dict:
         phi, pi = self._arrs()
-        out = np.zeros(11)
+        out = np.zeros(12)
         _chk(lib().orc_energy(C.byref(self._p), _pp(phi), _pp(pi), C.byref(self.clock), _dp(out)), "energy")
         return dict(EK=out[0:2].copy(), EG=out[2:4].copy(), EV=out[4:6].copy(), rho=out[6],
                     hubble_lhs=out[7], hubble_rhs=out[8], hubble_res=out[9], a=out[10],
-                    b=self.clock.b, t=self.clock.t)
+                    b=out[11], t=self.clock.t)
 
     @property
     def t(self):

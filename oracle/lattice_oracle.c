@@ -33,6 +33,19 @@
  *   R4  leapfrog energies are measured on momenta synchronised to integer
  *       time by a half kick that is not written back (sec. 6.1 describes the
  *       sync before measurements).
+ *   A3  leapfrog with self-consistent expansion (sec. 6.1 keeps the momentum
+ *       averages of the kicks and the field averages of the drifts for the
+ *       scale factor): fields and a at integer times, momenta and b = a' half a
+ *       step behind.  A full kick at time n advances pi by h K_phi(a_n, phi_n)
+ *       and b by h K_a(a_n, E_n), where E_G, E_V are those of phi_n and E_K is
+ *       the mean of the kinetic energies of the momenta before and after the
+ *       kick (both at a_n); then a_{n+1} = a_n + h b and phi drifts with
+ *       ((a_n + a_{n+1})/2)^{alpha-3}.  The half kicks that leave or reach
+ *       integer time (the first kick from synchronised momenta, the sync) take
+ *       E_K of the momenta at the half step.  K_a is linear in E_K, so a sync
+ *       followed by a half kick is the full kick: the trajectory does not
+ *       depend on when it is synchronised, and the scheme is explicit and
+ *       time-reversible.
  *   R5  U(1): compact formulation of the U(1) toolkit (sec. 3.2) with the
  *       plaquette V_i V_{j,+i} V*_{i,+j} V*_j and kicks equal to minus the
  *       derivative of the lattice Hamiltonian.  The complex field carries the
@@ -387,7 +400,6 @@ int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_cloc
 {
     if (p->N < 1 || p->nfields < 1 || p->nfields > 2) return -1;
     if (p->integrator < ORC_LF || p->integrator > ORC_VV10) return -1;
-    if (p->integrator == ORC_LF && p->expansion == ORC_SELF) return -2;
     if (nsteps == 0) return 0;
     int dir = nsteps > 0 ? 1 : -1;
     long ns = nsteps > 0 ? nsteps : -nsteps;
@@ -409,9 +421,23 @@ int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_cloc
         for (long k = 0; k < ns; ++k) {
             double t = t_start + (double)k * h;
             double w = (c->lf_stag == 0) ? 0.5 * h : h;  /* first kick after a sync is half */
-            kick(&st, a_at(&st, t), w);
-            double a_mid = p->expansion == ORC_FIXED ? fixed_a(p, t + 0.5 * h) : 1.0;
-            drift(&st, a_mid, h);
+            if (p->expansion == ORC_SELF) {
+                /* reading A3 */
+                energies Eb = energies_of(p, st.phi, st.pi, st.a);   /* pi before the kick, phi_n */
+                kick(&st, st.a, w);
+                energies Ea = energies_of(p, st.phi, st.pi, st.a);   /* pi after the kick, phi_n  */
+                if (c->lf_stag == 0)
+                    st.b += w * kernel_a(p, st.a, &Ea);
+                else
+                    st.b += 0.5 * h * kernel_a(p, st.a, &Eb) + 0.5 * h * kernel_a(p, st.a, &Ea);
+                double a_n1 = st.a + h * st.b;
+                drift(&st, 0.5 * (st.a + a_n1), h);
+                st.a = a_n1;
+            } else {
+                kick(&st, a_at(&st, t), w);
+                double a_mid = p->expansion == ORC_FIXED ? fixed_a(p, t + 0.5 * h) : 1.0;
+                drift(&st, a_mid, h);
+            }
             c->lf_stag = dir;
         }
     } else {
@@ -446,7 +472,9 @@ int orc_run(const orc_params *p, double *const *phi, double *const *pi, orc_cloc
     return 0;
 }
 
-/* Leapfrog sync (sec. 6.1): bring staggered momenta to integer time, in place. */
+/* Leapfrog sync (sec. 6.1): bring staggered momenta to integer time, in place;
+ * with self-consistent expansion b too, with E_K of the momenta at the half
+ * step (reading A3). */
 int orc_lf_sync(const orc_params *p, double *const *phi, double *const *pi, orc_clock *c)
 {
     if (c->lf_stag == 0) return 0;
@@ -458,18 +486,24 @@ int orc_lf_sync(const orc_params *p, double *const *phi, double *const *pi, orc_
     st.K[0] = (double *)malloc(V * sizeof(double));
     st.K[1] = (double *)malloc(V * sizeof(double));
     st.a = c->a;
-    kick(&st, a_at(&st, c->t), 0.5 * c->lf_stag * p->dt);
+    double w = 0.5 * c->lf_stag * p->dt;
+    if (p->expansion == ORC_SELF) {
+        energies E = energies_of(p, st.phi, st.pi, c->a);
+        c->b += w * kernel_a(p, c->a, &E);
+    }
+    kick(&st, a_at(&st, c->t), w);
     c->lf_stag = 0;
     free(st.K[0]);
     free(st.K[1]);
     return 0;
 }
 
-/* Energies of the state, output layout (11 doubles):
+/* Energies of the state, output layout (12 doubles):
  *   [0,1] E_K per field, [2,3] E_G per field, [4,5] E_V per term, [6] rho,
  *   [7] Hubble LHS b^2, [8] Hubble RHS a^{2alpha+2} kappa^2 rho/3,
- *   [9] (LHS-RHS)/(LHS+RHS), [10] a.
- * Leapfrog momenta are synchronised on a copy (reading R4). */
+ *   [9] (LHS-RHS)/(LHS+RHS), [10] a, [11] b at integer time.
+ * Leapfrog momenta (and b with self-consistent expansion) are synchronised on
+ * a copy (readings R4, A3). */
 int orc_energy(const orc_params *p, double *const *phi, double *const *pi, const orc_clock *c,
                double *out)
 {
@@ -479,14 +513,12 @@ int orc_energy(const orc_params *p, double *const *phi, double *const *pi, const
         pis[s] = (double *)malloc(V * sizeof(double));
         memcpy(pis[s], pi[s], V * sizeof(double));
     }
-    if (c->lf_stag != 0) {
-        orc_clock cc = *c;
-        orc_lf_sync(p, phi, pis, &cc);
-    }
+    orc_clock cc = *c;
+    if (c->lf_stag != 0) orc_lf_sync(p, phi, pis, &cc);
     energies E = energies_of(p, phi, pis, c->a);
     for (int s = 0; s < p->nfields; ++s) free(pis[s]);
     double rho = rho_tot(&E);
-    double lhs = c->b * c->b;
+    double lhs = cc.b * cc.b;
     double rhs = pow(c->a, 2.0 * p->alpha + 2.0) * p->kappa2 * rho / 3.0;
     out[0] = E.EK[0]; out[1] = E.EK[1];
     out[2] = E.EG[0]; out[3] = E.EG[1];
@@ -496,6 +528,7 @@ int orc_energy(const orc_params *p, double *const *phi, double *const *pi, const
     out[8] = rhs;
     out[9] = (lhs + rhs) != 0.0 ? (lhs - rhs) / (lhs + rhs) : 0.0;
     out[10] = c->a;
+    out[11] = cc.b;
     return 0;
 }
 

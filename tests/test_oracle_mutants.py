@@ -27,6 +27,17 @@ MUTANTS = [
      "vv_order(st, order - 2, t + x1 * h, x1 * h);", "test_oracle_scalar.py"),
     ("leapfrog first half kick", "double w = (c->lf_stag == 0) ? 0.5 * h : h;", "double w = h;",
      "test_oracle_scalar.py"),
+    ("leapfrog b kick without the kinetic average",
+     "st.b += 0.5 * h * kernel_a(p, st.a, &Eb) + 0.5 * h * kernel_a(p, st.a, &Ea);",
+     "st.b += h * kernel_a(p, st.a, &Ea);", "test_oracle_lf_self.py"),
+    ("leapfrog drift at the new scale factor", "drift(&st, 0.5 * (st.a + a_n1), h);", "drift(&st, a_n1, h);",
+     "test_oracle_lf_self.py"),
+    ("leapfrog half kick of b with the synchronised momenta",
+     "st.b += w * kernel_a(p, st.a, &Ea);", "st.b += w * kernel_a(p, st.a, &Eb);", "test_oracle_lf_self.py"),
+    ("leapfrog sync of b without the kinetic energy",
+     "        energies E = energies_of(p, st.phi, st.pi, c->a);\n        c->b += w * kernel_a(p, c->a, &E);",
+     "        energies E = energies_of(p, st.phi, st.pi, c->a);\n        E.EK[0] = E.EK[1] = 0.0;\n        c->b += w * kernel_a(p, c->a, &E);",
+     "test_oracle_lf_self.py"),
     ("gradient energy power of a", "/ (double)V / (2.0 * a * a);", "/ (double)V / (2.0 * a);",
      "test_oracle_scalar.py"),
     ("U(1) current sign", "double J = e / dx * (pr * ai - pim * ar);", "double J = e / dx * (pr * ai + pim * ar);",
