@@ -98,8 +98,16 @@ def lib():
         L.orc_u1_run_vv.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long, C.c_int]
         L.orc_su2_gauss_init.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
         L.orc_u1_gauss_init.argtypes = [C.POINTER(U1Params), pp, pp, pp, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's per-site loops (n > 0 sets them; returns the
+    count in use).  Results do not depend on it: volume sums are serial."""
+    return lib().orc_set_threads(int(n))
 
 
 def _dp(a: np.ndarray):

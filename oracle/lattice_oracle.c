@@ -71,6 +71,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* Parameters                                                          */
@@ -103,6 +106,21 @@ typedef struct orc_clock {
     int32_t lf_stag;
     int32_t pad;
 } orc_clock;
+
+/* Threads.  Built with OpenMP, the site loops that write one value per site
+ * (stencils, forces, kicks, drifts) are split over z planes; every volume sum
+ * stays a single serial compensated sum in z, y, x order, so results do not
+ * depend on the thread count.  Without OpenMP everything runs on one thread. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Lattice helpers                                                     */
@@ -145,6 +163,7 @@ static size_t vol(int N) { return (size_t)N * (size_t)N * (size_t)N; }
 int orc_laplacian(int N, double dx, const double *f, double *out)
 {
     if (N < 1) return -1;
+    #pragma omp parallel for schedule(static)
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
             for (int x = 0; x < N; ++x) {
@@ -204,6 +223,7 @@ static void kernel_field(const orc_params *p, double a, double *const *phi, int 
     double *lap = (double *)malloc(V * sizeof(double));
     orc_laplacian(N, p->dx, phi[s], lap);
     double c1 = pow(a, 1.0 + p->alpha), c3 = pow(a, 3.0 + p->alpha);
+    #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         double chi = p->nfields > 1 ? phi[1][n] : 0.0;
         out[n] = c1 * lap[n] - c3 * pot_deriv(p, s, phi[0][n], chi);
@@ -309,6 +329,7 @@ static void kick(stepper *st, double a_kick, double w)
     size_t V = vol(p->N);
     for (int s = 0; s < p->nfields; ++s) kernel_field(p, a_kick, st->phi, s, st->K[s]);
     for (int s = 0; s < p->nfields; ++s)
+        #pragma omp parallel for schedule(static)
         for (size_t n = 0; n < V; ++n) st->pi[s][n] += w * st->K[s][n];
 }
 
@@ -318,6 +339,7 @@ static void drift(stepper *st, double a_mid, double h)
     size_t V = vol(p->N);
     double c = h * pow(a_mid, p->alpha - 3.0);
     for (int s = 0; s < p->nfields; ++s)
+        #pragma omp parallel for schedule(static)
         for (size_t n = 0; n < V; ++n) st->phi[s][n] += c * st->pi[s][n];
 }
 
@@ -1017,6 +1039,7 @@ int orc_u1_forces(const orc_u1_params *p, double *const *phi, double *const *A,
 {
     int N = p->N;
     double dx = p->dx, e = p->e;
+    #pragma omp parallel for schedule(static)
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
             for (int x = 0; x < N; ++x) {
@@ -1131,6 +1154,7 @@ static void u1_kick(const orc_u1_params *p, double *const *phi, double *const *p
     double *F[5];
     for (int i = 0; i < 5; ++i) F[i] = (double *)malloc(V * sizeof(double));
     orc_u1_forces(p, phi, A, F, F + 2);
+    #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         pi[0][n] += w * F[0][n];
         pi[1][n] += w * F[1][n];
@@ -1174,6 +1198,7 @@ int orc_u1_run_lf(const orc_u1_params *p, double *const *phi, double *const *pi,
     size_t V = vol(p->N);
     for (long k = 0; k < ns; ++k) {
         u1_kick(p, phi, pi, A, piA, c->lf_stag == 0 ? 0.5 * h : h);
+        #pragma omp parallel for schedule(static)
         for (size_t n = 0; n < V; ++n) {
             phi[0][n] += h * pi[0][n];
             phi[1][n] += h * pi[1][n];
@@ -1585,6 +1610,7 @@ int orc_su2_forces(const orc_su2_params *p, double *const *phi, double *const *U
 {
     int N = p->N;
     double dx = p->dx, g = p->g;
+    #pragma omp parallel for schedule(static)
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
             for (int x = 0; x < N; ++x) {
@@ -1766,6 +1792,7 @@ static void su2_kick(const orc_su2_params *p, double *const *phi, double *const 
     double *F[13];
     for (int i = 0; i < 13; ++i) F[i] = (double *)malloc(V * sizeof(double));
     orc_su2_forces(p, phi, U, F, F + 4);
+    #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         for (int k = 0; k < 4; ++k) pi[k][n] += w * F[k][n];
         for (int k = 0; k < 9; ++k) E[k][n] += w * F[4 + k][n];
@@ -1788,6 +1815,7 @@ static void su2_drift(const orc_su2_params *p, double *const *phi, double *const
                       double *const *U, double *const *E, double h)
 {
     size_t V = vol(p->N);
+    #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         for (int k = 0; k < 4; ++k) phi[k][n] += h * pi[k][n];
         for (int i = 0; i < 3; ++i) {
@@ -1989,6 +2017,7 @@ static void u1_drift(const orc_u1_params *p, double *const *phi, double *const *
                      double *const *piA, double h)
 {
     size_t V = vol(p->N);
+    #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         phi[0][n] += h * pi[0][n];
         phi[1][n] += h * pi[1][n];
