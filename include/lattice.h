@@ -48,7 +48,7 @@ extern "C" {
 typedef enum lat_status {
     LAT_OK = 0,
     LAT_EINVAL = -1,        /* invalid argument (sizes, steps, null or misaligned pointers) */
-    LAT_EUNSUPPORTED = -2,  /* valid but not provided combination (e.g. LF with self-consistent expansion) */
+    LAT_EUNSUPPORTED = -2,  /* valid but not provided combination (e.g. a gauge model with expansion) */
     LAT_ENODEV = -3,        /* no usable GPU */
     LAT_EHIP = -4,          /* a HIP runtime call failed; see lattice_last_error */
     LAT_ESTATE = -5,        /* call not valid in the current state */
@@ -127,7 +127,8 @@ typedef struct lat_params {
     double t_ref;           /* LAT_EXP_FIXED: reference time with a(t_ref) = a0 */
     double a0;              /* LAT_EXP_SELF: initial a; LAT_EXP_FIXED: a(t_ref) */
     double b0;              /* LAT_EXP_SELF: initial b = a'; NaN = from the Hubble constraint
-                               (eq. NewFriedmannEQsI) on the initial fields */
+                               (eq. NewFriedmannEQsI) on the initial fields (leapfrog with
+                               lf_staggered != 0: b half a step behind, required) */
 } lat_params;
 
 typedef struct lat_fields {
@@ -173,7 +174,13 @@ typedef struct lat_ctx lat_ctx;
 /* Create a context for the fields f (device pointers, see lat_fields) and
  * validate p.  Allocates the library scratch, computes b0 from the Hubble
  * constraint when asked, and leaves the fields untouched.
- * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (LF with LAT_EXP_SELF; the U(1) and SU(2)
+ * Leapfrog with LAT_EXP_SELF follows the staggered scheme of sec. 6.1 (fields
+ * and a at integer times, momenta and b half a step behind; the b kick at time
+ * n takes E_K as the mean of the kinetic energies of the momenta before and
+ * after the momentum kick, the half kicks that leave or reach integer time
+ * that of the momenta at the half step); a staggered start (lf_staggered != 0)
+ * then needs b0 at the half step.
+ * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (the U(1) and SU(2)
  * models with expansion or in float32), LAT_ENODEV, LAT_ENOMEM,
  * LAT_EHIP.  On error *ctx is set to NULL. */
 lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
@@ -265,14 +272,17 @@ lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, in
  * Asynchronous on the context stream. */
 lat_status lattice_step(lat_ctx *ctx, int64_t nsteps);
 
-/* LF only: half-kick the momenta to integer time in place (the sync before
- * measurements of sec. 6.1).  The next step then starts with a half kick.
+/* LF only: half-kick the momenta (and, with LAT_EXP_SELF, b) to integer time
+ * in place (the sync before measurements of sec. 6.1).  The next step then
+ * starts with a half kick; a sync followed by steps gives the trajectory of
+ * the same steps without the sync.
  * No-op for VV integrators or already synchronised momenta. */
 lat_status lattice_sync(lat_ctx *ctx);
 
 /* Volume-averaged energies, Hubble and Gauss residuals of the current state
- * (sec. 4.4 outputs; sec. 5.4 Gauss measure).  LF momenta are synchronised on
- * the fly without writing them back.  Synchronises the stream; out is host memory. */
+ * (sec. 4.4 outputs; sec. 5.4 Gauss measure).  LF momenta (and b with
+ * LAT_EXP_SELF) are synchronised on the fly without writing them back.
+ * Synchronises the stream; out is host memory. */
 lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
 
 /* observable of lattice_grad */

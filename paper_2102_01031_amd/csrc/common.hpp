@@ -34,7 +34,11 @@ struct ScaleRecord {
     double maxes[4];
 };
 
-enum LastMode : int { kLastStore = 0, kLastSelf = 1 };
+// kLastSelf: velocity-Verlet update of b and a (self_update); kLastSelfLF:
+// leapfrog update (self_update_lf), which also keeps the raw sums of the
+// kicked momenta squared in ScaleRecord::sums[kPiPrev + f] for the next kick.
+enum LastMode : int { kLastStore = 0, kLastSelf = 1, kLastSelfLF = 2 };
+constexpr int kPiPrev = 8;
 
 __device__ inline double wave_sum(double v)
 {

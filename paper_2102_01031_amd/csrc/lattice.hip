@@ -138,6 +138,7 @@ struct lat_ctx {
     int rows_vw = 1;     // whole-row kernel sites per lane and access (1, or 16-byte vectors)
     int rows_y_fastest = 0;   // whole-row kernel block order (see stage_rows.hpp)
     int rows_alternate = 0;   // whole-row kernel: alternate the z march direction pass by pass
+    int rows_lp = 0;          // whole-row kernel load policy (see launch_rows)
     int zc = 0;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
     // launch statistics and optional event timing
@@ -323,6 +324,8 @@ void geometry_from_env(lat_ctx *c)
     // LATTICE_ROWS_ALT=0|1 overrides
     c->rows_alternate = c->N == 256 ? 1 : 0;
     if (const char *al = std::getenv("LATTICE_ROWS_ALT")) c->rows_alternate = std::atoi(al) != 0;
+    c->rows_lp = 0;
+    if (const char *lp = std::getenv("LATTICE_ROWS_NT")) c->rows_lp = std::min(5, std::max(0, std::atoi(lp)));
     const char *s = std::getenv("LATTICE_TILE");
     if (s && std::strncmp(s, "rows", 4) == 0 && rows_ok(c->N)) {
         int ty = 8, z = 0;
@@ -385,28 +388,28 @@ hipError_t launch_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream
     return hipGetLastError();
 }
 
-template <typename T, int NF, int XS, int TY, int PF = 1, int VW = 1>
+template <typename T, int NF, int XS, int TY, int PF = 1, int VW = 1, int LP = 0>
 hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
 {
     const dim3 grid(nb), block(64 * TY);
     switch (variant) {
     case kKickOnly:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true, PF, VW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, false, false, true, PF, VW, LP>), grid, block, 0, s, a);
         break;
     case kKickOnlyRed:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true, PF, VW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, true, PF, VW, LP>), grid, block, 0, s, a);
         break;
     case kDriftKick:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true, PF, VW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, false, true, true, PF, VW, LP>), grid, block, 0, s, a);
         break;
     case kDriftKickRed:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true, PF, VW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, true, false, true, true, true, PF, VW, LP>), grid, block, 0, s, a);
         break;
     case kKickDrift:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true, PF, VW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, true, false, true, true, PF, VW, LP>), grid, block, 0, s, a);
         break;
     case kEnergy:
-        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false, PF, VW>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((scalar_rows<T, NF, XS, TY, false, false, true, false, false, PF, VW, LP>), grid, block, 0, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -419,11 +422,35 @@ hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipS
 // vw > 1: 16-byte accesses (two float64 or four float32 sites per lane and
 // access), instantiated where the row holds a whole number of them per lane:
 // N = 128, 256 in float64, N = 256 in float32.
+// lp: cache policy of the row kernel (RowPolicy in stage_rows.hpp; 3 .. 5
+// vary it between the halves of the march), instantiated for the N = 256 defaults (float64 4-row blocks
+// two planes ahead, float32 4-row blocks four planes ahead with 16-byte
+// accesses); elsewhere loads are plain.
 template <typename T, int NF>
-hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s)
+hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s,
+                       int lp = 0)
 {
     const int xs = N / 64;
     constexpr int V = 16 / (int)sizeof(T);
+    if constexpr (sizeof(T) == 8) {
+        if (lp != 0 && vw == 1 && pf == 2 && xs == 4 && ty == 4) {
+            switch (lp) {
+            case 3: return launch_rows_variant<T, NF, 4, 4, 2, 1, 3>(variant, a, nb, s);
+            case 4: return launch_rows_variant<T, NF, 4, 4, 2, 1, 4>(variant, a, nb, s);
+            case 5: return launch_rows_variant<T, NF, 4, 4, 2, 1, 5>(variant, a, nb, s);
+            default: break;
+            }
+        }
+    } else {
+        if (lp != 0 && vw > 1 && pf == 4 && xs == 4 && ty == 4) {
+            switch (lp) {
+            case 3: return launch_rows_variant<T, NF, 4, 4, 4, V, 3>(variant, a, nb, s);
+            case 4: return launch_rows_variant<T, NF, 4, 4, 4, V, 4>(variant, a, nb, s);
+            case 5: return launch_rows_variant<T, NF, 4, 4, 4, V, 5>(variant, a, nb, s);
+            default: break;
+            }
+        }
+    }
     if (vw > 1 && xs % V == 0) {
         if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2, V>(variant, a, nb, s);
         if constexpr (V == 4) {
@@ -570,8 +597,10 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     }
     hipError_t e;
     if (c->rows)
-        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream)
-                       : launch_rows<T, 2>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream);
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream,
+                                           c->rows_lp)
+                       : launch_rows<T, 2>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream,
+                                           c->rows_lp);
     else
         e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
                        : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);
@@ -608,6 +637,9 @@ lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode)
 // caller's arrays (settled), so a replay ends in the same buffer state as the
 // captured launches.
 constexpr int64_t kGraphMinPasses = 8;
+// longest run of stencil passes one lattice_step call enqueues as a unit
+// (longer calls are split into chunks of this size)
+constexpr int64_t kChunkPasses = 1024;
 
 void drop_step_graphs(lat_ctx *c)
 {
@@ -754,8 +786,57 @@ lat_status settle(lat_ctx *c)
 // ---------------------------------------------------------------------------
 // scalar schedules
 // ---------------------------------------------------------------------------
+// Leapfrog with self-consistent expansion (reading A3): the drift after each
+// kick needs b after that kick, which needs the kicked momenta's volume sum, so
+// the drift moves into the next pass (drift on load) and the call ends with a
+// drift-only pass.  Pass k < ns kicks pi by c1 (h/2 for the first kick from
+// synchronised momenta, else h) and reduces the kicked momenta squared, E_G and
+// E_V; its last block kicks b and drifts a (self_update_lf) and writes the next
+// pass's drift and kick factors.  Pass ns drifts phi only.
+lat_status step_lf_self(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    const double al = c->p.alpha;
+    lat_status s = reserve_coef(c, (size_t)ns + 2);
+    if (s != LAT_OK) return s;
+    const double t_start = c->t;
+    int stag = c->lf_stag;
+    for (int64_t k = 0; k <= ns; ++k) {
+        PassCoef &P = c->coef_host[k];
+        P.t = t_start + (double)k * h;
+        if (k == ns) {   // drift only
+            P.c1 = P.c2 = 0.0;
+            P.t_next = P.t;
+            continue;
+        }
+        P.c1 = (stag == 0) ? 0.5 * h : h;
+        P.c2 = 0.0;
+        P.cL = (stag == 0) ? 0.0 : 0.5 * h;
+        P.cR = 0.5 * h;
+        P.h = h;
+        P.t_next = P.t + h;
+        stag = dir;
+    }
+    if ((s = upload_coef(c, (size_t)ns + 2)) != LAT_OK) return s;
+    s = launch_passes(c, dir * ns, ns + 1, [&](hipStream_t st) {
+        hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, st, c->coef, c->sc, al);
+        HIPCHK(c, hipGetLastError());
+        for (int64_t k = 0; k <= ns; ++k) {
+            const int v = k == ns ? kDriftKick : (k == 0 ? kKickOnlyRed : kDriftKickRed);
+            lat_status r = run_pass(c, v, (int)k, k == ns ? kLastStore : kLastSelfLF, st);
+            if (r != LAT_OK) return r;
+        }
+        return LAT_OK;
+    });
+    if (s != LAT_OK) return s;
+    c->lf_stag = dir;
+    c->t = t_start + (double)ns * h;
+    return LAT_OK;
+}
+
 lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
 {
+    if (c->p.expansion == LAT_EXP_SELF) return step_lf_self(c, ns, dir);
     const double h = dir * c->p.dt;
     const double al = c->p.alpha;
     lat_status s = reserve_coef(c, (size_t)ns + 1);
@@ -906,8 +987,9 @@ lat_status validate(const lat_params *p, const lat_fields *f)
     if (p->lf_staggered < -1 || p->lf_staggered > 1) return fail(nullptr, LAT_EINVAL, "lf_staggered must be -1, 0 or 1");
     if (p->lf_staggered != 0 && p->integrator != LAT_LF)
         return fail(nullptr, LAT_EINVAL, "lf_staggered needs the LF integrator");
-    if (p->integrator == LAT_LF && p->expansion == LAT_EXP_SELF)
-        return fail(nullptr, LAT_EUNSUPPORTED, "LF with self-consistent expansion is not provided");
+    if (p->integrator == LAT_LF && p->expansion == LAT_EXP_SELF && p->lf_staggered != 0 && std::isnan(p->b0))
+        return fail(nullptr, LAT_EINVAL, "a staggered leapfrog start with self-consistent expansion needs b0 "
+                                         "(a' half a step behind)");
     if (p->expansion == LAT_EXP_FIXED) {
         const double den = 3.0 * (1.0 + p->w_eos) - 2.0 * p->alpha;
         if (den == 0.0 || !(p->a0 > 0.0)) return fail(nullptr, LAT_EINVAL, "bad fixed background");
@@ -1139,6 +1221,18 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
             return bail(LAT_EHIP, "upload failed");
         if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
     }
+    if (p->expansion == LAT_EXP_SELF && p->integrator == LAT_LF && p->lf_staggered != 0) {
+        // a staggered start: the next kick's b update needs the sums of the
+        // stored half-step momenta squared (reading A3)
+        if (energy_sums(c, 0.0) != LAT_OK) return bail(LAT_EHIP, c->err);
+        for (int i = 0; i < c->nf; ++i) c->sc_host->sums[kPiPrev + i] = c->sc_host->sums[i];
+        c->sc_host->a = a;
+        c->sc_host->b = p->b0;
+        c->sc_host->t = p->t0;
+        if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return bail(LAT_EHIP, "upload failed");
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
+    }
     *out = c;
     return LAT_OK;
 }
@@ -1151,17 +1245,30 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
     const int64_t ns = nsteps > 0 ? nsteps : -nsteps;
     if (ns > (1LL << 30)) return fail(c, LAT_EINVAL, "too many steps in one call");
     lat_status s;
-    if (c->batch) return batch_step(c, nsteps);
-    if (c->p.integrator == LAT_LF) {
-        if (c->lf_stag != 0 && c->lf_stag != dir)
-            return fail(c, LAT_ESTATE, "leapfrog momenta are staggered in the other direction; sync first");
-        s = c->su2 ? su2_step_lf(c, ns, dir) : c->u1 ? u1_step_lf(c, ns, dir) : step_lf(c, ns, dir);
-    } else {
-        s = (c->u1 || c->su2) ? gauge_step_vv(c, ns, dir) : step_vv(c, ns, dir);
+    if (c->p.integrator == LAT_LF && !c->batch && c->lf_stag != 0 && c->lf_stag != dir)
+        return fail(c, LAT_ESTATE, "leapfrog momenta are staggered in the other direction; sync first");
+    // A long call runs as consecutive calls of at most kChunkPasses stencil
+    // passes, in chunks of equal length (+-1 step), so the per-call coefficient
+    // tables, pinned staging and captured graphs stay bounded whatever the step
+    // count; the result is bitwise that of the same steps issued as those
+    // shorter calls.
+    const int64_t per = c->p.integrator == LAT_LF ? 1 : (int64_t)vv_weights(c->p.integrator).size();
+    const int64_t cap = std::max<int64_t>(1, kChunkPasses / per);
+    const int64_t nchunks = (ns + cap - 1) / cap;
+    for (int64_t i = 0; i < nchunks; ++i) {
+        const int64_t n = ns / nchunks + (i < ns % nchunks ? 1 : 0);
+        if (c->batch) {
+            if ((s = batch_step(c, dir * n)) != LAT_OK) return s;
+            continue;
+        }
+        if (c->p.integrator == LAT_LF)
+            s = c->su2 ? su2_step_lf(c, n, dir) : c->u1 ? u1_step_lf(c, n, dir) : step_lf(c, n, dir);
+        else
+            s = (c->u1 || c->su2) ? gauge_step_vv(c, n, dir) : step_vv(c, n, dir);
+        if (s != LAT_OK) return s;
+        if ((s = settle(c)) != LAT_OK) return s;
+        c->step += dir * n;
     }
-    if (s != LAT_OK) return s;
-    if ((s = settle(c)) != LAT_OK) return s;
-    c->step += nsteps;
     return LAT_OK;
 }
 
@@ -1188,10 +1295,25 @@ lat_status lattice_sync(lat_ctx *c)
         const double a = scale_at(c, c->t);
         P.ka1 = std::pow(a, 1.0 + c->p.alpha);
         P.ka3 = std::pow(a, 3.0 + c->p.alpha);
-        P.c1 = 0.5 * c->lf_stag * c->p.dt;
         P.t = c->t;
-        if ((s = upload_coef(c, 1)) != LAT_OK) return s;
-        s = run_pass(c, kKickOnly, 0, kLastStore);
+        if (c->p.expansion == LAT_EXP_SELF) {
+            // reading A3: b's half kick takes E_K of the momenta before the
+            // kick (reduced with c1 = 0), the momenta kick by c2
+            P.c1 = 0.0;
+            P.c2 = 0.5 * c->lf_stag * c->p.dt;
+            P.cL = 0.0;
+            P.cR = 0.5 * c->lf_stag * c->p.dt;
+            P.h = 0.0;
+            P.t_next = c->t;
+            if ((s = upload_coef(c, 2)) != LAT_OK) return s;
+            hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, c->stream, c->coef, c->sc, c->p.alpha);
+            HIPCHK(c, hipGetLastError());
+            s = run_pass(c, kKickOnlyRed, 0, kLastSelfLF);
+        } else {
+            P.c1 = 0.5 * c->lf_stag * c->p.dt;
+            if ((s = upload_coef(c, 1)) != LAT_OK) return s;
+            s = run_pass(c, kKickOnly, 0, kLastStore);
+        }
     }
     if (s != LAT_OK) return s;
     if ((s = settle(c)) != LAT_OK) return s;
@@ -1218,12 +1340,26 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
     const double *S = c->sc_host->sums;
     const int nf = c->nf;
     const double V = (double)c->vol;
-    double rho = 0.0;
+    double rho = 0.0, skh = 0.0, sg = 0.0, sv = 0.0;
     for (int i = 0; i < nf; ++i) {
         out->EK[i] = S[i] / V / (2.0 * std::pow(a, 6.0));
         out->EG[i] = S[nf + i] / (c->p.dx * c->p.dx) / V / (2.0 * a * a);
         out->EV[i] = S[2 * nf + i] / V;
         rho += out->EK[i] + out->EG[i] + out->EV[i];
+        skh += S[kPiPrev + i];
+        sg += S[nf + i];
+        sv += S[2 * nf + i];
+    }
+    if (c->p.expansion == LAT_EXP_SELF && c->p.integrator == LAT_LF && c->lf_stag != 0) {
+        // b at integer time: its half kick with E_K of the stored half-step
+        // momenta (reading A3), not written back
+        const double al = c->p.alpha;
+        const double EK = skh / V / (2.0 * std::pow(a, 6.0));
+        const double EG = sg / (c->p.dx * c->p.dx) / V / (2.0 * a * a);
+        const double EV = sv / V;
+        const double Ka = std::pow(a, 2.0 * al + 1.0) / 3.0 * c->p.kappa2 *
+                          ((al - 2.0) * EK + al * EG + (al + 1.0) * EV);
+        b += 0.5 * c->lf_stag * c->p.dt * Ka;
     }
     out->t = c->t;
     out->a = a;

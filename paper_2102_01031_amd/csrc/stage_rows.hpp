@@ -21,6 +21,8 @@
 // ordinary stores (ScalarArgs::cached_out) instead of non-temporal ones those
 // planes are still held in the memory-side cache when the next pass reads them.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 #include "stage_scalar.hpp"
 
@@ -57,6 +59,17 @@ __device__ __forceinline__ VT ldv(const T *base, unsigned i)
     return *(const VT *)((const char *)base + (size_t)(i * (unsigned)sizeof(T)));
 }
 
+// the same load, non-temporal when NT (a streaming hint: the line is not kept
+// in the caches at the expense of others, so that the lines the previous pass
+// wrote stay in the memory-side cache for this pass to read)
+template <typename VT, bool NT, typename T>
+__device__ __forceinline__ VT ldp(const T *base, unsigned i)
+{
+    const VT *q = (const VT *)((const char *)base + (size_t)(i * (unsigned)sizeof(T)));
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+
 template <typename VT, typename T>
 __device__ __forceinline__ void stv_nt(T *base, unsigned i, VT v)
 {
@@ -67,10 +80,27 @@ __device__ __forceinline__ void stv_nt(T *base, unsigned i, VT v)
 // stores); lane l holds x = VW l + v + 64 VW j (v < VW, j < XS / VW), so the x
 // neighbours inside a lane's group come from registers and only the two at
 // the group's ends from the LDS row.
+// Cache policy of the loads and stores in phase PH (0: the first half of the
+// march, 1: the second half) under policy LP:
+//   0  plain loads;                         stores by ScalarArgs::cached_out
+//   1  own rows non-temporal, halos plain;  stores by cached_out
+//   2  every load non-temporal;             stores by cached_out
+//   3  plain loads; stores non-temporal in the first half, plain in the second
+//   4  as 3, own-row loads non-temporal in the second half
+//   5  as 3, every load non-temporal in the second half
+// (stores: 0 by cached_out, 1 non-temporal, 2 plain)
+template <int LP, int PH>
+struct RowPolicy {
+    static constexpr bool nto = LP == 1 || LP == 2 || (PH == 1 && (LP == 4 || LP == 5));
+    static constexpr bool nth = LP == 2 || (PH == 1 && LP == 5);
+    static constexpr int st = LP <= 2 ? 0 : (PH == 0 ? 1 : 2);
+};
+
 template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI, int PF = 1,
-          int VW = 1>
+          int VW = 1, int LP = 0>
 __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 {
+    constexpr bool NTO = RowPolicy<LP, 0>::nto, NTH = RowPolicy<LP, 0>::nth;
     static_assert(PF >= 1 && PF <= 4, "prefetch depth 1 .. 4");
     static_assert(XS % VW == 0 && VW * sizeof(T) <= 16, "vector width");
     using VT = typename RowVec<T, VW>::type;
@@ -155,16 +185,16 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             for (int j = 0; j < XV; ++j) {
                 const int x0 = VW * lane + 64 * VW * j;
                 const int o = yo + x0;
-                VT a = ldv<VT>(P, om + o);
-                if (DLOAD) a += dl * ldv<VT>(Q, om + o);
-                VT b = ldv<VT>(P, o0 + o);
-                const VT pb = ldv<VT>(Q, o0 + o);
+                VT a = ldp<VT, NTO>(P, om + o);
+                if (DLOAD) a += dl * ldp<VT, NTO>(Q, om + o);
+                VT b = ldp<VT, NTO>(P, o0 + o);
+                const VT pb = ldp<VT, NTO>(Q, o0 + o);
                 if (DLOAD) b += dl * pb;
-                VT c = ldv<VT>(P, o1 + o);
-                const VT pc = ldv<VT>(Q, o1 + o);
+                VT c = ldp<VT, NTO>(P, o1 + o);
+                const VT pc = ldp<VT, NTO>(Q, o1 + o);
                 if (DLOAD) c += dl * pc;
-                of[0][j][f] = ldv<VT>(P, o2 + o);
-                op[0][j][f] = ldv<VT>(Q, o2 + o);
+                of[0][j][f] = ldp<VT, NTO>(P, o2 + o);
+                op[0][j][f] = ldp<VT, NTO>(Q, o2 + o);
                 *(VT *)&lds[0][f][orow + x0] = b;
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {
@@ -180,11 +210,11 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             for (int j = 0; j < HPT; ++j) {
                 hf[0][j][f] = hp[0][j][f] = vzero;
                 if (hval[j]) {
-                    VT h = ldv<VT>(P, o0 + hoff[j]);
-                    if (DLOAD) h += dl * ldv<VT>(Q, o0 + hoff[j]);
+                    VT h = ldp<VT, NTH>(P, o0 + hoff[j]);
+                    if (DLOAD) h += dl * ldp<VT, NTH>(Q, o0 + hoff[j]);
                     *(VT *)&lds[0][f][hslot[j]] = h;
-                    hf[0][j][f] = ldv<VT>(P, oh1 + hoff[j]);
-                    if (DLOAD) hp[0][j][f] = ldv<VT>(Q, oh1 + hoff[j]);
+                    hf[0][j][f] = ldp<VT, NTH>(P, oh1 + hoff[j]);
+                    if (DLOAD) hp[0][j][f] = ldp<VT, NTH>(Q, oh1 + hoff[j]);
                 }
             }
             // sets 1 .. PF-1: own plane 2 + s of the march, halo plane 1 + s
@@ -195,15 +225,15 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
                 for (int j = 0; j < XV; ++j) {
                     const int o = yo + VW * lane + 64 * VW * j;
-                    of[st][j][f] = ldv<VT>(P, os + o);
-                    op[st][j][f] = ldv<VT>(Q, os + o);
+                    of[st][j][f] = ldp<VT, NTO>(P, os + o);
+                    op[st][j][f] = ldp<VT, NTO>(Q, os + o);
                 }
 #pragma unroll
                 for (int j = 0; j < HPT; ++j) {
                     hf[st][j][f] = hp[st][j][f] = vzero;
                     if (hval[j]) {
-                        hf[st][j][f] = ldv<VT>(P, ohs + hoff[j]);
-                        if (DLOAD) hp[st][j][f] = ldv<VT>(Q, ohs + hoff[j]);
+                        hf[st][j][f] = ldp<VT, NTH>(P, ohs + hoff[j]);
+                        if (DLOAD) hp[st][j][f] = ldp<VT, NTH>(Q, ohs + hoff[j]);
                     }
                 }
             }
@@ -217,8 +247,12 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 
     // step sm of the march: plane pl(sm); fm holds the plane behind it in the
     // march, fp the plane ahead
-    auto plane = [&](const int sm, VT (&oif)[XV][NF], VT (&oip)[XV][NF], VT (&hif)[HPT][NF], VT (&hip)[HPT][NF],
-                     VT (&oof)[XV][NF], VT (&oop)[XV][NF], VT (&hof)[HPT][NF], VT (&hop)[HPT][NF]) {
+    auto plane = [&](auto phase, const int sm, VT (&oif)[XV][NF], VT (&oip)[XV][NF], VT (&hif)[HPT][NF],
+                     VT (&hip)[HPT][NF], VT (&oof)[XV][NF], VT (&oop)[XV][NF], VT (&hof)[HPT][NF],
+                     VT (&hop)[HPT][NF]) {
+        using Pol = RowPolicy<LP, decltype(phase)::value>;
+        constexpr bool PNTO = Pol::nto, PNTH = Pol::nth;
+        const bool nt_out = Pol::st == 0 ? g.cached_out == 0 : Pol::st == 1;
         const int cur = sm & 1, nxt = cur ^ 1;
         const unsigned o3 = (unsigned)pl(min(sm + 2 + PF, len)) * NN;
         const unsigned o2 = (unsigned)pl(min(sm + 1 + PF, len - 1)) * NN;
@@ -228,14 +262,14 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
             for (int j = 0; j < XV; ++j) {
                 const int o = yo + VW * lane + 64 * VW * j;
-                oof[j][f] = ldv<VT>(g.phi_in[f], o3 + o);
-                oop[j][f] = ldv<VT>(g.pi_in[f], o3 + o);
+                oof[j][f] = ldp<VT, PNTO>(g.phi_in[f], o3 + o);
+                oop[j][f] = ldp<VT, PNTO>(g.pi_in[f], o3 + o);
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 if (hval[j]) {
-                    hof[j][f] = ldv<VT>(g.phi_in[f], o2 + hoff[j]);
-                    if (DLOAD) hop[j][f] = ldv<VT>(g.pi_in[f], o2 + hoff[j]);
+                    hof[j][f] = ldp<VT, PNTH>(g.phi_in[f], o2 + hoff[j]);
+                    if (DLOAD) hop[j][f] = ldp<VT, PNTH>(g.pi_in[f], o2 + hoff[j]);
                 }
             }
         }
@@ -328,7 +362,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             if (valid) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    if (g.cached_out) {
+                    if (!nt_out) {
                         if (WPHI) *(VT *)((char *)g.phi_out[f] + (size_t)((oz + x0) * (unsigned)sizeof(T))) = fov[f];
                         if (WPI) *(VT *)((char *)g.pi_out[f] + (size_t)((oz + x0) * (unsigned)sizeof(T))) = pnv[f];
                     } else {
@@ -361,12 +395,26 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     // at unrolled step u set u holds own plane s + 2 and halo plane s + 1 (read
     // by the rotation), and set (u + PF) mod (PF + 1) receives the loads PF
     // planes ahead
-    for (int sm = 0; sm < len; sm += PF + 1) {
+    // the two phases of the march (the second starts at a multiple of PF + 1,
+    // so the register sets rotate across the boundary as within a phase)
+    const int mid = LP >= 3 ? ((len / 2) / (PF + 1)) * (PF + 1) : 0;
+    for (int sm = 0; sm < mid; sm += PF + 1) {
 #pragma unroll
         for (int u = 0; u <= PF; ++u) {
             if (sm + u < len) {
                 const int d = (u + PF) % (PF + 1);
-                plane(sm + u, of[u], op[u], hf[u], hp[u], of[d], op[d], hf[d], hp[d]);
+                plane(std::integral_constant<int, 0>{}, sm + u, of[u], op[u], hf[u], hp[u], of[d], op[d], hf[d],
+                      hp[d]);
+            }
+        }
+    }
+    for (int sm = mid; sm < len; sm += PF + 1) {
+#pragma unroll
+        for (int u = 0; u <= PF; ++u) {
+            if (sm + u < len) {
+                const int d = (u + PF) % (PF + 1);
+                plane(std::integral_constant<int, LP >= 3 ? 1 : 0>{}, sm + u, of[u], op[u], hf[u], hp[u], of[d],
+                      op[d], hf[d], hp[d]);
             }
         }
     }
@@ -398,6 +446,8 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                 for (int k = 0; k < NQ; ++k) g.sc->sums[k] = fin[k];
                 if (g.last_mode == kLastSelf)
                     self_update<NF>(C, fin, g.sc, g.coef_next, g.alpha, g.kappa2, g.inv_vol, g.inv_dx2);
+                else if (g.last_mode == kLastSelfLF)
+                    self_update_lf<NF>(C, fin, g.sc, g.coef_next, g.alpha, g.kappa2, g.inv_vol, g.inv_dx2);
                 __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }

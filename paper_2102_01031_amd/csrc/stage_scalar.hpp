@@ -83,6 +83,45 @@ __device__ inline void self_update(const PassCoef &C, const double *fin, ScaleRe
     S->t = C.t_next;
 }
 
+// Leapfrog with self-consistent expansion (staggered: a at integer times, b
+// half a step behind).  The pass kicked the momenta at time n and reduced
+// the kicked momenta squared (fin[f]), E_G and E_V of phi_n; the momenta
+// before the kick are those the previous kick reduced (sums[kPiPrev + f]).
+//   b += cL K_a(a_n, E_K(before), E_G, E_V) + cR K_a(a_n, E_K(after), E_G, E_V)
+//   a' = a + h b; next drift h ((a + a')/2)^{alpha-3}
+// A full kick has cL = cR = h/2 (E_K the mean of the two), the half kick from
+// synchronised momenta cL = 0, cR = h/2, and the sync kick (which reduced the
+// momenta before its kick) cL = 0, cR = h/2 with h = 0.
+template <int NF>
+__device__ inline void self_update_lf(const PassCoef &C, const double *fin, ScaleRecord *S, PassCoef *Nx,
+                                      double alpha, double kappa2, double inv_vol, double inv_dx2)
+{
+    double a = S->a, b = S->b;
+    double sk0 = 0.0, sk1 = 0.0, sg = 0.0, sv = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        sk0 += S->sums[kPiPrev + f];
+        sk1 += fin[f];
+        sg += fin[NF + f];
+        sv += fin[2 * NF + f];
+    }
+    const double EG = sg * inv_dx2 * inv_vol / (2.0 * a * a);
+    const double EV = sv * inv_vol;
+    const double pre = pow(a, 2.0 * alpha + 1.0) / 3.0 * kappa2;
+    const double K0 = pre * ((alpha - 2.0) * (sk0 * inv_vol / (2.0 * pow(a, 6.0))) + alpha * EG + (alpha + 1.0) * EV);
+    const double K1 = pre * ((alpha - 2.0) * (sk1 * inv_vol / (2.0 * pow(a, 6.0))) + alpha * EG + (alpha + 1.0) * EV);
+    b += C.cL * K0 + C.cR * K1;
+    const double a1 = a + C.h * b;
+    Nx->ka1 = pow(a1, 1.0 + alpha);
+    Nx->ka3 = pow(a1, 3.0 + alpha);
+    Nx->dload = C.h * pow(0.5 * (a + a1), alpha - 3.0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) S->sums[kPiPrev + f] = fin[f];
+    S->a = a1;
+    S->b = b;
+    S->t = C.t_next;
+}
+
 template <typename T, int NF, int TX, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI>
 __global__ void __launch_bounds__(TX *TY) scalar_stage(const ScalarArgs<T> g)
 {
@@ -308,6 +347,8 @@ __global__ void __launch_bounds__(TX *TY) scalar_stage(const ScalarArgs<T> g)
                 for (int k = 0; k < NQ; ++k) g.sc->sums[k] = fin[k];
                 if (g.last_mode == kLastSelf)
                     self_update<NF>(C, fin, g.sc, g.coef_next, g.alpha, g.kappa2, g.inv_vol, g.inv_dx2);
+                else if (g.last_mode == kLastSelfLF)
+                    self_update_lf<NF>(C, fin, g.sc, g.coef_next, g.alpha, g.kappa2, g.inv_vol, g.inv_dx2);
                 __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }

@@ -52,7 +52,7 @@ def _init(params, fields):
     (dict(N=1, dx=0.5, dt=0.01), L.LAT_EINVAL),
     (dict(N=8, dx=0.5, dt=0.3), L.LAT_EINVAL),          # dt/dx above 1/sqrt(3)
     (dict(N=8, dx=-1.0, dt=0.01), L.LAT_EINVAL),
-    (dict(N=8, dx=0.5, dt=0.01, integrator="lf", expansion="self"), L.LAT_EUNSUPPORTED),
+    (dict(N=8, dx=0.5, dt=0.01, integrator="lf", expansion="self", lf_staggered=1), L.LAT_EINVAL),  # needs b0
     (dict(N=8, dx=0.5, dt=0.01, potential="abelian_higgs", integrator="vv2", expansion="fixed", H0=0.1),
      L.LAT_EUNSUPPORTED),
     (dict(N=8, dx=0.5, dt=0.01, potential="abelian_higgs", precision="f32"), L.LAT_EUNSUPPORTED),
@@ -181,3 +181,4 @@ def test_batch_validation_errors(kw, sizes, n, code):
     assert rc == code
     assert not ctx.value
     assert L.lib().lattice_last_error(None)
+

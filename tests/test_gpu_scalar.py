@@ -95,10 +95,41 @@ def test_preheat_128_full_size():
 
 def test_preheat_256_bench_config():
     """The benchmark workload (256^3, two fields, VV4, self-consistent) in the
-    benchmark's launch configuration, one step against the oracle."""
+    benchmark's launch configuration: five steps (15 stencil passes, in calls of
+    two and three steps) against
+    the oracle at 1e-12, fields and energies after each call."""
     wl = workloads.PREHEAT_256
     phi, pi = wl.initial_fields()
-    check_run(scalar_kwargs(wl), phi, pi, 1, what="preheat-256")
+    kw = scalar_kwargs(wl)
+    say("[parity] preheat-256 5 VV4 steps")
+    lat, tp, tq = gpu_scalar(kw, phi, pi, [])
+    st = oracle.ScalarState(oracle_model(kw), phi, pi)
+    for n in (2, 3):
+        lat.step(n)
+        st.run(n)
+        err = compare_state(tp, tq, st, TOL, f"preheat-256 +{n}")
+        compare_energy(lat.energy(), st.energy(), TOL, f"preheat-256 +{n}")
+        say(f"[parity]   +{n} steps: max rel diff {err:.2e}")
+    lat.close()
+
+
+def test_preheat_256_f32_five_steps_error_is_stated():
+    """The same five steps with float32 fields (float64 reductions, a, b, t):
+    the error against the float64 oracle is printed and bounded."""
+    wl = workloads.PREHEAT_256
+    phi, pi = wl.initial_fields()
+    kw = scalar_kwargs(wl)
+    lat, tp, tq = gpu_scalar(kw, phi, pi, [5], precision="f32")
+    eg = lat.energy()
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(5)
+    eo = st.energy()
+    ephi = max(rel_maxdiff(tp[s].cpu().numpy(), st.phi[s]) for s in range(2))
+    epi = max(rel_maxdiff(tq[s].cpu().numpy(), st.pi[s]) for s in range(2))
+    erho = abs(eg["rho"] - eo["rho"]) / eo["rho"]
+    ea = abs(eg["a"] - eo["a"]) / eo["a"]
+    say(f"[fp32] 256^3 5 VV4 steps: phi {ephi:.2e} pi {epi:.2e} rho {erho:.2e} a {ea:.2e}")
+    assert ephi < 5e-6 and epi < 5e-4 and erho < 1e-5 and ea < 1e-7
+    lat.close()
 
 
 @pytest.mark.parametrize("tile,pf", [("rows,4,3", "2"), ("rows,4,1", "2"), ("rows,4,5", "3"), ("rows,4,2", "3"),
@@ -405,3 +436,29 @@ def test_graph_replays_match_eager(integ, expn, N, monkeypatch):
     compare_state(tg, qg, st, TOL, "graph")
     lg.close()
     le.close()
+
+
+@pytest.mark.parametrize("integ,expn,steps,chunks", [("vv4", "self", 700, [234, 233, 233]),
+                                                     ("lf", "fixed", 2100, [700, 700, 700])])
+def test_long_call_runs_as_bounded_chunks(integ, expn, steps, chunks):
+    """A call longer than 1024 stencil passes runs as consecutive calls of
+    equal length (+-1 step), so its coefficient tables and graphs stay
+    bounded: bitwise equal to those shorter calls, and within 1e-11 of the
+    oracle's uninterrupted run (at most a few ulps per step of rounding growth)."""
+    import torch
+    wl = workloads.PREHEAT_128
+    N = 16
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N, integrator=integ, expansion=expn)
+    say(f"[chunks] {integ} {expn} {steps} steps as {chunks}")
+    lat1, tp1, tq1 = gpu_scalar(kw, phi, pi, [steps])
+    lat2, tp2, tq2 = gpu_scalar(kw, phi, pi, chunks)
+    for s in range(2):
+        assert torch.equal(tp1[s], tp2[s]) and torch.equal(tq1[s], tq2[s])
+    e1, e2 = lat1.energy(), lat2.energy()
+    assert e1["a"] == e2["a"] and e1["b"] == e2["b"] and e1["rho"] == e2["rho"] and e1["step"] == e2["step"] == steps
+    st = oracle.ScalarState(oracle_model(kw), phi, pi).run(steps)
+    compare_state(tp1, tq1, st, 1e-11, "long call")
+    compare_energy(e1, st.energy(), 1e-11, "long call")
+    lat1.close()
+    lat2.close()

@@ -106,16 +106,31 @@ def test_u1_rows_kernel_parity(N, spec, steps):
 
 
 def test_u1_parity_full_size():
+    """The Abelian-Higgs workload's whole run (128^3, 50 leapfrog steps) against
+    the oracle at 1e-12: every array, the energies, and the two terms of the
+    Gauss residual on the stored pairing, after 10 steps and after 50."""
     wl = workloads.ABELIAN_HIGGS_128
-    N, steps = wl.N, 3
+    N = wl.N
     kw = u1_kwargs(wl, N)
     fields = wl.initial_fields()
-    say(f"[u1] full size N={N} steps={steps}")
-    lat, gt = gpu_u1(kw, fields, [steps])
-    eg = lat.energy()
-    st = oracle_u1(kw, fields).run(steps)
-    compare_u1(gt, st, TOL, "u1-128")
-    compare_u1_energy(eg, st.energy(), TOL, "u1-128")
+    say(f"[u1] full size N={N} steps={wl.steps}")
+    lat, gt = gpu_u1(kw, fields, [])
+    st = oracle_u1(kw, fields)
+    done = 0
+    for n in (10, wl.steps - 10):
+        lat.step(n)
+        st.run(n)
+        done += n
+        eg = lat.energy()
+        compare_u1(gt, st, TOL, f"u1-128 after {done}")
+        compare_u1_energy(eg, st.energy(), TOL, f"u1-128 after {done}")
+        go = st.gauss()
+        for k, ko in (("gauss_div_max", "div_max"), ("gauss_charge_max", "charge_max")):
+            assert abs(eg[k] - go[ko]) <= TOL * go[ko], (k, eg[k], go[ko])
+        scale = max(go["div_max"], go["charge_max"])
+        assert eg["gauss_max"] <= 1e-12 * scale and go["gauss_max"] <= 1e-12 * scale
+        say(f"[u1]   {done} steps: rho {eg['rho']:.12e}, Gauss {eg['gauss_max'] / scale:.2e} of its terms")
+    assert done == 50
     lat.close()
 
 
