@@ -285,6 +285,33 @@ lat_status lattice_sync(lat_ctx *ctx);
  * Synchronises the stream; out is host memory. */
 lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
 
+/* Allocation-free variant of lattice_energy, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  It takes no context: p and f describe a
+ * real scalar state (LAT_PHI4 or LAT_PHI4_CHI2, float64 or float32 fields, as
+ * for lattice_init; nothing is read beyond the fields' N^3 elements) and the
+ * call enqueues on `stream` (a hipStream_t as void*, NULL = default stream)
+ * the volume reductions lattice_energy performs on a context just created with
+ * the same p and f: the scale factor a of p's start (1, the fixed background
+ * at t0, or a0), and for leapfrog with lf_staggered != 0 the on-the-fly half
+ * kick to integer time (nothing is written to the fields).
+ * out: caller-owned device memory, 8 float64 values written in stream order:
+ * EK[0], EK[1], EG[0], EG[1], EV[0], EV[1] (eq. EK_EG_EV; entries of an
+ * absent second field 0), rho, a.  The call does not synchronise and does not
+ * allocate: its partial sums, ticket counter and coefficients live in a fixed
+ * 513 KiB device array that every GPU the library runs on holds until the
+ * process ends (its address is looked up once per device, with that device
+ * current; call with the stream's device current).  Every call on a GPU
+ * shares that array, which keeps the last call's contents and is cleared where
+ * needed by the call itself: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ * Errors (reported by lattice_last_error(NULL), nothing enqueued):
+ * LAT_EINVAL for what lattice_init refuses, a null or misaligned out, or a
+ * lattice whose launch needs more block partials than the array holds
+ * (65408 float64: every N up to 832; beyond that it depends on N's launch shape);
+ * LAT_EUNSUPPORTED for the gauge models; LAT_ENODEV; LAT_EHIP. */
+lat_status lattice_energy_noalloc(const lat_params *p, const lat_fields *f, double *out, void *stream);
+
 /* observable of lattice_grad */
 enum lat_observable {
     LAT_OBS_ENERGY_FRACTION = 0,      /* O = (E_K^s + E_G^s) / rho of field s at the final time

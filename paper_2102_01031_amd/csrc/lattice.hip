@@ -21,8 +21,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -39,6 +41,12 @@
 #include "stage_adjoint_self.hpp"
 
 using namespace lat;
+
+// Fixed device scratch of lattice_energy_noalloc: every GPU the library runs
+// on holds one copy (513 KiB) until the process ends.  Host code never uses
+// this name as an address; it uses the per-device pointer that
+// hipGetSymbolAddress returns for it.
+static __device__ __align__(256) unsigned char scratch[512 * 1024 + 1024];
 
 struct lat_ctx;
 
@@ -1092,6 +1100,57 @@ void free_ctx(lat_ctx *c)
     delete c;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free energies (lattice_energy_noalloc)
+// ---------------------------------------------------------------------------
+// Byte layout of the fixed per-GPU scratch array: the pass coefficients, the
+// ticket counter, the record the last block writes the sums into, then the
+// per-block partial sums.
+constexpr size_t kNaCoef = 0, kNaTicket = 256, kNaRecord = 512, kNaPartials = 1024;
+constexpr size_t kNaBytes = 512 * 1024 + kNaPartials;   // 513 KiB per GPU
+constexpr size_t kNaPartialDoubles = (kNaBytes - kNaPartials) / sizeof(double);
+constexpr int kNaMaxDevices = 64;
+static_assert(sizeof(PassCoef) <= kNaTicket - kNaCoef && sizeof(ScaleRecord) <= kNaPartials - kNaRecord,
+              "scratch layout");
+static_assert(sizeof(scratch) == kNaBytes, "scratch size");
+
+// coefficients of the read-only energy pass (kick on a copy by c1, no drift)
+// and a cleared ticket; a kernel rather than a copy or a memset so that the
+// call stays capturable into a HIP graph
+__global__ void na_prepare(PassCoef *coef, unsigned *ticket, double ka1, double ka3, double c1, double t)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        PassCoef P{};
+        P.ka1 = ka1;
+        P.ka3 = ka3;
+        P.c1 = c1;
+        P.t = t;
+        *coef = P;
+        *ticket = 0u;
+    }
+}
+
+// energies from the raw volume sums (eq. EK_EG_EV): out = EK[0], EK[1], EG[0],
+// EG[1], EV[0], EV[1], rho, a
+__global__ void na_finish(const ScaleRecord *sc, double *out, int nf, double inv_vol, double inv_dx2, double a)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double rho = 0.0;
+        for (int i = 0; i < 2; ++i) {
+            const bool on = i < nf;
+            const double ek = on ? sc->sums[i] * inv_vol / (2.0 * pow(a, 6.0)) : 0.0;
+            const double eg = on ? sc->sums[nf + i] * inv_dx2 * inv_vol / (2.0 * a * a) : 0.0;
+            const double ev = on ? sc->sums[2 * nf + i] * inv_vol : 0.0;
+            out[i] = ek;
+            out[2 + i] = eg;
+            out[4 + i] = ev;
+            rho += ek + eg + ev;
+        }
+        out[6] = rho;
+        out[7] = a;
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1370,6 +1429,118 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
     const double den = out->hubble_lhs + out->hubble_rhs;
     out->hubble_res = den != 0.0 ? (out->hubble_lhs - out->hubble_rhs) / den : 0.0;
     out->step = c->step;
+    return LAT_OK;
+}
+
+// Allocation-free energies of a real scalar state given directly (no
+// context): the pass that lattice_energy launches, with its coefficients,
+// ticket, sum record and block partials in the fixed per-GPU scratch array.
+namespace {
+std::mutex g_na_mu;
+void *g_na_ptr[kNaMaxDevices] = {};
+
+// address of this device's copy of the scratch array (looked up once per
+// device, with that device current)
+lat_status na_scratch(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, LAT_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_na_ptr[dev] = ptr;
+    }
+    *out = (char *)g_na_ptr[dev];
+    return LAT_OK;
+}
+}  // namespace
+
+lat_status lattice_energy_noalloc(const lat_params *p, const lat_fields *f, double *out, void *stream)
+{
+    lat_status s = validate(p, f);
+    if (s != LAT_OK) return s;
+    if (p->potential != LAT_PHI4 && p->potential != LAT_PHI4_CHI2)
+        return fail(nullptr, LAT_EUNSUPPORTED, "lattice_energy_noalloc takes the real scalar models");
+    if (!out || !aligned(out, 8)) return fail(nullptr, LAT_EINVAL, "null or misaligned output pointer");
+    // the launch geometry lattice_init would choose (a host record only)
+    lat_ctx g;
+    g.N = p->N;
+    g.f32 = p->precision == LAT_PREC_F32;
+    g.nf = p->potential == LAT_PHI4 ? 1 : 2;
+    g.vol = (size_t)p->N * p->N * p->N;
+    geometry_from_env(&g);
+    const int NQ = 3 * g.nf;
+    if ((size_t)g.nblocks * NQ > kNaPartialDoubles)
+        return fail(nullptr, LAT_EINVAL,
+                    "lattice too large for the fixed scratch of lattice_energy_noalloc (" +
+                        std::to_string((size_t)g.nblocks * NQ) + " block partials, at most " +
+                        std::to_string(kNaPartialDoubles) + ")");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(nullptr, LAT_ENODEV, "no current GPU");
+    if (dev >= kNaMaxDevices) return fail(nullptr, LAT_EUNSUPPORTED, "device index beyond the scratch table");
+    char *base = nullptr;
+    if ((s = na_scratch(dev, &base)) != LAT_OK) return s;
+    PassCoef *coef = (PassCoef *)(base + kNaCoef);
+    unsigned *ticket = (unsigned *)(base + kNaTicket);
+    ScaleRecord *rec = (ScaleRecord *)(base + kNaRecord);
+    double *partials = (double *)(base + kNaPartials);
+
+    // the scale factor and on-the-fly leapfrog half kick of lattice_energy on a
+    // context just created with p
+    double a = 1.0, b = 0.0;
+    if (p->expansion == LAT_EXP_FIXED) fixed_ab(*p, p->t0, &a, &b);
+    if (p->expansion == LAT_EXP_SELF) a = p->a0;
+    const double c1 = (p->integrator == LAT_LF && p->lf_staggered != 0) ? 0.5 * p->lf_staggered * p->dt : 0.0;
+    const hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(na_prepare, dim3(1), dim3(64), 0, st, coef, ticket, std::pow(a, 1.0 + p->alpha),
+                       std::pow(a, 3.0 + p->alpha), c1, p->t0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, LAT_EHIP, std::string("na_prepare: ") + hipGetErrorString(e));
+    auto args = [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        ScalarArgs<T> A{};
+        for (int i = 0; i < g.nf; ++i) {
+            A.phi_in[i] = (const T *)f->phi[i];
+            A.pi_in[i] = (const T *)f->pi[i];
+        }
+        A.N = g.N;
+        A.zc = g.zc;
+        A.tiles_x = g.tiles_x;
+        A.tiles_y = g.tiles_y;
+        A.y_fastest = g.rows_y_fastest;
+        A.inv_dx2 = 1.0 / (p->dx * p->dx);
+        A.lam = p->lambda;
+        A.q = p->potential == LAT_PHI4_CHI2 ? p->q : 0.0;
+        A.coef = coef;
+        A.coef_next = coef;
+        A.partials = partials;
+        A.ticket = ticket;
+        A.sc = rec;
+        A.last_mode = kLastStore;
+        A.alpha = p->alpha;
+        A.kappa2 = p->kappa2;
+        A.inv_vol = 1.0 / (double)g.vol;
+        return A;
+    };
+    if (g.f32) {
+        const ScalarArgs<float> A = args((float *)nullptr);
+        e = g.rows ? (g.nf == 1 ? launch_rows<float, 1>(g.N, g.rows_ty, g.rows_pf, g.rows_vw, kEnergy, A, g.nblocks, st)
+                                : launch_rows<float, 2>(g.N, g.rows_ty, g.rows_pf, g.rows_vw, kEnergy, A, g.nblocks, st))
+                   : (g.nf == 1 ? launch_tile<float, 1>(g.tile, kEnergy, A, g.nblocks, st)
+                                : launch_tile<float, 2>(g.tile, kEnergy, A, g.nblocks, st));
+    } else {
+        const ScalarArgs<double> A = args((double *)nullptr);
+        e = g.rows ? (g.nf == 1 ? launch_rows<double, 1>(g.N, g.rows_ty, g.rows_pf, g.rows_vw, kEnergy, A, g.nblocks, st)
+                                : launch_rows<double, 2>(g.N, g.rows_ty, g.rows_pf, g.rows_vw, kEnergy, A, g.nblocks, st))
+                   : (g.nf == 1 ? launch_tile<double, 1>(g.tile, kEnergy, A, g.nblocks, st)
+                                : launch_tile<double, 2>(g.tile, kEnergy, A, g.nblocks, st));
+    }
+    if (e != hipSuccess) return fail(nullptr, LAT_EHIP, std::string("energy pass: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL(na_finish, dim3(1), dim3(64), 0, st, rec, out, g.nf, 1.0 / (double)g.vol,
+                       1.0 / (p->dx * p->dx), a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, LAT_EHIP, std::string("na_finish: ") + hipGetErrorString(e));
     return LAT_OK;
 }
 

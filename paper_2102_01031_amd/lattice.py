@@ -119,6 +119,8 @@ def lib():
         L.lattice_batch_tile.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32)]
         L.lattice_batch_tile.restype = C.c_int
+        L.lattice_energy_noalloc.argtypes = [C.POINTER(LatParams), C.POINTER(LatFields), vp, vp]
+        L.lattice_energy_noalloc.restype = C.c_int
         _lib = L
     return _lib
 
@@ -367,3 +369,29 @@ class LatticeBatch:
             self.close()
         except Exception:
             pass
+
+
+def energy_noalloc(phi, pi, out, *, stream=None, **kw):
+    """lattice_energy_noalloc: energies of the real scalar state (phi, pi) (lists
+    of CUDA tensors as for Lattice) enqueued on the stream without a context or
+    any allocation; out: a CUDA float64 tensor of 8 elements receiving EK[0],
+    EK[1], EG[0], EG[1], EV[0], EV[1], rho, a.  Other keywords as for Lattice."""
+    import torch
+    params = make_params(**kw)
+    dtype = torch.float32 if kw.get("precision", "f64") == "f32" else torch.float64
+    N = kw["N"]
+    for t in list(phi) + list(pi):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and t.numel() == N ** 3):
+            raise ValueError("fields must be contiguous CUDA tensors of N^3 elements with the run's dtype")
+    if not (out.is_cuda and out.is_contiguous() and out.dtype == torch.float64 and out.numel() >= 8):
+        raise ValueError("out must be a contiguous CUDA float64 tensor of at least 8 elements")
+    f = LatFields()
+    for i, t in enumerate(phi):
+        f.phi[i] = t.data_ptr()
+    for i, t in enumerate(pi):
+        f.pi[i] = t.data_ptr()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().lattice_energy_noalloc(C.byref(params), C.byref(f), C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(stream.cuda_stream)), None)
+    return out

@@ -182,3 +182,26 @@ def test_batch_validation_errors(kw, sizes, n, code):
     assert not ctx.value
     assert L.lib().lattice_last_error(None)
 
+
+def test_noalloc_energy_refusals_before_any_device_call():
+    """lattice_energy_noalloc validates like lattice_init and refuses lattices
+    whose launch needs more block partials than its fixed scratch holds, before
+    any device call (fake, aligned pointers)."""
+    lib = L.lib()
+    out = C.c_void_p(0x50000)
+    for kw, code in [
+        (dict(N=1, dx=0.5, dt=0.01), L.LAT_EINVAL),
+        (dict(N=8, dx=0.5, dt=0.3), L.LAT_EINVAL),
+        (dict(N=8, dx=0.5, dt=0.01, potential="abelian_higgs", e=0.5), L.LAT_EUNSUPPORTED),
+        # odd N takes 8 x 8 tiles: ceil(1001/8)^2 blocks x 6 sums > 65408
+        (dict(N=1001, dx=0.5, dt=0.01, potential="phi4_chi2", q=1.0), L.LAT_EINVAL),
+    ]:
+        p = L.make_params(**kw)
+        rc = lib.lattice_energy_noalloc(C.byref(p), C.byref(_fields(2, True)), out, None)
+        assert rc == code, (kw, rc)
+        assert lib.lattice_last_error(None)
+    p = L.make_params(N=8, dx=0.5, dt=0.01)
+    assert lib.lattice_energy_noalloc(C.byref(p), C.byref(_fields(1)), None, None) == L.LAT_EINVAL
+    assert lib.lattice_energy_noalloc(C.byref(p), C.byref(_fields(1)), C.c_void_p(0x50004), None) == L.LAT_EINVAL
+    msg = lib.lattice_last_error(None).decode()
+    assert "output" in msg
