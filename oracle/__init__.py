@@ -37,9 +37,10 @@ class Clock(C.Structure):
 
 
 class U1Params(C.Structure):
-    _fields_ = [("N", C.c_int32), ("pad", C.c_int32), ("dx", C.c_double), ("dt", C.c_double),
+    _fields_ = [("N", C.c_int32), ("expansion", C.c_int32), ("dx", C.c_double), ("dt", C.c_double),
                 ("lam", C.c_double), ("v", C.c_double), ("e", C.c_double),
-                ("kappa_g", C.c_double)]
+                ("kappa_g", C.c_double), ("alpha", C.c_double), ("kappa2", C.c_double),
+                ("w_eos", C.c_double), ("H0", C.c_double), ("t0", C.c_double), ("a0", C.c_double)]
 
 
 class SU2Params(C.Structure):
@@ -96,6 +97,9 @@ def lib():
         L.orc_gauss_solve.argtypes = [C.c_int, C.c_double, dp, pp]
         L.orc_su2_run_vv.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long, C.c_int]
         L.orc_u1_run_vv.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.POINTER(Clock), C.c_long, C.c_int]
+        L.orc_u1_fixed_background.argtypes = [C.POINTER(U1Params), C.c_double, dp, dp]
+        L.orc_u1_forces_at.argtypes = [C.POINTER(U1Params), C.c_double, pp, pp, pp, pp]
+        L.orc_u1_hubble_b0.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.c_double, dp]
         L.orc_su2_gauss_init.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
         L.orc_u1_gauss_init.argtypes = [C.POINTER(U1Params), pp, pp, pp, dp]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -356,20 +360,55 @@ class U1Model:
     v: float = 1.0
     e: float = 0.5
     kappa_g: float = 1.0
+    expansion: int = NONE
+    alpha: float = 1.0
+    kappa2: float = 0.25
+    w_eos: float = 1.0 / 3.0
+    H0: float = 0.0
+    t0: float = 0.0
+    a0: float = 1.0
 
     def cparams(self) -> U1Params:
-        return U1Params(self.N, 0, self.dx, self.dt, self.lam, self.v, self.e, self.kappa_g)
+        return U1Params(self.N, self.expansion, self.dx, self.dt, self.lam, self.v, self.e, self.kappa_g,
+                        self.alpha, self.kappa2, self.w_eos, self.H0, self.t0, self.a0)
 
 
 class U1State:
-    """phi: 2 real components, pi: 2, A: 3 link fields, piA: 3 (each N^3)."""
+    """phi: 2 real components, pi: 2, A: 3 link fields, piA: 3 (each N^3).
+    With expansion the clock holds a and b = a' (fixed background: the closed
+    form at t; self-consistent: a0 and b from the Hubble constraint unless given)."""
 
-    def __init__(self, model: U1Model, phi, pi, A, piA, t=0.0, lf_stag=0):
+    def __init__(self, model: U1Model, phi, pi, A, piA, t=0.0, lf_stag=0, a=None, b=None):
         self.m = model
         cp = lambda L: [np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1)).copy() for f in L]
         self.phi, self.pi, self.A, self.piA = cp(phi), cp(pi), cp(A), cp(piA)
         self._p = model.cparams()
-        self.clock = Clock(t, 1.0, 0.0, lf_stag, 0)
+        if model.expansion == FIXED:
+            aa, bb = C.c_double(), C.c_double()
+            _chk(lib().orc_u1_fixed_background(C.byref(self._p), float(t), C.byref(aa), C.byref(bb)), "u1 fixed")
+            a = aa.value if a is None else a
+            b = bb.value if b is None else b
+        elif model.expansion == SELF:
+            a = model.a0 if a is None else a
+            if b is None:
+                bb = C.c_double()
+                _chk(lib().orc_u1_hubble_b0(C.byref(self._p), *self._args(), float(a), C.byref(bb)), "u1 b0")
+                b = bb.value
+        else:
+            a, b = 1.0, 0.0
+        self.clock = Clock(t, a, b, lf_stag, 0)
+
+    @property
+    def a(self):
+        return self.clock.a
+
+    @property
+    def b(self):
+        return self.clock.b
+
+    @property
+    def t(self):
+        return self.clock.t
 
     def _args(self):
         return _pp(self.phi), _pp(self.pi), _pp(self.A), _pp(self.piA)
@@ -383,9 +422,12 @@ class U1State:
         return self
 
     def energy(self) -> dict:
-        out = np.zeros(12)
+        out = np.zeros(17)
         _chk(lib().orc_u1_energy(C.byref(self._p), *self._args(), C.byref(self.clock), _dp(out)), "u1 energy")
-        return _u1_dict(out)
+        d = _u1_dict(out)
+        d.update(a=out[12], b=out[13], hubble_lhs=out[14], hubble_rhs=out[15], hubble_res=out[16],
+                 t=self.clock.t)
+        return d
 
     def gauss(self) -> dict:
         out = np.zeros(12)
@@ -404,6 +446,13 @@ class U1State:
         _chk(lib().orc_u1_gauss_init(C.byref(self._p), _pp(self.phi), _pp(self.pi), _pp(self.piA), _dp(mean)),
              "u1 gauss init")
         return mean
+
+    def forces_at(self, a):
+        """Forces (kicks per unit time) at scale factor a."""
+        F = [np.zeros_like(self.phi[0]) for _ in range(5)]
+        _chk(lib().orc_u1_forces_at(C.byref(self._p), float(a), _pp(self.phi), _pp(self.A), _pp(F[:2]), _pp(F[2:])),
+             "u1 forces at a")
+        return F[:2], F[2:]
 
     def forces(self):
         F = [np.zeros_like(self.phi[0]) for _ in range(5)]

@@ -1018,9 +1018,43 @@ int orc_adjoint_vv2_self(const orc_params *p, int kind, int field, int bin, doub
 /* ------------------------------------------------------------------ */
 
 typedef struct orc_u1_params {
-    int32_t N, pad;
+    int32_t N;
+    int32_t expansion;                      /* ORC_NONE, ORC_FIXED, ORC_SELF (as for the scalars) */
     double dx, dt, lambda, v, e, kappa_g;   /* kappa_g = (f_star/omega_star)^2 */
+    double alpha, kappa2;                   /* alpha-time exponent; (f_star/m_p)^2 */
+    double w_eos, H0, t0, a0;               /* fixed background (eq. ScaleFactorPowerLaw); SELF: a0 */
 } orc_u1_params;
+
+/* U(1) sector in an expanding background (sec. 5.5.2, reading U1).  With
+ * pi = a^{3-alpha} phi' and pi_A = a^{1-alpha} F_0i (eqs. momU1singlet,
+ * momU1vec) the kernels of eq. kernelcomplexscalar and the one after it are
+ * the a = 1 forces with each term scaled:
+ *   K_phi = a^{1+alpha} (covariant Laplacian) - a^{3+alpha} (potential force),
+ *   K_A   = a^{1+alpha} kappa_g J - a^{alpha-1} (magnetic force),
+ * and the drifts are phi' = a^{alpha-3} pi, A_i' = a^{alpha-1} pi_A (eqs.
+ * momU1singlet, momU1vec with A_0 = 0).  The energies of eq. energy-contrib in
+ * these variables are the a = 1 ones divided by a^6 (scalar kinetic), a^2
+ * (scalar gradient) and a^4 (electric, magnetic); the scale-factor kernel adds
+ * (alpha - 1)(E_K^A + E_G^A) (the b' equation of sec. 5.5.2).  The Gauss law
+ * (eq. GaussU1-eom) in these variables, div pi_A = 2 e kappa_g Im(phi* pi),
+ * carries no power of a, and the kicks keep it exactly for any a.  Kicks and
+ * drifts take a at the kick time and at the drift midpoint (fixed background,
+ * reading R3), or follow readings R1 (velocity-Verlet) and A3 (leapfrog) with
+ * self-consistent expansion. */
+
+static void u1_fixed_ab(const orc_u1_params *p, double t, double *a, double *b)
+{
+    double pw = 2.0 / (3.0 * (1.0 + p->w_eos) - 2.0 * p->alpha);
+    double u = 1.0 + p->H0 * (t - p->t0) / pw;
+    *a = p->a0 * pow(u, pw);
+    *b = p->a0 * p->H0 * pow(u, pw - 1.0);
+}
+
+int orc_u1_fixed_background(const orc_u1_params *p, double t, double *a, double *b)
+{
+    u1_fixed_ab(p, t, a, b);
+    return 0;
+}
 
 static double theta(const orc_u1_params *p, double *const *A, int x, int y, int z, int i, int j)
 {
@@ -1030,15 +1064,17 @@ static double theta(const orc_u1_params *p, double *const *A, int x, int y, int 
             A[i][at(N, x, y, z)]);
 }
 
-/* forces = minus the derivative of the lattice Hamiltonian:
- *   Fphi_c = {Re,Im}(D^2 psi) - lambda/2 (|phi|^2 - v^2) phi_c
- *   FA_i   = kappa_g J_i - (e dx^3)^-1 sum_{j != i} [sin theta_ij(n) - sin theta_ij(n-j)]
+/* forces = minus the derivative of the lattice Hamiltonian (at scale factor a):
+ *   Fphi_c = a^{1+alpha} {Re,Im}(D^2 psi) - a^{3+alpha} lambda/2 (|phi|^2 - v^2) phi_c
+ *   FA_i   = a^{1+alpha} kappa_g J_i
+ *            - a^{alpha-1} (e dx^3)^-1 sum_{j != i} [sin theta_ij(n) - sin theta_ij(n-j)]
  *   J_i    = (e/dx) Im[ conj(psi(n)) V_i(n) psi(n+i) ]                       */
-int orc_u1_forces(const orc_u1_params *p, double *const *phi, double *const *A,
-                  double *const *Fphi, double *const *FA)
+static int u1_forces_a(const orc_u1_params *p, double a, double *const *phi, double *const *A,
+                       double *const *Fphi, double *const *FA)
 {
     int N = p->N;
     double dx = p->dx, e = p->e;
+    double cl = pow(a, 1.0 + p->alpha), cv = pow(a, 3.0 + p->alpha), cm_ = pow(a, p->alpha - 1.0);
     #pragma omp parallel for schedule(static)
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
@@ -1067,14 +1103,26 @@ int orc_u1_forces(const orc_u1_params *p, double *const *phi, double *const *A,
                         c[j] = dn(c[j], N);
                         mag += sin(theta(p, A, x, y, z, i, j)) - sin(theta(p, A, c[0], c[1], c[2], i, j));
                     }
-                    FA[i][n] = p->kappa_g * J - mag / (e * dx * dx * dx);
+                    FA[i][n] = cl * (p->kappa_g * J) - cm_ * (mag / (e * dx * dx * dx));
                 }
                 double m2 = 0.5 * (pr * pr + pim * pim);
                 double vp = 0.5 * p->lambda * (m2 - p->v * p->v);
-                Fphi[0][n] = dre / (dx * dx) - vp * pr;
-                Fphi[1][n] = dim / (dx * dx) - vp * pim;
+                Fphi[0][n] = cl * (dre / (dx * dx)) - cv * (vp * pr);
+                Fphi[1][n] = cl * (dim / (dx * dx)) - cv * (vp * pim);
             }
     return 0;
+}
+
+int orc_u1_forces(const orc_u1_params *p, double *const *phi, double *const *A,
+                  double *const *Fphi, double *const *FA)
+{
+    return u1_forces_a(p, 1.0, phi, A, Fphi, FA);
+}
+
+int orc_u1_forces_at(const orc_u1_params *p, double a, double *const *phi, double *const *A,
+                     double *const *Fphi, double *const *FA)
+{
+    return u1_forces_a(p, a, phi, A, Fphi, FA);
 }
 
 /* U(1) energies and Gauss constraint. Output layout (12 doubles):
@@ -1085,7 +1133,7 @@ int orc_u1_forces(const orc_u1_params *p, double *const *phi, double *const *A,
  *  with G = div^- piA - e kappa_g (phi0 pi1 - phi1 pi0) (eq. GaussU1-eom, a = 1)
  *  [11] <|div piA| + |charge|>.
  * Leapfrog momenta are synchronised on copies when lf_stag != 0. */
-static void u1_energy_plain(const orc_u1_params *p, double *const *phi, double *const *pi,
+static void u1_energy_plain(const orc_u1_params *p, double a, double *const *phi, double *const *pi,
                             double *const *A, double *const *piA, double *out)
 {
     int N = p->N;
@@ -1133,11 +1181,12 @@ static void u1_energy_plain(const orc_u1_params *p, double *const *phi, double *
                 nadd(&sLR, fabs(div + charge));
                 nadd(&sLRabs, fabs(div) + fabs(charge));
             }
-    out[0] = nval(&sk) / (double)V;
-    out[1] = nval(&sg) / (double)V;
+    const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+    out[0] = nval(&sk) / (double)V / a6;
+    out[1] = nval(&sg) / (double)V / a2;
     out[2] = nval(&sv) / (double)V;
-    out[3] = nval(&ska) / (double)V;
-    out[4] = nval(&sga) / (double)V;
+    out[3] = nval(&ska) / (double)V / a4;
+    out[4] = nval(&sga) / (double)V / a4;
     out[5] = out[0] + out[1] + out[2] + out[3] + out[4];
     out[6] = gmax;
     out[7] = dmax;
@@ -1147,13 +1196,23 @@ static void u1_energy_plain(const orc_u1_params *p, double *const *phi, double *
     out[11] = nval(&sLRabs) / (double)V;
 }
 
-static void u1_kick(const orc_u1_params *p, double *const *phi, double *const *pi,
+/* kernel of b with the gauge energies (sec. 5.5.2):
+ *   K_a = a^{2 alpha + 1}/3 kappa^2 [(alpha-2) E_K^phi + alpha E_G^phi
+ *         + (alpha-1)(E_K^A + E_G^A) + (alpha+1) E_V]   (energies as u1_energy_plain) */
+static double u1_kernel_a(const orc_u1_params *p, double a, const double *E)
+{
+    double al = p->alpha;
+    return pow(a, 2.0 * al + 1.0) / 3.0 * p->kappa2 *
+           ((al - 2.0) * E[0] + al * E[1] + (al - 1.0) * (E[3] + E[4]) + (al + 1.0) * E[2]);
+}
+
+static void u1_kick(const orc_u1_params *p, double a, double *const *phi, double *const *pi,
                     double *const *A, double *const *piA, double w)
 {
     size_t V = vol(p->N);
     double *F[5];
     for (int i = 0; i < 5; ++i) F[i] = (double *)malloc(V * sizeof(double));
-    orc_u1_forces(p, phi, A, F, F + 2);
+    u1_forces_a(p, a, phi, A, F, F + 2);
     #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         pi[0][n] += w * F[0][n];
@@ -1163,6 +1222,11 @@ static void u1_kick(const orc_u1_params *p, double *const *phi, double *const *p
     for (int i = 0; i < 5; ++i) free(F[i]);
 }
 
+/* Energies at integer time, output layout (17 doubles): [0 .. 11] as
+ * u1_energy_plain at the clock's a; [12] a, [13] b at integer time,
+ * [14] Hubble LHS b^2, [15] RHS a^{2 alpha + 2} kappa^2 rho / 3, [16] (LHS - RHS)/(LHS + RHS).
+ * Leapfrog momenta (and b with self-consistent expansion) are synchronised on
+ * copies (readings R4, A3). */
 int orc_u1_energy(const orc_u1_params *p, double *const *phi, double *const *pi,
                   double *const *A, double *const *piA, const orc_clock *c, double *out)
 {
@@ -1170,10 +1234,25 @@ int orc_u1_energy(const orc_u1_params *p, double *const *phi, double *const *pi,
     double *ps[2], *pa[3];
     for (int i = 0; i < 2; ++i) { ps[i] = (double *)malloc(B); memcpy(ps[i], pi[i], B); }
     for (int i = 0; i < 3; ++i) { pa[i] = (double *)malloc(B); memcpy(pa[i], piA[i], B); }
-    if (c->lf_stag != 0) u1_kick(p, phi, ps, A, pa, 0.5 * c->lf_stag * p->dt);
-    u1_energy_plain(p, phi, ps, A, pa, out);
+    double b = c->b;
+    if (c->lf_stag != 0) {
+        double w = 0.5 * c->lf_stag * p->dt;
+        if (p->expansion == ORC_SELF) {
+            double E[12];
+            u1_energy_plain(p, c->a, phi, ps, A, pa, E);
+            b += w * u1_kernel_a(p, c->a, E);
+        }
+        u1_kick(p, c->a, phi, ps, A, pa, w);
+    }
+    u1_energy_plain(p, c->a, phi, ps, A, pa, out);
     for (int i = 0; i < 2; ++i) free(ps[i]);
     for (int i = 0; i < 3; ++i) free(pa[i]);
+    double lhs = b * b, rhs = pow(c->a, 2.0 * p->alpha + 2.0) * p->kappa2 * out[5] / 3.0;
+    out[12] = c->a;
+    out[13] = b;
+    out[14] = lhs;
+    out[15] = rhs;
+    out[16] = (lhs + rhs) != 0.0 ? (lhs - rhs) / (lhs + rhs) : 0.0;
     return 0;
 }
 
@@ -1181,8 +1260,33 @@ int orc_u1_energy(const orc_u1_params *p, double *const *phi, double *const *pi,
 int orc_u1_gauss(const orc_u1_params *p, double *const *phi, double *const *pi,
                  double *const *A, double *const *piA, double *out)
 {
-    u1_energy_plain(p, phi, pi, A, piA, out);
+    u1_energy_plain(p, 1.0, phi, pi, A, piA, out);
     return 0;
+}
+
+/* Hubble constraint (eq. FriedmannHubble) for b at the start: b0^2 = a^{2 alpha + 2} kappa^2 rho / 3 */
+int orc_u1_hubble_b0(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
+                     double *const *piA, double a, double *b0)
+{
+    double E[12];
+    u1_energy_plain(p, a, phi, pi, A, piA, E);
+    double rhs = pow(a, 2.0 * p->alpha + 2.0) * p->kappa2 * E[5] / 3.0;
+    if (rhs < 0.0) return -1;
+    *b0 = sqrt(rhs);
+    return 0;
+}
+
+static void u1_drift_a(const orc_u1_params *p, double a_mid, double *const *phi, double *const *pi,
+                       double *const *A, double *const *piA, double h)
+{
+    size_t V = vol(p->N);
+    double cp = h * pow(a_mid, p->alpha - 3.0), ca = h * pow(a_mid, p->alpha - 1.0);
+    #pragma omp parallel for schedule(static)
+    for (size_t n = 0; n < V; ++n) {
+        phi[0][n] += cp * pi[0][n];
+        phi[1][n] += cp * pi[1][n];
+        for (int i = 0; i < 3; ++i) A[i][n] += ca * piA[i][n];
+    }
 }
 
 /* Staggered leapfrog for the U(1) system (a = 1): kick all momenta, then drift
@@ -1195,20 +1299,42 @@ int orc_u1_run_lf(const orc_u1_params *p, double *const *phi, double *const *pi,
     long ns = nsteps > 0 ? nsteps : -nsteps;
     double h = dir * p->dt;
     if (c->lf_stag != 0 && c->lf_stag != dir) return -3;
-    size_t V = vol(p->N);
+    double t_start = c->t;
     for (long k = 0; k < ns; ++k) {
-        u1_kick(p, phi, pi, A, piA, c->lf_stag == 0 ? 0.5 * h : h);
-        #pragma omp parallel for schedule(static)
-        for (size_t n = 0; n < V; ++n) {
-            phi[0][n] += h * pi[0][n];
-            phi[1][n] += h * pi[1][n];
-            for (int i = 0; i < 3; ++i) A[i][n] += h * piA[i][n];
+        double t = t_start + (double)k * h;
+        double w = c->lf_stag == 0 ? 0.5 * h : h;
+        if (p->expansion == ORC_SELF) {
+            /* reading A3 with every momentum-dependent energy (E_K^phi, E_K^A) */
+            double Eb[12], Ea[12];
+            u1_energy_plain(p, c->a, phi, pi, A, piA, Eb);
+            u1_kick(p, c->a, phi, pi, A, piA, w);
+            u1_energy_plain(p, c->a, phi, pi, A, piA, Ea);
+            if (c->lf_stag == 0)
+                c->b += w * u1_kernel_a(p, c->a, Ea);
+            else
+                c->b += 0.5 * h * u1_kernel_a(p, c->a, Eb) + 0.5 * h * u1_kernel_a(p, c->a, Ea);
+            double a1 = c->a + h * c->b;
+            u1_drift_a(p, 0.5 * (c->a + a1), phi, pi, A, piA, h);
+            c->a = a1;
+        } else if (p->expansion == ORC_FIXED) {
+            double a, b, am;
+            u1_fixed_ab(p, t, &a, &b);
+            u1_kick(p, a, phi, pi, A, piA, w);
+            u1_fixed_ab(p, t + 0.5 * h, &am, &b);
+            u1_drift_a(p, am, phi, pi, A, piA, h);
+        } else {
+            u1_kick(p, 1.0, phi, pi, A, piA, w);
+            u1_drift_a(p, 1.0, phi, pi, A, piA, h);
         }
         c->lf_stag = dir;
     }
-    c->t += (double)ns * h;
-    c->a = 1.0;
-    c->b = 0.0;
+    c->t = t_start + (double)ns * h;
+    if (p->expansion == ORC_FIXED) {
+        u1_fixed_ab(p, c->t, &c->a, &c->b);
+    } else if (p->expansion == ORC_NONE) {
+        c->a = 1.0;
+        c->b = 0.0;
+    }
     return 0;
 }
 
@@ -1216,7 +1342,13 @@ int orc_u1_lf_sync(const orc_u1_params *p, double *const *phi, double *const *pi
                    double *const *A, double *const *piA, orc_clock *c)
 {
     if (c->lf_stag == 0) return 0;
-    u1_kick(p, phi, pi, A, piA, 0.5 * c->lf_stag * p->dt);
+    double w = 0.5 * c->lf_stag * p->dt;
+    if (p->expansion == ORC_SELF) {
+        double E[12];
+        u1_energy_plain(p, c->a, phi, pi, A, piA, E);
+        c->b += w * u1_kernel_a(p, c->a, E);
+    }
+    u1_kick(p, c->a, phi, pi, A, piA, w);
     c->lf_stag = 0;
     return 0;
 }
@@ -2013,32 +2145,48 @@ int orc_su2_run_vv(const orc_su2_params *p, double *const *phi, double *const *p
     return 0;
 }
 
-static void u1_drift(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
-                     double *const *piA, double h)
+/* One second-order map of size h from time t (reading R15; with expansion
+ * readings R1 and R3): kick(h/2) at a_n, [b kick with E_n, a drift], drift with
+ * the midpoint a, kick(h/2) at a_{n+1}, [energies, b kick]. */
+static void u1_vv2(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
+                   double *const *piA, orc_clock *c, double t, double h)
 {
-    size_t V = vol(p->N);
-    #pragma omp parallel for schedule(static)
-    for (size_t n = 0; n < V; ++n) {
-        phi[0][n] += h * pi[0][n];
-        phi[1][n] += h * pi[1][n];
-        for (int i = 0; i < 3; ++i) A[i][n] += h * piA[i][n];
+    if (p->expansion == ORC_SELF) {
+        double E[12];
+        u1_energy_plain(p, c->a, phi, pi, A, piA, E);
+        u1_kick(p, c->a, phi, pi, A, piA, 0.5 * h);
+        c->b += 0.5 * h * u1_kernel_a(p, c->a, E);
+        double a1 = c->a + h * c->b;
+        u1_drift_a(p, 0.5 * (c->a + a1), phi, pi, A, piA, h);
+        c->a = a1;
+        u1_kick(p, c->a, phi, pi, A, piA, 0.5 * h);
+        u1_energy_plain(p, c->a, phi, pi, A, piA, E);
+        c->b += 0.5 * h * u1_kernel_a(p, c->a, E);
+        return;
     }
+    double a0 = 1.0, am = 1.0, a1 = 1.0, b;
+    if (p->expansion == ORC_FIXED) {
+        u1_fixed_ab(p, t, &a0, &b);
+        u1_fixed_ab(p, t + 0.5 * h, &am, &b);
+        u1_fixed_ab(p, t + h, &a1, &b);
+    }
+    u1_kick(p, a0, phi, pi, A, piA, 0.5 * h);
+    u1_drift_a(p, am, phi, pi, A, piA, h);
+    u1_kick(p, a1, phi, pi, A, piA, 0.5 * h);
 }
 
 static void u1_vv(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
-                  double *const *piA, int order, double h)
+                  double *const *piA, orc_clock *c, int order, double t, double h)
 {
     if (order <= 2) {
-        u1_kick(p, phi, pi, A, piA, 0.5 * h);
-        u1_drift(p, phi, pi, A, piA, h);
-        u1_kick(p, phi, pi, A, piA, 0.5 * h);
+        u1_vv2(p, phi, pi, A, piA, c, t, h);
         return;
     }
-    double c = pow(2.0, 1.0 / (double)(order - 1));
-    double x1 = 1.0 / (2.0 - c), x0 = -c / (2.0 - c);
-    u1_vv(p, phi, pi, A, piA, order - 2, x1 * h);
-    u1_vv(p, phi, pi, A, piA, order - 2, x0 * h);
-    u1_vv(p, phi, pi, A, piA, order - 2, x1 * h);
+    double cc = pow(2.0, 1.0 / (double)(order - 1));
+    double x1 = 1.0 / (2.0 - cc), x0 = -cc / (2.0 - cc);
+    u1_vv(p, phi, pi, A, piA, c, order - 2, t, x1 * h);
+    u1_vv(p, phi, pi, A, piA, c, order - 2, t + x1 * h, x0 * h);
+    u1_vv(p, phi, pi, A, piA, c, order - 2, t + x1 * h + x0 * h, x1 * h);
 }
 
 int orc_u1_run_vv(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
@@ -2047,7 +2195,9 @@ int orc_u1_run_vv(const orc_u1_params *p, double *const *phi, double *const *pi,
     if (c->lf_stag != 0) return -3;
     double h = nsteps >= 0 ? p->dt : -p->dt;
     long ns = nsteps >= 0 ? nsteps : -nsteps;
-    for (long k = 0; k < ns; ++k) u1_vv(p, phi, pi, A, piA, order, h);
-    c->t += (double)ns * h;
+    double t_start = c->t;
+    for (long k = 0; k < ns; ++k) u1_vv(p, phi, pi, A, piA, c, order, t_start + (double)k * h, h);
+    c->t = t_start + (double)ns * h;
+    if (p->expansion == ORC_FIXED) u1_fixed_ab(p, c->t, &c->a, &c->b);
     return 0;
 }
