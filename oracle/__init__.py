@@ -102,6 +102,8 @@ def lib():
         L.orc_u1_hubble_b0.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.c_double, dp]
         L.orc_su2_gauss_init.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
         L.orc_u1_gauss_init.argtypes = [C.POINTER(U1Params), pp, pp, pp, dp]
+        L.orc_vv_stages.argtypes = [C.c_int, dp]
+        L.orc_vv_stages.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = C.c_int
         _lib = L
@@ -265,6 +267,17 @@ def yoshida4():
     w1, w0 = C.c_double(), C.c_double()
     lib().orc_yoshida4(C.byref(w1), C.byref(w0))
     return w1.value, w0.value
+
+
+def vv_stages(order):
+    """Weights (in units of h) of the second-order maps of one velocity-Verlet
+    step of the given order (2 ... 10)."""
+    w = np.zeros(45)
+    n = lib().orc_vv_stages(int(order), _dp(w))
+    if n <= 0:
+        raise RuntimeError(f"no velocity-Verlet step of order {order}")
+    return w[:n].copy()
+
 
 def triple_jump(n):
     """Weights (x1, x0) raising a symmetric map of order n to order n + 2."""

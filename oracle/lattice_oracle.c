@@ -23,10 +23,10 @@
  *       integer times.
  *   R2  4th order velocity-Verlet = Yoshida's triple-jump composition of the
  *       whole second-order map (Yoshida 1990, Phys. Lett. A 150, 262).  The
- *       6th, 8th and 10th orders repeat the same construction on the map one
- *       order below: S_{n+2}(h) = S_n(x1 h) S_n(x0 h) S_n(x1 h) with
- *       x1 = 1/(2 - c), x0 = -c/(2 - c), c = 2^{1/(n+1)} (the recursive triple
- *       jump of the same paper), 3, 9, 27 and 81 second-order maps per step.
+ *       6th and 8th orders are the symmetric compositions of the same paper
+ *       with 7 maps (solution A) and 15 maps (solution D); the 10th order is
+ *       the triple jump S_10(h) = S_8(x1 h) S_8(x0 h) S_8(x1 h), x1 = 1/(2 - c),
+ *       x0 = -c/(2 - c), c = 2^{1/9}: 3, 7, 15 and 45 second-order maps per step.
  *   R3  fixed background: every kick uses a(t) at the kick time and every
  *       drift uses a(t) at the midpoint time of the drift (closed form of
  *       eq. ScaleFactorPowerLaw).
@@ -64,7 +64,7 @@
  *       of eq. GaugeCurrentFluc would leave a residual of order dx^2).
  *   R15 gauge models with the velocity-Verlet family: the second-order map
  *       kick(h/2) drift(h) kick(h/2) of the whole U(1) or SU(2) system, and
- *       the triple jump of R2 above it; the kicks and drifts are those of the
+ *       the compositions of R2 above it; the kicks and drifts are those of the
  *       leapfrog (the paper applies its VV evolvers to gauge theories too).
  */
 #include <math.h>
@@ -399,20 +399,66 @@ void orc_triple_jump(int n, double *x1, double *x0)
     *x0 = -c / (2.0 - c);
 }
 
+/* Stage weights of one velocity-Verlet step of even order `order` (reading R2):
+ * the step is the product of second-order maps of sizes w[0] h, w[1] h, ...
+ *   order 2: one map;
+ *   order 4: Yoshida's triple jump (w1, w0, w1);
+ *   order 6: Yoshida (1990, Phys. Lett. A 150, 262) solution A, seven maps
+ *            w3 w2 w1 w0 w1 w2 w3 with w0 = 1 - 2(w1 + w2 + w3);
+ *   order 8: the same paper's solution D, fifteen maps w7 ... w1 w0 w1 ... w7;
+ *   order 10: the triple jump of the order-8 step (x1, x0, x1 with
+ *            c = 2^{1/9}), 45 maps.
+ * Returns the number of maps (at most 45). */
+int orc_vv_stages(int order, double *w)
+{
+    static const double yA[3] = {-1.17767998417887, 0.235573213359357, 0.784513610477560};
+    static const double yD[7] = {0.102799849391985, -1.96061023297549, 1.93813913762276, -0.158240635368243,
+                                 -1.44485223686048, 0.253693336566229, 0.914844246229740};
+    if (order == 2) {
+        w[0] = 1.0;
+        return 1;
+    }
+    if (order == 4) {
+        orc_triple_jump(2, &w[0], &w[1]);
+        w[2] = w[0];
+        return 3;
+    }
+    if (order == 6 || order == 8) {
+        const int m = order == 6 ? 3 : 7;
+        const double *y = order == 6 ? yA : yD;
+        double sum = 0.0;
+        for (int i = 0; i < m; ++i) sum += y[i];
+        for (int i = 0; i < m; ++i) {
+            w[i] = y[m - 1 - i];          /* outermost first */
+            w[2 * m - i] = y[m - 1 - i];
+        }
+        w[m] = 1.0 - 2.0 * sum;
+        return 2 * m + 1;
+    }
+    if (order == 10) {
+        double inner[15], x1, x0;
+        const int n = orc_vv_stages(8, inner);
+        orc_triple_jump(8, &x1, &x0);
+        for (int i = 0; i < n; ++i) {
+            w[i] = x1 * inner[i];
+            w[n + i] = x0 * inner[i];
+            w[2 * n + i] = x1 * inner[i];
+        }
+        return 3 * n;
+    }
+    return 0;
+}
+
 /* One step of the velocity-Verlet map of even order `order` (>= 2) of size h
- * starting at time t: order 2 is vv2, higher orders the triple jump of the
- * map two orders below. */
+ * starting at time t: the second-order maps of orc_vv_stages in order. */
 static void vv_order(stepper *st, int order, double t, double h)
 {
-    if (order == 2) {
-        vv2(st, t, h);
-        return;
+    double w[45];
+    const int n = orc_vv_stages(order, w);
+    for (int i = 0; i < n; ++i) {
+        vv2(st, t, w[i] * h);
+        t += w[i] * h;
     }
-    double x1, x0;
-    orc_triple_jump(order - 2, &x1, &x0);
-    vv_order(st, order - 2, t, x1 * h);
-    vv_order(st, order - 2, t + x1 * h, x0 * h);
-    vv_order(st, order - 2, t + x1 * h + x0 * h, x1 * h);
 }
 
 /* Evolve |nsteps| steps (backward in time if nsteps < 0).
@@ -2111,26 +2157,21 @@ int orc_u1_gauss_init(const orc_u1_params *p, double *const *phi, double *const 
 /* ------------------------------------------------------------------ */
 /* Velocity-Verlet family for the gauge models (sec. 4.3 evolvers VV2..VV10 */
 /* applied to the U(1) and SU(2) systems at a = 1; readings R2, R15): the   */
-/* second-order map kick(h/2) drift(h) kick(h/2), and the triple jump of    */
-/* the map one order below, S_{m}(h) = S_{m-2}(x1 h) S_{m-2}(x0 h)          */
-/* S_{m-2}(x1 h), x1 = 1/(2 - c), x0 = -c/(2 - c), c = 2^{1/(m-1)}.          */
+/* second-order map kick(h/2) drift(h) kick(h/2), composed with the       */
+/* weights of orc_vv_stages (reading R2).                                   */
 /* Plain composition: every half kick is applied on its own.               */
 /* ------------------------------------------------------------------ */
 
 static void su2_vv(const orc_su2_params *p, double *const *phi, double *const *pi, double *const *U,
                    double *const *E, int order, double h)
 {
-    if (order <= 2) {
-        su2_kick(p, phi, pi, U, E, 0.5 * h);
-        su2_drift(p, phi, pi, U, E, h);
-        su2_kick(p, phi, pi, U, E, 0.5 * h);
-        return;
+    double w[45];
+    const int n = orc_vv_stages(order, w);
+    for (int i = 0; i < n; ++i) {
+        su2_kick(p, phi, pi, U, E, 0.5 * w[i] * h);
+        su2_drift(p, phi, pi, U, E, w[i] * h);
+        su2_kick(p, phi, pi, U, E, 0.5 * w[i] * h);
     }
-    double c = pow(2.0, 1.0 / (double)(order - 1));
-    double x1 = 1.0 / (2.0 - c), x0 = -c / (2.0 - c);
-    su2_vv(p, phi, pi, U, E, order - 2, x1 * h);
-    su2_vv(p, phi, pi, U, E, order - 2, x0 * h);
-    su2_vv(p, phi, pi, U, E, order - 2, x1 * h);
 }
 
 /* order in {2, 4, 6, 8, 10}; momenta at integer time (lf_stag = 0) */
@@ -2178,15 +2219,12 @@ static void u1_vv2(const orc_u1_params *p, double *const *phi, double *const *pi
 static void u1_vv(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
                   double *const *piA, orc_clock *c, int order, double t, double h)
 {
-    if (order <= 2) {
-        u1_vv2(p, phi, pi, A, piA, c, t, h);
-        return;
+    double w[45];
+    const int n = orc_vv_stages(order, w);
+    for (int i = 0; i < n; ++i) {
+        u1_vv2(p, phi, pi, A, piA, c, t, w[i] * h);
+        t += w[i] * h;
     }
-    double cc = pow(2.0, 1.0 / (double)(order - 1));
-    double x1 = 1.0 / (2.0 - cc), x0 = -cc / (2.0 - cc);
-    u1_vv(p, phi, pi, A, piA, c, order - 2, t, x1 * h);
-    u1_vv(p, phi, pi, A, piA, c, order - 2, t + x1 * h, x0 * h);
-    u1_vv(p, phi, pi, A, piA, c, order - 2, t + x1 * h + x0 * h, x1 * h);
 }
 
 int orc_u1_run_vv(const orc_u1_params *p, double *const *phi, double *const *pi, double *const *A,
