@@ -29,6 +29,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def stored_traffic(kind: str, per_launch_alg: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -122,11 +133,13 @@ def run_extras(args, log, only=None):
         lat.close()
         log(f"[bench] adjoint: reverse/forward {r['reverse_ms'] / r['forward_ms']:.2f}, per pass {aus / fus:.2f}")
         # the same workload with the self-consistent expansion (kappa^2 = 0.25):
-        # step-by-step forward and reverse
+        # the forward sweep as one call per checkpoint segment, the reverse as
+        # one fused pass per time point (a short call first builds the graphs)
         tp = [torch.tensor(f.reshape(-1), device=dev) for f in phi]
         tq = [torch.tensor(f.reshape(-1), device=dev) for f in pi]
         ls = Lattice(tp, tq, N=wl.N, dx=wl.dx, dt=wl.dt, integrator="vv2", expansion="self", potential="phi4_chi2",
                      lam=wl.lam, q=wl.q, kappa2=0.25)
+        ls.grad(50)
         rs = ls.grad(wl.steps)
         res["adjoint_self"] = {"workload": wl.name + " self-consistent expansion", "steps": wl.steps,
                                "value": rs["value"], "dO_dq": rs["dO_dq"], "dO_da0": rs["dO_da0"],
@@ -259,7 +272,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--main-only", action="store_true", help="only the 256^3 workload (for profiling)")
     ap.add_argument("--only", choices=["adjoint", "u1", "su2", "batch", "lphi4_32"],
                     help="only this other workload; prints its JSON object (for profiling)")
@@ -326,13 +339,17 @@ def main():
     e = lat.energy()
     log(f"[bench] {n_launch} '{kind}' launches, mean {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s; "
         f"a={e['a']:.6f} hubble_res={e['hubble_res']:.2e}")
-    # measurement pass (energies and Hubble residual; read-only over phi, pi)
-    lat.stats(reset=True)
-    lat.profile(True)
+    # measurement pass (energies and Hubble residual; read-only over phi, pi).
+    # After a step the context reports the sums its last pass reduced, so the
+    # pass is timed on a second context over the same arrays.
+    lm = Lattice(tp, tq, stream=stream, **kw)
+    lm.stats(reset=True)
+    lm.profile(True)
     for _ in range(5):
-        lat.energy()
-    se = lat.stats(reset=True)
-    lat.profile(False)
+        lm.energy()
+    se = lm.stats(reset=True)
+    lm.profile(False)
+    lm.close()
     e_us = 1e3 * se["kernel_ms"]["energy"] / max(se["launches"]["energy"], 1)
     energy_pass = {"mean_launch_us": e_us, "alg_bytes_per_launch": N ** 3 * 2 * 2 * esize,
                    "achieved_GBs_alg": N ** 3 * 2 * 2 * esize / (e_us * 1e-6) / 1e9}
@@ -383,15 +400,28 @@ def main():
         m = oracle.ScalarModel(N=N, dx=wl.dx, dt=wl.dt, nfields=2, potential=oracle.PHI4_CHI2,
                                expansion=oracle.SELF, integrator=oracle.VV4, lam=wl.lam, q=wl.q,
                                alpha=wl.alpha, kappa2=wl.kappa2, a0=wl.a0)
-        log(f"[bench] oracle on the host: {args.cpu_steps} VV4 steps at {N}^3")
-        ost = oracle.ScalarState(m, phi, pi)
-        c0 = time.perf_counter()
-        ost.run(args.cpu_steps)
-        cwall = time.perf_counter() - c0
-        cpu = {"value": N ** 3 * 3 * args.cpu_steps / cwall, "unit": "site-updates/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} VV4 steps ({3 * args.cpu_steps} stages) of the same {N}^3 "
-                         f"two-field self-consistent workload, single-threaded plain C oracle, {cwall:.1f} s"}
+        # the oracle on one core, then on the host's cores (OpenMP over z planes
+        # in its per-site loops; its volume sums stay serial)
+        threads_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        before = oracle.set_threads(0)
+        timing = {}
+        for nt in (1, threads_all):
+            used = oracle.set_threads(nt)
+            log(f"[bench] oracle on the host, {used} thread(s): {args.cpu_steps} VV4 steps at {N}^3")
+            ost = oracle.ScalarState(m, phi, pi)
+            c0 = time.perf_counter()
+            ost.run(args.cpu_steps)
+            timing[nt] = (time.perf_counter() - c0, used)
+        oracle.set_threads(before)
+        cwall, used = timing[threads_all]
+        w1, _ = timing[1]
+        sample = (f"{args.cpu_steps} VV4 steps ({3 * args.cpu_steps} stages) of the same {N}^3 two-field "
+                  f"self-consistent workload, plain C oracle")
+        cpu = {"value": N ** 3 * 3 * args.cpu_steps / cwall, "unit": "site-updates/s", "cores": used,
+               "kind": "oracle", "sample": f"{sample}, {used} threads, {cwall:.1f} s",
+               "one_core": {"value": N ** 3 * 3 * args.cpu_steps / w1, "cores": 1,
+                            "sample": f"{sample}, 1 thread, {w1:.1f} s"},
+               "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()}}
 
     out = {
         "metric": METRIC,

@@ -60,12 +60,12 @@ enum lat_integrator {
     LAT_LF = 0,    /* staggered leapfrog, 2nd order: kick then drift, momenta half a step behind */
     LAT_VV2 = 1,   /* velocity-Verlet, 2nd order, fields and momenta at the same time */
     LAT_VV4 = 2,   /* 4th order: Yoshida triple-jump composition of three VV2 maps */
-    LAT_VV6 = 3,   /* 6th order: triple jump of VV4 maps, 9 VV2 maps (9 kick points) per step */
-    LAT_VV8 = 4,   /* 8th order: triple jump of VV6 maps, 27 VV2 maps per step */
-    LAT_VV10 = 5   /* 10th order: triple jump of VV8 maps, 81 VV2 maps per step.  The VV
-                      family of sec. 4.3 (evolver VV2..VV10); each level S_{n+2}(h) =
-                      S_n(x1 h) S_n(x0 h) S_n(x1 h), x1 = 1/(2 - c), x0 = -c/(2 - c),
-                      c = 2^{1/(n+1)} (Yoshida 1990, Phys. Lett. A 150, 262) */
+    LAT_VV6 = 3,   /* 6th order: Yoshida's solution A, 7 VV2 maps (7 kick points) per step */
+    LAT_VV8 = 4,   /* 8th order: Yoshida's solution D, 15 VV2 maps per step */
+    LAT_VV10 = 5   /* 10th order: triple jump of VV8 maps, S(x1 h) S(x0 h) S(x1 h) with
+                      x1 = 1/(2 - c), x0 = -c/(2 - c), c = 2^{1/9}: 45 VV2 maps per step.
+                      The VV family of sec. 4.3 (evolver VV2..VV10); the compositions are
+                      those of Yoshida 1990, Phys. Lett. A 150, 262 (VV4: c = 2^{1/3}) */
 };
 
 /* background (sec. 4.3 "expansion", "fixedBackground"; eqs. NewFriedmannEQsII, ScaleFactorPowerLaw) */
@@ -91,9 +91,10 @@ enum lat_potential {
                               P_ij = U_i U_j(n+i) U_i(n+j)^dag U_j^dag (the toolkit plaquette);
                               kicks are minus its derivative, the link drift is
                               U <- exp(-i dt g dx E^a T_a) U.  Provided with LF and the VV
-                              family (VV2 = kick(h/2) drift(h) kick(h/2), VV4..VV10 its triple
-                              jumps), a = 1 and float64; (f_star/omega_star)^2 = 1 (kappa_g is
-                              not used).  The U(1) model has the same integrators. */
+                              family (VV2 = kick(h/2) drift(h) kick(h/2), VV4..VV10 its symmetric
+                              compositions), a = 1 and float64; (f_star/omega_star)^2 = 1 (kappa_g is
+                              not used).  The U(1) model has the same integrators and every
+                              expansion (see lattice_init). */
 };
 
 enum lat_precision {
@@ -180,9 +181,17 @@ typedef struct lat_ctx lat_ctx;
  * after the momentum kick, the half kicks that leave or reach integer time
  * that of the momenta at the half step); a staggered start (lf_staggered != 0)
  * then needs b0 at the half step.
- * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (the U(1) and SU(2)
- * models with expansion or in float32), LAT_ENODEV, LAT_ENOMEM,
- * LAT_EHIP.  On error *ctx is set to NULL. */
+ * The U(1) model takes every expansion: in an expanding background its kicks
+ * scale the covariant Laplacian and the current by a^{1+alpha}, the potential
+ * force by a^{3+alpha} and the magnetic force by a^{alpha-1}, its drifts are
+ * a^{alpha-3} pi and a^{alpha-1} pi_A, its energies are divided by a^6, a^2,
+ * a^4 (kinetic, gradient, gauge), and the scale-factor kernel adds
+ * (alpha - 1)(E_K^A + E_G^A) (sec. 5.5.2); with self-consistent expansion the
+ * kicks, energy sums and drifts run as separate passes with the scale factor
+ * updated on the device between them.
+ * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (the SU(2) model with expansion, the
+ * gauge models in float32), LAT_ENODEV, LAT_ENOMEM, LAT_EHIP.  On error *ctx
+ * is set to NULL. */
 lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
 
 /* Create one context for a batch of n_real independent lattices that share p
@@ -282,7 +291,12 @@ lat_status lattice_sync(lat_ctx *ctx);
 /* Volume-averaged energies, Hubble and Gauss residuals of the current state
  * (sec. 4.4 outputs; sec. 5.4 Gauss measure).  LF momenta (and b with
  * LAT_EXP_SELF) are synchronised on the fly without writing them back.
- * Synchronises the stream; out is host memory. */
+ * Right after lattice_step with a VV integrator and LAT_EXP_SELF the volume
+ * sums are those the step's last pass reduced for the scale-factor update
+ * (the same state, at integer time), so no pass of its own runs; in that mode
+ * the state is (fields, a, b) as the library left it, and a caller that
+ * writes the field arrays between calls starts from a state a and b do not
+ * follow.  Synchronises the stream; out is host memory. */
 lat_status lattice_energy(lat_ctx *ctx, lat_energies *out);
 
 /* Allocation-free variant of lattice_energy, for callers that cannot allocate
@@ -351,12 +365,17 @@ typedef struct lat_grad_out {
  * fixed background the steps run from the context's current time, kicks use
  * a^{1+alpha} and a^{3+alpha} at the kick time, drifts a^{alpha-3} at the
  * midpoint, and the energies of O are those at a(T).  With the self-consistent
- * expansion the forward sweep is the library's own step; a and a' at the
- * start are independent inputs (dO_da0, dO_db0; a caller whose a' comes from
- * the Hubble constraint adds dO_db0 times its derivative), and the scale
- * factor, a', time and step count are restored on return.  The
- * library allocates the checkpoints (T/stride + 1 copies of the state) and the
- * adjoint arrays on first use and keeps them until lattice_destroy.
+ * expansion the forward sweep is the library's own step, one call per
+ * checkpoint segment, recording a and a' of every step on the device; the
+ * reverse sweep re-runs each segment from its checkpoint with those scale
+ * factors and runs one fused adjoint pass per time point, the adjoints of a
+ * and a' carried on the device.  a and a' at the start are independent inputs
+ * (dO_da0, dO_db0; a caller whose a' comes from the Hubble constraint adds
+ * dO_db0 times its derivative), and the scale factor, a', time and step count
+ * are restored on return.  The library allocates the checkpoints (T/stride + 1
+ * copies of the state), the adjoint arrays and, with the self-consistent
+ * expansion, the stride + 1 states of a segment on first use and keeps them
+ * until lattice_destroy.  N^3 must stay below 2^32 (LAT_EUNSUPPORTED).
  * LAT_OBS_SPECTRUM_BIN seeds the adjoint with dDelta(b)/dphi_s: the
  * unnormalised inverse transform of phi_s's spectrum kept on shell b, scaled
  * by 2 c_b (hipFFT float64 transforms; their buffers and plans are kept like

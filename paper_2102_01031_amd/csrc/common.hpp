@@ -21,7 +21,8 @@ struct PassCoef {
     double cL, cR;  // weights of the two half kicks of b at this point
     double t;       // time at this kick point
     double t_next;  // time at the next kick point
-    double pad;
+    double *traj;   // if set, the update at this point stores (a, b) here: a at the
+                    // point and b after its left half kick (integer time for VV2)
 };
 
 // Scale factor record on the device (self-consistent expansion) and the raw
@@ -32,6 +33,7 @@ struct ScaleRecord {
     double pad;
     double sums[kMaxQ];
     double maxes[4];
+    double w[8];    // U(1) pass weights written on the device (self-consistent expansion)
 };
 
 // kLastSelf: velocity-Verlet update of b and a (self_update); kLastSelfLF:

@@ -146,7 +146,8 @@ struct lat_ctx {
     int rows_vw = 1;     // whole-row kernel sites per lane and access (1, or 16-byte vectors)
     int rows_y_fastest = 0;   // whole-row kernel block order (see stage_rows.hpp)
     int rows_alternate = 0;   // whole-row kernel: alternate the z march direction pass by pass
-    int rows_lp = 0;          // whole-row kernel load policy (see launch_rows)
+    int rows_lp = 0;          // whole-row kernel store policy (see launch_rows)
+    int rows_split = 6;       // store policy 1: eighths of the march with non-temporal stores
     int zc = 0;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
     // launch statistics and optional event timing
@@ -170,6 +171,8 @@ struct lat_ctx {
     size_t self_seg_cap = 0;            // (in states)
     double *self_part = nullptr;        // its per-block partials and totals
     size_t self_part_cap = 0;
+    bool sums_fresh = false;            // sc->sums are those of the current state (see lattice_energy)
+    double *traj_rec = nullptr;         // set: velocity-Verlet passes store (a, b) of kick point p at traj_rec + 2 p
     double *self_traj = nullptr;        // a, a' of every step, scale records of the checkpoints, scalars
     size_t self_traj_cap = 0;           // (in doubles)
     // batch of independent lattices
@@ -332,8 +335,14 @@ void geometry_from_env(lat_ctx *c)
     // LATTICE_ROWS_ALT=0|1 overrides
     c->rows_alternate = c->N == 256 ? 1 : 0;
     if (const char *al = std::getenv("LATTICE_ROWS_ALT")) c->rows_alternate = std::atoi(al) != 0;
-    c->rows_lp = 0;
-    if (const char *lp = std::getenv("LATTICE_ROWS_NT")) c->rows_lp = std::min(5, std::max(0, std::atoi(lp)));
+    // store policy at N = 256 in float64: non-temporal stores over the first
+    // six eighths of the march, ordinary stores over the rest (196.5 against
+    // 207.7 us a pass; splits of 2 .. 7 eighths measured 1 .. 5 us slower).
+    // LATTICE_ROWS_STORES=0|1 and LATTICE_ROWS_SPLIT=0..8 override
+    c->rows_lp = (c->N == 256 && !c->f32) ? 1 : 0;
+    if (const char *lp = std::getenv("LATTICE_ROWS_STORES")) c->rows_lp = std::atoi(lp) != 0;
+    c->rows_split = 6;
+    if (const char *sp = std::getenv("LATTICE_ROWS_SPLIT")) c->rows_split = std::min(8, std::max(0, std::atoi(sp)));
     const char *s = std::getenv("LATTICE_TILE");
     if (s && std::strncmp(s, "rows", 4) == 0 && rows_ok(c->N)) {
         int ty = 8, z = 0;
@@ -430,10 +439,10 @@ hipError_t launch_rows_variant(int variant, const ScalarArgs<T> &a, int nb, hipS
 // vw > 1: 16-byte accesses (two float64 or four float32 sites per lane and
 // access), instantiated where the row holds a whole number of them per lane:
 // N = 128, 256 in float64, N = 256 in float32.
-// lp: cache policy of the row kernel (RowPolicy in stage_rows.hpp; 3 .. 5
-// vary it between the halves of the march), instantiated for the N = 256 defaults (float64 4-row blocks
-// two planes ahead, float32 4-row blocks four planes ahead with 16-byte
-// accesses); elsewhere loads are plain.
+// lp: store policy of the row kernel (RowPolicy in stage_rows.hpp; 1 streams
+// the first part of the march past the caches), instantiated for the N = 256
+// defaults (float64 4-row blocks two planes ahead, float32 4-row blocks four
+// planes ahead with 16-byte accesses); elsewhere policy 0.
 template <typename T, int NF>
 hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarArgs<T> &a, int nb, hipStream_t s,
                        int lp = 0)
@@ -441,23 +450,11 @@ hipError_t launch_rows(int N, int ty, int pf, int vw, int variant, const ScalarA
     const int xs = N / 64;
     constexpr int V = 16 / (int)sizeof(T);
     if constexpr (sizeof(T) == 8) {
-        if (lp != 0 && vw == 1 && pf == 2 && xs == 4 && ty == 4) {
-            switch (lp) {
-            case 3: return launch_rows_variant<T, NF, 4, 4, 2, 1, 3>(variant, a, nb, s);
-            case 4: return launch_rows_variant<T, NF, 4, 4, 2, 1, 4>(variant, a, nb, s);
-            case 5: return launch_rows_variant<T, NF, 4, 4, 2, 1, 5>(variant, a, nb, s);
-            default: break;
-            }
-        }
+        if (lp == 1 && vw == 1 && pf == 2 && xs == 4 && ty == 4)
+            return launch_rows_variant<T, NF, 4, 4, 2, 1, 1>(variant, a, nb, s);
     } else {
-        if (lp != 0 && vw > 1 && pf == 4 && xs == 4 && ty == 4) {
-            switch (lp) {
-            case 3: return launch_rows_variant<T, NF, 4, 4, 4, V, 3>(variant, a, nb, s);
-            case 4: return launch_rows_variant<T, NF, 4, 4, 4, V, 4>(variant, a, nb, s);
-            case 5: return launch_rows_variant<T, NF, 4, 4, 4, V, 5>(variant, a, nb, s);
-            default: break;
-            }
-        }
+        if (lp == 1 && vw > 1 && pf == 4 && xs == 4 && ty == 4)
+            return launch_rows_variant<T, NF, 4, 4, 4, V, 1>(variant, a, nb, s);
     }
     if (vw > 1 && xs % V == 0) {
         if (pf == 2 && xs == 4 && ty == 4) return launch_rows_variant<T, NF, 4, 4, 2, V>(variant, a, nb, s);
@@ -563,8 +560,21 @@ lat_status harvest_timing(lat_ctx *c)
     return LAT_OK;
 }
 
+// Deferred finalisation of a pass (see ScalarArgs): where its block sums go
+// and which earlier sums its prologue finalises.
+struct PassLink {
+    int defer = 0;
+    double *partials = nullptr;    // this pass's block sums (defer = 1)
+    const double *fin = nullptr;   // previous pass's block sums to finalise, or null
+    int fin_mode = kLastSelf;
+    const PassCoef *fin_coef = nullptr;
+    const ScaleRecord *fin_in = nullptr;
+    ScaleRecord *fin_out = nullptr;
+};
+
 template <typename T>
-lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream)
+lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream,
+                      const PassLink *lk = nullptr)
 {
     const VariantIO io = variant_io(variant);
     ScalarArgs<T> a{};
@@ -586,6 +596,7 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     // outputs go through the caches so that those planes are still there
     a.down = c->rows_alternate ? (pass_index & 1) : 0;
     a.cached_out = c->rows_alternate;
+    a.split = c->rows_split;
     a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
     a.lam = c->p.lambda;
     a.q = c->p.potential == LAT_PHI4_CHI2 ? c->p.q : 0.0;
@@ -598,6 +609,16 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     a.alpha = c->p.alpha;
     a.kappa2 = c->p.kappa2;
     a.inv_vol = 1.0 / (double)c->vol;
+    if (lk) {
+        a.defer = lk->defer;
+        if (lk->defer) a.partials = lk->partials;
+        a.fin = lk->fin;
+        a.fin_nb = c->nblocks;
+        a.fin_mode = lk->fin_mode;
+        a.fin_coef = lk->fin_coef;
+        a.fin_in = lk->fin_in;
+        a.fin_out = lk->fin_out;
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (c->profiling) {
         lat_status st = timing_begin(c, &ev0, &ev1);
@@ -625,10 +646,70 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     return LAT_OK;
 }
 
-lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream)
+lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream,
+                    const PassLink *lk = nullptr)
 {
-    return c->f32 ? run_pass_t<float>(c, variant, pass_index, last_mode, stream)
-                  : run_pass_t<double>(c, variant, pass_index, last_mode, stream);
+    return c->f32 ? run_pass_t<float>(c, variant, pass_index, last_mode, stream, lk)
+                  : run_pass_t<double>(c, variant, pass_index, last_mode, stream, lk);
+}
+
+// the deferred-finalisation chain of a call's passes 0 .. M (all reducing and
+// deferring except where the caller says): pass p >= 1 finalises pass p - 1
+// from the record R_{p-2} (the context's record for p = 1) into R_{p-1}; the
+// two block-sum buffers and the two spare records alternate by pass parity
+PassLink pass_link(lat_ctx *c, int64_t p, int mode, bool defer)
+{
+    PassLink lk;
+    double *buf[2] = {c->partials, c->partials + (size_t)c->nblocks * 8};
+    ScaleRecord *tmp[2] = {c->sc + 1, c->sc + 2};
+    lk.defer = defer ? 1 : 0;
+    lk.partials = buf[p & 1];
+    if (p >= 1) {
+        lk.fin = buf[(p - 1) & 1];
+        lk.fin_mode = mode;
+        lk.fin_coef = c->coef + (p - 1);
+        lk.fin_in = p == 1 ? c->sc : tmp[(p - 2) & 1];
+        lk.fin_out = tmp[(p - 1) & 1];
+    }
+    return lk;
+}
+
+// the finaliser after the last deferring pass M of a call: its sums, applied
+// to R_{M-1}, give the context's record
+lat_status finish_chain(lat_ctx *c, int64_t M, int mode, hipStream_t st)
+{
+    double *buf[2] = {c->partials, c->partials + (size_t)c->nblocks * 8};
+    const ScaleRecord *in = M == 0 ? c->sc : c->sc + 1 + ((M - 1) & 1);
+    const double iv = 1.0 / (double)c->vol, idx2 = 1.0 / (c->p.dx * c->p.dx);
+    const int NT = c->rows ? 64 * c->rows_ty : kTiles[c->tile].tx * kTiles[c->tile].ty;
+    const double *P = buf[M & 1];
+    PassCoef *Nx = c->coef + M + 1;
+    if (NT == 64) {
+        if (c->nf == 1)
+            hipLaunchKernelGGL((self_finish<64, 1>), dim3(1), dim3(64), 0, st, P, c->nblocks, mode, c->coef + M, in,
+                               c->sc, Nx, c->p.alpha, c->p.kappa2, iv, idx2);
+        else
+            hipLaunchKernelGGL((self_finish<64, 2>), dim3(1), dim3(64), 0, st, P, c->nblocks, mode, c->coef + M, in,
+                               c->sc, Nx, c->p.alpha, c->p.kappa2, iv, idx2);
+    } else if (NT == 256) {
+        if (c->nf == 1)
+            hipLaunchKernelGGL((self_finish<256, 1>), dim3(1), dim3(256), 0, st, P, c->nblocks, mode, c->coef + M, in,
+                               c->sc, Nx, c->p.alpha, c->p.kappa2, iv, idx2);
+        else
+            hipLaunchKernelGGL((self_finish<256, 2>), dim3(1), dim3(256), 0, st, P, c->nblocks, mode, c->coef + M, in,
+                               c->sc, Nx, c->p.alpha, c->p.kappa2, iv, idx2);
+    } else if (NT == 512) {
+        if (c->nf == 1)
+            hipLaunchKernelGGL((self_finish<512, 1>), dim3(1), dim3(512), 0, st, P, c->nblocks, mode, c->coef + M, in,
+                               c->sc, Nx, c->p.alpha, c->p.kappa2, iv, idx2);
+        else
+            hipLaunchKernelGGL((self_finish<512, 2>), dim3(1), dim3(512), 0, st, P, c->nblocks, mode, c->coef + M, in,
+                               c->sc, Nx, c->p.alpha, c->p.kappa2, iv, idx2);
+    } else {
+        return fail(c, LAT_EHIP, "unexpected block size for the finaliser");
+    }
+    HIPCHK(c, hipGetLastError());
+    return LAT_OK;
 }
 
 lat_status run_pass(lat_ctx *c, int variant, int pass_index, int last_mode)
@@ -755,6 +836,8 @@ lat_status reserve_coef(lat_ctx *c, size_t n)
 lat_status upload_coef(lat_ctx *c, size_t n)
 {
     const int k = c->ring_slot;
+    if (!c->traj_rec)
+        for (size_t i = 0; i < n; ++i) c->coef_host[i].traj = nullptr;
     HIPCHK(c, hipMemcpyAsync(c->coef, c->coef_host, n * sizeof(PassCoef), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(c->ring_ev[k], c->stream));
     c->ring_pending[k] = true;
@@ -831,9 +914,15 @@ lat_status step_lf_self(lat_ctx *c, int64_t ns, int dir)
         HIPCHK(c, hipGetLastError());
         for (int64_t k = 0; k <= ns; ++k) {
             const int v = k == ns ? kDriftKick : (k == 0 ? kKickOnlyRed : kDriftKickRed);
-            lat_status r = run_pass(c, v, (int)k, k == ns ? kLastStore : kLastSelfLF, st);
+            // the drift-only pass finalises the last kick's sums and reduces nothing
+            const PassLink lk = pass_link(c, k, kLastSelfLF, k < ns);
+            lat_status r = run_pass(c, v, (int)k, k == ns ? kLastStore : kLastSelfLF, st, &lk);
             if (r != LAT_OK) return r;
         }
+        // the record the drift-only pass wrote is the context's
+        hipLaunchKernelGGL(record_copy, dim3(1), dim3(64), 0, st, (const ScaleRecord *)(c->sc + 1 + ((ns - 1) & 1)),
+                           c->sc);
+        HIPCHK(c, hipGetLastError());
         return LAT_OK;
     });
     if (s != LAT_OK) return s;
@@ -878,23 +967,44 @@ lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
 }
 
 // Sub-step weights (in units of h) of one velocity-Verlet step of the
-// context's order: VV2 is {1}; each higher order is the triple jump of the
-// order below, S_{n+2}(h) = S_n(x1 h) S_n(x0 h) S_n(x1 h) with x1 = 1/(2 - c),
-// x0 = -c/(2 - c), c = 2^{1/(n+1)} (sec. 4.3 VV family; Yoshida 1990).
+// context's order, as symmetric products of VV2 maps (sec. 4.3 VV family):
+//   VV2   {1}
+//   VV4   triple jump S(x1 h) S(x0 h) S(x1 h), x1 = 1/(2 - 2^{1/3}), x0 = 1 - 2 x1
+//   VV6   Yoshida (1990) solution A, 7 maps: y3 y2 y1 y0 y1 y2 y3
+//   VV8   Yoshida (1990) solution D, 15 maps: y7 ... y1 y0 y1 ... y7
+//   VV10  triple jump of VV8 with c = 2^{1/9}: 45 maps
+// where y0 = 1 - 2 (y1 + ... + ym) makes the weights sum to one.
 std::vector<double> vv_weights(int integrator)
 {
-    std::vector<double> w{1.0};
-    const int order = integrator == LAT_VV2 ? 2 : 2 * integrator;   // VV4: 4 ... VV10: 10
-    for (int n = 2; n < order; n += 2) {
-        const double cc = n == 2 ? std::cbrt(2.0) : std::pow(2.0, 1.0 / (double)(n + 1));
+    static const double solA[3] = {-1.17767998417887, 0.235573213359357, 0.784513610477560};
+    static const double solD[7] = {0.102799849391985, -1.96061023297549, 1.93813913762276,
+                                   -0.158240635368243, -1.44485223686048, 0.253693336566229,
+                                   0.914844246229740};
+    auto jump = [](const std::vector<double> &inner, double cc) {
         const double x1 = 1.0 / (2.0 - cc), x0 = -cc / (2.0 - cc);
-        std::vector<double> next;
-        next.reserve(3 * w.size());
+        std::vector<double> out;
+        out.reserve(3 * inner.size());
         for (double x : {x1, x0, x1})
-            for (double v : w) next.push_back(x * v);
-        w.swap(next);
+            for (double v : inner) out.push_back(x * v);
+        return out;
+    };
+    auto palindrome = [](const double *y, int m) {
+        double tot = 0.0;
+        for (int i = 0; i < m; ++i) tot += y[i];
+        std::vector<double> out;
+        out.reserve(2 * m + 1);
+        for (int i = m - 1; i >= 0; --i) out.push_back(y[i]);
+        out.push_back(1.0 - 2.0 * tot);
+        for (int i = 0; i < m; ++i) out.push_back(y[i]);
+        return out;
+    };
+    switch (integrator) {
+    case LAT_VV4: return jump({1.0}, std::cbrt(2.0));
+    case LAT_VV6: return palindrome(solA, 3);
+    case LAT_VV8: return palindrome(solD, 7);
+    case LAT_VV10: return jump(palindrome(solD, 7), std::pow(2.0, 1.0 / 9.0));
+    default: return {1.0};
     }
-    return w;
 }
 
 lat_status step_vv(lat_ctx *c, int64_t ns, int dir)
@@ -929,6 +1039,7 @@ lat_status step_vv(lat_ctx *c, int64_t ns, int dir)
         P.t = ts(p);
         P.t_next = p < M ? ts(p + 1) : ts(M);
         P.dend = 0.0;
+        P.traj = c->traj_rec ? c->traj_rec + 2 * p : nullptr;
         if (!self) {
             const double a = scale_at(c, P.t);
             P.ka1 = std::pow(a, 1.0 + al);
@@ -945,10 +1056,11 @@ lat_status step_vv(lat_ctx *c, int64_t ns, int dir)
         }
         for (int64_t p = 0; p <= M; ++p) {
             const int v = p == 0 ? (self ? kKickOnlyRed : kKickOnly) : (self ? kDriftKickRed : kDriftKick);
-            lat_status r = run_pass(c, v, (int)p, mode, st);
+            const PassLink lk = self ? pass_link(c, p, kLastSelf, true) : PassLink{};
+            lat_status r = run_pass(c, v, (int)p, mode, st, self ? &lk : nullptr);
             if (r != LAT_OK) return r;
         }
-        return LAT_OK;
+        return self ? finish_chain(c, M, kLastSelf, st) : LAT_OK;
     });
     if (s != LAT_OK) return s;
     c->t = t_start + (double)ns * h;
@@ -1011,8 +1123,6 @@ lat_status validate(const lat_params *p, const lat_fields *f)
             return fail(nullptr, LAT_EINVAL, "misaligned field pointer");
     }
     if (p->potential == LAT_ABELIAN_HIGGS) {
-        if (p->expansion != LAT_EXP_NONE)
-            return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model is provided at a = 1");
         if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the U(1) model runs in float64");
         if (!(p->e_charge != 0.0) || !(p->kappa_g > 0.0)) return fail(nullptr, LAT_EINVAL, "bad U(1) couplings");
         for (int i = 0; i < 3; ++i) {
@@ -1236,7 +1346,8 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     }
     if (hipMalloc(&c->partials, c->partial_cap * sizeof(double)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&c->ticket, 64) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
-    if (hipMalloc(&c->sc, sizeof(ScaleRecord)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
+    // the record, then two records for the deferred updates inside a call
+    if (hipMalloc(&c->sc, 3 * sizeof(ScaleRecord)) != hipSuccess) return bail(LAT_ENOMEM, "scratch allocation failed");
     if (hipHostMalloc((void **)&c->sc_host, sizeof(ScaleRecord), hipHostMallocDefault) != hipSuccess)
         return bail(LAT_ENOMEM, "pinned allocation failed");
     for (auto &e : c->ring_ev)
@@ -1258,7 +1369,19 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return bail(LAT_EHIP, "upload failed");
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
-    if (p->expansion == LAT_EXP_SELF && std::isnan(p->b0)) {
+    if (p->expansion == LAT_EXP_SELF && std::isnan(p->b0) && c->u1) {
+        // Hubble constraint (eq. FriedmannHubble) with the U(1) energies at a0
+        lat_energies e{};
+        if (u1_energy(c, &e) != LAT_OK) return bail(LAT_EHIP, c->err);
+        const double rhs = std::pow(a, 2.0 * p->alpha + 2.0) * p->kappa2 * e.rho / 3.0;
+        if (!(rhs >= 0.0)) return bail(LAT_EINVAL, "negative energy: Hubble constraint has no root");
+        c->sc_host->a = a;
+        c->sc_host->b = std::sqrt(rhs);
+        c->sc_host->t = p->t0;
+        if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return bail(LAT_EHIP, "upload failed");
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
+    } else if (p->expansion == LAT_EXP_SELF && std::isnan(p->b0)) {
         // Hubble constraint (eq. NewFriedmannEQsI): b0^2 = a0^{2 alpha + 2} kappa2 rho / 3
         if (energy_sums(c, 0.0) != LAT_OK) return bail(LAT_EHIP, c->err);
         const double *S = c->sc_host->sums;
@@ -1280,7 +1403,7 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
             return bail(LAT_EHIP, "upload failed");
         if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
     }
-    if (p->expansion == LAT_EXP_SELF && p->integrator == LAT_LF && p->lf_staggered != 0) {
+    if (p->expansion == LAT_EXP_SELF && p->integrator == LAT_LF && p->lf_staggered != 0 && !c->u1) {
         // a staggered start: the next kick's b update needs the sums of the
         // stored half-step momenta squared (reading A3)
         if (energy_sums(c, 0.0) != LAT_OK) return bail(LAT_EHIP, c->err);
@@ -1311,6 +1434,7 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
     // tables, pinned staging and captured graphs stay bounded whatever the step
     // count; the result is bitwise that of the same steps issued as those
     // shorter calls.
+    c->sums_fresh = false;
     const int64_t per = c->p.integrator == LAT_LF ? 1 : (int64_t)vv_weights(c->p.integrator).size();
     const int64_t cap = std::max<int64_t>(1, kChunkPasses / per);
     const int64_t nchunks = (ns + cap - 1) / cap;
@@ -1328,6 +1452,9 @@ lat_status lattice_step(lat_ctx *c, int64_t nsteps)
         if ((s = settle(c)) != LAT_OK) return s;
         c->step += dir * n;
     }
+    // velocity-Verlet with self-consistent expansion: the call's last pass
+    // reduced the energy sums of the state it leaves (momenta at integer time)
+    c->sums_fresh = c->p.integrator != LAT_LF && c->p.expansion == LAT_EXP_SELF && !c->batch && !c->u1 && !c->su2;
     return LAT_OK;
 }
 
@@ -1388,8 +1515,14 @@ lat_status lattice_energy(lat_ctx *c, lat_energies *out)
     if (c->u1) return u1_energy(c, out);
     if (c->su2) return su2_energy(c, out);
     const double c1 = (c->p.integrator == LAT_LF && c->lf_stag != 0) ? 0.5 * c->lf_stag * c->p.dt : 0.0;
-    lat_status s = energy_sums(c, c1);
-    if (s != LAT_OK) return s;
+    if (c->sums_fresh) {
+        // the sums the last step call reduced at the state it left
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        lat_status s = energy_sums(c, c1);
+        if (s != LAT_OK) return s;
+    }
     double a = 1.0, b = 0.0;
     if (c->p.expansion == LAT_EXP_FIXED) fixed_ab(c->p, c->t, &a, &b);
     if (c->p.expansion == LAT_EXP_SELF) {
@@ -1606,6 +1739,7 @@ static lat_status forward_transform(lat_ctx *c, const void *src, double2 *out)
 lat_status lattice_gauss_init(lat_ctx *c, double *mean_charge)
 {
     if (!c) return fail(nullptr, LAT_EINVAL, "null context");
+    c->sums_fresh = false;
     if (c->batch) return fail(c, LAT_EINVAL, "batch context: use a single-lattice context");
     if (!c->su2 && !c->u1) return fail(c, LAT_EINVAL, "the Gauss law belongs to the U(1) and SU(2) models");
     lat_status st = ensure_fft(c, false);
@@ -1862,10 +1996,40 @@ U1Args u1_args(lat_ctx *c, double ck, double hd, bool write_fields)
     a.kappa_g = c->p.kappa_g;
     a.ck = ck;
     a.hd = hd;
+    a.la1 = a.la3 = a.lam1 = 1.0;
+    a.hdA = hd;
+    a.dw = nullptr;
     a.partials = c->partials;
     a.ticket = c->ticket;
     a.sc = c->sc;
     return a;
+}
+
+// the same in an expanding background: kick weights at scale factor ak, drift
+// weights at the drift's midpoint am (sec. 5.5.2 kernels; reading R3)
+U1Args u1_args_bg(lat_ctx *c, double ck, double h, double ak, double am, bool write_fields)
+{
+    U1Args a = u1_args(c, ck, h, write_fields);
+    const double al = c->p.alpha;
+    a.la1 = std::pow(ak, 1.0 + al);
+    a.la3 = std::pow(ak, 3.0 + al);
+    a.lam1 = std::pow(ak, al - 1.0);
+    a.hd = h * std::pow(am, al - 3.0);
+    a.hdA = h * std::pow(am, al - 1.0);
+    return a;
+}
+
+// weights from the device record (self-consistent expansion)
+U1Args u1_args_dev(lat_ctx *c, bool write_fields)
+{
+    U1Args a = u1_args(c, 0.0, 0.0, write_fields);
+    a.dw = c->sc->w;
+    return a;
+}
+
+U1SelfConst u1_self_const(const lat_ctx *c)
+{
+    return U1SelfConst{c->p.alpha, c->p.kappa2, 1.0 / (double)c->vol};
 }
 
 // whole-row leapfrog pass: N = 64 XS, rows per block TY in {4, 8} (N = 64)
@@ -1940,16 +2104,40 @@ lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
     return LAT_OK;
 }
 
-lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir)
+lat_status u1_flip(lat_ctx *c)
+{
+    for (int i = 0; i < 2; ++i) c->cur_phi[i] ^= 1;
+    for (int i = 0; i < 3; ++i) c->cur_A[i] ^= 1;
+    return LAT_OK;
+}
+
+#define U1K(kernel, ...)                                                            \
+    do {                                                                            \
+        hipLaunchKernelGGL(kernel, dim3(1), dim3(64), 0, c->stream, __VA_ARGS__);   \
+        HIPCHK(c, hipGetLastError());                                               \
+    } while (0)
+
+// Self-consistent expansion (readings A3 and R1 for the U(1) model): the kicks,
+// energy sums and drifts as separate passes, the scale factor, b and the pass
+// weights updated on the device between them (stage_u1.hpp, U1SelfConst).
+lat_status u1_step_self_lf(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
+    const U1SelfConst kc = u1_self_const(c);
     int stag = c->lf_stag;
+    lat_status s;
     for (int64_t k = 0; k < ns; ++k) {
-        const double ck = stag == 0 ? 0.5 * h : h;
-        lat_status s = u1_launch(c, kU1Step, u1_args(c, ck, h, true));
-        if (s != LAT_OK) return s;
-        for (int i = 0; i < 2; ++i) c->cur_phi[i] ^= 1;
-        for (int i = 0; i < 3; ++i) c->cur_A[i] ^= 1;
+        const double w = stag == 0 ? 0.5 * h : h;
+        if (stag != 0) {   // sums of the momenta before the kick
+            if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+            U1K(u1_self_stash, c->sc);
+        }
+        U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
+        if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
+        if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+        U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc);
+        if ((s = u1_launch(c, kU1Step, u1_args_dev(c, true))) != LAT_OK) return s;
+        u1_flip(c);
         stag = dir;
     }
     c->lf_stag = dir;
@@ -1957,29 +2145,86 @@ lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir)
     return LAT_OK;
 }
 
+lat_status u1_step_lf(lat_ctx *c, int64_t ns, int dir)
+{
+    if (c->p.expansion == LAT_EXP_SELF) return u1_step_self_lf(c, ns, dir);
+    const double h = dir * c->p.dt;
+    const double t0 = c->t;
+    int stag = c->lf_stag;
+    for (int64_t k = 0; k < ns; ++k) {
+        const double ck = stag == 0 ? 0.5 * h : h;
+        const double t = t0 + (double)k * h;
+        lat_status s = u1_launch(c, kU1Step, c->p.expansion == LAT_EXP_FIXED
+                                                 ? u1_args_bg(c, ck, h, scale_at(c, t), scale_at(c, t + 0.5 * h), true)
+                                                 : u1_args(c, ck, h, true));
+        if (s != LAT_OK) return s;
+        u1_flip(c);
+        stag = dir;
+    }
+    c->lf_stag = dir;
+    c->t = t0 + (double)ns * h;
+    return LAT_OK;
+}
+
 lat_status u1_sync(lat_ctx *c)
 {
-    return u1_launch(c, kU1Kick, u1_args(c, 0.5 * c->lf_stag * c->p.dt, 0.0, false));
+    const double w = 0.5 * c->lf_stag * c->p.dt;
+    if (c->p.expansion == LAT_EXP_SELF) {
+        lat_status s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false));
+        if (s != LAT_OK) return s;
+        U1K(u1_self_b_kick, c->sc, w, u1_self_const(c));
+        U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
+        return u1_launch(c, kU1Kick, u1_args_dev(c, false));
+    }
+    const double a = scale_at(c, c->t);
+    return u1_launch(c, kU1Kick, u1_args_bg(c, w, 0.0, a, a, false));
 }
 
 lat_status u1_energy(lat_ctx *c, lat_energies *out)
 {
     const double ck = c->lf_stag != 0 ? 0.5 * c->lf_stag * c->p.dt : 0.0;
-    lat_status s = u1_launch(c, kU1Energy, u1_args(c, ck, 0.0, false));
+    const double V = (double)c->vol, al = c->p.alpha;
+    double a = 1.0, b = 0.0;
+    lat_status s;
+    if (c->p.expansion == LAT_EXP_FIXED) fixed_ab(c->p, c->t, &a, &b);
+    if (c->p.expansion == LAT_EXP_SELF) {
+        // a and b of the record; a staggered b is half-kicked on the fly with
+        // the sums of the stored half-step momenta (reading A3)
+        if (ck != 0.0 && (s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        a = c->sc_host->a;
+        b = c->sc_host->b;
+        if (ck != 0.0) {
+            const double *S = c->sc_host->sums;
+            const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+            const double Ka = std::pow(a, 2.0 * al + 1.0) / 3.0 * c->p.kappa2 *
+                              ((al - 2.0) * S[0] / V / a6 + al * S[1] / V / a2 +
+                               (al - 1.0) * (S[3] / V / a4 + S[4] / V / a4) + (al + 1.0) * S[2] / V);
+            b += ck * Ka;
+        }
+    }
+    s = u1_launch(c, kU1Energy, u1_args_bg(c, ck, 0.0, a, a, false));
     if (s != LAT_OK) return s;
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const double V = (double)c->vol;
     const double *S = c->sc_host->sums, *M = c->sc_host->maxes;
+    const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
     out->t = c->t;
-    out->a = 1.0;
-    out->b = 0.0;
-    out->EK[0] = S[0] / V;
-    out->EG[0] = S[1] / V;
+    out->a = a;
+    out->b = b;
+    out->EK[0] = S[0] / V / a6;
+    out->EG[0] = S[1] / V / a2;
     out->EV[0] = S[2] / V;
-    out->EK_A = S[3] / V;
-    out->EG_A = S[4] / V;
+    out->EK_A = S[3] / V / a4;
+    out->EG_A = S[4] / V / a4;
     out->rho = out->EK[0] + out->EG[0] + out->EV[0] + out->EK_A + out->EG_A;
+    out->hubble_lhs = b * b;
+    out->hubble_rhs = std::pow(a, 2.0 * al + 2.0) * c->p.kappa2 * out->rho / 3.0;
+    {
+        const double den = out->hubble_lhs + out->hubble_rhs;
+        out->hubble_res = den != 0.0 ? (out->hubble_lhs - out->hubble_rhs) / den : 0.0;
+    }
     out->gauss_mean = S[5] / V;
     out->gauss_sum_mean = S[6] / V;
     out->gauss_abs_mean = S[7] / V;
@@ -2207,15 +2452,47 @@ lat_status su2_energy(lat_ctx *c, lat_energies *out)
 }
 
 // Velocity-Verlet family for the U(1) and SU(2) models (a = 1): the sub-steps
-// h_p = w_p h of the triple-jump schedule (vv_weights), one kick-and-drift
+// h_p = w_p h of the composition (vv_weights), one kick-and-drift
 // pass per sub-step whose kick merges the half kicks that meet at its point,
 // (h_{p-1} + h_p)/2, and a closing kick-only pass of h_{M-1}/2; momenta end
 // at integer time.
-lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
+// U(1) velocity-Verlet family with self-consistent expansion (reading R1 for
+// each second-order map of the composition): kick(hs/2) at a_n, b half kick with
+// E_n, a drift, field drift at the mean a, kick(hs/2) at a_{n+1}, energies,
+// b half kick; every piece its own pass.
+lat_status u1_step_self_vv(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
     const std::vector<double> w = vv_weights(c->p.integrator);
+    const U1SelfConst kc = u1_self_const(c);
+    lat_status s;
+    if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;   // E_n
+    for (int64_t k = 0; k < ns; ++k)
+        for (double wp : w) {
+            const double hs = wp * h;
+            U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
+            if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
+            U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc);
+            if ((s = u1_launch(c, kU1Step, u1_args_dev(c, true))) != LAT_OK) return s;
+            u1_flip(c);
+            U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
+            if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
+            if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+            U1K(u1_self_b_kick, c->sc, 0.5 * hs, kc);
+        }
+    c->t += (double)ns * h;
+    return LAT_OK;
+}
+
+lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
+{
+    if (c->u1 && c->p.expansion == LAT_EXP_SELF) return u1_step_self_vv(c, ns, dir);
+    const double h = dir * c->p.dt;
+    const std::vector<double> w = vv_weights(c->p.integrator);
     const int64_t J = (int64_t)w.size(), M = J * ns;
+    const bool fixed = c->p.expansion == LAT_EXP_FIXED;
+    const double t_start = c->t;
+    double tk = t_start;   // time of the current kick point
     double prev = 0.0;
     const bool aos = c->su2 && c->su2_aos_on && M >= kSU2AosMinPasses;
     int buf = 0;
@@ -2234,9 +2511,13 @@ lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
             s = su2_launch(c, kSU2Step, su2_args(c, ck, hp, true));
             c->cur_su2 ^= 1;
         } else {
-            s = u1_launch(c, kU1Step, u1_args(c, ck, hp, true));
-            for (int i = 0; i < 2; ++i) c->cur_phi[i] ^= 1;
-            for (int i = 0; i < 3; ++i) c->cur_A[i] ^= 1;
+            // fixed background: kicks at the kick point's a, drift at the
+            // sub-step's midpoint (reading R3)
+            if (p % J == 0) tk = t_start + (double)(p / J) * h;
+            s = u1_launch(c, kU1Step, fixed ? u1_args_bg(c, ck, hp, scale_at(c, tk), scale_at(c, tk + 0.5 * hp), true)
+                                            : u1_args(c, ck, hp, true));
+            u1_flip(c);
+            tk += hp;
         }
         if (s != LAT_OK) return s;
         prev = hp;
@@ -2245,10 +2526,13 @@ lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
         lat_status s = su2_aos_leave(c, buf);
         if (s != LAT_OK) return s;
     }
+    const double tend = t_start + (double)ns * h;
     lat_status s = c->su2 ? su2_launch(c, kSU2Kick, su2_args(c, 0.5 * prev, 0.0, false))
-                          : u1_launch(c, kU1Kick, u1_args(c, 0.5 * prev, 0.0, false));
+                          : u1_launch(c, kU1Kick, fixed ? u1_args_bg(c, 0.5 * prev, 0.0, scale_at(c, tend),
+                                                                     scale_at(c, tend), false)
+                                                        : u1_args(c, 0.5 * prev, 0.0, false));
     if (s != LAT_OK) return s;
-    c->t += (double)ns * h;
+    c->t = tend;
     return LAT_OK;
 }
 
@@ -2337,6 +2621,7 @@ lat_status checkpoint_io(lat_ctx *c, size_t j, bool store)
 extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_grad_out *out)
 {
     if (!c || !spec || !out) return fail(c, LAT_EINVAL, "null argument");
+    c->sums_fresh = false;
     const bool spec_obs = spec->observable == LAT_OBS_SPECTRUM_BIN;
     if (spec->observable != LAT_OBS_ENERGY_FRACTION && !spec_obs)
         return fail(c, LAT_EINVAL, "unknown observable");
@@ -2356,6 +2641,7 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     }
     const int64_t T = spec->nsteps;
     if (T < 1 || T > (1LL << 26)) return fail(c, LAT_EINVAL, "nsteps out of range");
+    if ((double)c->vol >= 4294967296.0) return fail(c, LAT_EUNSUPPORTED, "lattice_grad needs N^3 < 2^32");
     int64_t k = spec->checkpoint_stride;
     if (k <= 0) {
         k = 1;
@@ -2400,20 +2686,26 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
         }
         c->adj_partial_cap = need;
     }
-    const int nbk = seed_blocks;   // one site per thread, 256 per block
+    // self-consistent reverse passes: a few sites per thread, so that every
+    // block can add up all blocks' sums of the point before in its prologue
+    const int rev_sites = (int)std::max<size_t>(1, (c->vol + (size_t)kSelfAdjThreads * 512 - 1) /
+                                                       ((size_t)kSelfAdjThreads * 512));
+    const int nbr = (int)((c->vol + (size_t)kSelfAdjThreads * rev_sites - 1) / ((size_t)kSelfAdjThreads * rev_sites));
     if (self) {
-        const size_t seg_states = (size_t)k + 1;
-        if (seg_states > c->self_seg_cap) {
+        // the k + 1 states of a segment (phi, pi of both fields) and two
+        // generations of the re-run's half-step momenta
+        const size_t seg_arrays = ((size_t)k + 1) * 4 + 4;
+        if (seg_arrays > c->self_seg_cap) {
             if (c->self_seg) HIPCHK(c, hipFree(c->self_seg));
             c->self_seg = nullptr;
-            if (hipMalloc(&c->self_seg, seg_states * 4 * bytes) != hipSuccess) {
+            if (hipMalloc(&c->self_seg, seg_arrays * bytes) != hipSuccess) {
                 c->self_seg_cap = 0;
                 return fail(c, LAT_ENOMEM, "segment state allocation failed");
             }
-            c->self_seg_cap = seg_states;
+            c->self_seg_cap = seg_arrays;
         }
         const size_t rec_d = (sizeof(ScaleRecord) + sizeof(double) - 1) / sizeof(double);
-        const size_t tneed = (size_t)2 * ((size_t)T + 1) + ncp * rec_d + 16;
+        const size_t tneed = (size_t)2 * ((size_t)T + 1) + rec_d + 16;
         if (tneed > c->self_traj_cap) {
             if (c->self_traj) HIPCHK(c, hipFree(c->self_traj));
             c->self_traj = nullptr;
@@ -2423,7 +2715,7 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
             }
             c->self_traj_cap = tneed;
         }
-        const size_t pneed = (size_t)4 * nbk + 32;
+        const size_t pneed = (size_t)2 * nbr * kRevQ + 3 * sizeof(SelfScalars) / sizeof(double) + 16;
         if (pneed > c->self_part_cap) {
             if (c->self_part) HIPCHK(c, hipFree(c->self_part));
             c->self_part = nullptr;
@@ -2462,26 +2754,23 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     // ---- forward sweep (leapfrog form of T VV2 steps) with checkpoints
     HIPCHK(c, hipEventRecord(e0, c->stream));
     GCHK(checkpoint_io(c, 0, true));
-    // self-consistent expansion: the library's own VV2 step, one at a time, with
-    // the scale factor and a' of every step and the scale record of every
-    // checkpoint kept on the host
-    // device layout of self_traj: (a, a') per step, then the checkpoints' scale records
+    // self-consistent expansion: the library's own VV2 steps, one call per
+    // segment between checkpoints, each pass storing (a, a') of its point on
+    // the device; the scale factors come back to the host once, at the end
+    // device layout of self_traj: (a, a') per step, then the initial scale record
     std::vector<double> traj_a;
     const int64_t step_save = c->step;
     double *traj_dev = c->self_traj;
     ScaleRecord *rec_dev = self ? (ScaleRecord *)(c->self_traj + 2 * ((size_t)T + 1)) : nullptr;
     if (self) {
-        HIPCHK(c, hipMemcpyAsync(traj_dev, &c->sc->a, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(rec_dev, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToDevice, c->stream));
-        for (int64_t p = 0; p < T; ++p) {
-            GCHK(step_vv(c, 1, 1));
-            HIPCHK(c, hipMemcpyAsync(traj_dev + 2 * ((size_t)p + 1), &c->sc->a, 2 * sizeof(double),
-                                     hipMemcpyDeviceToDevice, c->stream));
-            if ((p + 1) % k == 0 && p + 1 < T) {
-                GCHK(checkpoint_io(c, (size_t)((p + 1) / k), true));
-                HIPCHK(c, hipMemcpyAsync(rec_dev + (p + 1) / k, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToDevice,
-                                         c->stream));
-            }
+        for (int64_t s0 = 0; s0 < T; s0 += k) {
+            const int64_t len = std::min<int64_t>(k, T - s0);
+            c->traj_rec = traj_dev + 2 * (size_t)s0;
+            const lat_status r = step_vv(c, len, 1);
+            c->traj_rec = nullptr;
+            GCHK(r);
+            if (s0 + len < T) GCHK(checkpoint_io(c, (size_t)((s0 + len) / k), true));
         }
         std::vector<double> tr(2 * ((size_t)T + 1));
         HIPCHK(c, hipMemcpyAsync(tr.data(), traj_dev, tr.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -2588,121 +2877,110 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
             if (p % k == 0) GCHK(checkpoint_io(c, (size_t)(p / k), false));
         }
     } else {
-        // Self-consistent expansion, step by step in reverse (steps (6) ... (1) of
-        // stage_adjoint_self.hpp): the states of each segment are re-run from its
-        // checkpoint and kept; field pieces and the adjoints of a and b run on the
-        // device, from fixed-order device sums, with no host round trip per step.
+        // Self-consistent expansion: one fused pass per time point (stage_adjoint_self.hpp),
+        // the states of each segment re-run from its checkpoint with the
+        // recorded scale factors; the scalar adjoints stay on the device.
         HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         seed_sum = c->sc_host->sums[kMaxQ - 2];
-        const double al = c->p.alpha, idx2 = 1.0 / (c->p.dx * c->p.dx);
-        double *part = c->self_part, *tot = c->self_part + (size_t)4 * nbk;
-        SelfScalars *scal = (SelfScalars *)(c->self_traj + (c->self_traj_cap - 16));
+        const SelfConst kc{h, c->p.alpha, c->p.kappa2, V, 1.0 / (c->p.dx * c->p.dx), c->p.lambda, c->p.q};
+        const double al = c->p.alpha;
+        double *part[2] = {c->self_part, c->self_part + (size_t)nbr * kRevQ};
+        SelfScalars *R = (SelfScalars *)(c->self_part + (size_t)2 * nbr * kRevQ);
         {
             SelfScalars s0{};
             s0.la = la_T;
-            HIPCHK(c, hipMemcpyAsync(scal, &s0, sizeof(s0), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(R + ((T + 1) & 1), &s0, sizeof(s0), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
+        auto point = [&](int64_t n) {
+            SelfPoint P{};
+            P.a = traj_a[(size_t)n];
+            P.ka1 = std::pow(P.a, 1.0 + al);
+            P.ka3 = std::pow(P.a, 3.0 + al);
+            P.pa = std::pow(P.a, al);
+            P.pa2 = std::pow(P.a, 2.0 + al);
+            P.C = std::pow(P.a, 2.0 * al + 1.0) / 3.0 * c->p.kappa2;
+            P.kA = n < T;
+            P.kB = n > 0;
+            if (n > 0) {
+                const double abar = 0.5 * (traj_a[(size_t)n - 1] + P.a);
+                P.dr = h * std::pow(abar, al - 3.0);
+                P.pbar = std::pow(abar, al - 4.0);
+            }
+            return P;
+        };
         auto state = [&](int64_t j, int which, int f) {
             return c->self_seg + ((size_t)j * 4 + (size_t)(2 * which + f)) * c->vol;
         };
-        auto args = [&](int64_t j) {
-            SelfAdjArgs g{};
-            for (int f = 0; f < 2; ++f) {
-                g.phi[f] = state(j, 0, f);
-                g.pi[f] = state(j, 1, f);
-                g.lphi[f] = (double *)c->lam[0][f][c->cur_lam[0][f]];
-                g.lpi[f] = (double *)c->lam[1][f][c->cur_lam[1][f]];
-            }
-            g.N = N;
-            g.inv_dx2 = idx2;
-            g.lam = c->p.lambda;
-            g.q = c->p.q;
-            g.part = part;
-            g.dcoef = scal->bk;
-            return g;
+        auto carry = [&](int64_t j, int f) {
+            return c->self_seg + (((size_t)k + 1) * 4 + (size_t)(2 * (j & 1) + f)) * c->vol;
         };
-        auto reduce = [&](int nq, int off) -> lat_status {
-            HIPCHK(c, hipGetLastError());
-            hipLaunchKernelGGL(self_adj_reduce, dim3((unsigned)nq), dim3(kSelfAdjThreads), 0, c->stream,
-                               (const double *)part, nbk, nq, tot + off);
-            HIPCHK(c, hipGetLastError());
-            return LAT_OK;
-        };
-        auto keep = [&](int64_t j) -> lat_status {
-            for (int f = 0; f < 2; ++f) {
-                HIPCHK(c, hipMemcpyAsync(state(j, 0, f), c->phi[f][c->cur_phi[f]], bytes, hipMemcpyDeviceToDevice,
-                                         c->stream));
-                HIPCHK(c, hipMemcpyAsync(state(j, 1, f), c->pi[f][c->cur_pi[f]], bytes, hipMemcpyDeviceToDevice,
-                                         c->stream));
-            }
-            return LAT_OK;
-        };
-        const dim3 grid((unsigned)nbk), blk(kSelfAdjThreads), one(1), w64(64);
+        const dim3 grid_site((unsigned)seed_blocks), grid_rev((unsigned)nbr), blk(kSelfAdjThreads);
         for (int64_t s0 = ((T - 1) / k) * k; s0 >= 0; s0 -= k) {
             const int64_t s1 = std::min<int64_t>(s0 + k, T);
-            GCHK(checkpoint_io(c, (size_t)(s0 / k), false));
-            HIPCHK(c, hipMemcpyAsync(c->sc, rec_dev + s0 / k, sizeof(ScaleRecord), hipMemcpyDeviceToDevice, c->stream));
-            c->t = t_start + (double)s0 * h;
-            GCHK(keep(0));
-            for (int64_t n = s0; n < s1; ++n) {
-                GCHK(step_vv(c, 1, 1));
-                GCHK(keep(n + 1 - s0));
+            const int64_t m = s1 == T ? s1 - s0 : s1 - s0 - 1;   // states s0 .. s0 + m
+            // re-run: the checkpoint into state 0, then m steps
+            for (int64_t j = 0; j <= m; ++j) {
+                SelfRerunArgs r{};
+                for (int f = 0; f < 2; ++f) {
+                    if (j == 0) {
+                        r.phi_in[f] = c->ckpt + ((size_t)(s0 / k) * 4 + (size_t)f) * c->vol;
+                        r.pp_in[f] = c->ckpt + ((size_t)(s0 / k) * 4 + 2 + (size_t)f) * c->vol;
+                    } else {
+                        r.phi_in[f] = state(j - 1, 0, f);
+                        r.pp_in[f] = carry(j - 1, f);
+                    }
+                    r.phi_out[f] = state(j, 0, f);
+                    r.pi_out[f] = state(j, 1, f);
+                    r.pp_out[f] = carry(j, f);
+                }
+                const double an = traj_a[(size_t)(s0 + j)];
+                r.N = N;
+                r.inv_dx2 = kc.inv_dx2;
+                r.lam = kc.lam;
+                r.q = kc.q;
+                r.ka1 = std::pow(an, 1.0 + al);
+                r.ka3 = std::pow(an, 3.0 + al);
+                r.ch = 0.5 * h;
+                if (j > 0) {
+                    r.cf = 0.5 * h;
+                    r.dr = h * std::pow(0.5 * (traj_a[(size_t)(s0 + j - 1)] + an), al - 3.0);
+                }
+                hipLaunchKernelGGL(self_rerun, grid_site, blk, 0, c->stream, r);
+                HIPCHK(c, hipGetLastError());
             }
-            for (int64_t n = s1 - 1; n >= s0; --n) {
-                SelfStepConst kc{};
-                kc.a0 = traj_a[(size_t)n];
-                kc.a1 = traj_a[(size_t)n + 1];
-                kc.abar = 0.5 * (kc.a0 + kc.a1);
-                kc.h = h;
-                kc.alpha = al;
-                kc.kappa2 = c->p.kappa2;
-                kc.V = V;
-                const SelfAdjArgs g1 = args(n + 1 - s0), g0 = args(n - s0);
-                hipLaunchKernelGGL(self_adj_energy, grid, blk, 0, c->stream, g1);
-                GCHK(reduce(4, 0));
-                hipLaunchKernelGGL(self_adj_energy, grid, blk, 0, c->stream, g0);
-                GCHK(reduce(4, 4));
-                hipLaunchKernelGGL(self_scal_pre, one, w64, 0, c->stream, (const double *)tot, kc, scal);
-                HIPCHK(c, hipGetLastError());
-                hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g1);            // (6)
-                HIPCHK(c, hipGetLastError());
-                {   // (5) field kick at n + 1
-                    SelfAdjArgs g = g1;
-                    g.c0 = 0.5 * h * std::pow(kc.a1, 1.0 + al);
-                    g.c1 = 0.5 * h * std::pow(kc.a1, 3.0 + al);
-                    hipLaunchKernelGGL(self_adj_kick, grid, blk, 0, c->stream, g);
-                    GCHK(reduce(3, 8));
+            for (int64_t n = s0 + m; n >= s0; --n) {
+                SelfRevArgs g{};
+                for (int f = 0; f < 2; ++f) {
+                    g.phi[f] = state(n - s0, 0, f);
+                    g.pi[f] = state(n - s0, 1, f);
+                    g.lphi[f] = (double *)c->lam[0][f][c->cur_lam[0][f]];
+                    g.lpi_in[f] = (const double *)c->lam[1][f][c->cur_lam[1][f]];
+                    g.lpi_out[f] = (double *)c->lam[1][f][c->cur_lam[1][f] ^ 1];
                 }
-                {   // (4) drift
-                    SelfDriftArgs d{};
-                    d.g = g0;
-                    d.g.c0 = 0.5 * h;
-                    d.g.c1 = std::pow(kc.a0, 1.0 + al);
-                    d.g.c2 = std::pow(kc.a0, 3.0 + al);
-                    d.dr = h * std::pow(kc.abar, al - 3.0);
-                    hipLaunchKernelGGL(self_adj_drift, grid, blk, 0, c->stream, d);
-                    GCHK(reduce(1, 11));
-                }
-                hipLaunchKernelGGL(self_scal_mid, one, w64, 0, c->stream, (const double *)tot, kc, scal);   // (3)
+                g.N = N;
+                g.sites = rev_sites;
+                g.k = kc;
+                g.P = point(n);
+                g.has_prev = n < T;
+                if (n < T) g.Pp = point(n + 1);
+                g.part_in = part[(n + 1) & 1];
+                g.nb_in = nbr;
+                g.part_out = part[n & 1];
+                g.sc_in = R + ((n + 1) & 1);
+                g.sc_out = R + (n & 1);
+                hipLaunchKernelGGL(self_rev, grid_rev, blk, 0, c->stream, g);
                 HIPCHK(c, hipGetLastError());
-                {   // (1) field kick at n
-                    SelfAdjArgs g = g0;
-                    g.c0 = 0.5 * h * std::pow(kc.a0, 1.0 + al);
-                    g.c1 = 0.5 * h * std::pow(kc.a0, 3.0 + al);
-                    hipLaunchKernelGGL(self_adj_kick, grid, blk, 0, c->stream, g);
-                    GCHK(reduce(3, 12));
-                }
-                hipLaunchKernelGGL(self_adj_bkick, grid, blk, 0, c->stream, g0);            // (2)
-                HIPCHK(c, hipGetLastError());
-                hipLaunchKernelGGL(self_scal_post, one, w64, 0, c->stream, (const double *)tot, kc, scal);
-                HIPCHK(c, hipGetLastError());
+                for (int f = 0; f < 2; ++f) c->cur_lam[1][f] ^= 1;
             }
         }
+        hipLaunchKernelGGL(self_rev_finish, dim3(1), blk, 0, c->stream, (const double *)part[0], nbr, point(0), kc,
+                           (const SelfScalars *)R, R + 2);
+        HIPCHK(c, hipGetLastError());
         {
             SelfScalars sf{};
-            HIPCHK(c, hipMemcpyAsync(&sf, scal, sizeof(sf), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(&sf, R + 2, sizeof(sf), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             la = sf.la;
             lb = sf.lb;

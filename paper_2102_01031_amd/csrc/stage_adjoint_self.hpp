@@ -1,6 +1,6 @@
-// stage_adjoint_self.hpp -- pieces of the adjoint of one velocity-Verlet step
-// with the self-consistent expansion (sec. 4.5.2 Hamiltonian system with the
-// scale factor as a dynamical variable), two real fields with
+// stage_adjoint_self.hpp -- adjoint of the velocity-Verlet evolution with the
+// self-consistent expansion (sec. 4.5.2 Hamiltonian system with the scale
+// factor as a dynamical variable), two real fields with
 // V = lambda/4 phi^4 + q/2 phi^2 chi^2.  One step from (phi_n, pi_n, a_n, b_n):
 //   (1) pi'  = pi_n + h/2 K(a_n, phi_n)
 //   (2) b'   = b_n + h/2 K_a(a_n, E(phi_n, pi_n, a_n))
@@ -10,24 +10,40 @@
 //   (6) b1   = b' + h/2 K_a(a1, E(phi1, pi1, a1))
 // with K = a^{1+alpha} Lap phi - a^{3+alpha} grad V and K_a = C(a) Q,
 // C = a^{2 alpha+1} kappa^2/3, Q = (alpha-2) E_K + alpha E_G + (alpha+1) E_V.
-// The field-shaped parts run one site per thread with neighbours through the
-// caches and write per-block partial sums (NQ per block, fixed order) of the
-// scalar products that the scalar adjoints of a and b need; three one-thread
-// kernels per step pull those scalars back on the device.
+//
+// The reverse sweep visits the time points n = T, ..., 0 once each.  At point n
+// it undoes, in order, (1) and (2) of step n (if n < T), then (6), (5), (4) of
+// step n - 1 (if n > 0), all of which act on the state (phi_n, pi_n) at a_n:
+//   - both b kicks at n have the weight h/2 lb with the same lb (the pull-backs
+//     of (1) and (2) leave lb alone), so their field parts add up;
+//   - the field kick of (1) pulls back the momentum adjoint lpi before the b
+//     kicks add to it, the kick of (5) pulls back lpi after both;
+//   - pi' of step n - 1 is rebuilt as pi_n - h/2 K(a_n, phi_n).
+// One pass per point does all of that site by site and leaves per-block
+// partial sums of the eight scalar products the scalar adjoints need; the next
+// pass (or self_rev_finish) adds them up in block order in every block, so the
+// chain of scalar adjoints (la, lb, dO/dq) runs on the device, in a fixed order,
+// without a launch of its own.  (3) is the scalar step between points.
+//
+// The states of a segment are re-run from its checkpoint by self_rerun with
+// the scale factors the forward sweep recorded.
 #pragma once
 #include "common.hpp"
 
 namespace lat {
 
 constexpr int kSelfAdjThreads = 256;
+constexpr int kRevQ = 8;   // energy sums (4), kick products (3), drift product (1)
 
 struct SelfAdjSite {
     size_t xp, xm, yp, ym, zp, zm;
 };
 
+// (32-bit index arithmetic: N^3 < 2^32)
 __device__ inline SelfAdjSite self_adj_nbrs(size_t n, int N)
 {
-    const int x = (int)(n % N), y = (int)((n / N) % N), z = (int)(n / ((size_t)N * N));
+    const unsigned u = (unsigned)n, Nu = (unsigned)N, yz = u / Nu;
+    const int x = (int)(u - yz * Nu), z = (int)(yz / Nu), y = (int)(yz - (unsigned)z * Nu);
     const size_t NN = (size_t)N * N;
     SelfAdjSite s;
     s.xp = n - x + (x + 1 == N ? 0 : x + 1);
@@ -45,234 +61,238 @@ __device__ inline double self_adj_lap(const double *f, size_t n, const SelfAdjSi
     return ((f[s.xp] - 2.0 * c + f[s.xm]) + (f[s.yp] - 2.0 * c + f[s.ym]) + (f[s.zp] - 2.0 * c + f[s.zm])) * idx2;
 }
 
-// Block partial sums of NQ per-thread values, written to part[q * gridDim.x + block].
-template <int NQ>
-__device__ inline void self_adj_partials(const double (&v)[NQ], double *part)
-{
-    __shared__ double lds[NQ][kSelfAdjThreads / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double s = wave_sum(v[q]);
-        if (lane == 0) lds[q][w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NQ) {
-        double s = 0.0;
-        for (int k = 0; k < kSelfAdjThreads / 64; ++k) s += lds[threadIdx.x][k];
-        part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
-    }
-}
-
-struct SelfAdjArgs {
-    const double *phi[2], *pi[2];   // the state the piece is taken at
-    double *lphi[2], *lpi[2];       // adjoint arrays (updated in place, own site only)
+// ---------------------------------------------------------------------------
+// re-run of a segment: from (phi_j, pi'_j) to the state (phi_{j+1}, pi_{j+1})
+// and pi'_{j+1}, with the recorded scale factors:
+//   phi_{j+1} = phi_j + dr pi'_j,  K = ka1 Lap phi_{j+1} - ka3 grad V(phi_{j+1}),
+//   pi_{j+1} = pi'_j + cf K,  pi'_{j+1} = pi_{j+1} + h/2 K
+// (cf = h/2, dr = h abar^{alpha-3}).  The first call of a segment takes the
+// checkpoint (phi, pi) with dr = cf = 0: it copies the state and forms pi'.
+struct SelfRerunArgs {
+    const double *phi_in[2], *pp_in[2];
+    double *phi_out[2], *pi_out[2], *pp_out[2];
     int N;
     double inv_dx2, lam, q;
-    double c0, c1, c2;              // piece coefficients (see each kernel)
-    double *part;                   // per-block partials
-    const double *dcoef;            // b kick: its three coefficients, on the device
+    double dr, cf, ch;       // drift, first and second half kick weights
+    double ka1, ka3;         // a^{1+alpha}, a^{3+alpha} at the new point
 };
 
-// Energy sums of (phi, pi), both fields together: sum pi^2,
-// sum |grad+ phi|^2 (forward differences over dx), sum V, sum phi^2 chi^2 / 2.
-// No adjoint update.
-__global__ void __launch_bounds__(kSelfAdjThreads) self_adj_energy(const SelfAdjArgs g)
-{
-    const int N = g.N;
-    const size_t V = (size_t)N * N * N;
-    const size_t n = (size_t)blockIdx.x * kSelfAdjThreads + threadIdx.x;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (n < V) {
-        const SelfAdjSite s = self_adj_nbrs(n, N);
-        const double u = g.phi[0][n], w = g.phi[1][n];
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            const double *P = g.phi[f];
-            const double c = P[n], dx = P[s.xp] - c, dy = P[s.yp] - c, dz = P[s.zp] - c;
-            v[0] += g.pi[f][n] * g.pi[f][n];
-            v[1] += (dx * dx + dy * dy + dz * dz) * g.inv_dx2;
-        }
-        v[2] = 0.25 * g.lam * u * u * u * u + 0.5 * g.q * u * u * w * w;
-        v[3] = 0.5 * u * u * w * w;
-    }
-    self_adj_partials<4>(v, g.part);
-}
-
-// Pull-back of a b kick b += wb K_a(a, E(phi, pi, a)) into the fields:
-//   lphi_s += d0 (-Lap phi_s) + d1 dV/dphi_s,   lpi_s += d2 pi_s
-// with (d0, d1, d2) = dcoef = wb lb C (alpha/(a^2 V), (alpha+1)/V, (alpha-2)/(a^6 V)).
-__global__ void __launch_bounds__(kSelfAdjThreads) self_adj_bkick(const SelfAdjArgs g)
+__global__ void __launch_bounds__(kSelfAdjThreads) self_rerun(const SelfRerunArgs g)
 {
     const int N = g.N;
     const size_t V = (size_t)N * N * N;
     const size_t n = (size_t)blockIdx.x * kSelfAdjThreads + threadIdx.x;
     if (n >= V) return;
-    const double d0 = g.dcoef[0], d1 = g.dcoef[1], d2 = g.dcoef[2];
     const SelfAdjSite s = self_adj_nbrs(n, N);
-    const double u = g.phi[0][n], w = g.phi[1][n];
+    double ph[2], lap[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        const double *P = g.phi_in[f], *Q = g.pp_in[f];
+        auto at = [&](size_t m) { return P[m] + g.dr * Q[m]; };
+        const double c = at(n);
+        ph[f] = c;
+        lap[f] = ((at(s.xp) - 2.0 * c + at(s.xm)) + (at(s.yp) - 2.0 * c + at(s.ym)) +
+                  (at(s.zp) - 2.0 * c + at(s.zm))) * g.inv_dx2;
+    }
+    const double u = ph[0], w = ph[1];
     const double dV[2] = {g.lam * u * u * u + g.q * u * w * w, g.q * u * u * w};
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-        const double lap = self_adj_lap(g.phi[f], n, s, g.inv_dx2);
-        g.lphi[f][n] += d0 * (-lap) + d1 * dV[f];
-        g.lpi[f][n] += d2 * g.pi[f][n];
+        const double K = g.ka1 * lap[f] - g.ka3 * dV[f];
+        const double p1 = g.pp_in[f][n] + g.cf * K;
+        g.phi_out[f][n] = ph[f];
+        g.pi_out[f][n] = p1;
+        g.pp_out[f][n] = p1 + g.ch * K;
     }
 }
 
-// Pull-back of a field kick pi += wk K(a, phi), c0 = wk a^{1+alpha}, c1 = wk a^{3+alpha}:
-//   lphi_s += c0 Lap lpi_s - c1 (H_V(phi) lpi)_s
-// and partials of  sum lpi . (Lap phi) ,  sum lpi . dV/dphi ,  sum lpi . dF/dq
-// (dF/dq = -(phi chi^2, phi^2 chi)), from which the host forms dK/da and dK/dq.
-__global__ void __launch_bounds__(kSelfAdjThreads) self_adj_kick(const SelfAdjArgs g)
-{
-    const int N = g.N;
-    const size_t V = (size_t)N * N * N;
-    const size_t n = (size_t)blockIdx.x * kSelfAdjThreads + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (n < V) {
-        const SelfAdjSite s = self_adj_nbrs(n, N);
-        const double u = g.phi[0][n], w = g.phi[1][n];
-        const double l0 = g.lpi[0][n], l1 = g.lpi[1][n];
-        const double h00 = 3.0 * g.lam * u * u + g.q * w * w, h01 = 2.0 * g.q * u * w, h11 = g.q * u * u;
-        const double dV0 = g.lam * u * u * u + g.q * u * w * w, dV1 = g.q * u * u * w;
-        const double ll0 = self_adj_lap(g.lpi[0], n, s, g.inv_dx2), ll1 = self_adj_lap(g.lpi[1], n, s, g.inv_dx2);
-        const double lp0 = self_adj_lap(g.phi[0], n, s, g.inv_dx2), lp1 = self_adj_lap(g.phi[1], n, s, g.inv_dx2);
-        g.lphi[0][n] += g.c0 * ll0 - g.c1 * (h00 * l0 + h01 * l1);
-        g.lphi[1][n] += g.c0 * ll1 - g.c1 * (h01 * l0 + h11 * l1);
-        v[0] = l0 * lp0 + l1 * lp1;
-        v[1] = l0 * dV0 + l1 * dV1;
-        v[2] = -(l0 * u * w * w) - (l1 * u * u * w);
-    }
-    self_adj_partials<3>(v, g.part);
-}
-
-// Pull-back of the drift phi1 = phi_n + dr pi', with pi' = pi_n + c0 K(a_n, phi_n)
-// rebuilt on the fly (c1 = a_n^{1+alpha}, c2 = a_n^{3+alpha}): partial of
-// sum lphi . pi', then lpi += dr lphi.
-struct SelfDriftArgs {
-    SelfAdjArgs g;
-    double dr;
+// ---------------------------------------------------------------------------
+// scalar adjoints carried from point to point
+struct SelfScalars {
+    double la;   // adjoint of a at the current point (what is known of it so far)
+    double lb;   // adjoint of b
+    double dq;   // dO/dq accumulated
+    double pad;
 };
 
-__global__ void __launch_bounds__(kSelfAdjThreads) self_adj_drift(const SelfDriftArgs d)
+// one time point of the reverse sweep, with the powers of the scale factor
+// its pieces need (formed on the host from the recorded a_n)
+struct SelfPoint {
+    double a;          // a_n
+    double ka1, ka3;   // a_n^{1+alpha}, a_n^{3+alpha}
+    double pa, pa2;    // a_n^alpha, a_n^{2+alpha}
+    double C;          // a_n^{2 alpha+1} kappa^2 / 3
+    double dr;         // h abar^{alpha-3}, abar = (a_{n-1} + a_n)/2, the drift of step n-1  (kB)
+    double pbar;       // abar^{alpha-4}                                                   (kB)
+    int kA;            // step n leaves n (n < T): (1), (2)
+    int kB;            // step n - 1 ends at n (n > 0): (6), (5), (4), (3)
+};
+
+struct SelfConst {
+    double h, alpha, kappa2, V, inv_dx2, lam, q;
+};
+
+// dK_a/da and dK_a/dq at point P from the energy sums E (sum pi^2,
+// sum |grad+ phi|^2 over dx^2, sum V, sum phi^2 chi^2 / 2), K_a = C Q
+__device__ inline void self_ka(const SelfPoint &P, const double *E, const SelfConst &k, double &dKda, double &dKdq)
 {
-    const SelfAdjArgs &g = d.g;
+    const double al = k.alpha, a = P.a;
+    const double ia2 = 1.0 / (a * a), ia6 = ia2 * ia2 * ia2;
+    const double EK = E[0] / (2.0 * k.V) * ia6, EG = E[1] / (2.0 * k.V) * ia2, EV = E[2] / k.V;
+    const double Q = (al - 2.0) * EK + al * EG + (al + 1.0) * EV;
+    dKda = (2.0 * al + 1.0) * P.C * Q / a + P.C * ((al - 2.0) * (-6.0) * EK / a + al * (-2.0) * EG / a);
+    dKdq = P.C * (al + 1.0) * E[3] / k.V;
+}
+
+// The scalar part of point P from its sums tot (kRevQ, in the order of the
+// pass): both b kicks' da terms, the field kicks' da and dq terms, and for
+// kB the drift's dabar term and (3), which leaves la as the part of the
+// adjoint of a_{n-1} known so far.
+__device__ inline void self_rev_finalise(const SelfPoint &P, const double *tot, const SelfConst &k, SelfScalars &s)
+{
+    const double al = k.alpha, h = k.h;
+    const int nbk = P.kA + P.kB;
+    double dKda, dKdq;
+    self_ka(P, tot, k, dKda, dKdq);
+    const double wl = 0.5 * h * s.lb;
+    double la = s.la + (double)nbk * wl * dKda + 0.5 * h * ((1.0 + al) * P.pa * tot[4] - (3.0 + al) * P.pa2 * tot[5]);
+    s.dq += (double)nbk * wl * dKdq + 0.5 * h * P.ka3 * tot[6];
+    if (P.kB) {
+        const double labar = h * (al - 3.0) * P.pbar * tot[7];
+        la += 0.5 * labar;      // a_n's share of abar
+        s.lb += h * la;         // (3): a_n = a_{n-1} + h b'
+        la = 0.5 * labar + la;  // a_{n-1}: its share of abar, and through (3)
+    }
+    s.la = la;
+}
+
+struct SelfRevArgs {
+    const double *phi[2], *pi[2];   // the state at the point
+    double *lphi[2];                // field adjoint, updated in place (own site)
+    const double *lpi_in[2];        // momentum adjoint in (read with neighbours) ...
+    double *lpi_out[2];             // ... and out
+    int N, sites;                   // sites per thread
+    SelfConst k;
+    SelfPoint P;                    // this point
+    SelfPoint Pp;                   // the point before (n + 1), finalised in the prologue
+    int has_prev;
+    const double *part_in;          // its per-block sums, kRevQ per block
+    int nb_in;
+    double *part_out;               // this pass's, kRevQ per block
+    const SelfScalars *sc_in;
+    SelfScalars *sc_out;            // written by block 0
+};
+
+template <int NT, int NQ>
+__device__ inline void self_sum_partials(const double *part, int nb, double *lds_red, double (&tot)[NQ])
+{
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += NT) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += part[(size_t)i * NQ + q];
+    }
+    block_sums<NT, NQ>(acc, lds_red, tot);
+}
+
+__global__ void __launch_bounds__(kSelfAdjThreads) self_rev(const SelfRevArgs g)
+{
+    constexpr int NT = kSelfAdjThreads;
+    __shared__ double lds_red[(NT / 64) * kRevQ];
+    __shared__ double lds_lb;
+    const int tid = threadIdx.x;
+    // scalars up to this point: finalise the previous point in every block
+    {
+        double tot[kRevQ];
+        if (g.has_prev) self_sum_partials<NT, kRevQ>(g.part_in, g.nb_in, lds_red, tot);
+        if (tid == 0) {
+            SelfScalars s = *g.sc_in;
+            if (g.has_prev) self_rev_finalise(g.Pp, tot, g.k, s);
+            lds_lb = s.lb;
+            if (blockIdx.x == 0) *g.sc_out = s;
+        }
+        __syncthreads();
+    }
+    const SelfConst &k = g.k;
+    const SelfPoint &P = g.P;
+    const double lb = lds_lb;
+    const int nbk = P.kA + P.kB;
+    // b kick pull-back coefficients at a_n (both kicks), field kick weights
+    const double ia2 = 1.0 / (P.a * P.a), ia6 = ia2 * ia2 * ia2;
+    const double wl = 0.5 * k.h * lb;
+    const double d0 = wl * P.C * k.alpha * ia2 / k.V, d1 = wl * P.C * (k.alpha + 1.0) / k.V;
+    const double nd2 = (double)nbk * wl * P.C * (k.alpha - 2.0) * ia6 / k.V;
+    const double c0 = 0.5 * k.h * P.ka1, c1 = 0.5 * k.h * P.ka3;
+    const double fA = (double)P.kA, fB = (double)P.kB;
+
     const int N = g.N;
     const size_t V = (size_t)N * N * N;
-    const size_t n = (size_t)blockIdx.x * kSelfAdjThreads + threadIdx.x;
-    double v[1] = {0.0};
-    if (n < V) {
+    double acc[kRevQ];
+#pragma unroll
+    for (int q = 0; q < kRevQ; ++q) acc[q] = 0.0;
+    for (int it = 0; it < g.sites; ++it) {
+        const size_t n = ((size_t)blockIdx.x * g.sites + it) * NT + tid;
+        if (n >= V) break;
         const SelfAdjSite s = self_adj_nbrs(n, N);
         const double u = g.phi[0][n], w = g.phi[1][n];
-        const double dV[2] = {g.lam * u * u * u + g.q * u * w * w, g.q * u * u * w};
-        double acc = 0.0;
+        const double dV[2] = {k.lam * u * u * u + k.q * u * w * w, k.q * u * u * w};
+        const double h00 = 3.0 * k.lam * u * u + k.q * w * w, h01 = 2.0 * k.q * u * w, h11 = k.q * u * u;
+        double Lp[2], y[2], Ly[2], l1[2], pv[2];
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-            const double K = g.c1 * self_adj_lap(g.phi[f], n, s, g.inv_dx2) - g.c2 * dV[f];
-            const double pp = g.pi[f][n] + g.c0 * K;
-            const double lf = g.lphi[f][n];
-            acc += lf * pp;
-            g.lpi[f][n] += d.dr * lf;
+            const double *Pf = g.phi[f];
+            const double c = Pf[n], ex = Pf[s.xp] - c, ey = Pf[s.yp] - c, ez = Pf[s.zp] - c;
+            Lp[f] = self_adj_lap(Pf, n, s, k.inv_dx2);
+            pv[f] = g.pi[f][n];
+            const double lpi = g.lpi_in[f][n];
+            l1[f] = lpi + nd2 * pv[f];                      // after both b kicks
+            y[f] = fA * lpi + fB * l1[f];                  // what the two field kicks pull back
+            Ly[f] = (fA + fB) * self_adj_lap(g.lpi_in[f], n, s, k.inv_dx2) +
+                    fB * nd2 * self_adj_lap(g.pi[f], n, s, k.inv_dx2);
+            acc[0] += pv[f] * pv[f];
+            acc[1] += (ex * ex + ey * ey + ez * ez) * k.inv_dx2;
         }
-        v[0] = acc;
+        acc[2] += 0.25 * k.lam * u * u * u * u + 0.5 * k.q * u * u * w * w;
+        acc[3] += 0.5 * u * u * w * w;
+        const double Hy[2] = {h00 * y[0] + h01 * y[1], h01 * y[0] + h11 * y[1]};
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const double lf = g.lphi[f][n] + (double)nbk * (d0 * (-Lp[f]) + d1 * dV[f]) + c0 * Ly[f] - c1 * Hy[f];
+            acc[4] += y[f] * Lp[f];
+            acc[5] += y[f] * dV[f];
+            double lp = l1[f];
+            if (P.kB) {
+                const double pp = pv[f] - 0.5 * k.h * (P.ka1 * Lp[f] - P.ka3 * dV[f]);   // pi' of step n - 1
+                acc[7] += lf * pp;
+                lp += P.dr * lf;
+            }
+            g.lphi[f][n] = lf;
+            g.lpi_out[f][n] = lp;
+        }
+        acc[6] += -(y[0] * u * w * w) - (y[1] * u * u * w);
     }
-    self_adj_partials<1>(v, g.part);
+    double tot[kRevQ];
+    block_sums<NT, kRevQ>(acc, lds_red, tot);
+    if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < kRevQ; ++q) g.part_out[(size_t)blockIdx.x * kRevQ + q] = tot[q];
+    }
 }
 
-// Scalar adjoints of one reverse step, on the device.  tot holds, in order:
-// energy sums (sum pi^2, sum |grad+ phi|^2, sum V, sum phi^2 chi^2/2) at n + 1
-// [0..3] and at n [4..7]; the field kick sums at n + 1 (sum lpi.Lap phi,
-// sum lpi.dV/dphi, sum lpi.dF/dq) [8..10]; the drift sum lphi.pi' [11]; the
-// field kick sums at n [12..14].
-struct SelfScalars {
-    double la, lb, dq;      // adjoints of a and b, and dO/dq, accumulated
-    double la1, la0;        // adjoints of a_{n+1} and a_n within the step
-    double bk[3];           // coefficients of the next b kick pull-back
-};
-
-struct SelfStepConst {
-    double a0, a1, abar, h, alpha, kappa2, V;
-};
-
-// K_a = C Q at scale factor a from the energy sums S: C, 1/a^2, 1/a^6, dK_a/da, dK_a/dq
-__device__ inline void self_ka(double a, const double *S, const SelfStepConst &k, double &C, double &ia2,
-                               double &ia6, double &dKda, double &dKdq)
+// the last point's sums (one block)
+__global__ void __launch_bounds__(kSelfAdjThreads) self_rev_finish(const double *part, int nb, const SelfPoint P,
+                                                                   const SelfConst k, const SelfScalars *sc_in,
+                                                                   SelfScalars *sc_out)
 {
-    const double al = k.alpha;
-    ia2 = 1.0 / (a * a);
-    ia6 = ia2 * ia2 * ia2;
-    const double EK = S[0] / (2.0 * k.V) * ia6, EG = S[1] / (2.0 * k.V) * ia2, EV = S[2] / k.V;
-    C = pow(a, 2.0 * al + 1.0) / 3.0 * k.kappa2;
-    const double Q = (al - 2.0) * EK + al * EG + (al + 1.0) * EV;
-    dKda = (2.0 * al + 1.0) * C * Q / a + C * ((al - 2.0) * (-6.0) * EK / a + al * (-2.0) * EG / a);
-    dKdq = C * (al + 1.0) * S[3] / k.V;
-}
-
-__device__ inline void self_bk(SelfScalars *s, double wl, double C, double ia2, double ia6, const SelfStepConst &k)
-{
-    s->bk[0] = wl * C * k.alpha * ia2 / k.V;
-    s->bk[1] = wl * C * (k.alpha + 1.0) / k.V;
-    s->bk[2] = wl * C * (k.alpha - 2.0) * ia6 / k.V;
-}
-
-// (6): the b kick at n + 1 (before its field pull-back)
-__global__ void self_scal_pre(const double *tot, const SelfStepConst k, SelfScalars *s)
-{
-    if (threadIdx.x != 0) return;
-    double C, ia2, ia6, dKda, dKdq;
-    self_ka(k.a1, tot, k, C, ia2, ia6, dKda, dKdq);
-    const double wl = 0.5 * k.h * s->lb;
-    self_bk(s, wl, C, ia2, ia6, k);
-    s->la1 = s->la + wl * dKda;
-    s->dq += wl * dKdq;
-}
-
-// (5), (4), (3) and the scalar part of (2)
-__global__ void self_scal_mid(const double *tot, const SelfStepConst k, SelfScalars *s)
-{
-    if (threadIdx.x != 0) return;
-    const double al = k.alpha, h = k.h;
-    double la1 = s->la1 + 0.5 * h * ((1.0 + al) * pow(k.a1, al) * tot[8] - (3.0 + al) * pow(k.a1, 2.0 + al) * tot[9]);
-    s->dq += 0.5 * h * pow(k.a1, 3.0 + al) * tot[10];
-    const double labar = h * (al - 3.0) * pow(k.abar, al - 4.0) * tot[11];
-    la1 += 0.5 * labar;
-    double la0 = 0.5 * labar + la1;   // (3) a1 = a_n + h b'
-    s->lb += h * la1;
-    double C, ia2, ia6, dKda, dKdq;
-    self_ka(k.a0, tot + 4, k, C, ia2, ia6, dKda, dKdq);
-    const double wl = 0.5 * h * s->lb;
-    self_bk(s, wl, C, ia2, ia6, k);
-    s->la0 = la0 + wl * dKda;
-    s->dq += wl * dKdq;
-}
-
-// (1): the field kick at n
-__global__ void self_scal_post(const double *tot, const SelfStepConst k, SelfScalars *s)
-{
-    if (threadIdx.x != 0) return;
-    const double al = k.alpha, h = k.h;
-    s->la = s->la0 + 0.5 * h * ((1.0 + al) * pow(k.a0, al) * tot[12] - (3.0 + al) * pow(k.a0, 2.0 + al) * tot[13]);
-    s->dq += 0.5 * h * pow(k.a0, 3.0 + al) * tot[14];
-}
-
-// Sum each of the nq rows of nb partials: block q, each thread a fixed strided
-// subset in order, then the fixed wave and block tree; out[q].
-__global__ void __launch_bounds__(kSelfAdjThreads) self_adj_reduce(const double *__restrict__ part, int nb, int nq,
-                                                                   double *__restrict__ out)
-{
-    __shared__ double lds[kSelfAdjThreads / 64];
-    const int q = blockIdx.x;
-    if (q >= nq) return;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nb; k += kSelfAdjThreads) s += part[(size_t)q * nb + k];
-    const double w = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = w;
-    __syncthreads();
+    constexpr int NT = kSelfAdjThreads;
+    __shared__ double lds_red[(NT / 64) * kRevQ];
+    double tot[kRevQ];
+    self_sum_partials<NT, kRevQ>(part, nb, lds_red, tot);
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kSelfAdjThreads / 64; ++i) t += lds[i];
-        out[q] = t;
+        SelfScalars s = *sc_in;
+        self_rev_finalise(P, tot, k, s);
+        *sc_out = s;
     }
 }
 

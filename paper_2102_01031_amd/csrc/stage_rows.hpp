@@ -59,17 +59,6 @@ __device__ __forceinline__ VT ldv(const T *base, unsigned i)
     return *(const VT *)((const char *)base + (size_t)(i * (unsigned)sizeof(T)));
 }
 
-// the same load, non-temporal when NT (a streaming hint: the line is not kept
-// in the caches at the expense of others, so that the lines the previous pass
-// wrote stay in the memory-side cache for this pass to read)
-template <typename VT, bool NT, typename T>
-__device__ __forceinline__ VT ldp(const T *base, unsigned i)
-{
-    const VT *q = (const VT *)((const char *)base + (size_t)(i * (unsigned)sizeof(T)));
-    if constexpr (NT) return __builtin_nontemporal_load(q);
-    else return *q;
-}
-
 template <typename VT, typename T>
 __device__ __forceinline__ void stv_nt(T *base, unsigned i, VT v)
 {
@@ -80,27 +69,24 @@ __device__ __forceinline__ void stv_nt(T *base, unsigned i, VT v)
 // stores); lane l holds x = VW l + v + 64 VW j (v < VW, j < XS / VW), so the x
 // neighbours inside a lane's group come from registers and only the two at
 // the group's ends from the LDS row.
-// Cache policy of the loads and stores in phase PH (0: the first half of the
-// march, 1: the second half) under policy LP:
-//   0  plain loads;                         stores by ScalarArgs::cached_out
-//   1  own rows non-temporal, halos plain;  stores by cached_out
-//   2  every load non-temporal;             stores by cached_out
-//   3  plain loads; stores non-temporal in the first half, plain in the second
-//   4  as 3, own-row loads non-temporal in the second half
-//   5  as 3, every load non-temporal in the second half
-// (stores: 0 by cached_out, 1 non-temporal, 2 plain)
+// Store policy in phase PH of the march (0: its first split / 8, 1: the rest)
+// under policy LP:
+//   0  stores by ScalarArgs::cached_out in both phases
+//   1  non-temporal stores in phase 0, ordinary stores in phase 1: the planes
+//      a pass writes last stay in the caches for the next pass, which marches
+//      the other way and starts on them, while the rest streams past
+// (st: 0 by cached_out, 1 non-temporal, 2 ordinary).  Loads are always
+// ordinary: non-temporal loads measured slower, since each halo row is read
+// again by the neighbouring block and loses its L2 hit.
 template <int LP, int PH>
 struct RowPolicy {
-    static constexpr bool nto = LP == 1 || LP == 2 || (PH == 1 && (LP == 4 || LP == 5));
-    static constexpr bool nth = LP == 2 || (PH == 1 && LP == 5);
-    static constexpr int st = LP <= 2 ? 0 : (PH == 0 ? 1 : 2);
+    static constexpr int st = LP == 0 ? 0 : (PH == 0 ? 1 : 2);
 };
 
 template <typename T, int NF, int XS, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI, int PF = 1,
           int VW = 1, int LP = 0>
 __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 {
-    constexpr bool NTO = RowPolicy<LP, 0>::nto, NTH = RowPolicy<LP, 0>::nth;
     static_assert(PF >= 1 && PF <= 4, "prefetch depth 1 .. 4");
     static_assert(XS % VW == 0 && VW * sizeof(T) <= 16, "vector width");
     using VT = typename RowVec<T, VW>::type;
@@ -160,17 +146,17 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
         hoff[j] = hval[j] ? x + N * hy : 0;
     }
 
-    const PassCoef C = *g.coef;
-    const T dl = (T)C.dload, c1 = (T)C.c1, c2 = (T)C.c2, de = (T)C.dend;
-    const T ka1 = (T)C.ka1, ka3 = (T)C.ka3, idx2 = (T)g.inv_dx2;
-    const T lam = (T)g.lam, qc = (T)g.q;
-    const double lamd = g.lam, qd = g.q;
     const VT vzero = (VT)T(0);
-
     T fm[XS][NF], f0[XS][NF], fp[XS][NF], p0[XS][NF], pp[XS][NF];
     // register set s (s < PF + 1) of own-row phi, pi and halo-row phi, pi loads
     VT of[PF + 1][XV][NF], op[PF + 1][XV][NF], hf[PF + 1][HPT][NF], hp[PF + 1][HPT][NF];
 
+    // first planes of the march: planes -1, 0, 1 of the own rows and plane 0
+    // of the halo rows as loaded (the drift on load is applied below, once the
+    // coefficients are known), set 0 .. PF-1 of the prefetch window.  Issued
+    // before the prologue so that their latency overlaps it.
+    VT ra[XV][NF], rpa[XV][NF], rb[XV][NF], rpb[XV][NF], rc[XV][NF], rpc[XV][NF];
+    VT rh[HPT][NF], rph[HPT][NF];
     {
         const unsigned om = (unsigned)pl(-1) * NN;
         const unsigned o0 = (unsigned)pl(0) * NN;
@@ -183,38 +169,24 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
             const T *Q = g.pi_in[f];
 #pragma unroll
             for (int j = 0; j < XV; ++j) {
-                const int x0 = VW * lane + 64 * VW * j;
-                const int o = yo + x0;
-                VT a = ldp<VT, NTO>(P, om + o);
-                if (DLOAD) a += dl * ldp<VT, NTO>(Q, om + o);
-                VT b = ldp<VT, NTO>(P, o0 + o);
-                const VT pb = ldp<VT, NTO>(Q, o0 + o);
-                if (DLOAD) b += dl * pb;
-                VT c = ldp<VT, NTO>(P, o1 + o);
-                const VT pc = ldp<VT, NTO>(Q, o1 + o);
-                if (DLOAD) c += dl * pc;
-                of[0][j][f] = ldp<VT, NTO>(P, o2 + o);
-                op[0][j][f] = ldp<VT, NTO>(Q, o2 + o);
-                *(VT *)&lds[0][f][orow + x0] = b;
-#pragma unroll
-                for (int v = 0; v < VW; ++v) {
-                    const int k = j * VW + v;
-                    fm[k][f] = vget<T>(a, v);
-                    f0[k][f] = vget<T>(b, v);
-                    p0[k][f] = vget<T>(pb, v);
-                    fp[k][f] = vget<T>(c, v);
-                    pp[k][f] = vget<T>(pc, v);
-                }
+                const int o = yo + VW * lane + 64 * VW * j;
+                ra[j][f] = ldv<VT>(P, om + o);
+                rpa[j][f] = DLOAD ? ldv<VT>(Q, om + o) : vzero;
+                rb[j][f] = ldv<VT>(P, o0 + o);
+                rpb[j][f] = ldv<VT>(Q, o0 + o);
+                rc[j][f] = ldv<VT>(P, o1 + o);
+                rpc[j][f] = ldv<VT>(Q, o1 + o);
+                of[0][j][f] = ldv<VT>(P, o2 + o);
+                op[0][j][f] = ldv<VT>(Q, o2 + o);
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
-                hf[0][j][f] = hp[0][j][f] = vzero;
+                rh[j][f] = rph[j][f] = hf[0][j][f] = hp[0][j][f] = vzero;
                 if (hval[j]) {
-                    VT h = ldp<VT, NTH>(P, o0 + hoff[j]);
-                    if (DLOAD) h += dl * ldp<VT, NTH>(Q, o0 + hoff[j]);
-                    *(VT *)&lds[0][f][hslot[j]] = h;
-                    hf[0][j][f] = ldp<VT, NTH>(P, oh1 + hoff[j]);
-                    if (DLOAD) hp[0][j][f] = ldp<VT, NTH>(Q, oh1 + hoff[j]);
+                    rh[j][f] = ldv<VT>(P, o0 + hoff[j]);
+                    if (DLOAD) rph[j][f] = ldv<VT>(Q, o0 + hoff[j]);
+                    hf[0][j][f] = ldv<VT>(P, oh1 + hoff[j]);
+                    if (DLOAD) hp[0][j][f] = ldv<VT>(Q, oh1 + hoff[j]);
                 }
             }
             // sets 1 .. PF-1: own plane 2 + s of the march, halo plane 1 + s
@@ -225,17 +197,62 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
                 for (int j = 0; j < XV; ++j) {
                     const int o = yo + VW * lane + 64 * VW * j;
-                    of[st][j][f] = ldp<VT, NTO>(P, os + o);
-                    op[st][j][f] = ldp<VT, NTO>(Q, os + o);
+                    of[st][j][f] = ldv<VT>(P, os + o);
+                    op[st][j][f] = ldv<VT>(Q, os + o);
                 }
 #pragma unroll
                 for (int j = 0; j < HPT; ++j) {
                     hf[st][j][f] = hp[st][j][f] = vzero;
                     if (hval[j]) {
-                        hf[st][j][f] = ldp<VT, NTH>(P, ohs + hoff[j]);
-                        if (DLOAD) hp[st][j][f] = ldp<VT, NTH>(Q, ohs + hoff[j]);
+                        hf[st][j][f] = ldv<VT>(P, ohs + hoff[j]);
+                        if (DLOAD) hp[st][j][f] = ldv<VT>(Q, ohs + hoff[j]);
                     }
                 }
+            }
+        }
+    }
+
+    PassCoef C = *g.coef;
+    if (g.fin) {
+        __shared__ double lds_coef[4];
+        finalise_prologue<NT, NF>(g, lds_red, lds_coef, C);
+    }
+    const T dl = (T)C.dload, c1 = (T)C.c1, c2 = (T)C.c2, de = (T)C.dend;
+    const T ka1 = (T)C.ka1, ka3 = (T)C.ka3, idx2 = (T)g.inv_dx2;
+    const T lam = (T)g.lam, qc = (T)g.q;
+    const double lamd = g.lam, qd = g.q;
+
+    // the drift on load of the first planes; plane 0 into the LDS row
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int j = 0; j < XV; ++j) {
+            const int x0 = VW * lane + 64 * VW * j;
+            VT a = ra[j][f];
+            if (DLOAD) a += dl * rpa[j][f];
+            VT b = rb[j][f];
+            const VT pb = rpb[j][f];
+            if (DLOAD) b += dl * pb;
+            VT c = rc[j][f];
+            const VT pc = rpc[j][f];
+            if (DLOAD) c += dl * pc;
+            *(VT *)&lds[0][f][orow + x0] = b;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int k = j * VW + v;
+                fm[k][f] = vget<T>(a, v);
+                f0[k][f] = vget<T>(b, v);
+                p0[k][f] = vget<T>(pb, v);
+                fp[k][f] = vget<T>(c, v);
+                pp[k][f] = vget<T>(pc, v);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (hval[j]) {
+                VT h = rh[j][f];
+                if (DLOAD) h += dl * rph[j][f];
+                *(VT *)&lds[0][f][hslot[j]] = h;
             }
         }
     }
@@ -251,7 +268,6 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                      VT (&hip)[HPT][NF], VT (&oof)[XV][NF], VT (&oop)[XV][NF], VT (&hof)[HPT][NF],
                      VT (&hop)[HPT][NF]) {
         using Pol = RowPolicy<LP, decltype(phase)::value>;
-        constexpr bool PNTO = Pol::nto, PNTH = Pol::nth;
         const bool nt_out = Pol::st == 0 ? g.cached_out == 0 : Pol::st == 1;
         const int cur = sm & 1, nxt = cur ^ 1;
         const unsigned o3 = (unsigned)pl(min(sm + 2 + PF, len)) * NN;
@@ -262,14 +278,14 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
 #pragma unroll
             for (int j = 0; j < XV; ++j) {
                 const int o = yo + VW * lane + 64 * VW * j;
-                oof[j][f] = ldp<VT, PNTO>(g.phi_in[f], o3 + o);
-                oop[j][f] = ldp<VT, PNTO>(g.pi_in[f], o3 + o);
+                oof[j][f] = ldv<VT>(g.phi_in[f], o3 + o);
+                oop[j][f] = ldv<VT>(g.pi_in[f], o3 + o);
             }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 if (hval[j]) {
-                    hof[j][f] = ldp<VT, PNTH>(g.phi_in[f], o2 + hoff[j]);
-                    if (DLOAD) hop[j][f] = ldp<VT, PNTH>(g.pi_in[f], o2 + hoff[j]);
+                    hof[j][f] = ldv<VT>(g.phi_in[f], o2 + hoff[j]);
+                    if (DLOAD) hop[j][f] = ldv<VT>(g.pi_in[f], o2 + hoff[j]);
                 }
             }
         }
@@ -397,7 +413,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     // planes ahead
     // the two phases of the march (the second starts at a multiple of PF + 1,
     // so the register sets rotate across the boundary as within a phase)
-    const int mid = LP >= 3 ? ((len / 2) / (PF + 1)) * (PF + 1) : 0;
+    const int mid = LP == 1 ? ((len * g.split / 8) / (PF + 1)) * (PF + 1) : 0;
     for (int sm = 0; sm < mid; sm += PF + 1) {
 #pragma unroll
         for (int u = 0; u <= PF; ++u) {
@@ -413,7 +429,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
         for (int u = 0; u <= PF; ++u) {
             if (sm + u < len) {
                 const int d = (u + PF) % (PF + 1);
-                plane(std::integral_constant<int, LP >= 3 ? 1 : 0>{}, sm + u, of[u], op[u], hf[u], hp[u], of[d],
+                plane(std::integral_constant<int, LP == 1 ? 1 : 0>{}, sm + u, of[u], op[u], hf[u], hp[u], of[d],
                       op[d], hf[d], hp[d]);
             }
         }
@@ -422,6 +438,13 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     if constexpr (RED) {
         double tot[NQ];
         block_sums<NT, NQ>(acc, lds_red, tot);
+        if (g.defer) {
+            if (tid == 0) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) g.partials[(size_t)lid * NQ + k] = tot[k];
+            }
+            return;
+        }
         if (tid == 0) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) store_agent(&g.partials[(size_t)lid * NQ + k], tot[k]);

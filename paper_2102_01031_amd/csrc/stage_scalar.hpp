@@ -38,6 +38,7 @@ struct ScalarArgs {
     int y_fastest;          // whole-row kernel block order: 0 z chunk fastest, 1 y tile fastest
     int down;               // whole-row kernel: march each z chunk downward
     int cached_out;         // whole-row kernel: ordinary stores (else non-temporal)
+    int split;              // whole-row kernel, phased cache policies: first phase = split/8 of the march
     double inv_dx2;
     double lam, q;
     const PassCoef *coef;   // this pass
@@ -47,6 +48,21 @@ struct ScalarArgs {
     ScaleRecord *sc;
     int last_mode;
     double alpha, kappa2, inv_vol;
+    // Deferred finalisation of the self-consistent passes of a lattice_step call.
+    // A deferring pass (defer = 1) stores its block sums to `partials` with
+    // plain stores and takes no ticket: no block waits on a device-wide fence.
+    // The next pass finalises them in its prologue (fin != null): every block
+    // sums the fin_nb partials in block order, applies the scale-factor update
+    // of fin_mode with the previous pass's coefficients fin_coef to the record
+    // fin_in, and takes the resulting kick and drift factors as its own; block 0
+    // writes the updated record to fin_out.  The kernel boundary between the
+    // passes orders the stores and loads.
+    int defer;
+    int fin_nb, fin_mode;
+    const double *fin;
+    const PassCoef *fin_coef;
+    const ScaleRecord *fin_in;
+    ScaleRecord *fin_out;
 };
 
 // Scale-factor half kicks and drift of the self-consistent mode (sec. 4.5.2,
@@ -54,10 +70,22 @@ struct ScalarArgs {
 //   E_K = sum_s <pi_s^2>/(2 a^6), E_G = sum_s <(grad+ phi_s)^2>/(2 a^2), E_V = <V>
 //   K_a = a^{2 alpha+1}/3 kappa^2 [(alpha-2) E_K + alpha E_G + (alpha+1) E_V]
 //   b += cL K_a; b += cR K_a; a' = a + h b; next drift h ((a + a')/2)^{alpha-3}
+// The outcome of a reducing pass's scale-factor update.
+struct SelfOut {
+    double a, b, t;            // after the update (b kicked, a drifted)
+    double ka1, ka3, dload;    // the next pass's kick factors and drift-on-load coefficient
+    double a0, bl;             // a at the kick point, b after the left half kick only
+};
+
+// b and a after the update, from the two powers of the current a that the
+// kernel K_a needs (a6 = a^6, p21 = a^{2 alpha + 1}).
+struct SelfPre {
+    double b, bl, a1;
+};
+
 template <int NF>
-__device__ inline void self_update(const PassCoef &C, const double *fin, ScaleRecord *S,
-                                   PassCoef *Nx, double alpha, double kappa2, double inv_vol,
-                                   double inv_dx2)
+__device__ inline SelfPre self_core_vv(const PassCoef &C, const double *fin, const ScaleRecord *S, double alpha,
+                                       double kappa2, double inv_vol, double inv_dx2, double a6, double p21)
 {
     double a = S->a, b = S->b;
     double sk = 0.0, sg = 0.0, sv = 0.0;
@@ -67,20 +95,14 @@ __device__ inline void self_update(const PassCoef &C, const double *fin, ScaleRe
         sg += fin[NF + f];
         sv += fin[2 * NF + f];
     }
-    const double EK = sk * inv_vol / (2.0 * pow(a, 6.0));
+    const double EK = sk * inv_vol / (2.0 * a6);
     const double EG = sg * inv_dx2 * inv_vol / (2.0 * a * a);
     const double EV = sv * inv_vol;
-    const double Ka = pow(a, 2.0 * alpha + 1.0) / 3.0 * kappa2 *
-                      ((alpha - 2.0) * EK + alpha * EG + (alpha + 1.0) * EV);
+    const double Ka = p21 / 3.0 * kappa2 * ((alpha - 2.0) * EK + alpha * EG + (alpha + 1.0) * EV);
     b += C.cL * Ka;
+    const double bl = b;
     b += C.cR * Ka;
-    const double a1 = a + C.h * b;
-    Nx->ka1 = pow(a1, 1.0 + alpha);
-    Nx->ka3 = pow(a1, 3.0 + alpha);
-    Nx->dload = C.h * pow(0.5 * (a + a1), alpha - 3.0);
-    S->a = a1;
-    S->b = b;
-    S->t = C.t_next;
+    return SelfPre{b, bl, a + C.h * b};
 }
 
 // Leapfrog with self-consistent expansion (staggered: a at integer times, b
@@ -93,8 +115,8 @@ __device__ inline void self_update(const PassCoef &C, const double *fin, ScaleRe
 // synchronised momenta cL = 0, cR = h/2, and the sync kick (which reduced the
 // momenta before its kick) cL = 0, cR = h/2 with h = 0.
 template <int NF>
-__device__ inline void self_update_lf(const PassCoef &C, const double *fin, ScaleRecord *S, PassCoef *Nx,
-                                      double alpha, double kappa2, double inv_vol, double inv_dx2)
+__device__ inline SelfPre self_core_lf(const PassCoef &C, const double *fin, const ScaleRecord *S, double alpha,
+                                       double kappa2, double inv_vol, double inv_dx2, double a6, double p21)
 {
     double a = S->a, b = S->b;
     double sk0 = 0.0, sk1 = 0.0, sg = 0.0, sv = 0.0;
@@ -107,19 +129,172 @@ __device__ inline void self_update_lf(const PassCoef &C, const double *fin, Scal
     }
     const double EG = sg * inv_dx2 * inv_vol / (2.0 * a * a);
     const double EV = sv * inv_vol;
-    const double pre = pow(a, 2.0 * alpha + 1.0) / 3.0 * kappa2;
-    const double K0 = pre * ((alpha - 2.0) * (sk0 * inv_vol / (2.0 * pow(a, 6.0))) + alpha * EG + (alpha + 1.0) * EV);
-    const double K1 = pre * ((alpha - 2.0) * (sk1 * inv_vol / (2.0 * pow(a, 6.0))) + alpha * EG + (alpha + 1.0) * EV);
+    const double pre = p21 / 3.0 * kappa2;
+    const double K0 = pre * ((alpha - 2.0) * (sk0 * inv_vol / (2.0 * a6)) + alpha * EG + (alpha + 1.0) * EV);
+    const double K1 = pre * ((alpha - 2.0) * (sk1 * inv_vol / (2.0 * a6)) + alpha * EG + (alpha + 1.0) * EV);
+    const double bl = b + C.cL * K0;
     b += C.cL * K0 + C.cR * K1;
-    const double a1 = a + C.h * b;
-    Nx->ka1 = pow(a1, 1.0 + alpha);
-    Nx->ka3 = pow(a1, 3.0 + alpha);
-    Nx->dload = C.h * pow(0.5 * (a + a1), alpha - 3.0);
+    return SelfPre{b, bl, a + C.h * b};
+}
+
+template <int NF>
+__device__ inline SelfPre self_core(int mode, const PassCoef &C, const double *fin, const ScaleRecord *S,
+                                    double alpha, double kappa2, double inv_vol, double inv_dx2, double a6, double p21)
+{
+    return mode == kLastSelfLF ? self_core_lf<NF>(C, fin, S, alpha, kappa2, inv_vol, inv_dx2, a6, p21)
+                               : self_core_vv<NF>(C, fin, S, alpha, kappa2, inv_vol, inv_dx2, a6, p21);
+}
+
+// The update by one thread: K_a needs pow(a, 6) and pow(a, 2 alpha + 1), the
+// next pass pow(a1, 1 + alpha), pow(a1, 3 + alpha) and pow((a + a1)/2, alpha - 3).
+template <int NF>
+__device__ inline SelfOut self_compute_mode(int mode, const PassCoef &C, const double *fin, const ScaleRecord *S,
+                                            double alpha, double kappa2, double inv_vol, double inv_dx2)
+{
+    const double a = S->a;
+    const SelfPre p = self_core<NF>(mode, C, fin, S, alpha, kappa2, inv_vol, inv_dx2, pow(a, 6.0),
+                                    pow(a, 2.0 * alpha + 1.0));
+    return SelfOut{p.a1, p.b, C.t_next, pow(p.a1, 1.0 + alpha), pow(p.a1, 3.0 + alpha),
+                   C.h * pow(0.5 * (a + p.a1), alpha - 3.0), a, p.bl};
+}
+
+// The same update by the 64 lanes of one wave (fin valid in every lane): the
+// powers of each stage are evaluated side by side in lanes 0 .. 2, so the
+// update waits for two pow latencies instead of five.  Bitwise equal to
+// self_compute_mode.
+template <int NF>
+__device__ inline SelfOut self_compute_wave(int mode, const PassCoef &C, const double *fin, const ScaleRecord *S,
+                                            double alpha, double kappa2, double inv_vol, double inv_dx2)
+{
+    const int lane = threadIdx.x & 63;
+    const double a = S->a;
+    const double e1 = pow(a, lane == 0 ? 6.0 : 2.0 * alpha + 1.0);
+    const SelfPre p = self_core<NF>(mode, C, fin, S, alpha, kappa2, inv_vol, inv_dx2, __shfl(e1, 0, 64),
+                                    __shfl(e1, 1, 64));
+    const double base = lane == 2 ? 0.5 * (a + p.a1) : p.a1;
+    const double ex = lane == 0 ? 1.0 + alpha : (lane == 1 ? 3.0 + alpha : alpha - 3.0);
+    const double e2 = pow(base, ex);
+    return SelfOut{p.a1, p.b, C.t_next, __shfl(e2, 0, 64), __shfl(e2, 1, 64), C.h * __shfl(e2, 2, 64), a, p.bl};
+}
+
+// the record after the update: a, b, t, the raw sums, and for the leapfrog the
+// kicked momenta's sums for the next kick; (a, b) at the kick point into traj
+// when the pass asks for it
+template <int NF>
+__device__ inline void self_store(int mode, const SelfOut &o, const double *fin, ScaleRecord *S, double *traj)
+{
+    if (traj) {
+        traj[0] = o.a0;
+        traj[1] = o.bl;
+    }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) S->sums[kPiPrev + f] = fin[f];
-    S->a = a1;
-    S->b = b;
-    S->t = C.t_next;
+    for (int k = 0; k < 3 * NF; ++k) S->sums[k] = fin[k];
+    if (mode == kLastSelfLF) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) S->sums[kPiPrev + f] = fin[f];
+    }
+    S->a = o.a;
+    S->b = o.b;
+    S->t = o.t;
+}
+
+template <int NF>
+__device__ inline void self_update(const PassCoef &C, const double *fin, ScaleRecord *S, PassCoef *Nx, double alpha,
+                                   double kappa2, double inv_vol, double inv_dx2)
+{
+    const SelfOut o = self_compute_mode<NF>(kLastSelf, C, fin, S, alpha, kappa2, inv_vol, inv_dx2);
+    Nx->ka1 = o.ka1;
+    Nx->ka3 = o.ka3;
+    Nx->dload = o.dload;
+    self_store<NF>(kLastSelf, o, fin, S, C.traj);
+}
+
+template <int NF>
+__device__ inline void self_update_lf(const PassCoef &C, const double *fin, ScaleRecord *S, PassCoef *Nx,
+                                      double alpha, double kappa2, double inv_vol, double inv_dx2)
+{
+    const SelfOut o = self_compute_mode<NF>(kLastSelfLF, C, fin, S, alpha, kappa2, inv_vol, inv_dx2);
+    Nx->ka1 = o.ka1;
+    Nx->ka3 = o.ka3;
+    Nx->dload = o.dload;
+    self_store<NF>(kLastSelfLF, o, fin, S, C.traj);
+}
+
+// Prologue of a pass that finalises the previous pass's deferred sums: the
+// block sums the partials in block order (as the last block of a ticketed pass
+// does), the first wave applies the update, and the new kick and drift
+// factors are returned to every thread in C.
+template <int NT, int NF, typename T>
+__device__ inline void finalise_prologue(const ScalarArgs<T> &g, double *lds_red, double *lds_coef, PassCoef &C)
+{
+    constexpr int NQ = 3 * NF;
+    const int tid = threadIdx.x;
+    double part[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) part[k] = 0.0;
+    for (int i = tid; i < g.fin_nb; i += NT) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) part[k] += g.fin[(size_t)i * NQ + k];
+    }
+    double fin[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) fin[k] = 0.0;
+    block_sums<NT, NQ>(part, lds_red, fin);
+    if (tid < 64) {
+        // the sums from thread 0 to its wave, which applies the update
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) fin[k] = __shfl(fin[k], 0, 64);
+        const SelfOut o = self_compute_wave<NF>(g.fin_mode, *g.fin_coef, fin, g.fin_in, g.alpha, g.kappa2,
+                                                g.inv_vol, g.inv_dx2);
+        if (tid == 0) {
+            lds_coef[0] = o.ka1;
+            lds_coef[1] = o.ka3;
+            lds_coef[2] = o.dload;
+            if (blockIdx.x == 0) self_store<NF>(g.fin_mode, o, fin, g.fin_out, g.fin_coef->traj);
+        }
+    }
+    __syncthreads();
+    C.ka1 = lds_coef[0];
+    C.ka3 = lds_coef[1];
+    C.dload = lds_coef[2];
+}
+
+// The deferred sums of the last pass of a call, finalised by one block of NT
+// threads (NT as the stencil kernel's, so the sums are added in the same order).
+template <int NT, int NF>
+__global__ void __launch_bounds__(NT) self_finish(const double *partials, int nb, int mode, const PassCoef *C,
+                                                  const ScaleRecord *Sin, ScaleRecord *Sout, PassCoef *Nx,
+                                                  double alpha, double kappa2, double inv_vol, double inv_dx2)
+{
+    constexpr int NQ = 3 * NF;
+    __shared__ double lds_red[(NT / 64) * NQ];
+    const int tid = threadIdx.x;
+    double part[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) part[k] = 0.0;
+    for (int i = tid; i < nb; i += NT) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) part[k] += partials[(size_t)i * NQ + k];
+    }
+    double fin[NQ];
+    block_sums<NT, NQ>(part, lds_red, fin);
+    if (tid == 0) {
+        const SelfOut o = self_compute_mode<NF>(mode, *C, fin, Sin, alpha, kappa2, inv_vol, inv_dx2);
+        Nx->ka1 = o.ka1;
+        Nx->ka3 = o.ka3;
+        Nx->dload = o.dload;
+        if (Sout != Sin) {
+            // carry what the update does not rewrite (the leapfrog's momentum sums)
+            for (int k = 0; k < kMaxQ; ++k) Sout->sums[k] = Sin->sums[k];
+        }
+        self_store<NF>(mode, o, fin, Sout, C->traj);
+    }
+}
+
+// copy of a record (one thread)
+__global__ void record_copy(const ScaleRecord *src, ScaleRecord *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
 }
 
 template <typename T, int NF, int TX, int TY, bool DLOAD, bool DEND, bool RED, bool WPHI, bool WPI>
@@ -175,7 +350,11 @@ __global__ void __launch_bounds__(TX *TY) scalar_stage(const ScalarArgs<T> g)
         hoff = hx + N * hy;
     }
 
-    const PassCoef C = *g.coef;
+    PassCoef C = *g.coef;
+    if (g.fin) {
+        __shared__ double lds_coef[4];
+        finalise_prologue<NT, NF>(g, lds_red, lds_coef, C);
+    }
     const T dl = (T)C.dload, c1 = (T)C.c1, c2 = (T)C.c2, de = (T)C.dend;
     const T ka1 = (T)C.ka1, ka3 = (T)C.ka3, idx2 = (T)g.inv_dx2;
     const T lam = (T)g.lam, qc = (T)g.q;
@@ -323,6 +502,13 @@ __global__ void __launch_bounds__(TX *TY) scalar_stage(const ScalarArgs<T> g)
     if constexpr (RED) {
         double tot[NQ];
         block_sums<NT, NQ>(acc, lds_red, tot);
+        if (g.defer) {
+            if (tid == 0) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) g.partials[(size_t)lid * NQ + k] = tot[k];
+            }
+            return;
+        }
         if (tid == 0) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) store_agent(&g.partials[(size_t)lid * NQ + k], tot[k]);

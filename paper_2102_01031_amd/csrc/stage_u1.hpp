@@ -1,4 +1,6 @@
-// stage_u1.hpp -- one pass of the U(1) (Abelian-Higgs) lattice system, a = 1.
+// stage_u1.hpp -- one pass of the U(1) (Abelian-Higgs) lattice system (the
+// forces below at a = 1; in an expanding background each term carries its
+// power of a, see U1Args).
 //
 // Complex scalar phi = (phi0 + i phi1)/sqrt(2) (eq. ChargedScalars); psi = phi0 + i phi1.
 // Links V_i(n) = exp(-i e dx A_i(n)); plaquette angle (U(1) toolkit, sec. 3.2)
@@ -32,8 +34,16 @@ struct U1Args {
     double *piA[3];
     int N, tiles_x, tiles_y, zc;
     double dx, e, lam, v, kappa_g;
-    double ck;   // kick weight
-    double hd;   // drift weight
+    double ck;   // kick weight (time)
+    double hd;   // drift weight of phi (time times a^{alpha-3})
+    // expanding background (sec. 5.5.2 kernels): the covariant Laplacian and the
+    // current scale with la1 = a^{1+alpha}, the potential force with
+    // la3 = a^{3+alpha}, the magnetic force with lam1 = a^{alpha-1}; hdA is the
+    // drift weight of A (time times a^{alpha-1}).  All 1 (hdA = hd) at a = 1.
+    double la1, la3, lam1, hdA;
+    // if not null: {ck, la1, la3, lam1, hd, hdA} from device memory (written by
+    // the self-consistent scale-factor kernels), in place of the values above
+    const double *dw;
     double *partials;
     unsigned *ticket;
     ScaleRecord *sc;
@@ -118,15 +128,24 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
                 grad2 += dr * dr + di * di;
             }
         }
+        double ck = g.ck, la1 = g.la1, la3 = g.la3, lm1 = g.lam1, hdP = g.hd, hdA = g.hdA;
+        if (g.dw) {
+            ck = g.dw[0];
+            la1 = g.dw[1];
+            la3 = g.dw[2];
+            lm1 = g.dw[3];
+            hdP = g.dw[4];
+            hdA = g.dw[5];
+        }
         const double m2 = 0.5 * (pr * pr + pim * pim);
         const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
         const double inv_dx2 = 1.0 / (g.dx * g.dx);
-        const double F0 = d2r * inv_dx2 - vp * pr;
-        const double F1 = d2i * inv_dx2 - vp * pim;
+        const double F0 = la1 * (d2r * inv_dx2) - la3 * (vp * pr);
+        const double F1 = la1 * (d2i * inv_dx2) - la3 * (vp * pim);
         const double inv_edx3 = 1.0 / (g.e * g.dx * g.dx * g.dx);
         double FA[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) FA[i] = g.kappa_g * J[i] - mag[i] * inv_edx3;
+        for (int i = 0; i < 3; ++i) FA[i] = la1 * (g.kappa_g * J[i]) - lm1 * (mag[i] * inv_edx3);
 
         const double p0 = g.pi[0][n], p1 = g.pi[1][n];
         double pa[3];
@@ -134,7 +153,7 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
         for (int i = 0; i < 3; ++i) pa[i] = g.piA[i][n];
 
         if (MODE == kU1Energy) {
-            const double s0 = p0 + g.ck * F0, s1 = p1 + g.ck * F1;
+            const double s0 = p0 + ck * F0, s1 = p1 + ck * F1;
             acc[0] = 0.5 * (s0 * s0 + s1 * s1);
             acc[1] = grad2 * inv_dx2 * 0.5;
             const double u = m2 - g.v * g.v;
@@ -142,7 +161,7 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
             double ka = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double sa = pa[i] + g.ck * FA[i];
+                const double sa = pa[i] + ck * FA[i];
                 ka += sa * sa;
             }
             acc[3] = ka / (2.0 * g.kappa_g);
@@ -160,20 +179,20 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
             acc[9] = fabs(div);
             acc[10] = fabs(charge);
         } else {
-            const double q0 = p0 + g.ck * F0, q1 = p1 + g.ck * F1;
+            const double q0 = p0 + ck * F0, q1 = p1 + ck * F1;
             g.pi[0][n] = q0;
             g.pi[1][n] = q1;
             double qa[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                qa[i] = pa[i] + g.ck * FA[i];
+                qa[i] = pa[i] + ck * FA[i];
                 g.piA[i][n] = qa[i];
             }
             if (MODE == kU1Step) {
-                g.phi_out[0][n] = pr + g.hd * q0;
-                g.phi_out[1][n] = pim + g.hd * q1;
+                g.phi_out[0][n] = pr + hdP * q0;
+                g.phi_out[1][n] = pim + hdP * q1;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) g.A_out[i][n] = g.A_in[i][n] + g.hd * qa[i];
+                for (int i = 0; i < 3; ++i) g.A_out[i][n] = g.A_in[i][n] + hdA * qa[i];
             }
         }
     }
@@ -228,6 +247,81 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
                 __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Self-consistent expansion of the U(1) model (sec. 5.5.2, the b' equation with
+// the gauge energies): one-thread kernels between the lattice passes.  An
+// energy pass with ck = 0 leaves the raw volume sums in ScaleRecord::sums[0..4]
+// (pi part, gradient, potential, electric, magnetic; the a = 1 forms), from
+// which the energies at a are
+//   E_K = S0/(V a^6), E_G = S1/(V a^2), E_V = S2/V, E_K^A = S3/(V a^4), E_G^A = S4/(V a^4),
+// and the kernel of b is
+//   K_a = a^{2 alpha+1}/3 kappa^2 [(alpha-2) E_K + alpha E_G + (alpha-1)(E_K^A + E_G^A) + (alpha+1) E_V].
+// The weights of the next pass go to ScaleRecord::w in U1Args::dw order.
+// ---------------------------------------------------------------------------
+struct U1SelfConst {
+    double alpha, kappa2, inv_vol;
+};
+
+__device__ inline double u1_kernel_b(double a, const double *S, const U1SelfConst &k)
+{
+    const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+    const double EK = S[0] * k.inv_vol / a6, EG = S[1] * k.inv_vol / a2, EV = S[2] * k.inv_vol;
+    const double EA = S[3] * k.inv_vol / a4 + S[4] * k.inv_vol / a4;
+    const double al = k.alpha;
+    return pow(a, 2.0 * al + 1.0) / 3.0 * k.kappa2 *
+           ((al - 2.0) * EK + al * EG + (al - 1.0) * EA + (al + 1.0) * EV);
+}
+
+// kick weights at the record's a: {ck, a^{1+alpha}, a^{3+alpha}, a^{alpha-1}, 0, 0}
+__global__ void u1_self_kick_w(ScaleRecord *S, double ck, double alpha)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double a = S->a;
+        S->w[0] = ck;
+        S->w[1] = pow(a, 1.0 + alpha);
+        S->w[2] = pow(a, 3.0 + alpha);
+        S->w[3] = pow(a, alpha - 1.0);
+        S->w[4] = 0.0;
+        S->w[5] = 0.0;
+    }
+}
+
+// keep the sums of the state before a kick (sums[8..12])
+__global__ void u1_self_stash(ScaleRecord *S)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (int k = 0; k < 5; ++k) S->sums[8 + k] = S->sums[k];
+}
+
+// b += w K_a(a, sums[0..4]) (the sync's half kick, or a velocity-Verlet half kick)
+__global__ void u1_self_b_kick(ScaleRecord *S, double w, U1SelfConst k)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) S->b += w * u1_kernel_b(S->a, S->sums, k);
+}
+
+// Leapfrog (reading A3): b += cL K_a(before, sums[8..12]) + cR K_a(after, sums[0..4]);
+// velocity-Verlet (reading R1, cL = 0): b += cR K_a(sums[0..4]).  Then a' = a + h b and
+// the drift weights {0, 1, 1, 1, h abar^{alpha-3}, h abar^{alpha-1}}, abar = (a + a')/2.
+__global__ void u1_self_drift_w(ScaleRecord *S, double h, double cL, double cR, U1SelfConst k)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double a = S->a;
+        double b = S->b;
+        if (cL != 0.0) b += cL * u1_kernel_b(a, S->sums + 8, k);
+        b += cR * u1_kernel_b(a, S->sums, k);
+        const double a1 = a + h * b;
+        const double am = 0.5 * (a + a1);
+        S->w[0] = 0.0;
+        S->w[1] = 1.0;
+        S->w[2] = 1.0;
+        S->w[3] = 1.0;
+        S->w[4] = h * pow(am, k.alpha - 3.0);
+        S->w[5] = h * pow(am, k.alpha - 1.0);
+        S->a = a1;
+        S->b = b;
     }
 }
 
@@ -286,7 +380,15 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
     const double edx = g.e * g.dx;
     const double inv_dx2 = 1.0 / (g.dx * g.dx);
     const double inv_edx3 = 1.0 / (g.e * g.dx * g.dx * g.dx);
-    const double ck = g.ck, hd = g.hd;
+    double ck = g.ck, la1 = g.la1, la3 = g.la3, lm1 = g.lam1, hd = g.hd, hdA = g.hdA;
+    if (g.dw) {
+        ck = g.dw[0];
+        la1 = g.dw[1];
+        la3 = g.dw[2];
+        lm1 = g.dw[3];
+        hd = g.dw[4];
+        hdA = g.dw[5];
+    }
 
     // halo cells: c < NX is row 0 (y0 - 1), else row TY + 1 (y0 + TY)
     int hrow[HPT], hx[HPT];
@@ -490,8 +592,8 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             }
             const double m2 = 0.5 * (pr * pr + pim * pim);
             const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
-            const double F0 = d2r * inv_dx2 - vp * pr;
-            const double F1 = d2i * inv_dx2 - vp * pim;
+            const double F0 = la1 * (d2r * inv_dx2) - la3 * (vp * pr);
+            const double F1 = la1 * (d2i * inv_dx2) - la3 * (vp * pim);
             const double q0 = pq[0] + ck * F0, q1 = pq[1] + ck * F1;
             st32(g.pi[0], o, q0);
             st32(g.pi[1], o, q1);
@@ -499,10 +601,10 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             st32(g.phi_out[1], o, pim + hd * q1);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double FA = g.kappa_g * J[i] - mag[i] * inv_edx3;
+                const double FA = la1 * (g.kappa_g * J[i]) - lm1 * (mag[i] * inv_edx3);
                 const double qa = pa[i] + ck * FA;
                 st32(g.piA[i], o, qa);
-                st32(g.A_out[i], o, a0[i] + hd * qa);
+                st32(g.A_out[i], o, a0[i] + hdA * qa);
             }
             czm = s_cz[wo];
             szm = s_sz[wo];

@@ -1,9 +1,11 @@
 """Turn rocprofv3 outputs of the benchmark into the committed summaries.
 
 Inputs (directories written by rocprofv3 -d ... --output-format csv):
-  --trace DIR        --kernel-trace --stats run of bench.py
-  --fetch DIR        --pmc FETCH_SIZE run of bench.py
-  --write DIR        --pmc WRITE_SIZE run of bench.py
+  --trace DIR...     --kernel-trace --stats runs of bench.py
+  --fetch DIR...     --pmc FETCH_SIZE runs of bench.py
+  --write DIR...     --pmc WRITE_SIZE runs of bench.py
+                     (one directory per profiled command, in the order of
+                     --command; float64 and float32 runs give separate rows)
   --copy-fetch DIR   --pmc FETCH_SIZE run of pmc_copy.py
   --copy-write DIR   --pmc WRITE_SIZE run of pmc_copy.py
 Outputs: profiles/pmc_stage_preheat256.json (read by bench.py for
@@ -93,12 +95,12 @@ def all_kernels(trace_dir, command, out_dir):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--trace", required=True, nargs="+")
+    ap.add_argument("--fetch", required=True, nargs="+")
+    ap.add_argument("--write", required=True, nargs="+")
     ap.add_argument("--copy-fetch", required=True)
     ap.add_argument("--copy-write", required=True)
-    ap.add_argument("--command", required=True, help="the bench command that was profiled")
+    ap.add_argument("--command", required=True, nargs="+", help="the bench commands that were profiled")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     ap.add_argument("--all-trace", help="--kernel-trace --stats run of the whole default benchmark")
     ap.add_argument("--all-command", default="python3 bench.py --no-cpu-baseline")
@@ -110,21 +112,24 @@ def main():
     ff, fk = copy_factor(a.copy_fetch, "FETCH_SIZE")
     wf, wk = copy_factor(a.copy_write, "WRITE_SIZE")
     per = defaultdict(dict)
-    for counter, d, fac in (("FETCH_SIZE", a.fetch, ff), ("WRITE_SIZE", a.write, wf)):
-        for name, vals in counters(d, counter).items():
-            k = variant_key(name)
-            if k:
-                per[k][counter] = sum(vals) / len(vals)
-                per[k][counter + "_scaled_bytes"] = fac * per[k][counter] * 1024
-                per[k]["launches"] = len(vals)
-                per[k]["kernel_name"] = name
-    stats = list(csv.DictReader(open(csv_in(a.trace, "kernel_stats.csv"))))
-    trace = list(csv.DictReader(open(csv_in(a.trace, "kernel_trace.csv"))))
+    for counter, dirs, fac in (("FETCH_SIZE", a.fetch, ff), ("WRITE_SIZE", a.write, wf)):
+        for d in dirs:
+            for name, vals in counters(d, counter).items():
+                k = variant_key(name)
+                if k:
+                    per[k][counter] = sum(vals) / len(vals)
+                    per[k][counter + "_scaled_bytes"] = fac * per[k][counter] * 1024
+                    per[k]["launches"] = len(vals)
+                    per[k]["kernel_name"] = name
+    stats = []
     dur = defaultdict(list)
-    for r in trace:
-        k = variant_key(r["Kernel_Name"])
-        if k:
-            dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    for d in a.trace:
+        stats += list(csv.DictReader(open(csv_in(d, "kernel_stats.csv"))))
+        for r in csv.DictReader(open(csv_in(d, "kernel_trace.csv"))):
+            k = variant_key(r["Kernel_Name"])
+            if k:
+                dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
     kernels = {}
     for k, d in per.items():
         kernels[k] = {
@@ -135,18 +140,20 @@ def main():
             "mean_us_trace": sum(dur[k]) / len(dur[k]) if dur.get(k) else None,
             "kernel_name": d.get("kernel_name"),
         }
-    out = {"kernel_hash": kernel_hash(), "command": a.command,
+    out = {"kernel_hash": kernel_hash(), "command": " ; ".join(a.command),
            "fetch_factor": ff, "write_factor": wf, "copy_fetch_kib": fk, "copy_write_kib": wk,
            "copy_bytes": COPY_BYTES, "kernels": kernels}
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, "pmc_stage_preheat256.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     lines = ["# scalar stage kernel, preheat-256^3-VV4-self workload", "",
-             f"Profiled command: `{a.command}`", "",
-             "rocprofv3 runs (each its own pass):", "",
-             f"- `rocprofv3 --kernel-trace --stats -d <dir> -o trace --output-format csv -- {a.command}`",
-             f"- `rocprofv3 --pmc FETCH_SIZE -d <dir> -o fetch --output-format csv -- {a.command}`",
-             f"- `rocprofv3 --pmc WRITE_SIZE -d <dir> -o write --output-format csv -- {a.command}`",
+             "Profiled commands: " + ", ".join(f"`{c}`" for c in a.command), "",
+             "rocprofv3 runs (each its own pass, for each command):", ""]
+    for c in a.command:
+        lines += [f"- `rocprofv3 --kernel-trace --stats -d <dir> -o trace --output-format csv -- {c}`",
+                  f"- `rocprofv3 --pmc FETCH_SIZE -d <dir> -o fetch --output-format csv -- {c}`",
+                  f"- `rocprofv3 --pmc WRITE_SIZE -d <dir> -o write --output-format csv -- {c}`"]
+    lines += [
              "- the same two counter runs on `python3 paper_2102_01031_amd/pmc_copy.py` (1 GiB device copy)",
              "", f"Kernel source hash: `{out['kernel_hash']}`", ""] + ([a.note, ""] if a.note else []) + [
              

@@ -79,8 +79,9 @@ def test_integrator_expansion_matrix(integ, expn):
                                                 ("vv10", "self", 16, 1), ("vv6", "none", 64, 2),
                                                 ("vv8", "self", 64, 1)])
 def test_higher_order_vv(integ, expn, N, steps):
-    """VV6 / VV8 / VV10 (9, 27, 81 kick points per step, the recursive triple
-    jump) on the tiled and on the whole-row kernel, against the oracle."""
+    """VV6 / VV8 / VV10 (7, 15, 45 kick points per step: Yoshida's solutions
+    A and D and the triple jump of D) on the tiled and on the whole-row kernel,
+    against the oracle."""
     wl = workloads.PREHEAT_128
     phi, pi = wl.initial_fields(N=N)
     kw = scalar_kwargs(wl, N=N, integrator=integ, expansion=expn)
@@ -462,3 +463,26 @@ def test_long_call_runs_as_bounded_chunks(integ, expn, steps, chunks):
     compare_energy(e1, st.energy(), 1e-11, "long call")
     lat1.close()
     lat2.close()
+
+
+@pytest.mark.parametrize("N,integ", [(20, "vv2"), (64, "vv4")])
+def test_energy_after_self_consistent_step_uses_the_last_pass_sums(N, integ):
+    """After a velocity-Verlet call with self-consistent expansion the energies
+    come from the sums the call's last pass reduced: no energy pass runs, the
+    result matches the oracle at 1e-12 and repeats exactly."""
+    wl = workloads.PREHEAT_128
+    phi, pi = wl.initial_fields(N=N)
+    kw = scalar_kwargs(wl, N=N, integrator=integ, expansion="self")
+    lat, tp, tq = gpu_scalar(kw, phi, pi, [4])
+    lat.stats(reset=True)
+    lat.profile(True)
+    e1 = lat.energy()
+    e2 = lat.energy()
+    st_ = lat.stats(reset=True)
+    lat.profile(False)
+    assert st_["launches"].get("energy", 0) == 0
+    assert e1 == e2
+    ref = oracle.ScalarState(oracle_model(kw), phi, pi).run(4)
+    compare_state(tp, tq, ref, TOL, "reuse")
+    compare_energy(e1, ref.energy(), TOL, "reuse")
+    lat.close()
