@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const T dl = (T)C.dload, c1 = (T)C.c1, c2 = (T)C.c2, de = (T)C.dend;
     const T ka1 = (T)C.ka1, ka3 = (T)C.ka3, idx2 = (T)g.inv_dx2;
     const T lam = (T)g.lam, qc = (T)g.q;
-    const double lamd = g.lam, qd = g.q;
+    const T qv4 = (T)(0.25 * g.lam), qv2 = (T)(0.5 * g.q);   // V = lam/4 u^4 + q/2 u^2 v^2
 
     // the drift on load of the first planes; plane 0 into the LDS row
 #pragma unroll
@@ -355,24 +355,19 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
                     const T F = ka1 * lap[f] - ka3 * dV[f];
                     const T pm = p0[k][f] + c1 * F;
                     if (RED && valid) {
-                        const double pmd = (double)pm;
-                        acc[f] += pmd * pmd;
-                        const double gx = (double)(xp[f] - f0[k][f]);
-                        const double gy = (double)(yp[f] - f0[k][f]);
-                        const double gz = (double)(zpv[f] - f0[k][f]);
-                        acc[NF + f] += gx * gx + gy * gy + gz * gz;
+                        // site terms in the field precision, volume sums in float64
+                        const T gx = xp[f] - f0[k][f], gy = yp[f] - f0[k][f], gz = zpv[f] - f0[k][f];
+                        acc[f] += (double)(pm * pm);
+                        acc[NF + f] += (double)(gx * gx + gy * gy + gz * gz);
                     }
                     const T pn = pm + c2 * F;
                     vset<T>(fov[f], v, DEND ? f0[k][f] + de * pn : f0[k][f]);
                     vset<T>(pnv[f], v, pn);
                 }
                 if (RED && valid) {
-                    const double u = (double)f0[k][0];
-                    acc[2 * NF] += 0.25 * lamd * u * u * u * u;
-                    if constexpr (NF == 2) {
-                        const double v2 = (double)f0[k][1];
-                        acc[2 * NF + 1] += 0.5 * qd * u * u * v2 * v2;
-                    }
+                    const T u2 = f0[k][0] * f0[k][0];
+                    acc[2 * NF] += (double)(qv4 * u2 * u2);
+                    if constexpr (NF == 2) acc[2 * NF + 1] += (double)(qv2 * u2 * (f0[k][1] * f0[k][1]));
                 }
             }
             if (valid) {
