@@ -44,8 +44,10 @@ class U1Params(C.Structure):
 
 
 class SU2Params(C.Structure):
-    _fields_ = [("N", C.c_int32), ("pad", C.c_int32), ("dx", C.c_double), ("dt", C.c_double),
-                ("lam", C.c_double), ("v", C.c_double), ("g", C.c_double)]
+    _fields_ = [("N", C.c_int32), ("expansion", C.c_int32), ("dx", C.c_double), ("dt", C.c_double),
+                ("lam", C.c_double), ("v", C.c_double), ("g", C.c_double),
+                ("alpha", C.c_double), ("kappa2", C.c_double),
+                ("w_eos", C.c_double), ("H0", C.c_double), ("t0", C.c_double), ("a0", C.c_double)]
 
 
 _lib = None
@@ -101,6 +103,9 @@ def lib():
         L.orc_u1_forces_at.argtypes = [C.POINTER(U1Params), C.c_double, pp, pp, pp, pp]
         L.orc_u1_hubble_b0.argtypes = [C.POINTER(U1Params), pp, pp, pp, pp, C.c_double, dp]
         L.orc_su2_gauss_init.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, dp]
+        L.orc_su2_fixed_background.argtypes = [C.POINTER(SU2Params), C.c_double, dp, dp]
+        L.orc_su2_forces_at.argtypes = [C.POINTER(SU2Params), C.c_double, pp, pp, pp, pp]
+        L.orc_su2_hubble_b0.argtypes = [C.POINTER(SU2Params), pp, pp, pp, pp, C.c_double, dp]
         L.orc_u1_gauss_init.argtypes = [C.POINTER(U1Params), pp, pp, pp, dp]
         L.orc_vv_stages.argtypes = [C.c_int, dp]
         L.orc_vv_stages.restype = C.c_int
@@ -491,22 +496,57 @@ class SU2Model:
     lam: float = 1.0
     v: float = 1.0
     g: float = 0.5
+    expansion: int = NONE
+    alpha: float = 1.0
+    kappa2: float = 0.25
+    w_eos: float = 1.0 / 3.0
+    H0: float = 0.0
+    t0: float = 0.0
+    a0: float = 1.0
 
     def cparams(self) -> SU2Params:
-        return SU2Params(self.N, 0, self.dx, self.dt, self.lam, self.v, self.g)
+        return SU2Params(self.N, self.expansion, self.dx, self.dt, self.lam, self.v, self.g, self.alpha,
+                         self.kappa2, self.w_eos, self.H0, self.t0, self.a0)
 
 
 class SU2State:
     """phi: 4 real doublet components, pi: 4, U: 12 link arrays (link i, quaternion
-    component k at index 4 i + k), E: 9 electric arrays (link i, colour a at 3 i + a)."""
+    component k at index 4 i + k), E: 9 electric arrays (link i, colour a at 3 i + a).
+    With expansion the clock holds a and b = a' (fixed background: the closed
+    form at t; self-consistent: a0 and b from the Hubble constraint unless given)."""
 
-    def __init__(self, model: SU2Model, phi, pi, U, E, t=0.0, lf_stag=0):
+    def __init__(self, model: SU2Model, phi, pi, U, E, t=0.0, lf_stag=0, a=None, b=None):
         self.m = model
         cp = lambda L: [np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1)).copy() for f in L]
         self.phi, self.pi, self.U, self.E = cp(phi), cp(pi), cp(U), cp(E)
         assert len(self.phi) == 4 and len(self.pi) == 4 and len(self.U) == 12 and len(self.E) == 9
         self._p = model.cparams()
-        self.clock = Clock(t, 1.0, 0.0, lf_stag, 0)
+        if model.expansion == FIXED:
+            aa, bb = C.c_double(), C.c_double()
+            _chk(lib().orc_su2_fixed_background(C.byref(self._p), float(t), C.byref(aa), C.byref(bb)), "su2 fixed")
+            a = aa.value if a is None else a
+            b = bb.value if b is None else b
+        elif model.expansion == SELF:
+            a = model.a0 if a is None else a
+            if b is None:
+                bb = C.c_double()
+                _chk(lib().orc_su2_hubble_b0(C.byref(self._p), *self._args(), float(a), C.byref(bb)), "su2 b0")
+                b = bb.value
+        else:
+            a, b = 1.0, 0.0
+        self.clock = Clock(t, a, b, lf_stag, 0)
+
+    @property
+    def a(self):
+        return self.clock.a
+
+    @property
+    def b(self):
+        return self.clock.b
+
+    @property
+    def t(self):
+        return self.clock.t
 
     def _args(self):
         return _pp(self.phi), _pp(self.pi), _pp(self.U), _pp(self.E)
@@ -520,9 +560,19 @@ class SU2State:
         return self
 
     def energy(self) -> dict:
-        out = np.zeros(12)
+        out = np.zeros(17)
         _chk(lib().orc_su2_energy(C.byref(self._p), *self._args(), C.byref(self.clock), _dp(out)), "su2 energy")
-        return _su2_dict(out)
+        d = _su2_dict(out)
+        d.update(a=out[12], b=out[13], hubble_lhs=out[14], hubble_rhs=out[15], hubble_res=out[16],
+                 t=self.clock.t)
+        return d
+
+    def forces_at(self, a):
+        """Forces (kicks per unit time) at scale factor a."""
+        F = [np.zeros_like(self.phi[0]) for _ in range(13)]
+        _chk(lib().orc_su2_forces_at(C.byref(self._p), float(a), _pp(self.phi), _pp(self.U), _pp(F[:4]),
+                                     _pp(F[4:])), "su2 forces at a")
+        return F[:4], F[4:]
 
     def gauss(self) -> dict:
         out = np.zeros(12)

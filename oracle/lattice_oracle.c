@@ -49,14 +49,16 @@
  *   R5  U(1): compact formulation of the U(1) toolkit (sec. 3.2) with the
  *       plaquette V_i V_{j,+i} V*_{i,+j} V*_j and kicks equal to minus the
  *       derivative of the lattice Hamiltonian.  The complex field carries the
- *       1/sqrt(2) normalisation of eq. ChargedScalars.  Only a = 1.
+ *       1/sqrt(2) normalisation of eq. ChargedScalars.  With expansion the
+ *       terms take the powers of a of reading U1 (at the U(1) code).
  *   R6  SU(2): compact formulation of the SU(N) toolkit (sec. 3.2) for a
  *       doublet and SU(2) links, Hamiltonian form with the electric field
  *       conjugate to the link under left multiplication, kicks equal to minus
  *       the derivative of the lattice Hamiltonian and the link drift
  *       U <- exp(-i h g dx E^a T_a) U; the magnetic term 2/(g^2 dx^4) (2 - Tr P)
  *       per plaquette is the normalisation the toolkit's expansion of Tr P
- *       fixes.  Only a = 1.
+ *       fixes.  With expansion the terms take the powers of a of reading U1
+ *       (below, at the SU(2) code).
  *   R14 Gauss-consistent initial gauge momenta: with the links at the
  *       identity (the initial condition of sec. 5.5.1) the Gauss law is the
  *       plain lattice divergence div- E = rho; its longitudinal solution uses
@@ -1697,9 +1699,25 @@ int orc_occupation(const orc_params *p, double a, double bdot, double *const *ph
 #include <complex.h>
 
 typedef struct orc_su2_params {
-    int32_t N, pad;
+    int32_t N;
+    int32_t expansion;                      /* ORC_NONE, ORC_FIXED, ORC_SELF (as for the scalars) */
     double dx, dt, lambda, v, g;
+    double alpha, kappa2;                   /* alpha-time exponent; (f_star/m_p)^2 */
+    double w_eos, H0, t0, a0;               /* fixed background (eq. ScaleFactorPowerLaw); SELF: a0 */
 } orc_su2_params;
+
+/* SU(2) sector in an expanding background (sec. 5.5.2, reading U1 applied to
+ * the doublet and its links).  With pi_Phi = a^{3-alpha} Phi' and
+ * pi_B = a^{1-alpha} G_0i (eqs. momSU2doublet, momSU2vec) the kernels of eq.
+ * kernelsSU21 and the one after it are the a = 1 forces with each term scaled:
+ *   K_Phi = a^{1+alpha} (covariant Laplacian) - a^{3+alpha} (potential force),
+ *   K_B   = a^{1+alpha} J - a^{alpha-1} (staple force),
+ * the drifts are Phi' = a^{alpha-3} pi_Phi and U <- exp(-i h a^{alpha-1} g dx
+ * E^a T_a) U, the energies are the a = 1 ones over a^6 (doublet kinetic), a^2
+ * (doublet gradient) and a^4 (electric, magnetic), and the scale-factor
+ * kernel adds (alpha - 1)(E_K^B + E_G^B).  The Gauss law (eq. GaussSU2-eom)
+ * in these variables carries no power of a.  Kicks and drifts take a as the
+ * U(1) model does (readings R3, R1, A3). */
 
 typedef struct { double complex m[2][2]; } mat2;
 
@@ -1783,11 +1801,12 @@ static void shift(int N, const int *c, int d, int s, int *o)
  *   with the staples S+_ij = U_j(n+i) U_i(n+j)^dag U_j(n)^dag and
  *   S-_ij = U_j(n+i-j)^dag U_i(n-j)^dag U_j(n-j), and vec_a[M] = u_a of
  *   M = u0 I - i u.sigma, i.e. -d Tr(exp(-i eps g dx T_a) U S)/d eps = g dx vec_a.  */
-int orc_su2_forces(const orc_su2_params *p, double *const *phi, double *const *U,
-                   double *const *Fphi, double *const *FE)
+static int su2_forces_a(const orc_su2_params *p, double a, double *const *phi, double *const *U,
+                        double *const *Fphi, double *const *FE)
 {
     int N = p->N;
     double dx = p->dx, g = p->g;
+    double cl = pow(a, 1.0 + p->alpha), cv = pow(a, 3.0 + p->alpha), cm_ = pow(a, p->alpha - 1.0);
     #pragma omp parallel for schedule(static)
     for (int z = 0; z < N; ++z)
         for (int y = 0; y < N; ++y)
@@ -1831,24 +1850,37 @@ int orc_su2_forces(const orc_su2_params *p, double *const *phi, double *const *U
                         double complex t = 0.0;
                         for (int r = 0; r < 2; ++r)
                             for (int s = 0; s < 2; ++s) t += conj(psi[r]) * 0.5 * PAULI[k][r][s] * a[s];
-                        FE[3 * i + k][n] = g / dx * cimag(t) - 2.0 / (g * dx * dx * dx) * vs[k];
+                        FE[3 * i + k][n] = cl * (g / dx * cimag(t)) - cm_ * (2.0 / (g * dx * dx * dx) * vs[k]);
                     }
                 }
                 double m2 = 0.0;
                 for (int k = 0; k < 4; ++k) m2 += 0.5 * phi[k][n] * phi[k][n];
                 double vp = 0.5 * p->lambda * (m2 - p->v * p->v);
-                Fphi[0][n] = creal(d2[0]) / (dx * dx) - vp * phi[0][n];
-                Fphi[1][n] = cimag(d2[0]) / (dx * dx) - vp * phi[1][n];
-                Fphi[2][n] = creal(d2[1]) / (dx * dx) - vp * phi[2][n];
-                Fphi[3][n] = cimag(d2[1]) / (dx * dx) - vp * phi[3][n];
+                Fphi[0][n] = cl * (creal(d2[0]) / (dx * dx)) - cv * (vp * phi[0][n]);
+                Fphi[1][n] = cl * (cimag(d2[0]) / (dx * dx)) - cv * (vp * phi[1][n]);
+                Fphi[2][n] = cl * (creal(d2[1]) / (dx * dx)) - cv * (vp * phi[2][n]);
+                Fphi[3][n] = cl * (cimag(d2[1]) / (dx * dx)) - cv * (vp * phi[3][n]);
             }
     return 0;
+}
+
+int orc_su2_forces(const orc_su2_params *p, double *const *phi, double *const *U,
+                   double *const *Fphi, double *const *FE)
+{
+    return su2_forces_a(p, 1.0, phi, U, Fphi, FE);
+}
+
+int orc_su2_forces_at(const orc_su2_params *p, double a, double *const *phi, double *const *U,
+                      double *const *Fphi, double *const *FE)
+{
+    return su2_forces_a(p, a, phi, U, Fphi, FE);
 }
 
 /* SU(2) energies and Gauss constraint.  Output layout (12 doubles):
  *  [0] E_K^Phi = <sum_c pi_c^2 / 2>, [1] E_G^Phi = <sum_i |U_i psi(n+i) - psi(n)|^2>/(2 dx^2),
  *  [2] E_V = <lambda/4 (|Phi|^2 - v^2)^2>, [3] E_K^B = <sum_{i,a} (E_i^a)^2>/2,
- *  [4] E_G^B = <2/(g^2 dx^4) sum_{i<j} (2 - Tr P_ij)>, [5] rho,
+ *  [4] E_G^B = <2/(g^2 dx^4) sum_{i<j} (2 - Tr P_ij)>, [5] rho
+ *  (at scale factor a: [0] over a^6, [1] over a^2, [3] and [4] over a^4),
  *  [6] max|G|, [7] max|div E|, [8] max|charge|, [9] <|G|>, [10] <|div E + charge|>,
  *  [11] <|div E| + |charge|>, with |.| the Euclidean norm over a and
  *  (eq. GaussSU2-eom at a = 1, the covariant backward divergence)
@@ -1857,7 +1889,7 @@ int orc_su2_forces(const orc_su2_params *p, double *const *phi, double *const *U
  *  2 - Tr P = 2 (1 - p0) is evaluated as 2 |p|^2 / (1 + p0) for P = p0 - i p.sigma
  *  (the same number for a unitary P, det P = p0^2 + |p|^2 = 1, without the
  *  cancellation of 1 - p0 at small plaquette angles).                    */
-static void su2_energy_plain(const orc_su2_params *p, double *const *phi, double *const *pi,
+static void su2_energy_plain(const orc_su2_params *p, double a, double *const *phi, double *const *pi,
                              double *const *U, double *const *E, double *out)
 {
     int N = p->N;
@@ -1949,11 +1981,12 @@ static void su2_energy_plain(const orc_su2_params *p, double *const *phi, double
                 nadd(&sLR, sqrt(lr));
                 nadd(&sLRabs, dn2 + cn);
             }
-    out[0] = nval(&sk) / (double)V;
-    out[1] = nval(&sg) / (double)V;
+    const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+    out[0] = nval(&sk) / (double)V / a6;
+    out[1] = nval(&sg) / (double)V / a2;
     out[2] = nval(&sv) / (double)V;
-    out[3] = nval(&ske) / (double)V;
-    out[4] = nval(&sgb) / (double)V;
+    out[3] = nval(&ske) / (double)V / a4;
+    out[4] = nval(&sgb) / (double)V / a4;
     out[5] = out[0] + out[1] + out[2] + out[3] + out[4];
     out[6] = gmax;
     out[7] = dmax;
@@ -1963,13 +1996,37 @@ static void su2_energy_plain(const orc_su2_params *p, double *const *phi, double
     out[11] = nval(&sLRabs) / (double)V;
 }
 
-static void su2_kick(const orc_su2_params *p, double *const *phi, double *const *pi,
+/* kernel of b with the gauge energies (sec. 5.5.2):
+ *   K_a = a^{2 alpha + 1}/3 kappa^2 [(alpha-2) E_K^Phi + alpha E_G^Phi
+ *         + (alpha-1)(E_K^B + E_G^B) + (alpha+1) E_V]   (energies as su2_energy_plain) */
+static double su2_kernel_a(const orc_su2_params *p, double a, const double *E)
+{
+    double al = p->alpha;
+    return pow(a, 2.0 * al + 1.0) / 3.0 * p->kappa2 *
+           ((al - 2.0) * E[0] + al * E[1] + (al - 1.0) * (E[3] + E[4]) + (al + 1.0) * E[2]);
+}
+
+static void su2_fixed_ab(const orc_su2_params *p, double t, double *a, double *b)
+{
+    double pw = 2.0 / (3.0 * (1.0 + p->w_eos) - 2.0 * p->alpha);
+    double u = 1.0 + p->H0 * (t - p->t0) / pw;
+    *a = p->a0 * pow(u, pw);
+    *b = p->a0 * p->H0 * pow(u, pw - 1.0);
+}
+
+int orc_su2_fixed_background(const orc_su2_params *p, double t, double *a, double *b)
+{
+    su2_fixed_ab(p, t, a, b);
+    return 0;
+}
+
+static void su2_kick(const orc_su2_params *p, double a, double *const *phi, double *const *pi,
                      double *const *U, double *const *E, double w)
 {
     size_t V = vol(p->N);
     double *F[13];
     for (int i = 0; i < 13; ++i) F[i] = (double *)malloc(V * sizeof(double));
-    orc_su2_forces(p, phi, U, F, F + 4);
+    su2_forces_a(p, a, phi, U, F, F + 4);
     #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
         for (int k = 0; k < 4; ++k) pi[k][n] += w * F[k][n];
@@ -1989,16 +2046,19 @@ static mat2 su2_exp(double wgdx, const double *Ev)
     return m2_from_quat(cos(0.5 * th), u);
 }
 
-static void su2_drift(const orc_su2_params *p, double *const *phi, double *const *pi,
+/* drift by h with the scale factor a_mid of its midpoint: Phi += h a^{alpha-3} pi,
+ * U <- exp(-i h a^{alpha-1} g dx E^a T_a) U */
+static void su2_drift(const orc_su2_params *p, double a_mid, double *const *phi, double *const *pi,
                       double *const *U, double *const *E, double h)
 {
     size_t V = vol(p->N);
+    double cp = h * pow(a_mid, p->alpha - 3.0), cu = h * pow(a_mid, p->alpha - 1.0);
     #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < V; ++n) {
-        for (int k = 0; k < 4; ++k) phi[k][n] += h * pi[k][n];
+        for (int k = 0; k < 4; ++k) phi[k][n] += cp * pi[k][n];
         for (int i = 0; i < 3; ++i) {
             double Ev[3] = {E[3 * i][n], E[3 * i + 1][n], E[3 * i + 2][n]};
-            mat2 R = m2_mul(su2_exp(h * p->g * p->dx, Ev), su2_link(U, i, n));
+            mat2 R = m2_mul(su2_exp(cu * p->g * p->dx, Ev), su2_link(U, i, n));
             double q[4];
             m2_to_quat(R, q);
             for (int k = 0; k < 4; ++k) U[4 * i + k][n] = q[k];
@@ -2006,6 +2066,11 @@ static void su2_drift(const orc_su2_params *p, double *const *phi, double *const
     }
 }
 
+/* Energies at integer time, output layout (17 doubles): [0 .. 11] as
+ * su2_energy_plain at the clock's a; [12] a, [13] b at integer time,
+ * [14] Hubble LHS b^2, [15] RHS a^{2 alpha + 2} kappa^2 rho / 3, [16] (LHS - RHS)/(LHS + RHS).
+ * Leapfrog momenta (and b with self-consistent expansion) are synchronised on
+ * copies (readings R4, A3). */
 int orc_su2_energy(const orc_su2_params *p, double *const *phi, double *const *pi,
                    double *const *U, double *const *E, const orc_clock *c, double *out)
 {
@@ -2013,10 +2078,37 @@ int orc_su2_energy(const orc_su2_params *p, double *const *phi, double *const *p
     double *ps[4], *pe[9];
     for (int i = 0; i < 4; ++i) { ps[i] = (double *)malloc(B); memcpy(ps[i], pi[i], B); }
     for (int i = 0; i < 9; ++i) { pe[i] = (double *)malloc(B); memcpy(pe[i], E[i], B); }
-    if (c->lf_stag != 0) su2_kick(p, phi, ps, U, pe, 0.5 * c->lf_stag * p->dt);
-    su2_energy_plain(p, phi, ps, U, pe, out);
+    double b = c->b;
+    if (c->lf_stag != 0) {
+        double w = 0.5 * c->lf_stag * p->dt;
+        if (p->expansion == ORC_SELF) {
+            double Eb[12];
+            su2_energy_plain(p, c->a, phi, ps, U, pe, Eb);
+            b += w * su2_kernel_a(p, c->a, Eb);
+        }
+        su2_kick(p, c->a, phi, ps, U, pe, w);
+    }
+    su2_energy_plain(p, c->a, phi, ps, U, pe, out);
     for (int i = 0; i < 4; ++i) free(ps[i]);
     for (int i = 0; i < 9; ++i) free(pe[i]);
+    double lhs = b * b, rhs = pow(c->a, 2.0 * p->alpha + 2.0) * p->kappa2 * out[5] / 3.0;
+    out[12] = c->a;
+    out[13] = b;
+    out[14] = lhs;
+    out[15] = rhs;
+    out[16] = (lhs + rhs) != 0.0 ? (lhs - rhs) / (lhs + rhs) : 0.0;
+    return 0;
+}
+
+/* Hubble constraint (eq. FriedmannHubble) for b at the start: b0^2 = a^{2 alpha + 2} kappa^2 rho / 3 */
+int orc_su2_hubble_b0(const orc_su2_params *p, double *const *phi, double *const *pi, double *const *U,
+                      double *const *E, double a, double *b0)
+{
+    double En[12];
+    su2_energy_plain(p, a, phi, pi, U, E, En);
+    double rhs = pow(a, 2.0 * p->alpha + 2.0) * p->kappa2 * En[5] / 3.0;
+    if (rhs < 0.0) return -1;
+    *b0 = sqrt(rhs);
     return 0;
 }
 
@@ -2024,12 +2116,13 @@ int orc_su2_energy(const orc_su2_params *p, double *const *phi, double *const *p
 int orc_su2_gauss(const orc_su2_params *p, double *const *phi, double *const *pi,
                   double *const *U, double *const *E, double *out)
 {
-    su2_energy_plain(p, phi, pi, U, E, out);
+    su2_energy_plain(p, 1.0, phi, pi, U, E, out);
     return 0;
 }
 
-/* Staggered leapfrog for the SU(2) system (a = 1): kick all momenta, then
- * drift the doublet and the links.  Same staggering convention as orc_run. */
+/* Staggered leapfrog for the SU(2) system: kick all momenta, then drift the
+ * doublet and the links.  Same staggering convention as orc_run; with
+ * expansion as orc_u1_run_lf (reading A3 for the self-consistent case). */
 int orc_su2_run_lf(const orc_su2_params *p, double *const *phi, double *const *pi,
                    double *const *U, double *const *E, orc_clock *c, long nsteps)
 {
@@ -2038,14 +2131,41 @@ int orc_su2_run_lf(const orc_su2_params *p, double *const *phi, double *const *p
     long ns = nsteps > 0 ? nsteps : -nsteps;
     double h = dir * p->dt;
     if (c->lf_stag != 0 && c->lf_stag != dir) return -3;
+    double t_start = c->t;
     for (long k = 0; k < ns; ++k) {
-        su2_kick(p, phi, pi, U, E, c->lf_stag == 0 ? 0.5 * h : h);
-        su2_drift(p, phi, pi, U, E, h);
+        double t = t_start + (double)k * h;
+        double w = c->lf_stag == 0 ? 0.5 * h : h;
+        if (p->expansion == ORC_SELF) {
+            double Eb[12], Ea[12];
+            su2_energy_plain(p, c->a, phi, pi, U, E, Eb);
+            su2_kick(p, c->a, phi, pi, U, E, w);
+            su2_energy_plain(p, c->a, phi, pi, U, E, Ea);
+            if (c->lf_stag == 0)
+                c->b += w * su2_kernel_a(p, c->a, Ea);
+            else
+                c->b += 0.5 * h * su2_kernel_a(p, c->a, Eb) + 0.5 * h * su2_kernel_a(p, c->a, Ea);
+            double a1 = c->a + h * c->b;
+            su2_drift(p, 0.5 * (c->a + a1), phi, pi, U, E, h);
+            c->a = a1;
+        } else if (p->expansion == ORC_FIXED) {
+            double a, b, am;
+            su2_fixed_ab(p, t, &a, &b);
+            su2_kick(p, a, phi, pi, U, E, w);
+            su2_fixed_ab(p, t + 0.5 * h, &am, &b);
+            su2_drift(p, am, phi, pi, U, E, h);
+        } else {
+            su2_kick(p, 1.0, phi, pi, U, E, w);
+            su2_drift(p, 1.0, phi, pi, U, E, h);
+        }
         c->lf_stag = dir;
     }
-    c->t += (double)ns * h;
-    c->a = 1.0;
-    c->b = 0.0;
+    c->t = t_start + (double)ns * h;
+    if (p->expansion == ORC_FIXED) {
+        su2_fixed_ab(p, c->t, &c->a, &c->b);
+    } else if (p->expansion == ORC_NONE) {
+        c->a = 1.0;
+        c->b = 0.0;
+    }
     return 0;
 }
 
@@ -2053,7 +2173,13 @@ int orc_su2_lf_sync(const orc_su2_params *p, double *const *phi, double *const *
                     double *const *U, double *const *E, orc_clock *c)
 {
     if (c->lf_stag == 0) return 0;
-    su2_kick(p, phi, pi, U, E, 0.5 * c->lf_stag * p->dt);
+    double w = 0.5 * c->lf_stag * p->dt;
+    if (p->expansion == ORC_SELF) {
+        double En[12];
+        su2_energy_plain(p, c->a, phi, pi, U, E, En);
+        c->b += w * su2_kernel_a(p, c->a, En);
+    }
+    su2_kick(p, c->a, phi, pi, U, E, w);
     c->lf_stag = 0;
     return 0;
 }
@@ -2162,15 +2288,43 @@ int orc_u1_gauss_init(const orc_u1_params *p, double *const *phi, double *const 
 /* Plain composition: every half kick is applied on its own.               */
 /* ------------------------------------------------------------------ */
 
+/* One second-order map of size h from time t (reading R15; with expansion
+ * readings R1 and R3), as u1_vv2. */
+static void su2_vv2(const orc_su2_params *p, double *const *phi, double *const *pi, double *const *U,
+                    double *const *E, orc_clock *c, double t, double h)
+{
+    if (p->expansion == ORC_SELF) {
+        double En[12];
+        su2_energy_plain(p, c->a, phi, pi, U, E, En);
+        su2_kick(p, c->a, phi, pi, U, E, 0.5 * h);
+        c->b += 0.5 * h * su2_kernel_a(p, c->a, En);
+        double a1 = c->a + h * c->b;
+        su2_drift(p, 0.5 * (c->a + a1), phi, pi, U, E, h);
+        c->a = a1;
+        su2_kick(p, c->a, phi, pi, U, E, 0.5 * h);
+        su2_energy_plain(p, c->a, phi, pi, U, E, En);
+        c->b += 0.5 * h * su2_kernel_a(p, c->a, En);
+        return;
+    }
+    double a0 = 1.0, am = 1.0, a1 = 1.0, b;
+    if (p->expansion == ORC_FIXED) {
+        su2_fixed_ab(p, t, &a0, &b);
+        su2_fixed_ab(p, t + 0.5 * h, &am, &b);
+        su2_fixed_ab(p, t + h, &a1, &b);
+    }
+    su2_kick(p, a0, phi, pi, U, E, 0.5 * h);
+    su2_drift(p, am, phi, pi, U, E, h);
+    su2_kick(p, a1, phi, pi, U, E, 0.5 * h);
+}
+
 static void su2_vv(const orc_su2_params *p, double *const *phi, double *const *pi, double *const *U,
-                   double *const *E, int order, double h)
+                   double *const *E, orc_clock *c, int order, double t, double h)
 {
     double w[45];
     const int n = orc_vv_stages(order, w);
     for (int i = 0; i < n; ++i) {
-        su2_kick(p, phi, pi, U, E, 0.5 * w[i] * h);
-        su2_drift(p, phi, pi, U, E, w[i] * h);
-        su2_kick(p, phi, pi, U, E, 0.5 * w[i] * h);
+        su2_vv2(p, phi, pi, U, E, c, t, w[i] * h);
+        t += w[i] * h;
     }
 }
 
@@ -2181,8 +2335,10 @@ int orc_su2_run_vv(const orc_su2_params *p, double *const *phi, double *const *p
     if (c->lf_stag != 0) return -3;
     double h = nsteps >= 0 ? p->dt : -p->dt;
     long ns = nsteps >= 0 ? nsteps : -nsteps;
-    for (long k = 0; k < ns; ++k) su2_vv(p, phi, pi, U, E, order, h);
-    c->t += (double)ns * h;
+    double t_start = c->t;
+    for (long k = 0; k < ns; ++k) su2_vv(p, phi, pi, U, E, c, order, t_start + (double)k * h, h);
+    c->t = t_start + (double)ns * h;
+    if (p->expansion == ORC_FIXED) su2_fixed_ab(p, c->t, &c->a, &c->b);
     return 0;
 }
 

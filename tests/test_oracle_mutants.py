@@ -119,8 +119,8 @@ MUTANTS = [
     ("SU(2) magnetic energy normalisation", "nadd(&sgb, 2.0 * mag /", "nadd(&sgb, mag /", "test_oracle_su2.py"),
     ("SU(2) link drift direction", "u[a] = sin(0.5 * th) * Ev[a] / len;", "u[a] = -sin(0.5 * th) * Ev[a] / len;",
      "test_oracle_su2.py"),
-    ("SU(2) link drift on the right", "mat2 R = m2_mul(su2_exp(h * p->g * p->dx, Ev), su2_link(U, i, n));",
-     "mat2 R = m2_mul(su2_link(U, i, n), su2_exp(h * p->g * p->dx, Ev));", "test_oracle_su2.py"),
+    ("SU(2) link drift on the right", "mat2 R = m2_mul(su2_exp(cu * p->g * p->dx, Ev), su2_link(U, i, n));",
+     "mat2 R = m2_mul(su2_link(U, i, n), su2_exp(cu * p->g * p->dx, Ev));", "test_oracle_su2.py"),
     ("SU(2) Gauss transport the other way", "mat2 Y = m2_mul(m2_mul(m2_dag(Um), X), Um);",
      "mat2 Y = m2_mul(m2_mul(Um, X), m2_dag(Um));", "test_oracle_su2.py"),
     ("SU(2) backward link not conjugated", "m2_apply(m2_dag(su2_link(U, i, nm)), qm, b);",
@@ -132,12 +132,32 @@ MUTANTS = [
      "E[i][n] = (re[n] - re[nbr(N, x, y, z, i, -1)]) / dx;", "test_oracle_gauss_init.py"),
     ("SU(2) initial charge without the 1/2 of T_a", "t += conj(psi[r]) * 0.5 * PAULI[a][r][q] * pp[q];",
      "t += conj(psi[r]) * PAULI[a][r][q] * pp[q];", "test_oracle_gauss_init.py"),
-    ("gauge VV half kicks of the full step", "su2_kick(p, phi, pi, U, E, 0.5 * w[i] * h);",
-     "su2_kick(p, phi, pi, U, E, 0.5 * h);", "test_oracle_gauge_vv.py"),
+    ("SU(2) VV stages of the full step", "su2_vv2(p, phi, pi, U, E, c, t, w[i] * h);",
+     "su2_vv2(p, phi, pi, U, E, c, t, h);", "test_oracle_gauge_vv.py"),
     ("U(1) VV stages without the time advance", "        u1_vv2(p, phi, pi, A, piA, c, t, w[i] * h);\n        t += w[i] * h;",
      "        u1_vv2(p, phi, pi, A, piA, c, t, w[i] * h);", "test_oracle_u1_expansion.py"),
     ("SU(2) plaquette order", "mat2 P = m2_mul(m2_mul(su2_link(U, i, n), su2_link(U, j, at(N, ci[0], ci[1], ci[2]))),",
      "mat2 P = m2_mul(m2_mul(su2_link(U, j, at(N, ci[0], ci[1], ci[2])), su2_link(U, i, n)),", "test_oracle_su2.py"),
+    ("SU(2) staple force with a^{1+alpha}", "- cm_ * (2.0 / (g * dx * dx * dx) * vs[k]);",
+     "- cl * (2.0 / (g * dx * dx * dx) * vs[k]);", "test_oracle_su2_expansion.py"),
+    ("SU(2) current without a^{1+alpha}", "FE[3 * i + k][n] = cl * (g / dx * cimag(t))",
+     "FE[3 * i + k][n] = (g / dx * cimag(t))", "test_oracle_su2_expansion.py"),
+    ("SU(2) link drift without a^{alpha-1}", "cu = h * pow(a_mid, p->alpha - 1.0);", "cu = h;",
+     "test_oracle_su2_expansion.py"),
+    ("SU(2) electric energy over a^2", "out[3] = nval(&ske) / (double)V / a4;", "out[3] = nval(&ske) / (double)V / a2;",
+     "test_oracle_su2_expansion.py"),
+    ("SU(2) gauge energies in the b kernel with weight alpha",
+     "static double su2_kernel_a(const orc_su2_params *p, double a, const double *E)\n{\n    double al = p->alpha;\n"
+     "    return pow(a, 2.0 * al + 1.0) / 3.0 * p->kappa2 *\n"
+     "           ((al - 2.0) * E[0] + al * E[1] + (al - 1.0) * (E[3] + E[4])",
+     "static double su2_kernel_a(const orc_su2_params *p, double a, const double *E)\n{\n    double al = p->alpha;\n"
+     "    return pow(a, 2.0 * al + 1.0) / 3.0 * p->kappa2 *\n"
+     "           ((al - 2.0) * E[0] + al * E[1] + (al) * (E[3] + E[4])", "test_oracle_su2_expansion.py"),
+    ("SU(2) leapfrog sync without the b half kick",
+     "        su2_energy_plain(p, c->a, phi, pi, U, E, En);\n        c->b += w * su2_kernel_a(p, c->a, En);\n    }\n"
+     "    su2_kick(p, c->a, phi, pi, U, E, w);\n    c->lf_stag = 0;",
+     "        su2_energy_plain(p, c->a, phi, pi, U, E, En);\n    }\n"
+     "    su2_kick(p, c->a, phi, pi, U, E, w);\n    c->lf_stag = 0;", "test_oracle_su2_expansion.py"),
 ]
 
 
