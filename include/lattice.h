@@ -48,7 +48,7 @@ extern "C" {
 typedef enum lat_status {
     LAT_OK = 0,
     LAT_EINVAL = -1,        /* invalid argument (sizes, steps, null or misaligned pointers) */
-    LAT_EUNSUPPORTED = -2,  /* valid but not provided combination (e.g. a gauge model with expansion) */
+    LAT_EUNSUPPORTED = -2,  /* valid but not provided combination (e.g. a gauge model in float32) */
     LAT_ENODEV = -3,        /* no usable GPU */
     LAT_EHIP = -4,          /* a HIP runtime call failed; see lattice_last_error */
     LAT_ESTATE = -5,        /* call not valid in the current state */
@@ -92,9 +92,13 @@ enum lat_potential {
                               kicks are minus its derivative, the link drift is
                               U <- exp(-i dt g dx E^a T_a) U.  Provided with LF and the VV
                               family (VV2 = kick(h/2) drift(h) kick(h/2), VV4..VV10 its symmetric
-                              compositions), a = 1 and float64; (f_star/omega_star)^2 = 1 (kappa_g is
-                              not used).  The U(1) model has the same integrators and every
-                              expansion (see lattice_init). */
+                              compositions) and every expansion, in float64; (f_star/omega_star)^2 = 1
+                              (kappa_g is not used).  In an expanding background (sec. 5.5.2, eq.
+                              kernelsSU21 and the one after it) the covariant Laplacian and the current
+                              take a^{1+alpha}, the potential force a^{3+alpha}, the staple force
+                              a^{alpha-1}; the doublet drifts with a^{alpha-3}, the links with
+                              exp(-i dt a^{alpha-1} g dx E^a T_a); energies as the U(1) model's.  The
+                              U(1) model has the same integrators and every expansion (see lattice_init). */
 };
 
 enum lat_precision {
@@ -139,11 +143,11 @@ typedef struct lat_fields {
     void *A[3];     /* LAT_ABELIAN_HIGGS: A_i on the link n -> n + i (sec. 3.2) */
     void *piA[3];   /* LAT_ABELIAN_HIGGS: pi_A,i = a^{1-alpha} F_0i (sec. 5.5.2) */
     void *doublet[4];     /* LAT_SU2_HIGGS: the real components phi0..phi3 of the doublet */
-    void *pi_doublet[4];  /* LAT_SU2_HIGGS: their momenta pi_c = phi_c' (a = 1) */
+    void *pi_doublet[4];  /* LAT_SU2_HIGGS: their momenta pi_c = a^{3-alpha} phi_c' (eq. momSU2doublet) */
     void *U[12];          /* LAT_SU2_HIGGS: link n -> n + i, unit quaternion component k at
                              U[4 i + k], U = U[4i] I - i (U[4i+1], U[4i+2], U[4i+3]).sigma */
     void *E[9];           /* LAT_SU2_HIGGS: electric field E_i^a at E[3 i + a] (a = 0, 1, 2
-                             for sigma_1..3), the momentum pi_B of sec. 5 at a = 1 */
+                             for sigma_1..3), the momentum pi_B = a^{1-alpha} G_0i (eq. momSU2vec) */
 } lat_fields;
 
 typedef struct lat_energies {
@@ -181,16 +185,17 @@ typedef struct lat_ctx lat_ctx;
  * after the momentum kick, the half kicks that leave or reach integer time
  * that of the momenta at the half step); a staggered start (lf_staggered != 0)
  * then needs b0 at the half step.
- * The U(1) model takes every expansion: in an expanding background its kicks
+ * The gauge models take every expansion: in an expanding background their kicks
  * scale the covariant Laplacian and the current by a^{1+alpha}, the potential
- * force by a^{3+alpha} and the magnetic force by a^{alpha-1}, its drifts are
- * a^{alpha-3} pi and a^{alpha-1} pi_A, its energies are divided by a^6, a^2,
- * a^4 (kinetic, gradient, gauge), and the scale-factor kernel adds
- * (alpha - 1)(E_K^A + E_G^A) (sec. 5.5.2); with self-consistent expansion the
+ * force by a^{3+alpha} and the magnetic (SU(2): staple) force by a^{alpha-1},
+ * their drifts are a^{alpha-3} pi and a^{alpha-1} pi_A (SU(2): the link
+ * exponential of a^{alpha-1} E), their energies are divided by a^6, a^2, a^4
+ * (kinetic, gradient, gauge), and the scale-factor kernel adds
+ * (alpha - 1)(E_K^gauge + E_G^gauge) (sec. 5.5.2); with self-consistent expansion the
  * kicks, energy sums and drifts run as separate passes with the scale factor
  * updated on the device between them.
- * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (the SU(2) model with expansion, the
- * gauge models in float32), LAT_ENODEV, LAT_ENOMEM, LAT_EHIP.  On error *ctx
+ * Errors: LAT_EINVAL, LAT_EUNSUPPORTED (the gauge models in float32),
+ * LAT_ENODEV, LAT_ENOMEM, LAT_EHIP.  On error *ctx
  * is set to NULL. */
 lat_status lattice_init(lat_ctx **ctx, const lat_params *p, const lat_fields *f, void *stream);
 

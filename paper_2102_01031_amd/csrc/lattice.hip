@@ -148,6 +148,7 @@ struct lat_ctx {
     int rows_alternate = 0;   // whole-row kernel: alternate the z march direction pass by pass
     int rows_lp = 0;          // whole-row kernel store policy (see launch_rows)
     int rows_split = 6;       // store policy 1: eighths of the march with non-temporal stores
+    int rows_zpair = 0;       // whole-row kernel: odd z chunks march the other way
     int zc = 0;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, nblocks = 0;
     // launch statistics and optional event timing
@@ -343,6 +344,12 @@ void geometry_from_env(lat_ctx *c)
     if (const char *lp = std::getenv("LATTICE_ROWS_STORES")) c->rows_lp = std::atoi(lp) != 0;
     c->rows_split = 6;
     if (const char *sp = std::getenv("LATTICE_ROWS_SPLIT")) c->rows_split = std::min(8, std::max(0, std::atoi(sp)));
+    // opposite marches of neighbouring z chunks (so both read the planes at
+    // their common boundary at the same time) at N = 256 in float32: 105.2
+    // against 106.2 us; float64 ran slower with it (208 against 195 us, with
+    // its store policy).  LATTICE_ROWS_ZPAIR=0|1 overrides
+    c->rows_zpair = (c->N == 256 && c->f32) ? 1 : 0;
+    if (const char *zp = std::getenv("LATTICE_ROWS_ZPAIR")) c->rows_zpair = std::atoi(zp) != 0;
     const char *s = std::getenv("LATTICE_TILE");
     if (s && std::strncmp(s, "rows", 4) == 0 && rows_ok(c->N)) {
         int ty = 8, z = 0;
@@ -595,6 +602,7 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
     // call, so graph replays and direct launches take the same directions), and
     // outputs go through the caches so that those planes are still there
     a.down = c->rows_alternate ? (pass_index & 1) : 0;
+    a.zpair = c->rows_zpair;
     a.cached_out = c->rows_alternate;
     a.split = c->rows_split;
     a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
@@ -1132,8 +1140,6 @@ lat_status validate(const lat_params *p, const lat_fields *f)
         }
     }
     if (p->potential == LAT_SU2_HIGGS) {
-        if (p->expansion != LAT_EXP_NONE)
-            return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model is provided at a = 1");
         if (p->precision != LAT_PREC_F64) return fail(nullptr, LAT_EUNSUPPORTED, "the SU(2) model runs in float64");
         if (!(p->e_charge != 0.0) || !std::isfinite(p->e_charge)) return fail(nullptr, LAT_EINVAL, "bad SU(2) coupling");
         if ((double)p->N * p->N * p->N * 8.0 >= 4294967296.0)
@@ -1369,10 +1375,10 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     if (hipMemcpyAsync(c->sc, c->sc_host, sizeof(ScaleRecord), hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return bail(LAT_EHIP, "upload failed");
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
-    if (p->expansion == LAT_EXP_SELF && std::isnan(p->b0) && c->u1) {
-        // Hubble constraint (eq. FriedmannHubble) with the U(1) energies at a0
+    if (p->expansion == LAT_EXP_SELF && std::isnan(p->b0) && (c->u1 || c->su2)) {
+        // Hubble constraint (eq. FriedmannHubble) with the gauge model's energies at a0
         lat_energies e{};
-        if (u1_energy(c, &e) != LAT_OK) return bail(LAT_EHIP, c->err);
+        if ((c->u1 ? u1_energy(c, &e) : su2_energy(c, &e)) != LAT_OK) return bail(LAT_EHIP, c->err);
         const double rhs = std::pow(a, 2.0 * p->alpha + 2.0) * p->kappa2 * e.rho / 3.0;
         if (!(rhs >= 0.0)) return bail(LAT_EINVAL, "negative energy: Hubble constraint has no root");
         c->sc_host->a = a;
@@ -1403,7 +1409,7 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
             return bail(LAT_EHIP, "upload failed");
         if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LAT_EHIP, "stream synchronize failed");
     }
-    if (p->expansion == LAT_EXP_SELF && p->integrator == LAT_LF && p->lf_staggered != 0 && !c->u1) {
+    if (p->expansion == LAT_EXP_SELF && p->integrator == LAT_LF && p->lf_staggered != 0 && !c->u1 && !c->su2) {
         // a staggered start: the next kick's b update needs the sums of the
         // stored half-step momenta squared (reading A3)
         if (energy_sums(c, 0.0) != LAT_OK) return bail(LAT_EHIP, c->err);
@@ -2288,9 +2294,39 @@ SU2Args su2_args(lat_ctx *c, double ck, double hd, bool write_fields)
     a.v = c->p.v;
     a.ck = ck;
     a.hd = hd;
+    a.la1 = a.la3 = a.lam1 = 1.0;
+    a.hdU = hd;
+    a.dw = nullptr;
     a.partials = c->partials;
     a.ticket = c->ticket;
     a.sc = c->sc;
+    return a;
+}
+
+// expanding background: kick weights at scale factor ak, drift weights at the
+// drift's midpoint am (sec. 5.5.2 kernels; reading R3)
+void su2_bg(const lat_ctx *c, SU2Args &a, double h, double ak, double am)
+{
+    const double al = c->p.alpha;
+    a.la1 = std::pow(ak, 1.0 + al);
+    a.la3 = std::pow(ak, 3.0 + al);
+    a.lam1 = std::pow(ak, al - 1.0);
+    a.hd = h * std::pow(am, al - 3.0);
+    a.hdU = h * std::pow(am, al - 1.0);
+}
+
+SU2Args su2_args_bg(lat_ctx *c, double ck, double h, double ak, double am, bool write_fields)
+{
+    SU2Args a = su2_args(c, ck, h, write_fields);
+    su2_bg(c, a, h, ak, am);
+    return a;
+}
+
+// weights from the device record (self-consistent expansion)
+SU2Args su2_args_dev(lat_ctx *c, bool write_fields)
+{
+    SU2Args a = su2_args(c, 0.0, 0.0, write_fields);
+    a.dw = c->sc->w;
     return a;
 }
 
@@ -2383,33 +2419,29 @@ static bool su2_alternate()
     return e ? std::atoi(e) != 0 : true;
 }
 
-lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
+// Self-consistent expansion (readings A3 and R1 for the SU(2) model), as the
+// U(1) model's: the kicks, energy sums and drifts as separate passes on the
+// plain arrays, the scale factor, b and the pass weights updated on the device
+// between them with the U(1) model's one-thread kernels (the SU(2) energy pass
+// leaves its sums in the same slots: doublet kinetic, gradient, potential,
+// electric, magnetic).
+lat_status su2_step_self_lf(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
+    const U1SelfConst kc = u1_self_const(c);
     int stag = c->lf_stag;
-    if (c->su2_aos_on && ns >= kSU2AosMinPasses) {
-        lat_status s = su2_aos_enter(c);
-        if (s != LAT_OK) return s;
-        int buf = 0;
-        for (int64_t k = 0; k < ns; ++k) {
-            const double ck = stag == 0 ? 0.5 * h : h;
-            SU2Args a = su2_args_aos(c, ck, h, buf);
-            a.down = su2_alternate() ? (int)(k & 1) : 0;
-            if ((s = su2_launch(c, kSU2StepAoS, a)) != LAT_OK) return s;
-            buf ^= 1;
-            stag = dir;
-        }
-        if ((s = su2_aos_leave(c, buf)) != LAT_OK) return s;
-        c->lf_stag = dir;
-        c->t += (double)ns * h;
-        return LAT_OK;
-    }
+    lat_status s;
     for (int64_t k = 0; k < ns; ++k) {
-        const double ck = stag == 0 ? 0.5 * h : h;
-        SU2Args a = su2_args(c, ck, h, true);
-        a.down = su2_alternate() ? (int)(k & 1) : 0;
-        lat_status s = su2_launch(c, kSU2Step, a);
-        if (s != LAT_OK) return s;
+        const double w = stag == 0 ? 0.5 * h : h;
+        if (stag != 0) {   // sums of the momenta before the kick
+            if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+            U1K(u1_self_stash, c->sc);
+        }
+        U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
+        if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
+        if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+        U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc);
+        if ((s = su2_launch(c, kSU2Step, su2_args_dev(c, true))) != LAT_OK) return s;
         c->cur_su2 ^= 1;
         stag = dir;
     }
@@ -2418,29 +2450,109 @@ lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
     return LAT_OK;
 }
 
+lat_status su2_step_lf(lat_ctx *c, int64_t ns, int dir)
+{
+    if (c->p.expansion == LAT_EXP_SELF) return su2_step_self_lf(c, ns, dir);
+    const double h = dir * c->p.dt;
+    const double t0 = c->t;
+    const bool fixed = c->p.expansion == LAT_EXP_FIXED;
+    int stag = c->lf_stag;
+    if (c->su2_aos_on && ns >= kSU2AosMinPasses) {
+        lat_status s = su2_aos_enter(c);
+        if (s != LAT_OK) return s;
+        int buf = 0;
+        for (int64_t k = 0; k < ns; ++k) {
+            const double ck = stag == 0 ? 0.5 * h : h;
+            SU2Args a = su2_args_aos(c, ck, h, buf);
+            if (fixed) {   // kick at t, drift at the midpoint (reading R3)
+                const double t = t0 + (double)k * h;
+                su2_bg(c, a, h, scale_at(c, t), scale_at(c, t + 0.5 * h));
+            }
+            a.down = su2_alternate() ? (int)(k & 1) : 0;
+            if ((s = su2_launch(c, kSU2StepAoS, a)) != LAT_OK) return s;
+            buf ^= 1;
+            stag = dir;
+        }
+        if ((s = su2_aos_leave(c, buf)) != LAT_OK) return s;
+        c->lf_stag = dir;
+        c->t = t0 + (double)ns * h;
+        return LAT_OK;
+    }
+    for (int64_t k = 0; k < ns; ++k) {
+        const double ck = stag == 0 ? 0.5 * h : h;
+        const double t = t0 + (double)k * h;
+        SU2Args a = fixed ? su2_args_bg(c, ck, h, scale_at(c, t), scale_at(c, t + 0.5 * h), true)
+                          : su2_args(c, ck, h, true);
+        a.down = su2_alternate() ? (int)(k & 1) : 0;
+        lat_status s = su2_launch(c, kSU2Step, a);
+        if (s != LAT_OK) return s;
+        c->cur_su2 ^= 1;
+        stag = dir;
+    }
+    c->lf_stag = dir;
+    c->t = t0 + (double)ns * h;
+    return LAT_OK;
+}
+
 lat_status su2_sync(lat_ctx *c)
 {
-    return su2_launch(c, kSU2Kick, su2_args(c, 0.5 * c->lf_stag * c->p.dt, 0.0, false));
+    const double w = 0.5 * c->lf_stag * c->p.dt;
+    if (c->p.expansion == LAT_EXP_SELF) {
+        lat_status s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false));
+        if (s != LAT_OK) return s;
+        U1K(u1_self_b_kick, c->sc, w, u1_self_const(c));
+        U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
+        return su2_launch(c, kSU2Kick, su2_args_dev(c, false));
+    }
+    const double a = scale_at(c, c->t);
+    return su2_launch(c, kSU2Kick, su2_args_bg(c, w, 0.0, a, a, false));
 }
 
 lat_status su2_energy(lat_ctx *c, lat_energies *out)
 {
     const double ck = c->lf_stag != 0 ? 0.5 * c->lf_stag * c->p.dt : 0.0;
-    lat_status s = su2_launch(c, kSU2Energy, su2_args(c, ck, 0.0, false));
+    const double V = (double)c->vol, al = c->p.alpha;
+    double a = 1.0, b = 0.0;
+    lat_status s;
+    if (c->p.expansion == LAT_EXP_FIXED) fixed_ab(c->p, c->t, &a, &b);
+    if (c->p.expansion == LAT_EXP_SELF) {
+        // a and b of the record; a staggered b is half-kicked on the fly with
+        // the sums of the stored half-step momenta (reading A3)
+        if (ck != 0.0 && (s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        a = c->sc_host->a;
+        b = c->sc_host->b;
+        if (ck != 0.0) {
+            const double *S = c->sc_host->sums;
+            const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+            const double Ka = std::pow(a, 2.0 * al + 1.0) / 3.0 * c->p.kappa2 *
+                              ((al - 2.0) * S[0] / V / a6 + al * S[1] / V / a2 +
+                               (al - 1.0) * (S[3] / V / a4 + S[4] / V / a4) + (al + 1.0) * S[2] / V);
+            b += ck * Ka;
+        }
+    }
+    s = su2_launch(c, kSU2Energy, su2_args_bg(c, ck, 0.0, a, a, false));
     if (s != LAT_OK) return s;
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const double V = (double)c->vol;
     const double *S = c->sc_host->sums, *M = c->sc_host->maxes;
+    const double a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
     out->t = c->t;
-    out->a = 1.0;
-    out->b = 0.0;
-    out->EK[0] = S[0] / V;
-    out->EG[0] = S[1] / V;
+    out->a = a;
+    out->b = b;
+    out->EK[0] = S[0] / V / a6;
+    out->EG[0] = S[1] / V / a2;
     out->EV[0] = S[2] / V;
-    out->EK_B = S[3] / V;
-    out->EG_B = S[4] / V;
+    out->EK_B = S[3] / V / a4;
+    out->EG_B = S[4] / V / a4;
     out->rho = out->EK[0] + out->EG[0] + out->EV[0] + out->EK_B + out->EG_B;
+    out->hubble_lhs = b * b;
+    out->hubble_rhs = std::pow(a, 2.0 * al + 2.0) * c->p.kappa2 * out->rho / 3.0;
+    {
+        const double den = out->hubble_lhs + out->hubble_rhs;
+        out->hubble_res = den != 0.0 ? (out->hubble_lhs - out->hubble_rhs) / den : 0.0;
+    }
     out->gauss_mean = S[5] / V;
     out->gauss_sum_mean = S[6] / V;
     out->gauss_abs_mean = S[7] / V;
@@ -2484,9 +2596,35 @@ lat_status u1_step_self_vv(lat_ctx *c, int64_t ns, int dir)
     return LAT_OK;
 }
 
+// SU(2) velocity-Verlet family with self-consistent expansion: as the U(1) model's.
+lat_status su2_step_self_vv(lat_ctx *c, int64_t ns, int dir)
+{
+    const double h = dir * c->p.dt;
+    const std::vector<double> w = vv_weights(c->p.integrator);
+    const U1SelfConst kc = u1_self_const(c);
+    lat_status s;
+    if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;   // E_n
+    for (int64_t k = 0; k < ns; ++k)
+        for (double wp : w) {
+            const double hs = wp * h;
+            U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
+            if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
+            U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc);
+            if ((s = su2_launch(c, kSU2Step, su2_args_dev(c, true))) != LAT_OK) return s;
+            c->cur_su2 ^= 1;
+            U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
+            if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
+            if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+            U1K(u1_self_b_kick, c->sc, 0.5 * hs, kc);
+        }
+    c->t += (double)ns * h;
+    return LAT_OK;
+}
+
 lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
 {
     if (c->u1 && c->p.expansion == LAT_EXP_SELF) return u1_step_self_vv(c, ns, dir);
+    if (c->su2 && c->p.expansion == LAT_EXP_SELF) return su2_step_self_vv(c, ns, dir);
     const double h = dir * c->p.dt;
     const std::vector<double> w = vv_weights(c->p.integrator);
     const int64_t J = (int64_t)w.size(), M = J * ns;
@@ -2503,22 +2641,25 @@ lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
     for (int64_t p = 0; p < M; ++p) {
         const double hp = w[(size_t)(p % J)] * h;
         const double ck = 0.5 * (prev + hp);
+        // fixed background: kicks at the kick point's a, drift at the
+        // sub-step's midpoint (reading R3)
+        if (p % J == 0) tk = t_start + (double)(p / J) * h;
         lat_status s;
         if (aos) {
-            s = su2_launch(c, kSU2StepAoS, su2_args_aos(c, ck, hp, buf));
+            SU2Args a = su2_args_aos(c, ck, hp, buf);
+            if (fixed) su2_bg(c, a, hp, scale_at(c, tk), scale_at(c, tk + 0.5 * hp));
+            s = su2_launch(c, kSU2StepAoS, a);
             buf ^= 1;
         } else if (c->su2) {
-            s = su2_launch(c, kSU2Step, su2_args(c, ck, hp, true));
+            s = su2_launch(c, kSU2Step, fixed ? su2_args_bg(c, ck, hp, scale_at(c, tk), scale_at(c, tk + 0.5 * hp), true)
+                                              : su2_args(c, ck, hp, true));
             c->cur_su2 ^= 1;
         } else {
-            // fixed background: kicks at the kick point's a, drift at the
-            // sub-step's midpoint (reading R3)
-            if (p % J == 0) tk = t_start + (double)(p / J) * h;
             s = u1_launch(c, kU1Step, fixed ? u1_args_bg(c, ck, hp, scale_at(c, tk), scale_at(c, tk + 0.5 * hp), true)
                                             : u1_args(c, ck, hp, true));
             u1_flip(c);
-            tk += hp;
         }
+        tk += hp;
         if (s != LAT_OK) return s;
         prev = hp;
     }
@@ -2527,9 +2668,10 @@ lat_status gauge_step_vv(lat_ctx *c, int64_t ns, int dir)
         if (s != LAT_OK) return s;
     }
     const double tend = t_start + (double)ns * h;
-    lat_status s = c->su2 ? su2_launch(c, kSU2Kick, su2_args(c, 0.5 * prev, 0.0, false))
-                          : u1_launch(c, kU1Kick, fixed ? u1_args_bg(c, 0.5 * prev, 0.0, scale_at(c, tend),
-                                                                     scale_at(c, tend), false)
+    const double ae = scale_at(c, tend);
+    lat_status s = c->su2 ? su2_launch(c, kSU2Kick, fixed ? su2_args_bg(c, 0.5 * prev, 0.0, ae, ae, false)
+                                                          : su2_args(c, 0.5 * prev, 0.0, false))
+                          : u1_launch(c, kU1Kick, fixed ? u1_args_bg(c, 0.5 * prev, 0.0, ae, ae, false)
                                                         : u1_args(c, 0.5 * prev, 0.0, false));
     if (s != LAT_OK) return s;
     c->t = tend;

@@ -118,7 +118,10 @@ __global__ void __launch_bounds__(64 * TY) scalar_rows(const ScalarArgs<T> g)
     const int len = z1 - z0;
     // march direction: up (z0, z0 + 1, ...) or down (z1 - 1, z1 - 2, ...);
     // pl(k) is the k-th plane of the march, k = -1 .. len, wrapped periodically
-    const bool down = g.down != 0;
+    // with zpair, neighbouring chunks march in opposite directions, so the
+    // plane on either side of a chunk boundary is read by both chunks at the
+    // same time (both at their start, or both at their end)
+    const bool down = (g.down != 0) != (g.zpair != 0 && (bz & 1) != 0);
     auto pl = [&](const int k) {
         int z = down ? z1 - 1 - k : z0 + k;
         if (z < 0) z += N;

@@ -37,6 +37,7 @@ struct ScalarArgs {
     int N, zc, tiles_x, tiles_y;
     int y_fastest;          // whole-row kernel block order: 0 z chunk fastest, 1 y tile fastest
     int down;               // whole-row kernel: march each z chunk downward
+    int zpair;              // whole-row kernel: odd z chunks march the other way (see stage_rows.hpp)
     int cached_out;         // whole-row kernel: ordinary stores (else non-temporal)
     int split;              // whole-row kernel, phased cache policies: first phase = split/8 of the march
     double inv_dx2;

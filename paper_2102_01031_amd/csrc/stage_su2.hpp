@@ -1,4 +1,4 @@
-// stage_su2.hpp -- SU(2) doublet with SU(2) links at a = 1: the leapfrog pass
+// stage_su2.hpp -- SU(2) doublet with SU(2) links: the leapfrog pass
 // (kick of the doublet momenta and electric fields, drift of the doublet and
 // the links), the sync half kick, and the energy / Gauss reduction pass.
 //
@@ -42,7 +42,15 @@ struct SU2Args {
     int down;                      // march the z column downward (sites are independent)
     double dx, g, lam, v;
     double ck;   // kick weight
-    double hd;   // drift weight
+    double hd;   // drift weight of the doublet (time times a^{alpha-3})
+    // expanding background (sec. 5.5.2 kernels): the covariant Laplacian and
+    // the current scale with la1 = a^{1+alpha}, the potential force with
+    // la3 = a^{3+alpha}, the staple force with lam1 = a^{alpha-1}; hdU is the
+    // link drift weight (time times a^{alpha-1}).  All 1 (hdU = hd) at a = 1.
+    double la1, la3, lam1, hdU;
+    // if not null: {ck, la1, la3, lam1, hd, hdU} from device memory (written by
+    // the self-consistent scale-factor update)
+    const double *dw;
     double *partials;
     unsigned *ticket;
     ScaleRecord *sc;
@@ -104,9 +112,20 @@ __device__ __forceinline__ void isospin(double a, double b, double c, double d, 
 // checks 8 N^3 < 2^32), so every array access is a uniform base plus one
 // 32-bit offset.  c[] = (x, y, z), cp[] / cm[] their periodic successors and
 // predecessors.
+// the pass weights of SU2Args, from device memory if SU2Args::dw is set
+struct SU2W {
+    double ck, la1, la3, lm1, hd, hdU;
+};
+
+__device__ inline SU2W su2_weights(const SU2Args &g)
+{
+    if (g.dw) return SU2W{g.dw[0], g.dw[1], g.dw[2], g.dw[3], g.dw[4], g.dw[5]};
+    return SU2W{g.ck, g.la1, g.la3, g.lam1, g.hd, g.hdU};
+}
+
 template <int MODE, int NQ>
-__device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], const int (&cp)[3], const int (&cm)[3],
-                                         double (&acc)[NQ])
+__device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const int (&c)[3], const int (&cp)[3],
+                                         const int (&cm)[3], double (&acc)[NQ])
 {
     const unsigned N = (unsigned)g.N;
     auto off = [&](int x, int y, int z) { return (unsigned)x + N * ((unsigned)y + N * (unsigned)z); };
@@ -182,14 +201,14 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
             S = qadd(S, qadd(Sp, Sm));
         }
         const Q4 W = qmul(Ul[i], S);
-        FE[3 * i + 0] = gdx * j1 - mcoef * W.x;
-        FE[3 * i + 1] = gdx * j2 - mcoef * W.y;
-        FE[3 * i + 2] = gdx * j3 - mcoef * W.z;
+        FE[3 * i + 0] = wt.la1 * (gdx * j1) - wt.lm1 * (mcoef * W.x);
+        FE[3 * i + 1] = wt.la1 * (gdx * j2) - wt.lm1 * (mcoef * W.y);
+        FE[3 * i + 2] = wt.la1 * (gdx * j3) - wt.lm1 * (mcoef * W.z);
     }
     const double m2 = 0.5 * (a0 * a0 + b0 * b0 + c0 * c0 + d0 * d0);
     const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
-    const double F[4] = {l0 * inv_dx2 - vp * a0, l1 * inv_dx2 - vp * b0, l2 * inv_dx2 - vp * c0,
-                         l3 * inv_dx2 - vp * d0};
+    const double F[4] = {wt.la1 * (l0 * inv_dx2) - wt.la3 * (vp * a0), wt.la1 * (l1 * inv_dx2) - wt.la3 * (vp * b0),
+                         wt.la1 * (l2 * inv_dx2) - wt.la3 * (vp * c0), wt.la1 * (l3 * inv_dx2) - wt.la3 * (vp * d0)};
     double pv[4], ev[9];
 #pragma unroll
     for (int k = 0; k < 4; ++k) pv[k] = ld32((const double *)g.pi[k], n);
@@ -200,12 +219,12 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
         double kin = 0.0, ke = 0.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double s = pv[k] + g.ck * F[k];
+            const double s = pv[k] + wt.ck * F[k];
             kin += s * s;
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const double s = ev[k] + g.ck * FE[k];
+            const double s = ev[k] + wt.ck * FE[k];
             ke += s * s;
         }
         acc[0] += 0.5 * kin;
@@ -265,16 +284,16 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
         double pn[4], en[9];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            pn[k] = pv[k] + g.ck * F[k];
+            pn[k] = pv[k] + wt.ck * F[k];
             st32(g.pi[k], n, pn[k]);
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            en[k] = ev[k] + g.ck * FE[k];
+            en[k] = ev[k] + wt.ck * FE[k];
             st32(g.E[k], n, en[k]);
         }
         if (MODE == kSU2Step || AOS) {
-            const double4 po{a0 + g.hd * pn[0], b0 + g.hd * pn[1], c0 + g.hd * pn[2], d0 + g.hd * pn[3]};
+            const double4 po{a0 + wt.hd * pn[0], b0 + wt.hd * pn[1], c0 + wt.hd * pn[2], d0 + wt.hd * pn[3]};
             if constexpr (AOS) {
                 st4(g.phi_out4, n, po);
             } else {
@@ -283,10 +302,10 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const int (&c)[3], co
                 st32(g.phi_out[2], n, po.z);
                 st32(g.phi_out[3], n, po.w);
             }
-            const double hgdx = g.hd * g.g * g.dx;
+            const double hgdx = wt.hdU * g.g * g.dx;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                // exp(-i hd g dx E.T) = cos(th/2) - i sin(th/2) e.sigma, th = hd g dx |E|
+                // exp(-i hdU g dx E.T) = cos(th/2) - i sin(th/2) e.sigma, th = hdU g dx |E|
                 const double ex = en[3 * i], ey = en[3 * i + 1], ez = en[3 * i + 2];
                 const double len = sqrt(ex * ex + ey * ey + ez * ez);
                 double sh, chh;
@@ -339,6 +358,7 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
 #pragma unroll
     for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
 
+    const SU2W wt = su2_weights(g);
     if (x < N && y < N) {
         int c[3] = {x, y, z0}, cp[3], cm[3];
         cp[0] = x + 1 == N ? 0 : x + 1;
@@ -350,7 +370,7 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
             c[2] = z;
             cp[2] = z + 1 == N ? 0 : z + 1;
             cm[2] = z == 0 ? N - 1 : z - 1;
-            su2_site<MODE, NQ>(g, c, cp, cm, acc);
+            su2_site<MODE, NQ>(g, wt, c, cp, cm, acc);
         }
     }
 

@@ -53,8 +53,8 @@ def _init(params, fields):
     (dict(N=8, dx=0.5, dt=0.3), L.LAT_EINVAL),          # dt/dx above 1/sqrt(3)
     (dict(N=8, dx=-1.0, dt=0.01), L.LAT_EINVAL),
     (dict(N=8, dx=0.5, dt=0.01, integrator="lf", expansion="self", lf_staggered=1), L.LAT_EINVAL),  # needs b0
-    (dict(N=8, dx=0.5, dt=0.01, potential="su2_higgs", integrator="vv2", expansion="fixed", H0=0.1),
-     L.LAT_EUNSUPPORTED),
+    (dict(N=8, dx=0.5, dt=0.01, potential="su2_higgs", integrator="vv2", expansion="fixed", H0=0.1,
+          precision="f32"), L.LAT_EUNSUPPORTED),
     (dict(N=8, dx=0.5, dt=0.01, potential="abelian_higgs", precision="f32"), L.LAT_EUNSUPPORTED),
     (dict(N=8, dx=0.5, dt=0.01, integrator="vv2", lf_staggered=1), L.LAT_EINVAL),
 ])
@@ -109,8 +109,6 @@ def _su2_fields():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(integrator="vv4", expansion="self"), L.LAT_EUNSUPPORTED),
-    (dict(expansion="fixed", H0=0.1), L.LAT_EUNSUPPORTED),
     (dict(precision="f32"), L.LAT_EUNSUPPORTED),
     (dict(g=0.0), L.LAT_EINVAL),
     (dict(N=1700), L.LAT_EUNSUPPORTED),        # 8 N^3 >= 2^32: 32-bit offsets

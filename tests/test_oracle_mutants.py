@@ -108,8 +108,8 @@ MUTANTS = [
     ("a drift adjoint without h", "*lb += h * la1;", "*lb += la1;", "test_oracle_adjoint_self.py"),
     ("adjoint drift", "for (size_t n = 0; n < V; ++n) lpi[s][n] += dr * lphi[s][n];",
      "for (size_t n = 0; n < V; ++n) lpi[s][n] += 0.5 * dr * lphi[s][n];", "test_oracle_adjoint.py"),
-    ("SU(2) magnetic force sign", "- 2.0 / (g * dx * dx * dx) * vs[k];", "+ 2.0 / (g * dx * dx * dx) * vs[k];",
-     "test_oracle_su2.py"),
+    ("SU(2) magnetic force sign", "- cm_ * (2.0 / (g * dx * dx * dx) * vs[k]);",
+     "+ cm_ * (2.0 / (g * dx * dx * dx) * vs[k]);", "test_oracle_su2.py"),
     ("SU(2) current without conjugation", "t += conj(psi[r]) * 0.5 * PAULI[k][r][s] * a[s];",
      "t += psi[r] * 0.5 * PAULI[k][r][s] * a[s];", "test_oracle_su2.py"),
     ("SU(2) lower staple without a dagger", "mat2 Sm = m2_mul(m2_mul(m2_dag(su2_link(U, j, nimj)),",
