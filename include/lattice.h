@@ -283,6 +283,10 @@ lat_status lattice_batch_tile(const lat_ctx *ctx, int32_t N, int32_t *tile_x, in
 /* Advance |nsteps| time steps (sec. 4.5.2; LF and VV of sec. 4.3), backward
  * in time (dt -> -dt) when nsteps < 0.  For LF a backward run needs momenta at
  * integer time or staggered backward (LAT_ESTATE otherwise; call lattice_sync).
+ * LF steps of real scalar fields with N <= 32 and no self-consistent
+ * expansion run up to four steps per kernel launch (each block recomputes the
+ * edge of its window, so the state agrees with one pass per step to
+ * rounding); the number of launches is visible in lattice_stats.
  * Asynchronous on the context stream. */
 lat_status lattice_step(lat_ctx *ctx, int64_t nsteps);
 

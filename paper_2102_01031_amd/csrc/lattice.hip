@@ -37,6 +37,7 @@
 #include "stage_gauss.hpp"
 #include "stage_adjoint.hpp"
 #include "stage_batch.hpp"
+#include "stage_slab.hpp"
 #include "spectrum.hpp"
 #include "stage_adjoint_self.hpp"
 
@@ -173,6 +174,9 @@ struct lat_ctx {
     double *self_part = nullptr;        // its per-block partials and totals
     size_t self_part_cap = 0;
     bool sums_fresh = false;            // sc->sums are those of the current state (see lattice_energy)
+    int slab_steps = 0, slab_zs = 0, slab_yb = 0;   // lf_slab: steps per launch (0: off), planes and rows per block
+    const void *slab_fn = nullptr;      // the lf_slab instance for those, and its dynamic LDS
+    size_t slab_lds = 0;
     double *traj_rec = nullptr;         // set: velocity-Verlet passes store (a, b) of kick point p at traj_rec + 2 p
     double *self_traj = nullptr;        // a, a' of every step, scale records of the checkpoints, scalars
     size_t self_traj_cap = 0;           // (in doubles)
@@ -939,6 +943,128 @@ lat_status step_lf_self(lat_ctx *c, int64_t ns, int dir)
     return LAT_OK;
 }
 
+// Temporal blocking for small lattices (stage_slab.hpp): S leapfrog steps per
+// launch, blocks of ZS planes by YB rows, for real scalar lattices with
+// N <= 32, S = 2 .. 5 and ZS = 1 or 2 compiled.  The window (ZS + 2 S planes
+// by YB + 2 S rows) must not wrap onto itself, its rows of N sites must fit a
+// block and its advanced planes the LDS a block may use.  Default S = 4,
+// ZS = 1, YB = 4 (at 32^3: 256 blocks of 12 x 32 threads); LATTICE_SLAB=
+// "S,ZS[,YB]" overrides, "0" turns it off.
+template <typename T, int NF, int S, int ZS>
+void slab_kernel_of(const void **fn, size_t *lds, int N, int yb)
+{
+    *fn = (const void *)lf_slab<T, NF, S, ZS>;
+    *lds = slab_lds<T, NF, S, ZS>(N, yb);
+}
+
+template <typename T, int NF, int S>
+bool slab_pick_zs(int zs, const void **fn, size_t *lds, int N, int yb)
+{
+    switch (zs) {
+    case 1: slab_kernel_of<T, NF, S, 1>(fn, lds, N, yb); return true;
+    case 2: slab_kernel_of<T, NF, S, 2>(fn, lds, N, yb); return true;
+    default: return false;
+    }
+}
+
+template <typename T, int NF>
+bool slab_pick(int S, int zs, const void **fn, size_t *lds, int N, int yb)
+{
+    switch (S) {
+    case 2: return slab_pick_zs<T, NF, 2>(zs, fn, lds, N, yb);
+    case 3: return slab_pick_zs<T, NF, 3>(zs, fn, lds, N, yb);
+    case 4: return slab_pick_zs<T, NF, 4>(zs, fn, lds, N, yb);
+    case 5: return slab_pick_zs<T, NF, 5>(zs, fn, lds, N, yb);
+    default: return false;
+    }
+}
+
+bool slab_kernel(const lat_ctx *c, int S, int zs, int yb, const void **fn, size_t *lds)
+{
+    if (c->f32)
+        return c->nf == 1 ? slab_pick<float, 1>(S, zs, fn, lds, c->N, yb) : slab_pick<float, 2>(S, zs, fn, lds, c->N, yb);
+    return c->nf == 1 ? slab_pick<double, 1>(S, zs, fn, lds, c->N, yb) : slab_pick<double, 2>(S, zs, fn, lds, c->N, yb);
+}
+
+void slab_config(lat_ctx *c)
+{
+    c->slab_steps = c->slab_zs = c->slab_yb = 0;
+    c->slab_fn = nullptr;
+    c->slab_lds = 0;
+    if (c->batch || c->u1 || c->su2 || c->N > 32) return;
+    int S = 4, zs = 1, yb = 4;
+    if (const char *e = std::getenv("LATTICE_SLAB")) {
+        if (std::atoi(e) == 0) return;
+        if (std::sscanf(e, "%d,%d,%d", &S, &zs, &yb) < 2) return;
+    }
+    int lim = 0;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || lim <= 0)
+        return;
+    const void *fn = nullptr;
+    size_t lds = 0;
+    // fall back to fewer steps per launch, then fewer rows per block, while
+    // the window does not fit
+    const int N = c->N;
+    for (S = std::min(S, 5); S >= 2; --S) {
+        int b = std::min(yb, N - 2 * S);
+        while (b >= 1 && (b + 2 * S) * N > kSlabMaxThreads) --b;
+        if (b >= 1 && zs + 2 * S <= N && slab_kernel(c, S, zs, b, &fn, &lds) && lds <= (size_t)lim) {
+            yb = b;
+            break;
+        }
+    }
+    if (S < 2) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    c->slab_steps = S;
+    c->slab_zs = zs;
+    c->slab_yb = yb;
+    c->slab_fn = fn;
+    c->slab_lds = lds;
+}
+
+// one launch of `steps` (1 .. S) leapfrog steps from the coefficients of step `first`
+template <typename T>
+lat_status slab_launch_t(lat_ctx *c, int64_t first, int steps, hipStream_t st)
+{
+    SlabArgs<T> a{};
+    for (int f = 0; f < c->nf; ++f) {
+        a.phi_in[f] = (const T *)c->phi[f][c->cur_phi[f]];
+        a.pi_in[f] = (const T *)c->pi[f][c->cur_pi[f]];
+        a.phi_out[f] = (T *)c->phi[f][c->cur_phi[f] ^ 1];
+        a.pi_out[f] = (T *)c->pi[f][c->cur_pi[f] ^ 1];
+    }
+    a.N = c->N;
+    a.yb = c->slab_yb;
+    a.steps = steps;
+    a.inv_dx2 = 1.0 / (c->p.dx * c->p.dx);
+    a.lam = c->p.lambda;
+    a.q = c->p.potential == LAT_PHI4_CHI2 ? c->p.q : 0.0;
+    a.coef = c->coef + first;
+    const dim3 grid((unsigned)((c->N + c->slab_zs - 1) / c->slab_zs),
+                    (unsigned)((c->N + c->slab_yb - 1) / c->slab_yb));
+    const dim3 blk((unsigned)((((c->slab_yb + 2 * c->slab_steps) * c->N + 63) / 64) * 64));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->profiling) {
+        lat_status s = timing_begin(c, &ev0, &ev1);
+        if (s != LAT_OK) return s;
+    }
+    void *args[] = {&a};
+    HIPCHK(c, hipLaunchKernel(c->slab_fn, grid, blk, args, c->slab_lds, st));
+    if (c->profiling) {
+        lat_status s = timing_end(c, ev0, ev1, kKickDrift);
+        if (s != LAT_OK) return s;
+    }
+    c->launches[kKickDrift] += 1;
+    for (int f = 0; f < c->nf; ++f) {
+        c->cur_phi[f] ^= 1;
+        c->cur_pi[f] ^= 1;
+    }
+    return LAT_OK;
+}
+
 lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
 {
     if (c->p.expansion == LAT_EXP_SELF) return step_lf_self(c, ns, dir);
@@ -961,13 +1087,26 @@ lat_status step_lf(lat_ctx *c, int64_t ns, int dir)
         stag = dir;
     }
     if ((s = upload_coef(c, (size_t)ns)) != LAT_OK) return s;
-    s = launch_passes(c, dir * ns, ns, [&](hipStream_t st) {
-        for (int64_t k = 0; k < ns; ++k) {
-            lat_status r = run_pass(c, kKickDrift, (int)k, kLastStore, st);
-            if (r != LAT_OK) return r;
-        }
-        return LAT_OK;
-    });
+    if (c->slab_steps > 0) {
+        const int64_t S = c->slab_steps, nl = (ns + S - 1) / S;
+        s = launch_passes(c, dir * ns, nl, [&](hipStream_t st) {
+            for (int64_t j = 0; j < nl; ++j) {
+                const int steps = (int)std::min<int64_t>(S, ns - j * S);
+                lat_status r = c->f32 ? slab_launch_t<float>(c, j * S, steps, st)
+                                      : slab_launch_t<double>(c, j * S, steps, st);
+                if (r != LAT_OK) return r;
+            }
+            return LAT_OK;
+        });
+    } else {
+        s = launch_passes(c, dir * ns, ns, [&](hipStream_t st) {
+            for (int64_t k = 0; k < ns; ++k) {
+                lat_status r = run_pass(c, kKickDrift, (int)k, kLastStore, st);
+                if (r != LAT_OK) return r;
+            }
+            return LAT_OK;
+        });
+    }
     if (s != LAT_OK) return s;
     c->lf_stag = dir;
     c->t = t_start + (double)ns * h;
@@ -1305,6 +1444,7 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     c->t = p->t0;
     c->lf_stag = p->lf_staggered;
     geometry_from_env(c);
+    slab_config(c);
     const size_t bytes = c->vol * c->esize;
 
     auto bail = [&](lat_status st, const std::string &m) {
