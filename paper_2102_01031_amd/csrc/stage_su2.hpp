@@ -39,6 +39,7 @@ struct SU2Args {
     const double4 *U_in4[3];
     double4 *U_out4[3];
     int N, tiles_x, tiles_y, zc;   // zc: z planes per block
+    int band;                      // > 0: y tiles per XCD band (tiles_y = 8 band), see su2_stage
     int down;                      // march the z column downward (sites are independent)
     double dx, g, lam, v;
     double ck;   // kick weight
@@ -66,6 +67,35 @@ __device__ __forceinline__ double4 ld4(const double4 *base, unsigned i)
 __device__ __forceinline__ void st4(double4 *base, unsigned i, double4 v)
 {
     *(double4 *)((char *)base + (size_t)(i * 32u)) = v;
+}
+
+// Streamed accesses of the pass (the momenta, read and written once, and the
+// output records): non-temporal when NT, so they do not displace the input
+// records that neighbouring sites read again from L2.
+typedef double su2_nd4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ double ld_s(const double *base, unsigned i)
+{
+    const double *p = (const double *)((const char *)base + (size_t)(i * 8u));
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st_s(double *base, unsigned i, double v)
+{
+    double *p = (double *)((char *)base + (size_t)(i * 8u));
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st4_s(double4 *base, unsigned i, double4 v)
+{
+    if constexpr (NT) {
+        const su2_nd4 w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, (su2_nd4 *)((char *)base + (size_t)(i * 32u)));
+    } else {
+        st4(base, i, v);
+    }
 }
 constexpr int kSU2Sums = 8, kSU2Maxes = 3;
 
@@ -123,7 +153,7 @@ __device__ inline SU2W su2_weights(const SU2Args &g)
     return SU2W{g.ck, g.la1, g.la3, g.lam1, g.hd, g.hdU};
 }
 
-template <int MODE, int NQ>
+template <int MODE, int NQ, bool NT>
 __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const int (&c)[3], const int (&cp)[3],
                                          const int (&cm)[3], double (&acc)[NQ])
 {
@@ -211,9 +241,9 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
                          wt.la1 * (l2 * inv_dx2) - wt.la3 * (vp * c0), wt.la1 * (l3 * inv_dx2) - wt.la3 * (vp * d0)};
     double pv[4], ev[9];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pv[k] = ld32((const double *)g.pi[k], n);
+    for (int k = 0; k < 4; ++k) pv[k] = ld_s<NT>((const double *)g.pi[k], n);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) ev[k] = ld32((const double *)g.E[k], n);
+    for (int k = 0; k < 9; ++k) ev[k] = ld_s<NT>((const double *)g.E[k], n);
 
     if (MODE == kSU2Energy) {
         double kin = 0.0, ke = 0.0;
@@ -285,22 +315,22 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             pn[k] = pv[k] + wt.ck * F[k];
-            st32(g.pi[k], n, pn[k]);
+            st_s<NT>(g.pi[k], n, pn[k]);
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             en[k] = ev[k] + wt.ck * FE[k];
-            st32(g.E[k], n, en[k]);
+            st_s<NT>(g.E[k], n, en[k]);
         }
         if (MODE == kSU2Step || AOS) {
             const double4 po{a0 + wt.hd * pn[0], b0 + wt.hd * pn[1], c0 + wt.hd * pn[2], d0 + wt.hd * pn[3]};
             if constexpr (AOS) {
-                st4(g.phi_out4, n, po);
+                st4_s<NT>(g.phi_out4, n, po);
             } else {
-                st32(g.phi_out[0], n, po.x);
-                st32(g.phi_out[1], n, po.y);
-                st32(g.phi_out[2], n, po.z);
-                st32(g.phi_out[3], n, po.w);
+                st_s<NT>(g.phi_out[0], n, po.x);
+                st_s<NT>(g.phi_out[1], n, po.y);
+                st_s<NT>(g.phi_out[2], n, po.z);
+                st_s<NT>(g.phi_out[3], n, po.w);
             }
             const double hgdx = wt.hdU * g.g * g.dx;
 #pragma unroll
@@ -318,24 +348,27 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
                 }
                 const Q4 Un = qmul(R, Ul[i]);
                 if constexpr (AOS) {
-                    st4(g.U_out4[i], n, double4{Un.w, Un.x, Un.y, Un.z});
+                    st4_s<NT>(g.U_out4[i], n, double4{Un.w, Un.x, Un.y, Un.z});
                 } else {
-                    st32(g.U_out[4 * i], n, Un.w);
-                    st32(g.U_out[4 * i + 1], n, Un.x);
-                    st32(g.U_out[4 * i + 2], n, Un.y);
-                    st32(g.U_out[4 * i + 3], n, Un.z);
+                    st_s<NT>(g.U_out[4 * i], n, Un.w);
+                    st_s<NT>(g.U_out[4 * i + 1], n, Un.x);
+                    st_s<NT>(g.U_out[4 * i + 2], n, Un.y);
+                    st_s<NT>(g.U_out[4 * i + 3], n, Un.z);
                 }
             }
         }
     }
 }
 
-// Block = TX x TY sites of a z column [z0, z0 + zc); logical blocks run x
-// tile fastest, then y tile, then z chunk, dealt to the XCDs in contiguous
-// ranges, so the blocks of one XCD march neighbouring columns together and
-// a site's values are reused from L2 by the planes z - 1, z, z + 1 that
-// read them.
-template <int TX, int TY, int MODE>
+// Block = TX x TY sites of a z column [z0, z0 + zc).  Logical blocks are
+// dealt to the XCDs in contiguous ranges.  Plane-wide order (band = 0): x
+// tile fastest, then y tile, then z chunk, so an XCD's resident blocks march
+// whole planes together.  Band order (band > 0): XCD k owns the y tiles
+// [k band, (k + 1) band) over all z chunks, x tile fastest, then y tile, then
+// z chunk (in reverse when marching down), so its resident blocks cover a
+// compact region and the records of the planes z - 1, z, z + 1 that a site's
+// stencil reads stay in that XCD's L2 between their uses.
+template <int TX, int TY, int MODE, bool STREAM>
 __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
 {
     constexpr int NT = TX * TY;
@@ -346,11 +379,22 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int lid = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int bx = lid % g.tiles_x;
-    const int rest = lid / g.tiles_x;
-    const int by = rest % g.tiles_y;
-    const int bz = rest / g.tiles_y;
     const int N = g.N;
+    int bx, by, bz;
+    if (g.band > 0) {
+        const int per = gridDim.x / 8;   // the host launches 8 tiles_x band z-chunk blocks
+        const int xcd = lid / per, r = lid % per;
+        bx = r % g.tiles_x;
+        const int r2 = r / g.tiles_x;
+        by = xcd * g.band + r2 % g.band;
+        bz = r2 / g.band;
+        if (g.down) bz = (N + g.zc - 1) / g.zc - 1 - bz;
+    } else {
+        bx = lid % g.tiles_x;
+        const int rest = lid / g.tiles_x;
+        by = rest % g.tiles_y;
+        bz = rest / g.tiles_y;
+    }
     const int x = bx * TX + tx, y = by * TY + ty;
     const int z0 = bz * g.zc, z1 = min(z0 + g.zc, N);
 
@@ -370,7 +414,7 @@ __global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
             c[2] = z;
             cp[2] = z + 1 == N ? 0 : z + 1;
             cm[2] = z == 0 ? N - 1 : z - 1;
-            su2_site<MODE, NQ>(g, wt, c, cp, cm, acc);
+            su2_site<MODE, NQ, STREAM>(g, wt, c, cp, cm, acc);
         }
     }
 

@@ -138,6 +138,38 @@ def test_su2_alternating_march(N, zc, steps, layout):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("layout", ["records", "soa"])
+@pytest.mark.parametrize("N,zc,steps", [(32, None, 5), (64, None, 4), (64, 3, 3)])
+def test_su2_band_order(N, zc, steps, layout):
+    """Blocks dealt to the XCDs in y bands over all planes (the default where
+    N is a multiple of 32; with a ragged last z chunk at 64 / 3) with the
+    momenta and output records non-temporal (the default), marches
+    alternating: against the oracle, and every field bitwise equal to the
+    plane-wide order (LATTICE_SU2_BAND=0) and to cached streams
+    (LATTICE_SU2_NT=0)."""
+    import torch
+    wl = workloads.SU2_HIGGS_128
+    kw = su2_kwargs(wl, N)
+    fields = inputs.random_su2_state(N, 90 + N)
+    say(f"[su2] band order N={N} zc={zc} steps={steps} layout={layout}")
+    out = []
+    for band, nt in ((None, None), ("0", None), (None, "0")):
+        with tile_env(band, "LATTICE_SU2_BAND"), tile_env(nt, "LATTICE_SU2_NT"), \
+                tile_env(None if zc is None else str(zc), "LATTICE_SU2_ZC"), \
+                tile_env("0" if layout == "soa" else None, "LATTICE_SU2_AOS"):
+            lat, gt = gpu_su2(kw, fields, [steps])
+        out.append([t.cpu() for group in gt for t in (group if isinstance(group, (list, tuple)) else [group])])
+        if band is None and nt is None:
+            eg = lat.energy()
+            st = oracle_su2(kw, fields).run(steps)
+            compare_su2(gt, st, TOL, f"su2-band-{N}")
+            compare_su2_energy(eg, st.energy(), TOL, f"su2-band-{N}")
+        lat.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("N,steps", [(12, 40), (32, 10)])
 def test_su2_parity_workload_state(N, steps):
     """The bench workload's initial state (white-noise doublet direction, unit
