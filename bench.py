@@ -57,6 +57,28 @@ def stored_traffic(kind: str, per_launch_alg: float):
     return k["hbm_bytes_per_launch"]
 
 
+def device_warmup(Lattice, tp, tq, stream, kw, log, min_ms=30.0):
+    """Step a scratch context on copies of the fields for at least min_ms of
+    wall time; returns what was run (reported in the JSON line)."""
+    import torch
+    cp = [t.clone() for t in tp]
+    cq = [t.clone() for t in tq]
+    scratch = Lattice(cp, cq, stream=stream, **kw)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    steps = 0
+    while 1e3 * (time.perf_counter() - c0) < min_ms:
+        scratch.step(5)
+        torch.cuda.synchronize()
+        steps += 5
+    ms = 1e3 * (time.perf_counter() - c0)
+    scratch.close()
+    del cp, cq
+    log(f"[bench] device warm-up: {steps} steps on a scratch copy, {ms:.1f} ms")
+    return {"what": "steps of a scratch context on copies of the fields, before the W warmup steps",
+            "steps": steps, "ms": ms}
+
+
 def measured_ceiling(log):
     """Streaming ceiling of the stage kernel's access pattern (4 float64 arrays
     of 256^3 in, 4 out) from the probe csrc/ceiling, run as a child process
@@ -307,6 +329,13 @@ def main():
     kw = dict(N=N, dx=wl.dx, dt=wl.dt, integrator=wl.integrator, expansion=wl.expansion, potential=wl.potential,
               lam=wl.lam, q=wl.q, alpha=wl.alpha, kappa2=wl.kappa2, a0=wl.a0, precision=args.precision)
     stream = torch.cuda.current_stream()
+    # device warm-up: the stage kernel reaches its steady per-pass time only
+    # after about 10 ms of sustained stepping (measured on one box: 200 us per
+    # pass in a first 20-step call after 5 steps, 191.9 us after 20, 206.9 us
+    # after 0.2 s idle), so a scratch context on copies of the fields steps
+    # for at least 30 ms first.  It touches neither the timed lattice nor its
+    # state; the W warmup steps and the K timed steps below are unchanged.
+    dw = device_warmup(Lattice, tp, tq, stream, kw, log)
     lat = Lattice(tp, tq, stream=stream, **kw)
     log(f"[bench] warmup {args.warmup} steps")
     lat.step(args.warmup)
@@ -430,6 +459,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "device_warmup": dw,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",

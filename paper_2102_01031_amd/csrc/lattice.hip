@@ -811,6 +811,12 @@ lat_status launch_passes(lat_ctx *c, int64_t key_n, int64_t passes, F &&enqueue)
 // ---------------------------------------------------------------------------
 // coefficient tables
 // ---------------------------------------------------------------------------
+// Coefficient tables start with room for 2048 kick points (192 KB on the
+// device, four pinned staging slots of the same size) and at least double
+// when a call needs more, so that calls after the first rarely allocate (the
+// growth frees and reallocates, which synchronises and drops captured graphs).
+constexpr size_t kCoefInitial = 2048;
+
 lat_status reserve_coef(lat_ctx *c, size_t n)
 {
     if (n > c->coef_cap) {
@@ -819,7 +825,7 @@ lat_status reserve_coef(lat_ctx *c, size_t n)
         c->graph_n = 0;
         if (c->coef) HIPCHK(c, hipFree(c->coef));
         c->coef = nullptr;
-        size_t cap = n < 64 ? 64 : n;
+        const size_t cap = std::max(n, std::max(kCoefInitial, 2 * c->coef_cap));
         if (hipMalloc(&c->coef, cap * sizeof(PassCoef)) != hipSuccess)
             return fail(c, LAT_ENOMEM, "coefficient table allocation failed");
         c->coef_cap = cap;
@@ -831,7 +837,7 @@ lat_status reserve_coef(lat_ctx *c, size_t n)
         }
         if (c->ring_base) HIPCHK(c, hipHostFree(c->ring_base));
         c->ring_base = nullptr;
-        size_t cap = n < 64 ? 64 : n;
+        const size_t cap = std::max(n, std::max(kCoefInitial, 2 * c->ring_cap));
         if (hipHostMalloc((void **)&c->ring_base, lat_ctx::kRing * cap * sizeof(PassCoef), hipHostMallocDefault) !=
             hipSuccess)
             return fail(c, LAT_ENOMEM, "pinned coefficient staging allocation failed");
