@@ -147,6 +147,7 @@ struct lat_ctx {
     bool rows = false;   // whole-row kernel (N = 64 * XS)
     int rows_ty = 8;
     int rows_pf = 1;     // whole-row kernel prefetch depth (planes)
+    int en_pf = 0, en_zc = 0, en_nblocks = 0;   // energy pass geometry (en_nblocks 0: that of the stage passes)
     int rows_vw = 1;     // whole-row kernel sites per lane and access (1, or 16-byte vectors)
     int rows_y_fastest = 0;   // whole-row kernel block order (see stage_rows.hpp)
     int rows_alternate = 0;   // whole-row kernel: alternate the z march direction pass by pass
@@ -311,6 +312,30 @@ void set_rows_geometry(lat_ctx *c, int ty, int zc)
     c->zc = zc;
     c->chunks_z = (N + zc - 1) / zc;
     c->nblocks = c->tiles_y * c->chunks_z;
+}
+
+// Energy pass geometry of the whole-row kernel.  Read-only, the pass needs
+// more bytes in flight than the stage passes' one wave per SIMD give: at
+// N = 256 it runs one plane ahead in float64 (246 VGPRs, two waves per SIMD)
+// and two in float32, with 32-plane z chunks (two blocks per CU); 134-144
+// against 125-130 us in float64, 74-75 against 56-58 us in float32 (twice,
+// one box).  LATTICE_ENERGY_GEOM="pf,zc" overrides (same rows per block),
+// "0": the stage passes' geometry.
+void energy_geometry(lat_ctx *c)
+{
+    c->en_pf = c->en_zc = c->en_nblocks = 0;
+    if (!c->rows || c->batch) return;
+    int pf = 0, zc = 0;
+    if (c->N == 256 && c->rows_ty == 4) {
+        pf = c->f32 ? 2 : 1;
+        zc = 32;
+    }
+    if (const char *e = std::getenv("LATTICE_ENERGY_GEOM"))
+        if (std::sscanf(e, "%d,%d", &pf, &zc) != 2) pf = zc = 0;
+    if (pf < 1 || pf > 3 || zc < 1 || zc > c->N) return;
+    c->en_pf = pf;
+    c->en_zc = zc;
+    c->en_nblocks = c->tiles_y * ((c->N + zc - 1) / zc);
 }
 
 void geometry_from_env(lat_ctx *c)
@@ -640,11 +665,16 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
         if (st != LAT_OK) return st;
     }
     hipError_t e;
+    int nb = c->nblocks, pf = c->rows_pf, lp = c->rows_lp;
+    if (variant == kEnergy && c->rows && c->en_nblocks > 0) {
+        a.zc = c->en_zc;
+        nb = c->en_nblocks;
+        pf = c->en_pf;
+        lp = 0;
+    }
     if (c->rows)
-        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream,
-                                           c->rows_lp)
-                       : launch_rows<T, 2>(c->N, c->rows_ty, c->rows_pf, c->rows_vw, variant, a, c->nblocks, stream,
-                                           c->rows_lp);
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, pf, c->rows_vw, variant, a, nb, stream, lp)
+                       : launch_rows<T, 2>(c->N, c->rows_ty, pf, c->rows_vw, variant, a, nb, stream, lp);
     else
         e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
                        : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);
@@ -1454,6 +1484,7 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
     c->lf_stag = p->lf_staggered;
     geometry_from_env(c);
     slab_config(c);
+    energy_geometry(c);
     const size_t bytes = c->vol * c->esize;
 
     auto bail = [&](lat_status st, const std::string &m) {
@@ -1493,7 +1524,7 @@ lat_status lattice_init(lat_ctx **out, const lat_params *p, const lat_fields *f,
         const char *aenv = std::getenv("LATTICE_SU2_AOS");
         c->su2_aos_on = !(aenv && std::atoi(aenv) == 0) && (double)c->vol * 32.0 < 4294967296.0;
     }
-    c->partial_cap = (size_t)(c->nblocks > 1 ? c->nblocks : 1) * kMaxQ + 64;
+    c->partial_cap = (size_t)std::max(c->nblocks > 1 ? c->nblocks : 1, c->en_nblocks) * kMaxQ + 64;
     if (c->su2) c->partial_cap = su2_partial_capacity(c->N) + 64;
     if (c->u1) {
         c->partial_cap = u1_partial_capacity(c->N) + 64;
