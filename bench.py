@@ -330,7 +330,7 @@ def main():
               lam=wl.lam, q=wl.q, alpha=wl.alpha, kappa2=wl.kappa2, a0=wl.a0, precision=args.precision)
     stream = torch.cuda.current_stream()
     # device warm-up: the stage kernel reaches its steady per-pass time only
-    # after about 10 ms of sustained stepping (measured on one box: 200 us per
+    # after about 10 ms of sustained stepping (measured on one GPU: 200 us per
     # pass in a first 20-step call after 5 steps, 191.9 us after 20, 206.9 us
     # after 0.2 s idle), so a scratch context on copies of the fields steps
     # for at least 30 ms first.  It touches neither the timed lattice nor its

@@ -319,7 +319,7 @@ void set_rows_geometry(lat_ctx *c, int ty, int zc)
 // N = 256 it runs one plane ahead in float64 (246 VGPRs, two waves per SIMD)
 // and two in float32, with 32-plane z chunks (two blocks per CU); 134-144
 // against 125-130 us in float64, 74-75 against 56-58 us in float32 (twice,
-// one box).  LATTICE_ENERGY_GEOM="pf,zc" overrides (same rows per block),
+// one GPU).  LATTICE_ENERGY_GEOM="pf,zc" overrides (same rows per block),
 // "0": the stage passes' geometry.
 void energy_geometry(lat_ctx *c)
 {
@@ -2445,7 +2445,7 @@ size_t su2_partial_capacity(int N)
 // overrides the planes per block.  The step passes read and write the
 // momenta and write the output records non-temporally (LATTICE_SU2_NT=0:
 // through the caches), which keeps the input records in L2.  At 128^3 on
-// one box: 286.7 us per pass plane-wide, 236.7-240.1 in bands, 227.6-228.0
+// one GPU: 286.7 us per pass plane-wide, 236.7-240.1 in bands, 227.6-228.0
 // in bands with the streams non-temporal.
 void su2_geometry(lat_ctx *c)
 {

@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     ap.add_argument("--all-trace", help="--kernel-trace --stats run of the whole default benchmark")
     ap.add_argument("--all-command", default="python3 bench.py --no-cpu-baseline")
-    ap.add_argument("--note", default="", help="provenance line for the summary (which runs, which boxes)")
+    ap.add_argument("--note", default="", help="provenance line for the summary (which runs, which machines)")
     a = ap.parse_args()
     if a.all_trace:
         all_kernels(a.all_trace, a.all_command, a.out)
