@@ -103,3 +103,28 @@ def test_slab_staggered_sync_and_energy():
         st.run(4)
         compare_state(tp, tq, st, TOL, "after sync")
         lat.close()
+
+
+def test_slab_graph_replays_match_direct_launches(monkeypatch):
+    """Calls of 40 steps (10 launches, captured once and replayed) give bitwise
+    the arrays of the same calls launched directly (LATTICE_NO_GRAPH)."""
+    import torch
+    wl = workloads.LPHI4_32
+    phi, pi = wl.initial_fields(N=32)
+    kw = scalar_kwargs(wl, N=32, integrator="lf", expansion="fixed")
+    with tile_env(None, "LATTICE_SLAB"):
+        la, pa, qa = gpu_scalar(kw, phi, pi, [])
+        lb, pb, qb = gpu_scalar(kw, phi, pi, [])
+    for rep in range(3):
+        monkeypatch.delenv("LATTICE_NO_GRAPH", raising=False)
+        la.step(40)
+        torch.cuda.synchronize()
+        monkeypatch.setenv("LATTICE_NO_GRAPH", "1")
+        lb.step(40)
+        torch.cuda.synchronize()
+        for x, y in zip(pa + qa, pb + qb):
+            assert torch.equal(x, y), f"call {rep} differs"
+    monkeypatch.delenv("LATTICE_NO_GRAPH", raising=False)
+    assert la.stats()["launches"]["kick_drift"] == 30
+    la.close()
+    lb.close()
