@@ -368,8 +368,12 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
 // z chunk (in reverse when marching down), so its resident blocks cover a
 // compact region and the records of the planes z - 1, z, z + 1 that a site's
 // stencil reads stay in that XCD's L2 between their uses.
+// Two waves per SIMD in every mode: the kick-only and energy passes then
+// spill 24 and 28 bytes per lane to scratch instead of holding 256 VGPRs and
+// 6 AGPRs at one wave (energy pass 361 -> 298 us at 128^3, self-consistent
+// leapfrog step 1316 -> 1133 us); the record step pass fits in 240 VGPRs.
 template <int TX, int TY, int MODE, bool STREAM>
-__global__ void __launch_bounds__(TX *TY) su2_stage(const SU2Args g)
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) su2_stage(const SU2Args g)
 {
     constexpr int NT = TX * TY;
     constexpr int NQ = kSU2Sums + kSU2Maxes;
