@@ -1782,7 +1782,8 @@ lat_status lattice_energy_noalloc(const lat_params *p, const lat_fields *f, doub
     if (p->potential != LAT_PHI4 && p->potential != LAT_PHI4_CHI2)
         return fail(nullptr, LAT_EUNSUPPORTED, "lattice_energy_noalloc takes the real scalar models");
     if (!out || !aligned(out, 8)) return fail(nullptr, LAT_EINVAL, "null or misaligned output pointer");
-    // the launch geometry lattice_init would choose (a host record only)
+    // the stage passes' launch geometry lattice_init would choose (a host record
+    // only; lattice_energy at N = 256 runs its pass in a geometry of its own)
     lat_ctx g;
     g.N = p->N;
     g.f32 = p->precision == LAT_PREC_F32;
