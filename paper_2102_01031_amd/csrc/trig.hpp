@@ -3,12 +3,15 @@
 // few radians.
 //
 // Method: Cody-Waite reduction x = r + k pi/2 with pi/2 split into three
-// doubles (each product k * part formed inside a fused multiply-add), then the
-// Taylor series of sin and cos on |r| <= pi/4, summed to r^17 and r^16: the
-// first omitted terms, (pi/4)^19/19! and (pi/4)^18/18!, are below 1e-19 and
-// 2e-18, far under half an ulp.  Constants: pi/2 and 2/pi rounded to double,
-// the remainders pi/2 - hi and pi/2 - hi - mid rounded to double (from pi to
-// 100 digits), and the reciprocals of the factorials rounded to double.
+// doubles (each product k * part formed inside a fused multiply-add), then
+// polynomials on |r| <= pi/4 in u = r^2: sin r = r (1 + u P(u)) with P of
+// degree 5 and cos r = 1 + u Q(u) with Q of degree 6, which interpolate the
+// exact functions at the Chebyshev nodes of the interval (trig_coeffs.py
+// computes them in 60-digit arithmetic; relative error of the rounded
+// polynomials about 2e-17 and 6e-19, under a quarter ulp).  They replace the
+// Taylor series to r^17 and r^16 with two and one fused multiply-adds fewer.
+// Constants: pi/2 and 2/pi rounded to double, the remainders pi/2 - hi and
+// pi/2 - hi - mid rounded to double (from pi to 100 digits).
 // Arguments beyond 2^20 in magnitude (and NaN, inf) go to the library sincos,
 // whose reduction covers the whole range.  Measured against glibc over random
 // and special arguments: at most 1 ulp.
@@ -31,31 +34,28 @@ constexpr double kPio2Mid = 0x1.1a62633145c07p-54;
 constexpr double kPio2Lo = -0x1.f1976b7ed8fbcp-110;
 constexpr double kMaxReduced = 1048576.0;   // 2^20
 
-// r - r^3/3! + ... + r^17/17!, with z = r^2
+// sin r = r + r z P(z), z = r^2 (coefficients of P from trig_coeffs.py)
 LAT_HD inline double sin_poly(double r, double z)
 {
-    double p = 2.8114572543455206e-15;    // 1/17!
-    p = fma(p, z, -7.647163731819816e-13);  // -1/15!
-    p = fma(p, z, 1.6059043836821613e-10);  // 1/13!
-    p = fma(p, z, -2.505210838544172e-08);  // -1/11!
-    p = fma(p, z, 2.7557319223985893e-06);  // 1/9!
-    p = fma(p, z, -0.0001984126984126984);  // -1/7!
-    p = fma(p, z, 0.008333333333333333);    // 1/5!
-    p = fma(p, z, -0.16666666666666666);    // -1/3!
+    double p = 1.591810123027412e-10;
+    p = fma(p, z, -2.5051131455427946e-08);
+    p = fma(p, z, 2.755731610068303e-06);
+    p = fma(p, z, -0.0001984126983675497);
+    p = fma(p, z, 0.008333333333330946);
+    p = fma(p, z, -0.16666666666666666);
     return fma(r * z, p, r);
 }
 
-// 1 - z/2! + ... + z^8/16!
+// cos r = 1 + z Q(z), z = r^2 (coefficients of Q from trig_coeffs.py)
 LAT_HD inline double cos_poly(double z)
 {
-    double p = 4.779477332387385e-14;     // 1/16!
-    p = fma(p, z, -1.1470745597729725e-11);  // -1/14!
-    p = fma(p, z, 2.08767569878681e-09);     // 1/12!
-    p = fma(p, z, -2.755731922398589e-07);   // -1/10!
-    p = fma(p, z, 2.48015873015873e-05);     // 1/8!
-    p = fma(p, z, -0.001388888888888889);    // -1/6!
-    p = fma(p, z, 0.041666666666666664);     // 1/4!
-    p = fma(p, z, -0.5);                     // -1/2!
+    double p = -1.1367978191553177e-11;
+    p = fma(p, z, 2.0875886390883725e-09);
+    p = fma(p, z, -2.755731556415141e-07);
+    p = fma(p, z, 2.480158729368715e-05);
+    p = fma(p, z, -0.0013888888888880767);
+    p = fma(p, z, 0.04166666666666664);
+    p = fma(p, z, -0.5);
     return fma(z, p, 1.0);
 }
 
