@@ -147,7 +147,7 @@ struct lat_ctx {
     bool rows = false;   // whole-row kernel (N = 64 * XS)
     int rows_ty = 8;
     int rows_pf = 1;     // whole-row kernel prefetch depth (planes)
-    int en_pf = 0, en_zc = 0, en_nblocks = 0;   // energy pass geometry (en_nblocks 0: that of the stage passes)
+    int en_pf = 0, en_zc = 0, en_ty = 0, en_nblocks = 0;   // energy pass geometry (en_nblocks 0: the stage passes')
     int rows_vw = 1;     // whole-row kernel sites per lane and access (1, or 16-byte vectors)
     int rows_y_fastest = 0;   // whole-row kernel block order (see stage_rows.hpp)
     int rows_alternate = 0;   // whole-row kernel: alternate the z march direction pass by pass
@@ -316,26 +316,29 @@ void set_rows_geometry(lat_ctx *c, int ty, int zc)
 
 // Energy pass geometry of the whole-row kernel.  Read-only, the pass needs
 // more bytes in flight than the stage passes' one wave per SIMD give: at
-// N = 256 it runs one plane ahead in float64 (246 VGPRs, two waves per SIMD)
-// and two in float32, with 32-plane z chunks (two blocks per CU); 134-144
-// against 125-130 us in float64, 74-75 against 56-58 us in float32 (twice,
-// one GPU).  LATTICE_ENERGY_GEOM="pf,zc" overrides (same rows per block),
-// "0": the stage passes' geometry.
+// N = 256 it runs 32-plane z chunks with two waves per SIMD, in float64 one
+// plane ahead in 8-row blocks (235 VGPRs; 108-113 against 124-130 us with
+// 4-row blocks and 134-144 us in the stage geometry), in float32 two planes
+// ahead in 4-row blocks (56-58 against 74-75 us).  LATTICE_ENERGY_GEOM=
+// "pf,zc[,ty]" overrides (ty = 4 or 8 rows per block), "0": the stage
+// passes' geometry.
 void energy_geometry(lat_ctx *c)
 {
-    c->en_pf = c->en_zc = c->en_nblocks = 0;
+    c->en_pf = c->en_zc = c->en_ty = c->en_nblocks = 0;
     if (!c->rows || c->batch) return;
-    int pf = 0, zc = 0;
+    int pf = 0, zc = 0, ty = c->rows_ty;
     if (c->N == 256 && c->rows_ty == 4) {
         pf = c->f32 ? 2 : 1;
         zc = 32;
+        ty = c->f32 ? 4 : 8;
     }
     if (const char *e = std::getenv("LATTICE_ENERGY_GEOM"))
-        if (std::sscanf(e, "%d,%d", &pf, &zc) != 2) pf = zc = 0;
-    if (pf < 1 || pf > 3 || zc < 1 || zc > c->N) return;
+        if (std::sscanf(e, "%d,%d,%d", &pf, &zc, &ty) < 2) pf = zc = 0;
+    if (pf < 1 || pf > 3 || zc < 1 || zc > c->N || (ty != 4 && ty != 8)) return;
     c->en_pf = pf;
     c->en_zc = zc;
-    c->en_nblocks = c->tiles_y * ((c->N + zc - 1) / zc);
+    c->en_ty = ty;
+    c->en_nblocks = ((c->N + ty - 1) / ty) * ((c->N + zc - 1) / zc);
 }
 
 void geometry_from_env(lat_ctx *c)
@@ -665,16 +668,18 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
         if (st != LAT_OK) return st;
     }
     hipError_t e;
-    int nb = c->nblocks, pf = c->rows_pf, lp = c->rows_lp;
+    int nb = c->nblocks, pf = c->rows_pf, lp = c->rows_lp, ty = c->rows_ty;
     if (variant == kEnergy && c->rows && c->en_nblocks > 0) {
         a.zc = c->en_zc;
+        ty = c->en_ty;
+        a.tiles_y = (c->N + ty - 1) / ty;
         nb = c->en_nblocks;
         pf = c->en_pf;
         lp = 0;
     }
     if (c->rows)
-        e = c->nf == 1 ? launch_rows<T, 1>(c->N, c->rows_ty, pf, c->rows_vw, variant, a, nb, stream, lp)
-                       : launch_rows<T, 2>(c->N, c->rows_ty, pf, c->rows_vw, variant, a, nb, stream, lp);
+        e = c->nf == 1 ? launch_rows<T, 1>(c->N, ty, pf, c->rows_vw, variant, a, nb, stream, lp)
+                       : launch_rows<T, 2>(c->N, ty, pf, c->rows_vw, variant, a, nb, stream, lp);
     else
         e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
                        : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);
