@@ -101,10 +101,10 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
         const double tyz_ym = edx * ((Az[n] - Az[nym]) - Ay[u1_at(N, x, ym, zp)] + Ay[nym]);
         const double txz_zm = edx * ((Az[u1_at(N, xp, y, zm)] - Az[nzm]) - Ax[n] + Ax[nzm]);
         const double tyz_zm = edx * ((Az[u1_at(N, x, yp, zm)] - Az[nzm]) - Ay[n] + Ay[nzm]);
-        const double sxy = sin(txy), sxz = sin(txz), syz = sin(tyz);
-        const double mag[3] = {(sxy - sin(txy_ym)) + (sxz - sin(txz_zm)),
-                               (-sxy + sin(txy_xm)) + (syz - sin(tyz_zm)),
-                               (-sxz + sin(txz_xm)) + (-syz + sin(tyz_ym))};
+        const double sxy = lat_sin(txy), sxz = lat_sin(txz), syz = lat_sin(tyz);
+        const double mag[3] = {(sxy - lat_sin(txy_ym)) + (sxz - lat_sin(txz_zm)),
+                               (-sxy + lat_sin(txy_xm)) + (syz - lat_sin(tyz_zm)),
+                               (-sxz + lat_sin(txz_xm)) + (-syz + lat_sin(tyz_ym))};
 
         // covariant Laplacian and current
         const double pr = g.phi_in[0][n], pim = g.phi_in[1][n];
@@ -113,8 +113,8 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             double s, c, sm, cm;
-            sincos(edx * g.A_in[i][n], &s, &c);
-            sincos(edx * g.A_in[i][nm_[i]], &sm, &cm);
+            lat_sincos(edx * g.A_in[i][n], &s, &c);
+            lat_sincos(edx * g.A_in[i][nm_[i]], &sm, &cm);
             s = -s;   // V_i(n) = c + i s ; conj(V_i(n-i)) = cm + i sm
             const double qr = g.phi_in[0][np_[i]], qi = g.phi_in[1][np_[i]];
             const double rr = g.phi_in[0][nm_[i]], ri = g.phi_in[1][nm_[i]];
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
                 ka += sa * sa;
             }
             acc[3] = ka / (2.0 * g.kappa_g);
-            const double hxy = sin(0.5 * txy), hxz = sin(0.5 * txz), hyz = sin(0.5 * tyz);
+            const double hxy = lat_sin(0.5 * txy), hxz = lat_sin(0.5 * txz), hyz = lat_sin(0.5 * tyz);
             const double mg = 2.0 * hxy * hxy + 2.0 * hxz * hxz + 2.0 * hyz * hyz;
             acc[4] = mg / (g.kappa_g * g.e * g.e * g.dx * g.dx * g.dx * g.dx);
             // Gauss residual of the stored pairing
