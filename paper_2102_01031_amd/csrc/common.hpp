@@ -66,6 +66,21 @@ __device__ inline double load_agent(const double *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A block's arrival at a last-block reduction, called by the thread that stored
+// the block's partials: the ticket increment releases them at agent scope, and
+// only the block that takes the last ticket then acquires.  An agent-scope
+// acquire invalidates the XCD's L2, so taking it in every block would throw out
+// the neighbour planes that the other blocks on that XCD still read.  The
+// acquire fence after the increment that read the final count synchronises with
+// every block's release (the increments form one release sequence).
+__device__ inline bool ticket_arrive(unsigned *ticket, unsigned nblocks)
+{
+    const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev != nblocks - 1) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
 // Logical block id from the hardware block id: consecutive hardware blocks are
 // dealt round-robin to the 8 XCDs, so give each XCD a contiguous range of
 // logical tiles (neighbouring tiles then share that XCD's L2).

@@ -121,6 +121,7 @@ struct lat_ctx {
     int su2_aos_on = 0;
     bool u1_rows = false;   // whole-row U(1) leapfrog kernel
     int u1_ty = 4, u1_zc = 8;
+    int u1_ezc = 1;         // z planes per block of the U(1) energy pass
     // scratch
     double *partials = nullptr;
     size_t partial_cap = 0;
@@ -2231,14 +2232,15 @@ bool u1_rows_shape_ok(int N, int ty)
     return (N == 64 && (ty == 4 || ty == 8)) || (N == 128 && (ty == 2 || ty == 4));
 }
 
+template <int MODE>
 hipError_t launch_u1_rows(const lat_ctx *c, const U1Args &a)
 {
     const int nb = (c->N / c->u1_ty) * ((c->N + c->u1_zc - 1) / c->u1_zc);
     const dim3 nt(c->N * c->u1_ty);
-    if (c->N == 64 && c->u1_ty == 4) hipLaunchKernelGGL((u1_rows<1, 4>), dim3(nb), nt, 0, c->stream, a);
-    else if (c->N == 64) hipLaunchKernelGGL((u1_rows<1, 8>), dim3(nb), nt, 0, c->stream, a);
-    else if (c->u1_ty == 2) hipLaunchKernelGGL((u1_rows<2, 2>), dim3(nb), nt, 0, c->stream, a);
-    else hipLaunchKernelGGL((u1_rows<2, 4>), dim3(nb), nt, 0, c->stream, a);
+    if (c->N == 64 && c->u1_ty == 4) hipLaunchKernelGGL((u1_rows<1, 4, MODE>), dim3(nb), nt, 0, c->stream, a);
+    else if (c->N == 64) hipLaunchKernelGGL((u1_rows<1, 8, MODE>), dim3(nb), nt, 0, c->stream, a);
+    else if (c->u1_ty == 2) hipLaunchKernelGGL((u1_rows<2, 2, MODE>), dim3(nb), nt, 0, c->stream, a);
+    else hipLaunchKernelGGL((u1_rows<2, 4, MODE>), dim3(nb), nt, 0, c->stream, a);
     return hipGetLastError();
 }
 
@@ -2249,6 +2251,17 @@ void u1_geometry(lat_ctx *c)
     c->u1_rows = c->N == 64 || c->N == 128;
     c->u1_ty = 4;
     c->u1_zc = c->N == 128 ? 16 : 4;
+    // the energy pass gives each block a column of z planes, about 256 blocks in
+    // all: every block's ticket release writes back its XCD's L2, and these
+    // releases queue per XCD (at 128^3: 337 us per pass in 8192 one-plane
+    // blocks, 140 us at 8 planes, 114 us at 32 planes, 256 blocks).
+    // LATTICE_U1_ENERGY_ZC overrides the planes per block.
+    const long tpp = (long)((c->N + kU1TX - 1) / kU1TX) * ((c->N + kU1TY - 1) / kU1TY);
+    c->u1_ezc = (int)std::min<long>(c->N, std::max<long>(1, ((long)c->N * tpp + 255) / 256));
+    if (const char *ez = std::getenv("LATTICE_U1_ENERGY_ZC")) {
+        const int v = std::atoi(ez);
+        if (v >= 1 && v <= c->N) c->u1_ezc = v;
+    }
     const char *env = std::getenv("LATTICE_U1_TILE");
     if (!env) return;
     if (std::strcmp(env, "tile") == 0) {
@@ -2275,17 +2288,29 @@ lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
     switch (mode) {
     case kU1Step:
         if (c->u1_rows) {
-            HIPCHK(c, launch_u1_rows(c, a));
+            HIPCHK(c, launch_u1_rows<kU1Step>(c, a));
             break;
         }
         hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Step>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
         break;
     case kU1Kick:
+        if (c->u1_rows) {
+            HIPCHK(c, launch_u1_rows<kU1Kick>(c, a));
+            break;
+        }
         hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Kick>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
         break;
-    default:
-        hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Energy>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
+    default: {
+        if (c->u1_rows) {
+            HIPCHK(c, launch_u1_rows<kU1Energy>(c, a));
+            break;
+        }
+        U1Args e = a;
+        e.zc = c->u1_ezc;
+        const int nbe = a.tiles_x * a.tiles_y * ((c->N + e.zc - 1) / e.zc);
+        hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Energy>), dim3(nbe), dim3(kU1TX * kU1TY), 0, c->stream, e);
         break;
+    }
     }
     HIPCHK(c, hipGetLastError());
     if (c->profiling) {
@@ -2309,6 +2334,16 @@ lat_status u1_flip(lat_ctx *c)
         HIPCHK(c, hipGetLastError());                                               \
     } while (0)
 
+// Leapfrog steps of the self-consistent gauge models after a call's first take
+// the sums before the kick from the neighbouring passes (u1_self_drift_w) in
+// place of an energy pass of their own; LATTICE_SELF_CARRY=0 measures them on
+// every step (the same values).
+static bool self_carry()
+{
+    const char *e = std::getenv("LATTICE_SELF_CARRY");
+    return e ? std::atoi(e) != 0 : true;
+}
+
 // Self-consistent expansion (readings A3 and R1 for the U(1) model): the kicks,
 // energy sums and drifts as separate passes, the scale factor, b and the pass
 // weights updated on the device between them (stage_u1.hpp, U1SelfConst).
@@ -2318,16 +2353,20 @@ lat_status u1_step_self_lf(lat_ctx *c, int64_t ns, int dir)
     const U1SelfConst kc = u1_self_const(c);
     int stag = c->lf_stag;
     lat_status s;
+    const bool carry_on = self_carry();
     for (int64_t k = 0; k < ns; ++k) {
         const double w = stag == 0 ? 0.5 * h : h;
-        if (stag != 0) {   // sums of the momenta before the kick
+        // sums of the state before the kick: measured on a call's first step,
+        // carried from the passes around it on the later ones
+        const int carry = stag != 0 && k > 0 && carry_on;
+        if (stag != 0 && !carry) {
             if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
             U1K(u1_self_stash, c->sc);
         }
         U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
         if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
         if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
-        U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc);
+        U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc, carry);
         if ((s = u1_launch(c, kU1Step, u1_args_dev(c, true))) != LAT_OK) return s;
         u1_flip(c);
         stag = dir;
@@ -2652,16 +2691,18 @@ lat_status su2_step_self_lf(lat_ctx *c, int64_t ns, int dir)
     const U1SelfConst kc = u1_self_const(c);
     int stag = c->lf_stag;
     lat_status s;
+    const bool carry_on = self_carry();
     for (int64_t k = 0; k < ns; ++k) {
         const double w = stag == 0 ? 0.5 * h : h;
-        if (stag != 0) {   // sums of the momenta before the kick
+        const int carry = stag != 0 && k > 0 && carry_on;   // as in u1_step_self_lf
+        if (stag != 0 && !carry) {
             if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
             U1K(u1_self_stash, c->sc);
         }
         U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
         if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
         if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
-        U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc);
+        U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc, carry);
         if ((s = su2_launch(c, kSU2Step, su2_args_dev(c, true))) != LAT_OK) return s;
         c->cur_su2 ^= 1;
         stag = dir;
@@ -2805,7 +2846,7 @@ lat_status u1_step_self_vv(lat_ctx *c, int64_t ns, int dir)
             const double hs = wp * h;
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
             if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
-            U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc);
+            U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc, 0);
             if ((s = u1_launch(c, kU1Step, u1_args_dev(c, true))) != LAT_OK) return s;
             u1_flip(c);
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
@@ -2830,7 +2871,7 @@ lat_status su2_step_self_vv(lat_ctx *c, int64_t ns, int dir)
             const double hs = wp * h;
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
             if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
-            U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc);
+            U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc, 0);
             if ((s = su2_launch(c, kSU2Step, su2_args_dev(c, true))) != LAT_OK) return s;
             c->cur_su2 ^= 1;
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);

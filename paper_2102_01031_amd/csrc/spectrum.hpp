@@ -108,8 +108,7 @@ __global__ void __launch_bounds__(kSpecThreads) spectrum_shell_seed(double2 *__r
         double sb = 0.0;
         for (int k = 0; k < kSpecThreads / 64; ++k) sb += lds_red[k];
         store_agent(&partials[blockIdx.x], sb);
-        const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+        last_flag = ticket_arrive(ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (last_flag) {

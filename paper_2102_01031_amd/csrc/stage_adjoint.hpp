@@ -217,8 +217,7 @@ __global__ void __launch_bounds__(TX *TY) adjoint_stage(const AdjArgs g)
         double s = 0.0;
         for (int i = 0; i < NT / 64; ++i) s += lds_red[i];
         store_agent(&g.partials[lid], s);
-        const unsigned prev = __hip_atomic_fetch_add(g.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+        last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (last_flag) {
@@ -287,8 +286,7 @@ __global__ void __launch_bounds__(256) adjoint_seed(const SeedArgs g)
     __syncthreads();
     if (tid == 0) {
         store_agent(&g.partials[blockIdx.x], lds_red[0] + lds_red[1] + lds_red[2] + lds_red[3]);
-        const unsigned prev = __hip_atomic_fetch_add(g.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+        last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (last_flag) {

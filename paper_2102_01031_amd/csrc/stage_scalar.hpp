@@ -513,9 +513,7 @@ __global__ void __launch_bounds__(TX *TY) scalar_stage(const ScalarArgs<T> g)
         if (tid == 0) {
 #pragma unroll
             for (int k = 0; k < NQ; ++k) store_agent(&g.partials[(size_t)lid * NQ + k], tot[k]);
-            const unsigned prev =
-                __hip_atomic_fetch_add(g.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
         }
         __syncthreads();
         if (last_flag) {

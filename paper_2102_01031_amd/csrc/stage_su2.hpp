@@ -439,8 +439,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))
                     r = k < kSU2Sums ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
                 store_agent(&g.partials[(size_t)lid * NQ + k], r);
             }
-            const unsigned prev = __hip_atomic_fetch_add(g.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
         }
         __syncthreads();
         if (last_flag) {

@@ -71,15 +71,20 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
     const int bx = lid % g.tiles_x;
     const int rest = lid / g.tiles_x;
     const int by = rest % g.tiles_y;
-    const int z = rest / g.tiles_y;
     const int N = g.N;
     const int x = bx * TX + tx, y = by * TY + ty;
     const bool valid = x < N && y < N;
+    // the energy pass takes a column of zc planes per block (fewer blocks, so
+    // fewer ticket releases); the other passes one plane
+    const int zb = MODE == kU1Energy ? (rest / g.tiles_y) * g.zc : rest / g.tiles_y;
+    const int ze = MODE == kU1Energy ? min(zb + g.zc, N) : zb + 1;
 
     double acc[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
 
+#pragma unroll 1
+    for (int z = zb; z < ze; ++z) {
     if (valid) {
         const int xm = x == 0 ? N - 1 : x - 1, xp = x + 1 == N ? 0 : x + 1;
         const int ym = y == 0 ? N - 1 : y - 1, yp = y + 1 == N ? 0 : y + 1;
@@ -153,31 +158,34 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
         for (int i = 0; i < 3; ++i) pa[i] = g.piA[i][n];
 
         if (MODE == kU1Energy) {
+            double t[NQ];
             const double s0 = p0 + ck * F0, s1 = p1 + ck * F1;
-            acc[0] = 0.5 * (s0 * s0 + s1 * s1);
-            acc[1] = grad2 * inv_dx2 * 0.5;
+            t[0] = 0.5 * (s0 * s0 + s1 * s1);
+            t[1] = grad2 * inv_dx2 * 0.5;
             const double u = m2 - g.v * g.v;
-            acc[2] = 0.25 * g.lam * u * u;
+            t[2] = 0.25 * g.lam * u * u;
             double ka = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const double sa = pa[i] + ck * FA[i];
                 ka += sa * sa;
             }
-            acc[3] = ka / (2.0 * g.kappa_g);
+            t[3] = ka / (2.0 * g.kappa_g);
             const double hxy = lat_sin(0.5 * txy), hxz = lat_sin(0.5 * txz), hyz = lat_sin(0.5 * tyz);
             const double mg = 2.0 * hxy * hxy + 2.0 * hxz * hxz + 2.0 * hyz * hyz;
-            acc[4] = mg / (g.kappa_g * g.e * g.e * g.dx * g.dx * g.dx * g.dx);
+            t[4] = mg / (g.kappa_g * g.e * g.e * g.dx * g.dx * g.dx * g.dx);
             // Gauss residual of the stored pairing
             const double div = ((pa[0] - g.piA[0][nxm]) + (pa[1] - g.piA[1][nym]) + (pa[2] - g.piA[2][nzm])) / g.dx;
             const double charge = g.e * g.kappa_g * (pr * p1 - pim * p0);
             const double G = div - charge;
-            acc[5] = fabs(G);
-            acc[6] = fabs(div + charge);
-            acc[7] = fabs(div) + fabs(charge);
-            acc[8] = fabs(G);
-            acc[9] = fabs(div);
-            acc[10] = fabs(charge);
+            t[5] = fabs(G);
+            t[6] = fabs(div + charge);
+            t[7] = fabs(div) + fabs(charge);
+            t[8] = fabs(G);
+            t[9] = fabs(div);
+            t[10] = fabs(charge);
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) acc[k] = k < kU1Sums ? acc[k] + t[k] : fmax(acc[k], t[k]);
         } else {
             const double q0 = p0 + ck * F0, q1 = p1 + ck * F1;
             g.pi[0][n] = q0;
@@ -196,6 +204,7 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
             }
         }
     }
+    }
 
     if constexpr (MODE == kU1Energy) {
         // block reduction: sums for [0, kU1Sums), maxes for the rest
@@ -213,9 +222,7 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
                     r = k < kU1Sums ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
                 store_agent(&g.partials[(size_t)lid * NQ + k], r);
             }
-            const unsigned prev =
-                __hip_atomic_fetch_add(g.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            last_flag = (prev == gridDim.x - 1) ? 1 : 0;
+            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
         }
         __syncthreads();
         if (last_flag) {
@@ -305,9 +312,22 @@ __global__ void u1_self_b_kick(ScaleRecord *S, double w, U1SelfConst k)
 // Leapfrog (reading A3): b += cL K_a(before, sums[8..12]) + cR K_a(after, sums[0..4]);
 // velocity-Verlet (reading R1, cL = 0): b += cR K_a(sums[0..4]).  Then a' = a + h b and
 // the drift weights {0, 1, 1, 1, h abar^{alpha-3}, h abar^{alpha-1}}, abar = (a + a')/2.
-__global__ void u1_self_drift_w(ScaleRecord *S, double h, double cL, double cR, U1SelfConst k)
+// Every call leaves the momentum sums of the kicked state (sums[0], sums[3]) in
+// sums[8] and sums[11]: the drift that follows moves only the positions, so they
+// are the next step's momentum sums before its kick.  With carry != 0 the sums
+// before this step's kick were not measured: their momentum parts are those the
+// previous call left, and their position parts (sums[1], [2], [4]) are the
+// after-kick ones, the kick having moved only the momenta.  An energy pass with
+// zero kick weight sums p + 0 F = p, so the carried sums equal measured ones bit
+// for bit.
+__global__ void u1_self_drift_w(ScaleRecord *S, double h, double cL, double cR, U1SelfConst k, int carry)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (carry) {
+            S->sums[9] = S->sums[1];
+            S->sums[10] = S->sums[2];
+            S->sums[12] = S->sums[4];
+        }
         const double a = S->a;
         double b = S->b;
         if (cL != 0.0) b += cL * u1_kernel_b(a, S->sums + 8, k);
@@ -322,6 +342,8 @@ __global__ void u1_self_drift_w(ScaleRecord *S, double h, double cL, double cR, 
         S->w[5] = h * pow(am, k.alpha - 1.0);
         S->a = a1;
         S->b = b;
+        S->sums[8] = S->sums[0];
+        S->sums[11] = S->sums[3];
     }
 }
 
@@ -335,7 +357,7 @@ __global__ void u1_self_drift_w(ScaleRecord *S, double h, double cL, double cR, 
 // the row y0 - 1 below the block is evaluated by the block's threads, one
 // operation each.  Every angle is formed by the same expression, in the same
 // order, as in u1_stage: the same arithmetic without the repeated sines.
-template <int XS, int TY>
+template <int XS, int TY, int MODE>
 __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
 {
     constexpr int NT = 64 * XS * TY;
@@ -356,6 +378,10 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
     __shared__ double s_sxz[TY * NX];                             // own rows (index row - 1)
     __shared__ double s_cx[TY * NX], s_sx[TY * NX];               // phase of A_x, own rows
     __shared__ double s_cz[TY * NX], s_sz[TY * NX];               // phase of A_z, own rows
+    constexpr bool EN = MODE == kU1Energy;
+    constexpr int NQ = kU1Sums + kU1Maxes;
+    __shared__ double lds_red[EN ? (NT / 64) * NQ : 1];
+    __shared__ int last_flag;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -408,6 +434,9 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
     double a0[3], a1[3];          // A at z, z + 1
     double czm, szm, sxzm, syzm;  // link phase of A_z and sines theta_xz, theta_yz at n - z
     double hp0[HPT], hp1[HPT], hax[HPT], hay[HPT], haz[HPT], hayn[HPT];
+    double acc[NQ];   // energy mode: the site terms of u1_stage, summed over the column
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
 
     // ---- prologue: window, A, halo rows of plane z0, carried values of plane z0 - 1
     {
@@ -508,10 +537,14 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
 
         // (B) own plaquette sines and link phases into LDS; then the halo
         // row's, one operation per thread
+        double th[3];   // own plaquette angles (the energy mode's magnetic term)
         {
             const double txy = edx * ((s_ay[b][r * NX + xp] - a0[1]) - s_ax[b][(r + 1) * NX + x] + a0[0]);
             const double txz = edx * ((s_az[b][r * NX + xp] - a0[2]) - a1[0] + a0[0]);
             const double tyz = edx * ((s_az[b][(r + 1) * NX + x] - a0[2]) - a1[1] + a0[1]);
+            th[0] = txy;
+            th[1] = txz;
+            th[2] = tyz;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double t = j == 0 ? txy : (j == 1 ? txz : tyz);
@@ -563,7 +596,7 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                                    (-sxy + s_sxy[r * NX + xm]) + (syz - syzm),
                                    (-sxz + s_sxz[(r - 1) * NX + xm]) + (-syz + s_syz[ro - NX])};
             const double pr = w0[0], pim = w0[1];
-            double d2r = 0.0, d2i = 0.0, J[3];
+            double d2r = 0.0, d2i = 0.0, J[3], grad2 = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 double qr, qi, rr, ri, sm, cm;
@@ -589,22 +622,64 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                 d2r += ar - 2.0 * pr + br;
                 d2i += ai - 2.0 * pim + bi;
                 J[i] = g.e / g.dx * (pr * ai - pim * ar);
+                if constexpr (EN) {
+                    const double dr = ar - pr, di = ai - pim;
+                    grad2 += dr * dr + di * di;
+                }
             }
             const double m2 = 0.5 * (pr * pr + pim * pim);
             const double vp = 0.5 * g.lam * (m2 - g.v * g.v);
             const double F0 = la1 * (d2r * inv_dx2) - la3 * (vp * pr);
             const double F1 = la1 * (d2i * inv_dx2) - la3 * (vp * pim);
             const double q0 = pq[0] + ck * F0, q1 = pq[1] + ck * F1;
-            st32(g.pi[0], o, q0);
-            st32(g.pi[1], o, q1);
-            st32(g.phi_out[0], o, pr + hd * q0);
-            st32(g.phi_out[1], o, pim + hd * q1);
+            if constexpr (EN) {
+                // the energies and Gauss terms of u1_stage's energy mode
+                double t[NQ];
+                t[0] = 0.5 * (q0 * q0 + q1 * q1);
+                t[1] = grad2 * inv_dx2 * 0.5;
+                const double u = m2 - g.v * g.v;
+                t[2] = 0.25 * g.lam * u * u;
+                double ka = 0.0;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double FA = la1 * (g.kappa_g * J[i]) - lm1 * (mag[i] * inv_edx3);
-                const double qa = pa[i] + ck * FA;
-                st32(g.piA[i], o, qa);
-                st32(g.A_out[i], o, a0[i] + hdA * qa);
+                for (int i = 0; i < 3; ++i) {
+                    const double FA = la1 * (g.kappa_g * J[i]) - lm1 * (mag[i] * inv_edx3);
+                    const double sa = pa[i] + ck * FA;
+                    ka += sa * sa;
+                }
+                t[3] = ka / (2.0 * g.kappa_g);
+                const double hxy = lat_sin(0.5 * th[0]), hxz = lat_sin(0.5 * th[1]), hyz = lat_sin(0.5 * th[2]);
+                const double mg = 2.0 * hxy * hxy + 2.0 * hxz * hxz + 2.0 * hyz * hyz;
+                t[4] = mg / (g.kappa_g * g.e * g.e * g.dx * g.dx * g.dx * g.dx);
+                const int yy = y0 + r - 1;
+                const unsigned oxm = oz + (unsigned)(yy * N + xm);
+                const unsigned oym = oz + (unsigned)((yy == 0 ? N - 1 : yy - 1) * N + x);
+                const unsigned ozm = (unsigned)(z == 0 ? N - 1 : z - 1) * NN + so;
+                const double div = ((pa[0] - ld32(g.piA[0], oxm)) + (pa[1] - ld32(g.piA[1], oym)) +
+                                    (pa[2] - ld32(g.piA[2], ozm))) / g.dx;
+                const double charge = g.e * g.kappa_g * (pr * pq[1] - pim * pq[0]);
+                const double G = div - charge;
+                t[5] = fabs(G);
+                t[6] = fabs(div + charge);
+                t[7] = fabs(div) + fabs(charge);
+                t[8] = fabs(G);
+                t[9] = fabs(div);
+                t[10] = fabs(charge);
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) acc[k] = k < kU1Sums ? acc[k] + t[k] : fmax(acc[k], t[k]);
+            } else {
+                st32(g.pi[0], o, q0);
+                st32(g.pi[1], o, q1);
+                if constexpr (MODE == kU1Step) {
+                    st32(g.phi_out[0], o, pr + hd * q0);
+                    st32(g.phi_out[1], o, pim + hd * q1);
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double FA = la1 * (g.kappa_g * J[i]) - lm1 * (mag[i] * inv_edx3);
+                    const double qa = pa[i] + ck * FA;
+                    st32(g.piA[i], o, qa);
+                    if constexpr (MODE == kU1Step) st32(g.A_out[i], o, a0[i] + hdA * qa);
+                }
             }
             czm = s_cz[wo];
             szm = s_sz[wo];
@@ -623,6 +698,55 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
         for (int i = 0; i < 3; ++i) {
             a0[i] = a1[i];
             a1[i] = na[i];
+        }
+    }
+
+    if constexpr (EN) {
+        // the block tree and last-block reduction of u1_stage's energy mode
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const double rv = k < kU1Sums ? wave_sum(acc[k]) : wave_max(acc[k]);
+            if (lane == 0) lds_red[w * NQ + k] = rv;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int k = 0; k < NQ; ++k) {
+                double rv = 0.0;
+                for (int i = 0; i < NT / 64; ++i)
+                    rv = k < kU1Sums ? rv + lds_red[i * NQ + k] : fmax(rv, lds_red[i * NQ + k]);
+                store_agent(&g.partials[(size_t)lid * NQ + k], rv);
+            }
+            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
+        }
+        __syncthreads();
+        if (last_flag) {
+            const int nb = gridDim.x;
+            double part[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) part[k] = 0.0;
+            for (int i = tid; i < nb; i += NT) {
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    const double v = load_agent(&g.partials[(size_t)i * NQ + k]);
+                    part[k] = k < kU1Sums ? part[k] + v : fmax(part[k], v);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const double rv = k < kU1Sums ? wave_sum(part[k]) : wave_max(part[k]);
+                if (lane == 0) lds_red[w * NQ + k] = rv;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int k = 0; k < NQ; ++k) {
+                    double rv = 0.0;
+                    for (int i = 0; i < NT / 64; ++i)
+                        rv = k < kU1Sums ? rv + lds_red[i * NQ + k] : fmax(rv, lds_red[i * NQ + k]);
+                    if (k < kU1Sums) g.sc->sums[k] = rv;
+                    else g.sc->maxes[k - kU1Sums] = rv;
+                }
+                __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }

@@ -118,3 +118,34 @@ def test_su2_expanding_reversal_and_gauss(integ, expansion):
         for g, o in zip(gl, ol):
             assert np.max(np.abs(g.cpu().numpy() - np.asarray(o).reshape(-1))) <= 1e-11
     lat.close()
+
+
+@pytest.mark.parametrize("N", [13, 64])
+def test_su2_self_carry_bitwise(N):
+    """Self-consistent leapfrog steps after a call's first take the sums before
+    the kick from the passes around them: fields, a and b equal, bit for bit,
+    those of a run that measures them in an energy pass on every step
+    (LATTICE_SELF_CARRY=0)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, "lf", "self", 0.5)
+    fields = inputs.random_su2_state(N, 41)
+    runs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_SELF_CARRY"):
+            say(f"[su2-carry] N={N} LATTICE_SELF_CARRY={spec}")
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(doublet=t[0], pi_doublet=t[1], U=t[2], E=t[3], **kw)
+            lat.step(1)
+            lat.step(5)
+            lat.sync()
+            lat.step(-3)
+            e = lat.energy()
+            torch.cuda.synchronize()
+            runs.append(([g.cpu().numpy() for grp in t for g in grp], e["a"], e["b"]))
+            lat.close()
+    (f1, a1, b1), (f0, a0, b0) = runs
+    assert a1 == a0 and b1 == b0, (a1, a0, b1, b0)
+    for g1, g0 in zip(f1, f0):
+        assert np.array_equal(g1, g0)

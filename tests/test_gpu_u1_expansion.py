@@ -129,3 +129,58 @@ def test_u1_expanding_reversal_and_gauss(integ, expansion):
     for g, o in zip(phi + pi + A + piA, fields[0] + fields[1] + fields[2] + fields[3]):
         assert np.max(np.abs(g.cpu().numpy() - o.reshape(-1))) <= 1e-11
     lat.close()
+
+
+@pytest.mark.parametrize("N", [13, 64])
+def test_u1_self_carry_bitwise(N):
+    """Self-consistent leapfrog steps after a call's first take the sums before
+    the kick from the passes around them: fields, a and b equal, bit for bit,
+    those of a run that measures them in an energy pass on every step
+    (LATTICE_SELF_CARRY=0)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, "lf", "self", 0.5)
+    fields = fields_of(N)
+    runs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_SELF_CARRY"):
+            say(f"[u1-carry] N={N} LATTICE_SELF_CARRY={spec}")
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(t[0], t[1], A=t[2], piA=t[3], **kw)
+            lat.step(1)
+            lat.step(6)
+            lat.sync()
+            lat.step(-3)
+            e = lat.energy()
+            torch.cuda.synchronize()
+            runs.append(([g.cpu().numpy() for grp in t for g in grp], e["a"], e["b"]))
+            lat.close()
+    (f1, a1, b1), (f0, a0, b0) = runs
+    assert a1 == a0 and b1 == b0, (a1, a0, b1, b0)
+    for g1, g0 in zip(f1, f0):
+        assert np.array_equal(g1, g0)
+
+
+@pytest.mark.parametrize("N,spec", [(13, "5"), (64, None), (64, "64")])
+def test_u1_energy_columns(N, spec):
+    """The energy pass in columns of z planes per block (the default, about 256
+    blocks; or LATTICE_U1_ENERGY_ZC, with a ragged last column at N = 13)
+    against one plane per block: the same site terms summed in another order."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, "lf", "none", 1.0)
+    fields = fields_of(N)
+    es = []
+    for s in (spec, "1"):
+        with tile_env(s, "LATTICE_U1_ENERGY_ZC"):
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(t[0], t[1], A=t[2], piA=t[3], **kw)
+            lat.step(2)
+            es.append(lat.energy())
+            lat.close()
+    for k in ("rho", "EK_A", "EG_A"):
+        assert abs(es[0][k] - es[1][k]) <= 1e-13 * abs(es[1][k]), (k, es[0][k], es[1][k])
+    for k in ("gauss_max", "gauss_div_max", "gauss_charge_max"):
+        assert es[0][k] == es[1][k], k
