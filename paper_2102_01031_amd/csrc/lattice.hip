@@ -2300,6 +2300,13 @@ lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
         }
         hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Kick>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
         break;
+    case kU1KickSums:
+        HIPCHK(c, launch_u1_rows<kU1KickSums>(c, a));
+        break;
+    case kU1Drift:
+        hipLaunchKernelGGL(u1_drift, dim3((unsigned)((c->vol + 255) / 256)), dim3(256), 0, c->stream, a,
+                           (unsigned)c->vol);
+        break;
     default: {
         if (c->u1_rows) {
             HIPCHK(c, launch_u1_rows<kU1Energy>(c, a));
@@ -2334,6 +2341,34 @@ lat_status u1_flip(lat_ctx *c)
         HIPCHK(c, hipGetLastError());                                               \
     } while (0)
 
+// LATTICE_U1_FUSE=0 turns off the two shortcuts of the self-consistent U(1)
+// steps below (the same results, bit for bit).
+static bool u1_fuse_on()
+{
+    const char *e = std::getenv("LATTICE_U1_FUSE");
+    return e ? std::atoi(e) != 0 : true;
+}
+
+// The drift with the record's weights (its kick weight is zero): u1_drift in
+// place of a step pass.
+lat_status u1_drift_pass(lat_ctx *c)
+{
+    const bool drift = u1_fuse_on() && c->vol <= 0xffffffffu;   // 32-bit site index
+    return u1_launch(c, drift ? kU1Drift : kU1Step, u1_args_dev(c, true));
+}
+
+// The kick with the record's weights followed by the volume sums of the kicked
+// state (the b kick's "after" sums): one row-kernel pass where the row kernel
+// runs, which forms the sums an energy pass with zero kick weight would, bit for
+// bit.
+lat_status u1_kick_sums(lat_ctx *c)
+{
+    if (c->u1_rows && u1_fuse_on()) return u1_launch(c, kU1KickSums, u1_args_dev(c, false));
+    lat_status s = u1_launch(c, kU1Kick, u1_args_dev(c, false));
+    if (s != LAT_OK) return s;
+    return u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false));
+}
+
 // Leapfrog steps of the self-consistent gauge models after a call's first take
 // the sums before the kick from the neighbouring passes (u1_self_drift_w) in
 // place of an energy pass of their own; LATTICE_SELF_CARRY=0 measures them on
@@ -2364,10 +2399,9 @@ lat_status u1_step_self_lf(lat_ctx *c, int64_t ns, int dir)
             U1K(u1_self_stash, c->sc);
         }
         U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
-        if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
-        if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+        if ((s = u1_kick_sums(c)) != LAT_OK) return s;
         U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc, carry);
-        if ((s = u1_launch(c, kU1Step, u1_args_dev(c, true))) != LAT_OK) return s;
+        if ((s = u1_drift_pass(c)) != LAT_OK) return s;
         u1_flip(c);
         stag = dir;
     }
@@ -2847,11 +2881,10 @@ lat_status u1_step_self_vv(lat_ctx *c, int64_t ns, int dir)
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
             if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
             U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc, 0);
-            if ((s = u1_launch(c, kU1Step, u1_args_dev(c, true))) != LAT_OK) return s;
+            if ((s = u1_drift_pass(c)) != LAT_OK) return s;
             u1_flip(c);
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
-            if ((s = u1_launch(c, kU1Kick, u1_args_dev(c, false))) != LAT_OK) return s;
-            if ((s = u1_launch(c, kU1Energy, u1_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+            if ((s = u1_kick_sums(c)) != LAT_OK) return s;
             U1K(u1_self_b_kick, c->sc, 0.5 * hs, kc);
         }
     c->t += (double)ns * h;

@@ -49,7 +49,11 @@ struct U1Args {
     ScaleRecord *sc;
 };
 
-enum U1Mode : int { kU1Step = 0, kU1Kick = 1, kU1Energy = 2 };
+// kU1KickSums (row kernel only): the kick-only pass that also leaves the volume
+// sums [0, 5) of the kicked state, as an energy pass with zero kick weight after
+// it would (Gauss terms not measured: sums [5, 8) and the maxes are zero)
+// kU1Drift: the drift alone (u1_drift), for a step pass whose kick weight is zero
+enum U1Mode : int { kU1Step = 0, kU1Kick = 1, kU1Energy = 2, kU1KickSums = 3, kU1Drift = 4 };
 constexpr int kU1Sums = 8, kU1Maxes = 3;
 
 __device__ inline size_t u1_at(int N, int x, int y, int z)
@@ -257,6 +261,22 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
     }
 }
 
+// Drift only, with the record's weights hd = dw[4], hdA = dw[5]: phi' = phi + hd pi,
+// A_i' = A_i + hdA piA_i into the other position buffers, one site per thread.
+// The self-consistent steps' drift pass has zero kick weight, where a step
+// pass forms the same values (p + 0 F = p) and rewrites the momenta unchanged:
+// this reads 10 and writes 5 arrays, with no forces.
+__global__ void __launch_bounds__(256) u1_drift(const U1Args g, unsigned vol)
+{
+    const unsigned n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= vol) return;
+    const double hd = g.dw[4], hdA = g.dw[5];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) g.phi_out[c][n] = g.phi_in[c][n] + hd * g.pi[c][n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g.A_out[i][n] = g.A_in[i][n] + hdA * g.piA[i][n];
+}
+
 // ---------------------------------------------------------------------------
 // Self-consistent expansion of the U(1) model (sec. 5.5.2, the b' equation with
 // the gauge energies): one-thread kernels between the lattice passes.  An
@@ -378,7 +398,7 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
     __shared__ double s_sxz[TY * NX];                             // own rows (index row - 1)
     __shared__ double s_cx[TY * NX], s_sx[TY * NX];               // phase of A_x, own rows
     __shared__ double s_cz[TY * NX], s_sz[TY * NX];               // phase of A_z, own rows
-    constexpr bool EN = MODE == kU1Energy;
+    constexpr bool EN = MODE == kU1Energy || MODE == kU1KickSums;   // ends with the reduction
     constexpr int NQ = kU1Sums + kU1Maxes;
     __shared__ double lds_red[EN ? (NT / 64) * NQ : 1];
     __shared__ int last_flag;
@@ -632,7 +652,7 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
             const double F0 = la1 * (d2r * inv_dx2) - la3 * (vp * pr);
             const double F1 = la1 * (d2i * inv_dx2) - la3 * (vp * pim);
             const double q0 = pq[0] + ck * F0, q1 = pq[1] + ck * F1;
-            if constexpr (EN) {
+            if constexpr (MODE == kU1Energy) {
                 // the energies and Gauss terms of u1_stage's energy mode
                 double t[NQ];
                 t[0] = 0.5 * (q0 * q0 + q1 * q1);
@@ -673,12 +693,31 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                     st32(g.phi_out[0], o, pr + hd * q0);
                     st32(g.phi_out[1], o, pim + hd * q1);
                 }
+                double ka = 0.0;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const double FA = la1 * (g.kappa_g * J[i]) - lm1 * (mag[i] * inv_edx3);
                     const double qa = pa[i] + ck * FA;
                     st32(g.piA[i], o, qa);
                     if constexpr (MODE == kU1Step) st32(g.A_out[i], o, a0[i] + hdA * qa);
+                    if constexpr (MODE == kU1KickSums) ka += qa * qa;
+                }
+                if constexpr (MODE == kU1KickSums) {
+                    // the terms the energy mode forms after this kick: there the
+                    // stored momenta are q, qa and p + 0 F = p
+                    double t[NQ];
+                    t[0] = 0.5 * (q0 * q0 + q1 * q1);
+                    t[1] = grad2 * inv_dx2 * 0.5;
+                    const double u = m2 - g.v * g.v;
+                    t[2] = 0.25 * g.lam * u * u;
+                    t[3] = ka / (2.0 * g.kappa_g);
+                    const double hxy = lat_sin(0.5 * th[0]), hxz = lat_sin(0.5 * th[1]), hyz = lat_sin(0.5 * th[2]);
+                    const double mg = 2.0 * hxy * hxy + 2.0 * hxz * hxz + 2.0 * hyz * hyz;
+                    t[4] = mg / (g.kappa_g * g.e * g.e * g.dx * g.dx * g.dx * g.dx);
+#pragma unroll
+                    for (int k = 5; k < NQ; ++k) t[k] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NQ; ++k) acc[k] = k < kU1Sums ? acc[k] + t[k] : fmax(acc[k], t[k]);
                 }
             }
             czm = s_cz[wo];

@@ -184,3 +184,34 @@ def test_u1_energy_columns(N, spec):
         assert abs(es[0][k] - es[1][k]) <= 1e-13 * abs(es[1][k]), (k, es[0][k], es[1][k])
     for k in ("gauss_max", "gauss_div_max", "gauss_charge_max"):
         assert es[0][k] == es[1][k], k
+
+
+@pytest.mark.parametrize("N,integ", [(64, "lf"), (64, "vv4"), (13, "lf")])
+def test_u1_self_fused_kick_sums_bitwise(N, integ):
+    """The self-consistent steps' shortcuts: on the whole-row kernel (N = 64) the
+    kick pass also forms the volume sums of the kicked state that the b kick
+    needs, and at every N the drift runs alone (u1_drift) in place of a step
+    pass with zero kick weight.  Fields, a and b equal, bit for bit, those of a
+    run with a separate energy pass after each kick and full step passes
+    (LATTICE_U1_FUSE=0)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, integ, "self", 0.5)
+    fields = fields_of(N)
+    runs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_U1_FUSE"):
+            say(f"[u1-fuse] N={N} {integ} LATTICE_U1_FUSE={spec}")
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(t[0], t[1], A=t[2], piA=t[3], **kw)
+            lat.step(3)
+            lat.step(2)
+            e = lat.energy()
+            torch.cuda.synchronize()
+            runs.append(([g.cpu().numpy() for grp in t for g in grp], e["a"], e["b"], e["rho"]))
+            lat.close()
+    (f1, a1, b1, r1), (f0, a0, b0, r0) = runs
+    assert a1 == a0 and b1 == b0 and r1 == r0, (a1, a0, b1, b0, r1, r0)
+    for g1, g0 in zip(f1, f0):
+        assert np.array_equal(g1, g0)
