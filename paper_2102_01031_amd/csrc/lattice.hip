@@ -2341,8 +2341,9 @@ lat_status u1_flip(lat_ctx *c)
         HIPCHK(c, hipGetLastError());                                               \
     } while (0)
 
-// LATTICE_U1_FUSE=0 turns off the two shortcuts of the self-consistent U(1)
-// steps below (the same results, bit for bit).
+// LATTICE_U1_FUSE=0 turns off the shortcuts of the self-consistent gauge steps
+// (the U(1) kick pass that also forms the sums and the U(1) drift-only pass,
+// bit for bit the same results; the SU(2) drift-only pass, the same to rounding).
 static bool u1_fuse_on()
 {
     const char *e = std::getenv("LATTICE_U1_FUSE");
@@ -2634,6 +2635,10 @@ lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &args)
     const dim3 grid(nb), blk(kSU2TX * kSU2TY);
     const bool nt = c->su2_nt != 0;
     switch (mode) {
+    case kSU2Drift:
+        hipLaunchKernelGGL(su2_drift, dim3((unsigned)((c->vol + 255) / 256)), dim3(256), 0, c->stream, a,
+                           (unsigned)c->vol);
+        break;
     case kSU2Step:
         if (nt) hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Step, true>), grid, blk, 0, c->stream, a);
         else hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Step, false>), grid, blk, 0, c->stream, a);
@@ -2719,6 +2724,15 @@ static bool su2_alternate()
 // between them with the U(1) model's one-thread kernels (the SU(2) energy pass
 // leaves its sums in the same slots: doublet kinetic, gradient, potential,
 // electric, magnetic).
+// The drift with the record's weights (its kick weight is zero): su2_drift in
+// place of a step pass (the same values to rounding); LATTICE_U1_FUSE=0 runs
+// the step pass, as for the U(1) model.
+lat_status su2_drift_pass(lat_ctx *c)
+{
+    const bool drift = u1_fuse_on() && c->vol <= 0xffffffffu;
+    return su2_launch(c, drift ? kSU2Drift : kSU2Step, su2_args_dev(c, true));
+}
+
 lat_status su2_step_self_lf(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
@@ -2737,7 +2751,7 @@ lat_status su2_step_self_lf(lat_ctx *c, int64_t ns, int dir)
         if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
         if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
         U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc, carry);
-        if ((s = su2_launch(c, kSU2Step, su2_args_dev(c, true))) != LAT_OK) return s;
+        if ((s = su2_drift_pass(c)) != LAT_OK) return s;
         c->cur_su2 ^= 1;
         stag = dir;
     }
@@ -2905,7 +2919,7 @@ lat_status su2_step_self_vv(lat_ctx *c, int64_t ns, int dir)
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
             if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
             U1K(u1_self_drift_w, c->sc, hs, 0.0, 0.5 * hs, kc, 0);
-            if ((s = su2_launch(c, kSU2Step, su2_args_dev(c, true))) != LAT_OK) return s;
+            if ((s = su2_drift_pass(c)) != LAT_OK) return s;
             c->cur_su2 ^= 1;
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
             if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;

@@ -57,7 +57,8 @@ struct SU2Args {
     ScaleRecord *sc;
 };
 
-enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2, kSU2StepAoS = 3 };
+// kSU2Drift: the drift alone (su2_drift), for a step pass whose kick weight is zero
+enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2, kSU2StepAoS = 3, kSU2Drift = 4 };
 
 // one 32-byte record through a 32-bit byte offset (valid while 32 N^3 < 2^32)
 __device__ __forceinline__ double4 ld4(const double4 *base, unsigned i)
@@ -357,6 +358,42 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
                 }
             }
         }
+    }
+}
+
+// Drift only, with the record's weights hd = dw[4], hdU = dw[5], on the plain
+// arrays, one site per thread: the doublet phi + hd pi and the links
+// exp(-i hdU g dx E.T) U, the step pass's drift formed by the same expressions
+// (the compiler may contract them differently: equal to rounding).  The
+// self-consistent steps' drift pass has zero kick weight, where a step pass
+// computes the forces for nothing (p + 0 F = p) and rewrites the momenta and
+// electric fields unchanged: this reads 29 arrays and writes 16.
+__global__ void __launch_bounds__(256) su2_drift(const SU2Args g, unsigned vol)
+{
+    const unsigned n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= vol) return;
+    const double hd = g.dw[4], hdU = g.dw[5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g.phi_out[k][n] = g.phi_in[k][n] + hd * g.pi[k][n];
+    const double hgdx = hdU * g.g * g.dx;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double ex = g.E[3 * i][n], ey = g.E[3 * i + 1][n], ez = g.E[3 * i + 2][n];
+        const double len = sqrt(ex * ex + ey * ey + ez * ez);
+        double sh, chh;
+        sincos(0.5 * (hgdx * len), &sh, &chh);
+        Q4 R{chh, 0.0, 0.0, 0.0};
+        if (len > 0.0) {
+            R.x = sh * ex / len;
+            R.y = sh * ey / len;
+            R.z = sh * ez / len;
+        }
+        const Q4 U{g.U_in[4 * i][n], g.U_in[4 * i + 1][n], g.U_in[4 * i + 2][n], g.U_in[4 * i + 3][n]};
+        const Q4 Un = qmul(R, U);
+        g.U_out[4 * i][n] = Un.w;
+        g.U_out[4 * i + 1][n] = Un.x;
+        g.U_out[4 * i + 2][n] = Un.y;
+        g.U_out[4 * i + 3][n] = Un.z;
     }
 }
 

@@ -149,3 +149,34 @@ def test_su2_self_carry_bitwise(N):
     assert a1 == a0 and b1 == b0, (a1, a0, b1, b0)
     for g1, g0 in zip(f1, f0):
         assert np.array_equal(g1, g0)
+
+
+@pytest.mark.parametrize("N,integ", [(13, "lf"), (64, "lf"), (13, "vv4")])
+def test_su2_self_drift_only(N, integ):
+    """The self-consistent steps' drift (zero kick weight) runs alone
+    (su2_drift) in place of a step pass: the same expressions, which the
+    compiler may contract into fused multiply-adds differently in the two
+    kernels, so fields, a, b and rho agree with a run of full step passes
+    (LATTICE_U1_FUSE=0) to rounding (1e-14)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, integ, "self", 0.5)
+    fields = inputs.random_su2_state(N, 41)
+    runs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_U1_FUSE"):
+            say(f"[su2-drift] N={N} {integ} LATTICE_U1_FUSE={spec}")
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(doublet=t[0], pi_doublet=t[1], U=t[2], E=t[3], **kw)
+            lat.step(3)
+            lat.step(2)
+            e = lat.energy()
+            torch.cuda.synchronize()
+            runs.append(([g.cpu().numpy() for grp in t for g in grp], e["a"], e["b"], e["rho"]))
+            lat.close()
+    (f1, a1, b1, r1), (f0, a0, b0, r0) = runs
+    for v1, v0 in ((a1, a0), (b1, b0), (r1, r0)):
+        assert abs(v1 - v0) <= 1e-14 * abs(v0), (v1, v0)
+    for g1, g0 in zip(f1, f0):
+        assert rel_maxdiff(g1, g0) <= 1e-14
