@@ -2618,12 +2618,13 @@ lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &args)
     // band order's one-plane blocks its last block would sum 16x more block
     // partials (654 against 357 us at 128^3)
     SU2Args a = args;
-    if (mode == kSU2Energy && a.band > 0) {
+    const bool sums = mode == kSU2Energy || mode == kSU2KickSums;
+    if (sums && a.band > 0) {
         a.band = 0;
         a.zc = su2_zc(c->N, false);
     }
     const size_t nbz = (size_t)a.tiles_x * a.tiles_y * (size_t)((c->N + a.zc - 1) / a.zc);
-    if (nbz > 0x7fffffffu || (mode == kSU2Energy && nbz * (kSU2Sums + kSU2Maxes) > c->partial_cap))
+    if (nbz > 0x7fffffffu || (sums && nbz * (kSU2Sums + kSU2Maxes) > c->partial_cap))
         return fail(c, LAT_EINVAL, "SU(2) launch exceeds the partials buffer");
     const int nb = (int)nbz;
     const int kind = 6;
@@ -2644,6 +2645,9 @@ lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &args)
         else hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Step, false>), grid, blk, 0, c->stream, a);
         break;
     case kSU2Kick: hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Kick, false>), grid, blk, 0, c->stream, a); break;
+    case kSU2KickSums:
+        hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2KickSums, false>), grid, blk, 0, c->stream, a);
+        break;
     case kSU2StepAoS:
         if (nt) hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2StepAoS, true>), grid, blk, 0, c->stream, a);
         else hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2StepAoS, false>), grid, blk, 0, c->stream, a);
@@ -2733,6 +2737,17 @@ lat_status su2_drift_pass(lat_ctx *c)
     return su2_launch(c, drift ? kSU2Drift : kSU2Step, su2_args_dev(c, true));
 }
 
+// The kick with the record's weights followed by the volume sums of the kicked
+// state: one pass in the energy pass's launch shape (kSU2KickSums) forming the
+// sums that pass would; LATTICE_U1_FUSE=0 runs the two passes.
+lat_status su2_kick_sums(lat_ctx *c)
+{
+    if (u1_fuse_on()) return su2_launch(c, kSU2KickSums, su2_args_dev(c, false));
+    lat_status s = su2_launch(c, kSU2Kick, su2_args_dev(c, false));
+    if (s != LAT_OK) return s;
+    return su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false));
+}
+
 lat_status su2_step_self_lf(lat_ctx *c, int64_t ns, int dir)
 {
     const double h = dir * c->p.dt;
@@ -2748,8 +2763,7 @@ lat_status su2_step_self_lf(lat_ctx *c, int64_t ns, int dir)
             U1K(u1_self_stash, c->sc);
         }
         U1K(u1_self_kick_w, c->sc, w, c->p.alpha);
-        if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
-        if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+        if ((s = su2_kick_sums(c)) != LAT_OK) return s;
         U1K(u1_self_drift_w, c->sc, h, stag == 0 ? 0.0 : 0.5 * h, stag == 0 ? w : 0.5 * h, kc, carry);
         if ((s = su2_drift_pass(c)) != LAT_OK) return s;
         c->cur_su2 ^= 1;
@@ -2922,8 +2936,7 @@ lat_status su2_step_self_vv(lat_ctx *c, int64_t ns, int dir)
             if ((s = su2_drift_pass(c)) != LAT_OK) return s;
             c->cur_su2 ^= 1;
             U1K(u1_self_kick_w, c->sc, 0.5 * hs, c->p.alpha);
-            if ((s = su2_launch(c, kSU2Kick, su2_args_dev(c, false))) != LAT_OK) return s;
-            if ((s = su2_launch(c, kSU2Energy, su2_args(c, 0.0, 0.0, false))) != LAT_OK) return s;
+            if ((s = su2_kick_sums(c)) != LAT_OK) return s;
             U1K(u1_self_b_kick, c->sc, 0.5 * hs, kc);
         }
     c->t += (double)ns * h;

@@ -57,8 +57,11 @@ struct SU2Args {
     ScaleRecord *sc;
 };
 
-// kSU2Drift: the drift alone (su2_drift), for a step pass whose kick weight is zero
-enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2, kSU2StepAoS = 3, kSU2Drift = 4 };
+// kSU2Drift: the drift alone (su2_drift), for a step pass whose kick weight is zero.
+// kSU2KickSums: the kick-only pass that also leaves the volume sums [0, 5) of
+// the kicked state, as an energy pass with zero kick weight after it would (in
+// that pass's launch shape; Gauss terms not measured: the rest stays zero).
+enum SU2Mode : int { kSU2Step = 0, kSU2Kick = 1, kSU2Energy = 2, kSU2StepAoS = 3, kSU2Drift = 4, kSU2KickSums = 5 };
 
 // one 32-byte record through a 32-bit byte offset (valid while 32 N^3 < 2^32)
 __device__ __forceinline__ double4 ld4(const double4 *base, unsigned i)
@@ -215,7 +218,7 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
         l1 += s0 - 2.0 * b0 + u0;
         l2 += r1 - 2.0 * c0 + t1;
         l3 += s1 - 2.0 * d0 + u1;
-        if (MODE == kSU2Energy) {
+        if (MODE == kSU2Energy || MODE == kSU2KickSums) {
             const double e0 = r0 - a0, e1 = s0 - b0, e2 = r1 - c0, e3 = s1 - d0;
             grad2 += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
         }
@@ -322,6 +325,30 @@ __device__ __forceinline__ void su2_site(const SU2Args &g, const SU2W &wt, const
         for (int k = 0; k < 9; ++k) {
             en[k] = ev[k] + wt.ck * FE[k];
             st_s<NT>(g.E[k], n, en[k]);
+        }
+        if constexpr (MODE == kSU2KickSums) {
+            // the terms the energy mode forms after this kick, where the stored
+            // momenta are pn, en and p + 0 F = p
+            double kin = 0.0, ke = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) kin += pn[k] * pn[k];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) ke += en[k] * en[k];
+            acc[0] += 0.5 * kin;
+            acc[1] += grad2 * inv_dx2 * 0.5;
+            const double u = m2 - g.v * g.v;
+            acc[2] += 0.25 * g.lam * u * u;
+            acc[3] += 0.5 * ke;
+            double mg = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i + 1; j < 3; ++j) {
+                    const Q4 Pij =
+                        qmul(qmul(Ul[i], L(j, at1(i, cp[i]))), qmul(qdag(L(i, at1(j, cp[j]))), qdag(Ul[j])));
+                    mg += 2.0 * (Pij.x * Pij.x + Pij.y * Pij.y + Pij.z * Pij.z) / (1.0 + Pij.w);
+                }
+            acc[4] += 2.0 * mg / (g.g * g.g * g.dx * g.dx * g.dx * g.dx);
         }
         if (MODE == kSU2Step || AOS) {
             const double4 po{a0 + wt.hd * pn[0], b0 + wt.hd * pn[1], c0 + wt.hd * pn[2], d0 + wt.hd * pn[3]};
@@ -459,7 +486,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))
         }
     }
 
-    if constexpr (MODE == kSU2Energy) {
+    if constexpr (MODE == kSU2Energy || MODE == kSU2KickSums) {
         // block reduction: sums for [0, kSU2Sums), maxes for the rest; the last
         // block (ticket) combines the block partials in block order
         const int lane = tid & 63, w = tid >> 6;

@@ -153,10 +153,12 @@ def test_su2_self_carry_bitwise(N):
 
 @pytest.mark.parametrize("N,integ", [(13, "lf"), (64, "lf"), (13, "vv4")])
 def test_su2_self_drift_only(N, integ):
-    """The self-consistent steps' drift (zero kick weight) runs alone
-    (su2_drift) in place of a step pass: the same expressions, which the
-    compiler may contract into fused multiply-adds differently in the two
-    kernels, so fields, a, b and rho agree with a run of full step passes
+    """The self-consistent steps' shortcuts: the drift (zero kick weight) runs
+    alone (su2_drift) in place of a step pass, and the kick pass also forms the
+    volume sums of the kicked state (in the energy pass's launch shape) in
+    place of a separate energy pass.  The same expressions, which the compiler
+    may contract into fused multiply-adds differently in different kernels, so
+    fields, a, b and rho agree with a run without the shortcuts
     (LATTICE_U1_FUSE=0) to rounding (1e-14)."""
     import torch
     from paper_2102_01031_amd.lattice import Lattice
