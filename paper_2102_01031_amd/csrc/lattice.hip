@@ -2619,9 +2619,14 @@ lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &args)
     // partials (654 against 357 us at 128^3)
     SU2Args a = args;
     const bool sums = mode == kSU2Energy || mode == kSU2KickSums;
-    if (sums && a.band > 0) {
+    if (sums) {
         a.band = 0;
         a.zc = su2_zc(c->N, false);
+        // LATTICE_SU2_ENERGY_ZC: z planes per block of the summing passes alone
+        if (const char *ez = std::getenv("LATTICE_SU2_ENERGY_ZC")) {
+            const int v = std::atoi(ez);
+            if (v >= 1 && v <= c->N) a.zc = v;
+        }
     }
     const size_t nbz = (size_t)a.tiles_x * a.tiles_y * (size_t)((c->N + a.zc - 1) / a.zc);
     if (nbz > 0x7fffffffu || (sums && nbz * (kSU2Sums + kSU2Maxes) > c->partial_cap))
