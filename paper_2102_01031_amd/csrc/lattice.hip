@@ -613,7 +613,50 @@ struct PassLink {
     const PassCoef *fin_coef = nullptr;
     const ScaleRecord *fin_in = nullptr;
     ScaleRecord *fin_out = nullptr;
+    // defer = 1 on a store-only pass: sums_finish adds this pass's block sums
+    // into store_to->sums right after it (inside the pass's timed region)
+    ScaleRecord *store_to = nullptr;
 };
+
+// The deferred block sums of a store-only pass (the energy pass), added by one
+// block of NT threads (NT as the pass's, so in the order of the last-block
+// reduction) into Sout->sums: the same values as that reduction, with no
+// ticket release in the pass's blocks.
+template <int NT, int NQ>
+__global__ void __launch_bounds__(NT) sums_finish(const double *partials, int nb, ScaleRecord *Sout)
+{
+    __shared__ double lds_red[(NT / 64) * NQ];
+    const int tid = threadIdx.x;
+    double part[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) part[k] = 0.0;
+    for (int i = tid; i < nb; i += NT) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) part[k] += partials[(size_t)i * NQ + k];
+    }
+    double fin[NQ];
+    block_sums<NT, NQ>(part, lds_red, fin);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) Sout->sums[k] = fin[k];
+    }
+}
+
+hipError_t launch_sums_finish(int NT, int nf, const double *partials, int nb, ScaleRecord *S, hipStream_t st)
+{
+#define SUMS_FIN(nt)                                                                                       \
+    if (NT == nt) {                                                                                        \
+        if (nf == 1) hipLaunchKernelGGL((sums_finish<nt, 3>), dim3(1), dim3(nt), 0, st, partials, nb, S); \
+        else hipLaunchKernelGGL((sums_finish<nt, 6>), dim3(1), dim3(nt), 0, st, partials, nb, S);         \
+        return hipGetLastError();                                                                          \
+    }
+    SUMS_FIN(64)
+    SUMS_FIN(128)
+    SUMS_FIN(256)
+    SUMS_FIN(512)
+#undef SUMS_FIN
+    return hipErrorInvalidValue;
+}
 
 template <typename T>
 lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream,
@@ -685,6 +728,11 @@ lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hi
         e = c->nf == 1 ? launch_tile<T, 1>(c->tile, variant, a, c->nblocks, stream)
                        : launch_tile<T, 2>(c->tile, variant, a, c->nblocks, stream);
     if (e != hipSuccess) return fail(c, LAT_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
+    if (lk && lk->defer && lk->store_to) {
+        const int NT = c->rows ? 64 * ty : kTiles[c->tile].tx * kTiles[c->tile].ty;
+        e = launch_sums_finish(NT, c->nf, lk->partials, c->rows ? nb : c->nblocks, lk->store_to, stream);
+        if (e != hipSuccess) return fail(c, LAT_EHIP, std::string("sums launch: ") + hipGetErrorString(e));
+    }
     if (c->profiling) {
         lat_status st = timing_end(c, ev0, ev1, variant);
         if (st != LAT_OK) return st;
@@ -1275,7 +1323,16 @@ lat_status energy_sums(lat_ctx *c, double kick_c1)
         hipLaunchKernelGGL(self_prologue, dim3(1), dim3(64), 0, c->stream, c->coef, c->sc, c->p.alpha);
         HIPCHK(c, hipGetLastError());
     }
-    if ((s = run_pass(c, kEnergy, 0, kLastStore)) != LAT_OK) return s;
+    // the block sums go to a one-block kernel after the pass rather than to a
+    // last block: no ticket release in the pass's blocks (LATTICE_ENERGY_DEFER=0
+    // keeps the ticket; the same sums)
+    const char *ed = std::getenv("LATTICE_ENERGY_DEFER");
+    PassLink el;
+    el.defer = 1;
+    el.partials = c->partials;
+    el.store_to = c->sc;
+    if ((s = run_pass(c, kEnergy, 0, kLastStore, c->stream, (ed && std::atoi(ed) == 0) ? nullptr : &el)) != LAT_OK)
+        return s;
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(ScaleRecord), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LAT_OK;
