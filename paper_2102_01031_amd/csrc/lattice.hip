@@ -658,6 +658,60 @@ hipError_t launch_sums_finish(int NT, int nf, const double *partials, int nb, Sc
     return hipErrorInvalidValue;
 }
 
+// The deferred block partials of a gauge summing pass (the U(1) and SU(2)
+// energy and kick-and-sums passes: 8 sums, then 3 maxima per block), combined
+// by one block of NT threads, NT the pass's block size: the order and the
+// arithmetic of the pass's own last-block reduction.
+static_assert(kU1Sums == 8 && kU1Maxes == 3 && kSU2Sums == 8 && kSU2Maxes == 3, "gauge sum layout");
+template <int NT>
+__global__ void __launch_bounds__(NT) gauge_sums_finish(const double *partials, int nb, ScaleRecord *S)
+{
+    constexpr int NS = 8, NQ = 11;
+    __shared__ double lds_red[(NT / 64) * NQ];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double part[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) part[k] = 0.0;
+    for (int i = tid; i < nb; i += NT) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const double v = partials[(size_t)i * NQ + k];
+            part[k] = k < NS ? part[k] + v : fmax(part[k], v);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const double r = k < NS ? wave_sum(part[k]) : wave_max(part[k]);
+        if (lane == 0) lds_red[w * NQ + k] = r;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < NQ; ++k) {
+            double r = 0.0;
+            for (int i = 0; i < NT / 64; ++i) r = k < NS ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
+            if (k < NS) S->sums[k] = r;
+            else S->maxes[k - NS] = r;
+        }
+    }
+}
+
+hipError_t launch_gauge_sums_finish(int NT, const double *partials, int nb, ScaleRecord *S, hipStream_t st)
+{
+    if (NT == 256) hipLaunchKernelGGL(gauge_sums_finish<256>, dim3(1), dim3(256), 0, st, partials, nb, S);
+    else if (NT == 512) hipLaunchKernelGGL(gauge_sums_finish<512>, dim3(1), dim3(512), 0, st, partials, nb, S);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Summing passes of the gauge models leave their block partials to
+// gauge_sums_finish (no ticket release in their blocks); LATTICE_ENERGY_DEFER=0
+// keeps the ticketed last block (the same results, bit for bit).
+static bool gauge_defer_on()
+{
+    const char *e = std::getenv("LATTICE_ENERGY_DEFER");
+    return e ? std::atoi(e) != 0 : true;
+}
+
 template <typename T>
 lat_status run_pass_t(lat_ctx *c, int variant, int pass_index, int last_mode, hipStream_t stream,
                       const PassLink *lk = nullptr)
@@ -2357,22 +2411,27 @@ lat_status u1_launch(lat_ctx *c, int mode, const U1Args &a)
         }
         hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Kick>), dim3(nb), dim3(kU1TX * kU1TY), 0, c->stream, a);
         break;
-    case kU1KickSums:
-        HIPCHK(c, launch_u1_rows<kU1KickSums>(c, a));
-        break;
     case kU1Drift:
         hipLaunchKernelGGL(u1_drift, dim3((unsigned)((c->vol + 255) / 256)), dim3(256), 0, c->stream, a,
                            (unsigned)c->vol);
         break;
-    default: {
-        if (c->u1_rows) {
-            HIPCHK(c, launch_u1_rows<kU1Energy>(c, a));
-            break;
-        }
+    default: {   // the summing passes: energy, kick and sums (row kernel only)
         U1Args e = a;
-        e.zc = c->u1_ezc;
-        const int nbe = a.tiles_x * a.tiles_y * ((c->N + e.zc - 1) / e.zc);
-        hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Energy>), dim3(nbe), dim3(kU1TX * kU1TY), 0, c->stream, e);
+        e.defer = gauge_defer_on() ? 1 : 0;
+        int fnt, fnb;
+        if (c->u1_rows) {
+            HIPCHK(c, mode == kU1KickSums ? launch_u1_rows<kU1KickSums>(c, e) : launch_u1_rows<kU1Energy>(c, e));
+            fnt = c->N * c->u1_ty;
+            fnb = (c->N / c->u1_ty) * ((c->N + c->u1_zc - 1) / c->u1_zc);
+        } else {
+            if (mode == kU1KickSums) return fail(c, LAT_EINVAL, "U(1) kick-and-sums pass needs the row kernel");
+            e.zc = c->u1_ezc;
+            fnb = a.tiles_x * a.tiles_y * ((c->N + e.zc - 1) / e.zc);
+            fnt = kU1TX * kU1TY;
+            hipLaunchKernelGGL((u1_stage<kU1TX, kU1TY, kU1Energy>), dim3(fnb), dim3(fnt), 0, c->stream, e);
+        }
+        HIPCHK(c, hipGetLastError());
+        if (e.defer) HIPCHK(c, launch_gauge_sums_finish(fnt, e.partials, fnb, e.sc, c->stream));
         break;
     }
     }
@@ -2679,6 +2738,7 @@ lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &args)
     if (sums) {
         a.band = 0;
         a.zc = su2_zc(c->N, false);
+        a.defer = gauge_defer_on() ? 1 : 0;
         // LATTICE_SU2_ENERGY_ZC: z planes per block of the summing passes alone
         if (const char *ez = std::getenv("LATTICE_SU2_ENERGY_ZC")) {
             const int v = std::atoi(ez);
@@ -2709,12 +2769,18 @@ lat_status su2_launch(lat_ctx *c, int mode, const SU2Args &args)
     case kSU2Kick: hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Kick, false>), grid, blk, 0, c->stream, a); break;
     case kSU2KickSums:
         hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2KickSums, false>), grid, blk, 0, c->stream, a);
+        HIPCHK(c, hipGetLastError());
+        if (a.defer) HIPCHK(c, launch_gauge_sums_finish(kSU2TX * kSU2TY, a.partials, nb, a.sc, c->stream));
         break;
     case kSU2StepAoS:
         if (nt) hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2StepAoS, true>), grid, blk, 0, c->stream, a);
         else hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2StepAoS, false>), grid, blk, 0, c->stream, a);
         break;
-    default: hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Energy, false>), grid, blk, 0, c->stream, a); break;
+    default:
+        hipLaunchKernelGGL((su2_stage<kSU2TX, kSU2TY, kSU2Energy, false>), grid, blk, 0, c->stream, a);
+        HIPCHK(c, hipGetLastError());
+        if (a.defer) HIPCHK(c, launch_gauge_sums_finish(kSU2TX * kSU2TY, a.partials, nb, a.sc, c->stream));
+        break;
     }
     HIPCHK(c, hipGetLastError());
     if (c->profiling) {

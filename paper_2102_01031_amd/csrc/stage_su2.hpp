@@ -55,6 +55,7 @@ struct SU2Args {
     double *partials;
     unsigned *ticket;
     ScaleRecord *sc;
+    int defer;   // summing passes: leave the block partials, take no ticket
 };
 
 // kSU2Drift: the drift alone (su2_drift), for a step pass whose kick weight is zero.
@@ -503,7 +504,8 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))
                     r = k < kSU2Sums ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
                 store_agent(&g.partials[(size_t)lid * NQ + k], r);
             }
-            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
+            // defer: the block partials are combined by a kernel after this one
+            last_flag = g.defer ? 0 : (ticket_arrive(g.ticket, gridDim.x) ? 1 : 0);
         }
         __syncthreads();
         if (last_flag) {

@@ -47,6 +47,7 @@ struct U1Args {
     double *partials;
     unsigned *ticket;
     ScaleRecord *sc;
+    int defer;   // summing passes: leave the block partials, take no ticket
 };
 
 // kU1KickSums (row kernel only): the kick-only pass that also leaves the volume
@@ -226,7 +227,8 @@ __global__ void __launch_bounds__(TX *TY) u1_stage(const U1Args g)
                     r = k < kU1Sums ? r + lds_red[i * NQ + k] : fmax(r, lds_red[i * NQ + k]);
                 store_agent(&g.partials[(size_t)lid * NQ + k], r);
             }
-            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
+            // defer: the block partials are combined by a kernel after this one
+            last_flag = g.defer ? 0 : (ticket_arrive(g.ticket, gridDim.x) ? 1 : 0);
         }
         __syncthreads();
         if (last_flag) {
@@ -755,7 +757,8 @@ __global__ void __launch_bounds__(64 * XS * TY) u1_rows(const U1Args g)
                     rv = k < kU1Sums ? rv + lds_red[i * NQ + k] : fmax(rv, lds_red[i * NQ + k]);
                 store_agent(&g.partials[(size_t)lid * NQ + k], rv);
             }
-            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
+            // defer: the block partials are combined by a kernel after this one
+            last_flag = g.defer ? 0 : (ticket_arrive(g.ticket, gridDim.x) ? 1 : 0);
         }
         __syncthreads();
         if (last_flag) {

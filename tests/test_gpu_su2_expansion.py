@@ -182,3 +182,32 @@ def test_su2_self_drift_only(N, integ):
         assert abs(v1 - v0) <= 1e-14 * abs(v0), (v1, v0)
     for g1, g0 in zip(f1, f0):
         assert rel_maxdiff(g1, g0) <= 1e-14
+
+
+@pytest.mark.parametrize("N,integ,expansion", [(13, "lf", "self"), (64, "lf", "none")])
+def test_su2_deferred_sums_bitwise(N, integ, expansion):
+    """The summing passes (energy; kick and sums) leave their block partials to
+    a one-block kernel after them instead of a ticketed last block: energies,
+    Gauss maxima, fields, a and b equal, bit for bit, those of the ticketed
+    passes (LATTICE_ENERGY_DEFER=0)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, integ, expansion, 0.5)
+    fields = inputs.random_su2_state(N, 41)
+    runs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_ENERGY_DEFER"):
+            say(f"[su2-defer] N={N} {integ} {expansion} LATTICE_ENERGY_DEFER={spec}")
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(doublet=t[0], pi_doublet=t[1], U=t[2], E=t[3], **kw)
+            lat.step(4)
+            e = lat.energy()
+            torch.cuda.synchronize()
+            runs.append(([g.cpu().numpy() for grp in t for g in grp], e))
+            lat.close()
+    (f1, e1), (f0, e0) = runs
+    for k in ("rho", "EK_B", "EG_B", "a", "b", "gauss_max", "gauss_div_max", "gauss_charge_max", "gauss_mean"):
+        assert e1[k] == e0[k], (k, e1[k], e0[k])
+    for g1, g0 in zip(f1, f0):
+        assert np.array_equal(g1, g0)

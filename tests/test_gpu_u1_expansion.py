@@ -215,3 +215,34 @@ def test_u1_self_fused_kick_sums_bitwise(N, integ):
     assert a1 == a0 and b1 == b0 and r1 == r0, (a1, a0, b1, b0, r1, r0)
     for g1, g0 in zip(f1, f0):
         assert np.array_equal(g1, g0)
+
+
+@pytest.mark.parametrize("N,integ,expansion", [(64, "lf", "self"), (13, "lf", "self"), (64, "vv4", "none"),
+                                               (13, "lf", "none")])
+def test_u1_deferred_sums_bitwise(N, integ, expansion):
+    """The summing passes (energy; kick and sums) leave their block partials to
+    a one-block kernel after them instead of a ticketed last block: energies,
+    Gauss maxima, fields, a and b equal, bit for bit, those of the ticketed
+    passes (LATTICE_ENERGY_DEFER=0), on the whole-row kernel (64) and the
+    per-site kernel (13)."""
+    import torch
+    from paper_2102_01031_amd.lattice import Lattice
+    from gpu_util import tile_env
+    kw = kw_of(N, integ, expansion, 0.5)
+    fields = fields_of(N)
+    runs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_ENERGY_DEFER"):
+            say(f"[u1-defer] N={N} {integ} {expansion} LATTICE_ENERGY_DEFER={spec}")
+            t = [to_dev(f, torch.float64) for f in fields]
+            lat = Lattice(t[0], t[1], A=t[2], piA=t[3], **kw)
+            lat.step(4)
+            e = lat.energy()
+            torch.cuda.synchronize()
+            runs.append(([g.cpu().numpy() for grp in t for g in grp], e))
+            lat.close()
+    (f1, e1), (f0, e0) = runs
+    for k in ("rho", "EK_A", "EG_A", "a", "b", "gauss_max", "gauss_div_max", "gauss_charge_max", "gauss_mean"):
+        assert e1[k] == e0[k], (k, e1[k], e0[k])
+    for g1, g0 in zip(f1, f0):
+        assert np.array_equal(g1, g0)
