@@ -3138,9 +3138,10 @@ namespace {
 constexpr int kAdjTX = 64, kAdjTY = 4;
 
 lat_status adj_pass(lat_ctx *c, double dphi, double dlam, double cA, double cB, double kL, double kV, int nb, int zc,
-                    int tiles_x, int tiles_y)
+                    int tiles_x, int tiles_y, double *dq_slots = nullptr)
 {
     AdjArgs a{};
+    a.dq_slots = dq_slots;
     for (int f = 0; f < 2; ++f) {
         const int cp = c->cur_phi[f], cq = c->cur_pi[f];
         const int cl = c->cur_lam[0][f], cm = c->cur_lam[1][f];
@@ -3462,11 +3463,26 @@ extern "C" lat_status lattice_grad(lat_ctx *c, const lat_grad_spec *spec, lat_gr
     // ---- reverse sweep
     double la = la_T, lb = 0.0, dq_self = 0.0, seed_sum = 0.0;
     if (!self) {
-        GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, kick_l(T), kick_v(T), nb, zc, tiles_x, tiles_y));   // closing half kick
+        // dO/dq: every block of the passes adds its partial to its own slot
+        // (c->adj_partials, free once the seed has finished), summed after the
+        // sweep, so no pass ends with ticket releases; LATTICE_ENERGY_DEFER=0
+        // keeps the per-pass ticketed sums (the same value to rounding)
+        double *slots = gauge_defer_on() ? c->adj_partials : nullptr;
+        if (slots) {
+            hipLaunchKernelGGL(zero_doubles, dim3((nb + 255) / 256), dim3(256), 0, c->stream, slots, nb);
+            HIPCHK(c, hipGetLastError());
+        }
+        GCHK(adj_pass(c, 0.0, 0.0, 0.0, 0.5 * h, kick_l(T), kick_v(T), nb, zc, tiles_x, tiles_y, slots));   // closing half kick
         for (int64_t p = T - 1; p >= 0; --p) {
             const double d = h * drift_d(p);
-            GCHK(adj_pass(c, -d, d, p > 0 ? 0.5 * h : 0.0, 0.5 * h, kick_l(p), kick_v(p), nb, zc, tiles_x, tiles_y));
+            GCHK(adj_pass(c, -d, d, p > 0 ? 0.5 * h : 0.0, 0.5 * h, kick_l(p), kick_v(p), nb, zc, tiles_x, tiles_y,
+                          slots));
             if (p % k == 0) GCHK(checkpoint_io(c, (size_t)(p / k), false));
+        }
+        if (slots) {
+            hipLaunchKernelGGL(adj_dq_finish, dim3(1), dim3(256), 0, c->stream, (const double *)slots, nb,
+                               &c->sc->sums[kMaxQ - 1]);
+            HIPCHK(c, hipGetLastError());
         }
     } else {
         // Self-consistent expansion: one fused pass per time point (stage_adjoint_self.hpp),

@@ -34,6 +34,10 @@ struct AdjArgs {
     double *partials;
     unsigned *ticket;
     double *dq_acc;      // device accumulator of dO/dq
+    // if not null: each block adds its partial of dO/dq to its own slot (one
+    // per block, summed by adj_dq_finish after the sweep) instead of a ticketed
+    // last block adding the pass's sum to dq_acc
+    double *dq_slots;
 };
 
 template <int TX, int TY>
@@ -216,8 +220,13 @@ __global__ void __launch_bounds__(TX *TY) adjoint_stage(const AdjArgs g)
     if (tid == 0) {
         double s = 0.0;
         for (int i = 0; i < NT / 64; ++i) s += lds_red[i];
-        store_agent(&g.partials[lid], s);
-        last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
+        if (g.dq_slots) {
+            g.dq_slots[lid] += s;   // this block's slot: no other block writes it
+            last_flag = 0;
+        } else {
+            store_agent(&g.partials[lid], s);
+            last_flag = ticket_arrive(g.ticket, gridDim.x) ? 1 : 0;
+        }
     }
     __syncthreads();
     if (last_flag) {
@@ -300,6 +309,20 @@ __global__ void __launch_bounds__(256) adjoint_seed(const SeedArgs g)
             __hip_atomic_store(g.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// The per-block slots of dO/dq after a reverse sweep, added in block order
+// (per thread, wave, then the waves in order) into *dq_acc: one block of 256.
+__global__ void __launch_bounds__(256) adj_dq_finish(const double *slots, int nb, double *dq_acc)
+{
+    __shared__ double lds_red[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double part = 0.0;
+    for (int i = tid; i < nb; i += 256) part += slots[i];
+    const double ws = wave_sum(part);
+    if (lane == 0) lds_red[w] = ws;
+    __syncthreads();
+    if (tid == 0) *dq_acc += ((lds_red[0] + lds_red[1]) + lds_red[2]) + lds_red[3];
 }
 
 __global__ void zero_doubles(double *p, int n)

@@ -515,3 +515,27 @@ def test_autograd_with_expansion_and_forward_only_path(expansion, alpha):
                                                        lam=wl.lam, **bgk)
         assert torch.autograd.gradcheck(f, (*xs, q4), eps=1e-6, atol=1e-9, rtol=1e-5)
 
+
+
+@pytest.mark.parametrize("N,T", [(64, 40), (20, 17)])
+def test_grad_dq_slots_vs_ticketed(N, T):
+    """The reverse sweep adds each block's partial of dO/dq to the block's own
+    slot and sums the slots after the sweep, instead of a ticketed last block
+    adding each pass's sum: dO/dq agrees with the per-pass sums
+    (LATTICE_ENERGY_DEFER=0) to rounding, and the adjoint arrays, which do not
+    depend on it, bit for bit."""
+    from gpu_util import tile_env
+    wl = workloads.ADJ_64
+    phi, pi = wl.initial_fields(N=N)
+    rs = []
+    for spec in (None, "0"):
+        with tile_env(spec, "LATTICE_ENERGY_DEFER"):
+            say(f"[adj] dq slots N={N} T={T} LATTICE_ENERGY_DEFER={spec}")
+            lat, tp, tq, r = gpu_grad(wl, N, phi, pi, T)
+            rs.append((r["value"], r["dO_dq"], [a.cpu().numpy() for a in r["dO_dphi"] + r["dO_dpi"]]))
+            lat.close()
+    (v1, q1, g1), (v0, q0, g0) = rs
+    assert v1 == v0
+    assert abs(q1 - q0) <= 1e-13 * abs(q0), (q1, q0)
+    for a, b in zip(g1, g0):
+        assert np.array_equal(a, b)
